@@ -1,0 +1,9 @@
+"""Plain FP64 CPU oracle (test infrastructure only).
+
+Only the test suite, the smoke check and the CPU-baseline leg of the
+benchmark may import this package.  The GPU library never does, and this
+package never imports the GPU library.
+"""
+from .oracle import (  # noqa: F401
+    Oracle, build, lgl, load, hevi_coefficients, ark2_step, ark2_generic, column_matrix,
+)
