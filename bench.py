@@ -1,0 +1,146 @@
+"""Throughput of the SSP-RK3 step on one MI355X, printed as one JSON line.
+
+Workload: the per-GPU tropical-cyclone share, 128 x 128 x 20 elements of
+order 4 (E = 327,680; U = 21,233,664 unique nodes), doubly periodic
+1200 x 1200 x 20 km f-plane box, balanced warm-core vortex, heating bursts,
+Rayleigh sponge, dt = 0.25 s.  A step is one SSP-RK3 step: three launches of
+the fused RHS/DSS/RK stage kernel over the whole lattice, inputs resident in
+HBM.  value = unique DOF-stage updates per second (5 U x 3 stages per step).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per unique node and stage: read q^s (40 B), q^n (40 B in
+# stages 2 and 3), both heating snapshots (16 B), write q^{s+1} (40 B)
+BYTES_STAGE = {1: 40 + 16 + 40, 2: 40 + 40 + 16 + 40, 3: 40 + 40 + 16 + 40}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--workload", default="tc_large", choices=["tc_large", "tc_small"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-nel", type=int, default=48, help="horizontal elements of the oracle sample box")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, nel):
+    """The FP64 oracle, untuned, on a bounded sample of the same workload: one
+    SSP-RK3 step of a nel x nel x 20 element box with the same element size,
+    physics and order."""
+    import numpy as np
+    import oracle
+    from paper_2504_08157_amd import workloads as W
+    oracle.build(force=False)
+    half = 600.0e3 * nel / w.mesh.nel[0]
+    mesh = W._tc_mesh(nel, nel, w.mesh.nel[2], w.mesh.order, half=half)
+    sub = W.Workload(w.name, mesh, w.phys, w.dt, 1, w.reference, w.ic, vmax=w.vmax, heating_T=w.heating_T)
+    orc = oracle.Oracle(mesh, w.phys)
+    x, y, z = orc.lattice_coords()
+    orc.set_reference(*W.reference_profiles(sub, z))
+    t, Q = W.heating(sub, x, y, z)
+    orc.set_forcing(4, t, Q)
+    q = W.initial_state(sub, x, y, z)
+    t0 = time.perf_counter()
+    orc.rk3(0.0, w.dt, 1, q)
+    sec = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 5 * orc.U * 3 / sec, "unit": "DOF-stage updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"one SSP-RK3 step (3 RHS) of a {nel}x{nel}x{mesh.nel[2]} element N={mesh.order} "
+                      f"sub-box of the same workload (U={orc.U}), {sec:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
+              f"described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2504_08157_amd import nhsem
+    from paper_2504_08157_amd import workloads as W
+
+    w = W.cfg_tc_large() if args.workload == "tc_large" else W.cfg_tc_small()
+    prec = nhsem.NH_FP64 if args.precision == "fp64" else nhsem.NH_FP32_MIXED
+    ctx = nhsem.Context(w.mesh, w.phys, precision=prec)
+    x, y, z = ctx.nh_lattice_coords()
+    ctx.nh_set_reference(*W.reference_profiles(w, z))
+    t_snap, Q = W.heating(w, x, y, z)
+    Qd = torch.from_numpy(Q.reshape(len(t_snap), -1)).cuda()
+    del Q
+    ctx.nh_set_forcing(4, t_snap, Qd)
+    q0 = torch.from_numpy(W.initial_state(w, x, y, z)).cuda()
+    ctx.nh_set_state(q0)
+    torch.cuda.synchronize()
+
+    dt = w.dt
+    ctx.nh_rk_step(0.0, dt, args.warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    start.record()
+    ctx.nh_rk_step(args.warmup * dt, dt, args.steps)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    ms = start.elapsed_time(stop)
+    if ctx.nh_check_finite() != 0:
+        raise RuntimeError("non-finite state after the timed steps")
+
+    U = ctx.U
+    launches = 3 * args.steps
+    ms_step = ms / args.steps
+    value = 5 * U * 3 * args.steps / (ms / 1e3)
+    bytes_step = U * sum(BYTES_STAGE.values())
+    achieved = bytes_step * args.steps / (ms / 1e3) / 1e9
+    res = {
+        "metric": "DOF-stage updates/s (FP32/batched vs FP64 plain) at stated L2 error; % HBM peak",
+        "value": value,
+        "unit": "DOF-stage updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == nhsem.NH_FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": w.name,
+            "elements": list(w.mesh.nel), "order": w.mesh.order,
+            "unique_nodes": U, "local_nodes": ctx.L,
+            "dof_convention": "unique nodes x 5 fields; paper convention (E (N+1)^3 x 5) = "
+                              f"{value * ctx.L / U:.4e}",
+            "dt": dt, "precision": args.precision,
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "stage_kernel (fused RHS + DSS + SSP-RK stage)",
+            "avg_launch_ms": ms / launches,
+        },
+        "wall_s_timed": wall,
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(w, args.cpu_nel)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

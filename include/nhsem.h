@@ -1,0 +1,173 @@
+/*
+ * nhsem.h -- C ABI of the MI355X (gfx950) library for the hot path of the
+ * element-based Galerkin nonhydrostatic model of Kang, Giraldo & Camp
+ * (arXiv 2504.08157): the right-hand side of the perturbation-form Euler
+ * equations on hexahedral LGL spectral elements, its direct stiffness
+ * summation, and SSP-RK stage updates.
+ *
+ * Conventions (every entry point):
+ *   - Return value: nh_status; NH_OK on success.  No exception crosses the
+ *     ABI and the library never exits the process.  Arguments are validated
+ *     before any device work; a failed HIP call makes the context sticky
+ *     (NH_ESTATE for every later call); nh_last_error returns the text.
+ *   - Memory: the library never allocates device memory.  The caller sizes a
+ *     workspace with nh_workspace_bytes, allocates it (e.g. a torch uint8
+ *     tensor) and passes its device address; every pointer is borrowed and
+ *     must stay valid while the context uses it.
+ *   - Streams: a context is bound to one HIP stream (hipStream_t passed as
+ *     void*; NULL = default stream).  Calls enqueue asynchronously; only
+ *     calls that return host data synchronise that stream.
+ *   - Threading: a context is not thread-safe.
+ *   - Layout: states and node fields are FP64, field-major [f][U] with fields
+ *     (rho', u, v, w, theta') and unique node index
+ *     I = ix + n_x (iy + n_y iz), x fastest.  Element-local vectors
+ *     ("E-vectors") are [f][e][k][j][i] with e = ex + nel_x (ey + nel_y ez).
+ *   - Mesh: an axis-aligned box of nel_x x nel_y x nel_z hexahedra with
+ *     strictly increasing element edges (the paper's limited-area domain is
+ *     such a box, Sec. 4.1).  x and y are periodic or no-flux walls; z is
+ *     always no-flux at z = 0 and z = H.  Lattice sizes:
+ *     n_x = nel_x N + (periodic_x ? 0 : 1), n_y likewise, n_z = nel_z N + 1.
+ */
+#ifndef NHSEM_H
+#define NHSEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t nh_status;
+#define NH_OK 0
+#define NH_EINVAL (-1)        /* invalid argument; nothing was enqueued */
+#define NH_ESTATE (-2)        /* context is in a sticky error state */
+#define NH_EHIP (-3)          /* a HIP runtime call failed */
+#define NH_ENOCONV (-4)       /* an iterative solve did not converge */
+#define NH_ENONFINITE (-5)    /* NaN or Inf found in the state */
+#define NH_EUNSUPPORTED (-6)  /* valid request this build does not support */
+#define NH_ESPACE (-7)        /* workspace too small */
+
+#define NH_FP64 0             /* all element arithmetic in FP64 */
+#define NH_FP32_MIXED 1       /* element contractions and fluxes in FP32; EOS,
+                                 reference subtraction, DSS sums and RK
+                                 accumulation in FP64; every array stays FP64 */
+
+#define NH_DSS_SUM 0          /* out_I = sum_{(e,l)->I} in_(e,l) */
+#define NH_DSS_MASS_AVG 1     /* out_I = sum w_i w_j w_k J^e in_(e,l) / M_I */
+
+typedef struct nh_ctx nh_ctx;
+
+typedef struct {
+    int32_t nel[3];           /* elements per direction, >= 1 */
+    int32_t order;            /* polynomial order N, 2..6 */
+    const double *xe;         /* host, nel[0]+1 strictly increasing edges */
+    const double *ye;         /* host, nel[1]+1 */
+    const double *ze;         /* host, nel[2]+1 */
+    int32_t periodic[2];      /* x, y: 1 periodic, 0 no-flux walls */
+    int32_t precision;        /* NH_FP64 or NH_FP32_MIXED */
+} nh_mesh_desc;
+
+typedef struct {
+    double g, R, cp, cv, p_a; /* gravity, gas constant, heat capacities,
+                                 reference pressure of the EOS (Sec. 2.1) */
+    double f;                 /* f-plane Coriolis parameter [1/s] */
+    double sponge_z0;         /* Rayleigh sponge bottom [m] */
+    double sponge_tau;        /* sponge maximum rate [1/s]; 0 disables.
+                                 tau(z) = tau_max sin^2(pi/2 (z-z0)/(H-z0)),
+                                 applied to u, v, w, theta' */
+} nh_physics;
+
+/* Library version string (static storage). */
+const char *nh_version(void);
+
+/* Bytes of device workspace a context for this mesh needs.
+   NH_EINVAL for an invalid descriptor. */
+nh_status nh_workspace_bytes(const nh_mesh_desc *mesh, size_t *bytes);
+
+/* Create a context: LGL basis (Sec. 2.2), lattice numbering (the implicit
+   form of Algorithm 1's intma for a tensor box), per-direction metric and
+   DSS weights, diagonal mass (Eq. governing:matrix).  dev_ws: device
+   workspace of at least nh_workspace_bytes (256-byte aligned).  The state
+   starts at zero, the reference state is unset (nh_set_reference is
+   required before nh_rhs / nh_rk_step).  On error *out is NULL. */
+nh_status nh_init_mesh(const nh_mesh_desc *mesh, const nh_physics *phys, void *dev_ws,
+                       size_t ws_bytes, void *hip_stream, nh_ctx **out);
+
+/* Rebind the context to another HIP stream. */
+nh_status nh_set_stream(nh_ctx *ctx, void *hip_stream);
+
+/* Switch element arithmetic between NH_FP64 and NH_FP32_MIXED. */
+nh_status nh_set_precision(nh_ctx *ctx, int32_t precision);
+
+/* Sizes: U unique nodes, L local nodes (E (N+1)^3), lattice n[3]. */
+nh_status nh_sizes(const nh_ctx *ctx, int64_t *U, int64_t *L, int32_t n[3]);
+
+/* Host copies of the lattice coordinates x[n_x], y[n_y], z[n_z]. */
+nh_status nh_lattice_coords(const nh_ctx *ctx, double *x, double *y, double *z);
+
+/* Reference state per lattice level (host arrays of n_z doubles):
+   rho0(z), theta0(z) in hydrostatic balance (Sec. 2.1).  The library sets
+   p0 = p_a (rho0 R theta0 / p_a)^gamma so that a resting reference has
+   p' = 0 exactly, and the discrete vertical derivative of theta0. */
+nh_status nh_set_reference(nh_ctx *ctx, const double *rho0_z, const double *theta0_z);
+
+/* Prescribed forcing added to the tendency of one field: field 4 is the
+   heating source S_theta of Eq. governing:theta (observed heating in the
+   paper, Sec. 4.1; synthetic snapshots here); any field is accepted (e.g.
+   manufactured solutions).  nsnap snapshots at host times t_snap (strictly
+   increasing), device array dev_snap [nsnap][U] (BORROWED, not copied).  The
+   value at time t is the linear interpolation between the bracketing
+   snapshots, held constant outside [t_0, t_last].  nsnap = 0 removes it. */
+nh_status nh_set_forcing(nh_ctx *ctx, int32_t field, int32_t nsnap, const double *t_snap,
+                         const double *dev_snap);
+
+/* Copy a device state [5][U] into / out of the context. */
+nh_status nh_set_state(nh_ctx *ctx, const double *dev_q);
+nh_status nh_get_state(const nh_ctx *ctx, double *dev_q);
+
+/* Device pointer to the context's current state [5][U] (borrowed). */
+nh_status nh_state_ptr(nh_ctx *ctx, double **dev_q);
+
+/* dq/dt = M^{-1} DSS(w J S(q)) at time t (Eq. governing:matrix with S of
+   Eq. governing, hyper-diffusion excluded), with the wall-normal velocity
+   tendency zeroed on no-flux boundaries.  dev_q, dev_dqdt: device [5][U],
+   must not overlap. */
+nh_status nh_rhs(nh_ctx *ctx, double t, const double *dev_q, double *dev_dqdt);
+
+/* Advance the context state nsteps SSP-RK3 steps of size dt from time t:
+     q1 = q + dt R(q, t); q2 = 3/4 q + 1/4 (q1 + dt R(q1, t+dt));
+     q  = 1/3 q + 2/3 (q2 + dt R(q2, t+dt/2)). */
+nh_status nh_rk_step(nh_ctx *ctx, double t, double dt, int32_t nsteps);
+
+/* Direct stiffness summation (Algorithm 3, gather): dev_E [nfields][L]
+   element-local values -> dev_out [nfields][U] (mode NH_DSS_SUM or
+   NH_DSS_MASS_AVG).  Contributions of a node are summed in ascending
+   element order (deterministic, no atomics). */
+nh_status nh_dss(nh_ctx *ctx, int32_t nfields, int32_t mode, const double *dev_E, double *dev_out);
+
+/* Global-to-local scatter (Algorithm 1 gather, Algorithm 3 scatter):
+   dev_E[f][e][k][j][i] = dev_U[f][intma(i,j,k,e)]. */
+nh_status nh_scatter(nh_ctx *ctx, int32_t nfields, const double *dev_U, double *dev_E);
+
+/* Diagonal mass M_I [U] into device memory. */
+nh_status nh_mass(nh_ctx *ctx, double *dev_M);
+
+/* Diagnostics of the current state (synchronises the stream), host out[8]:
+   0 sum M rho', 1 max|u|, 2 max|v|, 3 max|w|, 4 min theta', 5 max theta',
+   6 sum M theta', 7 number of non-finite values. */
+nh_status nh_diagnostics(nh_ctx *ctx, double out[8]);
+
+/* NH_ENONFINITE if the state holds a NaN or Inf (synchronises). */
+nh_status nh_check_finite(nh_ctx *ctx);
+
+/* Text of the last error (always NUL-terminated when n > 0). */
+nh_status nh_last_error(const nh_ctx *ctx, char *buf, size_t n);
+
+/* Destroy the context (host memory only; the workspace stays the caller's). */
+nh_status nh_destroy(nh_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NHSEM_H */

@@ -1,0 +1,68 @@
+// Internal declarations shared by the host layer and the gfx950 kernels of
+// libnhsem.  Not part of the public ABI (see include/nhsem.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nh {
+
+constexpr int kMaxN = 6;
+constexpr int kMaxN1 = kMaxN + 1;
+constexpr int kLevW = 8;   // per-level table row: rho0 theta0 p0 dtheta0/dz tau wlo whi pad
+constexpr int kNF = 5;     // prognostic fields rho', u, v, w, theta'
+constexpr int kDiagBlocks = 512;
+constexpr int kEosTerms = 14;  // binomial-series terms of the EOS perturbation
+
+// Arguments of one fused RHS / SSP-RK stage launch.
+//   out = a * qn + b * qs + c * R(qs)
+// (a = b = 0, c = 1 evaluates the right-hand side alone).
+struct StageParams {
+    const double *qs;      // [5][U] state the tendency is evaluated at
+    const double *qn;      // [5][U] state at the start of the step (read iff a != 0)
+    double *out;           // [5][U]
+    double a, b, c;
+    const double *gx;      // [n_x][2N+1] DSS'd first-derivative stencil along x
+    const double *gy;      // [n_y][2N+1]
+    const float *gxf;      // FP32 copies for the mixed-precision path
+    const float *gyf;
+    const double *lev;     // [n_z][kLevW]
+    const double *hz2;     // [nel_z] 2 / h_z of each element layer
+    const double *cst;     // [kCst]: D (row-major, (N+1)^2) then the EOS series
+    const double *hq0;     // theta' forcing snapshot below t (or null)
+    const double *hq1;     // theta' forcing snapshot above t
+    double hlam;           // interpolation weight of hq1
+    int nx, ny, nz, nelz;
+    int perx, pery;
+    int ntx, nty;
+    double fcor, g, gamma;
+};
+
+// Layout of the constant table StageParams::cst.
+constexpr int kCstD = 0;                          // D[i][j] = h_j'(xi_i), (N+1)^2 entries
+constexpr int kCstEos = kMaxN1 * kMaxN1;          // C(gamma, n+1), n = 0..kEosTerms-1
+constexpr int kCst = kCstEos + kEosTerms;
+
+struct GeomParams {
+    int N, nelx, nely, nelz, nx, ny, nz, perx, pery;
+    const double *mx, *my, *mz;   // 1D assembled masses per lattice index
+    const double *wlgl;           // [N+1] LGL weights
+    const double *hx, *hy, *hz;   // element sizes
+};
+
+hipError_t launch_stage(int N, int precision, const StageParams &p, hipStream_t s);
+struct WallParams {
+    int nx, ny, nz, perx, pery;
+};
+
+hipError_t launch_add_forcing(const WallParams &wp, int field, double c, const double *f0, const double *f1,
+                              double lam, double *out, hipStream_t s);
+hipError_t launch_dss(const GeomParams &g, int nfields, int mode, const double *E, double *out,
+                      hipStream_t s);
+hipError_t launch_scatter(const GeomParams &g, int nfields, const double *Uv, double *E,
+                          hipStream_t s);
+hipError_t launch_mass(const GeomParams &g, double *M, hipStream_t s);
+hipError_t launch_diag(const GeomParams &g, const double *q, double *partials, double *out8,
+                       hipStream_t s);
+void stage_tile(int N, int precision, int *tx, int *ty);
+
+}  // namespace nh

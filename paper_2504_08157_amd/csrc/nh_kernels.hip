@@ -1,0 +1,602 @@
+// gfx950 kernels of libnhsem: the fused right-hand side / SSP-RK stage of the
+// perturbation-form Euler equations on LGL hexahedral elements (Eq. governing,
+// Eq. governing:matrix, Algorithms 1-3 of Kang, Giraldo & Camp), the
+// element-based DSS gather and scatter, the diagonal mass and diagnostics.
+//
+// Design of the stage kernel (one launch per RK stage):
+//   * The mesh is an axis-aligned tensor box, so the metric of element e is
+//     diag(2/h_x, 2/h_y, 2/h_z) and its quadrature weight factorises,
+//     w_i w_j w_k J^e = (w_i h_x/2)(w_j h_y/2)(w_k h_z/2).  Every term of S is
+//     a pointwise coefficient times one first derivative, so
+//       M_I^{-1} sum_{(i,e)->I} w J S  =  pointwise(I)
+//         + sum_d coef_d(I) * [ sum_{e_d ∋ I_d} m_d(e_d) d_d^{(e_d)} f(I) ] / M_d(I_d)
+//     -- the 3D direct stiffness summation collapses into one mass-weighted
+//     average of one-sided element derivatives per direction.  This is the
+//     same discrete operator as gather -> element contraction -> DSS -> M^{-1}
+//     (up to rounding), evaluated without element-local copies in HBM, without
+//     atomics, and with every unique node written exactly once.
+//   * x/y: the averaged derivative is a (2N+1)-point stencil along the
+//     lattice line with host-built coefficients (zero outside the one or two
+//     elements that share the node).  z: element-local contractions on a
+//     per-thread register column, with the lower element's contribution at a
+//     shared level carried in registers.
+//   * A workgroup owns a TX x TY tile of lattice columns (aligned to element
+//     boundaries) and marches upward one level at a time.  Each level's
+//     derived fields (p', u, v, w, theta', rho) for the tile and its halo
+//     (N nodes before, 1 after, in x and y) are staged in LDS (double
+//     buffered, one barrier per level); the EOS is evaluated once per staged
+//     node.  HBM traffic per node and stage: read q^s (40 B), q^n (40 B, when
+//     used), forcing (16 B), write q^{s+1} (40 B).
+#include "nh_internal.h"
+
+#include <math.h>
+
+namespace nh {
+
+// ---------------------------------------------------------------- EOS
+// p' = p0 ((1+a)(1+b))^gamma - p0 with a = rho'/rho0, b = theta'/theta0: the
+// equation of state p = p_a (rho R theta / p_a)^gamma (Sec. 2.1) relative to
+// p0 = EOS(rho0, theta0), written without cancellation.  s = a + b + ab is
+// formed without FMA contraction.  For |s| < 1/16 the binomial series
+// sum_{n=1}^{14} C(gamma, n) s^n (coefficients from the host; the first
+// omitted term is below 1e-19 of the result) replaces expm1(gamma log1p(s)).
+__device__ __noinline__ double pow_ratio_slow(double s, double gam)
+{
+    return expm1(gam * log1p(s));
+}
+
+__device__ __forceinline__ double pert_pressure(double rp, double tp, double rho0, double th0,
+                                                double p0, double gam, const double *eosc)
+{
+    const double a = rp / rho0;
+    const double b = tp / th0;
+    const double s = __dadd_rn(__dadd_rn(a, b), __dmul_rn(a, b));
+    double r;
+    if (fabs(s) < 0.0625) {
+        double acc = eosc[kEosTerms - 1];
+#pragma unroll
+        for (int n = kEosTerms - 2; n >= 0; --n) acc = fma(acc, s, eosc[n]);
+        r = acc * s;
+    } else {
+        r = pow_ratio_slow(s, gam);
+    }
+    return p0 * r;
+}
+
+// ---------------------------------------------------------------- stage
+// Workgroup shape of the stage kernel: tile of TX x TY lattice columns
+// (AX x AY elements), one thread per owned node of a z-element slab
+// (N levels x TX x TY), at most 1024 threads.
+template <int N, int AX, int AY>
+struct StageShape {
+    static constexpr int N1 = N + 1;
+    static constexpr int TX = AX * N, TY = AY * N, NCOL = TX * TY;
+    static constexpr int NOWN = N * NCOL;
+    static constexpr int NT0 = NOWN < 1024 ? NOWN : 1024;
+    static constexpr int NT = (NT0 + 63) / 64 * 64;
+    static constexpr int PX = TX + N + 1, PY = TY + N + 1, PS = PX * PY;
+    static constexpr int NSP = NCOL + (TX + TY) * N1;   // staged nodes per plane
+    static constexpr int NC = 2 * N + 1;
+    static_assert(NT >= NCOL, "bottom-level threads must own whole columns");
+};
+
+// One RK stage (or a bare RHS) over the whole lattice.
+//
+// A workgroup owns a TX x TY tile of lattice columns and walks up the
+// z-elements.  For element ez it stages the N+1 levels ez*N .. ez*N+N of the
+// tile and its x/y halo in LDS as derived fields (p', u, v, w, theta', rho)
+// -- the bottom level is kept from the previous element -- then each thread
+// evaluates one owned node: (2N+1)-point DSS'd derivative stencils along x
+// and y on its level, the one-sided z derivative inside the element from the
+// LDS column, sources, and the RK combination.  The element below's
+// contribution at the shared bottom level is carried in registers by the
+// threads that own the bottom level (same threads for every element).
+template <int N, int AX, int AY, typename T>
+__global__ void __launch_bounds__((StageShape<N, AX, AY>::NT))
+stage_kernel(const StageParams p)
+{
+    using S = StageShape<N, AX, AY>;
+    constexpr int N1 = S::N1, TX = S::TX, TY = S::TY, NCOL = S::NCOL, NOWN = S::NOWN;
+    constexpr int NT = S::NT, PX = S::PX, PS = S::PS, NSP = S::NSP, NC = S::NC;
+    constexpr bool kF64 = sizeof(T) == 8;
+
+    // Plane slots, plus N rows of padding: stencil taps past the last row of
+    // a plane read finite padding or the next plane (always with a zero
+    // coefficient), so tap addresses need no clamping.
+    __shared__ T plbuf[N1 * 6 * PS + N * PX];
+    T(*pl)[6][PS] = reinterpret_cast<T(*)[6][PS]>(plbuf);
+    __shared__ T cx[TX * NC];
+    __shared__ T cy[TY * NC];
+    __shared__ T sD[N1 * N1];
+    __shared__ double sE[kEosTerms];
+
+    const int tid = threadIdx.x;
+    const int bx = blockIdx.x % p.ntx, by = blockIdx.x / p.ntx;
+    const int x0 = bx * TX, y0 = by * TY;
+    const uint32_t nx = p.nx, ny = p.ny;
+    const uint32_t plane_bytes = nx * ny * 8u;
+    const uint64_t field_bytes = (uint64_t)plane_bytes * (uint32_t)p.nz;
+
+    for (int i = tid; i < TX * NC; i += NT) {
+        const int xg = x0 + i / NC;
+        if constexpr (kF64)
+            cx[i] = (xg < p.nx) ? p.gx[(long)xg * NC + i % NC] : 0.0;
+        else
+            cx[i] = (xg < p.nx) ? p.gxf[(long)xg * NC + i % NC] : 0.0f;
+    }
+    for (int i = tid; i < TY * NC; i += NT) {
+        const int yg = y0 + i / NC;
+        if constexpr (kF64)
+            cy[i] = (yg < p.ny) ? p.gy[(long)yg * NC + i % NC] : 0.0;
+        else
+            cy[i] = (yg < p.ny) ? p.gyf[(long)yg * NC + i % NC] : 0.0f;
+    }
+    for (int i = tid; i < N1 * N1; i += NT) sD[i] = T(p.cst[kCstD + i]);
+    for (int i = tid; i < kEosTerms; i += NT) sE[i] = p.cst[kCstEos + i];
+    // slots that are never staged (plane corners, padding) stay zero
+    for (int i = tid; i < N1 * 6 * PS + N * PX; i += NT) plbuf[i] = T(0);
+    __syncthreads();
+
+    // Stage node s (0 <= s < NSP) of level k into plane slot k mod (N+1).
+    auto stage = [&](int k, int s) {
+        int px, py;
+        if (s < NCOL) {
+            px = N + s % TX;
+            py = N + s / TX;
+        } else if (s < NCOL + TY * N1) {
+            const int s1 = s - NCOL, c = s1 % N1;
+            px = (c < N) ? c : N + TX;
+            py = N + s1 / N1;
+        } else {
+            const int s2 = s - NCOL - TY * N1, r = s2 / TX;
+            px = N + s2 % TX;
+            py = (r < N) ? r : N + TY;
+        }
+        int xg = x0 + px - N, yg = y0 + py - N;
+        bool ok = true;
+        if (xg < 0 || xg >= p.nx) {
+            if (p.perx) xg = (xg + p.nx) % p.nx; else ok = false;
+        }
+        if (yg < 0 || yg >= p.ny) {
+            if (p.pery) yg = (yg + p.ny) % p.ny; else ok = false;
+        }
+        double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0, v4 = 0.0, pp = 0.0, rho = 0.0;
+        if (ok) {
+            const double *L = p.lev + (long)k * kLevW;
+            const uint32_t o = ((uint32_t)xg + nx * (uint32_t)yg) * 8u + plane_bytes * (uint32_t)k;
+            const char *b = (const char *)p.qs + o;
+            v0 = *(const double *)(b);
+            v1 = *(const double *)(b + field_bytes);
+            v2 = *(const double *)(b + 2 * field_bytes);
+            v3 = *(const double *)(b + 3 * field_bytes);
+            v4 = *(const double *)(b + 4 * field_bytes);
+            pp = pert_pressure(v0, v4, L[0], L[1], L[2], p.gamma, sE);
+            rho = L[0] + v0;
+        }
+        T(*P)[PS] = pl[k % N1];
+        const int idx = py * PX + px;
+        P[0][idx] = T(pp);
+        P[1][idx] = T(v1);
+        P[2][idx] = T(v2);
+        P[3][idx] = T(v3);
+        P[4][idx] = T(v4);
+        P[5][idx] = T(rho);
+    };
+
+    // x/y part of the tendency at (tx, ty) of plane slot `sl`, plus the own
+    // fields (p', u, v, w, theta', rho).
+    // NH_FENCE: compiler-only memory fence between phases.  It stops the
+    // scheduler from front-loading every LDS read of the x, y and z
+    // contractions at once (which spills at the 1024-thread register budget).
+#define NH_FENCE() __builtin_amdgcn_sched_barrier(0)
+    // NH_PIN: ties the accumulators to an ordered point so instruction
+    // selection cannot defer the FMAs of a tap past the loads of later taps.
+#define NH_PIN(a)                                                                        \
+    asm volatile("" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]))
+    auto horizontal = [&](int sl, int tx, int ty, T *own, T *XY) {
+        NH_FENCE();
+        const T(*P)[PS] = pl[sl];
+        T dx[6], dy[6];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) { dx[f] = T(0); dy[f] = T(0); }
+        const int rowx = (N + ty) * PX;
+#pragma unroll
+        for (int m = 0; m < NC; ++m) {
+            const T c = cx[tx * NC + m];
+            const int j = rowx + tx + m;
+            dx[0] += c * P[0][j];
+            dx[1] += c * P[1][j];
+            dx[2] += c * P[2][j];
+            dx[3] += c * P[3][j];
+            dx[4] += c * P[4][j];
+            dx[5] += c * (P[5][j] * P[1][j]);
+            NH_PIN(dx);
+        }
+        NH_FENCE();
+#pragma unroll
+        for (int m = 0; m < NC; ++m) {
+            const T c = cy[ty * NC + m];
+            const int j = (ty + m) * PX + N + tx;
+            dy[0] += c * P[0][j];
+            dy[1] += c * P[1][j];
+            dy[2] += c * P[2][j];
+            dy[3] += c * P[3][j];
+            dy[4] += c * P[4][j];
+            dy[5] += c * (P[5][j] * P[2][j]);
+            NH_PIN(dy);
+        }
+        NH_FENCE();
+        const int jo = rowx + N + tx;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) own[f] = P[f][jo];
+        const T u = own[1], v = own[2];
+        const T inv = T(1) / own[5];
+        XY[0] = -(dx[5] + dy[5]);
+        XY[1] = -(u * dx[1] + v * dy[1]) - dx[0] * inv;
+        XY[2] = -(u * dx[2] + v * dy[2]) - dy[0] * inv;
+        XY[3] = -(u * dx[3] + v * dy[3]);
+        XY[4] = -(u * dx[4] + v * dy[4]);
+    };
+
+    // one-sided z derivative at local level r of element ez (column (tx,ty))
+    auto zderiv = [&](int ez, int r, int tx, int ty, T h2, T *dz) {
+        NH_FENCE();
+        const int jo = (N + ty) * PX + N + tx;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) dz[f] = T(0);
+#pragma unroll
+        for (int m = 0; m < N1; ++m) {
+            const T(*P)[PS] = pl[(ez * N + m) % N1];
+            const T d = sD[r * N1 + m];
+            const T w = P[3][jo];
+            dz[0] += d * P[0][jo];
+            dz[1] += d * P[1][jo];
+            dz[2] += d * P[2][jo];
+            dz[3] += d * w;
+            dz[4] += d * P[4][jo];
+            dz[5] += d * (P[5][jo] * w);
+            NH_PIN(dz);
+        }
+#pragma unroll
+        for (int f = 0; f < 6; ++f) dz[f] *= h2;
+    };
+
+    // Complete the tendency at level k and write a q^n + b q^s + c R.  Every
+    // thread runs the arithmetic (coordinates clamped into the lattice) and
+    // only the stores are predicated: a conditional use would let the
+    // compiler sink the contractions into the branch and keep every loaded
+    // LDS value alive across it.
+    auto finish = [&](int k, int gx0, int gy0, const T *own, const T *XY, const T *dz) {
+        NH_FENCE();
+        const bool valid = gx0 < p.nx && gy0 < p.ny;
+        const int gx = valid ? gx0 : 0, gy = valid ? gy0 : 0;
+        const double *L = p.lev + (long)k * kLevW;
+        const uint32_t o = ((uint32_t)gx + nx * (uint32_t)gy) * 8u + plane_bytes * (uint32_t)k;
+        const double rho0 = L[0];
+        const T u = own[1], v = own[2], w = own[3];
+        const T inv = T(1) / own[5];
+        const T tau = T(L[4]);
+        const char *qb = (const char *)p.qs + o;
+        double qs[5];
+        qs[0] = *(const double *)(qb);
+        qs[1] = *(const double *)(qb + field_bytes);
+        qs[2] = *(const double *)(qb + 2 * field_bytes);
+        qs[3] = *(const double *)(qb + 3 * field_bytes);
+        qs[4] = *(const double *)(qb + 4 * field_bytes);
+        const T rp = kF64 ? T(qs[0]) : T(own[5] - T(rho0));
+        T R[5];
+        R[0] = XY[0] - dz[5];
+        R[1] = XY[1] - w * dz[1] + T(p.fcor) * v - tau * u;
+        R[2] = XY[2] - w * dz[2] - T(p.fcor) * u - tau * v;
+        R[3] = XY[3] - w * dz[3] - dz[0] * inv - T(p.g) * rp * inv - tau * w;
+        R[4] = XY[4] - w * (dz[4] + T(L[3])) - tau * own[4];
+        double Rd[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) Rd[f] = double(R[f]);
+        if (p.hq0)
+            Rd[4] += (1.0 - p.hlam) * *(const double *)((const char *)p.hq0 + o) +
+                     p.hlam * *(const double *)((const char *)p.hq1 + o);
+        if (!p.perx && (gx == 0 || gx == p.nx - 1)) Rd[1] = 0.0;
+        if (!p.pery && (gy == 0 || gy == p.ny - 1)) Rd[2] = 0.0;
+        if (k == 0 || k == p.nz - 1) Rd[3] = 0.0;
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+            double r = p.b * qs[f] + p.c * Rd[f];
+            if (p.a != 0.0) r += p.a * *(const double *)((const char *)p.qn + o + f * field_bytes);
+            if (valid) *(double *)((char *)p.out + o + f * field_bytes) = r;
+        }
+    };
+
+    T carry[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) carry[f] = T(0);
+
+    for (int s = tid; s < NSP; s += NT) stage(0, s);
+    for (int ez = 0; ez < p.nelz; ++ez) {
+        for (int i = tid; i < N * NSP; i += NT) stage(ez * N + 1 + i / NSP, i % NSP);
+        __syncthreads();
+        const T h2 = T(p.hz2[ez]);
+        for (int idx = tid; idx < NOWN; idx += NT) {
+            const int l = idx / NCOL, col = idx % NCOL;
+            const int tx = col % TX, ty = col / TX;
+            const int gx = x0 + tx, gy = y0 + ty;
+            const int k = ez * N + l;
+            T own[6], XY[5], dz[6];
+            horizontal(k % N1, tx, ty, own, XY);
+            zderiv(ez, l, tx, ty, h2, dz);
+            if (l == 0) {
+                const T whi = T(p.lev[(long)k * kLevW + 6]);
+#pragma unroll
+                for (int f = 0; f < 6; ++f) dz[f] = whi * dz[f] + carry[f];
+                T dt[6];
+                zderiv(ez, N, tx, ty, h2, dt);
+                const T wlo = T(p.lev[(long)(k + N) * kLevW + 5]);
+#pragma unroll
+                for (int f = 0; f < 6; ++f) carry[f] = wlo * dt[f];
+            }
+            finish(k, gx, gy, own, XY, dz);
+        }
+        __syncthreads();
+    }
+    // top level: only the contribution of the element below
+    const int ktop = p.nz - 1;
+    for (int col = tid; col < NCOL; col += NT) {
+        const int tx = col % TX, ty = col / TX;
+        const int gx = x0 + tx, gy = y0 + ty;
+        T own[6], XY[5];
+        horizontal(ktop % N1, tx, ty, own, XY);
+        finish(ktop, gx, gy, own, XY, carry);
+    }
+#undef NH_FENCE
+#undef NH_PIN
+}
+
+#define NH_TILE_CASES(X) \
+    X(2, 8, 8)           \
+    X(3, 5, 5)           \
+    X(4, 4, 4)           \
+    X(5, 3, 2)           \
+    X(6, 2, 2)
+
+void stage_tile(int N, int precision, int *tx, int *ty)
+{
+    (void)precision;
+    switch (N) {
+#define NH_TILE(NN, AX, AY) case NN: *tx = AX * NN; *ty = AY * NN; return;
+        NH_TILE_CASES(NH_TILE)
+#undef NH_TILE
+    default: *tx = *ty = 0;
+    }
+}
+
+hipError_t launch_stage(int N, int precision, const StageParams &p, hipStream_t s)
+{
+    const dim3 grid(p.ntx * p.nty);
+    switch (N) {
+#define NH_LAUNCH(NN, AX, AY)                                                                  \
+    case NN:                                                                                   \
+        if (precision == 0)                                                                    \
+            hipLaunchKernelGGL((stage_kernel<NN, AX, AY, double>), grid,                       \
+                               dim3(StageShape<NN, AX, AY>::NT), 0, s, p);                     \
+        else                                                                                   \
+            hipLaunchKernelGGL((stage_kernel<NN, AX, AY, float>), grid,                        \
+                               dim3(StageShape<NN, AX, AY>::NT), 0, s, p);                     \
+        break;
+        NH_TILE_CASES(NH_LAUNCH)
+#undef NH_LAUNCH
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Forcing of fields other than theta' (manufactured solutions):
+// out += c ((1 - lam) f0 + lam f1), elementwise, except where the no-flux
+// condition fixes the tendency of that field (u on x-walls, v on y-walls,
+// w at z = 0 and z = H).
+__global__ void add_forcing_kernel(WallParams wp, int field, double c, const double *__restrict__ f0,
+                                   const double *__restrict__ f1, double lam, double *__restrict__ out)
+{
+    const long n = (long)wp.nx * wp.ny * wp.nz;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const int ix = (int)(i % wp.nx), iy = (int)((i / wp.nx) % wp.ny), iz = (int)(i / ((long)wp.nx * wp.ny));
+        bool wall = false;
+        if (field == 1) wall = !wp.perx && (ix == 0 || ix == wp.nx - 1);
+        if (field == 2) wall = !wp.pery && (iy == 0 || iy == wp.ny - 1);
+        if (field == 3) wall = (iz == 0 || iz == wp.nz - 1);
+        if (!wall) out[i] += c * ((1.0 - lam) * f0[i] + lam * f1[i]);
+    }
+}
+
+// ---------------------------------------------------------------- DSS / scatter
+// Elements sharing lattice index `i` along one direction, ascending element
+// index: up to two (element, local position) pairs.
+__device__ __forceinline__ int owners(int i, int N, int nel, int n, int per, int *e, int *loc)
+{
+    const int eq = i / N, r = i % N;
+    if (r != 0) { e[0] = eq; loc[0] = r; return 1; }
+    int c = 0;
+    int el = eq - 1, er = eq;
+    if (el < 0) el = per ? nel - 1 : -1;
+    if (er >= nel) er = per ? 0 : -1;
+    (void)n;
+    if (el >= 0 && er >= 0 && el > er) {
+        e[c] = er; loc[c] = 0; ++c;
+        e[c] = el; loc[c] = N; ++c;
+    } else {
+        if (el >= 0) { e[c] = el; loc[c] = N; ++c; }
+        if (er >= 0) { e[c] = er; loc[c] = 0; ++c; }
+    }
+    return c;
+}
+
+__global__ void dss_kernel(GeomParams g, int nfields, int mode, const double *__restrict__ E,
+                           double *__restrict__ out)
+{
+    const long U = (long)g.nx * g.ny * g.nz;
+    const int N1 = g.N + 1;
+    const long np = (long)N1 * N1 * N1;
+    const long L = (long)g.nelx * g.nely * g.nelz * np;
+    for (long I = blockIdx.x * (long)blockDim.x + threadIdx.x; I < U; I += (long)gridDim.x * blockDim.x) {
+        const int ix = (int)(I % g.nx), iy = (int)((I / g.nx) % g.ny), iz = (int)(I / ((long)g.nx * g.ny));
+        int ex[2], lx[2], ey[2], ly[2], ez[2], lz[2];
+        const int cxn = owners(ix, g.N, g.nelx, g.nx, g.perx, ex, lx);
+        const int cyn = owners(iy, g.N, g.nely, g.ny, g.pery, ey, ly);
+        const int czn = owners(iz, g.N, g.nelz, g.nz, 0, ez, lz);
+        for (int f = 0; f < nfields; ++f) {
+            double acc = 0.0;
+            for (int c = 0; c < czn; ++c)
+                for (int b = 0; b < cyn; ++b)
+                    for (int a = 0; a < cxn; ++a) {
+                        const long e = ex[a] + (long)g.nelx * (ey[b] + (long)g.nely * ez[c]);
+                        double v = E[f * L + e * np + lx[a] + N1 * (ly[b] + N1 * lz[c])];
+                        if (mode == 1) {
+                            const double J = g.hx[ex[a]] * g.hy[ey[b]] * g.hz[ez[c]] / 8.0;
+                            v = g.wlgl[lx[a]] * g.wlgl[ly[b]] * g.wlgl[lz[c]] * J * v;
+                        }
+                        acc += v;
+                    }
+            if (mode == 1) acc /= g.mx[ix] * g.my[iy] * g.mz[iz];
+            out[f * U + I] = acc;
+        }
+    }
+}
+
+__global__ void scatter_kernel(GeomParams g, int nfields, const double *__restrict__ Uv,
+                               double *__restrict__ E)
+{
+    const long U = (long)g.nx * g.ny * g.nz;
+    const int N1 = g.N + 1;
+    const long np = (long)N1 * N1 * N1;
+    const long L = (long)g.nelx * g.nely * g.nelz * np;
+    for (long m = blockIdx.x * (long)blockDim.x + threadIdx.x; m < L; m += (long)gridDim.x * blockDim.x) {
+        const long e = m / np;
+        const int loc = (int)(m % np);
+        const int i = loc % N1, j = (loc / N1) % N1, k = loc / (N1 * N1);
+        const int ex = (int)(e % g.nelx), ey = (int)((e / g.nelx) % g.nely), ez = (int)(e / ((long)g.nelx * g.nely));
+        int ix = ex * g.N + i, iy = ey * g.N + j;
+        const int iz = ez * g.N + k;
+        if (g.perx && ix == g.nx) ix = 0;
+        if (g.pery && iy == g.ny) iy = 0;
+        const long I = ix + (long)g.nx * (iy + (long)g.ny * iz);
+        for (int f = 0; f < nfields; ++f) E[f * L + m] = Uv[f * U + I];
+    }
+}
+
+__global__ void mass_kernel(GeomParams g, double *__restrict__ M)
+{
+    const long U = (long)g.nx * g.ny * g.nz;
+    for (long I = blockIdx.x * (long)blockDim.x + threadIdx.x; I < U; I += (long)gridDim.x * blockDim.x) {
+        const int ix = (int)(I % g.nx), iy = (int)((I / g.nx) % g.ny), iz = (int)(I / ((long)g.nx * g.ny));
+        M[I] = g.mx[ix] * g.my[iy] * g.mz[iz];
+    }
+}
+
+// Diagnostics: block partials [kDiagBlocks][8] then one block folds them in a
+// fixed order (deterministic).
+__global__ void __launch_bounds__(256) diag_partial_kernel(GeomParams g, const double *__restrict__ q,
+                                                           double *__restrict__ part)
+{
+    const long U = (long)g.nx * g.ny * g.nz;
+    double s_m = 0, mu = 0, mv = 0, mw = 0, tmin = INFINITY, tmax = -INFINITY, s_t = 0, bad = 0;
+    for (long I = blockIdx.x * (long)blockDim.x + threadIdx.x; I < U; I += (long)gridDim.x * blockDim.x) {
+        const int ix = (int)(I % g.nx), iy = (int)((I / g.nx) % g.ny), iz = (int)(I / ((long)g.nx * g.ny));
+        const double M = g.mx[ix] * g.my[iy] * g.mz[iz];
+        const double r = q[I], u = q[U + I], v = q[2 * U + I], w = q[3 * U + I], t = q[4 * U + I];
+        s_m += M * r;
+        s_t += M * t;
+        mu = fmax(mu, fabs(u));
+        mv = fmax(mv, fabs(v));
+        mw = fmax(mw, fabs(w));
+        tmin = fmin(tmin, t);
+        tmax = fmax(tmax, t);
+        bad += (double)(!isfinite(r)) + !isfinite(u) + !isfinite(v) + !isfinite(w) + !isfinite(t);
+    }
+    __shared__ double sh[8][256];
+    const int t = threadIdx.x;
+    sh[0][t] = s_m; sh[1][t] = mu; sh[2][t] = mv; sh[3][t] = mw;
+    sh[4][t] = tmin; sh[5][t] = tmax; sh[6][t] = s_t; sh[7][t] = bad;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+            sh[0][t] += sh[0][t + h];
+            sh[1][t] = fmax(sh[1][t], sh[1][t + h]);
+            sh[2][t] = fmax(sh[2][t], sh[2][t + h]);
+            sh[3][t] = fmax(sh[3][t], sh[3][t + h]);
+            sh[4][t] = fmin(sh[4][t], sh[4][t + h]);
+            sh[5][t] = fmax(sh[5][t], sh[5][t + h]);
+            sh[6][t] += sh[6][t + h];
+            sh[7][t] += sh[7][t + h];
+        }
+        __syncthreads();
+    }
+    if (t < 8) part[blockIdx.x * 8 + t] = sh[t][0];
+}
+
+__global__ void __launch_bounds__(64) diag_final_kernel(const double *__restrict__ part, int nb,
+                                                        double *__restrict__ out)
+{
+    if (threadIdx.x != 0) return;
+    double r[8] = {0, 0, 0, 0, INFINITY, -INFINITY, 0, 0};
+    for (int b = 0; b < nb; ++b) {
+        const double *pp = part + b * 8;
+        r[0] += pp[0];
+        r[1] = fmax(r[1], pp[1]);
+        r[2] = fmax(r[2], pp[2]);
+        r[3] = fmax(r[3], pp[3]);
+        r[4] = fmin(r[4], pp[4]);
+        r[5] = fmax(r[5], pp[5]);
+        r[6] += pp[6];
+        r[7] += pp[7];
+    }
+    for (int i = 0; i < 8; ++i) out[i] = r[i];
+}
+
+static int grid_for(long n, int block)
+{
+    long g = (n + block - 1) / block;
+    if (g > 65535) g = 65535;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+hipError_t launch_add_forcing(const WallParams &wp, int field, double c, const double *f0, const double *f1,
+                              double lam, double *out, hipStream_t s)
+{
+    const long n = (long)wp.nx * wp.ny * wp.nz;
+    hipLaunchKernelGGL(add_forcing_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, wp, field, c, f0, f1, lam,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_dss(const GeomParams &g, int nfields, int mode, const double *E, double *out,
+                      hipStream_t s)
+{
+    const long U = (long)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(dss_kernel, dim3(grid_for(U, 256)), dim3(256), 0, s, g, nfields, mode, E, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const GeomParams &g, int nfields, const double *Uv, double *E, hipStream_t s)
+{
+    const long N1 = g.N + 1;
+    const long L = (long)g.nelx * g.nely * g.nelz * N1 * N1 * N1;
+    hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(L, 256)), dim3(256), 0, s, g, nfields, Uv, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_mass(const GeomParams &g, double *M, hipStream_t s)
+{
+    const long U = (long)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(mass_kernel, dim3(grid_for(U, 256)), dim3(256), 0, s, g, M);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(const GeomParams &g, const double *q, double *partials, double *out8, hipStream_t s)
+{
+    hipLaunchKernelGGL(diag_partial_kernel, dim3(kDiagBlocks), dim3(256), 0, s, g, q, partials);
+    hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(64), 0, s, partials, kDiagBlocks, out8);
+    return hipGetLastError();
+}
+
+}  // namespace nh
