@@ -33,6 +33,7 @@ def parse():
     ap.add_argument("--workload", default="tc_large", choices=["tc_large", "tc_small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-nel", type=int, default=48, help="horizontal elements of the oracle sample box")
+    ap.add_argument("--tile", type=int, default=-1, help="stage-kernel tile variant; -1 = tune by timing")
     return ap.parse_args()
 
 
@@ -87,6 +88,20 @@ def main():
     torch.cuda.synchronize()
 
     dt = w.dt
+    tile = args.tile
+    tune = {}
+    if tile < 0:
+        # tile autotuning: time each variant over a few steps, keep the fastest
+        for v in (0, 1):
+            ctx.nh_set_tile(v)
+            ctx.nh_rk_step(0.0, dt, 2)
+            e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(); ctx.nh_rk_step(0.0, dt, 5); e1.record()
+            torch.cuda.synchronize()
+            tune[v] = e0.elapsed_time(e1) / 5
+        tile = min(tune, key=tune.get)
+        ctx.nh_set_state(q0)
+    ctx.nh_set_tile(tile)
     ctx.nh_rk_step(0.0, dt, args.warmup)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
@@ -127,6 +142,8 @@ def main():
             "dof_convention": "unique nodes x 5 fields; paper convention (E (N+1)^3 x 5) = "
                               f"{value * ctx.L / U:.4e}",
             "dt": dt, "precision": args.precision,
+            "tile_variant": tile, "tile_columns": list(nhsem.nh_tile_shape(w.mesh.order, tile)),
+            "tile_ms_per_step": {str(k): v for k, v in tune.items()},
             "parallelism": "single GPU",
         },
         "roofline": {

@@ -100,6 +100,16 @@ nh_status nh_set_stream(nh_ctx *ctx, void *hip_stream);
 /* Switch element arithmetic between NH_FP64 and NH_FP32_MIXED. */
 nh_status nh_set_precision(nh_ctx *ctx, int32_t precision);
 
+/* Workgroup tile of the stage kernel: variant 0 (default) covers about
+   16 x 16 lattice columns per workgroup (one workgroup per CU), variant 1 half
+   of that in y (two workgroups per CU).  Both compute every node with the
+   same arithmetic in the same order, so results are bitwise identical.
+   Chosen by the caller's tuner from measured times.  NH_EINVAL otherwise. */
+nh_status nh_set_tile(nh_ctx *ctx, int32_t variant);
+
+/* Columns per tile (tx x ty) of a variant for order N (no context needed). */
+nh_status nh_tile_shape(int32_t order, int32_t variant, int32_t *tx, int32_t *ty);
+
 /* Sizes: U unique nodes, L local nodes (E (N+1)^3), lattice n[3]. */
 nh_status nh_sizes(const nh_ctx *ctx, int64_t *U, int64_t *L, int32_t n[3]);
 

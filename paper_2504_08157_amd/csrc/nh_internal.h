@@ -8,7 +8,8 @@ namespace nh {
 
 constexpr int kMaxN = 6;
 constexpr int kMaxN1 = kMaxN + 1;
-constexpr int kLevW = 8;   // per-level table row: rho0 theta0 p0 dtheta0/dz tau wlo whi pad
+// per-level table row: rho0 theta0 p0 dtheta0/dz tau wlo whi 1/rho0 1/theta0 pad
+constexpr int kLevW = 10;
 constexpr int kNF = 5;     // prognostic fields rho', u, v, w, theta'
 constexpr int kDiagBlocks = 512;
 constexpr int kEosTerms = 14;  // binomial-series terms of the EOS perturbation
@@ -49,7 +50,7 @@ struct GeomParams {
     const double *hx, *hy, *hz;   // element sizes
 };
 
-hipError_t launch_stage(int N, int precision, const StageParams &p, hipStream_t s);
+hipError_t launch_stage(int N, int precision, int variant, const StageParams &p, hipStream_t s);
 struct WallParams {
     int nx, ny, nz, perx, pery;
 };
@@ -63,6 +64,7 @@ hipError_t launch_scatter(const GeomParams &g, int nfields, const double *Uv, do
 hipError_t launch_mass(const GeomParams &g, double *M, hipStream_t s);
 hipError_t launch_diag(const GeomParams &g, const double *q, double *partials, double *out8,
                        hipStream_t s);
-void stage_tile(int N, int precision, int *tx, int *ty);
+void stage_tile(int N, int variant, int *tx, int *ty);
+constexpr int kTileVariants = 2;
 
 }  // namespace nh

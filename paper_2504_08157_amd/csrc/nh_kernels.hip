@@ -36,8 +36,9 @@ namespace nh {
 // ---------------------------------------------------------------- EOS
 // p' = p0 ((1+a)(1+b))^gamma - p0 with a = rho'/rho0, b = theta'/theta0: the
 // equation of state p = p_a (rho R theta / p_a)^gamma (Sec. 2.1) relative to
-// p0 = EOS(rho0, theta0), written without cancellation.  s = a + b + ab is
-// formed without FMA contraction.  For |s| < 1/16 the binomial series
+// p0 = EOS(rho0, theta0), written without cancellation (a and b use the
+// reciprocals 1/rho0, 1/theta0 of the level table).  s = a + b + ab is formed
+// without FMA contraction.  For |s| < 1/16 the binomial series
 // sum_{n=1}^{14} C(gamma, n) s^n (coefficients from the host; the first
 // omitted term is below 1e-19 of the result) replaces expm1(gamma log1p(s)).
 __device__ __noinline__ double pow_ratio_slow(double s, double gam)
@@ -45,11 +46,11 @@ __device__ __noinline__ double pow_ratio_slow(double s, double gam)
     return expm1(gam * log1p(s));
 }
 
-__device__ __forceinline__ double pert_pressure(double rp, double tp, double rho0, double th0,
+__device__ __forceinline__ double pert_pressure(double rp, double tp, double inv_rho0, double inv_th0,
                                                 double p0, double gam, const double *eosc)
 {
-    const double a = rp / rho0;
-    const double b = tp / th0;
+    const double a = rp * inv_rho0;
+    const double b = tp * inv_th0;
     const double s = __dadd_rn(__dadd_rn(a, b), __dmul_rn(a, b));
     double r;
     if (fabs(s) < 0.0625) {
@@ -66,14 +67,14 @@ __device__ __forceinline__ double pert_pressure(double rp, double tp, double rho
 // ---------------------------------------------------------------- stage
 // Workgroup shape of the stage kernel: tile of TX x TY lattice columns
 // (AX x AY elements), one thread per owned node of a z-element slab
-// (N levels x TX x TY), at most 1024 threads.
+// (N levels x TX x TY, at most 1024).
 template <int N, int AX, int AY>
 struct StageShape {
     static constexpr int N1 = N + 1;
     static constexpr int TX = AX * N, TY = AY * N, NCOL = TX * TY;
     static constexpr int NOWN = N * NCOL;
-    static constexpr int NT0 = NOWN < 1024 ? NOWN : 1024;
-    static constexpr int NT = (NT0 + 63) / 64 * 64;
+    static constexpr int NT = (NOWN + 63) / 64 * 64;
+    static_assert(NT <= 1024, "one thread per owned node of a slab");
     static constexpr int PX = TX + N + 1, PY = TY + N + 1, PS = PX * PY;
     static constexpr int NSP = NCOL + (TX + TY) * N1;   // staged nodes per plane
     static constexpr int NC = 2 * N + 1;
@@ -84,7 +85,7 @@ struct StageShape {
 //
 // A workgroup owns a TX x TY tile of lattice columns and walks up the
 // z-elements.  For element ez it stages the N+1 levels ez*N .. ez*N+N of the
-// tile and its x/y halo in LDS as derived fields (p', u, v, w, theta', rho)
+// tile and its x/y halo in LDS as (p', u, v, w, theta', rho')
 // -- the bottom level is kept from the previous element -- then each thread
 // evaluates one owned node: (2N+1)-point DSS'd derivative stencils along x
 // and y on its level, the one-sided z derivative inside the element from the
@@ -160,7 +161,7 @@ stage_kernel(const StageParams p)
         if (yg < 0 || yg >= p.ny) {
             if (p.pery) yg = (yg + p.ny) % p.ny; else ok = false;
         }
-        double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0, v4 = 0.0, pp = 0.0, rho = 0.0;
+        double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0, v4 = 0.0, pp = 0.0;
         if (ok) {
             const double *L = p.lev + (long)k * kLevW;
             const uint32_t o = ((uint32_t)xg + nx * (uint32_t)yg) * 8u + plane_bytes * (uint32_t)k;
@@ -170,8 +171,7 @@ stage_kernel(const StageParams p)
             v2 = *(const double *)(b + 2 * field_bytes);
             v3 = *(const double *)(b + 3 * field_bytes);
             v4 = *(const double *)(b + 4 * field_bytes);
-            pp = pert_pressure(v0, v4, L[0], L[1], L[2], p.gamma, sE);
-            rho = L[0] + v0;
+            pp = pert_pressure(v0, v4, L[7], L[8], L[2], p.gamma, sE);
         }
         T(*P)[PS] = pl[k % N1];
         const int idx = py * PX + px;
@@ -180,11 +180,11 @@ stage_kernel(const StageParams p)
         P[2][idx] = T(v2);
         P[3][idx] = T(v3);
         P[4][idx] = T(v4);
-        P[5][idx] = T(rho);
+        P[5][idx] = T(v0);
     };
 
-    // x/y part of the tendency at (tx, ty) of plane slot `sl`, plus the own
-    // fields (p', u, v, w, theta', rho).
+    // x/y part of the tendency at (tx, ty) of plane slot `sl` (reference
+    // density r0 of that level), plus the own fields (p', u, v, w, theta', rho').
     // NH_FENCE: compiler-only memory fence between phases.  It stops the
     // scheduler from front-loading every LDS read of the x, y and z
     // contractions at once (which spills at the 1024-thread register budget).
@@ -193,7 +193,7 @@ stage_kernel(const StageParams p)
     // selection cannot defer the FMAs of a tap past the loads of later taps.
 #define NH_PIN(a)                                                                        \
     asm volatile("" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]))
-    auto horizontal = [&](int sl, int tx, int ty, T *own, T *XY) {
+    auto horizontal = [&](int sl, T r0, int tx, int ty, T *own, T *XY, T &inv) {
         NH_FENCE();
         const T(*P)[PS] = pl[sl];
         T dx[6], dy[6];
@@ -209,7 +209,7 @@ stage_kernel(const StageParams p)
             dx[2] += c * P[2][j];
             dx[3] += c * P[3][j];
             dx[4] += c * P[4][j];
-            dx[5] += c * (P[5][j] * P[1][j]);
+            dx[5] += c * ((r0 + P[5][j]) * P[1][j]);
             NH_PIN(dx);
         }
         NH_FENCE();
@@ -222,7 +222,7 @@ stage_kernel(const StageParams p)
             dy[2] += c * P[2][j];
             dy[3] += c * P[3][j];
             dy[4] += c * P[4][j];
-            dy[5] += c * (P[5][j] * P[2][j]);
+            dy[5] += c * ((r0 + P[5][j]) * P[2][j]);
             NH_PIN(dy);
         }
         NH_FENCE();
@@ -230,7 +230,7 @@ stage_kernel(const StageParams p)
 #pragma unroll
         for (int f = 0; f < 6; ++f) own[f] = P[f][jo];
         const T u = own[1], v = own[2];
-        const T inv = T(1) / own[5];
+        inv = T(1) / (r0 + own[5]);
         XY[0] = -(dx[5] + dy[5]);
         XY[1] = -(u * dx[1] + v * dy[1]) - dx[0] * inv;
         XY[2] = -(u * dx[2] + v * dy[2]) - dy[0] * inv;
@@ -249,41 +249,59 @@ stage_kernel(const StageParams p)
             const T(*P)[PS] = pl[(ez * N + m) % N1];
             const T d = sD[r * N1 + m];
             const T w = P[3][jo];
+            const T r0 = T(p.lev[(long)(ez * N + m) * kLevW]);
             dz[0] += d * P[0][jo];
             dz[1] += d * P[1][jo];
             dz[2] += d * P[2][jo];
             dz[3] += d * w;
             dz[4] += d * P[4][jo];
-            dz[5] += d * (P[5][jo] * w);
+            dz[5] += d * ((r0 + P[5][jo]) * w);
             NH_PIN(dz);
         }
 #pragma unroll
         for (int f = 0; f < 6; ++f) dz[f] *= h2;
     };
 
-    // Complete the tendency at level k and write a q^n + b q^s + c R.  Every
-    // thread runs the arithmetic (coordinates clamped into the lattice) and
-    // only the stores are predicated: a conditional use would let the
-    // compiler sink the contractions into the branch and keep every loaded
-    // LDS value alive across it.
-    auto finish = [&](int k, int gx0, int gy0, const T *own, const T *XY, const T *dz) {
+    // Loads of the node's own global data (q^n, heating) issued before the
+    // contractions so their latency overlaps them.  Every thread runs the
+    // arithmetic (coordinates clamped into the lattice) and only the stores
+    // are predicated: a conditional use would let the compiler sink the
+    // contractions into the branch and keep every loaded LDS value alive.
+    struct NodeIn {
+        uint32_t o;
+        bool valid;
+        double qn[5], h0, h1;
+    };
+    auto prefetch = [&](int k, int gx0, int gy0, NodeIn &nd) {
+        nd.valid = gx0 < p.nx && gy0 < p.ny;
+        const int gx = nd.valid ? gx0 : 0, gy = nd.valid ? gy0 : 0;
+        nd.o = ((uint32_t)gx + nx * (uint32_t)gy) * 8u + plane_bytes * (uint32_t)k;
+#pragma unroll
+        for (int f = 0; f < 5; ++f)
+            nd.qn[f] = (p.a != 0.0) ? *(const double *)((const char *)p.qn + nd.o + f * field_bytes) : 0.0;
+        nd.h0 = p.hq0 ? *(const double *)((const char *)p.hq0 + nd.o) : 0.0;
+        nd.h1 = p.hq0 ? *(const double *)((const char *)p.hq1 + nd.o) : 0.0;
+    };
+
+    // Complete the tendency at level k and write a q^n + b q^s + c R.
+    auto finish = [&](int k, int gx0, int gy0, const NodeIn &nd, const T *own, const T *XY, const T *dz,
+                      const T inv) {
         NH_FENCE();
-        const bool valid = gx0 < p.nx && gy0 < p.ny;
+        const bool valid = nd.valid;
         const int gx = valid ? gx0 : 0, gy = valid ? gy0 : 0;
         const double *L = p.lev + (long)k * kLevW;
-        const uint32_t o = ((uint32_t)gx + nx * (uint32_t)gy) * 8u + plane_bytes * (uint32_t)k;
-        const double rho0 = L[0];
+        const uint32_t o = nd.o;
         const T u = own[1], v = own[2], w = own[3];
-        const T inv = T(1) / own[5];
+        const T rp = own[5];
         const T tau = T(L[4]);
-        const char *qb = (const char *)p.qs + o;
         double qs[5];
-        qs[0] = *(const double *)(qb);
-        qs[1] = *(const double *)(qb + field_bytes);
-        qs[2] = *(const double *)(qb + 2 * field_bytes);
-        qs[3] = *(const double *)(qb + 3 * field_bytes);
-        qs[4] = *(const double *)(qb + 4 * field_bytes);
-        const T rp = kF64 ? T(qs[0]) : T(own[5] - T(rho0));
+        if constexpr (kF64) {
+            qs[0] = own[5]; qs[1] = own[1]; qs[2] = own[2]; qs[3] = own[3]; qs[4] = own[4];
+        } else {
+            const char *qb = (const char *)p.qs + o;
+#pragma unroll
+            for (int f = 0; f < 5; ++f) qs[f] = *(const double *)(qb + f * field_bytes);
+        }
         T R[5];
         R[0] = XY[0] - dz[5];
         R[1] = XY[1] - w * dz[1] + T(p.fcor) * v - tau * u;
@@ -293,16 +311,13 @@ stage_kernel(const StageParams p)
         double Rd[5];
 #pragma unroll
         for (int f = 0; f < 5; ++f) Rd[f] = double(R[f]);
-        if (p.hq0)
-            Rd[4] += (1.0 - p.hlam) * *(const double *)((const char *)p.hq0 + o) +
-                     p.hlam * *(const double *)((const char *)p.hq1 + o);
+        if (p.hq0) Rd[4] += (1.0 - p.hlam) * nd.h0 + p.hlam * nd.h1;
         if (!p.perx && (gx == 0 || gx == p.nx - 1)) Rd[1] = 0.0;
         if (!p.pery && (gy == 0 || gy == p.ny - 1)) Rd[2] = 0.0;
         if (k == 0 || k == p.nz - 1) Rd[3] = 0.0;
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
-            double r = p.b * qs[f] + p.c * Rd[f];
-            if (p.a != 0.0) r += p.a * *(const double *)((const char *)p.qn + o + f * field_bytes);
+            const double r = p.a * nd.qn[f] + p.b * qs[f] + p.c * Rd[f];
             if (valid) *(double *)((char *)p.out + o + f * field_bytes) = r;
         }
     };
@@ -321,8 +336,10 @@ stage_kernel(const StageParams p)
             const int tx = col % TX, ty = col / TX;
             const int gx = x0 + tx, gy = y0 + ty;
             const int k = ez * N + l;
-            T own[6], XY[5], dz[6];
-            horizontal(k % N1, tx, ty, own, XY);
+            T own[6], XY[5], dz[6], inv;
+            NodeIn nd;
+            prefetch(k, gx, gy, nd);
+            horizontal(k % N1, T(p.lev[(long)k * kLevW]), tx, ty, own, XY, inv);
             zderiv(ez, l, tx, ty, h2, dz);
             if (l == 0) {
                 const T whi = T(p.lev[(long)k * kLevW + 6]);
@@ -334,7 +351,7 @@ stage_kernel(const StageParams p)
 #pragma unroll
                 for (int f = 0; f < 6; ++f) carry[f] = wlo * dt[f];
             }
-            finish(k, gx, gy, own, XY, dz);
+            finish(k, gx, gy, nd, own, XY, dz, inv);
         }
         __syncthreads();
     }
@@ -343,44 +360,58 @@ stage_kernel(const StageParams p)
     for (int col = tid; col < NCOL; col += NT) {
         const int tx = col % TX, ty = col / TX;
         const int gx = x0 + tx, gy = y0 + ty;
-        T own[6], XY[5];
-        horizontal(ktop % N1, tx, ty, own, XY);
-        finish(ktop, gx, gy, own, XY, carry);
+        T own[6], XY[5], inv;
+        NodeIn nd;
+        prefetch(ktop, gx, gy, nd);
+        horizontal(ktop % N1, T(p.lev[(long)ktop * kLevW]), tx, ty, own, XY, inv);
+        finish(ktop, gx, gy, nd, own, XY, carry, inv);
     }
 #undef NH_FENCE
 #undef NH_PIN
 }
 
+// Tile shapes per order (AX x AY elements).  Variant 0 uses rows of 32 (or
+// 30) lattice columns so that each half-wave's stencil reads cover one
+// contiguous 256-byte LDS row (bank-conflict free); variant 1 is a squarer
+// ~16 x 16 tile with a smaller halo.
 #define NH_TILE_CASES(X) \
-    X(2, 8, 8)           \
-    X(3, 5, 5)           \
-    X(4, 4, 4)           \
-    X(5, 3, 2)           \
-    X(6, 2, 2)
+    X(2, 16, 4, 8, 8)    \
+    X(3, 10, 3, 5, 5)    \
+    X(4, 8, 2, 4, 4)     \
+    X(5, 6, 1, 3, 2)     \
+    X(6, 4, 1, 2, 2)
 
-void stage_tile(int N, int precision, int *tx, int *ty)
+void stage_tile(int N, int variant, int *tx, int *ty)
 {
-    (void)precision;
     switch (N) {
-#define NH_TILE(NN, AX, AY) case NN: *tx = AX * NN; *ty = AY * NN; return;
+#define NH_TILE(NN, AX0, AY0, AX1, AY1)                 \
+    case NN:                                            \
+        *tx = (variant ? AX1 : AX0) * NN;               \
+        *ty = (variant ? AY1 : AY0) * NN;               \
+        return;
         NH_TILE_CASES(NH_TILE)
 #undef NH_TILE
     default: *tx = *ty = 0;
     }
 }
 
-hipError_t launch_stage(int N, int precision, const StageParams &p, hipStream_t s)
+template <int N, int AX, int AY>
+static void launch_one(int precision, const StageParams &p, hipStream_t s)
 {
-    const dim3 grid(p.ntx * p.nty);
+    const dim3 grid(p.ntx * p.nty), block(StageShape<N, AX, AY>::NT);
+    if (precision == 0)
+        hipLaunchKernelGGL((stage_kernel<N, AX, AY, double>), grid, block, 0, s, p);
+    else
+        hipLaunchKernelGGL((stage_kernel<N, AX, AY, float>), grid, block, 0, s, p);
+}
+
+hipError_t launch_stage(int N, int precision, int variant, const StageParams &p, hipStream_t s)
+{
     switch (N) {
-#define NH_LAUNCH(NN, AX, AY)                                                                  \
-    case NN:                                                                                   \
-        if (precision == 0)                                                                    \
-            hipLaunchKernelGGL((stage_kernel<NN, AX, AY, double>), grid,                       \
-                               dim3(StageShape<NN, AX, AY>::NT), 0, s, p);                     \
-        else                                                                                   \
-            hipLaunchKernelGGL((stage_kernel<NN, AX, AY, float>), grid,                        \
-                               dim3(StageShape<NN, AX, AY>::NT), 0, s, p);                     \
+#define NH_LAUNCH(NN, AX0, AY0, AX1, AY1)                              \
+    case NN:                                                           \
+        if (variant) launch_one<NN, AX1, AY1>(precision, p, s);        \
+        else launch_one<NN, AX0, AY0>(precision, p, s);                \
         break;
         NH_TILE_CASES(NH_LAUNCH)
 #undef NH_LAUNCH

@@ -21,7 +21,7 @@
 using namespace nh;
 
 struct nh_ctx {
-    int N, nel[3], per[2], n[3], precision;
+    int N, nel[3], per[2], n[3], precision, tile;
     int64_t U, L;
     std::vector<double> xe, ye, ze;
     std::vector<double> xi, w, D;       // LGL basis
@@ -292,7 +292,7 @@ StageParams stage_params(const nh_ctx *c, double t, const double *qs, const doub
     p.nx = c->n[0]; p.ny = c->n[1]; p.nz = c->n[2]; p.nelz = c->nel[2];
     p.perx = c->per[0]; p.pery = c->per[1];
     int tx, ty;
-    stage_tile(c->N, c->precision, &tx, &ty);
+    stage_tile(c->N, c->tile, &tx, &ty);
     p.ntx = (c->n[0] + tx - 1) / tx;
     p.nty = (c->n[1] + ty - 1) / ty;
     p.fcor = c->phys.f; p.g = c->phys.g; p.gamma = c->phys.cp / c->phys.cv;
@@ -305,7 +305,7 @@ hipError_t run_stage(nh_ctx *c, double t, const double *qs, const double *qn, do
                      double b, double cc)
 {
     const StageParams p = stage_params(c, t, qs, qn, out, a, b, cc);
-    hipError_t e = launch_stage(c->N, c->precision, p, c->stream);
+    hipError_t e = launch_stage(c->N, c->precision, c->tile, p, c->stream);
     for (int f = 0; f < 4 && e == hipSuccess; ++f) {
         if (c->nsnap[f] == 0) continue;
         const double *f0, *f1;
@@ -359,6 +359,7 @@ nh_status nh_init_mesh(const nh_mesh_desc *mesh, const nh_physics *phys, void *d
     c->U = (int64_t)c->n[0] * c->n[1] * c->n[2];
     c->L = (int64_t)mesh->nel[0] * mesh->nel[1] * mesh->nel[2] * (c->N + 1) * (c->N + 1) * (c->N + 1);
     c->precision = mesh->precision;
+    c->tile = 0;
     c->xe.assign(mesh->xe, mesh->xe + mesh->nel[0] + 1);
     c->ye.assign(mesh->ye, mesh->ye + mesh->nel[1] + 1);
     c->ze.assign(mesh->ze, mesh->ze + mesh->nel[2] + 1);
@@ -449,6 +450,26 @@ nh_status nh_set_precision(nh_ctx *c, int32_t precision)
     return NH_OK;
 }
 
+nh_status nh_set_tile(nh_ctx *c, int32_t variant)
+{
+    nh_status st = guard(c);
+    if (st) return st;
+    if (variant < 0 || variant >= kTileVariants) return fail(c, NH_EINVAL, "tile variant must be 0 or 1");
+    c->tile = variant;
+    return NH_OK;
+}
+
+nh_status nh_tile_shape(int32_t order, int32_t variant, int32_t *tx, int32_t *ty)
+{
+    if (order < 2 || order > kMaxN || variant < 0 || variant >= kTileVariants || !tx || !ty)
+        return fail(nullptr, NH_EINVAL, "bad order or tile variant");
+    int a, b;
+    stage_tile(order, variant, &a, &b);
+    *tx = a;
+    *ty = b;
+    return NH_OK;
+}
+
 nh_status nh_sizes(const nh_ctx *c, int64_t *U, int64_t *L, int32_t n[3])
 {
     if (!c) return fail(nullptr, NH_EINVAL, "null context");
@@ -511,7 +532,9 @@ nh_status nh_set_reference(nh_ctx *c, const double *rho0, const double *theta0)
         }
         r[5] = wlo;
         r[6] = whi;
-        r[7] = 0.0;
+        r[7] = 1.0 / rho0[k];
+        r[8] = 1.0 / theta0[k];
+        r[9] = 0.0;
     }
     HIPCHK(c, hipMemcpyAsync(c->lev, c->levtab.data(), sizeof(double) * c->levtab.size(),
                              hipMemcpyHostToDevice, c->stream));

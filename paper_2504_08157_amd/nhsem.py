@@ -58,6 +58,9 @@ _SIGS = {
                                       ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
     "nh_set_stream": (ctypes.c_int32, [_vp, _vp]),
     "nh_set_precision": (ctypes.c_int32, [_vp, ctypes.c_int32]),
+    "nh_set_tile": (ctypes.c_int32, [_vp, ctypes.c_int32]),
+    "nh_tile_shape": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32)]),
     "nh_sizes": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                   ctypes.POINTER(ctypes.c_int32)]),
     "nh_lattice_coords": (ctypes.c_int32, [_vp, _dp, _dp, _dp]),
@@ -166,6 +169,12 @@ def nh_init_mesh(desc, phys, ws, stream=None):
     return out
 
 
+def nh_tile_shape(order, variant):
+    tx = ctypes.c_int32(); ty = ctypes.c_int32()
+    _check(None, load().nh_tile_shape(int(order), int(variant), ctypes.byref(tx), ctypes.byref(ty)))
+    return tx.value, ty.value
+
+
 class Context:
     """Owns a workspace tensor and a library context for one mesh."""
 
@@ -210,6 +219,9 @@ class Context:
 
     def nh_set_precision(self, precision):
         self._c(self.lib.nh_set_precision(self.h, int(precision)))
+
+    def nh_set_tile(self, variant):
+        self._c(self.lib.nh_set_tile(self.h, int(variant)))
 
     def nh_lattice_coords(self):
         x = np.zeros(self.nx); y = np.zeros(self.ny); z = np.zeros(self.nz)

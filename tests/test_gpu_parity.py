@@ -186,3 +186,18 @@ def test_fp32_mixed_rhs_close(oracle_mod):
     err = _rel(dq, orc.rhs(0.0, qo))
     print("fp32", err)
     assert (err <= 1e-4).all(), err
+
+
+@pytest.mark.parametrize("N", [3, 4, 5])
+def test_tile_variants_bitwise_equal(oracle_mod, N):
+    from paper_2504_08157_amd import nhsem
+    ph = W.Physics(f=1e-4, sponge_z0=500.0, sponge_tau=0.01)
+    ctx, orc, g, o, prof, torch = _pair(oracle_mod, _mesh((7, 5, 3), N, (True, False)), ph)
+    q = torch.from_numpy(W.smooth_random_state(*g, *prof(g[2]), seed=4, walls=(False, True))).cuda()
+    outs = []
+    for v in (0, 1):
+        ctx.nh_set_tile(v)
+        outs.append(ctx.nh_rhs(0.0, q).cpu().numpy())
+    np.testing.assert_array_equal(outs[0], outs[1])
+    with pytest.raises(nhsem.NHError):
+        ctx.nh_set_tile(2)
