@@ -171,6 +171,105 @@ nh_status nh_diagnostics(nh_ctx *ctx, double out[8]);
 /* NH_ENONFINITE if the state holds a NaN or Inf (synchronises). */
 nh_status nh_check_finite(nh_ctx *ctx);
 
+/* ------------------------------------------------------------------
+ * 1D-IMEX (HEVI) step (Sec. 2.3: IMEX split S = (S - L) + L with the fast
+ * waves implicit, ARK2 "ARK(2,3,2)b", matrix-free GMRES).  Here L = L_v, the
+ * linearisation of S about the resting reference restricted to vertical
+ * derivatives; every lattice column is an independent implicit system in
+ * (rho', w, theta').
+ * ------------------------------------------------------------------ */
+typedef struct nh_mlp nh_mlp;
+typedef struct {
+    int32_t restart;          /* Krylov vectors per cycle, 1..40 (paper: < 20) */
+    int32_t max_restarts;     /* restarts before NH_ENOCONV */
+    double rtol;              /* stop when ||b - A x||_2 <= rtol ||b||_2 */
+} nh_gmres_opts;
+typedef struct {
+    int64_t columns;          /* columns per solve */
+    int64_t solves;           /* column solves counted (columns x solves per call) */
+    int64_t iters_total;      /* Arnoldi steps summed over all column solves */
+    int64_t iters_max;        /* most Arnoldi steps of one column solve */
+    int64_t not_converged;    /* column solves that missed rtol */
+} nh_solve_stats;
+
+/* Device workspace the HEVI calls need (8 state-sized arrays + counters). */
+nh_status nh_hevi_workspace_bytes(const nh_ctx *ctx, size_t *bytes);
+
+/* Attach that workspace (borrowed, 256-byte aligned). */
+nh_status nh_hevi_attach(nh_ctx *ctx, void *dev_ws, size_t bytes);
+
+/* y = L_v x on device [5][U] arrays (u, v rows of y are zero; w rows zero at
+   z = 0 and z = H). */
+nh_status nh_lv_apply(nh_ctx *ctx, const double *dev_x, double *dev_y);
+
+/* Solve (I - alpha L_v) x = b in every column by restarted matrix-free
+   GMRES (one wavefront per column, Krylov basis in LDS).  dev_b, dev_x:
+   [5][U]; the u, v fields of x are copied from b.  dev_x0: initial guess of
+   (rho', w, theta') as [3][U], or NULL for x0 = b.  dev_iters: optional
+   device int32 [n_x n_y] receiving the Arnoldi steps per column (negative:
+   -steps-1 when the column did not converge).  stats (host, optional)
+   synchronises the stream.  NH_ENOCONV if any column missed rtol. */
+nh_status nh_column_solve(nh_ctx *ctx, double alpha, const double *dev_b, const double *dev_x0,
+                          double *dev_x, const nh_gmres_opts *opts, nh_solve_stats *stats,
+                          int32_t *dev_iters);
+
+/* One HEVI ARK2 step of the context state from t to t + dt: stages
+   (I - dt At_ii L_v) Q_i = q^n + dt sum_{j<i} [A_ij (S - L_v)(Q_j) + At_ij L_v(Q_j)],
+   q^{n+1} = q^n + dt sum_j b_j S(Q_j).  guess: a trained column MLP giving
+   the initial GMRES guess, or NULL (x0 = right-hand side).  The Krylov solve
+   always runs to opts->rtol.  stats (optional, host) synchronises. */
+nh_status nh_hevi_step(nh_ctx *ctx, double t, double dt, const nh_gmres_opts *opts, nh_mlp *guess,
+                       nh_solve_stats *stats);
+
+/* ------------------------------------------------------------------
+ * Column MLP for the initial guess of the HEVI column solves (trained on
+ * solves the method itself produces; the Krylov solve still runs to the
+ * same tolerance).  Network 400 -> 256 -> 256 -> 192 with SiLU; FP16
+ * weights and activations on MFMA with FP32 accumulation in the forward
+ * pass, FP32 backward, Adam on FP32 master weights.  Parameters, in order:
+ * W1 [256][400], b1 [256], W2 [256][256], b2 [256], W3 [192][256], b3 [192].
+ * Inputs x: FP16 [batch][400] (features of nh_mlp_samples); outputs y: FP32
+ * [batch][192].  batch: multiple of 64, at most the capacity given at
+ * creation.
+ * ------------------------------------------------------------------ */
+nh_status nh_mlp_workspace_bytes(int64_t max_batch, size_t *bytes);
+
+/* Create with Glorot-uniform weights from `seed` (last layer zero, so the
+   untrained guess equals the default guess). */
+nh_status nh_mlp_create(int64_t max_batch, uint64_t seed, void *dev_ws, size_t bytes, void *hip_stream,
+                        nh_mlp **out);
+
+/* Forward pass; keeps the activations for nh_mlp_backward.  dev_y may be
+   NULL. */
+nh_status nh_mlp_forward(nh_mlp *m, int64_t batch, const void *dev_x_f16, float *dev_y);
+
+/* Gradients of sum(y * dy) with respect to every parameter for the last
+   forward pass (FP32, overwritten). */
+nh_status nh_mlp_backward(nh_mlp *m, int64_t batch, const void *dev_x_f16, const float *dev_dy);
+
+/* forward, mean-squared-error loss against dev_t [batch][192], backward,
+   Adam (Kingma & Ba, bias-corrected).  dev_loss (device float, optional). */
+nh_status nh_mlp_train_step(nh_mlp *m, int64_t batch, const void *dev_x_f16, const float *dev_t, float lr,
+                            float b1, float b2, float eps, float *dev_loss);
+
+/* Copy FP32 master parameters and/or gradients to device arrays; *n = count. */
+nh_status nh_mlp_params(nh_mlp *m, float *dev_master, float *dev_grad, int64_t *n);
+
+/* Replace the FP32 master parameters (FP16 copies refreshed, Adam reset). */
+nh_status nh_mlp_set_params(nh_mlp *m, const float *dev_master);
+
+/* Training samples / features for columns [col0, col0 + ncol) of ctx: the
+   right-hand side b of (I - alpha L_v) x = b and, if dev_x is given, the
+   solution x.  dev_feat FP16 [ncol][400], dev_scale float [ncol][3] (the
+   per-field RMS), dev_tgt float [ncol][192] (the scaled correction x - b on
+   the canonical levels; needs dev_x), dev_tmp device [5][U] scratch. */
+nh_status nh_mlp_samples(nh_mlp *m, nh_ctx *ctx, double alpha, const double *dev_b, const double *dev_x,
+                         int64_t col0, int64_t ncol, void *dev_feat, float *dev_scale, float *dev_tgt,
+                         double *dev_tmp);
+
+nh_status nh_mlp_last_error(const nh_mlp *m, char *buf, size_t n);
+nh_status nh_mlp_destroy(nh_mlp *m);
+
 /* Text of the last error (always NUL-terminated when n > 0). */
 nh_status nh_last_error(const nh_ctx *ctx, char *buf, size_t n);
 

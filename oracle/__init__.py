@@ -7,3 +7,4 @@ package never imports the GPU library.
 from .oracle import (  # noqa: F401
     Oracle, build, lgl, load, hevi_coefficients, ark2_step, ark2_generic, column_matrix,
 )
+from . import mlp_oracle  # noqa: F401,E402

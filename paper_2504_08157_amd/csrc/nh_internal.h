@@ -55,6 +55,71 @@ struct WallParams {
     int nx, ny, nz, perx, pery;
 };
 
+// ---- 1D-IMEX (HEVI)
+struct HeviParams {
+    int nx, ny, nz, N;
+    const double *lev;   // [n_z][kLevW]
+    const double *gz;    // [n_z][2N+1] DSS'd vertical derivative stencil
+    double gamma, g;
+};
+
+struct GmresArgs {
+    const double *b;     // [5][U] right-hand sides
+    const double *x0;    // [3][U] initial guess of (rho', w, theta') or null (x0 = b)
+    double *x;           // [5][U] solution
+    double alpha;        // A = I - alpha L_v
+    double rtol;
+    int restart, max_restarts;
+    int *iters;          // [n_x n_y] Arnoldi steps per column (negative: not converged), or null
+};
+
+constexpr int kMaxComb = 6;
+struct LinComb {
+    const double *src[kMaxComb];
+    double c[kMaxComb];
+};
+
+size_t gmres_lds_bytes(int nz, int N, int restart);
+hipError_t launch_lv_apply(const HeviParams &h, const double *x, double *y, hipStream_t s);
+hipError_t launch_axpy_multi(long n, const double *base, int nsrc, const LinComb &lc, double *out,
+                             hipStream_t s);
+hipError_t launch_gmres(const HeviParams &h, const GmresArgs &g, hipStream_t s);
+
+// ---- column MLP
+constexpr int kMlpIn = 400;    // 388 features padded to a multiple of 16
+constexpr int kMlpHid = 256;
+constexpr int kMlpOut = 192;   // 3 fields x 64 canonical levels
+constexpr int kMlpLossBlocks = 256;
+
+struct MlpColParams {
+    int nx, ny, nz;
+    const double *z;   // [n_z] lattice levels
+    double alpha;
+};
+
+struct MlpNet {
+    long nparam;
+    float *master, *grad, *m, *v;  // FP32 [nparam]
+    void *half;                    // FP16 [nparam]
+    const void *wh[3];             // FP16 weights inside `half`
+    float *b[3];                   // FP32 biases inside `master`
+    float *gw[3], *gb[3];          // gradients inside `grad`
+    float *Z1, *Z2, *Y, *dY, *dH, *dZ, *part, *loss;
+    void *H1, *H2;                 // FP16 activations
+    void *feat;                    // FP16 [max_batch][kMlpIn]
+    float *scale;                  // [max_batch][3]
+};
+
+hipError_t launch_mlp_features(const MlpColParams &p, const double *b, const double *lb, const double *x,
+                               long col0, long ncol, void *feat, float *scale, float *tgt, hipStream_t s);
+hipError_t launch_mlp_guess(const MlpColParams &p, const double *b, long col0, long ncol, const float *y,
+                            const float *scale, double *x0, hipStream_t s);
+hipError_t mlp_forward(const MlpNet &net, int M, const void *X, hipStream_t s);
+hipError_t mlp_backward(const MlpNet &net, int M, const void *X, const float *dY, hipStream_t s);
+hipError_t mlp_loss_grad(const MlpNet &net, int M, const float *T, float *loss, hipStream_t s);
+hipError_t mlp_adam(const MlpNet &net, float lr, float b1, float b2, float eps, int step, hipStream_t s);
+hipError_t mlp_sync_half(const MlpNet &net, hipStream_t s);
+
 hipError_t launch_add_forcing(const WallParams &wp, int field, double c, const double *f0, const double *f1,
                               double lam, double *out, hipStream_t s);
 hipError_t launch_dss(const GeomParams &g, int nfields, int mode, const double *E, double *out,

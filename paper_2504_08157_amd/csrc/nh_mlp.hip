@@ -1,0 +1,373 @@
+// gfx950 kernels of the per-column MLP that predicts the initial guess of
+// the HEVI column solves: feature extraction and resampling, FP16 MFMA
+// forward GEMMs with FP32 accumulation, FP32 backward, Adam.
+//
+// Network: x (K0 = 400: 388 features zero-padded) -> SiLU(W1 x + b1) (256)
+//          -> SiLU(W2 h1 + b2) (256) -> W3 h2 + b3 (192).
+// Features of a column with right-hand side b (fields rho', w, theta' on the
+// n_z lattice levels): each field scaled by its own RMS s_f over the column,
+// resampled linearly in z to 64 canonical levels z_c = H c / 63, for b and for
+// alpha L_v b (the first Neumann term of (I - alpha L_v)^-1); then 4 scalars
+// (log10 s_f for the three fields, alpha / 10).  Output: the correction
+// delta_f on the canonical levels, x0_f = b_f + s_f * resample^-1(delta_f).
+#include "nh_internal.h"
+
+#include <hip/hip_fp16.h>
+#include <math.h>
+
+namespace nh {
+
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+typedef float float4v __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------- features
+// canonical level c of a column with lattice levels z[0..nz-1]: interval and weight
+__device__ __forceinline__ void canon_interp(const double *z, int nz, double zc, int *k0, double *t)
+{
+    int lo = 0, hi = nz - 1;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (z[mid] <= zc) lo = mid; else hi = mid;
+    }
+    *k0 = lo;
+    *t = (zc - z[lo]) / (z[lo + 1] - z[lo]);
+    if (*t < 0.0) *t = 0.0;
+    if (*t > 1.0) *t = 1.0;
+}
+
+// One wavefront per column; lane c = canonical level c.
+__global__ void __launch_bounds__(64) mlp_features_kernel(MlpColParams p, const double *__restrict__ b,
+                                                          const double *__restrict__ lb,
+                                                          const double *__restrict__ x, long col0,
+                                                          long ncol, _Float16 *__restrict__ feat,
+                                                          float *__restrict__ scale, float *__restrict__ tgt)
+{
+    const long nxy = (long)p.nx * p.ny;
+    const long U = nxy * p.nz;
+    const int lane = threadIdx.x;
+    const int fld[3] = {0, 3, 4};
+    const double H = p.z[p.nz - 1] - p.z[0];
+    for (long r = blockIdx.x; r < ncol; r += gridDim.x) {
+        const long col = col0 + r;
+        double s[3];
+        for (int f = 0; f < 3; ++f) {
+            double a = 0.0;
+            for (int k = lane; k < p.nz; k += 64) {
+                const double v = b[fld[f] * U + col + (long)k * nxy];
+                a += v * v;
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+            s[f] = sqrt(a / p.nz) + 1e-30;
+        }
+        const double zc = p.z[0] + H * lane / 63.0;
+        int k0;
+        double t;
+        canon_interp(p.z, p.nz, zc, &k0, &t);
+        _Float16 *fr = feat + r * kMlpIn;
+        for (int f = 0; f < 3; ++f) {
+            const long I0 = fld[f] * U + col + (long)k0 * nxy, I1 = I0 + nxy;
+            const double vb = (1.0 - t) * b[I0] + t * b[I1];
+            const double vl = (1.0 - t) * lb[I0] + t * lb[I1];
+            fr[f * 64 + lane] = (_Float16)(vb / s[f]);
+            fr[192 + f * 64 + lane] = (_Float16)(p.alpha * vl / s[f]);
+            if (tgt) {
+                const double vx = (1.0 - t) * x[I0] + t * x[I1];
+                tgt[r * kMlpOut + f * 64 + lane] = (float)((vx - vb) / s[f]);
+            }
+        }
+        if (lane < 3) fr[384 + lane] = (_Float16)log10(s[lane]);
+        if (lane == 3) fr[387] = (_Float16)(p.alpha / 10.0);
+        if (lane >= 4 && lane < 4 + (kMlpIn - 388)) fr[384 + lane] = (_Float16)0.0f;
+        if (lane < 3) scale[r * 3 + lane] = (float)s[lane];
+    }
+}
+
+// x0 = b + s_f * (delta_f resampled from canonical to lattice levels), one
+// thread per lattice node of the batch.
+__global__ void mlp_guess_kernel(MlpColParams p, const double *__restrict__ b, long col0, long ncol,
+                                 const float *__restrict__ y, const float *__restrict__ scale,
+                                 double *__restrict__ x0)
+{
+    const long nxy = (long)p.nx * p.ny;
+    const long U = nxy * p.nz;
+    const int fld[3] = {0, 3, 4};
+    const double H = p.z[p.nz - 1] - p.z[0];
+    const long n = ncol * p.nz;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const long r = i % ncol;
+        const int k = (int)(i / ncol);
+        const long I = col0 + r + (long)k * nxy;
+        double c = 63.0 * (p.z[k] - p.z[0]) / H;
+        int c0 = (int)floor(c);
+        if (c0 < 0) c0 = 0;
+        if (c0 > 62) c0 = 62;
+        double t = c - c0;
+        if (t < 0.0) t = 0.0;
+        if (t > 1.0) t = 1.0;
+        for (int f = 0; f < 3; ++f) {
+            const float *yr = y + r * kMlpOut + f * 64;
+            const double d = (1.0 - t) * yr[c0] + t * yr[c0 + 1];
+            x0[f * U + I] = b[fld[f] * U + I] + (double)scale[r * 3 + f] * d;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- forward GEMM (MFMA)
+// C[M x N] = A[M x K] W[N x K]^T + bias, A and W FP16 row-major, FP32
+// accumulation on v_mfma_f32_16x16x16_f16.  Workgroup: 256 threads = 4 waves,
+// 64 x 64 tile of C, each wave a 32 x 32 quarter (2 x 2 MFMA tiles).
+// Epilogue: Z (FP32, pre-activation) and, when act != 0, H = SiLU(Z) in FP16.
+// Requires M % 64 == 0, N % 64 == 0, K % 16 == 0.
+__global__ void __launch_bounds__(256) gemm_f16_kernel(const _Float16 *__restrict__ A,
+                                                       const _Float16 *__restrict__ W,
+                                                       const float *__restrict__ bias, int M, int N, int K,
+                                                       float *__restrict__ Z, _Float16 *__restrict__ Hout,
+                                                       int act)
+{
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int m0 = blockIdx.y * 64 + (wave / 2) * 32;
+    const int n0 = blockIdx.x * 64 + (wave % 2) * 32;
+    float4v acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[a][c] = float4v{0.f, 0.f, 0.f, 0.f};
+    const int r16 = lane % 16, kq = (lane / 16) * 4;
+    for (int k = 0; k < K; k += 16) {
+        half4 av[2], bv[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const _Float16 *pa = A + (long)(m0 + a * 16 + r16) * K + k + kq;
+            av[a] = *(const half4 *)pa;
+            const _Float16 *pb = W + (long)(n0 + a * 16 + r16) * K + k + kq;
+            bv[a] = *(const half4 *)pb;
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x16f16(av[a], bv[c], acc[a][c], 0, 0, 0);
+    }
+    // output layout: lane holds rows 4*(lane/16)+i, column lane%16 of each 16x16 tile
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = m0 + a * 16 + kq + i, col = n0 + c * 16 + r16;
+                const float z = acc[a][c][i] + bias[col];
+                Z[(long)row * N + col] = z;
+                if (act) Hout[(long)row * N + col] = (_Float16)(z / (1.0f + expf(-z)));
+            }
+}
+
+// ---------------------------------------------------------------- backward (FP32)
+// C[M x N] (=, or += when accum) sum_k A(m, k) B(k, n) with element strides;
+// A, B of type TA, TB (FP16 or FP32), FP32 accumulation, 64 x 64 tiles
+// staged through LDS in K-chunks of 16.
+template <typename TA, typename TB>
+__global__ void __launch_bounds__(256) gemm_f32_kernel(const TA *__restrict__ A, long sam, long sak,
+                                                       const TB *__restrict__ B, long sbk, long sbn, int M,
+                                                       int N, int K, float *__restrict__ C)
+{
+    __shared__ float As[16][64 + 1];
+    __shared__ float Bs[16][64 + 1];
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    float acc[4][4] = {};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        for (int i = threadIdx.x; i < 16 * 64; i += 256) {
+            const int kk = i / 64, mm = i % 64;
+            const int gm = m0 + mm, gk = k0 + kk;
+            As[kk][mm] = (gm < M && gk < K) ? (float)A[gm * sam + gk * sak] : 0.f;
+            const int gn = n0 + mm;
+            Bs[kk][mm] = (gn < N && gk < K) ? (float)B[gk * sbk + gn * sbn] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            float a[4], bb[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) { a[i] = As[kk][ty * 4 + i]; bb[i] = Bs[kk][tx * 4 + i]; }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * bb[j];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int gm = m0 + ty * 4 + i, gn = n0 + tx * 4 + j;
+            if (gm < M && gn < N) C[(long)gm * N + gn] = acc[i][j];
+        }
+}
+
+// column sums: out[n] = sum_m X[m][n]
+__global__ void colsum_kernel(const float *__restrict__ X, int M, int N, float *__restrict__ out)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.f;
+    for (int m = 0; m < M; ++m) s += X[(long)m * N + n];
+    out[n] = s;
+}
+
+// dY = 2 (Y - T) / (M N), loss partials per block
+__global__ void mse_grad_kernel(const float *__restrict__ Y, const float *__restrict__ T, long n, float scale,
+                                float *__restrict__ dY, float *__restrict__ part)
+{
+    __shared__ float sh[256];
+    float a = 0.f;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const float d = Y[i] - T[i];
+        dY[i] = 2.f * d * scale;
+        a += d * d;
+    }
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void sum_kernel(const float *__restrict__ part, int n, float scale, float *__restrict__ out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        float s = 0.f;
+        for (int i = 0; i < n; ++i) s += part[i];
+        *out = s * scale;
+    }
+}
+
+// dZ = dH * SiLU'(Z),  SiLU'(z) = sig(z) (1 + z (1 - sig(z)))
+__global__ void silu_back_kernel(const float *__restrict__ dH, const float *__restrict__ Z, long n,
+                                 float *__restrict__ dZ)
+{
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const float z = Z[i];
+        const float sg = 1.f / (1.f + expf(-z));
+        dZ[i] = dH[i] * sg * (1.f + z * (1.f - sg));
+    }
+}
+
+// Adam on FP32 masters (Kingma & Ba), then FP16 copies.
+__global__ void adam_kernel(long n, const float *__restrict__ g, float *__restrict__ w, float *__restrict__ m,
+                            float *__restrict__ v, _Float16 *__restrict__ wh, float lr, float b1, float b2,
+                            float eps, float c1, float c2)
+{
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        w[i] = wi;
+        wh[i] = (_Float16)wi;
+    }
+}
+
+__global__ void to_half_kernel(long n, const float *__restrict__ w, _Float16 *__restrict__ wh)
+{
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        wh[i] = (_Float16)w[i];
+}
+
+static int grid_for(long n, int block)
+{
+    long gsz = (n + block - 1) / block;
+    if (gsz > 65535) gsz = 65535;
+    if (gsz < 1) gsz = 1;
+    return (int)gsz;
+}
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_mlp_features(const MlpColParams &p, const double *b, const double *lb, const double *x,
+                               long col0, long ncol, void *feat, float *scale, float *tgt, hipStream_t s)
+{
+    const int grid = (int)(ncol < 16384 ? ncol : 16384);
+    hipLaunchKernelGGL(mlp_features_kernel, dim3(grid), dim3(64), 0, s, p, b, lb, x, col0, ncol,
+                       (_Float16 *)feat, scale, tgt);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_guess(const MlpColParams &p, const double *b, long col0, long ncol, const float *y,
+                            const float *scale, double *x0, hipStream_t s)
+{
+    hipLaunchKernelGGL(mlp_guess_kernel, dim3(grid_for(ncol * p.nz, 256)), dim3(256), 0, s, p, b, col0, ncol, y,
+                       scale, x0);
+    return hipGetLastError();
+}
+
+hipError_t mlp_forward(const MlpNet &net, int M, const void *X, hipStream_t s)
+{
+    const dim3 blk(256);
+    hipLaunchKernelGGL(gemm_f16_kernel, dim3(kMlpHid / 64, M / 64), blk, 0, s, (const _Float16 *)X,
+                       (const _Float16 *)net.wh[0], net.b[0], M, kMlpHid, kMlpIn, net.Z1, (_Float16 *)net.H1, 1);
+    hipLaunchKernelGGL(gemm_f16_kernel, dim3(kMlpHid / 64, M / 64), blk, 0, s, (const _Float16 *)net.H1,
+                       (const _Float16 *)net.wh[1], net.b[1], M, kMlpHid, kMlpHid, net.Z2, (_Float16 *)net.H2, 1);
+    hipLaunchKernelGGL(gemm_f16_kernel, dim3(kMlpOut / 64, M / 64), blk, 0, s, (const _Float16 *)net.H2,
+                       (const _Float16 *)net.wh[2], net.b[2], M, kMlpOut, kMlpHid, net.Y, (_Float16 *)nullptr, 0);
+    return hipGetLastError();
+}
+
+hipError_t mlp_backward(const MlpNet &net, int M, const void *X, const float *dY, hipStream_t s)
+{
+    const dim3 blk(256);
+    const _Float16 *Xh = (const _Float16 *)X, *H1 = (const _Float16 *)net.H1, *H2 = (const _Float16 *)net.H2;
+    const _Float16 *W2 = (const _Float16 *)net.wh[1], *W3 = (const _Float16 *)net.wh[2];
+    // layer 3: dW3 = dY^T H2 [192 x 256], db3 = sum dY, dH2 = dY W3 [M x 256]
+    hipLaunchKernelGGL((gemm_f32_kernel<float, _Float16>), dim3(kMlpHid / 64, kMlpOut / 64), blk, 0, s, dY, 1L,
+                       (long)kMlpOut, H2, (long)kMlpHid, 1L, kMlpOut, kMlpHid, M, net.gw[2]);
+    hipLaunchKernelGGL(colsum_kernel, dim3((kMlpOut + 255) / 256), blk, 0, s, dY, M, kMlpOut, net.gb[2]);
+    hipLaunchKernelGGL((gemm_f32_kernel<float, _Float16>), dim3(kMlpHid / 64, M / 64), blk, 0, s, dY,
+                       (long)kMlpOut, 1L, W3, (long)kMlpHid, 1L, M, kMlpHid, kMlpOut, net.dH);
+    hipLaunchKernelGGL(silu_back_kernel, dim3(grid_for((long)M * kMlpHid, 256)), blk, 0, s, net.dH, net.Z2,
+                       (long)M * kMlpHid, net.dZ);
+    // layer 2
+    hipLaunchKernelGGL((gemm_f32_kernel<float, _Float16>), dim3(kMlpHid / 64, kMlpHid / 64), blk, 0, s, net.dZ,
+                       1L, (long)kMlpHid, H1, (long)kMlpHid, 1L, kMlpHid, kMlpHid, M, net.gw[1]);
+    hipLaunchKernelGGL(colsum_kernel, dim3((kMlpHid + 255) / 256), blk, 0, s, net.dZ, M, kMlpHid, net.gb[1]);
+    hipLaunchKernelGGL((gemm_f32_kernel<float, _Float16>), dim3(kMlpHid / 64, M / 64), blk, 0, s, net.dZ,
+                       (long)kMlpHid, 1L, W2, (long)kMlpHid, 1L, M, kMlpHid, kMlpHid, net.dH);
+    hipLaunchKernelGGL(silu_back_kernel, dim3(grid_for((long)M * kMlpHid, 256)), blk, 0, s, net.dH, net.Z1,
+                       (long)M * kMlpHid, net.dZ);
+    // layer 1: dW1 = dZ1^T X [256 x K0]
+    hipLaunchKernelGGL((gemm_f32_kernel<float, _Float16>), dim3((kMlpIn + 63) / 64, kMlpHid / 64), blk, 0, s,
+                       net.dZ, 1L, (long)kMlpHid, Xh, (long)kMlpIn, 1L, kMlpHid, kMlpIn, M, net.gw[0]);
+    hipLaunchKernelGGL(colsum_kernel, dim3((kMlpHid + 255) / 256), blk, 0, s, net.dZ, M, kMlpHid, net.gb[0]);
+    return hipGetLastError();
+}
+
+hipError_t mlp_loss_grad(const MlpNet &net, int M, const float *T, float *loss, hipStream_t s)
+{
+    const long n = (long)M * kMlpOut;
+    hipLaunchKernelGGL(mse_grad_kernel, dim3(kMlpLossBlocks), dim3(256), 0, s, net.Y, T, n, 1.0f / (float)n, net.dY,
+                       net.part);
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(64), 0, s, net.part, kMlpLossBlocks, 1.0f / (float)n, loss);
+    return hipGetLastError();
+}
+
+hipError_t mlp_adam(const MlpNet &net, float lr, float b1, float b2, float eps, int step, hipStream_t s)
+{
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    hipLaunchKernelGGL(adam_kernel, dim3(grid_for(net.nparam, 256)), dim3(256), 0, s, net.nparam, net.grad,
+                       net.master, net.m, net.v, (_Float16 *)net.half, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t mlp_sync_half(const MlpNet &net, hipStream_t s)
+{
+    hipLaunchKernelGGL(to_half_kernel, dim3(grid_for(net.nparam, 256)), dim3(256), 0, s, net.nparam, net.master,
+                       (_Float16 *)net.half);
+    return hipGetLastError();
+}
+
+}  // namespace nh

@@ -16,6 +16,7 @@
 #include <string.h>
 
 #include <string>
+#include <algorithm>
 #include <vector>
 
 using namespace nh;
@@ -36,7 +37,11 @@ struct nh_ctx {
     char *ws;
     size_t ws_bytes;
     double *q[3];
-    double *gx, *gy, *lev, *hz2, *mx, *my, *mz, *hx, *hy, *hz, *wl, *cst, *diag_part, *diag_out;
+    double *gx, *gy, *gz, *zl, *lev, *hz2, *mx, *my, *mz, *hx, *hy, *hz, *wl, *cst, *diag_part, *diag_out;
+    // HEVI workspace (caller-provided, see nh_hevi_attach)
+    char *hws;
+    size_t hws_bytes;
+    int *hiters;
     float *gxf, *gyf;
     // forcing
     int nsnap[kNF];
@@ -179,7 +184,7 @@ void line_tables(int N, int nel, int periodic, const double *edges, const std::v
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t q[3], gx, gy, gxf, gyf, lev, hz2, mx, my, mz, hx, hy, hz, wl, cst, dpart, dout, total;
+    size_t q[3], gx, gy, gz, zl, gxf, gyf, lev, hz2, mx, my, mz, hx, hy, hz, wl, cst, dpart, dout, total;
 };
 
 bool valid_desc(const nh_mesh_desc *m, std::string *why)
@@ -224,6 +229,8 @@ Layout layout_for(const nh_mesh_desc *m)
     for (int i = 0; i < 3; ++i) L.q[i] = take(sizeof(double) * kNF * U);
     L.gx = take(sizeof(double) * nx * nc);
     L.gy = take(sizeof(double) * ny * nc);
+    L.gz = take(sizeof(double) * nz * nc);
+    L.zl = take(sizeof(double) * nz);
     L.gxf = take(sizeof(float) * nx * nc);
     L.gyf = take(sizeof(float) * ny * nc);
     L.lev = take(sizeof(double) * nz * kLevW);
@@ -371,7 +378,9 @@ nh_status nh_init_mesh(const nh_mesh_desc *mesh, const nh_physics *phys, void *d
     c->sticky = false;
     for (int f = 0; f < kNF; ++f) { c->nsnap[f] = 0; c->snap[f] = nullptr; }
     for (int i = 0; i < 3; ++i) c->q[i] = (double *)(c->ws + L.q[i]);
-    c->gx = (double *)(c->ws + L.gx); c->gy = (double *)(c->ws + L.gy);
+    c->gx = (double *)(c->ws + L.gx); c->gy = (double *)(c->ws + L.gy); c->gz = (double *)(c->ws + L.gz);
+    c->zl = (double *)(c->ws + L.zl);
+    c->hws = nullptr; c->hws_bytes = 0; c->hiters = nullptr;
     c->gxf = (float *)(c->ws + L.gxf); c->gyf = (float *)(c->ws + L.gyf);
     c->lev = (double *)(c->ws + L.lev); c->hz2 = (double *)(c->ws + L.hz2);
     c->mx = (double *)(c->ws + L.mx); c->my = (double *)(c->ws + L.my); c->mz = (double *)(c->ws + L.mz);
@@ -410,6 +419,8 @@ nh_status nh_init_mesh(const nh_mesh_desc *mesh, const nh_physics *phys, void *d
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = up(c->gx, c->G[0].data(), sizeof(double) * c->G[0].size());
     if (e == hipSuccess) e = up(c->gy, c->G[1].data(), sizeof(double) * c->G[1].size());
+    if (e == hipSuccess) e = up(c->gz, c->G[2].data(), sizeof(double) * c->G[2].size());
+    if (e == hipSuccess) e = up(c->zl, c->lz.data(), sizeof(double) * c->lz.size());
     if (e == hipSuccess) e = up(c->gxf, gxf.data(), sizeof(float) * gxf.size());
     if (e == hipSuccess) e = up(c->gyf, gyf.data(), sizeof(float) * gyf.size());
     if (e == hipSuccess) e = up(c->hz2, hz2.data(), sizeof(double) * hz2.size());
@@ -672,6 +683,191 @@ nh_status nh_check_finite(nh_ctx *c)
     return NH_OK;
 }
 
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ HEVI
+nh_status mlp_guess(nh_mlp *m, nh_ctx *c, double alpha, const double *b, double *lb, double *x0);
+
+namespace {
+
+// ARK2 of Giraldo, Kelly & Constantinescu (2013) ("ARK(2,3,2)b", Sec. 2.3):
+// explicit A, implicit At (singly diagonally implicit), b = bt, c.
+struct Ark2 {
+    double A[3][3], At[3][3], b[3], c[3];
+    Ark2()
+    {
+        const double g = 1.0 - 1.0 / sqrt(2.0), d = 1.0 / (2.0 * sqrt(2.0)), a = (3.0 + 2.0 * sqrt(2.0)) / 6.0;
+        const double A0[3][3] = {{0, 0, 0}, {2 * g, 0, 0}, {1 - a, a, 0}};
+        const double T0[3][3] = {{0, 0, 0}, {g, g, 0}, {d, d, g}};
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) { A[i][j] = A0[i][j]; At[i][j] = T0[i][j]; }
+        b[0] = d; b[1] = d; b[2] = g;
+        c[0] = 0.0; c[1] = 2 * g; c[2] = 1.0;
+    }
+};
+
+constexpr int kHeviArrays = 10;  // S1 S2 S3 L1 L2 Q2 Q3 R, L_v R and the guess for the MLP
+
+size_t hevi_bytes(const nh_ctx *c)
+{
+    const size_t fb = align_up(sizeof(double) * kNF * (size_t)c->U);
+    const size_t ib = align_up(sizeof(int) * 2 * (size_t)c->n[0] * c->n[1]);
+    return kHeviArrays * fb + ib;
+}
+
+double *hevi_arr(const nh_ctx *c, int i)
+{
+    const size_t fb = align_up(sizeof(double) * kNF * (size_t)c->U);
+    return (double *)(c->hws + fb * i);
+}
+
+HeviParams hevi_params(const nh_ctx *c)
+{
+    HeviParams h{};
+    h.nx = c->n[0]; h.ny = c->n[1]; h.nz = c->n[2]; h.N = c->N;
+    h.lev = c->lev; h.gz = c->gz;
+    h.gamma = c->phys.cp / c->phys.cv; h.g = c->phys.g;
+    return h;
+}
+
+nh_status check_gmres_opts(nh_ctx *c, const nh_gmres_opts *o)
+{
+    if (!o) return fail(c, NH_EINVAL, "null GMRES options");
+    if (o->restart < 1 || o->restart > 40) return fail(c, NH_EINVAL, "restart must be in 1..40");
+    if (o->max_restarts < 0 || o->max_restarts > 1000) return fail(c, NH_EINVAL, "max_restarts out of range");
+    if (!(o->rtol > 0.0) || !(o->rtol < 1.0)) return fail(c, NH_EINVAL, "rtol must be in (0, 1)");
+    if (gmres_lds_bytes(c->n[2], c->N, o->restart) > 160 * 1024)
+        return fail(c, NH_EUNSUPPORTED, "column too tall for an LDS-resident Krylov basis of this restart length");
+    return NH_OK;
+}
+
+hipError_t run_gmres(nh_ctx *c, double alpha, const double *b, const double *x0, double *x,
+                     const nh_gmres_opts *o, int *iters)
+{
+    GmresArgs g{};
+    g.b = b; g.x0 = x0; g.x = x; g.alpha = alpha; g.rtol = o->rtol;
+    g.restart = o->restart; g.max_restarts = o->max_restarts; g.iters = iters;
+    return launch_gmres(hevi_params(c), g, c->stream);
+}
+
+nh_status gather_stats(nh_ctx *c, const int *dev_iters, int nsolves, nh_solve_stats *st)
+{
+    if (!st) return NH_OK;
+    const size_t ncol = (size_t)c->n[0] * c->n[1];
+    std::vector<int> h(ncol * nsolves);
+    HIPCHK(c, hipMemcpyAsync(h.data(), dev_iters, sizeof(int) * h.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    st->columns = (int64_t)ncol;
+    st->solves = nsolves;
+    st->iters_total = 0; st->iters_max = 0; st->not_converged = 0;
+    for (int v : h) {
+        const int it = v >= 0 ? v : -v - 1;
+        st->iters_total += it;
+        if (it > st->iters_max) st->iters_max = it;
+        if (v < 0) ++st->not_converged;
+    }
+    return st->not_converged ? fail(c, NH_ENOCONV, "%lld column solves did not converge",
+                                    (long long)st->not_converged)
+                             : NH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+nh_status nh_hevi_workspace_bytes(const nh_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return fail(nullptr, NH_EINVAL, "null argument");
+    *bytes = hevi_bytes(c);
+    return NH_OK;
+}
+
+nh_status nh_hevi_attach(nh_ctx *c, void *dev_ws, size_t bytes)
+{
+    nh_status st = guard(c);
+    if (st) return st;
+    if (!dev_ws) return fail(c, NH_EINVAL, "null HEVI workspace");
+    if (((uintptr_t)dev_ws & 255) != 0) return fail(c, NH_EINVAL, "HEVI workspace must be 256-byte aligned");
+    if (bytes < hevi_bytes(c)) return fail(c, NH_ESPACE, "HEVI workspace %zu < %zu bytes", bytes, hevi_bytes(c));
+    c->hws = (char *)dev_ws;
+    c->hws_bytes = bytes;
+    c->hiters = (int *)(c->hws + kHeviArrays * align_up(sizeof(double) * kNF * (size_t)c->U));
+    return NH_OK;
+}
+
+nh_status nh_lv_apply(nh_ctx *c, const double *dev_x, double *dev_y)
+{
+    nh_status st = guard(c);
+    if (st) return st;
+    if (!dev_x || !dev_y) return fail(c, NH_EINVAL, "null arrays");
+    if (!c->have_ref) return fail(c, NH_EINVAL, "reference state not set");
+    HIPCHK(c, launch_lv_apply(hevi_params(c), dev_x, dev_y, c->stream));
+    return NH_OK;
+}
+
+nh_status nh_column_solve(nh_ctx *c, double alpha, const double *dev_b, const double *dev_x0, double *dev_x,
+                          const nh_gmres_opts *opts, nh_solve_stats *stats, int32_t *dev_iters)
+{
+    nh_status st = guard(c);
+    if (st) return st;
+    if (!dev_b || !dev_x) return fail(c, NH_EINVAL, "null arrays");
+    if (!c->have_ref) return fail(c, NH_EINVAL, "reference state not set");
+    if (!(alpha >= 0.0) || !isfinite(alpha)) return fail(c, NH_EINVAL, "alpha must be finite and >= 0");
+    if ((st = check_gmres_opts(c, opts))) return st;
+    int *it = dev_iters ? dev_iters : c->hiters;
+    if (!it && stats) return fail(c, NH_EINVAL, "stats need dev_iters or an attached HEVI workspace");
+    HIPCHK(c, run_gmres(c, alpha, dev_b, dev_x0, dev_x, opts, it));
+    return gather_stats(c, it, 1, stats);
+}
+
+nh_status nh_hevi_step(nh_ctx *c, double t, double dt, const nh_gmres_opts *opts, nh_mlp *guess,
+                       nh_solve_stats *stats)
+{
+    nh_status st = guard(c);
+    if (st) return st;
+    if (!c->hws) return fail(c, NH_EINVAL, "no HEVI workspace attached");
+    if (!c->have_ref) return fail(c, NH_EINVAL, "reference state not set");
+    if (!isfinite(t) || !(dt > 0.0) || !isfinite(dt)) return fail(c, NH_EINVAL, "bad time step");
+    if ((st = check_gmres_opts(c, opts))) return st;
+    static const Ark2 ark;
+    const long n = kNF * (long)c->U;
+    double *Q1 = c->q[0];
+    double *S[3] = {hevi_arr(c, 0), hevi_arr(c, 1), hevi_arr(c, 2)};
+    double *Lv[2] = {hevi_arr(c, 3), hevi_arr(c, 4)};
+    double *Q[3] = {Q1, hevi_arr(c, 5), hevi_arr(c, 6)};
+    double *R = hevi_arr(c, 7);
+    const size_t ncol = (size_t)c->n[0] * c->n[1];
+    for (int i = 0; i < 3; ++i) {
+        if (i > 0) {
+            // R = q^n + dt sum_{j<i} [A_ij S_j + (At_ij - A_ij) L_j]
+            LinComb lc{};
+            int ns = 0;
+            for (int j = 0; j < i; ++j) {
+                lc.src[ns] = S[j]; lc.c[ns++] = dt * ark.A[i][j];
+                lc.src[ns] = Lv[j]; lc.c[ns++] = dt * (ark.At[i][j] - ark.A[i][j]);
+            }
+            HIPCHK(c, launch_axpy_multi(n, Q1, ns, lc, R, c->stream));
+            const double *x0 = nullptr;
+            if (guess) {
+                st = mlp_guess(guess, c, dt * ark.At[i][i], R, hevi_arr(c, 8), hevi_arr(c, 9));
+                if (st) return st;
+                x0 = hevi_arr(c, 9);
+            }
+            HIPCHK(c, run_gmres(c, dt * ark.At[i][i], R, x0, Q[i], opts, c->hiters + (i - 1) * ncol));
+        }
+        HIPCHK(c, run_stage(c, t + ark.c[i] * dt, Q[i], nullptr, S[i], 0.0, 0.0, 1.0));
+        if (i < 2) HIPCHK(c, launch_lv_apply(hevi_params(c), Q[i], Lv[i], c->stream));
+    }
+    LinComb lc{};
+    for (int j = 0; j < 3; ++j) { lc.src[j] = S[j]; lc.c[j] = dt * ark.b[j]; }
+    HIPCHK(c, launch_axpy_multi(n, Q1, 3, lc, Q1, c->stream));
+    return gather_stats(c, c->hiters, 2, stats);
+}
+
+}  // extern "C"
+
+extern "C" {
 nh_status nh_last_error(const nh_ctx *c, char *buf, size_t n)
 {
     if (!buf || n == 0) return NH_EINVAL;
@@ -684,6 +880,282 @@ nh_status nh_destroy(nh_ctx *c)
 {
     if (!c) return NH_EINVAL;
     delete c;
+    return NH_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ column MLP
+struct nh_mlp {
+    MlpNet net;
+    long max_batch;
+    int step;
+    hipStream_t stream;
+    bool sticky;
+    std::string err;
+};
+
+namespace {
+
+struct MlpLayout {
+    size_t params[5], acts[10], feat, scale, total;
+};
+
+long mlp_nparam()
+{
+    return (long)kMlpHid * kMlpIn + kMlpHid + (long)kMlpHid * kMlpHid + kMlpHid + (long)kMlpOut * kMlpHid + kMlpOut;
+}
+
+MlpLayout mlp_layout(long B)
+{
+    MlpLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+    const long np = mlp_nparam();
+    for (int i = 0; i < 4; ++i) L.params[i] = take(sizeof(float) * np);   // master grad m v
+    L.params[4] = take(sizeof(uint16_t) * np);                             // half
+    L.acts[0] = take(sizeof(float) * B * kMlpHid);     // Z1
+    L.acts[1] = take(sizeof(float) * B * kMlpHid);     // Z2
+    L.acts[2] = take(sizeof(float) * B * kMlpOut);     // Y
+    L.acts[3] = take(sizeof(float) * B * kMlpOut);     // dY
+    L.acts[4] = take(sizeof(float) * B * kMlpHid);     // dH
+    L.acts[5] = take(sizeof(float) * B * kMlpHid);     // dZ
+    L.acts[6] = take(sizeof(float) * kMlpLossBlocks);  // part
+    L.acts[7] = take(sizeof(float) * 4);               // loss
+    L.acts[8] = take(sizeof(uint16_t) * B * kMlpHid);  // H1
+    L.acts[9] = take(sizeof(uint16_t) * B * kMlpHid);  // H2
+    L.feat = take(sizeof(uint16_t) * B * kMlpIn);
+    L.scale = take(sizeof(float) * B * 3);
+    L.total = off;
+    return L;
+}
+
+nh_status mfail(nh_mlp *m, nh_status code, const char *msg)
+{
+    if (m) {
+        m->err = msg;
+        if (code == NH_EHIP) m->sticky = true;
+    }
+    return fail(nullptr, code, "%s", msg);
+}
+
+#define MLPCHK(m, call)                                                                      \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess) return mfail((m), NH_EHIP, hipGetErrorString(e_));             \
+    } while (0)
+
+nh_status mlp_guard(const nh_mlp *m, int64_t batch)
+{
+    if (!m) return fail(nullptr, NH_EINVAL, "null MLP");
+    if (m->sticky) return NH_ESTATE;
+    if (batch <= 0 || batch > m->max_batch || batch % 64 != 0)
+        return fail(nullptr, NH_EINVAL, "batch must be a positive multiple of 64 up to the capacity");
+    return NH_OK;
+}
+
+// Glorot-uniform weights from a 64-bit LCG (seeded), zero biases; the last
+// layer starts at zero so an untrained network returns the default guess.
+void mlp_init_host(uint64_t seed, std::vector<float> &w)
+{
+    w.assign(mlp_nparam(), 0.0f);
+    uint64_t s = seed * 6364136223846793005ULL + 1442695040888963407ULL;
+    auto uni = [&]() {
+        s = s * 6364136223846793005ULL + 1442695040888963407ULL;
+        return ((s >> 11) * (1.0 / 9007199254740992.0)) * 2.0 - 1.0;
+    };
+    long off = 0;
+    const int fan[3][2] = {{kMlpIn, kMlpHid}, {kMlpHid, kMlpHid}, {kMlpHid, kMlpOut}};
+    for (int l = 0; l < 3; ++l) {
+        const int fin = fan[l][0], fout = fan[l][1];
+        const double a = sqrt(6.0 / (fin + fout));
+        for (long i = 0; i < (long)fin * fout; ++i) {
+            const int k = (int)(i % fin);
+            w[off + i] = (l == 2 || (l == 0 && k >= 388)) ? 0.0f : (float)(a * uni());
+        }
+        off += (long)fin * fout + fout;
+    }
+}
+
+}  // namespace
+
+nh_status mlp_guess(nh_mlp *m, nh_ctx *c, double alpha, const double *b, double *lb, double *x0)
+{
+    if (m->sticky) return fail(c, NH_ESTATE, "MLP in error state");
+    HIPCHK(c, launch_lv_apply(hevi_params(c), b, lb, c->stream));
+    MlpColParams cp{c->n[0], c->n[1], c->n[2], c->zl, alpha};
+    const long ncol = (long)c->n[0] * c->n[1];
+    for (long c0 = 0; c0 < ncol; c0 += m->max_batch) {
+        const long nb = std::min<long>(m->max_batch, ncol - c0);
+        const int M = (int)((nb + 63) / 64 * 64);
+        if (M > nb) HIPCHK(c, hipMemsetAsync(m->net.feat, 0, sizeof(uint16_t) * kMlpIn * M, c->stream));
+        HIPCHK(c, launch_mlp_features(cp, b, lb, nullptr, c0, nb, m->net.feat, m->net.scale, nullptr, c->stream));
+        HIPCHK(c, mlp_forward(m->net, M, m->net.feat, c->stream));
+        HIPCHK(c, launch_mlp_guess(cp, b, c0, nb, m->net.Y, m->net.scale, x0, c->stream));
+    }
+    return NH_OK;
+}
+
+extern "C" {
+
+nh_status nh_mlp_workspace_bytes(int64_t max_batch, size_t *bytes)
+{
+    if (!bytes || max_batch <= 0 || max_batch % 64 != 0 || max_batch > (1 << 22))
+        return fail(nullptr, NH_EINVAL, "max_batch must be a positive multiple of 64");
+    *bytes = mlp_layout(max_batch).total;
+    return NH_OK;
+}
+
+nh_status nh_mlp_create(int64_t max_batch, uint64_t seed, void *dev_ws, size_t bytes, void *hip_stream,
+                        nh_mlp **out)
+{
+    if (!out) return fail(nullptr, NH_EINVAL, "null output");
+    *out = nullptr;
+    size_t need;
+    nh_status st = nh_mlp_workspace_bytes(max_batch, &need);
+    if (st) return st;
+    if (!dev_ws || ((uintptr_t)dev_ws & 255)) return fail(nullptr, NH_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < need) return fail(nullptr, NH_ESPACE, "MLP workspace %zu < %zu bytes", bytes, need);
+    const MlpLayout L = mlp_layout(max_batch);
+    nh_mlp *m = new nh_mlp();
+    char *w = (char *)dev_ws;
+    MlpNet &n = m->net;
+    n.nparam = mlp_nparam();
+    n.master = (float *)(w + L.params[0]);
+    n.grad = (float *)(w + L.params[1]);
+    n.m = (float *)(w + L.params[2]);
+    n.v = (float *)(w + L.params[3]);
+    n.half = w + L.params[4];
+    const long offW[3] = {0, (long)kMlpHid * kMlpIn + kMlpHid,
+                          (long)kMlpHid * kMlpIn + kMlpHid + (long)kMlpHid * kMlpHid + kMlpHid};
+    const long offB[3] = {offW[0] + (long)kMlpHid * kMlpIn, offW[1] + (long)kMlpHid * kMlpHid,
+                          offW[2] + (long)kMlpOut * kMlpHid};
+    for (int l = 0; l < 3; ++l) {
+        n.wh[l] = (const char *)n.half + sizeof(uint16_t) * offW[l];
+        n.b[l] = n.master + offB[l];
+        n.gw[l] = n.grad + offW[l];
+        n.gb[l] = n.grad + offB[l];
+    }
+    n.Z1 = (float *)(w + L.acts[0]); n.Z2 = (float *)(w + L.acts[1]); n.Y = (float *)(w + L.acts[2]);
+    n.dY = (float *)(w + L.acts[3]); n.dH = (float *)(w + L.acts[4]); n.dZ = (float *)(w + L.acts[5]);
+    n.part = (float *)(w + L.acts[6]); n.loss = (float *)(w + L.acts[7]);
+    n.H1 = w + L.acts[8]; n.H2 = w + L.acts[9];
+    n.feat = w + L.feat; n.scale = (float *)(w + L.scale);
+    m->max_batch = max_batch;
+    m->step = 0;
+    m->stream = (hipStream_t)hip_stream;
+    m->sticky = false;
+    std::vector<float> h;
+    mlp_init_host(seed, h);
+    hipError_t e = hipMemcpyAsync(n.master, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, m->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(n.m, 0, sizeof(float) * n.nparam, m->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(n.v, 0, sizeof(float) * n.nparam, m->stream);
+    if (e == hipSuccess) e = mlp_sync_half(n, m->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+    if (e != hipSuccess) {
+        delete m;
+        return fail(nullptr, NH_EHIP, "nh_mlp_create: %s", hipGetErrorString(e));
+    }
+    *out = m;
+    return NH_OK;
+}
+
+nh_status nh_mlp_forward(nh_mlp *m, int64_t batch, const void *dev_x_f16, float *dev_y)
+{
+    nh_status st = mlp_guard(m, batch);
+    if (st) return st;
+    if (!dev_x_f16) return mfail(m, NH_EINVAL, "null input");
+    MLPCHK(m, mlp_forward(m->net, (int)batch, dev_x_f16, m->stream));
+    if (dev_y)
+        MLPCHK(m, hipMemcpyAsync(dev_y, m->net.Y, sizeof(float) * batch * kMlpOut, hipMemcpyDeviceToDevice,
+                                 m->stream));
+    return NH_OK;
+}
+
+nh_status nh_mlp_backward(nh_mlp *m, int64_t batch, const void *dev_x_f16, const float *dev_dy)
+{
+    nh_status st = mlp_guard(m, batch);
+    if (st) return st;
+    if (!dev_x_f16 || !dev_dy) return mfail(m, NH_EINVAL, "null input");
+    MLPCHK(m, mlp_backward(m->net, (int)batch, dev_x_f16, dev_dy, m->stream));
+    return NH_OK;
+}
+
+nh_status nh_mlp_train_step(nh_mlp *m, int64_t batch, const void *dev_x_f16, const float *dev_t, float lr,
+                            float b1, float b2, float eps, float *dev_loss)
+{
+    nh_status st = mlp_guard(m, batch);
+    if (st) return st;
+    if (!dev_x_f16 || !dev_t) return mfail(m, NH_EINVAL, "null input");
+    if (!(lr > 0) || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1) || !(eps > 0))
+        return mfail(m, NH_EINVAL, "bad Adam hyper-parameters");
+    const int M = (int)batch;
+    MLPCHK(m, mlp_forward(m->net, M, dev_x_f16, m->stream));
+    MLPCHK(m, mlp_loss_grad(m->net, M, dev_t, m->net.loss, m->stream));
+    MLPCHK(m, mlp_backward(m->net, M, dev_x_f16, m->net.dY, m->stream));
+    ++m->step;
+    MLPCHK(m, mlp_adam(m->net, lr, b1, b2, eps, m->step, m->stream));
+    if (dev_loss)
+        MLPCHK(m, hipMemcpyAsync(dev_loss, m->net.loss, sizeof(float), hipMemcpyDeviceToDevice, m->stream));
+    return NH_OK;
+}
+
+nh_status nh_mlp_params(nh_mlp *m, float *dev_master, float *dev_grad, int64_t *n)
+{
+    if (!m) return fail(nullptr, NH_EINVAL, "null MLP");
+    if (n) *n = m->net.nparam;
+    if (dev_master)
+        MLPCHK(m, hipMemcpyAsync(dev_master, m->net.master, sizeof(float) * m->net.nparam, hipMemcpyDeviceToDevice,
+                                 m->stream));
+    if (dev_grad)
+        MLPCHK(m, hipMemcpyAsync(dev_grad, m->net.grad, sizeof(float) * m->net.nparam, hipMemcpyDeviceToDevice,
+                                 m->stream));
+    return NH_OK;
+}
+
+nh_status nh_mlp_set_params(nh_mlp *m, const float *dev_master)
+{
+    if (!m) return fail(nullptr, NH_EINVAL, "null MLP");
+    if (m->sticky) return NH_ESTATE;
+    if (!dev_master) return mfail(m, NH_EINVAL, "null parameters");
+    MLPCHK(m, hipMemcpyAsync(m->net.master, dev_master, sizeof(float) * m->net.nparam, hipMemcpyDeviceToDevice,
+                             m->stream));
+    MLPCHK(m, hipMemsetAsync(m->net.m, 0, sizeof(float) * m->net.nparam, m->stream));
+    MLPCHK(m, hipMemsetAsync(m->net.v, 0, sizeof(float) * m->net.nparam, m->stream));
+    MLPCHK(m, mlp_sync_half(m->net, m->stream));
+    m->step = 0;
+    return NH_OK;
+}
+
+nh_status nh_mlp_samples(nh_mlp *m, nh_ctx *c, double alpha, const double *dev_b, const double *dev_x,
+                         int64_t col0, int64_t ncol, void *dev_feat, float *dev_scale, float *dev_tgt,
+                         double *dev_tmp)
+{
+    nh_status st = guard(c);
+    if (st) return st;
+    if (!m) return fail(c, NH_EINVAL, "null MLP");
+    if (!dev_b || !dev_feat || !dev_scale || !dev_tmp || (dev_tgt && !dev_x))
+        return fail(c, NH_EINVAL, "null arrays");
+    const long nc = (long)c->n[0] * c->n[1];
+    if (col0 < 0 || ncol <= 0 || col0 + ncol > nc) return fail(c, NH_EINVAL, "column range outside the lattice");
+    if (!c->have_ref) return fail(c, NH_EINVAL, "reference state not set");
+    HIPCHK(c, launch_lv_apply(hevi_params(c), dev_b, dev_tmp, c->stream));
+    MlpColParams cp{c->n[0], c->n[1], c->n[2], c->zl, alpha};
+    HIPCHK(c, launch_mlp_features(cp, dev_b, dev_tmp, dev_x, col0, ncol, dev_feat, dev_scale, dev_tgt, c->stream));
+    return NH_OK;
+}
+
+nh_status nh_mlp_last_error(const nh_mlp *m, char *buf, size_t n)
+{
+    if (!buf || n == 0) return NH_EINVAL;
+    snprintf(buf, n, "%s", m ? m->err.c_str() : g_last_global_error.c_str());
+    return NH_OK;
+}
+
+nh_status nh_mlp_destroy(nh_mlp *m)
+{
+    if (!m) return NH_EINVAL;
+    delete m;
     return NH_OK;
 }
 

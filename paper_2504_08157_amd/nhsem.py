@@ -50,6 +50,14 @@ class nh_physics(ctypes.Structure):
                 ("g", "R", "cp", "cv", "p_a", "f", "sponge_z0", "sponge_tau")]
 
 
+class nh_gmres_opts(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int32), ("max_restarts", ctypes.c_int32), ("rtol", ctypes.c_double)]
+
+
+class nh_solve_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("columns", "solves", "iters_total", "iters_max", "not_converged")]
+
+
 # name -> (restype, argtypes); mirrors include/nhsem.h
 _SIGS = {
     "nh_version": (ctypes.c_char_p, []),
@@ -76,6 +84,26 @@ _SIGS = {
     "nh_mass": (ctypes.c_int32, [_vp, _vp]),
     "nh_diagnostics": (ctypes.c_int32, [_vp, _dp]),
     "nh_check_finite": (ctypes.c_int32, [_vp]),
+    "nh_hevi_workspace_bytes": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "nh_hevi_attach": (ctypes.c_int32, [_vp, _vp, ctypes.c_size_t]),
+    "nh_lv_apply": (ctypes.c_int32, [_vp, _vp, _vp]),
+    "nh_column_solve": (ctypes.c_int32, [_vp, ctypes.c_double, _vp, _vp, _vp, ctypes.POINTER(nh_gmres_opts),
+                                         ctypes.POINTER(nh_solve_stats), _vp]),
+    "nh_hevi_step": (ctypes.c_int32, [_vp, ctypes.c_double, ctypes.c_double, ctypes.POINTER(nh_gmres_opts), _vp,
+                                      ctypes.POINTER(nh_solve_stats)]),
+    "nh_mlp_workspace_bytes": (ctypes.c_int32, [ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
+    "nh_mlp_create": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_uint64, _vp, ctypes.c_size_t, _vp,
+                                       ctypes.POINTER(_vp)]),
+    "nh_mlp_forward": (ctypes.c_int32, [_vp, ctypes.c_int64, _vp, _vp]),
+    "nh_mlp_backward": (ctypes.c_int32, [_vp, ctypes.c_int64, _vp, _vp]),
+    "nh_mlp_train_step": (ctypes.c_int32, [_vp, ctypes.c_int64, _vp, _vp, ctypes.c_float, ctypes.c_float,
+                                           ctypes.c_float, ctypes.c_float, _vp]),
+    "nh_mlp_params": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
+    "nh_mlp_set_params": (ctypes.c_int32, [_vp, _vp]),
+    "nh_mlp_samples": (ctypes.c_int32, [_vp, _vp, ctypes.c_double, _vp, _vp, ctypes.c_int64, ctypes.c_int64,
+                                        _vp, _vp, _vp, _vp]),
+    "nh_mlp_last_error": (ctypes.c_int32, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
+    "nh_mlp_destroy": (ctypes.c_int32, [_vp]),
     "nh_last_error": (ctypes.c_int32, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     "nh_destroy": (ctypes.c_int32, [_vp]),
 }
@@ -304,7 +332,126 @@ class Context:
     def nh_check_finite(self):
         return self.lib.nh_check_finite(self.h)
 
+    # -- HEVI
+    def nh_hevi_attach(self):
+        import torch
+        n = ctypes.c_size_t(0)
+        self._c(self.lib.nh_hevi_workspace_bytes(self.h, ctypes.byref(n)))
+        self.hws = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        self._c(self.lib.nh_hevi_attach(self.h, _tptr(self.hws), n.value))
+
+    def nh_lv_apply(self, x, out=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(x)
+        self._c(self.lib.nh_lv_apply(self.h, _tptr(x), _tptr(out)))
+        return out
+
+    def nh_column_solve(self, alpha, b, x0=None, out=None, restart=20, max_restarts=10, rtol=1e-10,
+                        iters=None, check=True):
+        import torch
+        if out is None:
+            out = torch.empty_like(b)
+        opts = nh_gmres_opts(restart, max_restarts, rtol)
+        st = nh_solve_stats()
+        code = self.lib.nh_column_solve(self.h, float(alpha), _tptr(b), _tptr(x0) if x0 is not None else None,
+                                        _tptr(out), ctypes.byref(opts), ctypes.byref(st),
+                                        _tptr(iters) if iters is not None else None)
+        if check:
+            self._c(code)
+        return out, st
+
+    def nh_hevi_step(self, t, dt, restart=20, max_restarts=10, rtol=1e-10, guess=None, check=True):
+        opts = nh_gmres_opts(restart, max_restarts, rtol)
+        st = nh_solve_stats()
+        code = self.lib.nh_hevi_step(self.h, float(t), float(dt), ctypes.byref(opts),
+                                     guess.h if guess is not None else None, ctypes.byref(st))
+        if check:
+            self._c(code)
+        return st
+
     def nh_last_error(self):
         buf = ctypes.create_string_buffer(512)
         self.lib.nh_last_error(self.h, buf, 512)
         return buf.value.decode(errors="replace")
+
+
+MLP_IN, MLP_HID, MLP_OUT = 400, 256, 192
+
+
+class ColumnMLP:
+    """Owns a workspace tensor and a library MLP (FP16 MFMA forward, FP32
+    backward, Adam)."""
+
+    def __init__(self, max_batch=4096, seed=7, device="cuda"):
+        import torch
+        self.lib = load()
+        n = ctypes.c_size_t(0)
+        _check(None, self.lib.nh_mlp_workspace_bytes(int(max_batch), ctypes.byref(n)))
+        self.ws = torch.empty(n.value, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        _check(None, self.lib.nh_mlp_create(int(max_batch), int(seed), _tptr(self.ws), n.value, _stream(),
+                                            ctypes.byref(h)))
+        self.h = h
+        self.max_batch = max_batch
+        cnt = ctypes.c_int64()
+        self._c(self.lib.nh_mlp_params(self.h, None, None, ctypes.byref(cnt)))
+        self.nparam = cnt.value
+        self.device = device
+
+    def _c(self, code):
+        if code != NH_OK:
+            buf = ctypes.create_string_buffer(512)
+            self.lib.nh_mlp_last_error(self.h, buf, 512)
+            raise NHError(code, buf.value.decode(errors="replace"))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.nh_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def nh_mlp_forward(self, x_f16, out=None):
+        import torch
+        B = x_f16.shape[0]
+        if out is None:
+            out = torch.empty((B, MLP_OUT), dtype=torch.float32, device=self.device)
+        self._c(self.lib.nh_mlp_forward(self.h, B, _tptr(x_f16), _tptr(out)))
+        return out
+
+    def nh_mlp_backward(self, x_f16, dy):
+        self._c(self.lib.nh_mlp_backward(self.h, x_f16.shape[0], _tptr(x_f16), _tptr(dy)))
+
+    def nh_mlp_train_step(self, x_f16, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, loss=None):
+        self._c(self.lib.nh_mlp_train_step(self.h, x_f16.shape[0], _tptr(x_f16), _tptr(t), lr, b1, b2, eps,
+                                           _tptr(loss) if loss is not None else None))
+
+    def nh_mlp_params(self):
+        import torch
+        w = torch.empty(self.nparam, dtype=torch.float32, device=self.device)
+        g = torch.empty(self.nparam, dtype=torch.float32, device=self.device)
+        self._c(self.lib.nh_mlp_params(self.h, _tptr(w), _tptr(g), None))
+        return w, g
+
+    def nh_mlp_set_params(self, w):
+        self._c(self.lib.nh_mlp_set_params(self.h, _tptr(w)))
+
+    def nh_mlp_samples(self, ctx, alpha, b, x=None, col0=0, ncol=None, tmp=None):
+        """Features (FP16 [ncol][400]), scales and, with x, targets of columns."""
+        import torch
+        ncol = ctx.nx * ctx.ny - col0 if ncol is None else ncol
+        feat = torch.empty((ncol, MLP_IN), dtype=torch.float16, device=self.device)
+        scale = torch.empty((ncol, 3), dtype=torch.float32, device=self.device)
+        tgt = torch.empty((ncol, MLP_OUT), dtype=torch.float32, device=self.device) if x is not None else None
+        if tmp is None:
+            tmp = torch.empty_like(b)
+        code = self.lib.nh_mlp_samples(self.h, ctx.h, float(alpha), _tptr(b), _tptr(x) if x is not None else None,
+                                       int(col0), int(ncol), _tptr(feat), _tptr(scale),
+                                       _tptr(tgt) if tgt is not None else None, _tptr(tmp))
+        _check(ctx.h, code)
+        return feat, scale, tgt

@@ -1,0 +1,92 @@
+"""Parity of the HEVI pieces (Sec. 2.3) with the oracle: the vertical
+operator L_v, the batched column GMRES against LAPACK direct solves, and the
+ARK2 step."""
+import numpy as np
+import pytest
+
+from paper_2504_08157_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _pair(oracle_mod, nel=(5, 4, 4), N=4, per=(True, True), H=12e3):
+    import torch
+    from paper_2504_08157_amd import nhsem
+    ph = W.Physics(f=5e-5, sponge_z0=0.75 * H, sponge_tau=0.01)
+    mesh = W.MeshSpec(nel, N, W.uniform_edges(0, 40e3, nel[0]), W.uniform_edges(0, 30e3, nel[1]),
+                      W.stretched_edges(0, H, nel[2], seed=3), per)
+    ctx = nhsem.Context(mesh, ph)
+    orc = oracle_mod.Oracle(mesh, ph)
+    g = ctx.nh_lattice_coords()
+    o = orc.lattice_coords()
+    ctx.nh_set_reference(*W.constant_n_reference(g[2]))
+    orc.set_reference(*W.constant_n_reference(o[2]))
+    ctx.nh_hevi_attach()
+    return ctx, orc, g, o, torch
+
+
+def _state(c, seed, amp=1.0, per=(True, True)):
+    return W.smooth_random_state(*c, *W.constant_n_reference(c[2]), seed=seed, amp=amp,
+                                 walls=(not per[0], not per[1]))
+
+
+def test_lv_apply_parity(oracle_mod):
+    ctx, orc, g, o, torch = _pair(oracle_mod, per=(False, True))
+    y = ctx.nh_lv_apply(torch.from_numpy(_state(g, 1, per=(False, True))).cuda()).cpu().numpy()
+    ref = orc.lv_apply(_state(o, 1, per=(False, True)))
+    for f in (0, 3, 4):
+        assert np.linalg.norm(y[f] - ref[f]) <= 1e-12 * np.linalg.norm(ref[f]), f
+    assert np.all(y[1] == 0) and np.all(y[2] == 0)
+
+
+@pytest.mark.parametrize("alpha", [0.3, 2.0])
+def test_column_gmres_vs_direct(oracle_mod, alpha):
+    ctx, orc, g, o, torch = _pair(oracle_mod)
+    Lm = oracle_mod.column_matrix(orc)
+    b = _state(o, 5)
+    nz = orc.nz
+    A = np.eye(3 * nz) - alpha * Lm
+    B = np.concatenate([b[0].reshape(nz, -1), b[3].reshape(nz, -1), b[4].reshape(nz, -1)])
+    X = np.linalg.solve(A, B)
+    bd = torch.from_numpy(_state(g, 5)).cuda()
+    iters = torch.zeros(ctx.nx * ctx.ny, dtype=torch.int32, device="cuda")
+    x, st = ctx.nh_column_solve(alpha, bd, rtol=1e-12, iters=iters)
+    x = x.cpu().numpy()
+    for f, blk in ((0, X[:nz]), (3, X[nz:2 * nz]), (4, X[2 * nz:])):
+        ref = blk.reshape(x[f].shape)
+        assert np.linalg.norm(x[f] - ref) <= 1e-9 * np.linalg.norm(ref), (f, np.linalg.norm(x[f] - ref) / np.linalg.norm(ref))
+    np.testing.assert_array_equal(x[1], b[1]); np.testing.assert_array_equal(x[2], b[2])
+    it = iters.cpu().numpy()
+    assert st.not_converged == 0 and (it > 0).all() and st.iters_total == it.sum()
+    print("alpha", alpha, "iters mean", it.mean(), "max", it.max())
+    # starting from the exact solution needs no Arnoldi step
+    x0 = torch.from_numpy(np.stack([x[0], x[3], x[4]])).cuda()
+    _, st0 = ctx.nh_column_solve(alpha, bd, x0=x0, rtol=1e-9, iters=iters)
+    assert st0.iters_total == 0
+
+
+def test_gmres_reports_non_convergence(oracle_mod):
+    from paper_2504_08157_amd import nhsem
+    ctx, orc, g, o, torch = _pair(oracle_mod)
+    bd = torch.from_numpy(_state(g, 6)).cuda()
+    x, st = ctx.nh_column_solve(2.0, bd, restart=2, max_restarts=0, rtol=1e-12, check=False)
+    assert st.not_converged == st.columns
+    with pytest.raises(nhsem.NHError) as e:
+        ctx.nh_column_solve(2.0, bd, restart=2, max_restarts=0, rtol=1e-12)
+    assert e.value.code == nhsem.NH_ENOCONV
+
+
+def test_hevi_step_parity(oracle_mod):
+    ctx, orc, g, o, torch = _pair(oracle_mod)
+    Lm = oracle_mod.column_matrix(orc)
+    q = _state(o, 9, amp=0.3)
+    ctx.nh_set_state(torch.from_numpy(_state(g, 9, amp=0.3)).cuda())
+    dt = 4.0
+    for n in range(2):
+        st = ctx.nh_hevi_step(n * dt, dt, rtol=1e-13, max_restarts=20)
+        q = oracle_mod.ark2_step(orc, Lm, n * dt, dt, q)
+        assert st.not_converged == 0 and st.solves == 2
+    got = ctx.nh_get_state().cpu().numpy()
+    for f in range(5):
+        err = np.linalg.norm(got[f] - q[f]) / np.linalg.norm(q[f])
+        assert err <= 1e-10, (f, err)
