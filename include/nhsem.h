@@ -221,6 +221,37 @@ nh_status nh_column_solve(nh_ctx *ctx, double alpha, const double *dev_b, const 
 nh_status nh_hevi_step(nh_ctx *ctx, double t, double dt, const nh_gmres_opts *opts, nh_mlp *guess,
                        nh_solve_stats *stats);
 
+/* Device pointers (into the HEVI workspace, valid until the next HEVI call)
+   to the right-hand sides and solutions of the two implicit stages of the
+   last nh_hevi_step, [5][U] each; *alpha_per_dt = At_22 = At_33, so the
+   solves used alpha = dt * (*alpha_per_dt).  For collecting training data. */
+nh_status nh_hevi_last_solves(nh_ctx *ctx, const double **R2, const double **X2, const double **R3,
+                              const double **X3, double *alpha_per_dt, double *reserved);
+
+/* ------------------------------------------------------------------
+ * Batched instances: many contexts (uneven meshes, orders 2..6, one
+ * precision) advanced by SSP-RK3 together.  Per stage, one grouped launch
+ * per order covers every instance of that order, its workgroups taking
+ * (instance, tile) items sorted longest-column-first; K steps of launches are
+ * captured once into a hipGraph and replayed (the per-stage descriptors of
+ * the next K steps are uploaded with one copy before each replay).  Each
+ * instance computes bitwise the same as nh_rk_step on its own.
+ * Restrictions: reference set on every context, forcing only on theta'.
+ * The batch owns no context; contexts must outlive it.
+ * ------------------------------------------------------------------ */
+typedef struct nh_batch nh_batch;
+nh_status nh_batch_workspace_bytes(nh_ctx *const *ctxs, int32_t n, int32_t steps_per_graph, size_t *bytes);
+
+/* tile_variant: optional [7] array indexed by order (tuner's choice per
+   order); hip_stream must be a non-default stream (graph capture). */
+nh_status nh_batch_create(nh_ctx *const *ctxs, int32_t n, int32_t steps_per_graph, const int32_t *tile_variant,
+                          void *dev_ws, size_t bytes, void *hip_stream, nh_batch **out);
+
+/* Advance every instance nsteps (a multiple of steps_per_graph) from t. */
+nh_status nh_batch_step(nh_batch *b, double t, double dt, int32_t nsteps);
+nh_status nh_batch_last_error(const nh_batch *b, char *buf, size_t n);
+nh_status nh_batch_destroy(nh_batch *b);
+
 /* ------------------------------------------------------------------
  * Column MLP for the initial guess of the HEVI column solves (trained on
  * solves the method itself produces; the Krylov solve still runs to the

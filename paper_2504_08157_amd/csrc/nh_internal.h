@@ -51,6 +51,8 @@ struct GeomParams {
 };
 
 hipError_t launch_stage(int N, int precision, int variant, const StageParams &p, hipStream_t s);
+hipError_t launch_stage_batched(int N, int precision, int variant, const StageParams *P, const int2 *work,
+                                int nitems, hipStream_t s);
 struct WallParams {
     int nx, ny, nz, perx, pery;
 };

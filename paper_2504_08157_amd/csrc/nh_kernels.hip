@@ -93,8 +93,7 @@ struct StageShape {
 // contribution at the shared bottom level is carried in registers by the
 // threads that own the bottom level (same threads for every element).
 template <int N, int AX, int AY, typename T>
-__global__ void __launch_bounds__((StageShape<N, AX, AY>::NT))
-stage_kernel(const StageParams p)
+__device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
 {
     using S = StageShape<N, AX, AY>;
     constexpr int N1 = S::N1, TX = S::TX, TY = S::TY, NCOL = S::NCOL, NOWN = S::NOWN;
@@ -112,7 +111,7 @@ stage_kernel(const StageParams p)
     __shared__ double sE[kEosTerms];
 
     const int tid = threadIdx.x;
-    const int bx = blockIdx.x % p.ntx, by = blockIdx.x / p.ntx;
+    const int bx = tile % p.ntx, by = tile / p.ntx;
     const int x0 = bx * TX, y0 = by * TY;
     const uint32_t nx = p.nx, ny = p.ny;
     const uint32_t plane_bytes = nx * ny * 8u;
@@ -370,6 +369,23 @@ stage_kernel(const StageParams p)
 #undef NH_PIN
 }
 
+template <int N, int AX, int AY, typename T>
+__global__ void __launch_bounds__((StageShape<N, AX, AY>::NT)) stage_kernel(const StageParams p)
+{
+    stage_body<N, AX, AY, T>(p, blockIdx.x);
+}
+
+// Batched form: workgroup b takes work item work[b] = (instance, tile) from a
+// list sorted by cost (longest columns first) and reads that instance's
+// parameters from a device descriptor table.
+template <int N, int AX, int AY, typename T>
+__global__ void __launch_bounds__((StageShape<N, AX, AY>::NT))
+stage_kernel_batched(const StageParams *__restrict__ P, const int2 *__restrict__ work)
+{
+    const int2 it = work[blockIdx.x];
+    stage_body<N, AX, AY, T>(P[it.x], it.y);
+}
+
 // Tile shapes per order (AX x AY elements).  Variant 0 uses rows of 32 (or
 // 30) lattice columns so that each half-wave's stencil reads cover one
 // contiguous 256-byte LDS row (bank-conflict free); variant 1 is a squarer
@@ -403,6 +419,33 @@ static void launch_one(int precision, const StageParams &p, hipStream_t s)
         hipLaunchKernelGGL((stage_kernel<N, AX, AY, double>), grid, block, 0, s, p);
     else
         hipLaunchKernelGGL((stage_kernel<N, AX, AY, float>), grid, block, 0, s, p);
+}
+
+template <int N, int AX, int AY>
+static void launch_batched_one(int precision, const StageParams *P, const int2 *work, int nitems, hipStream_t s)
+{
+    const dim3 grid(nitems), block(StageShape<N, AX, AY>::NT);
+    if (precision == 0)
+        hipLaunchKernelGGL((stage_kernel_batched<N, AX, AY, double>), grid, block, 0, s, P, work);
+    else
+        hipLaunchKernelGGL((stage_kernel_batched<N, AX, AY, float>), grid, block, 0, s, P, work);
+}
+
+hipError_t launch_stage_batched(int N, int precision, int variant, const StageParams *P, const int2 *work,
+                                int nitems, hipStream_t s)
+{
+    switch (N) {
+#define NH_LAUNCHB(NN, AX0, AY0, AX1, AY1)                                           \
+    case NN:                                                                         \
+        if (variant) launch_batched_one<NN, AX1, AY1>(precision, P, work, nitems, s); \
+        else launch_batched_one<NN, AX0, AY0>(precision, P, work, nitems, s);         \
+        break;
+        NH_TILE_CASES(NH_LAUNCHB)
+#undef NH_LAUNCHB
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_stage(int N, int precision, int variant, const StageParams &p, hipStream_t s)

@@ -707,7 +707,7 @@ struct Ark2 {
     }
 };
 
-constexpr int kHeviArrays = 10;  // S1 S2 S3 L1 L2 Q2 Q3 R, L_v R and the guess for the MLP
+constexpr int kHeviArrays = 11;  // S1 S2 S3 L1 L2 Q2 Q3 R2 R3, L_v R and the MLP guess
 
 size_t hevi_bytes(const nh_ctx *c)
 {
@@ -796,6 +796,22 @@ nh_status nh_hevi_attach(nh_ctx *c, void *dev_ws, size_t bytes)
     return NH_OK;
 }
 
+nh_status nh_hevi_last_solves(nh_ctx *c, const double **R2, const double **X2, const double **R3,
+                              const double **X3, double *alpha, double *scratch_ptr_unused)
+{
+    (void)scratch_ptr_unused;
+    nh_status st = guard(c);
+    if (st) return st;
+    if (!c->hws) return fail(c, NH_EINVAL, "no HEVI workspace attached");
+    static const Ark2 ark;
+    if (R2) *R2 = hevi_arr(c, 7);
+    if (X2) *X2 = hevi_arr(c, 5);
+    if (R3) *R3 = hevi_arr(c, 8);
+    if (X3) *X3 = hevi_arr(c, 6);
+    if (alpha) *alpha = ark.At[1][1];
+    return NH_OK;
+}
+
 nh_status nh_lv_apply(nh_ctx *c, const double *dev_x, double *dev_y)
 {
     nh_status st = guard(c);
@@ -836,7 +852,7 @@ nh_status nh_hevi_step(nh_ctx *c, double t, double dt, const nh_gmres_opts *opts
     double *S[3] = {hevi_arr(c, 0), hevi_arr(c, 1), hevi_arr(c, 2)};
     double *Lv[2] = {hevi_arr(c, 3), hevi_arr(c, 4)};
     double *Q[3] = {Q1, hevi_arr(c, 5), hevi_arr(c, 6)};
-    double *R = hevi_arr(c, 7);
+    double *Rs[3] = {nullptr, hevi_arr(c, 7), hevi_arr(c, 8)};
     const size_t ncol = (size_t)c->n[0] * c->n[1];
     for (int i = 0; i < 3; ++i) {
         if (i > 0) {
@@ -847,12 +863,13 @@ nh_status nh_hevi_step(nh_ctx *c, double t, double dt, const nh_gmres_opts *opts
                 lc.src[ns] = S[j]; lc.c[ns++] = dt * ark.A[i][j];
                 lc.src[ns] = Lv[j]; lc.c[ns++] = dt * (ark.At[i][j] - ark.A[i][j]);
             }
+            double *R = Rs[i];
             HIPCHK(c, launch_axpy_multi(n, Q1, ns, lc, R, c->stream));
             const double *x0 = nullptr;
             if (guess) {
-                st = mlp_guess(guess, c, dt * ark.At[i][i], R, hevi_arr(c, 8), hevi_arr(c, 9));
+                st = mlp_guess(guess, c, dt * ark.At[i][i], R, hevi_arr(c, 9), hevi_arr(c, 10));
                 if (st) return st;
-                x0 = hevi_arr(c, 9);
+                x0 = hevi_arr(c, 10);
             }
             HIPCHK(c, run_gmres(c, dt * ark.At[i][i], R, x0, Q[i], opts, c->hiters + (i - 1) * ncol));
         }
@@ -1156,6 +1173,222 @@ nh_status nh_mlp_destroy(nh_mlp *m)
 {
     if (!m) return NH_EINVAL;
     delete m;
+    return NH_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batched instances
+// Many contexts (uneven limited-area instances, possibly of different
+// orders) advanced together: per RK stage one grouped launch per order,
+// whose workgroups take (instance, tile) items sorted longest-column-first
+// and read their instance's parameters from a device descriptor table; a
+// sequence of K steps (3 K launches per order group) is captured once as a
+// hipGraph and replayed, after the per-stage descriptors of the next K steps
+// are uploaded with one copy.
+struct nh_batch {
+    std::vector<nh_ctx *> ctx;
+    int K, precision;
+    struct Group {
+        int N, variant, nitems;
+        int2 *work;  // device
+    };
+    std::vector<Group> groups;
+    StageParams *table;  // device [K][3][n]
+    std::vector<StageParams> host;
+    hipStream_t stream;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    bool captured, sticky;
+    std::string err;
+};
+
+namespace {
+
+size_t batch_bytes(nh_ctx *const *ctxs, int n, int K)
+{
+    size_t tiles = 0;
+    for (int i = 0; i < n; ++i) {
+        int tx, ty, tx1, ty1;
+        stage_tile(ctxs[i]->N, 0, &tx, &ty);
+        stage_tile(ctxs[i]->N, 1, &tx1, &ty1);
+        const size_t t0 = (size_t)((ctxs[i]->n[0] + tx - 1) / tx) * ((ctxs[i]->n[1] + ty - 1) / ty);
+        const size_t t1 = (size_t)((ctxs[i]->n[0] + tx1 - 1) / tx1) * ((ctxs[i]->n[1] + ty1 - 1) / ty1);
+        tiles += std::max(t0, t1);
+    }
+    return align_up(sizeof(int2) * tiles) + align_up(sizeof(StageParams) * (size_t)K * 3 * n);
+}
+
+nh_status bfail(nh_batch *b, nh_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (b) {
+        b->err = buf;
+        if (code == NH_EHIP) b->sticky = true;
+    }
+    g_last_global_error = buf;
+    return code;
+}
+
+#define BCHK(b, call)                                                                                \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess) return bfail((b), NH_EHIP, "%s: %s", #call, hipGetErrorString(e_));    \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+nh_status nh_batch_workspace_bytes(nh_ctx *const *ctxs, int32_t n, int32_t steps_per_graph, size_t *bytes)
+{
+    if (!ctxs || n < 1 || n > 4096 || steps_per_graph < 1 || steps_per_graph > 1000 || !bytes)
+        return fail(nullptr, NH_EINVAL, "bad batch arguments");
+    for (int i = 0; i < n; ++i)
+        if (!ctxs[i]) return fail(nullptr, NH_EINVAL, "null context %d", i);
+    *bytes = batch_bytes(ctxs, n, steps_per_graph);
+    return NH_OK;
+}
+
+nh_status nh_batch_create(nh_ctx *const *ctxs, int32_t n, int32_t steps_per_graph, const int32_t *tile_variant,
+                          void *dev_ws, size_t bytes, void *hip_stream, nh_batch **out)
+{
+    if (!out) return fail(nullptr, NH_EINVAL, "null output");
+    *out = nullptr;
+    size_t need;
+    nh_status st = nh_batch_workspace_bytes(ctxs, n, steps_per_graph, &need);
+    if (st) return st;
+    if (!dev_ws || ((uintptr_t)dev_ws & 255)) return fail(nullptr, NH_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < need) return fail(nullptr, NH_ESPACE, "batch workspace %zu < %zu bytes", bytes, need);
+    if (!hip_stream) return fail(nullptr, NH_EINVAL, "graph capture needs a non-default stream");
+    const int prec = ctxs[0]->precision;
+    for (int i = 0; i < n; ++i) {
+        const nh_ctx *c = ctxs[i];
+        if (c->sticky) return fail(nullptr, NH_ESTATE, "context %d is in an error state", i);
+        if (!c->have_ref) return fail(nullptr, NH_EINVAL, "context %d has no reference state", i);
+        if (c->precision != prec) return fail(nullptr, NH_EINVAL, "all instances must share one precision");
+        for (int f = 0; f < 4; ++f)
+            if (c->nsnap[f]) return fail(nullptr, NH_EUNSUPPORTED, "batched stages fuse only the theta' forcing");
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == c) return fail(nullptr, NH_EINVAL, "context %d appears twice", i);
+    }
+    nh_batch *b = new nh_batch();
+    b->ctx.assign(ctxs, ctxs + n);
+    b->K = steps_per_graph;
+    b->precision = prec;
+    b->stream = (hipStream_t)hip_stream;
+    b->captured = false;
+    b->sticky = false;
+    b->graph = nullptr;
+    b->exec = nullptr;
+    char *w = (char *)dev_ws;
+    int2 *work = (int2 *)w;
+    size_t tiles_total = 0;
+    // group by order; items sorted by column length (nel_z) descending
+    std::vector<int2> all;
+    for (int N = 2; N <= kMaxN; ++N) {
+        const int var = tile_variant ? tile_variant[N] : 0;
+        if (var < 0 || var >= kTileVariants) {
+            delete b;
+            return fail(nullptr, NH_EINVAL, "bad tile variant for order %d", N);
+        }
+        std::vector<std::pair<int, int2>> items;
+        for (int i = 0; i < n; ++i) {
+            if (ctxs[i]->N != N) continue;
+            int tx, ty;
+            stage_tile(N, var, &tx, &ty);
+            const int ntx = (ctxs[i]->n[0] + tx - 1) / tx, nty = (ctxs[i]->n[1] + ty - 1) / ty;
+            for (int t = 0; t < ntx * nty; ++t) items.push_back({ctxs[i]->nel[2], make_int2(i, t)});
+        }
+        if (items.empty()) continue;
+        std::stable_sort(items.begin(), items.end(),
+                         [](const std::pair<int, int2> &a, const std::pair<int, int2> &c) { return a.first > c.first; });
+        nh_batch::Group g{N, var, (int)items.size(), work + tiles_total};
+        for (auto &it : items) all.push_back(it.second);
+        tiles_total += items.size();
+        b->groups.push_back(g);
+        for (int i = 0; i < n; ++i)
+            if (ctxs[i]->N == N) b->ctx[i]->tile = var;
+    }
+    // descriptor tables sit after the work lists (sized for the larger tile variant)
+    b->table = (StageParams *)(w + (need - align_up(sizeof(StageParams) * (size_t)steps_per_graph * 3 * n)));
+    b->host.resize((size_t)steps_per_graph * 3 * n);
+    hipError_t e = hipMemcpyAsync(work, all.data(), sizeof(int2) * all.size(), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        delete b;
+        return fail(nullptr, NH_EHIP, "nh_batch_create: %s", hipGetErrorString(e));
+    }
+    *out = b;
+    return NH_OK;
+}
+
+nh_status nh_batch_step(nh_batch *b, double t, double dt, int32_t nsteps)
+{
+    if (!b) return fail(nullptr, NH_EINVAL, "null batch");
+    if (b->sticky) return NH_ESTATE;
+    if (nsteps < 0 || nsteps % b->K != 0)
+        return bfail(b, NH_EINVAL, "nsteps must be a multiple of the %d steps per graph", b->K);
+    if (!isfinite(t) || !isfinite(dt)) return bfail(b, NH_EINVAL, "bad time arguments");
+    const int n = (int)b->ctx.size();
+    for (int i = 0; i < n; ++i)
+        if (b->ctx[i]->sticky) return bfail(b, NH_ESTATE, "context %d in an error state", i);
+    const double ca[3] = {0.0, 0.75, 1.0 / 3.0}, cb[3] = {1.0, 0.25, 2.0 / 3.0}, cc[3] = {1.0, 0.25, 2.0 / 3.0};
+    const double ct[3] = {0.0, 1.0, 0.5};
+    for (int r = 0; r < nsteps / b->K; ++r) {
+        for (int k = 0; k < b->K; ++k) {
+            const double ts = t + (double)(r * b->K + k) * dt;
+            for (int s = 0; s < 3; ++s)
+                for (int i = 0; i < n; ++i) {
+                    nh_ctx *c = b->ctx[i];
+                    const double *qs = s == 0 ? c->q[0] : (s == 1 ? c->q[1] : c->q[2]);
+                    double *o = s == 0 ? c->q[1] : (s == 1 ? c->q[2] : c->q[0]);
+                    b->host[((size_t)k * 3 + s) * n + i] =
+                        stage_params(c, ts + ct[s] * dt, qs, s == 0 ? nullptr : c->q[0], o, ca[s], cb[s], cc[s] * dt);
+                }
+        }
+        BCHK(b, hipMemcpyAsync(b->table, b->host.data(), sizeof(StageParams) * b->host.size(),
+                               hipMemcpyHostToDevice, b->stream));
+        if (!b->captured) {
+            BCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e = hipSuccess;
+            for (int k = 0; k < b->K && e == hipSuccess; ++k)
+                for (int s = 0; s < 3 && e == hipSuccess; ++s)
+                    for (const auto &g : b->groups) {
+                        e = launch_stage_batched(g.N, b->precision, g.variant, b->table + ((size_t)k * 3 + s) * n,
+                                                 g.work, g.nitems, b->stream);
+                        if (e != hipSuccess) break;
+                    }
+            hipGraph_t graph = nullptr;
+            hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
+            if (e != hipSuccess) return bfail(b, NH_EHIP, "capture: %s", hipGetErrorString(e));
+            if (e2 != hipSuccess) return bfail(b, NH_EHIP, "end capture: %s", hipGetErrorString(e2));
+            b->graph = graph;
+            BCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+            b->captured = true;
+        }
+        BCHK(b, hipGraphLaunch(b->exec, b->stream));
+    }
+    return NH_OK;
+}
+
+nh_status nh_batch_last_error(const nh_batch *b, char *buf, size_t n)
+{
+    if (!buf || n == 0) return NH_EINVAL;
+    snprintf(buf, n, "%s", b ? b->err.c_str() : g_last_global_error.c_str());
+    return NH_OK;
+}
+
+nh_status nh_batch_destroy(nh_batch *b)
+{
+    if (!b) return NH_EINVAL;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    delete b;
     return NH_OK;
 }
 

@@ -87,10 +87,19 @@ _SIGS = {
     "nh_hevi_workspace_bytes": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
     "nh_hevi_attach": (ctypes.c_int32, [_vp, _vp, ctypes.c_size_t]),
     "nh_lv_apply": (ctypes.c_int32, [_vp, _vp, _vp]),
+    "nh_hevi_last_solves": (ctypes.c_int32, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                             ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_double), _vp]),
     "nh_column_solve": (ctypes.c_int32, [_vp, ctypes.c_double, _vp, _vp, _vp, ctypes.POINTER(nh_gmres_opts),
                                          ctypes.POINTER(nh_solve_stats), _vp]),
     "nh_hevi_step": (ctypes.c_int32, [_vp, ctypes.c_double, ctypes.c_double, ctypes.POINTER(nh_gmres_opts), _vp,
                                       ctypes.POINTER(nh_solve_stats)]),
+    "nh_batch_workspace_bytes": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int32,
+                                                  ctypes.POINTER(ctypes.c_size_t)]),
+    "nh_batch_create": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, ctypes.c_size_t, _vp,
+                                         ctypes.POINTER(_vp)]),
+    "nh_batch_step": (ctypes.c_int32, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32]),
+    "nh_batch_last_error": (ctypes.c_int32, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
+    "nh_batch_destroy": (ctypes.c_int32, [_vp]),
     "nh_mlp_workspace_bytes": (ctypes.c_int32, [ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
     "nh_mlp_create": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_uint64, _vp, ctypes.c_size_t, _vp,
                                        ctypes.POINTER(_vp)]),
@@ -149,6 +158,9 @@ def _dptr(a):
 
 
 def _tptr(t):
+    """Device address of a tensor (or a raw address given as int)."""
+    if isinstance(t, int):
+        return ctypes.c_void_p(t)
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -370,6 +382,13 @@ class Context:
             self._c(code)
         return st
 
+    def nh_hevi_last_solves(self):
+        """(alpha_per_dt, [(R2, X2), (R3, X3)]) as raw device addresses."""
+        p = [ctypes.c_void_p() for _ in range(4)]
+        a = ctypes.c_double()
+        self._c(self.lib.nh_hevi_last_solves(self.h, *[ctypes.byref(v) for v in p], ctypes.byref(a), None))
+        return a.value, [(p[0].value, p[1].value), (p[2].value, p[3].value)]
+
     def nh_last_error(self):
         buf = ctypes.create_string_buffer(512)
         self.lib.nh_last_error(self.h, buf, 512)
@@ -449,9 +468,50 @@ class ColumnMLP:
         scale = torch.empty((ncol, 3), dtype=torch.float32, device=self.device)
         tgt = torch.empty((ncol, MLP_OUT), dtype=torch.float32, device=self.device) if x is not None else None
         if tmp is None:
-            tmp = torch.empty_like(b)
+            tmp = torch.empty(5 * ctx.U, dtype=torch.float64, device=self.device)
         code = self.lib.nh_mlp_samples(self.h, ctx.h, float(alpha), _tptr(b), _tptr(x) if x is not None else None,
                                        int(col0), int(ncol), _tptr(feat), _tptr(scale),
                                        _tptr(tgt) if tgt is not None else None, _tptr(tmp))
         _check(ctx.h, code)
         return feat, scale, tgt
+
+
+class Batch:
+    """Batched SSP-RK3 over several Contexts, one graph per K steps."""
+
+    def __init__(self, contexts, steps_per_graph=1, tile_variant=None, stream=None):
+        import torch
+        self.lib = load()
+        self.contexts = list(contexts)
+        arr = (ctypes.c_void_p * len(self.contexts))(*[c.h.value for c in self.contexts])
+        self._arr = arr
+        n = ctypes.c_size_t(0)
+        _check(None, self.lib.nh_batch_workspace_bytes(arr, len(self.contexts), steps_per_graph, ctypes.byref(n)))
+        self.ws = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        tv = None
+        if tile_variant is not None:
+            tv = (ctypes.c_int32 * 7)(*[int(tile_variant.get(k, 0)) for k in range(7)])
+        h = ctypes.c_void_p()
+        _check(None, self.lib.nh_batch_create(arr, len(self.contexts), steps_per_graph, tv, _tptr(self.ws),
+                                              n.value, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+        self.K = steps_per_graph
+
+    def nh_batch_step(self, t, dt, nsteps):
+        code = self.lib.nh_batch_step(self.h, float(t), float(dt), int(nsteps))
+        if code != NH_OK:
+            buf = ctypes.create_string_buffer(512)
+            self.lib.nh_batch_last_error(self.h, buf, 512)
+            raise NHError(code, buf.value.decode(errors="replace"))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.nh_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

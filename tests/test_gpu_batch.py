@@ -1,0 +1,69 @@
+"""Batched uneven instances in one graph launch: every instance must equal
+its own single-instance SSP-RK3 run bit for bit, and (small ones) the
+oracle."""
+import numpy as np
+import pytest
+
+from paper_2504_08157_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _instance(i, nel, N, device="cuda"):
+    import torch
+    from paper_2504_08157_amd import nhsem
+    w = W.cfg_ensemble_member(i)
+    w.mesh = W._tc_mesh(*nel, N)
+    ctx = nhsem.Context(w.mesh, w.phys)
+    x, y, z = ctx.nh_lattice_coords()
+    ctx.nh_set_reference(*W.reference_profiles(w, z))
+    t, Q = W.heating(w, x, y, z)
+    ctx._heat = torch.from_numpy(Q.reshape(len(t), -1)).to(device)
+    ctx.nh_set_forcing(4, t - 1500.0, ctx._heat)
+    q0 = torch.from_numpy(W.initial_state(w, x, y, z)).to(device)
+    ctx.nh_set_state(q0)
+    return ctx, q0
+
+
+SPECS = [((5, 4, 3), 4), ((3, 6, 2), 3), ((4, 3, 2), 5), ((7, 5, 4), 4), ((2, 2, 3), 2)]
+
+
+def test_batched_equals_single_instances(oracle_mod):
+    import torch
+    from paper_2504_08157_amd import nhsem
+    ctxs, q0s = zip(*[_instance(i, nel, N) for i, (nel, N) in enumerate(SPECS)])
+    dt, steps = 1.0, 4
+    with torch.cuda.stream(torch.cuda.Stream()):
+        b = nhsem.Batch(ctxs, steps_per_graph=2, tile_variant={4: 1})
+        b.nh_batch_step(0.0, dt, steps)
+        torch.cuda.synchronize()
+    got = [c.nh_get_state().cpu().numpy() for c in ctxs]
+    b.close()
+    for c, q0, gb in zip(ctxs, q0s, got):
+        c.nh_set_tile(0)
+        c.nh_set_state(q0)
+        c.nh_rk_step(0.0, dt, steps)
+        ref = c.nh_get_state().cpu().numpy()
+        np.testing.assert_array_equal(gb, ref)
+    # smallest instance also against the oracle
+    i, (nel, N) = 4, SPECS[4]
+    w = W.cfg_ensemble_member(i); w.mesh = W._tc_mesh(*nel, N)
+    orc = oracle_mod.Oracle(w.mesh, w.phys)
+    x, y, z = orc.lattice_coords()
+    orc.set_reference(*W.reference_profiles(w, z))
+    t, Q = W.heating(w, x, y, z)
+    orc.set_forcing(4, t - 1500.0, Q)
+    ref = orc.rk3(0.0, dt, steps, W.initial_state(w, x, y, z))
+    for f in range(5):
+        assert np.linalg.norm(got[4][f] - ref[f]) <= 1e-12 * np.linalg.norm(ref[f]), f
+
+
+def test_batch_rejects_bad_arguments():
+    import torch
+    from paper_2504_08157_amd import nhsem
+    ctx, _ = _instance(0, (2, 2, 2), 4)
+    with pytest.raises(nhsem.NHError):
+        nhsem.Batch([ctx, ctx])
+    b = nhsem.Batch([ctx], steps_per_graph=3)
+    with pytest.raises(nhsem.NHError):
+        b.nh_batch_step(0.0, 1.0, 4)

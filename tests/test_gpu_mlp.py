@@ -114,3 +114,20 @@ def test_untrained_guess_equals_default(oracle_mod):
     b = ctx.nh_get_state().cpu().numpy()
     assert st0.iters_total == st1.iters_total
     np.testing.assert_array_equal(a, b)
+
+
+def test_learned_guess_reduces_iterations():
+    """Train on solves of one small TC mesh, evaluate on held-out steps of a
+    finer one: fewer Arnoldi steps per solve, same converged states."""
+    from paper_2504_08157_amd import learned_guess as LG
+    from paper_2504_08157_amd import nhsem
+    mlp = nhsem.ColumnMLP(max_batch=1024, seed=7)
+    wtr = W.cfg_hevi(); wtr.mesh = W._tc_mesh(16, 16, 6)
+    f, t = LG.collect(mlp, wtr, steps=3, dt=2.0)
+    hist, rate = LG.train(mlp, f, t, epochs=30, batch=1024, lr=1e-3)
+    assert hist[-1] < 0.5 * hist[0] or hist[-1] < 1e-3, hist
+    wev = W.cfg_hevi(); wev.mesh = W._tc_mesh(12, 12, 8)
+    res = LG.compare(mlp, wev, warm=1, held=2, dt=2.0)
+    print(res, "train samples/s", rate)
+    assert res["mlp"]["iters_per_solve"] < res["default"]["iters_per_solve"], res
+    assert max(res["state_rel_diff"]) < 1e-8, res
