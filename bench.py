@@ -34,6 +34,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-nel", type=int, default=48, help="horizontal elements of the oracle sample box")
     ap.add_argument("--tile", type=int, default=-1, help="stage-kernel tile variant; -1 = tune by timing")
+    ap.add_argument("--mode", choices=["rk", "hevi", "batched"], default="rk",
+                    help="rk: SSP-RK3 on the per-GPU TC share (headline); hevi: HEVI ARK2 step with and "
+                         "without the learned GMRES guess; batched: 48 uneven instances in graph launches")
+    ap.add_argument("--members", type=int, default=48)
     return ap.parse_args()
 
 
@@ -63,12 +67,130 @@ def cpu_baseline(w, nel):
                       f"sub-box of the same workload (U={orc.U}), {sec:.2f} s"}
 
 
+def bench_hevi(args):
+    """HEVI ARK2 steps on the 96 x 96 x 16, N = 4 case with the default GMRES
+    guess and with the column MLP trained on solves of the small TC mesh and
+    of the bubble mesh (same physics family), both to rtol 1e-10."""
+    import torch
+    from paper_2504_08157_amd import learned_guess as LG
+    from paper_2504_08157_amd import nhsem
+    from paper_2504_08157_amd import workloads as W
+    w = W.cfg_hevi()
+    mlp = nhsem.ColumnMLP(max_batch=8192, seed=7)
+    t0 = time.perf_counter()
+    wtr = W.cfg_tc_small()
+    f1, t1 = LG.collect(mlp, wtr, steps=3, dt=w.dt, max_per_step=32768)
+    wb = W.cfg_bubble()
+    f2, t2 = LG.collect(mlp, wb, steps=3, dt=0.05)
+    feats, tgts = torch.cat([f1, f2]), torch.cat([t1, t2])
+    t_collect = time.perf_counter() - t0
+    hist, rate = LG.train(mlp, feats, tgts, epochs=12, batch=4096, lr=1e-3)
+    res = LG.compare(mlp, w, warm=args.warmup, held=args.steps, dt=w.dt)
+    ctx = nhsem.Context(w.mesh, w.phys)
+    U = ctx.U
+    ctx.close()
+    d, m = res["default"], res["mlp"]
+    out = {
+        "metric": "DOF-stage updates/s (FP32/batched vs FP64 plain) at stated L2 error; % HBM peak",
+        "value": 5 * U * 3 / (m["ms_per_step"] / 1e3), "unit": "DOF-stage updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": m["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f16", "data": "synthetic",
+        "config": {"workload": w.name, "mode": "hevi", "dt": w.dt, "gmres": "GMRES(20), rtol 1e-10",
+                   "columns": res["columns"]},
+        "hevi": {"default": d, "mlp": m, "speedup_step": d["ms_per_step"] / m["ms_per_step"],
+                 "iteration_ratio": m["iters_per_solve"] / d["iters_per_solve"],
+                 "state_rel_diff_mlp_vs_default": res["state_rel_diff"],
+                 "training": {"samples": int(feats.shape[0]), "loss_first_last": [hist[0], hist[-1]],
+                              "samples_per_s": rate, "collect_s": t_collect}},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(args):
+    """48 uneven ensemble members (8x8x8 .. 40x40x16 elements, N in 3..5),
+    SSP-RK3 dt = 0.25 s, batched graph launches vs the same instances
+    stepped one by one."""
+    import torch
+    from paper_2504_08157_amd import nhsem
+    from paper_2504_08157_amd import workloads as W
+    prec = nhsem.NH_FP64 if args.precision == "fp64" else nhsem.NH_FP32_MIXED
+    ctxs, q0s = [], []
+    for i in range(args.members):
+        w = W.cfg_ensemble_member(i)
+        c = nhsem.Context(w.mesh, w.phys, precision=prec)
+        x, y, z = c.nh_lattice_coords()
+        c.nh_set_reference(*W.reference_profiles(w, z))
+        t, Q = W.heating(w, x, y, z)
+        c._heat = torch.from_numpy(Q.reshape(len(t), -1)).cuda()
+        c.nh_set_forcing(4, t, c._heat)
+        q0 = torch.from_numpy(W.initial_state(w, x, y, z)).cuda()
+        c.nh_set_state(q0)
+        ctxs.append(c); q0s.append(q0)
+    dt, K = 0.25, 5
+    Utot = sum(c.U for c in ctxs)
+    torch.cuda.synchronize()
+    # one by one
+    for c in ctxs:
+        c.nh_rk_step(0.0, dt, 2)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for c in ctxs:
+        c.nh_rk_step(0.0, dt, args.steps)
+    e1.record(); torch.cuda.synchronize()
+    ms_single = e0.elapsed_time(e1) / args.steps
+    for c, q0 in zip(ctxs, q0s):
+        c.nh_set_state(q0)
+    torch.cuda.synchronize()
+    # tile autotuning per order: time each variant on the batch
+    best = {}
+    s = torch.cuda.Stream()
+    tune = {}
+    for v in (0, 1):
+        with torch.cuda.stream(s):
+            b = nhsem.Batch(ctxs, steps_per_graph=K, tile_variant={n: v for n in range(7)}, stream=s)
+            b.nh_batch_step(0.0, dt, K)
+            a0 = torch.cuda.Event(enable_timing=True); a1 = torch.cuda.Event(enable_timing=True)
+            a0.record(s); b.nh_batch_step(0.0, dt, 2 * K); a1.record(s)
+        torch.cuda.synchronize()
+        tune[v] = a0.elapsed_time(a1) / (2 * K)
+        b.close()
+    v = min(tune, key=tune.get)
+    for c, q0 in zip(ctxs, q0s):
+        c.nh_set_state(q0)
+    torch.cuda.synchronize()
+    steps = (args.steps + K - 1) // K * K
+    with torch.cuda.stream(s):
+        b = nhsem.Batch(ctxs, steps_per_graph=K, tile_variant={n: v for n in range(7)}, stream=s)
+        b.nh_batch_step(0.0, dt, K)
+        a0 = torch.cuda.Event(enable_timing=True); a1 = torch.cuda.Event(enable_timing=True)
+        a0.record(s); b.nh_batch_step(K * dt, dt, steps); a1.record(s)
+    torch.cuda.synchronize()
+    ms_batch = a0.elapsed_time(a1) / steps
+    ok = all(c.nh_check_finite() == 0 for c in ctxs)
+    out = {
+        "metric": "DOF-stage updates/s (FP32/batched vs FP64 plain) at stated L2 error; % HBM peak",
+        "value": 5 * Utot * 3 / (ms_batch / 1e3), "unit": "DOF-stage updates/s", "n_gpus": 1,
+        "steps": steps, "warmup": K, "ms_per_step": ms_batch, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if prec == 0 else "f32+f64", "data": "synthetic",
+        "config": {"workload": "ensemble48_uneven", "mode": "batched", "members": len(ctxs), "unique_nodes": Utot,
+                   "steps_per_graph": K, "tile_variant": v, "tile_ms_per_step": tune},
+        "batched": {"ms_per_step_one_by_one": ms_single, "speedup_vs_one_by_one": ms_single / ms_batch,
+                    "finite": ok},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
               f"described in DESIGN.md", file=sys.stderr)
         sys.exit(2)
+    if args.mode == "hevi":
+        return bench_hevi(args)
+    if args.mode == "batched":
+        return bench_batched(args)
     import numpy as np
     import torch
     from paper_2504_08157_amd import nhsem

@@ -370,76 +370,128 @@ static double pprime(const or_ctx *c, int lev, double rhop, double thetap)
  * Q is the prescribed forcing.  Derivatives are reference-space contractions
  * with D (Algorithm 2) scaled by the affine metric 2/h.
  */
+/* Tendency r[f][m] = w_i w_j w_k J^e S_f of one element e at its (N+1)^3
+   local nodes m = i + (N+1)(j + (N+1) k). */
+static void element_one(const or_ctx *c, int64_t e, double t, const double *q, double *r, int64_t rstride)
+{
+    const int n1 = c->n1, np = c->np;
+    const int64_t U = c->U;
+    const int nxy = c->n[0] * c->n[1];
+    double F[8][MAXNP];      /* p', u, v, w, theta, rho u, rho v, rho w */
+    double rhoL[MAXNP], rpL[MAXNP], tpL[MAXNP];
+    int ex = (int)(e % c->nel[0]), ey = (int)((e / c->nel[0]) % c->nel[1]);
+    int ez = (int)(e / ((int64_t)c->nel[0] * c->nel[1]));
+    double hx = c->xe[ex + 1] - c->xe[ex], hy = c->ye[ey + 1] - c->ye[ey], hz = c->ze[ez + 1] - c->ze[ez];
+    double J = hx * hy * hz / 8.0;
+    /* global -> local gather and pointwise derived quantities */
+    for (int m = 0; m < np; ++m) {
+        int64_t I = c->intma[e * np + m];
+        int lev = (int)(I / nxy);
+        double rp = q[0 * U + I], u = q[1 * U + I], v = q[2 * U + I], w = q[3 * U + I], tp = q[4 * U + I];
+        double rho = c->rho0[lev] + rp;
+        F[0][m] = pprime(c, lev, rp, tp);
+        F[1][m] = u;
+        F[2][m] = v;
+        F[3][m] = w;
+        F[4][m] = c->theta0[lev] + tp;
+        F[5][m] = rho * u;
+        F[6][m] = rho * v;
+        F[7][m] = rho * w;
+        rhoL[m] = rho;
+        rpL[m] = rp;
+        tpL[m] = tp;
+    }
+    for (int k = 0; k < n1; ++k)
+        for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n1; ++i) {
+                int m = i + n1 * (j + n1 * k);
+                /* reference derivatives (Algorithm 2) */
+                double dxi[8], deta[8], dzeta[8];
+                for (int f = 0; f < 8; ++f) {
+                    double a = 0.0, b = 0.0, cc = 0.0;
+                    for (int l = 0; l < n1; ++l) {
+                        a += c->D[i * n1 + l] * F[f][l + n1 * (j + n1 * k)];
+                        b += c->D[j * n1 + l] * F[f][i + n1 * (l + n1 * k)];
+                        cc += c->D[k * n1 + l] * F[f][i + n1 * (j + n1 * l)];
+                    }
+                    dxi[f] = a; deta[f] = b; dzeta[f] = cc;
+                }
+                /* metric terms of the affine map */
+                double mx = 2.0 / hx, my = 2.0 / hy, mz = 2.0 / hz;
+                double gx[5], gy[5], gz[5];
+                for (int f = 0; f < 5; ++f) { gx[f] = mx * dxi[f]; gy[f] = my * deta[f]; gz[f] = mz * dzeta[f]; }
+                double divm = mx * dxi[5] + my * deta[6] + mz * dzeta[7];
+                int64_t I = c->intma[e * np + m];
+                int lev = (int)(I / nxy);
+                double u = F[1][m], v = F[2][m], w = F[3][m];
+                double rho = rhoL[m];
+                double tau = c->tau[lev];
+                double S[5];
+                S[0] = -divm;
+                S[1] = -(u * gx[1] + v * gy[1] + w * gz[1]) - gx[0] / rho + c->fcor * v - tau * u;
+                S[2] = -(u * gx[2] + v * gy[2] + w * gz[2]) - gy[0] / rho - c->fcor * u - tau * v;
+                S[3] = -(u * gx[3] + v * gy[3] + w * gz[3]) - gz[0] / rho - (rpL[m] / rho) * c->g - tau * w;
+                S[4] = -(u * gx[4] + v * gy[4] + w * gz[4]) - tau * tpL[m];
+                for (int f = 0; f < 5; ++f) S[f] += forcing_at(&c->frc[f], U, I, t);
+                double wJ = c->w[i] * c->w[j] * c->w[k] * J;
+                for (int f = 0; f < 5; ++f) r[f * rstride + m] = wJ * S[f];
+            }
+}
+
+/*
+ * Element tendencies r(f, e, k, j, i) = w_i w_j w_k J^e S_f at every local
+ * node (Algorithm 1: gather, gradient, divergence, evaluate f(grad q)).
+ * S (Eq. governing, hyper-diffusion excluded):
+ *   S_rho'   = - div(rho u)                                 rho = rho0 + rho'
+ *   S_u      = - u.grad u - (1/rho) dp'/dx + f v - tau u
+ *   S_v      = - u.grad v - (1/rho) dp'/dy - f u - tau v
+ *   S_w      = - u.grad w - (1/rho) dp'/dz - (rho'/rho) g - tau w
+ *   S_theta' = - u.grad(theta0 + theta') + Q - tau theta'
+ * Coriolis (f-plane) and the Rayleigh sponge are the workload's additions;
+ * Q is the prescribed forcing.  Derivatives are reference-space contractions
+ * with D (Algorithm 2) scaled by the affine metric 2/h.
+ */
 void or_element_tendency(void *p, double t, const double *q, double *r)
 {
     or_ctx *c = (or_ctx *)p;
-    const int N = c->N, n1 = c->n1, np = c->np;
-    const int64_t U = c->U, L = c->L;
-    const double gam = c->cp / c->cv;
-    const int nxy = c->n[0] * c->n[1];
 #pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < c->E; ++e) element_one(c, e, t, q, r + e * c->np, c->L);
+}
+
+/* The right-hand side at a sample of unique nodes only: the same element
+   tendencies, DSS (ascending element order) and mass inverse as or_rhs,
+   restricted to the elements that contain a requested node.  out is
+   [5][n]; nodes are unique indices I. */
+void or_rhs_sample(void *p, double t, const double *q, int64_t n, const int64_t *nodes, double *out)
+{
+    or_ctx *c = (or_ctx *)p;
+    const int np = c->np;
+    int64_t *slot = (int64_t *)malloc(sizeof(int64_t) * c->U);
+    for (int64_t I = 0; I < c->U; ++I) slot[I] = -1;
+    for (int64_t s = 0; s < n; ++s) slot[nodes[s]] = s;
+    for (int64_t s = 0; s < 5 * n; ++s) out[s] = 0.0;
+    double r[5 * MAXNP];
     for (int64_t e = 0; e < c->E; ++e) {
-        double F[8][MAXNP];      /* p', u, v, w, theta, rho u, rho v, rho w */
-        double rhoL[MAXNP], rpL[MAXNP], tpL[MAXNP];
-        int ex = (int)(e % c->nel[0]), ey = (int)((e / c->nel[0]) % c->nel[1]);
-        int ez = (int)(e / ((int64_t)c->nel[0] * c->nel[1]));
-        double hx = c->xe[ex + 1] - c->xe[ex], hy = c->ye[ey + 1] - c->ye[ey], hz = c->ze[ez + 1] - c->ze[ez];
-        double J = hx * hy * hz / 8.0;
-        /* global -> local gather and pointwise derived quantities */
+        int hit = 0;
+        for (int m = 0; m < np && !hit; ++m) hit = slot[c->intma[e * np + m]] >= 0;
+        if (!hit) continue;
+        element_one(c, e, t, q, r, np);
         for (int m = 0; m < np; ++m) {
-            int64_t I = c->intma[e * np + m];
-            int lev = (int)(I / nxy);
-            double rp = q[0 * U + I], u = q[1 * U + I], v = q[2 * U + I], w = q[3 * U + I], tp = q[4 * U + I];
-            double rho = c->rho0[lev] + rp;
-            F[0][m] = pprime(c, lev, rp, tp);
-            F[1][m] = u;
-            F[2][m] = v;
-            F[3][m] = w;
-            F[4][m] = c->theta0[lev] + tp;
-            F[5][m] = rho * u;
-            F[6][m] = rho * v;
-            F[7][m] = rho * w;
-            rhoL[m] = rho;
-            rpL[m] = rp;
-            tpL[m] = tp;
+            int64_t s = slot[c->intma[e * np + m]];
+            if (s < 0) continue;
+            for (int f = 0; f < NF; ++f) out[f * n + s] += r[f * np + m];
         }
-        (void)gam;
-        for (int k = 0; k < n1; ++k)
-            for (int j = 0; j < n1; ++j)
-                for (int i = 0; i < n1; ++i) {
-                    int m = i + n1 * (j + n1 * k);
-                    /* reference derivatives (Algorithm 2) */
-                    double dxi[8], deta[8], dzeta[8];
-                    for (int f = 0; f < 8; ++f) {
-                        double a = 0.0, b = 0.0, cc = 0.0;
-                        for (int l = 0; l < n1; ++l) {
-                            a += c->D[i * n1 + l] * F[f][l + n1 * (j + n1 * k)];
-                            b += c->D[j * n1 + l] * F[f][i + n1 * (l + n1 * k)];
-                            cc += c->D[k * n1 + l] * F[f][i + n1 * (j + n1 * l)];
-                        }
-                        dxi[f] = a; deta[f] = b; dzeta[f] = cc;
-                    }
-                    /* metric terms of the affine map */
-                    double mx = 2.0 / hx, my = 2.0 / hy, mz = 2.0 / hz;
-                    double gx[5], gy[5], gz[5];
-                    for (int f = 0; f < 5; ++f) { gx[f] = mx * dxi[f]; gy[f] = my * deta[f]; gz[f] = mz * dzeta[f]; }
-                    double divm = mx * dxi[5] + my * deta[6] + mz * dzeta[7];
-                    int64_t I = c->intma[e * np + m];
-                    int lev = (int)(I / nxy);
-                    double u = F[1][m], v = F[2][m], w = F[3][m];
-                    double rho = rhoL[m];
-                    double tau = c->tau[lev];
-                    double S[5];
-                    S[0] = -divm;
-                    S[1] = -(u * gx[1] + v * gy[1] + w * gz[1]) - gx[0] / rho + c->fcor * v - tau * u;
-                    S[2] = -(u * gx[2] + v * gy[2] + w * gz[2]) - gy[0] / rho - c->fcor * u - tau * v;
-                    S[3] = -(u * gx[3] + v * gy[3] + w * gz[3]) - gz[0] / rho - (rpL[m] / rho) * c->g - tau * w;
-                    S[4] = -(u * gx[4] + v * gy[4] + w * gz[4]) - tau * tpL[m];
-                    for (int f = 0; f < 5; ++f) S[f] += forcing_at(&c->frc[f], U, I, t);
-                    double wJ = c->w[i] * c->w[j] * c->w[k] * J;
-                    for (int f = 0; f < 5; ++f) r[f * L + e * np + m] = wJ * S[f];
-                }
     }
+    const int nx = c->n[0], ny = c->n[1], nz = c->n[2];
+    for (int64_t s = 0; s < n; ++s) {
+        int64_t I = nodes[s];
+        for (int f = 0; f < NF; ++f) out[f * n + s] /= c->M[I];
+        int ix = (int)(I % nx), iy = (int)((I / nx) % ny), iz = (int)(I / ((int64_t)nx * ny));
+        if (!c->per[0] && (ix == 0 || ix == nx - 1)) out[1 * n + s] = 0.0;
+        if (!c->per[1] && (iy == 0 || iy == ny - 1)) out[2 * n + s] = 0.0;
+        if (iz == 0 || iz == nz - 1) out[3 * n + s] = 0.0;
+    }
+    free(slot);
 }
 
 /* Zero the wall-normal velocity tendency at no-flux boundaries (reading:

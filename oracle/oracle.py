@@ -63,6 +63,7 @@ def load():
     lib.or_dss.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _dp, _dp]
     lib.or_scatter.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp]
     lib.or_lv_apply.argtypes = [ctypes.c_void_p, _dp, _dp]
+    lib.or_rhs_sample.argtypes = [ctypes.c_void_p, ctypes.c_double, _dp, ctypes.c_int64, _lp, _dp]
     _lib = lib
     return lib
 
@@ -176,6 +177,15 @@ class Oracle:
         out = np.zeros((5, self.U))
         self.lib.or_rhs(self.h, float(t), _p(q), _p(out))
         return out.reshape((5,) + self.shape)
+
+    def rhs_sample(self, t, q, nodes):
+        """Right-hand side [5][n] at unique nodes `nodes` only (same
+        arithmetic as rhs)."""
+        q = _c(q).reshape(5, self.U)
+        nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+        out = np.zeros((5, nodes.size))
+        self.lib.or_rhs_sample(self.h, float(t), _p(q), int(nodes.size), nodes.ctypes.data_as(_lp), _p(out))
+        return out
 
     def rk3(self, t, dt, nsteps, q):
         q = _c(q).reshape(5, self.U).copy()

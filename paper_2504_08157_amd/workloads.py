@@ -208,9 +208,9 @@ def vortex_state(x, y, z, rho0_z, theta0_z, exner0_z, dexner0_z, vmax=20.0, rmax
     function.  The balance is approximate; both sides receive identical
     arrays, so it does not affect parity."""
     p = phys or Physics()
-    X, Y, Z = grid3(x, y, z)
-    dx = X - center[0]
-    dy = Y - center[1]
+    # radial quantities on the horizontal plane, broadcast over levels
+    dx = (np.asarray(x) - center[0])[None, None, :]
+    dy = (np.asarray(y) - center[1])[None, :, None]
     r = np.sqrt(dx * dx + dy * dy)
     zz = np.asarray(z)
     Zf = np.exp(-zz * zz / (2 * D1 * D1))
@@ -238,7 +238,7 @@ def vortex_state(x, y, z, rho0_z, theta0_z, exner0_z, dexner0_z, vmax=20.0, rmax
     rho = p.p_a * pi ** (p.cv / p.R) / (p.R * theta)
     vt = vortex_profile(r, vmax, rmax) * Zc
     rs = np.where(r > 0, r, 1.0)
-    q = np.zeros((5,) + X.shape)
+    q = np.zeros((5, zz.size, dy.size, dx.size))
     q[0] = rho - rho0_z[:, None, None]
     q[1] = np.where(r > 0, -vt * dy / rs, 0.0)
     q[2] = np.where(r > 0, vt * dx / rs, 0.0)
@@ -287,7 +287,9 @@ def heating_field(x, y, z, t, sched: BurstSchedule):
 
 def heating_snapshots(x, y, z, T, sched: BurstSchedule, nsnap=11):
     t = np.array([k * T / (nsnap - 1) for k in range(nsnap)])
-    snaps = np.stack([heating_field(x, y, z, tk, sched) for tk in t])
+    snaps = np.empty((nsnap, np.size(z), np.size(y), np.size(x)))
+    for k, tk in enumerate(t):
+        snaps[k] = heating_field(x, y, z, tk, sched)
     return t, snaps
 
 

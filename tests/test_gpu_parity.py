@@ -201,3 +201,35 @@ def test_tile_variants_bitwise_equal(oracle_mod, N):
     np.testing.assert_array_equal(outs[0], outs[1])
     with pytest.raises(nhsem.NHError):
         ctx.nh_set_tile(2)
+
+
+def test_full_size_sampled_rhs_parity(oracle_mod):
+    """Tropical-cyclone box at its benchmark size (128 x 128 x 20 elements,
+    N = 4, 21.3 M unique nodes), in the launch configuration the benchmark
+    times (autotuned tile): the GPU tendency at 4096 seeded sample nodes
+    (plus every corner and edge class) against the oracle evaluated at those
+    nodes only."""
+    w = W.cfg_tc_large()
+    ctx, orc, g, o, prof, torch = _pair(oracle_mod, w.mesh, w.phys, reference="constant_n")
+    # one set of inputs (on the oracle's lattice) feeds both sides: at this
+    # size generating them twice would dominate the test
+    to, Qo = W.heating(w, *o)
+    Qdev = torch.from_numpy(Qo.reshape(len(to), -1)).cuda()
+    ctx.nh_set_forcing(4, to - 1500.0, Qdev)
+    orc.set_forcing(4, to - 1500.0, Qo)
+    qo = W.initial_state(w, *o)
+    qg = qo
+    rng = np.random.default_rng(2024)
+    nx, ny, nz = ctx.shape[2], ctx.shape[1], ctx.shape[0]
+    ix = np.concatenate([rng.integers(0, nx, 4096), [0, nx - 1, 0, nx - 1, 1, 4, 5]])
+    iy = np.concatenate([rng.integers(0, ny, 4096), [0, 0, ny - 1, ny - 1, 4, 1, 8]])
+    iz = np.concatenate([rng.integers(0, nz, 4096), [0, nz - 1, 4, 0, nz - 1, 5, 8]])
+    nodes = (iz * ny + iy) * nx + ix
+    qd = torch.from_numpy(qg).cuda()
+    for v in (0, 1):
+        ctx.nh_set_tile(v)
+        dq = ctx.nh_rhs(1600.0, qd).reshape(5, -1)[:, torch.from_numpy(nodes).cuda()].cpu().numpy()
+        ref = orc.rhs_sample(1600.0, qo, nodes)
+        err = _rel(dq, ref)
+        print("tile", v, err)
+        assert (err <= TOL64).all(), (v, err)
