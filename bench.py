@@ -32,19 +32,24 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--workload", default="tc_large", choices=["tc_large", "tc_small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-nel", type=int, default=48, help="horizontal elements of the oracle sample box")
+    ap.add_argument("--cpu-nel", type=int, default=128, help="horizontal elements of the oracle sample box")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="minimum oracle time of the CPU baseline")
     ap.add_argument("--tile", type=int, default=-1, help="stage-kernel tile variant; -1 = tune by timing")
-    ap.add_argument("--mode", choices=["rk", "hevi", "batched"], default="rk",
+    ap.add_argument("--copy-mib", type=int, default=1024, help="buffer size of the copy calibration")
+    ap.add_argument("--mode", choices=["rk", "hevi", "batched", "copy"], default="rk",
                     help="rk: SSP-RK3 on the per-GPU TC share (headline); hevi: HEVI ARK2 step with and "
-                         "without the learned GMRES guess; batched: 48 uneven instances in graph launches")
+                         "without the learned GMRES guess; batched: 48 uneven instances in graph launches; "
+                         "copy: a plain device-to-device copy of known size, the calibration run for the "
+                         "HBM byte counters")
     ap.add_argument("--members", type=int, default=48)
     return ap.parse_args()
 
 
-def cpu_baseline(w, nel):
-    """The FP64 oracle, untuned, on a bounded sample of the same workload: one
-    SSP-RK3 step of a nel x nel x 20 element box with the same element size,
-    physics and order."""
+def cpu_baseline(w, nel, min_seconds):
+    """The FP64 oracle, untuned, on a bounded sample of the same workload:
+    whole SSP-RK3 steps of a nel x nel x 20 element box with the same element
+    size, physics and order (nel = 128: the workload itself), repeated until
+    at least min_seconds of oracle time have passed."""
     import numpy as np
     import oracle
     from paper_2504_08157_amd import workloads as W
@@ -58,13 +63,16 @@ def cpu_baseline(w, nel):
     t, Q = W.heating(sub, x, y, z)
     orc.set_forcing(4, t, Q)
     q = W.initial_state(sub, x, y, z)
-    t0 = time.perf_counter()
-    orc.rk3(0.0, w.dt, 1, q)
-    sec = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": 5 * orc.U * 3 / sec, "unit": "DOF-stage updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"one SSP-RK3 step (3 RHS) of a {nel}x{nel}x{mesh.nel[2]} element N={mesh.order} "
-                      f"sub-box of the same workload (U={orc.U}), {sec:.2f} s"}
+    steps, sec = 0, 0.0
+    while sec < min_seconds and steps < 1000:
+        t0 = time.perf_counter()
+        q = orc.rk3(steps * w.dt, w.dt, 1, q)
+        sec += time.perf_counter() - t0
+        steps += 1
+    return {"value": 5 * orc.U * 3 * steps / sec, "unit": "DOF-stage updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} SSP-RK3 steps (3 RHS each) of a {nel}x{nel}x{mesh.nel[2]} element N={mesh.order} "
+                      f"box of the same workload (U={orc.U}), {sec:.2f} s"}
 
 
 def bench_hevi(args):
@@ -181,6 +189,29 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_copy(args):
+    """A plain device copy of args.copy_mib MiB, timed; under the FETCH_SIZE /
+    WRITE_SIZE counters it gives the counter-to-byte factor of this GPU."""
+    import torch
+    n = args.copy_mib * (1 << 20) // 8
+    src = torch.rand(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(args.warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / args.steps
+    nbytes = 2 * n * 8
+    print(json.dumps({"metric": "copy_bandwidth", "value": nbytes / ms / 1e6, "unit": "GB/s", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+                      "read_bytes": n * 8, "write_bytes": n * 8}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -191,6 +222,8 @@ def main():
         return bench_hevi(args)
     if args.mode == "batched":
         return bench_batched(args)
+    if args.mode == "copy":
+        return bench_copy(args)
     import numpy as np
     import torch
     from paper_2504_08157_amd import nhsem
@@ -277,7 +310,7 @@ def main():
         "wall_s_timed": wall,
     }
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(w, args.cpu_nel)
+        res["cpu_baseline"] = cpu_baseline(w, args.cpu_nel, args.cpu_seconds)
     print(json.dumps(res), flush=True)
 
 

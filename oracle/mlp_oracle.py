@@ -79,7 +79,9 @@ def column_features(b, lb, z, alpha):
     side and of L_v b; z: lattice levels.  Returns features [ncol][400] and
     the per-field scales [ncol][3]."""
     nz, ncol = b.shape[1], b.shape[2]
-    s = np.sqrt((b ** 2).mean(axis=1)) + 1e-30          # [3][ncol]
+    # per-field scale: RMS over the column of b_f together with the
+    # first-order correction alpha (L_v b)_f
+    s = np.sqrt((b ** 2).mean(axis=1) + ((alpha * lb) ** 2).mean(axis=1)) + 1e-30   # [3][ncol]
     zc = z[0] + (z[-1] - z[0]) * np.arange(64) / 63.0
     feat = np.zeros((ncol, IN))
     for f in range(3):

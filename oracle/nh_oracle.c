@@ -28,6 +28,7 @@
  * that applies them.  Parity of everything here is pinned by the CPU tests.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -658,3 +659,6 @@ void or_lv_apply(void *p, const double *x, double *y)
         if (iz == 0 || iz == c->n[2] - 1) y[3 * U + I] = 0.0;
     }
 }
+
+/* Threads an OpenMP loop of the oracle uses. */
+int or_num_threads(void) { return omp_get_max_threads(); }

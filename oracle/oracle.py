@@ -63,6 +63,7 @@ def load():
     lib.or_dss.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _dp, _dp]
     lib.or_scatter.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp]
     lib.or_lv_apply.argtypes = [ctypes.c_void_p, _dp, _dp]
+    lib.or_num_threads.restype = ctypes.c_int
     lib.or_rhs_sample.argtypes = [ctypes.c_void_p, ctypes.c_double, _dp, ctypes.c_int64, _lp, _dp]
     _lib = lib
     return lib
@@ -83,6 +84,11 @@ def lgl(N):
     if lib.or_lgl(N, _p(xi), _p(w), _p(D)) != 0:
         raise ValueError("unsupported order")
     return xi, w, D
+
+
+def num_threads():
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(load().or_num_threads())
 
 
 class Oracle:

@@ -49,12 +49,17 @@ __global__ void __launch_bounds__(64) mlp_features_kernel(MlpColParams p, const 
     const double H = p.z[p.nz - 1] - p.z[0];
     for (long r = blockIdx.x; r < ncol; r += gridDim.x) {
         const long col = col0 + r;
+        // s_f = RMS over the column of (b_f, alpha (L_v b)_f): the size of the
+        // right-hand side and of the first-order correction alpha L_v b, so
+        // that a field that is zero in b (w at rest) still gets the scale of
+        // its correction, and every feature is O(1).
         double s[3];
         for (int f = 0; f < 3; ++f) {
             double a = 0.0;
             for (int k = lane; k < p.nz; k += 64) {
                 const double v = b[fld[f] * U + col + (long)k * nxy];
-                a += v * v;
+                const double l = p.alpha * lb[fld[f] * U + col + (long)k * nxy];
+                a += v * v + l * l;
             }
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
@@ -107,7 +112,8 @@ __global__ void mlp_guess_kernel(MlpColParams p, const double *__restrict__ b, l
         if (t > 1.0) t = 1.0;
         for (int f = 0; f < 3; ++f) {
             const float *yr = y + r * kMlpOut + f * 64;
-            const double d = (1.0 - t) * yr[c0] + t * yr[c0 + 1];
+            double d = (1.0 - t) * yr[c0] + t * yr[c0 + 1];
+            if (!isfinite(d)) d = 0.0;  // a bad prediction falls back to x0 = b
             x0[f * U + I] = b[fld[f] * U + I] + (double)scale[r * 3 + f] * d;
         }
     }

@@ -52,7 +52,8 @@ def test_column_features_on_linear_profiles():
     zc = np.arange(64) / 63.0
     for f in range(3):
         for c in range(ncol):
-            rms = np.sqrt((b[f, :, c] ** 2).mean())
+            # scale = RMS of (b, alpha L_v b) = sqrt(1 + alpha^2) RMS(b) for lb = -b
+            rms = np.sqrt(5.0) * np.sqrt((b[f, :, c] ** 2).mean())
             np.testing.assert_allclose(s[c, f], rms, rtol=1e-15)
             np.testing.assert_allclose(feat[c, f * 64:(f + 1) * 64], (f + 1) * (c + 1) * (1 + zc) / rms, rtol=1e-14)
             np.testing.assert_allclose(feat[c, 192 + f * 64:192 + (f + 1) * 64],
@@ -60,3 +61,17 @@ def test_column_features_on_linear_profiles():
     assert np.all(feat[:, 388:] == 0) and np.allclose(feat[:, 387], 0.2)
     t = MO.column_targets(b, 2 * b, z, s)
     np.testing.assert_allclose(t, feat[:, :192], rtol=1e-14)
+
+
+def test_column_features_bounded_when_a_field_vanishes():
+    """w = 0 in b (a state at rest in the vertical) while L_v b has a w
+    component: the w scale is that of alpha L_v b, every feature is O(1)."""
+    z = np.linspace(0, 1000.0, 17)
+    b = np.zeros((3, 17, 1)); lb = np.zeros_like(b)
+    b[0, :, 0] = 1e-3 * np.cos(z / 300.0)
+    b[2, :, 0] = 0.5 * np.sin(z / 200.0)
+    lb[1, :, 0] = 2e-3 * np.sin(z / 250.0)
+    feat, s = MO.column_features(b, lb, z, alpha=3.0)
+    assert np.isclose(s[0, 1], 3.0 * np.sqrt((lb[1, :, 0] ** 2).mean()), rtol=1e-14)
+    rows = np.sqrt(17.0)  # |v| / RMS(v) <= sqrt(n)
+    assert np.all(np.abs(feat[:, :384]) <= rows + 1e-12)
