@@ -42,6 +42,7 @@ def parse():
                          "copy: a plain device-to-device copy of known size, the calibration run for the "
                          "HBM byte counters")
     ap.add_argument("--members", type=int, default=48)
+    ap.add_argument("--mlp-epochs", type=int, default=40, help="training epochs of the column MLP (hevi mode)")
     return ap.parse_args()
 
 
@@ -77,23 +78,20 @@ def cpu_baseline(w, nel, min_seconds):
 
 def bench_hevi(args):
     """HEVI ARK2 steps on the 96 x 96 x 16, N = 4 case with the default GMRES
-    guess and with the column MLP trained on solves of the small TC mesh and
-    of the bubble mesh (same physics family), both to rtol 1e-10."""
+    guess and with the column MLP, both to rtol 1e-10.  The MLP is trained on
+    solves the method generates: the small TC mesh and the bubble mesh, plus
+    the `warmup` default steps of this case (the held-out steps that are
+    timed come after them)."""
     import torch
     from paper_2504_08157_amd import learned_guess as LG
     from paper_2504_08157_amd import nhsem
     from paper_2504_08157_amd import workloads as W
     w = W.cfg_hevi()
     mlp = nhsem.ColumnMLP(max_batch=8192, seed=7)
-    t0 = time.perf_counter()
-    wtr = W.cfg_tc_small()
-    f1, t1 = LG.collect(mlp, wtr, steps=3, dt=w.dt, max_per_step=32768)
-    wb = W.cfg_bubble()
-    f2, t2 = LG.collect(mlp, wb, steps=3, dt=0.05)
-    feats, tgts = torch.cat([f1, f2]), torch.cat([t1, t2])
-    t_collect = time.perf_counter() - t0
-    hist, rate = LG.train(mlp, feats, tgts, epochs=12, batch=4096, lr=1e-3)
-    res = LG.compare(mlp, w, warm=args.warmup, held=args.steps, dt=w.dt)
+    warm = max(args.warmup, 1)
+    tr = LG.fit(mlp, w, w.dt, warm, [(W.cfg_tc_small(), 2, w.dt), (W.cfg_bubble(), 2, 0.5)],
+                epochs=args.mlp_epochs, batch=1024, lr=1e-3, max_per_step=24576)
+    res = LG.compare(mlp, w, warm=warm, held=args.steps, dt=w.dt)
     ctx = nhsem.Context(w.mesh, w.phys)
     U = ctx.U
     ctx.close()
@@ -101,15 +99,15 @@ def bench_hevi(args):
     out = {
         "metric": "DOF-stage updates/s (FP32/batched vs FP64 plain) at stated L2 error; % HBM peak",
         "value": 5 * U * 3 / (m["ms_per_step"] / 1e3), "unit": "DOF-stage updates/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": m["ms_per_step"],
+        "n_gpus": 1, "steps": args.steps, "warmup": warm, "ms_per_step": m["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f16", "data": "synthetic",
         "config": {"workload": w.name, "mode": "hevi", "dt": w.dt, "gmres": "GMRES(20), rtol 1e-10",
                    "columns": res["columns"]},
         "hevi": {"default": d, "mlp": m, "speedup_step": d["ms_per_step"] / m["ms_per_step"],
                  "iteration_ratio": m["iters_per_solve"] / d["iters_per_solve"],
                  "state_rel_diff_mlp_vs_default": res["state_rel_diff"],
-                 "training": {"samples": int(feats.shape[0]), "loss_first_last": [hist[0], hist[-1]],
-                              "samples_per_s": rate, "collect_s": t_collect}},
+                 "state_rel_diff_stacked": res["state_rel_diff_stacked"],
+                 "training": tr},
     }
     print(json.dumps(out), flush=True)
 

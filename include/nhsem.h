@@ -255,12 +255,12 @@ nh_status nh_batch_destroy(nh_batch *b);
 /* ------------------------------------------------------------------
  * Column MLP for the initial guess of the HEVI column solves (trained on
  * solves the method itself produces; the Krylov solve still runs to the
- * same tolerance).  Network 400 -> 256 -> 256 -> 192 with SiLU; FP16
+ * same tolerance).  Network 400 -> 256 -> 256 -> 256 with SiLU; FP16
  * weights and activations on MFMA with FP32 accumulation in the forward
  * pass, FP32 backward, Adam on FP32 master weights.  Parameters, in order:
- * W1 [256][400], b1 [256], W2 [256][256], b2 [256], W3 [192][256], b3 [192].
+ * W1 [256][400], b1 [256], W2 [256][256], b2 [256], W3 [256][256], b3 [256].
  * Inputs x: FP16 [batch][400] (features of nh_mlp_samples); outputs y: FP32
- * [batch][192].  batch: multiple of 64, at most the capacity given at
+ * [batch][256] (the first 3 x 65 are used).  batch: multiple of 64, at most the capacity given at
  * creation.
  * ------------------------------------------------------------------ */
 nh_status nh_mlp_workspace_bytes(int64_t max_batch, size_t *bytes);
@@ -278,7 +278,7 @@ nh_status nh_mlp_forward(nh_mlp *m, int64_t batch, const void *dev_x_f16, float 
    forward pass (FP32, overwritten). */
 nh_status nh_mlp_backward(nh_mlp *m, int64_t batch, const void *dev_x_f16, const float *dev_dy);
 
-/* forward, mean-squared-error loss against dev_t [batch][192], backward,
+/* forward, mean-squared-error loss against dev_t [batch][256], backward,
    Adam (Kingma & Ba, bias-corrected).  dev_loss (device float, optional). */
 nh_status nh_mlp_train_step(nh_mlp *m, int64_t batch, const void *dev_x_f16, const float *dev_t, float lr,
                             float b1, float b2, float eps, float *dev_loss);
@@ -291,11 +291,12 @@ nh_status nh_mlp_set_params(nh_mlp *m, const float *dev_master);
 
 /* Training samples / features for columns [col0, col0 + ncol) of ctx: the
    right-hand side b of (I - alpha L_v) x = b and, if dev_x is given, the
-   solution x.  dev_feat FP16 [ncol][400], dev_scale float [ncol][3] (the
-   per-field RMS), dev_tgt float [ncol][192] (the scaled correction x - b on
-   the canonical levels; needs dev_x), dev_tmp device [5][U] scratch. */
+   solution x.  dev_feat FP16 [ncol][400], dev_scale double [ncol] (the
+   column scale), dev_tgt float [ncol][256] (the scaled dimensionless
+   correction x - b on the 65 canonical levels per field, zero past 195;
+   needs dev_x), dev_tmp device [5][U] scratch. */
 nh_status nh_mlp_samples(nh_mlp *m, nh_ctx *ctx, double alpha, const double *dev_b, const double *dev_x,
-                         int64_t col0, int64_t ncol, void *dev_feat, float *dev_scale, float *dev_tgt,
+                         int64_t col0, int64_t ncol, void *dev_feat, double *dev_scale, float *dev_tgt,
                          double *dev_tmp);
 
 nh_status nh_mlp_last_error(const nh_mlp *m, char *buf, size_t n);

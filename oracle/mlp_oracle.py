@@ -2,16 +2,28 @@
 
 Network y = W3 s(W2 s(W1 x + b1) + b2) + b3 with SiLU s(z) = z / (1 + e^-z),
 parameters flattened in the order W1 [256][400], b1, W2 [256][256], b2,
-W3 [192][256], b3; mean-squared-error loss; Adam (Kingma & Ba 2015) with
-bias correction.  Column features and targets follow the definition used
-by the library: per-field RMS scaling, linear resampling to 64 canonical
-levels z_c = z_0 + H c / 63.
+W3 [256][256], b3; mean-squared-error loss; Adam (Kingma & Ba 2015) with
+bias correction.
+
+Column features, targets and the guess follow the definition used by the
+library (the learned-guess design is this project's own; the paper has no
+learned part):
+  * fields (rho', w, theta') are made dimensionless level by level with the
+    reference state: rho'/rho0, w/c0 (c0 = sqrt(gamma p0 / rho0)), theta'/theta0;
+  * one scale per column, s = RMS over the column's 3 n_z values of the
+    dimensionless b and alpha L_v b together;
+  * the canonical column is the 65 LGL nodes of 16 equal order-4 elements
+    on the normalised height (z - z_0) / H; lattice data are resampled to it
+    linearly in z, and the predicted correction back to the lattice levels
+    the same way.
 """
 from __future__ import annotations
 
 import numpy as np
 
-IN, HID, OUT = 400, 256, 192
+IN, HID, OUT = 400, 256, 256
+NC = 65          # canonical levels
+NF = 3 * NC      # used outputs (rho', w, theta' on the canonical levels)
 SHAPES = [(HID, IN), (HID,), (HID, HID), (HID,), (OUT, HID), (OUT,)]
 
 
@@ -74,30 +86,70 @@ def adam(w, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
     return w - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def column_features(b, lb, z, alpha):
+def canonical_levels():
+    """Normalised heights of the canonical column: LGL nodes of order 4 in
+    each of 16 equal elements, shared element faces counted once."""
+    from .oracle import lgl
+    xi = np.asarray(lgl(4)[0], dtype=np.float64)
+    zc = np.zeros(NC)
+    for k in range(NC):
+        e = min(k // 4, 15)
+        zc[k] = (e + (xi[k - 4 * e] + 1.0) / 2.0) / 16.0
+    return zc
+
+
+def dimension_factors(rho0, p0, theta0, gamma):
+    """Per-level factors D [3][n_z] that make (rho', w, theta') dimensionless."""
+    c0 = np.sqrt(gamma * np.asarray(p0) / np.asarray(rho0))
+    return np.stack([np.asarray(rho0, dtype=np.float64), c0, np.asarray(theta0, dtype=np.float64)])
+
+
+def column_features(b, lb, z, alpha, D):
     """b, lb: arrays [3][n_z][ncol] of (rho', w, theta') of the right-hand
-    side and of L_v b; z: lattice levels.  Returns features [ncol][400] and
-    the per-field scales [ncol][3]."""
+    side and of L_v b; z: lattice levels; D: dimension factors [3][n_z].
+    Returns features [ncol][400] and the column scales s [ncol]."""
     nz, ncol = b.shape[1], b.shape[2]
-    # per-field scale: RMS over the column of b_f together with the
-    # first-order correction alpha (L_v b)_f
-    s = np.sqrt((b ** 2).mean(axis=1) + ((alpha * lb) ** 2).mean(axis=1)) + 1e-30   # [3][ncol]
-    zc = z[0] + (z[-1] - z[0]) * np.arange(64) / 63.0
+    bh = b / D[:, :, None]
+    lh = alpha * lb / D[:, :, None]
+    s = np.sqrt(((bh ** 2).sum(axis=(0, 1)) + (lh ** 2).sum(axis=(0, 1))) / (3 * nz)) + 1e-300
+    H = z[-1] - z[0]
+    zc = z[0] + H * canonical_levels()
     feat = np.zeros((ncol, IN))
     for f in range(3):
         for c in range(ncol):
-            feat[c, f * 64:(f + 1) * 64] = np.interp(zc, z, b[f, :, c]) / s[f, c]
-            feat[c, 192 + f * 64:192 + (f + 1) * 64] = alpha * np.interp(zc, z, lb[f, :, c]) / s[f, c]
-    feat[:, 384:387] = np.log10(s.T)
-    feat[:, 387] = alpha / 10.0
-    return feat, s.T
+            feat[c, f * NC:(f + 1) * NC] = np.interp(zc, z, bh[f, :, c]) / s[c]
+            feat[c, NF + f * NC:NF + (f + 1) * NC] = np.interp(zc, z, lh[f, :, c]) / s[c]
+    feat[:, 2 * NF] = np.log10(s) / 10.0
+    feat[:, 2 * NF + 1] = alpha / 10.0
+    feat[:, 2 * NF + 2] = 100.0 * alpha * D[1, 0] / H
+    feat[:, 2 * NF + 3] = np.log10(H) / 5.0
+    return feat, s
 
 
-def column_targets(b, x, z, s):
-    zc = z[0] + (z[-1] - z[0]) * np.arange(64) / 63.0
+def column_targets(b, x, z, D, s):
+    """Scaled dimensionless correction (x - b) / (D s) on the canonical levels
+    [ncol][256] (entries past 3 x 65 are zero)."""
+    zc = z[0] + (z[-1] - z[0]) * canonical_levels()
     ncol = b.shape[2]
+    d = (x - b) / D[:, :, None]
     t = np.zeros((ncol, OUT))
     for f in range(3):
         for c in range(ncol):
-            t[c, f * 64:(f + 1) * 64] = (np.interp(zc, z, x[f, :, c]) - np.interp(zc, z, b[f, :, c])) / s[c, f]
+            t[c, f * NC:(f + 1) * NC] = np.interp(zc, z, d[f, :, c]) / s[c]
     return t
+
+
+def column_guess(b, y, z, D, s):
+    """Initial guess x0 = b + D s resample(y) on the lattice levels; the w
+    correction is zero on the bottom and top levels (walls)."""
+    zh = (z - z[0]) / (z[-1] - z[0])
+    zc = canonical_levels()
+    x0 = np.array(b, dtype=np.float64, copy=True)
+    for f in range(3):
+        for c in range(b.shape[2]):
+            d = np.interp(zh, zc, y[c, f * NC:(f + 1) * NC])
+            if f == 1:
+                d[0] = 0.0
+                d[-1] = 0.0
+            x0[f, :, c] += D[f] * s[c] * d
+    return x0

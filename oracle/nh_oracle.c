@@ -462,14 +462,21 @@ void or_element_tendency(void *p, double t, const double *q, double *r)
 /* The right-hand side at a sample of unique nodes only: the same element
    tendencies, DSS (ascending element order) and mass inverse as or_rhs,
    restricted to the elements that contain a requested node.  out is
-   [5][n]; nodes are unique indices I. */
-void or_rhs_sample(void *p, double t, const double *q, int64_t n, const int64_t *nodes, double *out)
+   [5][n]; nodes must be distinct unique-node indices I (returns -1, and
+   computes nothing, on a repeated or out-of-range index). */
+int or_rhs_sample(void *p, double t, const double *q, int64_t n, const int64_t *nodes, double *out)
 {
     or_ctx *c = (or_ctx *)p;
     const int np = c->np;
     int64_t *slot = (int64_t *)malloc(sizeof(int64_t) * c->U);
     for (int64_t I = 0; I < c->U; ++I) slot[I] = -1;
-    for (int64_t s = 0; s < n; ++s) slot[nodes[s]] = s;
+    for (int64_t s = 0; s < n; ++s) {
+        if (nodes[s] < 0 || nodes[s] >= c->U || slot[nodes[s]] >= 0) {
+            free(slot);
+            return -1;
+        }
+        slot[nodes[s]] = s;
+    }
     for (int64_t s = 0; s < 5 * n; ++s) out[s] = 0.0;
     double r[5 * MAXNP];
     for (int64_t e = 0; e < c->E; ++e) {
@@ -493,6 +500,7 @@ void or_rhs_sample(void *p, double t, const double *q, int64_t n, const int64_t 
         if (iz == 0 || iz == nz - 1) out[3 * n + s] = 0.0;
     }
     free(slot);
+    return 0;
 }
 
 /* Zero the wall-normal velocity tendency at no-flux boundaries (reading:

@@ -64,6 +64,7 @@ def load():
     lib.or_scatter.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp]
     lib.or_lv_apply.argtypes = [ctypes.c_void_p, _dp, _dp]
     lib.or_num_threads.restype = ctypes.c_int
+    lib.or_rhs_sample.restype = ctypes.c_int
     lib.or_rhs_sample.argtypes = [ctypes.c_void_p, ctypes.c_double, _dp, ctypes.c_int64, _lp, _dp]
     _lib = lib
     return lib
@@ -188,10 +189,13 @@ class Oracle:
         """Right-hand side [5][n] at unique nodes `nodes` only (same
         arithmetic as rhs)."""
         q = _c(q).reshape(5, self.U)
-        nodes = np.ascontiguousarray(nodes, dtype=np.int64)
-        out = np.zeros((5, nodes.size))
-        self.lib.or_rhs_sample(self.h, float(t), _p(q), int(nodes.size), nodes.ctypes.data_as(_lp), _p(out))
-        return out
+        uniq, inv = np.unique(np.asarray(nodes, dtype=np.int64), return_inverse=True)
+        uniq = np.ascontiguousarray(uniq)
+        out = np.zeros((5, uniq.size))
+        rc = self.lib.or_rhs_sample(self.h, float(t), _p(q), int(uniq.size), uniq.ctypes.data_as(_lp), _p(out))
+        if rc != 0:
+            raise ValueError("or_rhs_sample: node index out of range or repeated")
+        return out[:, inv.reshape(-1)]
 
     def rk3(self, t, dt, nsteps, q):
         q = _c(q).reshape(5, self.U).copy()

@@ -88,15 +88,19 @@ hipError_t launch_axpy_multi(long n, const double *base, int nsrc, const LinComb
 hipError_t launch_gmres(const HeviParams &h, const GmresArgs &g, hipStream_t s);
 
 // ---- column MLP
-constexpr int kMlpIn = 400;    // 388 features padded to a multiple of 16
+constexpr int kMlpIn = 400;    // 394 features padded to a multiple of 16
 constexpr int kMlpHid = 256;
-constexpr int kMlpOut = 192;   // 3 fields x 64 canonical levels
+constexpr int kMlpOut = 256;   // 3 fields x 65 canonical levels, padded to a multiple of 64
+constexpr int kMlpNC = 65;     // canonical levels: LGL nodes of 16 order-4 elements
+constexpr int kMlpNF = 3 * kMlpNC;
 constexpr int kMlpLossBlocks = 256;
 
 struct MlpColParams {
     int nx, ny, nz;
-    const double *z;   // [n_z] lattice levels
-    double alpha;
+    const double *z;     // [n_z] lattice levels
+    const double *lev;   // level table [n_z][kLevW] (rho0, theta0, p0, ...)
+    double alpha, gamma;
+    double zc[kMlpNC];   // canonical normalised heights in [0, 1]
 };
 
 struct MlpNet {
@@ -109,13 +113,13 @@ struct MlpNet {
     float *Z1, *Z2, *Y, *dY, *dH, *dZ, *part, *loss;
     void *H1, *H2;                 // FP16 activations
     void *feat;                    // FP16 [max_batch][kMlpIn]
-    float *scale;                  // [max_batch][3]
+    double *scale;                 // [max_batch] column scales
 };
 
 hipError_t launch_mlp_features(const MlpColParams &p, const double *b, const double *lb, const double *x,
-                               long col0, long ncol, void *feat, float *scale, float *tgt, hipStream_t s);
+                               long col0, long ncol, void *feat, double *scale, float *tgt, hipStream_t s);
 hipError_t launch_mlp_guess(const MlpColParams &p, const double *b, long col0, long ncol, const float *y,
-                            const float *scale, double *x0, hipStream_t s);
+                            const double *scale, double *x0, hipStream_t s);
 hipError_t mlp_forward(const MlpNet &net, int M, const void *X, hipStream_t s);
 hipError_t mlp_backward(const MlpNet &net, int M, const void *X, const float *dY, hipStream_t s);
 hipError_t mlp_loss_grad(const MlpNet &net, int M, const float *T, float *loss, hipStream_t s);

@@ -152,13 +152,28 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
             px = N + s2 % TX;
             py = (r < N) ? r : N + TY;
         }
+        // Periodic wrap by one period (no integer division): staged columns
+        // lie in [-N, n + TX), and every column a valid node reads with a
+        // nonzero coefficient lies in [-N, n - 1 + N], which one period maps
+        // into the lattice (n >= N).  Columns further out are only read with
+        // zero coefficients and are staged as zeros.
         int xg = x0 + px - N, yg = y0 + py - N;
         bool ok = true;
         if (xg < 0 || xg >= p.nx) {
-            if (p.perx) xg = (xg + p.nx) % p.nx; else ok = false;
+            if (p.perx) {
+                xg += (xg < 0) ? p.nx : -p.nx;
+                ok = xg < p.nx;
+            } else {
+                ok = false;
+            }
         }
         if (yg < 0 || yg >= p.ny) {
-            if (p.pery) yg = (yg + p.ny) % p.ny; else ok = false;
+            if (p.pery) {
+                yg += (yg < 0) ? p.ny : -p.ny;
+                ok = ok && yg < p.ny;
+            } else {
+                ok = false;
+            }
         }
         double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0, v4 = 0.0, pp = 0.0;
         if (ok) {
@@ -192,12 +207,6 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
     // selection cannot defer the FMAs of a tap past the loads of later taps.
 #define NH_PIN(a)                                                                        \
     asm volatile("" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]))
-    // The averaged derivative at a node interior to its element in x (or y)
-    // is that element's own derivative: N+1 taps.  Only nodes on an element
-    // face (position 0 in the element; the tile is element aligned) add the
-    // N taps of the element before; those lanes run the extra taps under a
-    // partial execution mask, so the LDS traffic of the stencil drops from
-    // 2N+1 to about N+2 reads per field.
     auto horizontal = [&](int sl, T r0, int tx, int ty, T *own, T *XY, T &inv) {
         NH_FENCE();
         const T(*P)[PS] = pl[sl];
@@ -205,8 +214,8 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
 #pragma unroll
         for (int f = 0; f < 6; ++f) { dx[f] = T(0); dy[f] = T(0); }
         const int rowx = (N + ty) * PX;
-        const int ix = tx % N, iy = ty % N;
-        auto xtap = [&](int m) {
+#pragma unroll
+        for (int m = 0; m < NC; ++m) {
             const T c = cx[tx * NC + m];
             const int j = rowx + tx + m;
             dx[0] += c * P[0][j];
@@ -216,8 +225,10 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
             dx[4] += c * P[4][j];
             dx[5] += c * ((r0 + P[5][j]) * P[1][j]);
             NH_PIN(dx);
-        };
-        auto ytap = [&](int m) {
+        }
+        NH_FENCE();
+#pragma unroll
+        for (int m = 0; m < NC; ++m) {
             const T c = cy[ty * NC + m];
             const int j = (ty + m) * PX + N + tx;
             dy[0] += c * P[0][j];
@@ -227,22 +238,7 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
             dy[4] += c * P[4][j];
             dy[5] += c * ((r0 + P[5][j]) * P[2][j]);
             NH_PIN(dy);
-        };
-        if (ix == 0) {
-#pragma unroll
-            for (int m = 0; m < N; ++m) xtap(m);
         }
-        NH_FENCE();
-#pragma unroll
-        for (int mm = 0; mm <= N; ++mm) xtap(N - ix + mm);
-        NH_FENCE();
-        if (iy == 0) {
-#pragma unroll
-            for (int m = 0; m < N; ++m) ytap(m);
-        }
-        NH_FENCE();
-#pragma unroll
-        for (int mm = 0; mm <= N; ++mm) ytap(N - iy + mm);
         NH_FENCE();
         const int jo = rowx + N + tx;
 #pragma unroll
@@ -288,7 +284,7 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
     struct NodeIn {
         uint32_t o;
         bool valid;
-        double qn[5];
+        double qn[5], h0, h1;
     };
     auto prefetch = [&](int k, int gx0, int gy0, NodeIn &nd) {
         nd.valid = gx0 < p.nx && gy0 < p.ny;
@@ -297,6 +293,8 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
 #pragma unroll
         for (int f = 0; f < 5; ++f)
             nd.qn[f] = (p.a != 0.0) ? *(const double *)((const char *)p.qn + nd.o + f * field_bytes) : 0.0;
+        nd.h0 = p.hq0 ? *(const double *)((const char *)p.hq0 + nd.o) : 0.0;
+        nd.h1 = p.hq0 ? *(const double *)((const char *)p.hq1 + nd.o) : 0.0;
     };
 
     // Complete the tendency at level k and write a q^n + b q^s + c R.
@@ -327,9 +325,7 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
         double Rd[5];
 #pragma unroll
         for (int f = 0; f < 5; ++f) Rd[f] = double(R[f]);
-        if (p.hq0)
-            Rd[4] += (1.0 - p.hlam) * *(const double *)((const char *)p.hq0 + o) +
-                     p.hlam * *(const double *)((const char *)p.hq1 + o);
+        if (p.hq0) Rd[4] += (1.0 - p.hlam) * nd.h0 + p.hlam * nd.h1;
         if (!p.perx && (gx == 0 || gx == p.nx - 1)) Rd[1] = 0.0;
         if (!p.pery && (gy == 0 || gy == p.ny - 1)) Rd[2] = 0.0;
         if (k == 0 || k == p.nz - 1) Rd[3] = 0.0;

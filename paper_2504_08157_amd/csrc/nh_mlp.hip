@@ -2,14 +2,18 @@
 // the HEVI column solves: feature extraction and resampling, FP16 MFMA
 // forward GEMMs with FP32 accumulation, FP32 backward, Adam.
 //
-// Network: x (K0 = 400: 388 features zero-padded) -> SiLU(W1 x + b1) (256)
-//          -> SiLU(W2 h1 + b2) (256) -> W3 h2 + b3 (192).
+// Network: x (400: 394 features zero-padded) -> SiLU(W1 x + b1) (256)
+//          -> SiLU(W2 h1 + b2) (256) -> W3 h2 + b3 (256: 195 used).
 // Features of a column with right-hand side b (fields rho', w, theta' on the
-// n_z lattice levels): each field scaled by its own RMS s_f over the column,
-// resampled linearly in z to 64 canonical levels z_c = H c / 63, for b and for
-// alpha L_v b (the first Neumann term of (I - alpha L_v)^-1); then 4 scalars
-// (log10 s_f for the three fields, alpha / 10).  Output: the correction
-// delta_f on the canonical levels, x0_f = b_f + s_f * resample^-1(delta_f).
+// n_z lattice levels): the fields are made dimensionless level by level
+// (rho'/rho0, w/c0 with c0 = sqrt(gamma p0 / rho0), theta'/theta0), divided
+// by one column scale s (RMS of the dimensionless b and alpha L_v b over the
+// column's 3 n_z values) and resampled linearly in z to the 65 canonical
+// levels (LGL nodes of 16 equal order-4 elements of the column), for b and
+// for alpha L_v b (the first Neumann term of (I - alpha L_v)^-1); then 4
+// scalars (log10 s / 10, alpha / 10, 100 alpha c0(z_0) / H, log10 H / 5).
+// Output: the dimensionless correction on the canonical levels,
+// x0 = b + D s resample^-1(y), with the w correction zero on the walls.
 #include "nh_internal.h"
 
 #include <hip/hip_fp16.h>
@@ -35,12 +39,22 @@ __device__ __forceinline__ void canon_interp(const double *z, int nz, double zc,
     if (*t > 1.0) *t = 1.0;
 }
 
-// One wavefront per column; lane c = canonical level c.
+// Dimension factor of field f (0: rho', 1: w, 2: theta') at lattice level k.
+__device__ __forceinline__ double dim_factor(const MlpColParams &p, int f, int k)
+{
+    const double *L = p.lev + (long)k * kLevW;
+    if (f == 0) return L[0];
+    if (f == 2) return L[1];
+    return sqrt(p.gamma * L[2] / L[0]);
+}
+
+// One wavefront per column; lanes stride over lattice levels for the scale
+// and over canonical levels for the resampling.
 __global__ void __launch_bounds__(64) mlp_features_kernel(MlpColParams p, const double *__restrict__ b,
                                                           const double *__restrict__ lb,
                                                           const double *__restrict__ x, long col0,
                                                           long ncol, _Float16 *__restrict__ feat,
-                                                          float *__restrict__ scale, float *__restrict__ tgt)
+                                                          double *__restrict__ scale, float *__restrict__ tgt)
 {
     const long nxy = (long)p.nx * p.ny;
     const long U = nxy * p.nz;
@@ -49,49 +63,52 @@ __global__ void __launch_bounds__(64) mlp_features_kernel(MlpColParams p, const 
     const double H = p.z[p.nz - 1] - p.z[0];
     for (long r = blockIdx.x; r < ncol; r += gridDim.x) {
         const long col = col0 + r;
-        // s_f = RMS over the column of (b_f, alpha (L_v b)_f): the size of the
-        // right-hand side and of the first-order correction alpha L_v b, so
-        // that a field that is zero in b (w at rest) still gets the scale of
-        // its correction, and every feature is O(1).
-        double s[3];
-        for (int f = 0; f < 3; ++f) {
-            double a = 0.0;
-            for (int k = lane; k < p.nz; k += 64) {
-                const double v = b[fld[f] * U + col + (long)k * nxy];
-                const double l = p.alpha * lb[fld[f] * U + col + (long)k * nxy];
+        double a = 0.0;
+        for (int k = lane; k < p.nz; k += 64) {
+            for (int f = 0; f < 3; ++f) {
+                const double d = 1.0 / dim_factor(p, f, k);
+                const double v = b[fld[f] * U + col + (long)k * nxy] * d;
+                const double l = p.alpha * lb[fld[f] * U + col + (long)k * nxy] * d;
                 a += v * v + l * l;
             }
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
-            s[f] = sqrt(a / p.nz) + 1e-30;
         }
-        const double zc = p.z[0] + H * lane / 63.0;
-        int k0;
-        double t;
-        canon_interp(p.z, p.nz, zc, &k0, &t);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+        const double s = sqrt(a / (3.0 * p.nz)) + 1e-300;
         _Float16 *fr = feat + r * kMlpIn;
-        for (int f = 0; f < 3; ++f) {
-            const long I0 = fld[f] * U + col + (long)k0 * nxy, I1 = I0 + nxy;
-            const double vb = (1.0 - t) * b[I0] + t * b[I1];
-            const double vl = (1.0 - t) * lb[I0] + t * lb[I1];
-            fr[f * 64 + lane] = (_Float16)(vb / s[f]);
-            fr[192 + f * 64 + lane] = (_Float16)(p.alpha * vl / s[f]);
-            if (tgt) {
-                const double vx = (1.0 - t) * x[I0] + t * x[I1];
-                tgt[r * kMlpOut + f * 64 + lane] = (float)((vx - vb) / s[f]);
+        for (int c = lane; c < kMlpNC; c += 64) {
+            int k0;
+            double t;
+            canon_interp(p.z, p.nz, p.z[0] + H * p.zc[c], &k0, &t);
+            for (int f = 0; f < 3; ++f) {
+                const long I0 = fld[f] * U + col + (long)k0 * nxy, I1 = I0 + nxy;
+                const double d0 = 1.0 / dim_factor(p, f, k0), d1 = 1.0 / dim_factor(p, f, k0 + 1);
+                const double vb = (1.0 - t) * (b[I0] * d0) + t * (b[I1] * d1);
+                const double vl = (1.0 - t) * (p.alpha * lb[I0] * d0) + t * (p.alpha * lb[I1] * d1);
+                fr[f * kMlpNC + c] = (_Float16)(vb / s);
+                fr[kMlpNF + f * kMlpNC + c] = (_Float16)(vl / s);
+                if (tgt) {
+                    const double vx = (1.0 - t) * ((x[I0] - b[I0]) * d0) + t * ((x[I1] - b[I1]) * d1);
+                    tgt[r * kMlpOut + f * kMlpNC + c] = (float)(vx / s);
+                }
             }
         }
-        if (lane < 3) fr[384 + lane] = (_Float16)log10(s[lane]);
-        if (lane == 3) fr[387] = (_Float16)(p.alpha / 10.0);
-        if (lane >= 4 && lane < 4 + (kMlpIn - 388)) fr[384 + lane] = (_Float16)0.0f;
-        if (lane < 3) scale[r * 3 + lane] = (float)s[lane];
+        if (lane == 0) fr[2 * kMlpNF] = (_Float16)(log10(s) / 10.0);
+        if (lane == 1) fr[2 * kMlpNF + 1] = (_Float16)(p.alpha / 10.0);
+        if (lane == 2) fr[2 * kMlpNF + 2] = (_Float16)(100.0 * p.alpha * dim_factor(p, 1, 0) / H);
+        if (lane == 3) fr[2 * kMlpNF + 3] = (_Float16)(log10(H) / 5.0);
+        for (int i = 2 * kMlpNF + 4 + lane; i < kMlpIn; i += 64) fr[i] = (_Float16)0.0f;
+        if (tgt)
+            for (int i = kMlpNF + lane; i < kMlpOut; i += 64) tgt[r * kMlpOut + i] = 0.0f;
+        if (lane == 0) scale[r] = s;
     }
 }
 
-// x0 = b + s_f * (delta_f resampled from canonical to lattice levels), one
-// thread per lattice node of the batch.
+// x0 = b + D s (y resampled from the canonical to the lattice levels), one
+// thread per lattice node of the batch; the w correction is zero on the
+// bottom and top levels, and a non-finite prediction falls back to x0 = b.
 __global__ void mlp_guess_kernel(MlpColParams p, const double *__restrict__ b, long col0, long ncol,
-                                 const float *__restrict__ y, const float *__restrict__ scale,
+                                 const float *__restrict__ y, const double *__restrict__ scale,
                                  double *__restrict__ x0)
 {
     const long nxy = (long)p.nx * p.ny;
@@ -103,18 +120,20 @@ __global__ void mlp_guess_kernel(MlpColParams p, const double *__restrict__ b, l
         const long r = i % ncol;
         const int k = (int)(i / ncol);
         const long I = col0 + r + (long)k * nxy;
-        double c = 63.0 * (p.z[k] - p.z[0]) / H;
-        int c0 = (int)floor(c);
-        if (c0 < 0) c0 = 0;
-        if (c0 > 62) c0 = 62;
-        double t = c - c0;
+        const double zh = (p.z[k] - p.z[0]) / H;
+        int lo = 0, hi = kMlpNC - 1;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (p.zc[mid] <= zh) lo = mid; else hi = mid;
+        }
+        double t = (zh - p.zc[lo]) / (p.zc[lo + 1] - p.zc[lo]);
         if (t < 0.0) t = 0.0;
         if (t > 1.0) t = 1.0;
         for (int f = 0; f < 3; ++f) {
-            const float *yr = y + r * kMlpOut + f * 64;
-            double d = (1.0 - t) * yr[c0] + t * yr[c0 + 1];
-            if (!isfinite(d)) d = 0.0;  // a bad prediction falls back to x0 = b
-            x0[f * U + I] = b[fld[f] * U + I] + (double)scale[r * 3 + f] * d;
+            const float *yr = y + r * kMlpOut + f * kMlpNC;
+            double d = (1.0 - t) * yr[lo] + t * yr[lo + 1];
+            if (!isfinite(d) || (f == 1 && (k == 0 || k == p.nz - 1))) d = 0.0;
+            x0[f * U + I] = b[fld[f] * U + I] + dim_factor(p, f, k) * scale[r] * d;
         }
     }
 }
@@ -296,7 +315,7 @@ static int grid_for(long n, int block)
 
 // ---------------------------------------------------------------- launchers
 hipError_t launch_mlp_features(const MlpColParams &p, const double *b, const double *lb, const double *x,
-                               long col0, long ncol, void *feat, float *scale, float *tgt, hipStream_t s)
+                               long col0, long ncol, void *feat, double *scale, float *tgt, hipStream_t s)
 {
     const int grid = (int)(ncol < 16384 ? ncol : 16384);
     hipLaunchKernelGGL(mlp_features_kernel, dim3(grid), dim3(64), 0, s, p, b, lb, x, col0, ncol,
@@ -305,7 +324,7 @@ hipError_t launch_mlp_features(const MlpColParams &p, const double *b, const dou
 }
 
 hipError_t launch_mlp_guess(const MlpColParams &p, const double *b, long col0, long ncol, const float *y,
-                            const float *scale, double *x0, hipStream_t s)
+                            const double *scale, double *x0, hipStream_t s)
 {
     hipLaunchKernelGGL(mlp_guess_kernel, dim3(grid_for(ncol * p.nz, 256)), dim3(256), 0, s, p, b, col0, ncol, y,
                        scale, x0);
@@ -329,7 +348,7 @@ hipError_t mlp_backward(const MlpNet &net, int M, const void *X, const float *dY
     const dim3 blk(256);
     const _Float16 *Xh = (const _Float16 *)X, *H1 = (const _Float16 *)net.H1, *H2 = (const _Float16 *)net.H2;
     const _Float16 *W2 = (const _Float16 *)net.wh[1], *W3 = (const _Float16 *)net.wh[2];
-    // layer 3: dW3 = dY^T H2 [192 x 256], db3 = sum dY, dH2 = dY W3 [M x 256]
+    // layer 3: dW3 = dY^T H2 [256 x 256], db3 = sum dY, dH2 = dY W3 [M x 256]
     hipLaunchKernelGGL((gemm_f32_kernel<float, _Float16>), dim3(kMlpHid / 64, kMlpOut / 64), blk, 0, s, dY, 1L,
                        (long)kMlpOut, H2, (long)kMlpHid, 1L, kMlpOut, kMlpHid, M, net.gw[2]);
     hipLaunchKernelGGL(colsum_kernel, dim3((kMlpOut + 255) / 256), blk, 0, s, dY, M, kMlpOut, net.gb[2]);

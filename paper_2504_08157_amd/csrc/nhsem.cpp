@@ -942,7 +942,7 @@ MlpLayout mlp_layout(long B)
     L.acts[8] = take(sizeof(uint16_t) * B * kMlpHid);  // H1
     L.acts[9] = take(sizeof(uint16_t) * B * kMlpHid);  // H2
     L.feat = take(sizeof(uint16_t) * B * kMlpIn);
-    L.scale = take(sizeof(float) * B * 3);
+    L.scale = take(sizeof(double) * B);
     L.total = off;
     return L;
 }
@@ -988,10 +988,30 @@ void mlp_init_host(uint64_t seed, std::vector<float> &w)
         const double a = sqrt(6.0 / (fin + fout));
         for (long i = 0; i < (long)fin * fout; ++i) {
             const int k = (int)(i % fin);
-            w[off + i] = (l == 2 || (l == 0 && k >= 388)) ? 0.0f : (float)(a * uni());
+            w[off + i] = (l == 2 || (l == 0 && k >= 2 * kMlpNF + 4)) ? 0.0f : (float)(a * uni());
         }
         off += (long)fin * fout + fout;
     }
+}
+
+// Column parameters of the feature and guess kernels; the canonical column is
+// the LGL nodes of order 4 in each of 16 equal elements of [0, 1].
+MlpColParams mlp_col_params(const nh_ctx *c, double alpha)
+{
+    MlpColParams p{};
+    p.nx = c->n[0]; p.ny = c->n[1]; p.nz = c->n[2];
+    p.z = c->zl; p.lev = c->lev;
+    p.alpha = alpha;
+    p.gamma = c->phys.cp / c->phys.cv;
+    std::vector<double> xi, w, D;
+    lgl_basis(4, xi, w, D);
+    for (int k = 0; k < kMlpNC; ++k) {
+        const int e = std::min(k / 4, 15);
+        p.zc[k] = (e + (xi[k - 4 * e] + 1.0) / 2.0) / 16.0;
+    }
+    p.zc[0] = 0.0;
+    p.zc[kMlpNC - 1] = 1.0;
+    return p;
 }
 
 }  // namespace
@@ -1000,7 +1020,7 @@ nh_status mlp_guess(nh_mlp *m, nh_ctx *c, double alpha, const double *b, double 
 {
     if (m->sticky) return fail(c, NH_ESTATE, "MLP in error state");
     HIPCHK(c, launch_lv_apply(hevi_params(c), b, lb, c->stream));
-    MlpColParams cp{c->n[0], c->n[1], c->n[2], c->zl, alpha};
+    const MlpColParams cp = mlp_col_params(c, alpha);
     const long ncol = (long)c->n[0] * c->n[1];
     for (long c0 = 0; c0 < ncol; c0 += m->max_batch) {
         const long nb = std::min<long>(m->max_batch, ncol - c0);
@@ -1057,7 +1077,7 @@ nh_status nh_mlp_create(int64_t max_batch, uint64_t seed, void *dev_ws, size_t b
     n.dY = (float *)(w + L.acts[3]); n.dH = (float *)(w + L.acts[4]); n.dZ = (float *)(w + L.acts[5]);
     n.part = (float *)(w + L.acts[6]); n.loss = (float *)(w + L.acts[7]);
     n.H1 = w + L.acts[8]; n.H2 = w + L.acts[9];
-    n.feat = w + L.feat; n.scale = (float *)(w + L.scale);
+    n.feat = w + L.feat; n.scale = (double *)(w + L.scale);
     m->max_batch = max_batch;
     m->step = 0;
     m->stream = (hipStream_t)hip_stream;
@@ -1145,7 +1165,7 @@ nh_status nh_mlp_set_params(nh_mlp *m, const float *dev_master)
 }
 
 nh_status nh_mlp_samples(nh_mlp *m, nh_ctx *c, double alpha, const double *dev_b, const double *dev_x,
-                         int64_t col0, int64_t ncol, void *dev_feat, float *dev_scale, float *dev_tgt,
+                         int64_t col0, int64_t ncol, void *dev_feat, double *dev_scale, float *dev_tgt,
                          double *dev_tmp)
 {
     nh_status st = guard(c);
@@ -1157,7 +1177,7 @@ nh_status nh_mlp_samples(nh_mlp *m, nh_ctx *c, double alpha, const double *dev_b
     if (col0 < 0 || ncol <= 0 || col0 + ncol > nc) return fail(c, NH_EINVAL, "column range outside the lattice");
     if (!c->have_ref) return fail(c, NH_EINVAL, "reference state not set");
     HIPCHK(c, launch_lv_apply(hevi_params(c), dev_b, dev_tmp, c->stream));
-    MlpColParams cp{c->n[0], c->n[1], c->n[2], c->zl, alpha};
+    const MlpColParams cp = mlp_col_params(c, alpha);
     HIPCHK(c, launch_mlp_features(cp, dev_b, dev_tmp, dev_x, col0, ncol, dev_feat, dev_scale, dev_tgt, c->stream));
     return NH_OK;
 }

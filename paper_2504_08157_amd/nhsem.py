@@ -395,7 +395,7 @@ class Context:
         return buf.value.decode(errors="replace")
 
 
-MLP_IN, MLP_HID, MLP_OUT = 400, 256, 192
+MLP_IN, MLP_HID, MLP_OUT = 400, 256, 256
 
 
 class ColumnMLP:
@@ -465,7 +465,7 @@ class ColumnMLP:
         import torch
         ncol = ctx.nx * ctx.ny - col0 if ncol is None else ncol
         feat = torch.empty((ncol, MLP_IN), dtype=torch.float16, device=self.device)
-        scale = torch.empty((ncol, 3), dtype=torch.float32, device=self.device)
+        scale = torch.empty(ncol, dtype=torch.float64, device=self.device)
         tgt = torch.empty((ncol, MLP_OUT), dtype=torch.float32, device=self.device) if x is not None else None
         if tmp is None:
             tmp = torch.empty(5 * ctx.U, dtype=torch.float64, device=self.device)

@@ -88,9 +88,11 @@ def test_features_match_oracle(oracle_mod):
     feat, scale, tgt = m.nh_mlp_samples(ctx, 0.7, torch.from_numpy(bq).cuda(), torch.from_numpy(xq).cuda())
     lb = orc.lv_apply(bq)
     sel = lambda a: np.stack([a[0], a[3], a[4]]).reshape(3, orc.nz, -1)
-    fo, so = MO.column_features(sel(bq), sel(lb), o[2], 0.7)
-    to = MO.column_targets(sel(bq), sel(xq), o[2], so)
-    np.testing.assert_allclose(scale.cpu().numpy(), so, rtol=1e-6)
+    rho0, th0 = W.constant_n_reference(o[2])
+    D = MO.dimension_factors(rho0, orc.reference_pressure(), th0, ph.cp / ph.cv)
+    fo, so = MO.column_features(sel(bq), sel(lb), o[2], 0.7, D)
+    to = MO.column_targets(sel(bq), sel(xq), o[2], D, so)
+    np.testing.assert_allclose(scale.cpu().numpy(), so, rtol=1e-12)
     assert _rel(feat.cpu().numpy().astype(np.float64), fo) <= 2e-3
     assert _rel(tgt.cpu().numpy(), to) <= 1e-6
 
@@ -117,17 +119,19 @@ def test_untrained_guess_equals_default(oracle_mod):
 
 
 def test_learned_guess_reduces_iterations():
-    """Train on solves of one small TC mesh, evaluate on held-out steps of a
-    finer one: fewer Arnoldi steps per solve, same converged states."""
+    """Train on solves the method generates (a small TC mesh, and the first
+    steps of the evaluation mesh), evaluate on the held-out steps that
+    follow: fewer Arnoldi steps per solve, states equal to the solver
+    tolerance."""
     from paper_2504_08157_amd import learned_guess as LG
     from paper_2504_08157_amd import nhsem
     mlp = nhsem.ColumnMLP(max_batch=1024, seed=7)
     wtr = W.cfg_hevi(); wtr.mesh = W._tc_mesh(16, 16, 6)
-    f, t = LG.collect(mlp, wtr, steps=3, dt=2.0)
-    hist, rate = LG.train(mlp, f, t, epochs=30, batch=1024, lr=1e-3)
-    assert hist[-1] < 0.5 * hist[0] or hist[-1] < 1e-3, hist
-    wev = W.cfg_hevi(); wev.mesh = W._tc_mesh(12, 12, 8)
-    res = LG.compare(mlp, wev, warm=1, held=2, dt=2.0)
-    print(res, "train samples/s", rate)
+    wev = W.cfg_hevi(); wev.mesh = W._tc_mesh(12, 12, 16)
+    tr = LG.fit(mlp, wev, 2.0, 3, [(wtr, 1, 2.0)], epochs=40, batch=512, lr=1e-3)
+    print("training", tr)
+    assert tr["loss_last"] < 0.05 * tr["loss_untrained"], tr
+    res = LG.compare(mlp, wev, warm=3, held=2, dt=2.0)
+    print(res)
     assert res["mlp"]["iters_per_solve"] < res["default"]["iters_per_solve"], res
-    assert max(res["state_rel_diff"]) < 1e-8, res
+    assert res["state_rel_diff_stacked"] < 1e-8, res

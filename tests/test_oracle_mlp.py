@@ -40,38 +40,85 @@ def test_silu_derivative():
     np.testing.assert_allclose(MO.dsilu(z), (MO.silu(z + h) - MO.silu(z - h)) / (2 * h), atol=1e-8)
 
 
+def test_canonical_levels():
+    """65 points: element faces at e/16, interior points at the order-4 LGL
+    nodes (0, +-sqrt(3/7)) of each element, increasing from 0 to 1."""
+    zc = MO.canonical_levels()
+    assert zc.size == 65 and zc[0] == 0.0 and zc[-1] == 1.0 and np.all(np.diff(zc) > 0)
+    r = np.sqrt(3.0 / 7.0)
+    for e in range(16):
+        np.testing.assert_allclose(zc[4 * e:4 * e + 4],
+                                   (e + (np.array([-1.0, -r, 0.0, r]) + 1.0) / 2.0) / 16.0, rtol=0, atol=1e-15)
+
+
+def _dims(nz, rho=1.2, c=340.0, th=300.0, gamma=1.4):
+    p0 = np.full(nz, c * c * rho / gamma)
+    return MO.dimension_factors(np.full(nz, rho), p0, np.full(nz, th), gamma)
+
+
 def test_column_features_on_linear_profiles():
+    """Linear profiles survive the linear resampling exactly; the common
+    scale is the RMS of the dimensionless b and alpha L_v b together."""
     z = np.linspace(0, 1000.0, 17)
     ncol = 3
+    D = _dims(17)
+    np.testing.assert_allclose(D[1], 340.0, rtol=1e-14)
     b = np.zeros((3, 17, ncol)); lb = np.zeros_like(b)
     for f in range(3):
         for c in range(ncol):
-            b[f, :, c] = (f + 1) * (c + 1) * (1.0 + z / 1000.0)
+            b[f, :, c] = D[f] * (f + 1) * (c + 1) * (1.0 + z / 1000.0)
             lb[f, :, c] = -b[f, :, c]
-    feat, s = MO.column_features(b, lb, z, alpha=2.0)
-    zc = np.arange(64) / 63.0
-    for f in range(3):
-        for c in range(ncol):
-            # scale = RMS of (b, alpha L_v b) = sqrt(1 + alpha^2) RMS(b) for lb = -b
-            rms = np.sqrt(5.0) * np.sqrt((b[f, :, c] ** 2).mean())
-            np.testing.assert_allclose(s[c, f], rms, rtol=1e-15)
-            np.testing.assert_allclose(feat[c, f * 64:(f + 1) * 64], (f + 1) * (c + 1) * (1 + zc) / rms, rtol=1e-14)
-            np.testing.assert_allclose(feat[c, 192 + f * 64:192 + (f + 1) * 64],
-                                       -2.0 * (f + 1) * (c + 1) * (1 + zc) / rms, rtol=1e-14)
-    assert np.all(feat[:, 388:] == 0) and np.allclose(feat[:, 387], 0.2)
-    t = MO.column_targets(b, 2 * b, z, s)
-    np.testing.assert_allclose(t, feat[:, :192], rtol=1e-14)
+    feat, s = MO.column_features(b, lb, z, alpha=2.0, D=D)
+    zc = MO.canonical_levels()
+    prof = 1.0 + z / 1000.0
+    for c in range(ncol):
+        # sum over fields of ((f+1)(c+1))^2 (1 + 4) mean(prof^2), over 3 n_z values
+        s_ref = np.sqrt(5.0 * (c + 1) ** 2 * (1 + 4 + 9) * (prof ** 2).mean() / 3.0)
+        np.testing.assert_allclose(s[c], s_ref, rtol=1e-14)
+        for f in range(3):
+            np.testing.assert_allclose(feat[c, f * 65:(f + 1) * 65], (f + 1) * (c + 1) * (1 + zc) / s_ref, rtol=1e-13)
+            np.testing.assert_allclose(feat[c, 195 + f * 65:195 + (f + 1) * 65],
+                                       -2.0 * (f + 1) * (c + 1) * (1 + zc) / s_ref, rtol=1e-13)
+        np.testing.assert_allclose(feat[c, 390], np.log10(s_ref) / 10.0, rtol=1e-14)
+    assert np.all(feat[:, 394:] == 0) and np.allclose(feat[:, 391], 0.2)
+    np.testing.assert_allclose(feat[:, 392], 100.0 * 2.0 * 340.0 / 1000.0, rtol=1e-14)
+    t = MO.column_targets(b, 2 * b, z, D, s)
+    np.testing.assert_allclose(t[:, :195], feat[:, :195], rtol=1e-13)
+    assert np.all(t[:, 195:] == 0)
+
+
+def test_column_guess_inverts_targets_on_the_canonical_grid():
+    """On a column whose levels are the canonical ones, resampling is the
+    identity: the guess built from the exact targets is the solution (the w
+    correction vanishing on the walls, as L_v keeps w fixed there)."""
+    H = 20e3
+    z = 100.0 + H * MO.canonical_levels()
+    rng = np.random.default_rng(4)
+    D = _dims(65)
+    b = rng.normal(size=(3, 65, 4)) * D[:, :, None]
+    x = b + 0.1 * rng.normal(size=b.shape) * D[:, :, None]
+    x[1, 0] = b[1, 0]
+    x[1, -1] = b[1, -1]
+    lb = rng.normal(size=b.shape)
+    feat, s = MO.column_features(b, lb, z, 0.5, D)
+    t = MO.column_targets(b, x, z, D, s)
+    np.testing.assert_allclose(MO.column_guess(b, t, z, D, s), x, rtol=1e-12, atol=0)
 
 
 def test_column_features_bounded_when_a_field_vanishes():
     """w = 0 in b (a state at rest in the vertical) while L_v b has a w
-    component: the w scale is that of alpha L_v b, every feature is O(1)."""
+    component: one common scale keeps every feature O(1) and the ratios
+    between the fields intact."""
     z = np.linspace(0, 1000.0, 17)
+    D = _dims(17)
     b = np.zeros((3, 17, 1)); lb = np.zeros_like(b)
     b[0, :, 0] = 1e-3 * np.cos(z / 300.0)
     b[2, :, 0] = 0.5 * np.sin(z / 200.0)
     lb[1, :, 0] = 2e-3 * np.sin(z / 250.0)
-    feat, s = MO.column_features(b, lb, z, alpha=3.0)
-    assert np.isclose(s[0, 1], 3.0 * np.sqrt((lb[1, :, 0] ** 2).mean()), rtol=1e-14)
-    rows = np.sqrt(17.0)  # |v| / RMS(v) <= sqrt(n)
-    assert np.all(np.abs(feat[:, :384]) <= rows + 1e-12)
+    feat, s = MO.column_features(b, lb, z, alpha=3.0, D=D)
+    assert np.all(np.abs(feat[:, :390]) <= np.sqrt(3 * 17.0) + 1e-12)
+    # the dimensionless rho' and theta' blocks keep their true ratio
+    k = 30
+    np.testing.assert_allclose(feat[0, k] / feat[0, 2 * 65 + k],
+                               np.interp(MO.canonical_levels()[k] * 1000.0, z, b[0, :, 0] / D[0]) /
+                               np.interp(MO.canonical_levels()[k] * 1000.0, z, b[2, :, 0] / D[2]), rtol=1e-12)

@@ -258,3 +258,20 @@ def test_bubble_mirror_symmetry(oracle_mod):
     assert (np.abs(flipy * sign - out).reshape(5, -1).max(axis=1) <= 1e-12 * scale + 1e-300).all()
     sw = out.transpose(0, 1, 3, 2)[[0, 2, 1, 3, 4]]
     assert (np.abs(sw - out).reshape(5, -1).max(axis=1) <= 1e-12 * scale + 1e-300).all()
+
+
+def test_rhs_sample_equals_full_rhs(oracle_mod):
+    """The sampled evaluation used at full size is the full right-hand side
+    restricted to the sample, bit for bit, with repeated and boundary nodes."""
+    ph = W.Physics(f=1e-4, sponge_z0=500.0, sponge_tau=0.02)
+    mesh = _cube(nel=(3, 4, 3), N=3, periodic=(True, False), stretch=True)
+    o, x, y, z, rho0, th0 = _setup(oracle_mod, mesh, ph)
+    q = W.smooth_random_state(x, y, z, rho0, th0, seed=12, walls=(False, True))
+    rng = np.random.default_rng(3)
+    F = rng.normal(size=(2,) + o.shape)
+    o.set_forcing(4, [0.0, 5.0], F)
+    R = o.rhs(1.5, q).reshape(5, -1)
+    nodes = np.concatenate([rng.integers(0, o.U, 300), [0, o.U - 1, 7, 7, 7]])
+    np.testing.assert_array_equal(o.rhs_sample(1.5, q, nodes), R[:, nodes])
+    with pytest.raises(ValueError):
+        o.rhs_sample(1.5, q, [o.U])
