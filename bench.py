@@ -24,6 +24,29 @@ HBM_PEAK_GBS = 8000.0
 BYTES_STAGE = {1: 40 + 16 + 40, 2: 40 + 40 + 16 + 40, 3: 40 + 40 + 16 + 40}
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "stage_kernel_tc_128x128x20_N4_fp64_hbm_counters.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2504_08157_amd", "csrc", "nh_kernels.hip")
+
+
+def measured_traffic(tile):
+    """HBM bytes per stage launch from the committed FETCH_SIZE / WRITE_SIZE
+    summary (copy-calibrated), or None when the stage kernel source or the
+    tile differs from the profiled one."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(COUNTERS):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.split()[0]
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        if kv.get("source_sha256") != sha or int(kv.get("tile_variant", -1)) != tile:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -36,11 +59,12 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="minimum oracle time of the CPU baseline")
     ap.add_argument("--tile", type=int, default=-1, help="stage-kernel tile variant; -1 = tune by timing")
     ap.add_argument("--copy-mib", type=int, default=1024, help="buffer size of the copy calibration")
-    ap.add_argument("--mode", choices=["rk", "hevi", "batched", "copy"], default="rk",
+    ap.add_argument("--err-steps", type=int, default=600, help="steps of the FP32-vs-FP64 comparison (precision mode)")
+    ap.add_argument("--mode", choices=["rk", "hevi", "batched", "copy", "precision"], default="rk",
                     help="rk: SSP-RK3 on the per-GPU TC share (headline); hevi: HEVI ARK2 step with and "
                          "without the learned GMRES guess; batched: 48 uneven instances in graph launches; "
                          "copy: a plain device-to-device copy of known size, the calibration run for the "
-                         "HBM byte counters")
+                         "HBM byte counters; precision: FP32-mixed vs FP64 after --err-steps steps")
     ap.add_argument("--members", type=int, default=48)
     ap.add_argument("--mlp-epochs", type=int, default=40, help="training epochs of the column MLP (hevi mode)")
     return ap.parse_args()
@@ -79,9 +103,10 @@ def cpu_baseline(w, nel, min_seconds):
 def bench_hevi(args):
     """HEVI ARK2 steps on the 96 x 96 x 16, N = 4 case with the default GMRES
     guess and with the column MLP, both to rtol 1e-10.  The MLP is trained on
-    solves the method generates: the small TC mesh and the bubble mesh, plus
-    the `warmup` default steps of this case (the held-out steps that are
-    timed come after them)."""
+    solves the method generates: the small TC mesh and the bubble mesh, the
+    `warmup` default steps of this case (the held-out steps that are timed
+    come after them), and random column right-hand sides solved by the
+    library's column GMRES on this vertical grid."""
     import torch
     from paper_2504_08157_amd import learned_guess as LG
     from paper_2504_08157_amd import nhsem
@@ -89,8 +114,11 @@ def bench_hevi(args):
     w = W.cfg_hevi()
     mlp = nhsem.ColumnMLP(max_batch=8192, seed=7)
     warm = max(args.warmup, 1)
+    wr = W.cfg_hevi()
+    wr.mesh = W._tc_mesh(32, 32, w.mesh.nel[2])   # same column grid, 16384 columns per random batch
     tr = LG.fit(mlp, w, w.dt, warm, [(W.cfg_tc_small(), 2, w.dt), (W.cfg_bubble(), 2, 0.5)],
-                epochs=args.mlp_epochs, batch=1024, lr=1e-3, max_per_step=24576)
+                epochs=args.mlp_epochs, batch=1024, lr=1e-3, max_per_step=24576, random_grid=wr,
+                random_batches=16)
     res = LG.compare(mlp, w, warm=warm, held=args.steps, dt=w.dt)
     ctx = nhsem.Context(w.mesh, w.phys)
     U = ctx.U
@@ -187,6 +215,64 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def _tc_context(w, prec):
+    import torch
+    from paper_2504_08157_amd import nhsem
+    from paper_2504_08157_amd import workloads as W
+    ctx = nhsem.Context(w.mesh, w.phys, precision=prec)
+    x, y, z = ctx.nh_lattice_coords()
+    ctx.nh_set_reference(*W.reference_profiles(w, z))
+    t_snap, Q = W.heating(w, x, y, z)
+    ctx._heat = torch.from_numpy(Q.reshape(len(t_snap), -1)).cuda()
+    del Q
+    ctx.nh_set_forcing(4, t_snap, ctx._heat)
+    q0 = torch.from_numpy(W.initial_state(w, x, y, z)).cuda()
+    ctx.nh_set_state(q0)
+    return ctx, q0
+
+
+def bench_precision(args):
+    """FP32-mixed (FP32 contractions and fluxes; FP64 EOS, reference
+    subtraction, DSS, RK) against the FP64 path on the per-GPU TC share:
+    per-field relative L2 difference after --err-steps SSP-RK3 steps from
+    the same initial state, and the time per step of each."""
+    import numpy as np
+    import torch
+    from paper_2504_08157_amd import nhsem
+    from paper_2504_08157_amd import workloads as W
+    w = W.cfg_tc_large() if args.workload == "tc_large" else W.cfg_tc_small()
+    out = {}
+    states = {}
+    for name, prec in (("fp64", nhsem.NH_FP64), ("fp32", nhsem.NH_FP32_MIXED)):
+        ctx, q0 = _tc_context(w, prec)
+        ctx.nh_set_tile(0 if args.tile < 0 else args.tile)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.nh_rk_step(0.0, w.dt, args.err_steps)
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = {"ms_per_step": e0.elapsed_time(e1) / args.err_steps}
+        states[name] = ctx.nh_get_state().cpu().numpy()
+        ctx.close()
+        del ctx, q0
+        torch.cuda.empty_cache()
+    a, b = states["fp32"], states["fp64"]
+    rel = [float(np.linalg.norm(a[f] - b[f]) / max(np.linalg.norm(b[f]), 1e-300)) for f in range(5)]
+    U = a[0].size
+    ms = out["fp32"]["ms_per_step"]
+    print(json.dumps({
+        "metric": "DOF-stage updates/s (FP32/batched vs FP64 plain) at stated L2 error; % HBM peak",
+        "value": 5 * U * 3 / (ms / 1e3), "unit": "DOF-stage updates/s", "n_gpus": 1,
+        "steps": args.err_steps, "warmup": 0, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": w.name, "mode": "precision", "dt": w.dt},
+        "precision": {"fields": ["rho'", "u", "v", "w", "theta'"], "rel_l2_fp32_vs_fp64": rel,
+                      "ms_per_step": out, "speedup_fp32_over_fp64": out["fp64"]["ms_per_step"] / ms,
+                      "simulated_s": args.err_steps * w.dt},
+    }), flush=True)
+
+
 def bench_copy(args):
     """A plain device copy of args.copy_mib MiB, timed; under the FETCH_SIZE /
     WRITE_SIZE counters it gives the counter-to-byte factor of this GPU."""
@@ -222,6 +308,8 @@ def main():
         return bench_batched(args)
     if args.mode == "copy":
         return bench_copy(args)
+    if args.mode == "precision":
+        return bench_precision(args)
     import numpy as np
     import torch
     from paper_2504_08157_amd import nhsem
@@ -275,6 +363,7 @@ def main():
     value = 5 * U * 3 * args.steps / (ms / 1e3)
     bytes_step = U * sum(BYTES_STAGE.values())
     achieved = bytes_step * args.steps / (ms / 1e3) / 1e9
+    traffic = measured_traffic(tile) if prec == nhsem.NH_FP64 and w.name == "tc_128x128x20_N4" else None
     res = {
         "metric": "DOF-stage updates/s (FP32/batched vs FP64 plain) at stated L2 error; % HBM peak",
         "value": value,
@@ -301,7 +390,9 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_unit": "HBM bytes per stage launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "algorithmic_bytes_per_launch": bytes_step / 3,
             "kernel": "stage_kernel (fused RHS + DSS + SSP-RK stage)",
             "avg_launch_ms": ms / launches,
         },

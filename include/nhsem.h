@@ -255,10 +255,11 @@ nh_status nh_batch_destroy(nh_batch *b);
 /* ------------------------------------------------------------------
  * Column MLP for the initial guess of the HEVI column solves (trained on
  * solves the method itself produces; the Krylov solve still runs to the
- * same tolerance).  Network 400 -> 256 -> 256 -> 256 with SiLU; FP16
- * weights and activations on MFMA with FP32 accumulation in the forward
- * pass, FP32 backward, Adam on FP32 master weights.  Parameters, in order:
- * W1 [256][400], b1 [256], W2 [256][256], b2 [256], W3 [256][256], b3 [256].
+ * same tolerance).  Network 400 -> 256 -> 256 -> 256 with SiLU and a
+ * linear bypass, y = W3 h2 + b3 + S x; FP16 weights and activations on MFMA
+ * with FP32 accumulation in the forward pass, FP32 backward, Adam on FP32
+ * master weights.  Parameters, in order: W1 [256][400], b1 [256],
+ * W2 [256][256], b2 [256], W3 [256][256], b3 [256], S [256][400].
  * Inputs x: FP16 [batch][400] (features of nh_mlp_samples); outputs y: FP32
  * [batch][256] (the first 3 x 65 are used).  batch: multiple of 64, at most the capacity given at
  * creation.

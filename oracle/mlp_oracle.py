@@ -1,9 +1,9 @@
 """FP64 NumPy oracle of the column MLP (test infrastructure only).
 
-Network y = W3 s(W2 s(W1 x + b1) + b2) + b3 with SiLU s(z) = z / (1 + e^-z),
-parameters flattened in the order W1 [256][400], b1, W2 [256][256], b2,
-W3 [256][256], b3; mean-squared-error loss; Adam (Kingma & Ba 2015) with
-bias correction.
+Network y = W3 s(W2 s(W1 x + b1) + b2) + b3 + S x with SiLU
+s(z) = z / (1 + e^-z) and a linear bypass S, parameters flattened in the
+order W1 [256][400], b1, W2 [256][256], b2, W3 [256][256], b3, S [256][400];
+mean-squared-error loss; Adam (Kingma & Ba 2015) with bias correction.
 
 Column features, targets and the guess follow the definition used by the
 library (the learned-guess design is this project's own; the paper has no
@@ -24,7 +24,7 @@ import numpy as np
 IN, HID, OUT = 400, 256, 256
 NC = 65          # canonical levels
 NF = 3 * NC      # used outputs (rho', w, theta' on the canonical levels)
-SHAPES = [(HID, IN), (HID,), (HID, HID), (HID,), (OUT, HID), (OUT,)]
+SHAPES = [(HID, IN), (HID,), (HID, HID), (HID,), (OUT, HID), (OUT,), (OUT, IN)]
 
 
 def unflatten(w):
@@ -50,19 +50,20 @@ def dsilu(z):
 
 
 def forward(w, x):
-    W1, b1, W2, b2, W3, b3 = unflatten(w)
+    W1, b1, W2, b2, W3, b3, S = unflatten(w)
     z1 = x @ W1.T + b1
     h1 = silu(z1)
     z2 = h1 @ W2.T + b2
     h2 = silu(z2)
-    y = h2 @ W3.T + b3
+    y = h2 @ W3.T + b3 + x @ S.T
     return y, (x, z1, h1, z2, h2)
 
 
 def backward(w, cache, dy):
     """Gradient of sum(y * dy) with respect to the flattened parameters."""
-    W1, b1, W2, b2, W3, b3 = unflatten(w)
+    W1, b1, W2, b2, W3, b3, S = unflatten(w)
     x, z1, h1, z2, h2 = cache
+    gS = dy.T @ x
     gW3 = dy.T @ h2
     gb3 = dy.sum(0)
     dz2 = (dy @ W3) * dsilu(z2)
@@ -71,7 +72,7 @@ def backward(w, cache, dy):
     dz1 = (dz2 @ W2) * dsilu(z1)
     gW1 = dz1.T @ x
     gb1 = dz1.sum(0)
-    return flatten([gW1, gb1, gW2, gb2, gW3, gb3])
+    return flatten([gW1, gb1, gW2, gb2, gW3, gb3, gS])
 
 
 def mse(y, t):

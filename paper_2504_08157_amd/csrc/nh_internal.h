@@ -107,9 +107,9 @@ struct MlpNet {
     long nparam;
     float *master, *grad, *m, *v;  // FP32 [nparam]
     void *half;                    // FP16 [nparam]
-    const void *wh[3];             // FP16 weights inside `half`
+    const void *wh[4];             // FP16 weights inside `half` (W1, W2, W3, linear bypass S)
     float *b[3];                   // FP32 biases inside `master`
-    float *gw[3], *gb[3];          // gradients inside `grad`
+    float *gw[4], *gb[3];          // gradients inside `grad`
     float *Z1, *Z2, *Y, *dY, *dH, *dZ, *part, *loss;
     void *H1, *H2;                 // FP16 activations
     void *feat;                    // FP16 [max_batch][kMlpIn]

@@ -3,7 +3,10 @@
 // forward GEMMs with FP32 accumulation, FP32 backward, Adam.
 //
 // Network: x (400: 394 features zero-padded) -> SiLU(W1 x + b1) (256)
-//          -> SiLU(W2 h1 + b2) (256) -> W3 h2 + b3 (256: 195 used).
+//          -> SiLU(W2 h1 + b2) (256) -> y = W3 h2 + b3 + S x (256: 195 used),
+// with a linear bypass S [256][400]: the exact map from the features to the
+// correction is linear for a fixed column grid and alpha ((I - alpha L_v)^-1
+// - I), the hidden layers carry its dependence on those.
 // Features of a column with right-hand side b (fields rho', w, theta' on the
 // n_z lattice levels): the fields are made dimensionless level by level
 // (rho'/rho0, w/c0 with c0 = sqrt(gamma p0 / rho0), theta'/theta0), divided
@@ -142,13 +145,16 @@ __global__ void mlp_guess_kernel(MlpColParams p, const double *__restrict__ b, l
 // C[M x N] = A[M x K] W[N x K]^T + bias, A and W FP16 row-major, FP32
 // accumulation on v_mfma_f32_16x16x16_f16.  Workgroup: 256 threads = 4 waves,
 // 64 x 64 tile of C, each wave a 32 x 32 quarter (2 x 2 MFMA tiles).
+// Optional second product A2[M x K2] W2[N x K2]^T into the same accumulators
+// (the linear bypass of the last layer).
 // Epilogue: Z (FP32, pre-activation) and, when act != 0, H = SiLU(Z) in FP16.
-// Requires M % 64 == 0, N % 64 == 0, K % 16 == 0.
+// Requires M % 64 == 0, N % 64 == 0, K % 16 == 0, K2 % 16 == 0.
 __global__ void __launch_bounds__(256) gemm_f16_kernel(const _Float16 *__restrict__ A,
                                                        const _Float16 *__restrict__ W,
                                                        const float *__restrict__ bias, int M, int N, int K,
                                                        float *__restrict__ Z, _Float16 *__restrict__ Hout,
-                                                       int act)
+                                                       int act, const _Float16 *__restrict__ A2,
+                                                       const _Float16 *__restrict__ W2, int K2)
 {
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int m0 = blockIdx.y * 64 + (wave / 2) * 32;
@@ -173,6 +179,21 @@ __global__ void __launch_bounds__(256) gemm_f16_kernel(const _Float16 *__restric
 #pragma unroll
             for (int c = 0; c < 2; ++c)
                 acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x16f16(av[a], bv[c], acc[a][c], 0, 0, 0);
+    }
+    if (A2) {
+        for (int k = 0; k < K2; k += 16) {
+            half4 av[2], bv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                av[a] = *(const half4 *)(A2 + (long)(m0 + a * 16 + r16) * K2 + k + kq);
+                bv[a] = *(const half4 *)(W2 + (long)(n0 + a * 16 + r16) * K2 + k + kq);
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x16f16(av[a], bv[c], acc[a][c], 0, 0, 0);
+        }
     }
     // output layout: lane holds rows 4*(lane/16)+i, column lane%16 of each 16x16 tile
 #pragma unroll
@@ -334,12 +355,16 @@ hipError_t launch_mlp_guess(const MlpColParams &p, const double *b, long col0, l
 hipError_t mlp_forward(const MlpNet &net, int M, const void *X, hipStream_t s)
 {
     const dim3 blk(256);
+    const _Float16 *none = nullptr;
     hipLaunchKernelGGL(gemm_f16_kernel, dim3(kMlpHid / 64, M / 64), blk, 0, s, (const _Float16 *)X,
-                       (const _Float16 *)net.wh[0], net.b[0], M, kMlpHid, kMlpIn, net.Z1, (_Float16 *)net.H1, 1);
+                       (const _Float16 *)net.wh[0], net.b[0], M, kMlpHid, kMlpIn, net.Z1, (_Float16 *)net.H1, 1,
+                       none, none, 0);
     hipLaunchKernelGGL(gemm_f16_kernel, dim3(kMlpHid / 64, M / 64), blk, 0, s, (const _Float16 *)net.H1,
-                       (const _Float16 *)net.wh[1], net.b[1], M, kMlpHid, kMlpHid, net.Z2, (_Float16 *)net.H2, 1);
+                       (const _Float16 *)net.wh[1], net.b[1], M, kMlpHid, kMlpHid, net.Z2, (_Float16 *)net.H2, 1,
+                       none, none, 0);
     hipLaunchKernelGGL(gemm_f16_kernel, dim3(kMlpOut / 64, M / 64), blk, 0, s, (const _Float16 *)net.H2,
-                       (const _Float16 *)net.wh[2], net.b[2], M, kMlpOut, kMlpHid, net.Y, (_Float16 *)nullptr, 0);
+                       (const _Float16 *)net.wh[2], net.b[2], M, kMlpOut, kMlpHid, net.Y, (_Float16 *)nullptr, 0,
+                       (const _Float16 *)X, (const _Float16 *)net.wh[3], kMlpIn);
     return hipGetLastError();
 }
 
@@ -348,6 +373,9 @@ hipError_t mlp_backward(const MlpNet &net, int M, const void *X, const float *dY
     const dim3 blk(256);
     const _Float16 *Xh = (const _Float16 *)X, *H1 = (const _Float16 *)net.H1, *H2 = (const _Float16 *)net.H2;
     const _Float16 *W2 = (const _Float16 *)net.wh[1], *W3 = (const _Float16 *)net.wh[2];
+    // linear bypass: dS = dY^T X [256 x 400]
+    hipLaunchKernelGGL((gemm_f32_kernel<float, _Float16>), dim3((kMlpIn + 63) / 64, kMlpOut / 64), blk, 0, s, dY,
+                       1L, (long)kMlpOut, Xh, (long)kMlpIn, 1L, kMlpOut, kMlpIn, M, net.gw[3]);
     // layer 3: dW3 = dY^T H2 [256 x 256], db3 = sum dY, dH2 = dY W3 [M x 256]
     hipLaunchKernelGGL((gemm_f32_kernel<float, _Float16>), dim3(kMlpHid / 64, kMlpOut / 64), blk, 0, s, dY, 1L,
                        (long)kMlpOut, H2, (long)kMlpHid, 1L, kMlpOut, kMlpHid, M, net.gw[2]);

@@ -920,7 +920,8 @@ struct MlpLayout {
 
 long mlp_nparam()
 {
-    return (long)kMlpHid * kMlpIn + kMlpHid + (long)kMlpHid * kMlpHid + kMlpHid + (long)kMlpOut * kMlpHid + kMlpOut;
+    return (long)kMlpHid * kMlpIn + kMlpHid + (long)kMlpHid * kMlpHid + kMlpHid + (long)kMlpOut * kMlpHid + kMlpOut +
+           (long)kMlpOut * kMlpIn;
 }
 
 MlpLayout mlp_layout(long B)
@@ -972,7 +973,8 @@ nh_status mlp_guard(const nh_mlp *m, int64_t batch)
 }
 
 // Glorot-uniform weights from a 64-bit LCG (seeded), zero biases; the last
-// layer starts at zero so an untrained network returns the default guess.
+// layer and the linear bypass start at zero so an untrained network returns
+// the default guess.
 void mlp_init_host(uint64_t seed, std::vector<float> &w)
 {
     w.assign(mlp_nparam(), 0.0f);
@@ -1073,6 +1075,9 @@ nh_status nh_mlp_create(int64_t max_batch, uint64_t seed, void *dev_ws, size_t b
         n.gw[l] = n.grad + offW[l];
         n.gb[l] = n.grad + offB[l];
     }
+    const long offS = offB[2] + kMlpOut;   // linear bypass S [kMlpOut][kMlpIn]
+    n.wh[3] = (const char *)n.half + sizeof(uint16_t) * offS;
+    n.gw[3] = n.grad + offS;
     n.Z1 = (float *)(w + L.acts[0]); n.Z2 = (float *)(w + L.acts[1]); n.Y = (float *)(w + L.acts[2]);
     n.dY = (float *)(w + L.acts[3]); n.dH = (float *)(w + L.acts[4]); n.dZ = (float *)(w + L.acts[5]);
     n.part = (float *)(w + L.acts[6]); n.loss = (float *)(w + L.acts[7]);

@@ -33,13 +33,14 @@ def hevi_context(w, device="cuda"):
 
 def collect(mlp, w, steps, dt, t0=0.0, rtol=1e-10, max_per_step=None, seed=8):
     """Run `steps` HEVI steps of workload w; after each, turn both implicit
-    solves into (features, targets).  Returns FP16 features and FP32 targets
-    (device tensors)."""
+    solves into (features, targets).  Returns FP16 features, FP32 targets
+    (device tensors) and the implicit coefficient per dt of the solves."""
     import torch
     ctx = hevi_context(w)
     feats, tgts = [], []
     ncol = ctx.nx * ctx.ny
     rng = np.random.default_rng(seed)
+    a_dt = None
     for s in range(steps):
         ctx.nh_hevi_step(t0 + s * dt, dt, rtol=rtol, max_restarts=30)
         a_dt, solves = ctx.nh_hevi_last_solves()
@@ -50,6 +51,34 @@ def collect(mlp, w, steps, dt, t0=0.0, rtol=1e-10, max_per_step=None, seed=8):
                 f, t = f[idx], t[idx]
             feats.append(f)
             tgts.append(t)
+    torch.cuda.synchronize()
+    ctx.close()
+    return torch.cat(feats), torch.cat(tgts), a_dt
+
+
+def collect_random(mlp, w, batches, alpha, seed=11, rtol=1e-12):
+    """Solves of seeded random column right-hand sides on the column grid of
+    workload w (the library's own batched GMRES, to rtol), turned into
+    (features, targets): they span every direction of the column space,
+    which the few structures of one simulation do not."""
+    import torch
+    ctx = nhsem.Context(w.mesh, w.phys)
+    x, y, z = ctx.nh_lattice_coords()
+    rho0, th0 = W.reference_profiles(w, z)
+    ctx.nh_set_reference(rho0, th0)
+    ctx.nh_hevi_attach()
+    # magnitudes of the random fields: reference density, a nominal sound
+    # speed, reference potential temperature
+    D = np.stack([rho0, np.full_like(rho0, 340.0), th0])
+    ncol = ctx.nx * ctx.ny
+    feats, tgts = [], []
+    for k in range(batches):
+        q = W.random_column_rhs(z, D, ncol, seed + k).reshape(5, -1)
+        b = torch.from_numpy(np.ascontiguousarray(q)).cuda()
+        xs, st = ctx.nh_column_solve(alpha, b, rtol=rtol, max_restarts=60)
+        f, _, t = mlp.nh_mlp_samples(ctx, alpha, b, xs)
+        feats.append(f)
+        tgts.append(t)
     torch.cuda.synchronize()
     ctx.close()
     return torch.cat(feats), torch.cat(tgts)
@@ -92,25 +121,34 @@ def initial_loss(feats, tgts):
     return float((tgts.double() ** 2).mean().item())
 
 
-def fit(mlp, w_eval, dt, warm, sources, epochs, batch=1024, lr=1e-3, max_per_step=None):
+def fit(mlp, w_eval, dt, warm, sources, epochs, batch=1024, lr=1e-3, max_per_step=None, random_grid=None,
+        random_batches=0):
     """Training set: the solves of `sources` (list of (workload, steps, dt))
-    and of the first `warm` steps of w_eval, all generated by the method
-    itself with the default guess; then train.  Returns a summary dict."""
+    and of the first `warm` (>= 1) steps of w_eval, all generated by the
+    method itself with the default guess, plus `random_batches` batches of
+    random column solves on the column grid of `random_grid` (a workload with
+    w_eval's vertical grid; default w_eval); then train.  Returns a summary
+    dict."""
     import torch
     t0 = time.perf_counter()
     F, T = [], []
     for (ws, steps, dts) in sources:
-        f, t = collect(mlp, ws, steps=steps, dt=dts, max_per_step=max_per_step)
+        f, t, _ = collect(mlp, ws, steps=steps, dt=dts, max_per_step=max_per_step)
         F.append(f); T.append(t)
-    if warm > 0:
-        f, t = collect(mlp, w_eval, steps=warm, dt=dt, max_per_step=max_per_step)
+    f, t, a_dt = collect(mlp, w_eval, steps=max(warm, 1), dt=dt, max_per_step=max_per_step)
+    F.append(f); T.append(t)
+    n_sim = sum(int(x.shape[0]) for x in F)
+    if random_batches > 0:
+        f, t = collect_random(mlp, random_grid or w_eval, random_batches, a_dt * dt)
         F.append(f); T.append(t)
     feats, tgts = torch.cat(F), torch.cat(T)
+    del F, T
     t_collect = time.perf_counter() - t0
     l0 = initial_loss(feats, tgts)
     hist, rate = train(mlp, feats, tgts, epochs=epochs, batch=batch, lr=lr)
-    return {"samples": int(feats.shape[0]), "loss_untrained": l0, "loss_last": hist[-1],
-            "samples_per_s": rate, "collect_s": t_collect, "epochs": epochs, "batch": batch}
+    return {"samples": int(feats.shape[0]), "samples_from_runs": n_sim, "loss_untrained": l0,
+            "loss_last": hist[-1], "samples_per_s": rate, "collect_s": t_collect, "epochs": epochs,
+            "batch": batch}
 
 
 def compare(mlp, w, warm, held, dt, rtol=1e-10):

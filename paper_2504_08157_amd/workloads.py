@@ -393,3 +393,31 @@ def heating(w: Workload, x, y, z, nsnap=11):
         return None
     sched = burst_schedule(T=w.heating_T, seed=w.heating_seed)
     return heating_snapshots(x, y, z, w.heating_T, sched, nsnap)
+
+
+def random_column_rhs(z, D, ncol, seed, modes=24):
+    """Seeded right-hand sides for column solves, [5][n_z][ncol]: for each of
+    (rho', w, theta') a random smooth profile (sum of sin(m pi zh / 2 + phase)
+    with amplitudes ~ m^-p, p uniform in [0.5, 2.5]) plus white noise of
+    log-uniform relative size, the field magnitude log-uniform over three
+    decades, times the level factors D [3][n_z] (the reference density,
+    sound speed and potential temperature); u = v = 0 and w = 0 on the bottom
+    and top levels."""
+    rng = np.random.default_rng(seed)
+    z = np.asarray(z, dtype=np.float64)
+    nz = z.size
+    zh = (z - z[0]) / (z[-1] - z[0])
+    q = np.zeros((5, nz, ncol))
+    for f, fld in enumerate((0, 3, 4)):
+        amp = 10.0 ** rng.uniform(-3.0, 0.0, size=ncol)
+        decay = rng.uniform(0.5, 2.5, size=ncol)
+        prof = np.zeros((nz, ncol))
+        for m in range(1, modes + 1):
+            a = rng.normal(size=ncol) * m ** (-decay)
+            ph = rng.uniform(0.0, 2.0 * np.pi, size=ncol)
+            prof += a * np.sin(m * np.pi * zh[:, None] / 2.0 + ph)
+        prof += rng.normal(size=(nz, ncol)) * 10.0 ** rng.uniform(-3.0, 0.0, size=ncol)
+        q[fld] = prof * amp * np.asarray(D[f])[:, None]
+    q[3, 0] = 0.0
+    q[3, -1] = 0.0
+    return q

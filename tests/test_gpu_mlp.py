@@ -24,7 +24,7 @@ def _mlp_with_random_params(seed=3, B=128):
     x = rng.normal(size=(B, MO.IN)).astype(np.float16)
     # oracle uses the FP16 copies of the weights and FP32 biases
     parts = MO.unflatten(w.astype(np.float64))
-    for i in (0, 2, 4):
+    for i in (0, 2, 4, 6):   # W1, W2, W3 and the bypass S are used in FP16
         parts[i] = parts[i].astype(np.float16).astype(np.float64)
     wo = MO.flatten(parts)
     return m, torch, w, wo, x
@@ -119,18 +119,18 @@ def test_untrained_guess_equals_default(oracle_mod):
 
 
 def test_learned_guess_reduces_iterations():
-    """Train on solves the method generates (a small TC mesh, and the first
-    steps of the evaluation mesh), evaluate on the held-out steps that
-    follow: fewer Arnoldi steps per solve, states equal to the solver
-    tolerance."""
+    """Train on solves the method generates (a small TC mesh, the first steps
+    of the evaluation mesh, random column right-hand sides on its grid),
+    evaluate on the held-out steps that follow: fewer Arnoldi steps per
+    solve, states equal to the solver tolerance."""
     from paper_2504_08157_amd import learned_guess as LG
     from paper_2504_08157_amd import nhsem
     mlp = nhsem.ColumnMLP(max_batch=1024, seed=7)
     wtr = W.cfg_hevi(); wtr.mesh = W._tc_mesh(16, 16, 6)
     wev = W.cfg_hevi(); wev.mesh = W._tc_mesh(12, 12, 16)
-    tr = LG.fit(mlp, wev, 2.0, 3, [(wtr, 1, 2.0)], epochs=40, batch=512, lr=1e-3)
+    tr = LG.fit(mlp, wev, 2.0, 3, [(wtr, 1, 2.0)], epochs=40, batch=512, lr=1e-3, random_batches=40)
     print("training", tr)
-    assert tr["loss_last"] < 0.05 * tr["loss_untrained"], tr
+    assert tr["loss_last"] < 0.01 * tr["loss_untrained"], tr
     res = LG.compare(mlp, wev, warm=3, held=2, dt=2.0)
     print(res)
     assert res["mlp"]["iters_per_solve"] < res["default"]["iters_per_solve"], res
