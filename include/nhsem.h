@@ -100,11 +100,13 @@ nh_status nh_set_stream(nh_ctx *ctx, void *hip_stream);
 /* Switch element arithmetic between NH_FP64 and NH_FP32_MIXED. */
 nh_status nh_set_precision(nh_ctx *ctx, int32_t precision);
 
-/* Workgroup tile of the stage kernel: variant 0 (default) covers about
-   16 x 16 lattice columns per workgroup (one workgroup per CU), variant 1 half
-   of that in y (two workgroups per CU).  Both compute every node with the
-   same arithmetic in the same order, so results are bitwise identical.
-   Chosen by the caller's tuner from measured times.  NH_EINVAL otherwise. */
+/* Workgroup tile of the stage kernel (columns per workgroup from
+   nh_tile_shape): variant 0 (default) rows of ~32 lattice columns, a few
+   element rows deep; variant 1 a squarer ~16 x 16 tile; variant 2 one element
+   row deep, so that two FP64 workgroups share a CU.  All variants compute
+   every node with the same arithmetic in the same order, so results are
+   bitwise identical.  Chosen by the caller's tuner from measured times.
+   NH_EINVAL for any other value. */
 nh_status nh_set_tile(nh_ctx *ctx, int32_t variant);
 
 /* Columns per tile (tx x ty) of a variant for order N (no context needed). */

@@ -79,6 +79,10 @@ struct StageShape {
     static constexpr int NSP = NCOL + (TX + TY) * N1;   // staged nodes per plane
     static constexpr int NC = 2 * N + 1;
     static_assert(NT >= NCOL, "bottom-level threads must own whole columns");
+    // Workgroups of at most 512 threads are meant to run two per CU (one
+    // stages its planes while the other computes): ask for the register
+    // budget of that occupancy.
+    static constexpr int WPE = NT <= 512 ? (2 * NT / 64 + 3) / 4 : 1;
 };
 
 // One RK stage (or a bare RHS) over the whole lattice.
@@ -395,7 +399,8 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
 }
 
 template <int N, int AX, int AY, typename T>
-__global__ void __launch_bounds__((StageShape<N, AX, AY>::NT)) stage_kernel(const StageParams p)
+__global__ void __launch_bounds__((StageShape<N, AX, AY>::NT))
+__attribute__((amdgpu_waves_per_eu(StageShape<N, AX, AY>::WPE))) stage_kernel(const StageParams p)
 {
     stage_body<N, AX, AY, T>(p, xcd_tile(blockIdx.x, gridDim.x));
 }
@@ -405,6 +410,7 @@ __global__ void __launch_bounds__((StageShape<N, AX, AY>::NT)) stage_kernel(cons
 // parameters from a device descriptor table.
 template <int N, int AX, int AY, typename T>
 __global__ void __launch_bounds__((StageShape<N, AX, AY>::NT))
+__attribute__((amdgpu_waves_per_eu(StageShape<N, AX, AY>::WPE)))
 stage_kernel_batched(const StageParams *__restrict__ P, const int2 *__restrict__ work)
 {
     const int2 it = work[blockIdx.x];
@@ -414,21 +420,23 @@ stage_kernel_batched(const StageParams *__restrict__ P, const int2 *__restrict__
 // Tile shapes per order (AX x AY elements).  Variant 0 uses rows of 32 (or
 // 30) lattice columns so that each half-wave's stencil reads cover one
 // contiguous 256-byte LDS row (bank-conflict free); variant 1 is a squarer
-// ~16 x 16 tile with a smaller halo.
-#define NH_TILE_CASES(X) \
-    X(2, 16, 4, 8, 8)    \
-    X(3, 10, 3, 5, 5)    \
-    X(4, 8, 2, 4, 4)     \
-    X(5, 6, 1, 3, 2)     \
-    X(6, 4, 1, 2, 2)
+// ~16 x 16 tile with a smaller halo; variant 2 is one element row deep, so
+// that (in FP64) two workgroups share a CU and one stages while the other
+// computes, at the price of a larger halo share.
+#define NH_TILE_CASES(X)      \
+    X(2, 16, 4, 8, 8, 16, 2)  \
+    X(3, 10, 3, 5, 5, 9, 1)   \
+    X(4, 8, 2, 4, 4, 7, 1)    \
+    X(5, 6, 1, 3, 2, 3, 1)    \
+    X(6, 4, 1, 2, 2, 1, 1)
 
 void stage_tile(int N, int variant, int *tx, int *ty)
 {
     switch (N) {
-#define NH_TILE(NN, AX0, AY0, AX1, AY1)                 \
-    case NN:                                            \
-        *tx = (variant ? AX1 : AX0) * NN;               \
-        *ty = (variant ? AY1 : AY0) * NN;               \
+#define NH_TILE(NN, AX0, AY0, AX1, AY1, AX2, AY2)                                  \
+    case NN:                                                                   \
+        *tx = (variant == 2 ? AX2 : variant ? AX1 : AX0) * NN;                 \
+        *ty = (variant == 2 ? AY2 : variant ? AY1 : AY0) * NN;                 \
         return;
         NH_TILE_CASES(NH_TILE)
 #undef NH_TILE
@@ -460,10 +468,11 @@ hipError_t launch_stage_batched(int N, int precision, int variant, const StagePa
                                 int nitems, hipStream_t s)
 {
     switch (N) {
-#define NH_LAUNCHB(NN, AX0, AY0, AX1, AY1)                                           \
-    case NN:                                                                         \
-        if (variant) launch_batched_one<NN, AX1, AY1>(precision, P, work, nitems, s); \
-        else launch_batched_one<NN, AX0, AY0>(precision, P, work, nitems, s);         \
+#define NH_LAUNCHB(NN, AX0, AY0, AX1, AY1, AX2, AY2)                                      \
+    case NN:                                                                             \
+        if (variant == 2) launch_batched_one<NN, AX2, AY2>(precision, P, work, nitems, s); \
+        else if (variant) launch_batched_one<NN, AX1, AY1>(precision, P, work, nitems, s); \
+        else launch_batched_one<NN, AX0, AY0>(precision, P, work, nitems, s);             \
         break;
         NH_TILE_CASES(NH_LAUNCHB)
 #undef NH_LAUNCHB
@@ -476,9 +485,10 @@ hipError_t launch_stage_batched(int N, int precision, int variant, const StagePa
 hipError_t launch_stage(int N, int precision, int variant, const StageParams &p, hipStream_t s)
 {
     switch (N) {
-#define NH_LAUNCH(NN, AX0, AY0, AX1, AY1)                              \
+#define NH_LAUNCH(NN, AX0, AY0, AX1, AY1, AX2, AY2)                    \
     case NN:                                                           \
-        if (variant) launch_one<NN, AX1, AY1>(precision, p, s);        \
+        if (variant == 2) launch_one<NN, AX2, AY2>(precision, p, s);   \
+        else if (variant) launch_one<NN, AX1, AY1>(precision, p, s);   \
         else launch_one<NN, AX0, AY0>(precision, p, s);                \
         break;
         NH_TILE_CASES(NH_LAUNCH)

@@ -188,19 +188,20 @@ def test_fp32_mixed_rhs_close(oracle_mod):
     assert (err <= 1e-4).all(), err
 
 
-@pytest.mark.parametrize("N", [3, 4, 5])
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 6])
 def test_tile_variants_bitwise_equal(oracle_mod, N):
     from paper_2504_08157_amd import nhsem
     ph = W.Physics(f=1e-4, sponge_z0=500.0, sponge_tau=0.01)
     ctx, orc, g, o, prof, torch = _pair(oracle_mod, _mesh((7, 5, 3), N, (True, False)), ph)
     q = torch.from_numpy(W.smooth_random_state(*g, *prof(g[2]), seed=4, walls=(False, True))).cuda()
     outs = []
-    for v in (0, 1):
+    for v in (0, 1, 2):
         ctx.nh_set_tile(v)
         outs.append(ctx.nh_rhs(0.0, q).cpu().numpy())
     np.testing.assert_array_equal(outs[0], outs[1])
+    np.testing.assert_array_equal(outs[0], outs[2])
     with pytest.raises(nhsem.NHError):
-        ctx.nh_set_tile(2)
+        ctx.nh_set_tile(3)
 
 
 def test_full_size_sampled_rhs_parity(oracle_mod):
@@ -240,7 +241,7 @@ def test_full_size_sampled_rhs_parity(oracle_mod):
 
     qr = W.smooth_random_state(*o, *prof(o[2]), seed=8, walls=(False, False))
     ref = orc.rhs_sample(t, qr, nodes)
-    for v in (0, 1):
+    for v in (0, 1, 2):
         err = _rel(gpu(qr, v), ref)
         print("random, tile", v, err)
         assert (err <= TOL64).all(), (v, err)
@@ -260,7 +261,7 @@ def test_full_size_sampled_rhs_parity(oracle_mod):
     rp = qv[0].reshape(-1)[nodes]
     inner = (iz > 0) & (iz < nz - 1)
     scale[3] = max(scale[3], np.linalg.norm(w.phys.g * rp[inner] / (rho0[inner] + rp[inner])))
-    for v in (0, 1):
+    for v in (0, 1, 2):
         err = np.linalg.norm(gpu(qv, v) - ref, axis=1) / scale
         print("vortex, tile", v, err, "scales", scale)
         assert (err <= TOL64).all(), (v, err)
