@@ -257,10 +257,19 @@ def test_full_size_sampled_rhs_parity(oracle_mod):
         qs[3 - comp] = 0.0
         scale = np.maximum(scale, np.linalg.norm(orc.rhs_sample(t, qs, nodes), axis=1))
         del qs
-    rho0 = prof(o[2])[0][iz]
+    rho0, th0 = prof(o[2])
     rp = qv[0].reshape(-1)[nodes]
     inner = (iz > 0) & (iz < nz - 1)
-    scale[3] = max(scale[3], np.linalg.norm(w.phys.g * rp[inner] / (rho0[inner] + rp[inner])))
+    scale[3] = max(scale[3], np.linalg.norm(w.phys.g * rp[inner] / (rho0[iz][inner] + rp[inner])))
+    # The oracle advects total theta = theta0 + theta' (its literal reading):
+    # its horizontal stencil sums terms of size theta0 (2/h) |D| u, so its own
+    # rounding is a few eps times that, ~1e-12 of the small u.grad(theta') of
+    # the vortex; the theta' error is allowed 1e-15 (~5 eps) of the summands.
+    Dm = np.asarray(oracle_mod.lgl(w.mesh.order)[2]).reshape(w.mesh.order + 1, -1)
+    hx = (w.mesh.xe[-1] - w.mesh.xe[0]) / w.mesh.nel[0]
+    wind = np.abs(qv[1].reshape(-1)[nodes]) + np.abs(qv[2].reshape(-1)[nodes])
+    summands = th0[iz] * (2.0 / hx) * np.abs(Dm).sum(axis=1).max() * wind
+    scale[4] = max(scale[4], 1e-3 * np.linalg.norm(summands))
     for v in (0, 1, 2):
         err = np.linalg.norm(gpu(qv, v) - ref, axis=1) / scale
         print("vortex, tile", v, err, "scales", scale)
