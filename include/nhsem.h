@@ -102,8 +102,7 @@ nh_status nh_set_precision(nh_ctx *ctx, int32_t precision);
 
 /* Workgroup tile of the stage kernel (columns per workgroup from
    nh_tile_shape): variant 0 (default) rows of ~32 lattice columns, a few
-   element rows deep; variant 1 a squarer ~16 x 16 tile; variant 2 one element
-   row deep, so that two FP64 workgroups share a CU.  All variants compute
+   element rows deep; variant 1 a squarer ~16 x 16 tile.  Both variants compute
    every node with the same arithmetic in the same order, so results are
    bitwise identical.  Chosen by the caller's tuner from measured times.
    NH_EINVAL for any other value. */

@@ -136,6 +136,6 @@ hipError_t launch_mass(const GeomParams &g, double *M, hipStream_t s);
 hipError_t launch_diag(const GeomParams &g, const double *q, double *partials, double *out8,
                        hipStream_t s);
 void stage_tile(int N, int variant, int *tx, int *ty);
-constexpr int kTileVariants = 3;
+constexpr int kTileVariants = 2;
 
 }  // namespace nh

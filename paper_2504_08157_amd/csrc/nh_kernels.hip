@@ -79,10 +79,6 @@ struct StageShape {
     static constexpr int NSP = NCOL + (TX + TY) * N1;   // staged nodes per plane
     static constexpr int NC = 2 * N + 1;
     static_assert(NT >= NCOL, "bottom-level threads must own whole columns");
-    // Workgroups of at most 512 threads are meant to run two per CU (one
-    // stages its planes while the other computes): ask for the register
-    // budget of that occupancy.
-    static constexpr int WPE = NT <= 512 ? (2 * NT / 64 + 3) / 4 : 1;
 };
 
 // One RK stage (or a bare RHS) over the whole lattice.
@@ -113,6 +109,7 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
     __shared__ T cy[TY * NC];
     __shared__ T sD[N1 * N1];
     __shared__ double sE[kEosTerms];
+    __shared__ T cbuf[2 * 6 * NCOL];
 
     const int tid = threadIdx.x;
     const int bx = tile % p.ntx, by = tile / p.ntx;
@@ -141,8 +138,16 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
     for (int i = tid; i < N1 * 6 * PS + N * PX; i += NT) plbuf[i] = T(0);
     __syncthreads();
 
-    // Stage node s (0 <= s < NSP) of level k into plane slot k mod (N+1).
-    auto stage = [&](int k, int s) {
+    // Staging of node s (0 <= s < NSP) of level k into plane slot k mod (N+1),
+    // in two halves: `fetch` issues the global loads, `put` evaluates the EOS
+    // and writes the slot, so that a thread can have the loads of two staged
+    // nodes in flight at once.
+    struct Staged {
+        double v[5];
+        int idx, slot, k;
+        bool ok;
+    };
+    auto fetch = [&](int k, int s, Staged &st) {
         int px, py;
         if (s < NCOL) {
             px = N + s % TX;
@@ -179,26 +184,44 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
                 ok = false;
             }
         }
-        double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0, v4 = 0.0, pp = 0.0;
+        st.ok = ok;
+        st.k = k;
+        st.slot = k % N1;
+        st.idx = py * PX + px;
+#pragma unroll
+        for (int f = 0; f < 5; ++f) st.v[f] = 0.0;
         if (ok) {
-            const double *L = p.lev + (long)k * kLevW;
             const uint32_t o = ((uint32_t)xg + nx * (uint32_t)yg) * 8u + plane_bytes * (uint32_t)k;
             const char *b = (const char *)p.qs + o;
-            v0 = *(const double *)(b);
-            v1 = *(const double *)(b + field_bytes);
-            v2 = *(const double *)(b + 2 * field_bytes);
-            v3 = *(const double *)(b + 3 * field_bytes);
-            v4 = *(const double *)(b + 4 * field_bytes);
-            pp = pert_pressure(v0, v4, L[7], L[8], L[2], p.gamma, sE);
+#pragma unroll
+            for (int f = 0; f < 5; ++f) st.v[f] = *(const double *)(b + f * field_bytes);
         }
-        T(*P)[PS] = pl[k % N1];
-        const int idx = py * PX + px;
-        P[0][idx] = T(pp);
-        P[1][idx] = T(v1);
-        P[2][idx] = T(v2);
-        P[3][idx] = T(v3);
-        P[4][idx] = T(v4);
-        P[5][idx] = T(v0);
+    };
+    auto put = [&](const Staged &st) {
+        double pp = 0.0;
+        if (st.ok) {
+            const double *L = p.lev + (long)st.k * kLevW;
+            pp = pert_pressure(st.v[0], st.v[4], L[7], L[8], L[2], p.gamma, sE);
+        }
+        T(*P)[PS] = pl[st.slot];
+        P[0][st.idx] = T(pp);
+        P[1][st.idx] = T(st.v[1]);
+        P[2][st.idx] = T(st.v[2]);
+        P[3][st.idx] = T(st.v[3]);
+        P[4][st.idx] = T(st.v[4]);
+        P[5][st.idx] = T(st.v[0]);
+    };
+    // stage the items [first, first + count) of the level-major list
+    // (level kbase + i / NSP, node i % NSP), two per thread per pass
+    auto stage_range = [&](int kbase, int count) {
+        for (int i = tid; i < count; i += 2 * NT) {
+            Staged a, b;
+            fetch(kbase + i / NSP, i % NSP, a);
+            const bool two = i + NT < count;
+            if (two) fetch(kbase + (i + NT) / NSP, (i + NT) % NSP, b);
+            put(a);
+            if (two) put(b);
+        }
     };
 
     // x/y part of the tendency at (tx, ty) of plane slot `sl` (reference
@@ -340,15 +363,35 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
         }
     };
 
-    T carry[6];
+    // z derivative of one field at the top level (r = N) of element ez,
+    // column (tx, ty), scaled by the element metric
+    auto ztop = [&](int ez, int f, int tx, int ty, T h2) {
+        const int jo = (N + ty) * PX + N + tx;
+        T d = T(0);
 #pragma unroll
-    for (int f = 0; f < 6; ++f) carry[f] = T(0);
+        for (int m = 0; m < N1; ++m) {
+            const T(*P)[PS] = pl[(ez * N + m) % N1];
+            const T c = sD[N * N1 + m];
+            const T v = (f == 5) ? (T(p.lev[(long)(ez * N + m) * kLevW]) + P[5][jo]) * P[3][jo] : P[f][jo];
+            d += c * v;
+        }
+        return d * h2;
+    };
 
-    for (int s = tid; s < NSP; s += NT) stage(0, s);
+    // The lower element's weighted contribution to the z derivative at the
+    // level it shares with the element above ("carry", 6 fields per column)
+    // lives in LDS, double buffered by element parity.  Every level group
+    // l >= 1 computes some of the 6 fields (field f by group 1 + f mod (N-1)),
+    // so the group that owns the shared bottom level does no extra
+    // contraction and all waves reach the barrier together.
+    for (int i = tid; i < 2 * 6 * NCOL; i += NT) cbuf[i] = T(0);
+    stage_range(0, NSP);
     for (int ez = 0; ez < p.nelz; ++ez) {
-        for (int i = tid; i < N * NSP; i += NT) stage(ez * N + 1 + i / NSP, i % NSP);
+        stage_range(ez * N + 1, N * NSP);
         __syncthreads();
         const T h2 = T(p.hz2[ez]);
+        const T *cin = cbuf + ((ez + 1) & 1) * 6 * NCOL;
+        T *cout = cbuf + (ez & 1) * 6 * NCOL;
         for (int idx = tid; idx < NOWN; idx += NT) {
             const int l = idx / NCOL, col = idx % NCOL;
             const int tx = col % TX, ty = col / TX;
@@ -362,12 +405,11 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
             if (l == 0) {
                 const T whi = T(p.lev[(long)k * kLevW + 6]);
 #pragma unroll
-                for (int f = 0; f < 6; ++f) dz[f] = whi * dz[f] + carry[f];
-                T dt[6];
-                zderiv(ez, N, tx, ty, h2, dt);
-                const T wlo = T(p.lev[(long)(k + N) * kLevW + 5]);
-#pragma unroll
-                for (int f = 0; f < 6; ++f) carry[f] = wlo * dt[f];
+                for (int f = 0; f < 6; ++f) dz[f] = whi * dz[f] + cin[f * NCOL + col];
+            } else {
+                const T wlo = T(p.lev[(long)(ez * N + N) * kLevW + 5]);
+                for (int f = 0; f < 6; ++f)
+                    if (1 + f % (N - 1) == l) cout[f * NCOL + col] = wlo * ztop(ez, f, tx, ty, h2);
             }
             finish(k, gx, gy, nd, own, XY, dz, inv);
         }
@@ -375,10 +417,13 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
     }
     // top level: only the contribution of the element below
     const int ktop = p.nz - 1;
+    const T *clast = cbuf + ((p.nelz - 1) & 1) * 6 * NCOL;
     for (int col = tid; col < NCOL; col += NT) {
         const int tx = col % TX, ty = col / TX;
         const int gx = x0 + tx, gy = y0 + ty;
-        T own[6], XY[5], inv;
+        T own[6], XY[5], inv, carry[6];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) carry[f] = clast[f * NCOL + col];
         NodeIn nd;
         prefetch(ktop, gx, gy, nd);
         horizontal(ktop % N1, T(p.lev[(long)ktop * kLevW]), tx, ty, own, XY, inv);
@@ -399,8 +444,7 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
 }
 
 template <int N, int AX, int AY, typename T>
-__global__ void __launch_bounds__((StageShape<N, AX, AY>::NT))
-__attribute__((amdgpu_waves_per_eu(StageShape<N, AX, AY>::WPE))) stage_kernel(const StageParams p)
+__global__ void __launch_bounds__((StageShape<N, AX, AY>::NT)) stage_kernel(const StageParams p)
 {
     stage_body<N, AX, AY, T>(p, xcd_tile(blockIdx.x, gridDim.x));
 }
@@ -410,7 +454,6 @@ __attribute__((amdgpu_waves_per_eu(StageShape<N, AX, AY>::WPE))) stage_kernel(co
 // parameters from a device descriptor table.
 template <int N, int AX, int AY, typename T>
 __global__ void __launch_bounds__((StageShape<N, AX, AY>::NT))
-__attribute__((amdgpu_waves_per_eu(StageShape<N, AX, AY>::WPE)))
 stage_kernel_batched(const StageParams *__restrict__ P, const int2 *__restrict__ work)
 {
     const int2 it = work[blockIdx.x];
@@ -420,23 +463,21 @@ stage_kernel_batched(const StageParams *__restrict__ P, const int2 *__restrict__
 // Tile shapes per order (AX x AY elements).  Variant 0 uses rows of 32 (or
 // 30) lattice columns so that each half-wave's stencil reads cover one
 // contiguous 256-byte LDS row (bank-conflict free); variant 1 is a squarer
-// ~16 x 16 tile with a smaller halo; variant 2 is one element row deep, so
-// that (in FP64) two workgroups share a CU and one stages while the other
-// computes, at the price of a larger halo share.
-#define NH_TILE_CASES(X)      \
-    X(2, 16, 4, 8, 8, 16, 2)  \
-    X(3, 10, 3, 5, 5, 9, 1)   \
-    X(4, 8, 2, 4, 4, 7, 1)    \
-    X(5, 6, 1, 3, 2, 3, 1)    \
-    X(6, 4, 1, 2, 2, 1, 1)
+// ~16 x 16 tile with a smaller halo.
+#define NH_TILE_CASES(X) \
+    X(2, 16, 4, 8, 8)    \
+    X(3, 10, 3, 5, 5)    \
+    X(4, 8, 2, 4, 4)     \
+    X(5, 6, 1, 3, 2)     \
+    X(6, 4, 1, 2, 2)
 
 void stage_tile(int N, int variant, int *tx, int *ty)
 {
     switch (N) {
-#define NH_TILE(NN, AX0, AY0, AX1, AY1, AX2, AY2)                                  \
-    case NN:                                                                   \
-        *tx = (variant == 2 ? AX2 : variant ? AX1 : AX0) * NN;                 \
-        *ty = (variant == 2 ? AY2 : variant ? AY1 : AY0) * NN;                 \
+#define NH_TILE(NN, AX0, AY0, AX1, AY1)                 \
+    case NN:                                            \
+        *tx = (variant ? AX1 : AX0) * NN;               \
+        *ty = (variant ? AY1 : AY0) * NN;               \
         return;
         NH_TILE_CASES(NH_TILE)
 #undef NH_TILE
@@ -468,11 +509,10 @@ hipError_t launch_stage_batched(int N, int precision, int variant, const StagePa
                                 int nitems, hipStream_t s)
 {
     switch (N) {
-#define NH_LAUNCHB(NN, AX0, AY0, AX1, AY1, AX2, AY2)                                      \
-    case NN:                                                                             \
-        if (variant == 2) launch_batched_one<NN, AX2, AY2>(precision, P, work, nitems, s); \
-        else if (variant) launch_batched_one<NN, AX1, AY1>(precision, P, work, nitems, s); \
-        else launch_batched_one<NN, AX0, AY0>(precision, P, work, nitems, s);             \
+#define NH_LAUNCHB(NN, AX0, AY0, AX1, AY1)                                           \
+    case NN:                                                                         \
+        if (variant) launch_batched_one<NN, AX1, AY1>(precision, P, work, nitems, s); \
+        else launch_batched_one<NN, AX0, AY0>(precision, P, work, nitems, s);         \
         break;
         NH_TILE_CASES(NH_LAUNCHB)
 #undef NH_LAUNCHB
@@ -485,10 +525,9 @@ hipError_t launch_stage_batched(int N, int precision, int variant, const StagePa
 hipError_t launch_stage(int N, int precision, int variant, const StageParams &p, hipStream_t s)
 {
     switch (N) {
-#define NH_LAUNCH(NN, AX0, AY0, AX1, AY1, AX2, AY2)                    \
+#define NH_LAUNCH(NN, AX0, AY0, AX1, AY1)                              \
     case NN:                                                           \
-        if (variant == 2) launch_one<NN, AX2, AY2>(precision, p, s);   \
-        else if (variant) launch_one<NN, AX1, AY1>(precision, p, s);   \
+        if (variant) launch_one<NN, AX1, AY1>(precision, p, s);        \
         else launch_one<NN, AX0, AY0>(precision, p, s);                \
         break;
         NH_TILE_CASES(NH_LAUNCH)

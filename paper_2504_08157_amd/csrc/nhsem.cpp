@@ -465,7 +465,7 @@ nh_status nh_set_tile(nh_ctx *c, int32_t variant)
 {
     nh_status st = guard(c);
     if (st) return st;
-    if (variant < 0 || variant >= kTileVariants) return fail(c, NH_EINVAL, "tile variant must be 0, 1 or 2");
+    if (variant < 0 || variant >= kTileVariants) return fail(c, NH_EINVAL, "tile variant must be 0 or 1");
     c->tile = variant;
     return NH_OK;
 }

@@ -195,13 +195,12 @@ def test_tile_variants_bitwise_equal(oracle_mod, N):
     ctx, orc, g, o, prof, torch = _pair(oracle_mod, _mesh((7, 5, 3), N, (True, False)), ph)
     q = torch.from_numpy(W.smooth_random_state(*g, *prof(g[2]), seed=4, walls=(False, True))).cuda()
     outs = []
-    for v in (0, 1, 2):
+    for v in (0, 1):
         ctx.nh_set_tile(v)
         outs.append(ctx.nh_rhs(0.0, q).cpu().numpy())
     np.testing.assert_array_equal(outs[0], outs[1])
-    np.testing.assert_array_equal(outs[0], outs[2])
     with pytest.raises(nhsem.NHError):
-        ctx.nh_set_tile(3)
+        ctx.nh_set_tile(2)
 
 
 def test_full_size_sampled_rhs_parity(oracle_mod):
@@ -241,7 +240,7 @@ def test_full_size_sampled_rhs_parity(oracle_mod):
 
     qr = W.smooth_random_state(*o, *prof(o[2]), seed=8, walls=(False, False))
     ref = orc.rhs_sample(t, qr, nodes)
-    for v in (0, 1, 2):
+    for v in (0, 1):
         err = _rel(gpu(qr, v), ref)
         print("random, tile", v, err)
         assert (err <= TOL64).all(), (v, err)
@@ -270,7 +269,7 @@ def test_full_size_sampled_rhs_parity(oracle_mod):
     wind = np.abs(qv[1].reshape(-1)[nodes]) + np.abs(qv[2].reshape(-1)[nodes])
     summands = th0[iz] * (2.0 / hx) * np.abs(Dm).sum(axis=1).max() * wind
     scale[4] = max(scale[4], 1e-3 * np.linalg.norm(summands))
-    for v in (0, 1, 2):
+    for v in (0, 1):
         err = np.linalg.norm(gpu(qv, v) - ref, axis=1) / scale
         print("vortex, tile", v, err, "scales", scale)
         assert (err <= TOL64).all(), (v, err)
