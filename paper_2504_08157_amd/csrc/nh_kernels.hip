@@ -109,7 +109,6 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
     __shared__ T cy[TY * NC];
     __shared__ T sD[N1 * N1];
     __shared__ double sE[kEosTerms];
-    __shared__ T cbuf[2 * 6 * NCOL];
 
     const int tid = threadIdx.x;
     const int bx = tile % p.ntx, by = tile / p.ntx;
@@ -138,16 +137,8 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
     for (int i = tid; i < N1 * 6 * PS + N * PX; i += NT) plbuf[i] = T(0);
     __syncthreads();
 
-    // Staging of node s (0 <= s < NSP) of level k into plane slot k mod (N+1),
-    // in two halves: `fetch` issues the global loads, `put` evaluates the EOS
-    // and writes the slot, so that a thread can have the loads of two staged
-    // nodes in flight at once.
-    struct Staged {
-        double v[5];
-        int idx, slot, k;
-        bool ok;
-    };
-    auto fetch = [&](int k, int s, Staged &st) {
+    // Stage node s (0 <= s < NSP) of level k into plane slot k mod (N+1).
+    auto stage = [&](int k, int s) {
         int px, py;
         if (s < NCOL) {
             px = N + s % TX;
@@ -184,44 +175,26 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
                 ok = false;
             }
         }
-        st.ok = ok;
-        st.k = k;
-        st.slot = k % N1;
-        st.idx = py * PX + px;
-#pragma unroll
-        for (int f = 0; f < 5; ++f) st.v[f] = 0.0;
+        double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0, v4 = 0.0, pp = 0.0;
         if (ok) {
+            const double *L = p.lev + (long)k * kLevW;
             const uint32_t o = ((uint32_t)xg + nx * (uint32_t)yg) * 8u + plane_bytes * (uint32_t)k;
             const char *b = (const char *)p.qs + o;
-#pragma unroll
-            for (int f = 0; f < 5; ++f) st.v[f] = *(const double *)(b + f * field_bytes);
+            v0 = *(const double *)(b);
+            v1 = *(const double *)(b + field_bytes);
+            v2 = *(const double *)(b + 2 * field_bytes);
+            v3 = *(const double *)(b + 3 * field_bytes);
+            v4 = *(const double *)(b + 4 * field_bytes);
+            pp = pert_pressure(v0, v4, L[7], L[8], L[2], p.gamma, sE);
         }
-    };
-    auto put = [&](const Staged &st) {
-        double pp = 0.0;
-        if (st.ok) {
-            const double *L = p.lev + (long)st.k * kLevW;
-            pp = pert_pressure(st.v[0], st.v[4], L[7], L[8], L[2], p.gamma, sE);
-        }
-        T(*P)[PS] = pl[st.slot];
-        P[0][st.idx] = T(pp);
-        P[1][st.idx] = T(st.v[1]);
-        P[2][st.idx] = T(st.v[2]);
-        P[3][st.idx] = T(st.v[3]);
-        P[4][st.idx] = T(st.v[4]);
-        P[5][st.idx] = T(st.v[0]);
-    };
-    // stage the items [first, first + count) of the level-major list
-    // (level kbase + i / NSP, node i % NSP), two per thread per pass
-    auto stage_range = [&](int kbase, int count) {
-        for (int i = tid; i < count; i += 2 * NT) {
-            Staged a, b;
-            fetch(kbase + i / NSP, i % NSP, a);
-            const bool two = i + NT < count;
-            if (two) fetch(kbase + (i + NT) / NSP, (i + NT) % NSP, b);
-            put(a);
-            if (two) put(b);
-        }
+        T(*P)[PS] = pl[k % N1];
+        const int idx = py * PX + px;
+        P[0][idx] = T(pp);
+        P[1][idx] = T(v1);
+        P[2][idx] = T(v2);
+        P[3][idx] = T(v3);
+        P[4][idx] = T(v4);
+        P[5][idx] = T(v0);
     };
 
     // x/y part of the tendency at (tx, ty) of plane slot `sl` (reference
@@ -363,35 +336,15 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
         }
     };
 
-    // z derivative of one field at the top level (r = N) of element ez,
-    // column (tx, ty), scaled by the element metric
-    auto ztop = [&](int ez, int f, int tx, int ty, T h2) {
-        const int jo = (N + ty) * PX + N + tx;
-        T d = T(0);
+    T carry[6];
 #pragma unroll
-        for (int m = 0; m < N1; ++m) {
-            const T(*P)[PS] = pl[(ez * N + m) % N1];
-            const T c = sD[N * N1 + m];
-            const T v = (f == 5) ? (T(p.lev[(long)(ez * N + m) * kLevW]) + P[5][jo]) * P[3][jo] : P[f][jo];
-            d += c * v;
-        }
-        return d * h2;
-    };
+    for (int f = 0; f < 6; ++f) carry[f] = T(0);
 
-    // The lower element's weighted contribution to the z derivative at the
-    // level it shares with the element above ("carry", 6 fields per column)
-    // lives in LDS, double buffered by element parity.  Every level group
-    // l >= 1 computes some of the 6 fields (field f by group 1 + f mod (N-1)),
-    // so the group that owns the shared bottom level does no extra
-    // contraction and all waves reach the barrier together.
-    for (int i = tid; i < 2 * 6 * NCOL; i += NT) cbuf[i] = T(0);
-    stage_range(0, NSP);
+    for (int s = tid; s < NSP; s += NT) stage(0, s);
     for (int ez = 0; ez < p.nelz; ++ez) {
-        stage_range(ez * N + 1, N * NSP);
+        for (int i = tid; i < N * NSP; i += NT) stage(ez * N + 1 + i / NSP, i % NSP);
         __syncthreads();
         const T h2 = T(p.hz2[ez]);
-        const T *cin = cbuf + ((ez + 1) & 1) * 6 * NCOL;
-        T *cout = cbuf + (ez & 1) * 6 * NCOL;
         for (int idx = tid; idx < NOWN; idx += NT) {
             const int l = idx / NCOL, col = idx % NCOL;
             const int tx = col % TX, ty = col / TX;
@@ -405,11 +358,12 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
             if (l == 0) {
                 const T whi = T(p.lev[(long)k * kLevW + 6]);
 #pragma unroll
-                for (int f = 0; f < 6; ++f) dz[f] = whi * dz[f] + cin[f * NCOL + col];
-            } else {
-                const T wlo = T(p.lev[(long)(ez * N + N) * kLevW + 5]);
-                for (int f = 0; f < 6; ++f)
-                    if (1 + f % (N - 1) == l) cout[f * NCOL + col] = wlo * ztop(ez, f, tx, ty, h2);
+                for (int f = 0; f < 6; ++f) dz[f] = whi * dz[f] + carry[f];
+                T dt[6];
+                zderiv(ez, N, tx, ty, h2, dt);
+                const T wlo = T(p.lev[(long)(k + N) * kLevW + 5]);
+#pragma unroll
+                for (int f = 0; f < 6; ++f) carry[f] = wlo * dt[f];
             }
             finish(k, gx, gy, nd, own, XY, dz, inv);
         }
@@ -417,13 +371,10 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
     }
     // top level: only the contribution of the element below
     const int ktop = p.nz - 1;
-    const T *clast = cbuf + ((p.nelz - 1) & 1) * 6 * NCOL;
     for (int col = tid; col < NCOL; col += NT) {
         const int tx = col % TX, ty = col / TX;
         const int gx = x0 + tx, gy = y0 + ty;
-        T own[6], XY[5], inv, carry[6];
-#pragma unroll
-        for (int f = 0; f < 6; ++f) carry[f] = clast[f * NCOL + col];
+        T own[6], XY[5], inv;
         NodeIn nd;
         prefetch(ktop, gx, gy, nd);
         horizontal(ktop % N1, T(p.lev[(long)ktop * kLevW]), tx, ty, own, XY, inv);
