@@ -109,6 +109,8 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
     __shared__ T cy[TY * NC];
     __shared__ T sD[N1 * N1];
     __shared__ double sE[kEosTerms];
+    __shared__ uint32_t smap[NSP];
+    __shared__ uint16_t sidx[NSP];
 
     const int tid = threadIdx.x;
     const int bx = tile % p.ntx, by = tile / p.ntx;
@@ -137,18 +139,20 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
     for (int i = tid; i < N1 * 6 * PS + N * PX; i += NT) plbuf[i] = T(0);
     __syncthreads();
 
-    // Stage node s (0 <= s < NSP) of level k into plane slot k mod (N+1).
-    auto stage = [&](int k, int s) {
+    // Staging map, the same for every level: staged node s (0 <= s < NSP)
+    // -> byte offset of its column in a level (0xffffffff: outside the
+    // lattice, staged as zeros) and its slot index in a plane.
+    for (int sn = tid; sn < NSP; sn += NT) {
         int px, py;
-        if (s < NCOL) {
-            px = N + s % TX;
-            py = N + s / TX;
-        } else if (s < NCOL + TY * N1) {
-            const int s1 = s - NCOL, c = s1 % N1;
+        if (sn < NCOL) {
+            px = N + sn % TX;
+            py = N + sn / TX;
+        } else if (sn < NCOL + TY * N1) {
+            const int s1 = sn - NCOL, c = s1 % N1;
             px = (c < N) ? c : N + TX;
             py = N + s1 / N1;
         } else {
-            const int s2 = s - NCOL - TY * N1, r = s2 / TX;
+            const int s2 = sn - NCOL - TY * N1, r = s2 / TX;
             px = N + s2 % TX;
             py = (r < N) ? r : N + TY;
         }
@@ -175,11 +179,18 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
                 ok = false;
             }
         }
+        smap[sn] = ok ? ((uint32_t)xg + nx * (uint32_t)yg) * 8u : 0xffffffffu;
+        sidx[sn] = (uint16_t)(py * PX + px);
+    }
+    __syncthreads();
+
+    // Stage node s (0 <= s < NSP) of level k into plane slot k mod (N+1).
+    auto stage = [&](int k, int s) {
+        const uint32_t off = smap[s];
         double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0, v4 = 0.0, pp = 0.0;
-        if (ok) {
+        if (off != 0xffffffffu) {
             const double *L = p.lev + (long)k * kLevW;
-            const uint32_t o = ((uint32_t)xg + nx * (uint32_t)yg) * 8u + plane_bytes * (uint32_t)k;
-            const char *b = (const char *)p.qs + o;
+            const char *b = (const char *)p.qs + (off + plane_bytes * (uint32_t)k);
             v0 = *(const double *)(b);
             v1 = *(const double *)(b + field_bytes);
             v2 = *(const double *)(b + 2 * field_bytes);
@@ -188,7 +199,7 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
             pp = pert_pressure(v0, v4, L[7], L[8], L[2], p.gamma, sE);
         }
         T(*P)[PS] = pl[k % N1];
-        const int idx = py * PX + px;
+        const int idx = sidx[s];
         P[0][idx] = T(pp);
         P[1][idx] = T(v1);
         P[2][idx] = T(v2);
