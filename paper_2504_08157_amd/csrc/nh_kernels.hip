@@ -111,6 +111,11 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
     __shared__ double sE[kEosTerms];
     __shared__ uint32_t smap[NSP];
     __shared__ uint16_t sidx[NSP];
+    // Level data of the current element's N+1 levels used by the compute
+    // phase (rho0, dtheta0/dz, tau, w_lo, w_hi): LDS reads, so that no vector
+    // load (and its wait on every outstanding vector-memory operation, the
+    // prefetches included) sits in the middle of the compute phase.
+    __shared__ double slev[N1 * 5];
 
     const int tid = threadIdx.x;
     const int bx = tile % p.ntx, by = tile / p.ntx;
@@ -274,7 +279,7 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
             const T(*P)[PS] = pl[(ez * N + m) % N1];
             const T d = sD[r * N1 + m];
             const T w = P[3][jo];
-            const T r0 = T(p.lev[(long)(ez * N + m) * kLevW]);
+            const T r0 = T(slev[m * 5]);
             dz[0] += d * P[0][jo];
             dz[1] += d * P[1][jo];
             dz[2] += d * P[2][jo];
@@ -309,16 +314,16 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
     };
 
     // Complete the tendency at level k and write a q^n + b q^s + c R.
-    auto finish = [&](int k, int gx0, int gy0, const NodeIn &nd, const T *own, const T *XY, const T *dz,
+    auto finish = [&](int k, int li, int gx0, int gy0, const NodeIn &nd, const T *own, const T *XY, const T *dz,
                       const T inv) {
         NH_FENCE();
         const bool valid = nd.valid;
         const int gx = valid ? gx0 : 0, gy = valid ? gy0 : 0;
-        const double *L = p.lev + (long)k * kLevW;
+        const double *L = slev + li * 5;
         const uint32_t o = nd.o;
         const T u = own[1], v = own[2], w = own[3];
         const T rp = own[5];
-        const T tau = T(L[4]);
+        const T tau = T(L[2]);
         double qs[5];
         if constexpr (kF64) {
             qs[0] = own[5]; qs[1] = own[1]; qs[2] = own[2]; qs[3] = own[3]; qs[4] = own[4];
@@ -332,7 +337,7 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
         R[1] = XY[1] - w * dz[1] + T(p.fcor) * v - tau * u;
         R[2] = XY[2] - w * dz[2] - T(p.fcor) * u - tau * v;
         R[3] = XY[3] - w * dz[3] - dz[0] * inv - T(p.g) * rp * inv - tau * w;
-        R[4] = XY[4] - w * (dz[4] + T(L[3])) - tau * own[4];
+        R[4] = XY[4] - w * (dz[4] + T(L[1])) - tau * own[4];
         double Rd[5];
 #pragma unroll
         for (int f = 0; f < 5; ++f) Rd[f] = double(R[f]);
@@ -354,6 +359,10 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
     for (int s = tid; s < NSP; s += NT) stage(0, s);
     for (int ez = 0; ez < p.nelz; ++ez) {
         for (int i = tid; i < N * NSP; i += NT) stage(ez * N + 1 + i / NSP, i % NSP);
+        for (int i = tid; i < N1 * 5; i += NT) {
+            const int c = i % 5;
+            slev[i] = p.lev[(long)(ez * N + i / 5) * kLevW + (c == 0 ? 0 : c + 2)];
+        }
         __syncthreads();
         const T h2 = T(p.hz2[ez]);
         for (int idx = tid; idx < NOWN; idx += NT) {
@@ -364,19 +373,19 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
             T own[6], XY[5], dz[6], inv;
             NodeIn nd;
             prefetch(k, gx, gy, nd);
-            horizontal(k % N1, T(p.lev[(long)k * kLevW]), tx, ty, own, XY, inv);
+            horizontal(k % N1, T(slev[l * 5]), tx, ty, own, XY, inv);
             zderiv(ez, l, tx, ty, h2, dz);
             if (l == 0) {
-                const T whi = T(p.lev[(long)k * kLevW + 6]);
+                const T whi = T(slev[4]);
 #pragma unroll
                 for (int f = 0; f < 6; ++f) dz[f] = whi * dz[f] + carry[f];
                 T dt[6];
                 zderiv(ez, N, tx, ty, h2, dt);
-                const T wlo = T(p.lev[(long)(k + N) * kLevW + 5]);
+                const T wlo = T(slev[N * 5 + 3]);
 #pragma unroll
                 for (int f = 0; f < 6; ++f) carry[f] = wlo * dt[f];
             }
-            finish(k, gx, gy, nd, own, XY, dz, inv);
+            finish(k, l, gx, gy, nd, own, XY, dz, inv);
         }
         __syncthreads();
     }
@@ -388,8 +397,8 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
         T own[6], XY[5], inv;
         NodeIn nd;
         prefetch(ktop, gx, gy, nd);
-        horizontal(ktop % N1, T(p.lev[(long)ktop * kLevW]), tx, ty, own, XY, inv);
-        finish(ktop, gx, gy, nd, own, XY, carry, inv);
+        horizontal(ktop % N1, T(slev[N * 5]), tx, ty, own, XY, inv);
+        finish(ktop, N, gx, gy, nd, own, XY, carry, inv);
     }
 #undef NH_FENCE
 #undef NH_PIN
