@@ -116,6 +116,10 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
     // load (and its wait on every outstanding vector-memory operation, the
     // prefetches included) sits in the middle of the compute phase.
     __shared__ double slev[N1 * 5];
+    // EOS level data (1/rho0, 1/theta0, p0) of the levels being staged:
+    // slot 0 the bottom level, slots 1..N the element's new levels.
+    __shared__ double stlev[N1 * 3];
+    __shared__ T scarry[6 * NCOL];
 
     const int tid = threadIdx.x;
     const int bx = tile % p.ntx, by = tile / p.ntx;
@@ -187,21 +191,35 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
         smap[sn] = ok ? ((uint32_t)xg + nx * (uint32_t)yg) * 8u : 0xffffffffu;
         sidx[sn] = (uint16_t)(py * PX + px);
     }
+    for (int i = tid; i < N1 * 3; i += NT) {
+        const int c = i % 3;
+        stlev[i] = p.lev[(long)(i / 3) * kLevW + (c == 0 ? 7 : c == 1 ? 8 : 2)];
+    }
     __syncthreads();
 
     // Stage node s (0 <= s < NSP) of level k into plane slot k mod (N+1).
-    auto stage = [&](int k, int s) {
+    // Fill stlev with the EOS data of levels k0 .. k0 + N (the first
+    // element's are filled with the staging map above).
+    auto fill_stlev = [&](int k0) {
+        for (int i = tid; i < N1 * 3; i += NT) {
+            const int c = i % 3;
+            stlev[i] = p.lev[(long)(k0 + i / 3) * kLevW + (c == 0 ? 7 : c == 1 ? 8 : 2)];
+        }
+    };
+
+    // Stage node s of level k (stlev slot j) into plane slot k mod (N+1).
+    auto stage = [&](int k, int j, int s) {
         const uint32_t off = smap[s];
         double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0, v4 = 0.0, pp = 0.0;
         if (off != 0xffffffffu) {
-            const double *L = p.lev + (long)k * kLevW;
+            const double *L = stlev + j * 3;
             const char *b = (const char *)p.qs + (off + plane_bytes * (uint32_t)k);
             v0 = *(const double *)(b);
             v1 = *(const double *)(b + field_bytes);
             v2 = *(const double *)(b + 2 * field_bytes);
             v3 = *(const double *)(b + 3 * field_bytes);
             v4 = *(const double *)(b + 4 * field_bytes);
-            pp = pert_pressure(v0, v4, L[7], L[8], L[2], p.gamma, sE);
+            pp = pert_pressure(v0, v4, L[0], L[1], L[2], p.gamma, sE);
         }
         T(*P)[PS] = pl[k % N1];
         const int idx = sidx[s];
@@ -352,13 +370,17 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
         }
     };
 
-    T carry[6];
+    // The lower element's weighted z-derivative at the shared level, per
+    // column: written and read only by the thread that owns the column's
+    // bottom level (thread col), so it needs no barrier; kept in LDS rather
+    // than in registers, which the compute phase needs.
+    if (tid < NCOL)
 #pragma unroll
-    for (int f = 0; f < 6; ++f) carry[f] = T(0);
+        for (int f = 0; f < 6; ++f) scarry[f * NCOL + tid] = T(0);
 
-    for (int s = tid; s < NSP; s += NT) stage(0, s);
+    for (int s = tid; s < NSP; s += NT) stage(0, 0, s);
     for (int ez = 0; ez < p.nelz; ++ez) {
-        for (int i = tid; i < N * NSP; i += NT) stage(ez * N + 1 + i / NSP, i % NSP);
+        for (int i = tid; i < N * NSP; i += NT) stage(ez * N + 1 + i / NSP, 1 + i / NSP, i % NSP);
         for (int i = tid; i < N1 * 5; i += NT) {
             const int c = i % 5;
             slev[i] = p.lev[(long)(ez * N + i / 5) * kLevW + (c == 0 ? 0 : c + 2)];
@@ -378,15 +400,18 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
             if (l == 0) {
                 const T whi = T(slev[4]);
 #pragma unroll
-                for (int f = 0; f < 6; ++f) dz[f] = whi * dz[f] + carry[f];
+                for (int f = 0; f < 6; ++f) dz[f] = whi * dz[f] + scarry[f * NCOL + col];
                 T dt[6];
                 zderiv(ez, N, tx, ty, h2, dt);
                 const T wlo = T(slev[N * 5 + 3]);
 #pragma unroll
-                for (int f = 0; f < 6; ++f) carry[f] = wlo * dt[f];
+                for (int f = 0; f < 6; ++f) scarry[f * NCOL + col] = wlo * dt[f];
             }
             finish(k, l, gx, gy, nd, own, XY, dz, inv);
         }
+        // EOS level data for the next element's staging (its reads of this
+        // element's data finished before the barrier above)
+        if (ez + 1 < p.nelz) fill_stlev((ez + 1) * N);
         __syncthreads();
     }
     // top level: only the contribution of the element below
@@ -394,7 +419,9 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
     for (int col = tid; col < NCOL; col += NT) {
         const int tx = col % TX, ty = col / TX;
         const int gx = x0 + tx, gy = y0 + ty;
-        T own[6], XY[5], inv;
+        T own[6], XY[5], inv, carry[6];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) carry[f] = scarry[f * NCOL + col];
         NodeIn nd;
         prefetch(ktop, gx, gy, nd);
         horizontal(ktop % N1, T(slev[N * 5]), tx, ty, own, XY, inv);
