@@ -232,7 +232,7 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
     };
 
     // x/y part of the tendency at (tx, ty) of plane slot `sl` (reference
-    // density r0 of that level), plus the own fields (p', u, v, w, theta', rho').
+    // density r0 of that level) and 1/rho there.
     // NH_FENCE: compiler-only memory fence between phases.  It stops the
     // scheduler from front-loading every LDS read of the x, y and z
     // contractions at once (which spills at the 1024-thread register budget).
@@ -241,7 +241,7 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
     // selection cannot defer the FMAs of a tap past the loads of later taps.
 #define NH_PIN(a)                                                                        \
     asm volatile("" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]))
-    auto horizontal = [&](int sl, T r0, int tx, int ty, T *own, T *XY, T &inv) {
+    auto horizontal = [&](int sl, T r0, int tx, int ty, T *XY, T &inv) {
         NH_FENCE();
         const T(*P)[PS] = pl[sl];
         T dx[6], dy[6];
@@ -275,10 +275,8 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
         }
         NH_FENCE();
         const int jo = rowx + N + tx;
-#pragma unroll
-        for (int f = 0; f < 6; ++f) own[f] = P[f][jo];
-        const T u = own[1], v = own[2];
-        inv = T(1) / (r0 + own[5]);
+        const T u = P[1][jo], v = P[2][jo];
+        inv = T(1) / (r0 + P[5][jo]);
         XY[0] = -(dx[5] + dy[5]);
         XY[1] = -(u * dx[1] + v * dy[1]) - dx[0] * inv;
         XY[2] = -(u * dx[2] + v * dy[2]) - dy[0] * inv;
@@ -332,9 +330,18 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
     };
 
     // Complete the tendency at level k and write a q^n + b q^s + c R.
-    auto finish = [&](int k, int li, int gx0, int gy0, const NodeIn &nd, const T *own, const T *XY, const T *dz,
+    auto finish = [&](int k, int li, int gx0, int gy0, const NodeIn &nd, int tx, int ty, const T *XY, const T *dz,
                       const T inv) {
         NH_FENCE();
+        // the node's own fields, re-read from its plane rather than kept in
+        // registers through the contractions
+        T own[6];
+        {
+            const T(*P)[PS] = pl[k % N1];
+            const int jo = (N + ty) * PX + N + tx;
+#pragma unroll
+            for (int f = 1; f < 6; ++f) own[f] = P[f][jo];
+        }
         const bool valid = nd.valid;
         const int gx = valid ? gx0 : 0, gy = valid ? gy0 : 0;
         const double *L = slev + li * 5;
@@ -392,10 +399,10 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
             const int tx = col % TX, ty = col / TX;
             const int gx = x0 + tx, gy = y0 + ty;
             const int k = ez * N + l;
-            T own[6], XY[5], dz[6], inv;
+            T XY[5], dz[6], inv;
             NodeIn nd;
             prefetch(k, gx, gy, nd);
-            horizontal(k % N1, T(slev[l * 5]), tx, ty, own, XY, inv);
+            horizontal(k % N1, T(slev[l * 5]), tx, ty, XY, inv);
             zderiv(ez, l, tx, ty, h2, dz);
             if (l == 0) {
                 const T whi = T(slev[4]);
@@ -407,7 +414,7 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
 #pragma unroll
                 for (int f = 0; f < 6; ++f) scarry[f * NCOL + col] = wlo * dt[f];
             }
-            finish(k, l, gx, gy, nd, own, XY, dz, inv);
+            finish(k, l, gx, gy, nd, tx, ty, XY, dz, inv);
         }
         // EOS level data for the next element's staging (its reads of this
         // element's data finished before the barrier above)
@@ -419,13 +426,13 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
     for (int col = tid; col < NCOL; col += NT) {
         const int tx = col % TX, ty = col / TX;
         const int gx = x0 + tx, gy = y0 + ty;
-        T own[6], XY[5], inv, carry[6];
+        T XY[5], inv, carry[6];
 #pragma unroll
         for (int f = 0; f < 6; ++f) carry[f] = scarry[f * NCOL + col];
         NodeIn nd;
         prefetch(ktop, gx, gy, nd);
-        horizontal(ktop % N1, T(slev[N * 5]), tx, ty, own, XY, inv);
-        finish(ktop, N, gx, gy, nd, own, XY, carry, inv);
+        horizontal(ktop % N1, T(slev[N * 5]), tx, ty, XY, inv);
+        finish(ktop, N, gx, gy, nd, tx, ty, XY, carry, inv);
     }
 #undef NH_FENCE
 #undef NH_PIN
