@@ -91,6 +91,7 @@ hipError_t launch_gmres(const HeviParams &h, const GmresArgs &g, hipStream_t s);
 constexpr int kMlpIn = 400;    // 394 features padded to a multiple of 16
 constexpr int kMlpHid = 256;
 constexpr int kMlpOut = 256;   // 3 fields x 65 canonical levels, padded to a multiple of 64
+constexpr int kMlpSlices = 16;  // batch slices of the weight-gradient GEMMs
 constexpr int kMlpNC = 65;     // canonical levels: LGL nodes of 16 order-4 elements
 constexpr int kMlpNF = 3 * kMlpNC;
 constexpr int kMlpLossBlocks = 256;
@@ -111,6 +112,7 @@ struct MlpNet {
     float *b[3];                   // FP32 biases inside `master`
     float *gw[4], *gb[3];          // gradients inside `grad`
     float *Z1, *Z2, *Y, *dY, *dH, *dZ, *part, *loss;
+    float *part_k;                 // [kMlpSlices][kMlpOut][kMlpIn] split-K partials
     void *H1, *H2;                 // FP16 activations
     void *feat;                    // FP16 [max_batch][kMlpIn]
     double *scale;                 // [max_batch] column scales

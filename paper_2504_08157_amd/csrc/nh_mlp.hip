@@ -210,26 +210,29 @@ __global__ void __launch_bounds__(256) gemm_f16_kernel(const _Float16 *__restric
 }
 
 // ---------------------------------------------------------------- backward (FP32)
-// C[M x N] (=, or += when accum) sum_k A(m, k) B(k, n) with element strides;
-// A, B of type TA, TB (FP16 or FP32), FP32 accumulation, 64 x 64 tiles
-// staged through LDS in K-chunks of 16.
+// C[M x N] = sum_k A(m, k) B(k, n) with element strides; A, B of type TA, TB
+// (FP16 or FP32), FP32 accumulation, 64 x 64 tiles staged through LDS in
+// K-chunks of 16.  Split K: workgroup z sums k in [z kslice, (z+1) kslice)
+// into C + z M N (partials reduced by sum_slices_kernel).
 template <typename TA, typename TB>
 __global__ void __launch_bounds__(256) gemm_f32_kernel(const TA *__restrict__ A, long sam, long sak,
                                                        const TB *__restrict__ B, long sbk, long sbn, int M,
-                                                       int N, int K, float *__restrict__ C)
+                                                       int N, int K, float *__restrict__ C, int kslice)
 {
     __shared__ float As[16][64 + 1];
     __shared__ float Bs[16][64 + 1];
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
     const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const int kb = blockIdx.z * kslice, ke = min(K, kb + kslice);
+    C += (long)blockIdx.z * M * N;
     float acc[4][4] = {};
-    for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int k0 = kb; k0 < ke; k0 += 16) {
         for (int i = threadIdx.x; i < 16 * 64; i += 256) {
             const int kk = i / 64, mm = i % 64;
             const int gm = m0 + mm, gk = k0 + kk;
-            As[kk][mm] = (gm < M && gk < K) ? (float)A[gm * sam + gk * sak] : 0.f;
+            As[kk][mm] = (gm < M && gk < ke) ? (float)A[gm * sam + gk * sak] : 0.f;
             const int gn = n0 + mm;
-            Bs[kk][mm] = (gn < N && gk < K) ? (float)B[gk * sbk + gn * sbn] : 0.f;
+            Bs[kk][mm] = (gn < N && gk < ke) ? (float)B[gk * sbk + gn * sbn] : 0.f;
         }
         __syncthreads();
 #pragma unroll
@@ -253,14 +256,36 @@ __global__ void __launch_bounds__(256) gemm_f32_kernel(const TA *__restrict__ A,
         }
 }
 
-// column sums: out[n] = sum_m X[m][n]
-__global__ void colsum_kernel(const float *__restrict__ X, int M, int N, float *__restrict__ out)
+// out[i] = sum_z P[z][i], z = 0 .. slices-1 in order (deterministic)
+__global__ void sum_slices_kernel(const float *__restrict__ P, int slices, long n, float *__restrict__ out)
 {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        float t = 0.f;
+        for (int z = 0; z < slices; ++z) t += P[z * n + i];
+        out[i] = t;
+    }
+}
+
+// column sums: out[n] = sum_m X[m][n].  Workgroup of 256 threads = 16
+// columns x 16 row phases (coalesced 64-byte row segments); the 16 partial
+// sums of a column are added in a fixed order, so the result is
+// deterministic.
+__global__ void __launch_bounds__(256) colsum_kernel(const float *__restrict__ X, int M, int N,
+                                                     float *__restrict__ out)
+{
+    __shared__ float part[16][17];
+    const int c = threadIdx.x % 16, r = threadIdx.x / 16;
+    const int n = blockIdx.x * 16 + c;
     float s = 0.f;
-    for (int m = 0; m < M; ++m) s += X[(long)m * N + n];
-    out[n] = s;
+    if (n < N)
+        for (int m = r; m < M; m += 16) s += X[(long)m * N + n];
+    part[r][c] = s;
+    __syncthreads();
+    if (r == 0 && n < N) {
+        float t = 0.f;
+        for (int i = 0; i < 16; ++i) t += part[i][c];
+        out[n] = t;
+    }
 }
 
 // dY = 2 (Y - T) / (M N), loss partials per block
@@ -368,34 +393,47 @@ hipError_t mlp_forward(const MlpNet &net, int M, const void *X, hipStream_t s)
     return hipGetLastError();
 }
 
+// Weight gradient G[Mo x No] = sum over the batch (K = M rows) of A^T B,
+// split over the batch so that enough workgroups run (a 256 x 400 gradient
+// is only 28 tiles), then the slices are summed in a fixed order.
+template <typename TB>
+static void weight_grad(const float *A, long lda, const TB *B, long ldb, int Mo, int No, int K, float *G,
+                        float *part, hipStream_t s)
+{
+    int slices = K / 64;
+    if (slices > kMlpSlices) slices = kMlpSlices;
+    if (slices < 1) slices = 1;
+    const int kslice = (K + slices - 1) / slices;
+    hipLaunchKernelGGL((gemm_f32_kernel<float, TB>), dim3((No + 63) / 64, (Mo + 63) / 64, slices), dim3(256), 0, s,
+                       A, 1L, lda, B, ldb, 1L, Mo, No, K, part, kslice);
+    const long n = (long)Mo * No;
+    hipLaunchKernelGGL(sum_slices_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, part, slices, n, G);
+}
+
 hipError_t mlp_backward(const MlpNet &net, int M, const void *X, const float *dY, hipStream_t s)
 {
     const dim3 blk(256);
     const _Float16 *Xh = (const _Float16 *)X, *H1 = (const _Float16 *)net.H1, *H2 = (const _Float16 *)net.H2;
     const _Float16 *W2 = (const _Float16 *)net.wh[1], *W3 = (const _Float16 *)net.wh[2];
     // linear bypass: dS = dY^T X [256 x 400]
-    hipLaunchKernelGGL((gemm_f32_kernel<float, _Float16>), dim3((kMlpIn + 63) / 64, kMlpOut / 64), blk, 0, s, dY,
-                       1L, (long)kMlpOut, Xh, (long)kMlpIn, 1L, kMlpOut, kMlpIn, M, net.gw[3]);
+    weight_grad(dY, (long)kMlpOut, Xh, (long)kMlpIn, kMlpOut, kMlpIn, M, net.gw[3], net.part_k, s);
     // layer 3: dW3 = dY^T H2 [256 x 256], db3 = sum dY, dH2 = dY W3 [M x 256]
-    hipLaunchKernelGGL((gemm_f32_kernel<float, _Float16>), dim3(kMlpHid / 64, kMlpOut / 64), blk, 0, s, dY, 1L,
-                       (long)kMlpOut, H2, (long)kMlpHid, 1L, kMlpOut, kMlpHid, M, net.gw[2]);
-    hipLaunchKernelGGL(colsum_kernel, dim3((kMlpOut + 255) / 256), blk, 0, s, dY, M, kMlpOut, net.gb[2]);
-    hipLaunchKernelGGL((gemm_f32_kernel<float, _Float16>), dim3(kMlpHid / 64, M / 64), blk, 0, s, dY,
-                       (long)kMlpOut, 1L, W3, (long)kMlpHid, 1L, M, kMlpHid, kMlpOut, net.dH);
+    weight_grad(dY, (long)kMlpOut, H2, (long)kMlpHid, kMlpOut, kMlpHid, M, net.gw[2], net.part_k, s);
+    hipLaunchKernelGGL(colsum_kernel, dim3((kMlpOut + 15) / 16), blk, 0, s, dY, M, kMlpOut, net.gb[2]);
+    hipLaunchKernelGGL((gemm_f32_kernel<float, _Float16>), dim3(kMlpHid / 64, M / 64, 1), blk, 0, s, dY,
+                       (long)kMlpOut, 1L, W3, (long)kMlpHid, 1L, M, kMlpHid, kMlpOut, net.dH, kMlpOut);
     hipLaunchKernelGGL(silu_back_kernel, dim3(grid_for((long)M * kMlpHid, 256)), blk, 0, s, net.dH, net.Z2,
                        (long)M * kMlpHid, net.dZ);
     // layer 2
-    hipLaunchKernelGGL((gemm_f32_kernel<float, _Float16>), dim3(kMlpHid / 64, kMlpHid / 64), blk, 0, s, net.dZ,
-                       1L, (long)kMlpHid, H1, (long)kMlpHid, 1L, kMlpHid, kMlpHid, M, net.gw[1]);
-    hipLaunchKernelGGL(colsum_kernel, dim3((kMlpHid + 255) / 256), blk, 0, s, net.dZ, M, kMlpHid, net.gb[1]);
-    hipLaunchKernelGGL((gemm_f32_kernel<float, _Float16>), dim3(kMlpHid / 64, M / 64), blk, 0, s, net.dZ,
-                       (long)kMlpHid, 1L, W2, (long)kMlpHid, 1L, M, kMlpHid, kMlpHid, net.dH);
+    weight_grad(net.dZ, (long)kMlpHid, H1, (long)kMlpHid, kMlpHid, kMlpHid, M, net.gw[1], net.part_k, s);
+    hipLaunchKernelGGL(colsum_kernel, dim3((kMlpHid + 15) / 16), blk, 0, s, net.dZ, M, kMlpHid, net.gb[1]);
+    hipLaunchKernelGGL((gemm_f32_kernel<float, _Float16>), dim3(kMlpHid / 64, M / 64, 1), blk, 0, s, net.dZ,
+                       (long)kMlpHid, 1L, W2, (long)kMlpHid, 1L, M, kMlpHid, kMlpHid, net.dH, kMlpHid);
     hipLaunchKernelGGL(silu_back_kernel, dim3(grid_for((long)M * kMlpHid, 256)), blk, 0, s, net.dH, net.Z1,
                        (long)M * kMlpHid, net.dZ);
     // layer 1: dW1 = dZ1^T X [256 x K0]
-    hipLaunchKernelGGL((gemm_f32_kernel<float, _Float16>), dim3((kMlpIn + 63) / 64, kMlpHid / 64), blk, 0, s,
-                       net.dZ, 1L, (long)kMlpHid, Xh, (long)kMlpIn, 1L, kMlpHid, kMlpIn, M, net.gw[0]);
-    hipLaunchKernelGGL(colsum_kernel, dim3((kMlpHid + 255) / 256), blk, 0, s, net.dZ, M, kMlpHid, net.gb[0]);
+    weight_grad(net.dZ, (long)kMlpHid, Xh, (long)kMlpIn, kMlpHid, kMlpIn, M, net.gw[0], net.part_k, s);
+    hipLaunchKernelGGL(colsum_kernel, dim3((kMlpHid + 15) / 16), blk, 0, s, net.dZ, M, kMlpHid, net.gb[0]);
     return hipGetLastError();
 }
 

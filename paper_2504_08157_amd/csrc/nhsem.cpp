@@ -915,7 +915,7 @@ struct nh_mlp {
 namespace {
 
 struct MlpLayout {
-    size_t params[5], acts[10], feat, scale, total;
+    size_t params[5], acts[11], feat, scale, total;
 };
 
 long mlp_nparam()
@@ -942,6 +942,7 @@ MlpLayout mlp_layout(long B)
     L.acts[7] = take(sizeof(float) * 4);               // loss
     L.acts[8] = take(sizeof(uint16_t) * B * kMlpHid);  // H1
     L.acts[9] = take(sizeof(uint16_t) * B * kMlpHid);  // H2
+    L.acts[10] = take(sizeof(float) * kMlpSlices * kMlpOut * kMlpIn);  // split-K partials
     L.feat = take(sizeof(uint16_t) * B * kMlpIn);
     L.scale = take(sizeof(double) * B);
     L.total = off;
@@ -1082,6 +1083,7 @@ nh_status nh_mlp_create(int64_t max_batch, uint64_t seed, void *dev_ws, size_t b
     n.dY = (float *)(w + L.acts[3]); n.dH = (float *)(w + L.acts[4]); n.dZ = (float *)(w + L.acts[5]);
     n.part = (float *)(w + L.acts[6]); n.loss = (float *)(w + L.acts[7]);
     n.H1 = w + L.acts[8]; n.H2 = w + L.acts[9];
+    n.part_k = (float *)(w + L.acts[10]);
     n.feat = w + L.feat; n.scale = (double *)(w + L.scale);
     m->max_batch = max_batch;
     m->step = 0;
