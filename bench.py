@@ -67,6 +67,7 @@ def parse():
                          "HBM byte counters; precision: FP32-mixed vs FP64 after --err-steps steps")
     ap.add_argument("--members", type=int, default=48)
     ap.add_argument("--mlp-epochs", type=int, default=40, help="training epochs of the column MLP (hevi mode)")
+    ap.add_argument("--gmres-restart", type=int, default=20, help="Krylov vectors per GMRES cycle (hevi mode)")
     return ap.parse_args()
 
 
@@ -112,14 +113,14 @@ def bench_hevi(args):
     from paper_2504_08157_amd import nhsem
     from paper_2504_08157_amd import workloads as W
     w = W.cfg_hevi()
-    mlp = nhsem.ColumnMLP(max_batch=8192, seed=7)
+    mlp = nhsem.ColumnMLP(max_batch=32768, seed=7)
     warm = max(args.warmup, 1)
     wr = W.cfg_hevi()
     wr.mesh = W._tc_mesh(32, 32, w.mesh.nel[2])   # same column grid, 16384 columns per random batch
     tr = LG.fit(mlp, w, w.dt, warm, [(W.cfg_tc_small(), 2, w.dt), (W.cfg_bubble(), 2, 0.5)],
                 epochs=args.mlp_epochs, batch=1024, lr=1e-3, max_per_step=24576, random_grid=wr,
                 random_batches=16)
-    res = LG.compare(mlp, w, warm=warm, held=args.steps, dt=w.dt)
+    res = LG.compare(mlp, w, warm=warm, held=args.steps, dt=w.dt, restart=args.gmres_restart)
     ctx = nhsem.Context(w.mesh, w.phys)
     U = ctx.U
     ctx.close()
@@ -129,7 +130,8 @@ def bench_hevi(args):
         "value": 5 * U * 3 / (m["ms_per_step"] / 1e3), "unit": "DOF-stage updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": warm, "ms_per_step": m["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f16", "data": "synthetic",
-        "config": {"workload": w.name, "mode": "hevi", "dt": w.dt, "gmres": "GMRES(20), rtol 1e-10",
+        "config": {"workload": w.name, "mode": "hevi", "dt": w.dt,
+                   "gmres": f"GMRES({args.gmres_restart}), rtol 1e-10",
                    "columns": res["columns"]},
         "hevi": {"default": d, "mlp": m, "speedup_step": d["ms_per_step"] / m["ms_per_step"],
                  "iteration_ratio": m["iters_per_solve"] / d["iters_per_solve"],

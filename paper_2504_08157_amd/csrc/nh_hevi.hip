@@ -18,8 +18,9 @@
 // GMRES(m), modified Gram-Schmidt, Givens rotations, stopping when the
 // residual estimate satisfies ||b - A x|| <= rtol ||b||.  One wavefront owns
 // one column: the column's 3 n_z unknowns are spread over the 64 lanes
-// (unknown u on lane u mod 64), the Krylov basis lives in LDS, dot products
-// are wave reductions.  A column never waits for another column.
+// (unknown u on lane u mod 64), dot products are wave reductions, and a
+// column never waits for another column.  For m = 10 (and 3 n_z <= 256) the
+// Krylov basis lives in registers; otherwise in LDS.
 #include "nh_internal.h"
 
 #include <math.h>
@@ -251,6 +252,218 @@ __global__ void __launch_bounds__(64) gmres_column_kernel(HeviParams h, GmresArg
     }
 }
 
+// ---------------------------------------------------------------- GMRES, register basis
+// The same restarted GMRES with the Krylov basis in registers: unknown u of
+// the column sits in slot u / 64 of lane u mod 64 (S slots cover 64 S
+// unknowns), and the loops over basis vectors are unrolled so that every
+// basis access is a register.  LDS holds only the level tables, one vector
+// for the lane exchange of L_v and the small Hessenberg data, so many more
+// columns run per CU than with the basis in LDS.
+template <int M, int S>
+__global__ void __launch_bounds__(64) gmres_reg_kernel(HeviParams h, GmresArgs g)
+{
+    extern __shared__ double smem[];
+    const int nz = h.nz, NU = 3 * nz, lane = threadIdx.x;
+    const int NC = 2 * h.N + 1;
+    double *slev = smem;                  // nz x kLevW
+    double *sgz = slev + nz * kLevW;      // nz x NC
+    double *xb = sgz + nz * NC;           // NU: the vector L_v is applied to
+    double *tmp = xb + NU;                // 2 nz: rho0 w and p'_L
+    double *H = tmp + 2 * nz;             // (M+1) x M
+    double *cs = H + (M + 1) * M;         // M
+    double *sn = cs + M;                  // M
+    double *gv = sn + M;                  // M+1
+
+    for (int i = lane; i < nz * kLevW; i += 64) slev[i] = h.lev[i];
+    for (int i = lane; i < nz * NC; i += 64) sgz[i] = h.gz[i];
+    __syncthreads();
+
+    // y = (I - alpha L_v) x on register vectors (slot s: unknown lane + 64 s)
+    auto apply = [&](const double *x, double *y) __attribute__((always_inline)) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int u = lane + 64 * s;
+            if (u < NU) xb[u] = x[s];
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (int k = lane; k < nz; k += 64) {
+            const double *L = slev + k * kLevW;
+            tmp[k] = L[0] * xb[nz + k];
+            tmp[nz + k] = h.gamma * L[2] * (xb[k] * L[7] + xb[2 * nz + k] * L[8]);
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int u = lane + 64 * s;
+            double r = 0.0;
+            if (u < NU) {
+                const int f = u / nz, k = u - f * nz;
+                const double *L = slev + k * kLevW;
+                double lv;
+                if (f == 0) {
+                    const double *G = sgz + k * NC;
+                    double d = 0.0;
+                    for (int o = -h.N; o <= h.N; ++o) {
+                        const int kk = k + o;
+                        if (kk >= 0 && kk < nz) d += G[o + h.N] * tmp[kk];
+                    }
+                    lv = -d;
+                } else if (f == 1) {
+                    if (k == 0 || k == nz - 1) {
+                        lv = 0.0;
+                    } else {
+                        const double *G = sgz + k * NC;
+                        double d = 0.0;
+                        for (int o = -h.N; o <= h.N; ++o) {
+                            const int kk = k + o;
+                            if (kk >= 0 && kk < nz) d += G[o + h.N] * tmp[nz + kk];
+                        }
+                        lv = -d * L[7] - h.g * xb[k] * L[7];
+                    }
+                } else {
+                    lv = -xb[nz + k] * L[3];
+                }
+                r = x[s] - g.alpha * lv;
+            }
+            y[s] = r;
+        }
+        // the exchange vector is rewritten by the next apply
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    };
+    auto dot = [&](const double *a, const double *c) __attribute__((always_inline)) {
+        double d = 0.0;
+#pragma unroll
+        for (int s = 0; s < S; ++s) d += a[s] * c[s];
+        return wave_sum(d);
+    };
+
+    const long nxy = (long)h.nx * h.ny;
+    const long U = nxy * nz;
+    const int fld[3] = {0, 3, 4};
+    for (long col = blockIdx.x; col < nxy; col += gridDim.x) {
+        double bv[S], xs[S], V[M + 1][S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int u = lane + 64 * s;
+            bv[s] = 0.0;
+            xs[s] = 0.0;
+            if (u < NU) {
+                const int f = u / nz, k = u - f * nz;
+                const long I = col + (long)k * nxy;
+                bv[s] = g.b[fld[f] * U + I];
+                xs[s] = g.x0 ? g.x0[f * U + I] : bv[s];
+            }
+        }
+        const double bn = sqrt(dot(bv, bv));
+        const double tol = g.rtol * bn;
+        int iters = 0;
+        bool conv = bn == 0.0;
+        if (conv)
+#pragma unroll
+            for (int s = 0; s < S; ++s) xs[s] = 0.0;
+        for (int rs = 0; rs <= g.max_restarts && !conv; ++rs) {
+            apply(xs, V[0]);
+#pragma unroll
+            for (int s = 0; s < S; ++s) V[0][s] = bv[s] - V[0][s];
+            const double rn = sqrt(dot(V[0], V[0]));
+            if (rn <= tol) { conv = true; break; }
+#pragma unroll
+            for (int s = 0; s < S; ++s) V[0][s] /= rn;
+            if (lane == 0) gv[0] = rn;
+            int jn = 0;
+            double res = rn;
+            bool done = false;
+            // fully unrolled (basis indices are registers): no early exit,
+            // the remaining steps are skipped by a wave-uniform flag
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                if (!done) {
+                    apply(V[j], V[j + 1]);
+#pragma unroll
+                    for (int i = 0; i <= j; ++i) {
+                        const double d = dot(V[j + 1], V[i]);
+#pragma unroll
+                        for (int s = 0; s < S; ++s) V[j + 1][s] -= d * V[i][s];
+                        if (lane == 0) H[i * M + j] = d;
+                    }
+                    const double nn = sqrt(dot(V[j + 1], V[j + 1]));
+                    if (nn > 0.0)
+#pragma unroll
+                        for (int s = 0; s < S; ++s) V[j + 1][s] /= nn;
+                    if (lane == 0) {
+                        H[(j + 1) * M + j] = nn;
+                        for (int i = 0; i < j; ++i) {
+                            const double a = H[i * M + j], bb = H[(i + 1) * M + j];
+                            H[i * M + j] = cs[i] * a + sn[i] * bb;
+                            H[(i + 1) * M + j] = -sn[i] * a + cs[i] * bb;
+                        }
+                        const double a = H[j * M + j], bb = H[(j + 1) * M + j];
+                        const double r = sqrt(a * a + bb * bb);
+                        const double c = r > 0.0 ? a / r : 1.0, sg = r > 0.0 ? bb / r : 0.0;
+                        cs[j] = c;
+                        sn[j] = sg;
+                        H[j * M + j] = r;
+                        H[(j + 1) * M + j] = 0.0;
+                        gv[j + 1] = -sg * gv[j];
+                        gv[j] = c * gv[j];
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    res = fabs(gv[j + 1]);
+                    ++iters;
+                    jn = j + 1;
+                    done = res <= tol || nn == 0.0;
+                }
+            }
+            // back substitution y = H^-1 g (lane 0), x += V y
+            if (lane == 0) {
+                for (int i = jn - 1; i >= 0; --i) {
+                    double sacc = gv[i];
+                    for (int l = i + 1; l < jn; ++l) sacc -= H[i * M + l] * gv[l];
+                    gv[i] = sacc / H[i * M + i];
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                if (i < jn) {
+                    const double yi = gv[i];
+#pragma unroll
+                    for (int s = 0; s < S; ++s) xs[s] += yi * V[i][s];
+                }
+            }
+            if (res <= tol) {
+                // confirm with the true residual
+                double t[S];
+                apply(xs, t);
+#pragma unroll
+                for (int s = 0; s < S; ++s) t[s] = bv[s] - t[s];
+                conv = sqrt(dot(t, t)) <= tol;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int u = lane + 64 * s;
+            if (u < NU) {
+                const int f = u / nz, k = u - f * nz;
+                g.x[fld[f] * U + col + (long)k * nxy] = xs[s];
+            }
+        }
+        for (int k = lane; k < nz; k += 64) {
+            const long I = col + (long)k * nxy;
+            g.x[U + I] = g.b[U + I];
+            g.x[2 * U + I] = g.b[2 * U + I];
+        }
+        if (lane == 0 && g.iters) g.iters[col] = conv ? iters : -iters - 1;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+}
+
 static int grid_for(long n, int block)
 {
     long gsz = (n + block - 1) / block;
@@ -284,6 +497,16 @@ hipError_t launch_axpy_multi(long n, const double *base, int nsrc, const LinComb
 hipError_t launch_gmres(const HeviParams &h, const GmresArgs &g, hipStream_t s)
 {
     const long ncol = (long)h.nx * h.ny;
+    if (g.restart == kGmresRegM && 3 * h.nz <= 64 * kGmresRegSlots) {
+        // register basis: LDS for the level tables, the exchange vector and
+        // the Hessenberg data only
+        const size_t lds = sizeof(double) * ((size_t)h.nz * kLevW + (size_t)h.nz * (2 * h.N + 1) + 3 * h.nz +
+                                             2 * h.nz + (kGmresRegM + 1) * kGmresRegM + 2 * kGmresRegM +
+                                             kGmresRegM + 1);
+        const int grid = (int)(ncol < 32768 ? ncol : 32768);
+        hipLaunchKernelGGL((gmres_reg_kernel<kGmresRegM, kGmresRegSlots>), dim3(grid), dim3(64), lds, s, h, g);
+        return hipGetLastError();
+    }
     const size_t lds = gmres_lds_bytes(h.nz, h.N, g.restart);
     const int grid = (int)(ncol < 8192 ? ncol : 8192);
     hipLaunchKernelGGL(gmres_column_kernel, dim3(grid), dim3(64), lds, s, h, g);

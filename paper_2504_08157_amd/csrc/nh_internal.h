@@ -88,6 +88,8 @@ hipError_t launch_axpy_multi(long n, const double *base, int nsrc, const LinComb
 hipError_t launch_gmres(const HeviParams &h, const GmresArgs &g, hipStream_t s);
 
 // ---- column MLP
+constexpr int kGmresRegM = 10;      // restart length of the register-basis GMRES
+constexpr int kGmresRegSlots = 4;   // unknowns per lane it supports (3 n_z <= 256)
 constexpr int kMlpIn = 400;    // 394 features padded to a multiple of 16
 constexpr int kMlpHid = 256;
 constexpr int kMlpOut = 256;   // 3 fields x 65 canonical levels, padded to a multiple of 64

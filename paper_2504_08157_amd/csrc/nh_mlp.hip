@@ -51,60 +51,76 @@ __device__ __forceinline__ double dim_factor(const MlpColParams &p, int f, int k
     return sqrt(p.gamma * L[2] / L[0]);
 }
 
-// One wavefront per column; lanes stride over lattice levels for the scale
-// and over canonical levels for the resampling.
-__global__ void __launch_bounds__(64) mlp_features_kernel(MlpColParams p, const double *__restrict__ b,
-                                                          const double *__restrict__ lb,
-                                                          const double *__restrict__ x, long col0,
-                                                          long ncol, _Float16 *__restrict__ feat,
-                                                          double *__restrict__ scale, float *__restrict__ tgt)
+// 64 columns per workgroup of 256 threads: lane = column (every load reads
+// 64 consecutive columns of one level, coalesced), the 4 waves split the
+// levels of the scale sum and the canonical levels of the resampling; the
+// features of the 64 columns are assembled in LDS and written out as whole
+// rows.
+__global__ void __launch_bounds__(256) mlp_features_kernel(MlpColParams p, const double *__restrict__ b,
+                                                           const double *__restrict__ lb,
+                                                           const double *__restrict__ x, long col0,
+                                                           long ncol, _Float16 *__restrict__ feat,
+                                                           double *__restrict__ scale, float *__restrict__ tgt)
 {
+    __shared__ _Float16 sf[64][kMlpIn];
+    __shared__ double spart[4][64];
     const long nxy = (long)p.nx * p.ny;
     const long U = nxy * p.nz;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int fld[3] = {0, 3, 4};
     const double H = p.z[p.nz - 1] - p.z[0];
-    for (long r = blockIdx.x; r < ncol; r += gridDim.x) {
-        const long col = col0 + r;
-        double a = 0.0;
-        for (int k = lane; k < p.nz; k += 64) {
-            for (int f = 0; f < 3; ++f) {
-                const double d = 1.0 / dim_factor(p, f, k);
-                const double v = b[fld[f] * U + col + (long)k * nxy] * d;
-                const double l = p.alpha * lb[fld[f] * U + col + (long)k * nxy] * d;
-                a += v * v + l * l;
-            }
+    const long r0 = (long)blockIdx.x * 64;
+    const long r = r0 + lane;
+    const bool ok = r < ncol;
+    const long col = col0 + (ok ? r : 0);
+    // s = RMS over the column of the dimensionless b and alpha L_v b
+    double a = 0.0;
+#pragma unroll 4
+    for (int k = q; k < p.nz; k += 4) {
+        const long I = col + (long)k * nxy;
+        for (int f = 0; f < 3; ++f) {
+            const double d = 1.0 / dim_factor(p, f, k);
+            const double v = b[fld[f] * U + I] * d;
+            const double l = p.alpha * lb[fld[f] * U + I] * d;
+            a += v * v + l * l;
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
-        const double s = sqrt(a / (3.0 * p.nz)) + 1e-300;
-        _Float16 *fr = feat + r * kMlpIn;
-        for (int c = lane; c < kMlpNC; c += 64) {
-            int k0;
-            double t;
-            canon_interp(p.z, p.nz, p.z[0] + H * p.zc[c], &k0, &t);
-            for (int f = 0; f < 3; ++f) {
-                const long I0 = fld[f] * U + col + (long)k0 * nxy, I1 = I0 + nxy;
-                const double d0 = 1.0 / dim_factor(p, f, k0), d1 = 1.0 / dim_factor(p, f, k0 + 1);
-                const double vb = (1.0 - t) * (b[I0] * d0) + t * (b[I1] * d1);
-                const double vl = (1.0 - t) * (p.alpha * lb[I0] * d0) + t * (p.alpha * lb[I1] * d1);
-                fr[f * kMlpNC + c] = (_Float16)(vb / s);
-                fr[kMlpNF + f * kMlpNC + c] = (_Float16)(vl / s);
-                if (tgt) {
-                    const double vx = (1.0 - t) * ((x[I0] - b[I0]) * d0) + t * ((x[I1] - b[I1]) * d1);
-                    tgt[r * kMlpOut + f * kMlpNC + c] = (float)(vx / s);
-                }
-            }
-        }
-        if (lane == 0) fr[2 * kMlpNF] = (_Float16)(log10(s) / 10.0);
-        if (lane == 1) fr[2 * kMlpNF + 1] = (_Float16)(p.alpha / 10.0);
-        if (lane == 2) fr[2 * kMlpNF + 2] = (_Float16)(100.0 * p.alpha * dim_factor(p, 1, 0) / H);
-        if (lane == 3) fr[2 * kMlpNF + 3] = (_Float16)(log10(H) / 5.0);
-        for (int i = 2 * kMlpNF + 4 + lane; i < kMlpIn; i += 64) fr[i] = (_Float16)0.0f;
-        if (tgt)
-            for (int i = kMlpNF + lane; i < kMlpOut; i += 64) tgt[r * kMlpOut + i] = 0.0f;
-        if (lane == 0) scale[r] = s;
     }
+    spart[q][lane] = a;
+    __syncthreads();
+    const double s = sqrt((spart[0][lane] + spart[1][lane] + spart[2][lane] + spart[3][lane]) / (3.0 * p.nz)) + 1e-300;
+    for (int c = q; c < kMlpNC; c += 4) {
+        int k0;
+        double t;
+        canon_interp(p.z, p.nz, p.z[0] + H * p.zc[c], &k0, &t);
+        for (int f = 0; f < 3; ++f) {
+            const long I0 = fld[f] * U + col + (long)k0 * nxy, I1 = I0 + nxy;
+            const double d0 = 1.0 / dim_factor(p, f, k0), d1 = 1.0 / dim_factor(p, f, k0 + 1);
+            const double vb = (1.0 - t) * (b[I0] * d0) + t * (b[I1] * d1);
+            const double vl = (1.0 - t) * (p.alpha * lb[I0] * d0) + t * (p.alpha * lb[I1] * d1);
+            sf[lane][f * kMlpNC + c] = (_Float16)(vb / s);
+            sf[lane][kMlpNF + f * kMlpNC + c] = (_Float16)(vl / s);
+            if (tgt && ok) {
+                const double vx = (1.0 - t) * ((x[I0] - b[I0]) * d0) + t * ((x[I1] - b[I1]) * d1);
+                tgt[r * kMlpOut + f * kMlpNC + c] = (float)(vx / s);
+            }
+        }
+    }
+    if (q == 0) {
+        sf[lane][2 * kMlpNF] = (_Float16)(log10(s) / 10.0);
+        sf[lane][2 * kMlpNF + 1] = (_Float16)(p.alpha / 10.0);
+        sf[lane][2 * kMlpNF + 2] = (_Float16)(100.0 * p.alpha * dim_factor(p, 1, 0) / H);
+        sf[lane][2 * kMlpNF + 3] = (_Float16)(log10(H) / 5.0);
+        for (int i = 2 * kMlpNF + 4; i < kMlpIn; ++i) sf[lane][i] = (_Float16)0.0f;
+        if (ok) scale[r] = s;
+    } else if (tgt && ok) {
+        for (int i = kMlpNF + q - 1; i < kMlpOut; i += 3) tgt[r * kMlpOut + i] = 0.0f;
+    }
+    __syncthreads();
+    // rows of 400 halves = 200 words; threads write consecutive words
+    const long nrow = ncol - r0 < 64 ? ncol - r0 : 64;
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(&sf[0][0]);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(feat + r0 * kMlpIn);
+    for (long i = threadIdx.x; i < nrow * (kMlpIn / 2); i += 256) dst[i] = src[i];
 }
 
 // x0 = b + D s (y resampled from the canonical to the lattice levels), one
@@ -363,8 +379,8 @@ static int grid_for(long n, int block)
 hipError_t launch_mlp_features(const MlpColParams &p, const double *b, const double *lb, const double *x,
                                long col0, long ncol, void *feat, double *scale, float *tgt, hipStream_t s)
 {
-    const int grid = (int)(ncol < 16384 ? ncol : 16384);
-    hipLaunchKernelGGL(mlp_features_kernel, dim3(grid), dim3(64), 0, s, p, b, lb, x, col0, ncol,
+    const int grid = (int)((ncol + 63) / 64);
+    hipLaunchKernelGGL(mlp_features_kernel, dim3(grid), dim3(256), 0, s, p, b, lb, x, col0, ncol,
                        (_Float16 *)feat, scale, tgt);
     return hipGetLastError();
 }

@@ -151,14 +151,14 @@ def fit(mlp, w_eval, dt, warm, sources, epochs, batch=1024, lr=1e-3, max_per_ste
             "batch": batch}
 
 
-def compare(mlp, w, warm, held, dt, rtol=1e-10):
+def compare(mlp, w, warm, held, dt, rtol=1e-10, restart=20):
     """From the state after `warm` default steps, run `held` steps twice --
     default guess and MLP guess -- and report GMRES iterations, step times
     and the difference of the final states."""
     import torch
     ctx = hevi_context(w)
     for s in range(warm):
-        ctx.nh_hevi_step(s * dt, dt, rtol=rtol, max_restarts=30)
+        ctx.nh_hevi_step(s * dt, dt, rtol=rtol, max_restarts=30, restart=restart)
     q0 = ctx.nh_get_state().clone()
     out = {}
     finals = {}
@@ -170,7 +170,7 @@ def compare(mlp, w, warm, held, dt, rtol=1e-10):
         for s in range(held):
             e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
-            st = ctx.nh_hevi_step((warm + s) * dt, dt, rtol=rtol, max_restarts=30, guess=g)
+            st = ctx.nh_hevi_step((warm + s) * dt, dt, rtol=rtol, max_restarts=60, restart=restart, guess=g)
             e1.record()
             torch.cuda.synchronize()
             ms += e0.elapsed_time(e1)

@@ -39,8 +39,10 @@ def test_lv_apply_parity(oracle_mod):
     assert np.all(y[1] == 0) and np.all(y[2] == 0)
 
 
+# restart 10 runs the register-basis kernel, 20 the LDS-basis one
+@pytest.mark.parametrize("restart", [20, 10])
 @pytest.mark.parametrize("alpha", [0.3, 2.0])
-def test_column_gmres_vs_direct(oracle_mod, alpha):
+def test_column_gmres_vs_direct(oracle_mod, alpha, restart):
     ctx, orc, g, o, torch = _pair(oracle_mod)
     Lm = oracle_mod.column_matrix(orc)
     b = _state(o, 5)
@@ -50,7 +52,7 @@ def test_column_gmres_vs_direct(oracle_mod, alpha):
     X = np.linalg.solve(A, B)
     bd = torch.from_numpy(_state(g, 5)).cuda()
     iters = torch.zeros(ctx.nx * ctx.ny, dtype=torch.int32, device="cuda")
-    x, st = ctx.nh_column_solve(alpha, bd, rtol=1e-12, iters=iters)
+    x, st = ctx.nh_column_solve(alpha, bd, restart=restart, max_restarts=30, rtol=1e-12, iters=iters)
     x = x.cpu().numpy()
     for f, blk in ((0, X[:nz]), (3, X[nz:2 * nz]), (4, X[2 * nz:])):
         ref = blk.reshape(x[f].shape)
@@ -59,10 +61,10 @@ def test_column_gmres_vs_direct(oracle_mod, alpha):
     np.testing.assert_array_equal(x[1], bg[1]); np.testing.assert_array_equal(x[2], bg[2])
     it = iters.cpu().numpy()
     assert st.not_converged == 0 and (it > 0).all() and st.iters_total == it.sum()
-    print("alpha", alpha, "iters mean", it.mean(), "max", it.max())
+    print("alpha", alpha, "restart", restart, "iters mean", it.mean(), "max", it.max())
     # starting from the exact solution needs no Arnoldi step
     x0 = torch.from_numpy(np.stack([x[0], x[3], x[4]])).cuda()
-    _, st0 = ctx.nh_column_solve(alpha, bd, x0=x0, rtol=1e-9, iters=iters)
+    _, st0 = ctx.nh_column_solve(alpha, bd, x0=x0, restart=restart, rtol=1e-9, iters=iters)
     assert st0.iters_total == 0
 
 
@@ -77,14 +79,15 @@ def test_gmres_reports_non_convergence(oracle_mod):
     assert e.value.code == nhsem.NH_ENOCONV
 
 
-def test_hevi_step_parity(oracle_mod):
+@pytest.mark.parametrize("restart", [20, 10])
+def test_hevi_step_parity(oracle_mod, restart):
     ctx, orc, g, o, torch = _pair(oracle_mod)
     Lm = oracle_mod.column_matrix(orc)
     q = _state(o, 9, amp=0.3)
     ctx.nh_set_state(torch.from_numpy(_state(g, 9, amp=0.3)).cuda())
     dt = 4.0
     for n in range(2):
-        st = ctx.nh_hevi_step(n * dt, dt, rtol=1e-13, max_restarts=20)
+        st = ctx.nh_hevi_step(n * dt, dt, restart=restart, rtol=1e-13, max_restarts=40)
         q = oracle_mod.ark2_step(orc, Lm, n * dt, dt, q)
         assert st.not_converged == 0 and st.solves == 2
     got = ctx.nh_get_state().cpu().numpy()
