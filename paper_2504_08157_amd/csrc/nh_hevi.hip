@@ -25,6 +25,8 @@
 
 #include <math.h>
 
+#include <utility>
+
 namespace nh {
 
 // ---------------------------------------------------------------- L_v on a state
@@ -253,214 +255,337 @@ __global__ void __launch_bounds__(64) gmres_column_kernel(HeviParams h, GmresArg
 }
 
 // ---------------------------------------------------------------- GMRES, register basis
+// Wave-wide sums through DPP lane moves (no LDS traffic): butterflies inside
+// each 16-lane row, then the row sums are chained by the row broadcasts; the
+// total ends in lane 63 and is read back as a wave-uniform value.  The order
+// of the additions is fixed, so the sum is deterministic.
+// Lane move with every source lane valid (all rows written).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Lane move into the rows of ROWS only; the other rows read zero.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move_rows(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWS, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+__device__ __forceinline__ double lane63(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(unsigned)b, 63);
+    const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// v[i] <- sum over the wave of v[i], i < cnt; the stages of the cnt
+// independent sums are interleaved.
+template <int K>
+__device__ __forceinline__ void wave_sum_n(double (&v)[K], int cnt)
+{
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        if (i < cnt) v[i] += dpp_move<0xB1>(v[i]);   // quad_perm [1,0,3,2]
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        if (i < cnt) v[i] += dpp_move<0x4E>(v[i]);   // quad_perm [2,3,0,1]
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        if (i < cnt) v[i] += dpp_move<0x141>(v[i]);  // row_half_mirror
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        if (i < cnt) v[i] += dpp_move<0x140>(v[i]);  // row_mirror
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        if (i < cnt) v[i] += dpp_move_rows<0x142, 0xa>(v[i]);  // row_bcast:15 into rows 1, 3
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        if (i < cnt) v[i] += dpp_move_rows<0x143, 0xc>(v[i]);  // row_bcast:31 into rows 2, 3
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        if (i < cnt) v[i] = lane63(v[i]);
+}
+
+__device__ __forceinline__ double wave_sum1(double v)
+{
+    double a[1] = {v};
+    wave_sum_n<1>(a, 1);
+    return a[0];
+}
+
+template <class F, int... J>
+__device__ __forceinline__ void static_for_impl(F &f, std::integer_sequence<int, J...>)
+{
+    (f(std::integral_constant<int, J>{}), ...);
+}
+
+// f(integral_constant<int, j>) for j = 0 .. n-1, in order
+template <int n, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, n>{});
+}
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
 // The same restarted GMRES with the Krylov basis in registers: unknown u of
 // the column sits in slot u / 64 of lane u mod 64 (S slots cover 64 S
-// unknowns), and the loops over basis vectors are unrolled so that every
-// basis access is a register.  LDS holds only the level tables, one vector
-// for the lane exchange of L_v and the small Hessenberg data, so many more
-// columns run per CU than with the basis in LDS.
+// unknowns) and the loops over basis vectors are unrolled, so every basis
+// access is a register.  Orthogonalisation is classical Gram-Schmidt applied
+// twice (as accurate as the modified form; its dot products are reduced
+// together, two reduction rounds per step instead of one per basis vector).
+// The Hessenberg column is rotated in registers on every lane; lane 0 keeps
+// the triangular factor and the rotations in LDS for the back substitution.
+// LDS holds the level coefficients, the lane exchange of L_v, b and x.
 template <int M, int S>
 __global__ void __launch_bounds__(64) gmres_reg_kernel(HeviParams h, GmresArgs g)
 {
     extern __shared__ double smem[];
-    const int nz = h.nz, NU = 3 * nz, lane = threadIdx.x;
-    const int NC = 2 * h.N + 1;
-    double *slev = smem;                  // nz x kLevW
-    double *sgz = slev + nz * kLevW;      // nz x NC
+    const int nz = h.nz, NU = 3 * nz, N = h.N, NC = 2 * N + 1, lane = threadIdx.x;
+    const int NP = nz + 2 * N;            // padded length of the L_v intermediates
+    double *slc = smem;                   // nz x 5: rho0, p0, d theta0/dz, 1/rho0, 1/theta0
+    double *sgz = slc + nz * 5;           // nz x NC
     double *xb = sgz + nz * NC;           // NU: the vector L_v is applied to
-    double *tmp = xb + NU;                // 2 nz: rho0 w and p'_L
-    double *H = tmp + 2 * nz;             // (M+1) x M
-    double *cs = H + (M + 1) * M;         // M
+    double *tp = xb + NU;                 // 2 NP: rho0 w and p'_L, N zeros on both ends
+    double *sb = tp + 2 * NP;             // NU: right-hand side
+    double *sx = sb + NU;                 // NU: iterate
+    double *R = sx + NU;                  // M x M triangular factor, R[i M + j]
+    double *cs = R + M * M;               // M
     double *sn = cs + M;                  // M
-    double *gv = sn + M;                  // M+1
+    double *gv = sn + M;                  // M: rotated residual
 
-    for (int i = lane; i < nz * kLevW; i += 64) slev[i] = h.lev[i];
+    for (int k = lane; k < nz; k += 64) {
+        const double *L = h.lev + k * kLevW;
+        slc[k * 5 + 0] = L[0];
+        slc[k * 5 + 1] = L[2];
+        slc[k * 5 + 2] = L[3];
+        slc[k * 5 + 3] = L[7];
+        slc[k * 5 + 4] = L[8];
+    }
     for (int i = lane; i < nz * NC; i += 64) sgz[i] = h.gz[i];
+    for (int i = lane; i < 2 * NP; i += 64) tp[i] = 0.0;
     __syncthreads();
 
-    // y = (I - alpha L_v) x on register vectors (slot s: unknown lane + 64 s)
-    auto apply = [&](const double *x, double *y) __attribute__((always_inline)) {
+    // slot s of this lane: field sf (0 rho', 1 w, 2 theta', 3 unused), level sk
+    int sf[S], sk[S];
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int u = lane + 64 * s;
-            if (u < NU) xb[u] = x[s];
-        }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (int s = 0; s < S; ++s) {
+        const int u = lane + 64 * s;
+        sf[s] = u < NU ? u / nz : 3;
+        sk[s] = u < NU ? u - sf[s] * nz : 0;
+    }
+
+    // y = (I - alpha L_v) x on register vectors
+    auto apply = [&](const double (&x)[S], double (&y)[S]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+            if (sf[s] < 3) xb[lane + 64 * s] = x[s];
+        wave_sync();
         for (int k = lane; k < nz; k += 64) {
-            const double *L = slev + k * kLevW;
-            tmp[k] = L[0] * xb[nz + k];
-            tmp[nz + k] = h.gamma * L[2] * (xb[k] * L[7] + xb[2 * nz + k] * L[8]);
+            const double *L = slc + k * 5;
+            tp[N + k] = L[0] * xb[nz + k];
+            tp[NP + N + k] = h.gamma * L[1] * (xb[k] * L[3] + xb[2 * nz + k] * L[4]);
         }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        wave_sync();
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            const int u = lane + 64 * s;
-            double r = 0.0;
-            if (u < NU) {
-                const int f = u / nz, k = u - f * nz;
-                const double *L = slev + k * kLevW;
-                double lv;
-                if (f == 0) {
-                    const double *G = sgz + k * NC;
-                    double d = 0.0;
-                    for (int o = -h.N; o <= h.N; ++o) {
-                        const int kk = k + o;
-                        if (kk >= 0 && kk < nz) d += G[o + h.N] * tmp[kk];
-                    }
-                    lv = -d;
-                } else if (f == 1) {
-                    if (k == 0 || k == nz - 1) {
-                        lv = 0.0;
-                    } else {
-                        const double *G = sgz + k * NC;
-                        double d = 0.0;
-                        for (int o = -h.N; o <= h.N; ++o) {
-                            const int kk = k + o;
-                            if (kk >= 0 && kk < nz) d += G[o + h.N] * tmp[nz + kk];
-                        }
-                        lv = -d * L[7] - h.g * xb[k] * L[7];
-                    }
-                } else {
-                    lv = -xb[nz + k] * L[3];
-                }
-                r = x[s] - g.alpha * lv;
+            const int f = sf[s], k = sk[s];
+            const double *L = slc + k * 5;
+            double lv = 0.0;
+            if (f == 0 || (f == 1 && k > 0 && k < nz - 1)) {
+                const double *G = sgz + k * NC;
+                const double *T = tp + (f == 0 ? 0 : NP) + k;
+                double d = 0.0;
+                for (int o = 0; o < NC; ++o) d += G[o] * T[o];
+                lv = f == 0 ? -d : -d * L[3] - h.g * xb[k] * L[3];
+            } else if (f == 2) {
+                lv = -xb[nz + k] * L[2];
             }
-            y[s] = r;
+            y[s] = f < 3 ? x[s] - g.alpha * lv : 0.0;
         }
-        // the exchange vector is rewritten by the next apply
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    };
-    auto dot = [&](const double *a, const double *c) __attribute__((always_inline)) {
-        double d = 0.0;
-#pragma unroll
-        for (int s = 0; s < S; ++s) d += a[s] * c[s];
-        return wave_sum(d);
+        // the exchange vectors are rewritten by the next apply
+        wave_sync();
     };
 
     const long nxy = (long)h.nx * h.ny;
     const long U = nxy * nz;
-    const int fld[3] = {0, 3, 4};
+    // offset of slot s's node in b and x (fields rho', w, theta' are state
+    // fields 0, 3, 4) and in x0 ([3][U])
+    auto ob = [&](int s) { return (sf[s] == 0 ? 0 : sf[s] == 1 ? 3 * U : 4 * U) + (long)sk[s] * nxy; };
+    auto o0 = [&](int s) { return sf[s] * U + (long)sk[s] * nxy; };
     for (long col = blockIdx.x; col < nxy; col += gridDim.x) {
-        double bv[S], xs[S], V[M + 1][S];
+        double bn2 = 0.0;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            const int u = lane + 64 * s;
-            bv[s] = 0.0;
-            xs[s] = 0.0;
-            if (u < NU) {
-                const int f = u / nz, k = u - f * nz;
-                const long I = col + (long)k * nxy;
-                bv[s] = g.b[fld[f] * U + I];
-                xs[s] = g.x0 ? g.x0[f * U + I] : bv[s];
+            if (sf[s] < 3) {
+                const double bb = g.b[ob(s) + col];
+                sb[lane + 64 * s] = bb;
+                sx[lane + 64 * s] = g.x0 ? g.x0[o0(s) + col] : bb;
+                bn2 += bb * bb;
             }
         }
-        const double bn = sqrt(dot(bv, bv));
+        const double bn = sqrt(wave_sum1(bn2));
         const double tol = g.rtol * bn;
         int iters = 0;
         bool conv = bn == 0.0;
         if (conv)
 #pragma unroll
-            for (int s = 0; s < S; ++s) xs[s] = 0.0;
+            for (int s = 0; s < S; ++s)
+                if (sf[s] < 3) sx[lane + 64 * s] = 0.0;
         for (int rs = 0; rs <= g.max_restarts && !conv; ++rs) {
-            apply(xs, V[0]);
+            double V[M + 1][S];
+            {
+                double t[S];
 #pragma unroll
-            for (int s = 0; s < S; ++s) V[0][s] = bv[s] - V[0][s];
-            const double rn = sqrt(dot(V[0], V[0]));
+                for (int s = 0; s < S; ++s) t[s] = sf[s] < 3 ? sx[lane + 64 * s] : 0.0;
+                apply(t, V[0]);
+            }
+            double rn2 = 0.0;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                V[0][s] = (sf[s] < 3 ? sb[lane + 64 * s] : 0.0) - V[0][s];
+                rn2 += V[0][s] * V[0][s];
+            }
+            const double rn = sqrt(wave_sum1(rn2));
             if (rn <= tol) { conv = true; break; }
+            {
+                const double inv = 1.0 / rn;
 #pragma unroll
-            for (int s = 0; s < S; ++s) V[0][s] /= rn;
-            if (lane == 0) gv[0] = rn;
+                for (int s = 0; s < S; ++s) V[0][s] *= inv;
+            }
+            double gj = rn, res = rn;
             int jn = 0;
-            double res = rn;
             bool done = false;
-            // fully unrolled (basis indices are registers): no early exit,
-            // the remaining steps are skipped by a wave-uniform flag
-#pragma unroll
-            for (int j = 0; j < M; ++j) {
+            // one instance per step (basis indices are registers): no early
+            // exit, the remaining steps are skipped by a wave-uniform flag
+            static_for<M>([&](auto jc) __attribute__((always_inline)) {
+                constexpr int j = decltype(jc)::value;
                 if (!done) {
                     apply(V[j], V[j + 1]);
+                    double hc[M + 1], e[M + 1];
+                    // first Gram-Schmidt pass
+#pragma unroll
+                    for (int i = 0; i <= M; ++i) {
+                        hc[i] = 0.0;
+                        if (i <= j)
+#pragma unroll
+                            for (int s = 0; s < S; ++s) hc[i] += V[j + 1][s] * V[i][s];
+                    }
+                    wave_sum_n<M + 1>(hc, j + 1);
+#pragma unroll
+                    for (int i = 0; i <= j; ++i)
+#pragma unroll
+                        for (int s = 0; s < S; ++s) V[j + 1][s] -= hc[i] * V[i][s];
+                    // second pass
+#pragma unroll
+                    for (int i = 0; i <= M; ++i) {
+                        e[i] = 0.0;
+                        if (i <= j)
+#pragma unroll
+                            for (int s = 0; s < S; ++s) e[i] += V[j + 1][s] * V[i][s];
+                    }
+                    wave_sum_n<M + 1>(e, j + 1);
 #pragma unroll
                     for (int i = 0; i <= j; ++i) {
-                        const double d = dot(V[j + 1], V[i]);
 #pragma unroll
-                        for (int s = 0; s < S; ++s) V[j + 1][s] -= d * V[i][s];
-                        if (lane == 0) H[i * M + j] = d;
+                        for (int s = 0; s < S; ++s) V[j + 1][s] -= e[i] * V[i][s];
+                        hc[i] += e[i];
                     }
-                    const double nn = sqrt(dot(V[j + 1], V[j + 1]));
-                    if (nn > 0.0)
+                    double nn2 = 0.0;
 #pragma unroll
-                        for (int s = 0; s < S; ++s) V[j + 1][s] /= nn;
+                    for (int s = 0; s < S; ++s) nn2 += V[j + 1][s] * V[j + 1][s];
+                    const double nn = sqrt(wave_sum1(nn2));
+                    if (nn > 0.0) {
+                        const double inv = 1.0 / nn;
+#pragma unroll
+                        for (int s = 0; s < S; ++s) V[j + 1][s] *= inv;
+                    }
+                    // earlier rotations on column j, then the new one
+#pragma unroll
+                    for (int i = 0; i < j; ++i) {
+                        const double c = cs[i], sg = sn[i], a = hc[i], bb = hc[i + 1];
+                        hc[i] = c * a + sg * bb;
+                        hc[i + 1] = -sg * a + c * bb;
+                    }
+                    const double a = hc[j];
+                    const double r = sqrt(a * a + nn * nn);
+                    const double c = r > 0.0 ? a / r : 1.0, sg = r > 0.0 ? nn / r : 0.0;
                     if (lane == 0) {
-                        H[(j + 1) * M + j] = nn;
-                        for (int i = 0; i < j; ++i) {
-                            const double a = H[i * M + j], bb = H[(i + 1) * M + j];
-                            H[i * M + j] = cs[i] * a + sn[i] * bb;
-                            H[(i + 1) * M + j] = -sn[i] * a + cs[i] * bb;
-                        }
-                        const double a = H[j * M + j], bb = H[(j + 1) * M + j];
-                        const double r = sqrt(a * a + bb * bb);
-                        const double c = r > 0.0 ? a / r : 1.0, sg = r > 0.0 ? bb / r : 0.0;
+#pragma unroll
+                        for (int i = 0; i < j; ++i) R[i * M + j] = hc[i];
+                        R[j * M + j] = r;
                         cs[j] = c;
                         sn[j] = sg;
-                        H[j * M + j] = r;
-                        H[(j + 1) * M + j] = 0.0;
-                        gv[j + 1] = -sg * gv[j];
-                        gv[j] = c * gv[j];
+                        gv[j] = c * gj;
                     }
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                    res = fabs(gv[j + 1]);
+                    wave_sync();
+                    gj = -sg * gj;
+                    res = fabs(gj);
                     ++iters;
                     jn = j + 1;
                     done = res <= tol || nn == 0.0;
                 }
-            }
-            // back substitution y = H^-1 g (lane 0), x += V y
-            if (lane == 0) {
-                for (int i = jn - 1; i >= 0; --i) {
-                    double sacc = gv[i];
-                    for (int l = i + 1; l < jn; ++l) sacc -= H[i * M + l] * gv[l];
-                    gv[i] = sacc / H[i * M + i];
+            });
+            // back substitution y = R^-1 g on every lane, x += V y
+            double y[M];
+#pragma unroll
+            for (int i = M - 1; i >= 0; --i) {
+                y[i] = 0.0;
+                if (i < jn) {
+                    double acc = gv[i];
+#pragma unroll
+                    for (int l = i + 1; l < M; ++l)
+                        if (l < jn) acc -= R[i * M + l] * y[l];
+                    y[i] = acc / R[i * M + i];
                 }
             }
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
-            for (int i = 0; i < M; ++i) {
-                if (i < jn) {
-                    const double yi = gv[i];
+            for (int s = 0; s < S; ++s) {
+                if (sf[s] < 3) {
+                    double acc = sx[lane + 64 * s];
 #pragma unroll
-                    for (int s = 0; s < S; ++s) xs[s] += yi * V[i][s];
+                    for (int i = 0; i < M; ++i) acc += y[i] * V[i][s];
+                    sx[lane + 64 * s] = acc;
                 }
             }
             if (res <= tol) {
                 // confirm with the true residual
-                double t[S];
-                apply(xs, t);
+                double t[S], w[S];
 #pragma unroll
-                for (int s = 0; s < S; ++s) t[s] = bv[s] - t[s];
-                conv = sqrt(dot(t, t)) <= tol;
+                for (int s = 0; s < S; ++s) t[s] = sf[s] < 3 ? sx[lane + 64 * s] : 0.0;
+                apply(t, w);
+                double tn2 = 0.0;
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    const double d = (sf[s] < 3 ? sb[lane + 64 * s] : 0.0) - w[s];
+                    tn2 += d * d;
+                }
+                conv = sqrt(wave_sum1(tn2)) <= tol;
             }
         }
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int u = lane + 64 * s;
-            if (u < NU) {
-                const int f = u / nz, k = u - f * nz;
-                g.x[fld[f] * U + col + (long)k * nxy] = xs[s];
-            }
-        }
+        for (int s = 0; s < S; ++s)
+            if (sf[s] < 3) g.x[ob(s) + col] = sx[lane + 64 * s];
         for (int k = lane; k < nz; k += 64) {
             const long I = col + (long)k * nxy;
             g.x[U + I] = g.b[U + I];
             g.x[2 * U + I] = g.b[2 * U + I];
         }
         if (lane == 0 && g.iters) g.iters[col] = conv ? iters : -iters - 1;
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        wave_sync();
     }
 }
 
@@ -500,9 +625,8 @@ hipError_t launch_gmres(const HeviParams &h, const GmresArgs &g, hipStream_t s)
     if (g.restart == kGmresRegM && 3 * h.nz <= 64 * kGmresRegSlots) {
         // register basis: LDS for the level tables, the exchange vector and
         // the Hessenberg data only
-        const size_t lds = sizeof(double) * ((size_t)h.nz * kLevW + (size_t)h.nz * (2 * h.N + 1) + 3 * h.nz +
-                                             2 * h.nz + (kGmresRegM + 1) * kGmresRegM + 2 * kGmresRegM +
-                                             kGmresRegM + 1);
+        const size_t lds = sizeof(double) * ((size_t)h.nz * 5 + (size_t)h.nz * (2 * h.N + 1) + 9 * h.nz +
+                                             2 * (h.nz + 2 * h.N) + kGmresRegM * kGmresRegM + 3 * kGmresRegM);
         const int grid = (int)(ncol < 32768 ? ncol : 32768);
         hipLaunchKernelGGL((gmres_reg_kernel<kGmresRegM, kGmresRegSlots>), dim3(grid), dim3(64), lds, s, h, g);
         return hipGetLastError();
