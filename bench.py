@@ -67,7 +67,7 @@ def parse():
                          "HBM byte counters; precision: FP32-mixed vs FP64 after --err-steps steps")
     ap.add_argument("--members", type=int, default=48)
     ap.add_argument("--mlp-epochs", type=int, default=40, help="training epochs of the column MLP (hevi mode)")
-    ap.add_argument("--gmres-restart", type=int, default=20, help="Krylov vectors per GMRES cycle (hevi mode)")
+    ap.add_argument("--gmres-restart", type=int, default=10, help="Krylov vectors per GMRES cycle (hevi mode)")
     return ap.parse_args()
 
 

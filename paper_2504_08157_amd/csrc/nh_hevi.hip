@@ -344,9 +344,14 @@ __device__ __forceinline__ void wave_sync()
 // The same restarted GMRES with the Krylov basis in registers: unknown u of
 // the column sits in slot u / 64 of lane u mod 64 (S slots cover 64 S
 // unknowns) and the loops over basis vectors are unrolled, so every basis
-// access is a register.  Orthogonalisation is classical Gram-Schmidt applied
-// twice (as accurate as the modified form; its dot products are reduced
-// together, two reduction rounds per step instead of one per basis vector).
+// access is a register.  Orthogonalisation is classical Gram-Schmidt with
+// the re-orthogonalisation test of Daniel, Gragg, Kaufman and Stewart (1976):
+// the dot products and |w|^2 are reduced together in one round, the new norm
+// follows from Pythagoras, and a second pass runs only where the projection
+// cancelled more than half of |w|^2 (one reduction round per step instead of
+// one per basis vector).  The Arnoldi process runs on L_v itself, which
+// spans the same Krylov space as A = I - alpha L_v (H_A = I - alpha H_L) but
+// without the identity part that the projection would cancel every step.
 // The Hessenberg column is rotated in registers on every lane; lane 0 keeps
 // the triangular factor and the rotations in LDS for the back substitution.
 // LDS holds the level coefficients, the lane exchange of L_v, b and x.
@@ -388,7 +393,7 @@ __global__ void __launch_bounds__(64) gmres_reg_kernel(HeviParams h, GmresArgs g
         sk[s] = u < NU ? u - sf[s] * nz : 0;
     }
 
-    // y = (I - alpha L_v) x on register vectors
+    // y = L_v x on register vectors
     auto apply = [&](const double (&x)[S], double (&y)[S]) __attribute__((always_inline)) {
 #pragma unroll
         for (int s = 0; s < S; ++s)
@@ -414,7 +419,7 @@ __global__ void __launch_bounds__(64) gmres_reg_kernel(HeviParams h, GmresArgs g
             } else if (f == 2) {
                 lv = -xb[nz + k] * L[2];
             }
-            y[s] = f < 3 ? x[s] - g.alpha * lv : 0.0;
+            y[s] = lv;
         }
         // the exchange vectors are rewritten by the next apply
         wave_sync();
@@ -452,13 +457,13 @@ __global__ void __launch_bounds__(64) gmres_reg_kernel(HeviParams h, GmresArgs g
 #pragma unroll
                 for (int s = 0; s < S; ++s) t[s] = sf[s] < 3 ? sx[lane + 64 * s] : 0.0;
                 apply(t, V[0]);
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+                    V[0][s] = sf[s] < 3 ? sb[lane + 64 * s] - (t[s] - g.alpha * V[0][s]) : 0.0;
             }
             double rn2 = 0.0;
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
-                V[0][s] = (sf[s] < 3 ? sb[lane + 64 * s] : 0.0) - V[0][s];
-                rn2 += V[0][s] * V[0][s];
-            }
+            for (int s = 0; s < S; ++s) rn2 += V[0][s] * V[0][s];
             const double rn = sqrt(wave_sum1(rn2));
             if (rn <= tol) { conv = true; break; }
             {
@@ -475,45 +480,63 @@ __global__ void __launch_bounds__(64) gmres_reg_kernel(HeviParams h, GmresArgs g
                 constexpr int j = decltype(jc)::value;
                 if (!done) {
                     apply(V[j], V[j + 1]);
-                    double hc[M + 1], e[M + 1];
-                    // first Gram-Schmidt pass
+                    // Gram-Schmidt: the dots with V_0..V_j and |w|^2 in one
+                    // batched reduction; |w - V h| from Pythagoras unless the
+                    // projection removed more than half of |w|^2, in which
+                    // case the pass is repeated and the norm taken directly
+                    double hc[M + 2];
 #pragma unroll
-                    for (int i = 0; i <= M; ++i) {
+                    for (int i = 0; i <= M + 1; ++i) {
                         hc[i] = 0.0;
                         if (i <= j)
 #pragma unroll
                             for (int s = 0; s < S; ++s) hc[i] += V[j + 1][s] * V[i][s];
+                        if (i == j + 1)
+#pragma unroll
+                            for (int s = 0; s < S; ++s) hc[i] += V[j + 1][s] * V[j + 1][s];
                     }
-                    wave_sum_n<M + 1>(hc, j + 1);
-#pragma unroll
-                    for (int i = 0; i <= j; ++i)
-#pragma unroll
-                        for (int s = 0; s < S; ++s) V[j + 1][s] -= hc[i] * V[i][s];
-                    // second pass
-#pragma unroll
-                    for (int i = 0; i <= M; ++i) {
-                        e[i] = 0.0;
-                        if (i <= j)
-#pragma unroll
-                            for (int s = 0; s < S; ++s) e[i] += V[j + 1][s] * V[i][s];
-                    }
-                    wave_sum_n<M + 1>(e, j + 1);
+                    wave_sum_n<M + 2>(hc, j + 2);
+                    const double w2 = hc[j + 1];
+                    double p2 = 0.0;
 #pragma unroll
                     for (int i = 0; i <= j; ++i) {
+                        p2 += hc[i] * hc[i];
 #pragma unroll
-                        for (int s = 0; s < S; ++s) V[j + 1][s] -= e[i] * V[i][s];
-                        hc[i] += e[i];
+                        for (int s = 0; s < S; ++s) V[j + 1][s] -= hc[i] * V[i][s];
                     }
-                    double nn2 = 0.0;
+                    double nn2 = w2 - p2;
+                    if (nn2 < 0.5 * w2) {
+                        double e[M + 1];
 #pragma unroll
-                    for (int s = 0; s < S; ++s) nn2 += V[j + 1][s] * V[j + 1][s];
-                    const double nn = sqrt(wave_sum1(nn2));
+                        for (int i = 0; i <= M; ++i) {
+                            e[i] = 0.0;
+                            if (i <= j)
+#pragma unroll
+                                for (int s = 0; s < S; ++s) e[i] += V[j + 1][s] * V[i][s];
+                        }
+                        wave_sum_n<M + 1>(e, j + 1);
+#pragma unroll
+                        for (int i = 0; i <= j; ++i) {
+#pragma unroll
+                            for (int s = 0; s < S; ++s) V[j + 1][s] -= e[i] * V[i][s];
+                            hc[i] += e[i];
+                        }
+                        double t2 = 0.0;
+#pragma unroll
+                        for (int s = 0; s < S; ++s) t2 += V[j + 1][s] * V[j + 1][s];
+                        nn2 = wave_sum1(t2);
+                    }
+                    const double nn = sqrt(nn2);
                     if (nn > 0.0) {
                         const double inv = 1.0 / nn;
 #pragma unroll
                         for (int s = 0; s < S; ++s) V[j + 1][s] *= inv;
                     }
-                    // earlier rotations on column j, then the new one
+                    // column j of the Hessenberg matrix of A = I - alpha L_v
+                    // from that of L_v, the earlier rotations, the new one
+#pragma unroll
+                    for (int i = 0; i <= j; ++i) hc[i] = (i == j ? 1.0 : 0.0) - g.alpha * hc[i];
+                    const double sub = -g.alpha * nn;
 #pragma unroll
                     for (int i = 0; i < j; ++i) {
                         const double c = cs[i], sg = sn[i], a = hc[i], bb = hc[i + 1];
@@ -521,8 +544,8 @@ __global__ void __launch_bounds__(64) gmres_reg_kernel(HeviParams h, GmresArgs g
                         hc[i + 1] = -sg * a + c * bb;
                     }
                     const double a = hc[j];
-                    const double r = sqrt(a * a + nn * nn);
-                    const double c = r > 0.0 ? a / r : 1.0, sg = r > 0.0 ? nn / r : 0.0;
+                    const double r = sqrt(a * a + sub * sub);
+                    const double c = r > 0.0 ? a / r : 1.0, sg = r > 0.0 ? sub / r : 0.0;
                     if (lane == 0) {
 #pragma unroll
                         for (int i = 0; i < j; ++i) R[i * M + j] = hc[i];
@@ -570,7 +593,7 @@ __global__ void __launch_bounds__(64) gmres_reg_kernel(HeviParams h, GmresArgs g
                 double tn2 = 0.0;
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
-                    const double d = (sf[s] < 3 ? sb[lane + 64 * s] : 0.0) - w[s];
+                    const double d = sf[s] < 3 ? sb[lane + 64 * s] - (t[s] - g.alpha * w[s]) : 0.0;
                     tn2 += d * d;
                 }
                 conv = sqrt(wave_sum1(tn2)) <= tol;
