@@ -255,11 +255,10 @@ __global__ void __launch_bounds__(64) gmres_column_kernel(HeviParams h, GmresArg
 }
 
 // ---------------------------------------------------------------- GMRES, register basis
-// Wave-wide sums through DPP lane moves (no LDS traffic): butterflies inside
-// each 16-lane row, then the row sums are chained by the row broadcasts; the
-// total ends in lane 63 and is read back as a wave-uniform value.  The order
-// of the additions is fixed, so the sum is deterministic.
-// Lane move with every source lane valid (all rows written).
+// Wave-wide sums in registers (no LDS traffic): gfx950 lane swaps between
+// register pairs and DPP butterflies inside 16-lane rows.
+
+// DPP lane move with every source lane valid.
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double v)
 {
@@ -269,57 +268,50 @@ __device__ __forceinline__ double dpp_move(double v)
     return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
-// Lane move into the rows of ROWS only; the other rows read zero.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_move_rows(double v)
+__device__ __forceinline__ double join_d(unsigned lo, unsigned hi)
+{
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// gfx950 lane swaps between two registers (one 16-lane row is a "row"):
+// swap32: a <- [a lanes 0-31, b lanes 0-31], b <- [a lanes 32-63, b lanes 32-63]
+// swap16: a <- [a row 0, b row 0, a row 2, b row 2], b <- [a row 1, b row 1, a row 3, b row 3]
+__device__ __forceinline__ void swap32(double &a, double &b)
+{
+    const unsigned long long ua = (unsigned long long)__double_as_longlong(a);
+    const unsigned long long ub = (unsigned long long)__double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+    a = join_d(lo[0], hi[0]);
+    b = join_d(lo[1], hi[1]);
+}
+
+__device__ __forceinline__ void swap16(double &a, double &b)
+{
+    const unsigned long long ua = (unsigned long long)__double_as_longlong(a);
+    const unsigned long long ub = (unsigned long long)__double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+    a = join_d(lo[0], hi[0]);
+    b = join_d(lo[1], hi[1]);
+}
+
+// every lane of each 16-lane row <- the sum over its row
+__device__ __forceinline__ double row_sum(double v)
+{
+    v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_move<0x141>(v);  // row_half_mirror
+    v += dpp_move<0x140>(v);  // row_mirror
+    return v;
+}
+
+template <int L>
+__device__ __forceinline__ double lane_value(double v)
 {
     const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWS, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWS, 0xf, false);
-    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-
-__device__ __forceinline__ double lane63(double v)
-{
-    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(unsigned)b, 63);
-    const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
-    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-
-// v[i] <- sum over the wave of v[i], i < cnt; the stages of the cnt
-// independent sums are interleaved.
-template <int K>
-__device__ __forceinline__ void wave_sum_n(double (&v)[K], int cnt)
-{
-#pragma unroll
-    for (int i = 0; i < K; ++i)
-        if (i < cnt) v[i] += dpp_move<0xB1>(v[i]);   // quad_perm [1,0,3,2]
-#pragma unroll
-    for (int i = 0; i < K; ++i)
-        if (i < cnt) v[i] += dpp_move<0x4E>(v[i]);   // quad_perm [2,3,0,1]
-#pragma unroll
-    for (int i = 0; i < K; ++i)
-        if (i < cnt) v[i] += dpp_move<0x141>(v[i]);  // row_half_mirror
-#pragma unroll
-    for (int i = 0; i < K; ++i)
-        if (i < cnt) v[i] += dpp_move<0x140>(v[i]);  // row_mirror
-#pragma unroll
-    for (int i = 0; i < K; ++i)
-        if (i < cnt) v[i] += dpp_move_rows<0x142, 0xa>(v[i]);  // row_bcast:15 into rows 1, 3
-#pragma unroll
-    for (int i = 0; i < K; ++i)
-        if (i < cnt) v[i] += dpp_move_rows<0x143, 0xc>(v[i]);  // row_bcast:31 into rows 2, 3
-#pragma unroll
-    for (int i = 0; i < K; ++i)
-        if (i < cnt) v[i] = lane63(v[i]);
-}
-
-__device__ __forceinline__ double wave_sum1(double v)
-{
-    double a[1] = {v};
-    wave_sum_n<1>(a, 1);
-    return a[0];
+    return join_d((unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, L),
+                  (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), L));
 }
 
 template <class F, int... J>
@@ -335,6 +327,40 @@ __device__ __forceinline__ void static_for(F &&f)
     static_for_impl(f, std::make_integer_sequence<int, n>{});
 }
 
+// v[i] <- sum over the wave of v[i] for i < CNT, four sums at a time: the
+// halves and then the rows of the four registers are exchanged and added
+// (each register then carries one sum per row), one row reduction follows,
+// and each sum is read from its row.  Fixed order of additions.
+template <int CNT, int K>
+__device__ __forceinline__ void wave_sum_t(double (&v)[K])
+{
+    static_for<(CNT + 3) / 4>([&](auto qc) __attribute__((always_inline)) {
+        constexpr int q = 4 * decltype(qc)::value;
+        double a = v[q], b = 0.0, c = 0.0, d = 0.0;
+        if constexpr (q + 1 < CNT) b = v[q + 1];
+        if constexpr (q + 2 < CNT) c = v[q + 2];
+        if constexpr (q + 3 < CNT) d = v[q + 3];
+        swap32(a, b);
+        swap32(c, d);
+        double p = a + b, r = c + d;   // lanes 0-31: sums q, q+2; lanes 32-63: q+1, q+3
+        swap16(p, r);
+        const double t = row_sum(p + r);   // rows 0..3: sums q, q+2, q+1, q+3
+        v[q] = lane_value<0>(t);
+        if constexpr (q + 1 < CNT) v[q + 1] = lane_value<32>(t);
+        if constexpr (q + 2 < CNT) v[q + 2] = lane_value<16>(t);
+        if constexpr (q + 3 < CNT) v[q + 3] = lane_value<48>(t);
+    });
+}
+
+// one sum, left in every lane
+__device__ __forceinline__ double wave_sum1(double v)
+{
+    double a = v, b = v;
+    swap32(a, b);
+    double p = a + b, r = p;
+    swap16(p, r);
+    return row_sum(p + r);
+}
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_wave_barrier();
@@ -495,7 +521,7 @@ __global__ void __launch_bounds__(64) gmres_reg_kernel(HeviParams h, GmresArgs g
 #pragma unroll
                             for (int s = 0; s < S; ++s) hc[i] += V[j + 1][s] * V[j + 1][s];
                     }
-                    wave_sum_n<M + 2>(hc, j + 2);
+                    wave_sum_t<j + 2>(hc);
                     const double w2 = hc[j + 1];
                     double p2 = 0.0;
 #pragma unroll
@@ -514,7 +540,7 @@ __global__ void __launch_bounds__(64) gmres_reg_kernel(HeviParams h, GmresArgs g
 #pragma unroll
                                 for (int s = 0; s < S; ++s) e[i] += V[j + 1][s] * V[i][s];
                         }
-                        wave_sum_n<M + 1>(e, j + 1);
+                        wave_sum_t<j + 1>(e);
 #pragma unroll
                         for (int i = 0; i <= j; ++i) {
 #pragma unroll
