@@ -124,7 +124,7 @@ hipError_t launch_mlp_features(const MlpColParams &p, const double *b, const dou
                                long col0, long ncol, void *feat, double *scale, float *tgt, hipStream_t s);
 hipError_t launch_mlp_guess(const MlpColParams &p, const double *b, long col0, long ncol, const float *y,
                             const double *scale, double *x0, hipStream_t s);
-hipError_t mlp_forward(const MlpNet &net, int M, const void *X, hipStream_t s);
+hipError_t mlp_forward(const MlpNet &net, int M, const void *X, hipStream_t s, bool keep_z = true);
 hipError_t mlp_backward(const MlpNet &net, int M, const void *X, const float *dY, hipStream_t s);
 hipError_t mlp_loss_grad(const MlpNet &net, int M, const float *T, float *loss, hipStream_t s);
 hipError_t mlp_adam(const MlpNet &net, float lr, float b1, float b2, float eps, int step, hipStream_t s);

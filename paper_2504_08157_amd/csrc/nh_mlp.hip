@@ -55,7 +55,9 @@ __device__ __forceinline__ double dim_factor(const MlpColParams &p, int f, int k
 // 64 consecutive columns of one level, coalesced), the 4 waves split the
 // levels of the scale sum and the canonical levels of the resampling; the
 // features of the 64 columns are assembled in LDS and written out as whole
-// rows.
+// rows.  The interpolation intervals of the canonical levels and the
+// inverse dimension factors of every level are tabulated in LDS first
+// (dynamic LDS: 3 n_z doubles).
 __global__ void __launch_bounds__(256) mlp_features_kernel(MlpColParams p, const double *__restrict__ b,
                                                            const double *__restrict__ lb,
                                                            const double *__restrict__ x, long col0,
@@ -64,11 +66,18 @@ __global__ void __launch_bounds__(256) mlp_features_kernel(MlpColParams p, const
 {
     __shared__ _Float16 sf[64][kMlpIn];
     __shared__ double spart[4][64];
+    __shared__ int sk0[kMlpNC];
+    __shared__ double st[kMlpNC];
+    extern __shared__ double sdinv[];   // [3][n_z]
+    const int nz = p.nz;
     const long nxy = (long)p.nx * p.ny;
-    const long U = nxy * p.nz;
+    const long U = nxy * nz;
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int fld[3] = {0, 3, 4};
-    const double H = p.z[p.nz - 1] - p.z[0];
+    const double H = p.z[nz - 1] - p.z[0];
+    for (int i = threadIdx.x; i < 3 * nz; i += 256) sdinv[i] = 1.0 / dim_factor(p, i / nz, i % nz);
+    for (int c = threadIdx.x; c < kMlpNC; c += 256) canon_interp(p.z, nz, p.z[0] + H * p.zc[c], &sk0[c], &st[c]);
+    __syncthreads();
     const long r0 = (long)blockIdx.x * 64;
     const long r = r0 + lane;
     const bool ok = r < ncol;
@@ -76,10 +85,10 @@ __global__ void __launch_bounds__(256) mlp_features_kernel(MlpColParams p, const
     // s = RMS over the column of the dimensionless b and alpha L_v b
     double a = 0.0;
 #pragma unroll 4
-    for (int k = q; k < p.nz; k += 4) {
+    for (int k = q; k < nz; k += 4) {
         const long I = col + (long)k * nxy;
         for (int f = 0; f < 3; ++f) {
-            const double d = 1.0 / dim_factor(p, f, k);
+            const double d = sdinv[f * nz + k];
             const double v = b[fld[f] * U + I] * d;
             const double l = p.alpha * lb[fld[f] * U + I] * d;
             a += v * v + l * l;
@@ -87,14 +96,13 @@ __global__ void __launch_bounds__(256) mlp_features_kernel(MlpColParams p, const
     }
     spart[q][lane] = a;
     __syncthreads();
-    const double s = sqrt((spart[0][lane] + spart[1][lane] + spart[2][lane] + spart[3][lane]) / (3.0 * p.nz)) + 1e-300;
+    const double s = sqrt((spart[0][lane] + spart[1][lane] + spart[2][lane] + spart[3][lane]) / (3.0 * nz)) + 1e-300;
     for (int c = q; c < kMlpNC; c += 4) {
-        int k0;
-        double t;
-        canon_interp(p.z, p.nz, p.z[0] + H * p.zc[c], &k0, &t);
+        const int k0 = sk0[c];
+        const double t = st[c];
         for (int f = 0; f < 3; ++f) {
             const long I0 = fld[f] * U + col + (long)k0 * nxy, I1 = I0 + nxy;
-            const double d0 = 1.0 / dim_factor(p, f, k0), d1 = 1.0 / dim_factor(p, f, k0 + 1);
+            const double d0 = sdinv[f * nz + k0], d1 = sdinv[f * nz + k0 + 1];
             const double vb = (1.0 - t) * (b[I0] * d0) + t * (b[I1] * d1);
             const double vl = (1.0 - t) * (p.alpha * lb[I0] * d0) + t * (p.alpha * lb[I1] * d1);
             sf[lane][f * kMlpNC + c] = (_Float16)(vb / s);
@@ -123,22 +131,28 @@ __global__ void __launch_bounds__(256) mlp_features_kernel(MlpColParams p, const
     for (long i = threadIdx.x; i < nrow * (kMlpIn / 2); i += 256) dst[i] = src[i];
 }
 
-// x0 = b + D s (y resampled from the canonical to the lattice levels), one
-// thread per lattice node of the batch; the w correction is zero on the
-// bottom and top levels, and a non-finite prediction falls back to x0 = b.
-__global__ void mlp_guess_kernel(MlpColParams p, const double *__restrict__ b, long col0, long ncol,
-                                 const float *__restrict__ y, const double *__restrict__ scale,
-                                 double *__restrict__ x0)
+// x0 = b + D s (y resampled from the canonical to the lattice levels); the
+// w correction is zero on the bottom and top levels, and a non-finite
+// prediction falls back to x0 = b.  64 columns per workgroup of 256
+// threads: the used outputs of the 64 rows of y are staged in LDS, lane =
+// column (b reads and x0 writes coalesced), the 4 waves split the levels.
+// Per-level tables (dynamic LDS: 4 n_z doubles and n_z ints): the canonical
+// interval and weight of each lattice level and its dimension factors.
+__global__ void __launch_bounds__(256) mlp_guess_kernel(MlpColParams p, const double *__restrict__ b, long col0,
+                                                        long ncol, const float *__restrict__ y,
+                                                        const double *__restrict__ scale, double *__restrict__ x0)
 {
+    __shared__ float sy[64][kMlpNF + 1];
+    extern __shared__ double sg[];
+    const int nz = p.nz;
+    double *tg = sg;              // [n_z] interpolation weight
+    double *dg = sg + nz;         // [3][n_z] dimension factors
+    int *lg = (int *)(sg + 4 * nz);   // [n_z] canonical interval
     const long nxy = (long)p.nx * p.ny;
-    const long U = nxy * p.nz;
+    const long U = nxy * nz;
     const int fld[3] = {0, 3, 4};
-    const double H = p.z[p.nz - 1] - p.z[0];
-    const long n = ncol * p.nz;
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        const long r = i % ncol;
-        const int k = (int)(i / ncol);
-        const long I = col0 + r + (long)k * nxy;
+    const double H = p.z[nz - 1] - p.z[0];
+    for (int k = threadIdx.x; k < nz; k += 256) {
         const double zh = (p.z[k] - p.z[0]) / H;
         int lo = 0, hi = kMlpNC - 1;
         while (hi - lo > 1) {
@@ -148,80 +162,109 @@ __global__ void mlp_guess_kernel(MlpColParams p, const double *__restrict__ b, l
         double t = (zh - p.zc[lo]) / (p.zc[lo + 1] - p.zc[lo]);
         if (t < 0.0) t = 0.0;
         if (t > 1.0) t = 1.0;
+        lg[k] = lo;
+        tg[k] = t;
+        for (int f = 0; f < 3; ++f) dg[f * nz + k] = dim_factor(p, f, k);
+    }
+    const long r0 = (long)blockIdx.x * 64;
+    const long nrow = ncol - r0 < 64 ? ncol - r0 : 64;
+    for (long i = threadIdx.x; i < nrow * kMlpNF; i += 256) {
+        const long rr = i / kMlpNF;
+        const int c = (int)(i - rr * kMlpNF);
+        sy[rr][c] = y[(r0 + rr) * kMlpOut + c];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    if (lane >= nrow) return;
+    const long r = r0 + lane;
+    const double s = scale[r];
+    for (int k = q; k < nz; k += 4) {
+        const long I = col0 + r + (long)k * nxy;
+        const int lo = lg[k];
+        const double t = tg[k];
         for (int f = 0; f < 3; ++f) {
-            const float *yr = y + r * kMlpOut + f * kMlpNC;
+            const float *yr = &sy[lane][f * kMlpNC];
             double d = (1.0 - t) * yr[lo] + t * yr[lo + 1];
-            if (!isfinite(d) || (f == 1 && (k == 0 || k == p.nz - 1))) d = 0.0;
-            x0[f * U + I] = b[fld[f] * U + I] + dim_factor(p, f, k) * scale[r] * d;
+            if (!isfinite(d) || (f == 1 && (k == 0 || k == nz - 1))) d = 0.0;
+            x0[f * U + I] = b[fld[f] * U + I] + dg[f * nz + k] * s * d;
         }
     }
 }
 
 // ---------------------------------------------------------------- forward GEMM (MFMA)
-// C[M x N] = A[M x K] W[N x K]^T + bias, A and W FP16 row-major, FP32
-// accumulation on v_mfma_f32_16x16x16_f16.  Workgroup: 256 threads = 4 waves,
-// 64 x 64 tile of C, each wave a 32 x 32 quarter (2 x 2 MFMA tiles).
-// Optional second product A2[M x K2] W2[N x K2]^T into the same accumulators
-// (the linear bypass of the last layer).
-// Epilogue: Z (FP32, pre-activation) and, when act != 0, H = SiLU(Z) in FP16.
-// Requires M % 64 == 0, N % 64 == 0, K % 16 == 0, K2 % 16 == 0.
-__global__ void __launch_bounds__(256) gemm_f16_kernel(const _Float16 *__restrict__ A,
-                                                       const _Float16 *__restrict__ W,
-                                                       const float *__restrict__ bias, int M, int N, int K,
-                                                       float *__restrict__ Z, _Float16 *__restrict__ Hout,
-                                                       int act, const _Float16 *__restrict__ A2,
-                                                       const _Float16 *__restrict__ W2, int K2)
+// C[M x 256] = A[M x K] W[256 x K]^T (+ A2[M x K2] W2[256 x K2]^T) + bias,
+// FP16 operands, FP32 accumulation on v_mfma_f32_16x16x16_f16.  Workgroup:
+// 64 rows and all 256 outputs, 4 waves (wave w: outputs 64 w .. 64 w + 63,
+// 4 x 4 MFMA tiles).  The K loop stages 16-wide slices of A (64 x 16) and
+// W (256 x 16) in LDS; the next slice is loaded into registers while the
+// current one is multiplied.  The optional second product (the linear bypass
+// of the last layer) accumulates into the same registers.
+// Epilogue: Z (FP32 pre-activation, skipped when null) and, when act != 0,
+// H = SiLU(Z) in FP16.  Requires M % 64 == 0, K % 16 == 0, K2 % 16 == 0.
+__global__ void __launch_bounds__(256) gemm_rows_kernel(const _Float16 *__restrict__ A,
+                                                        const _Float16 *__restrict__ W,
+                                                        const float *__restrict__ bias, int K,
+                                                        const _Float16 *__restrict__ A2,
+                                                        const _Float16 *__restrict__ W2, int K2,
+                                                        float *__restrict__ Z, _Float16 *__restrict__ Hout, int act)
 {
-    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int m0 = blockIdx.y * 64 + (wave / 2) * 32;
-    const int n0 = blockIdx.x * 64 + (wave % 2) * 32;
-    float4v acc[2][2];
+    __shared__ half4 sA[64 * 4];    // [row][k quad]
+    __shared__ half4 sB[256 * 4];   // [output][k quad]
+    const int t = threadIdx.x, wave = t / 64, lane = t % 64;
+    const long m0 = (long)blockIdx.x * 64;
+    const int r16 = lane % 16, kq = lane / 16;
+    float4v acc[4][4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) acc[a][c] = float4v{0.f, 0.f, 0.f, 0.f};
-    const int r16 = lane % 16, kq = (lane / 16) * 4;
-    for (int k = 0; k < K; k += 16) {
-        half4 av[2], bv[2];
+        for (int c = 0; c < 4; ++c) acc[a][c] = float4v{0.f, 0.f, 0.f, 0.f};
+
+    auto run = [&](const _Float16 *Ap, const _Float16 *Wp, int KK) {
+        // thread t stages quad t % 4 of A row t / 4 and all 4 quads of W row t
+        const _Float16 *ga = Ap + (m0 + t / 4) * KK + (t % 4) * 4;
+        const _Float16 *gw = Wp + (long)t * KK;
+        half4 ra = *(const half4 *)ga;
+        half4 rw[4];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            const _Float16 *pa = A + (long)(m0 + a * 16 + r16) * K + k + kq;
-            av[a] = *(const half4 *)pa;
-            const _Float16 *pb = W + (long)(n0 + a * 16 + r16) * K + k + kq;
-            bv[a] = *(const half4 *)pb;
-        }
+        for (int q = 0; q < 4; ++q) rw[q] = *(const half4 *)(gw + 4 * q);
+        for (int k = 0; k < KK; k += 16) {
+            __syncthreads();   // the previous slice has been read
+            sA[t] = ra;
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+            for (int q = 0; q < 4; ++q) sB[t * 4 + q] = rw[q];
+            __syncthreads();
+            if (k + 16 < KK) {
+                ra = *(const half4 *)(ga + k + 16);
 #pragma unroll
-            for (int c = 0; c < 2; ++c)
-                acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x16f16(av[a], bv[c], acc[a][c], 0, 0, 0);
-    }
-    if (A2) {
-        for (int k = 0; k < K2; k += 16) {
-            half4 av[2], bv[2];
-#pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                av[a] = *(const half4 *)(A2 + (long)(m0 + a * 16 + r16) * K2 + k + kq);
-                bv[a] = *(const half4 *)(W2 + (long)(n0 + a * 16 + r16) * K2 + k + kq);
+                for (int q = 0; q < 4; ++q) rw[q] = *(const half4 *)(gw + k + 16 + 4 * q);
             }
+            half4 av[4], bv[4];
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < 4; ++a) av[a] = sA[(16 * a + r16) * 4 + kq];
 #pragma unroll
-                for (int c = 0; c < 2; ++c)
+            for (int c = 0; c < 4; ++c) bv[c] = sB[(64 * wave + 16 * c + r16) * 4 + kq];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
                     acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x16f16(av[a], bv[c], acc[a][c], 0, 0, 0);
         }
-    }
-    // output layout: lane holds rows 4*(lane/16)+i, column lane%16 of each 16x16 tile
+    };
+    run(A, W, K);
+    if (A2) run(A2, W2, K2);
+
+    // output layout: lane holds rows 4 (lane / 16) + i, column lane % 16 of each 16 x 16 tile
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
+        for (int c = 0; c < 4; ++c)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int row = m0 + a * 16 + kq + i, col = n0 + c * 16 + r16;
+                const long row = m0 + 16 * a + 4 * kq + i;
+                const int col = 64 * wave + 16 * c + r16;
                 const float z = acc[a][c][i] + bias[col];
-                Z[(long)row * N + col] = z;
-                if (act) Hout[(long)row * N + col] = (_Float16)(z / (1.0f + expf(-z)));
+                if (Z) Z[row * 256 + col] = z;
+                if (act) Hout[row * 256 + col] = (_Float16)(z / (1.0f + expf(-z)));
             }
 }
 
@@ -380,7 +423,8 @@ hipError_t launch_mlp_features(const MlpColParams &p, const double *b, const dou
                                long col0, long ncol, void *feat, double *scale, float *tgt, hipStream_t s)
 {
     const int grid = (int)((ncol + 63) / 64);
-    hipLaunchKernelGGL(mlp_features_kernel, dim3(grid), dim3(256), 0, s, p, b, lb, x, col0, ncol,
+    const size_t lds = sizeof(double) * 3 * (size_t)p.nz;
+    hipLaunchKernelGGL(mlp_features_kernel, dim3(grid), dim3(256), lds, s, p, b, lb, x, col0, ncol,
                        (_Float16 *)feat, scale, tgt);
     return hipGetLastError();
 }
@@ -388,24 +432,24 @@ hipError_t launch_mlp_features(const MlpColParams &p, const double *b, const dou
 hipError_t launch_mlp_guess(const MlpColParams &p, const double *b, long col0, long ncol, const float *y,
                             const double *scale, double *x0, hipStream_t s)
 {
-    hipLaunchKernelGGL(mlp_guess_kernel, dim3(grid_for(ncol * p.nz, 256)), dim3(256), 0, s, p, b, col0, ncol, y,
-                       scale, x0);
+    const int grid = (int)((ncol + 63) / 64);
+    const size_t lds = (sizeof(double) * 4 + sizeof(int)) * (size_t)p.nz;
+    hipLaunchKernelGGL(mlp_guess_kernel, dim3(grid), dim3(256), lds, s, p, b, col0, ncol, y, scale, x0);
     return hipGetLastError();
 }
 
-hipError_t mlp_forward(const MlpNet &net, int M, const void *X, hipStream_t s)
+hipError_t mlp_forward(const MlpNet &net, int M, const void *X, hipStream_t s, bool keep_z)
 {
-    const dim3 blk(256);
+    static_assert(kMlpHid == 256 && kMlpOut == 256, "gemm_rows_kernel computes 256 outputs");
+    const dim3 blk(256), grid(M / 64);
     const _Float16 *none = nullptr;
-    hipLaunchKernelGGL(gemm_f16_kernel, dim3(kMlpHid / 64, M / 64), blk, 0, s, (const _Float16 *)X,
-                       (const _Float16 *)net.wh[0], net.b[0], M, kMlpHid, kMlpIn, net.Z1, (_Float16 *)net.H1, 1,
-                       none, none, 0);
-    hipLaunchKernelGGL(gemm_f16_kernel, dim3(kMlpHid / 64, M / 64), blk, 0, s, (const _Float16 *)net.H1,
-                       (const _Float16 *)net.wh[1], net.b[1], M, kMlpHid, kMlpHid, net.Z2, (_Float16 *)net.H2, 1,
-                       none, none, 0);
-    hipLaunchKernelGGL(gemm_f16_kernel, dim3(kMlpOut / 64, M / 64), blk, 0, s, (const _Float16 *)net.H2,
-                       (const _Float16 *)net.wh[2], net.b[2], M, kMlpOut, kMlpHid, net.Y, (_Float16 *)nullptr, 0,
-                       (const _Float16 *)X, (const _Float16 *)net.wh[3], kMlpIn);
+    hipLaunchKernelGGL(gemm_rows_kernel, grid, blk, 0, s, (const _Float16 *)X, (const _Float16 *)net.wh[0], net.b[0],
+                       kMlpIn, none, none, 0, keep_z ? net.Z1 : nullptr, (_Float16 *)net.H1, 1);
+    hipLaunchKernelGGL(gemm_rows_kernel, grid, blk, 0, s, (const _Float16 *)net.H1, (const _Float16 *)net.wh[1],
+                       net.b[1], kMlpHid, none, none, 0, keep_z ? net.Z2 : nullptr, (_Float16 *)net.H2, 1);
+    hipLaunchKernelGGL(gemm_rows_kernel, grid, blk, 0, s, (const _Float16 *)net.H2, (const _Float16 *)net.wh[2],
+                       net.b[2], kMlpHid, (const _Float16 *)X, (const _Float16 *)net.wh[3], kMlpIn, net.Y,
+                       (_Float16 *)nullptr, 0);
     return hipGetLastError();
 }
 

@@ -1030,7 +1030,7 @@ nh_status mlp_guess(nh_mlp *m, nh_ctx *c, double alpha, const double *b, double 
         const int M = (int)((nb + 63) / 64 * 64);
         if (M > nb) HIPCHK(c, hipMemsetAsync(m->net.feat, 0, sizeof(uint16_t) * kMlpIn * M, c->stream));
         HIPCHK(c, launch_mlp_features(cp, b, lb, nullptr, c0, nb, m->net.feat, m->net.scale, nullptr, c->stream));
-        HIPCHK(c, mlp_forward(m->net, M, m->net.feat, c->stream));
+        HIPCHK(c, mlp_forward(m->net, M, m->net.feat, c->stream, false));
         HIPCHK(c, launch_mlp_guess(cp, b, c0, nb, m->net.Y, m->net.scale, x0, c->stream));
     }
     return NH_OK;
