@@ -30,34 +30,59 @@
 namespace nh {
 
 // ---------------------------------------------------------------- L_v on a state
-// y = L_v x on [5][U]; one thread per node, z-neighbours read along the
-// column (stride n_x n_y), coalesced along x.
-__global__ void lv_apply_kernel(HeviParams h, const double *__restrict__ x, double *__restrict__ y)
+// y = L_v x on [5][U].  One thread per lattice column walks up the levels
+// keeping the (2N+1)-level window of the two stencil inputs (rho0 w and
+// p'_L) in registers, so every value of x is read once and every value of y
+// written once, coalesced along x.  Level data and stencil rows are
+// wave-uniform.  Taps outside the column see zero inputs.
+template <int N>
+__global__ void __launch_bounds__(256) lv_apply_kernel(HeviParams h, const double *__restrict__ x,
+                                                       double *__restrict__ y)
 {
+    constexpr int NC = 2 * N + 1;
     const long nxy = (long)h.nx * h.ny;
-    const long U = nxy * h.nz;
-    const int NC = 2 * h.N + 1;
-    for (long I = blockIdx.x * (long)blockDim.x + threadIdx.x; I < U; I += (long)gridDim.x * blockDim.x) {
-        const int k = (int)(I / nxy);
+    const long col = blockIdx.x * 256L + threadIdx.x;
+    if (col >= nxy) return;
+    const int nz = h.nz;
+    const long U = nxy * nz;
+    double ta[NC], tb[NC], rr[N + 1], ww[N + 1];
+    // level kk into the window's last slot (zeros above the top)
+    auto load = [&](int kk, double &a, double &bb, double &r, double &w) {
+        a = bb = r = w = 0.0;
+        if (kk < nz) {
+            const double *L = h.lev + (long)kk * kLevW;
+            const long J = col + (long)kk * nxy;
+            r = x[J];
+            w = x[3 * U + J];
+            a = L[0] * w;
+            bb = h.gamma * L[2] * (r * L[7] + x[4 * U + J] * L[8]);
+        }
+    };
+#pragma unroll
+    for (int o = 0; o < N; ++o) { ta[o] = 0.0; tb[o] = 0.0; }
+    // levels 0 .. N-1 into window slots N .. 2N-1 (rr/ww slots 0 .. N-1)
+#pragma unroll
+    for (int j = 0; j < N; ++j) load(j, ta[N + j], tb[N + j], rr[j], ww[j]);
+    for (int k = 0; k < nz; ++k) {
+        load(k + N, ta[2 * N], tb[2 * N], rr[N], ww[N]);
         const double *L = h.lev + (long)k * kLevW;
         const double *G = h.gz + (long)k * NC;
         double d_rw = 0.0, d_pl = 0.0;
-        for (int o = -h.N; o <= h.N; ++o) {
-            const int kk = k + o;
-            if (kk < 0 || kk >= h.nz) continue;
-            const double c = G[o + h.N];
-            if (c == 0.0) continue;
-            const double *Lk = h.lev + (long)kk * kLevW;
-            const long J = I + (long)o * nxy;
-            d_rw += c * (Lk[0] * x[3 * U + J]);
-            d_pl += c * (h.gamma * Lk[2] * (x[J] * Lk[7] + x[4 * U + J] * Lk[8]));
+#pragma unroll
+        for (int o = 0; o < NC; ++o) {
+            d_rw += G[o] * ta[o];
+            d_pl += G[o] * tb[o];
         }
-        const double rp = x[I], w = x[3 * U + I];
+        const long I = col + (long)k * nxy;
         y[I] = -d_rw;
         y[U + I] = 0.0;
         y[2 * U + I] = 0.0;
-        y[3 * U + I] = (k == 0 || k == h.nz - 1) ? 0.0 : -d_pl * L[7] - h.g * rp * L[7];
-        y[4 * U + I] = -w * L[3];
+        y[3 * U + I] = (k == 0 || k == nz - 1) ? 0.0 : -d_pl * L[7] - h.g * rr[0] * L[7];
+        y[4 * U + I] = -ww[0] * L[3];
+#pragma unroll
+        for (int o = 0; o < 2 * N; ++o) { ta[o] = ta[o + 1]; tb[o] = tb[o + 1]; }
+#pragma unroll
+        for (int j = 0; j < N; ++j) { rr[j] = rr[j + 1]; ww[j] = ww[j + 1]; }
     }
 }
 
@@ -656,8 +681,17 @@ size_t gmres_lds_bytes(int nz, int N, int restart)
 
 hipError_t launch_lv_apply(const HeviParams &h, const double *x, double *y, hipStream_t s)
 {
-    const long U = (long)h.nx * h.ny * h.nz;
-    hipLaunchKernelGGL(lv_apply_kernel, dim3(grid_for(U, 256)), dim3(256), 0, s, h, x, y);
+    const long nxy = (long)h.nx * h.ny;
+    const dim3 grid((unsigned)((nxy + 255) / 256)), blk(256);
+    switch (h.N) {
+    case 1: hipLaunchKernelGGL(lv_apply_kernel<1>, grid, blk, 0, s, h, x, y); break;
+    case 2: hipLaunchKernelGGL(lv_apply_kernel<2>, grid, blk, 0, s, h, x, y); break;
+    case 3: hipLaunchKernelGGL(lv_apply_kernel<3>, grid, blk, 0, s, h, x, y); break;
+    case 4: hipLaunchKernelGGL(lv_apply_kernel<4>, grid, blk, 0, s, h, x, y); break;
+    case 5: hipLaunchKernelGGL(lv_apply_kernel<5>, grid, blk, 0, s, h, x, y); break;
+    case 6: hipLaunchKernelGGL(lv_apply_kernel<6>, grid, blk, 0, s, h, x, y); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@
 namespace nh {
 
 typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef float float4v __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------- features
@@ -193,14 +194,17 @@ __global__ void __launch_bounds__(256) mlp_guess_kernel(MlpColParams p, const do
 
 // ---------------------------------------------------------------- forward GEMM (MFMA)
 // C[M x 256] = A[M x K] W[256 x K]^T (+ A2[M x K2] W2[256 x K2]^T) + bias,
-// FP16 operands, FP32 accumulation on v_mfma_f32_16x16x16_f16.  Workgroup:
-// 64 rows and all 256 outputs, 4 waves (wave w: outputs 64 w .. 64 w + 63,
-// 4 x 4 MFMA tiles).  The K loop stages 16-wide slices of A (64 x 16) and
-// W (256 x 16) in LDS; the next slice is loaded into registers while the
-// current one is multiplied.  The optional second product (the linear bypass
-// of the last layer) accumulates into the same registers.
-// Epilogue: Z (FP32 pre-activation, skipped when null) and, when act != 0,
-// H = SiLU(Z) in FP16.  Requires M % 64 == 0, K % 16 == 0, K2 % 16 == 0.
+// FP16 operands, FP32 accumulation on v_mfma_f32_16x16x32_f16 (a 16-wide
+// K remainder on v_mfma_f32_16x16x16_f16).  Workgroup: 64 rows and all 256
+// outputs, 4 waves (wave w: outputs 64 w .. 64 w + 63, 4 x 4 MFMA tiles).
+// The K loop stages 32-wide slices of A (64 x 32) and W (256 x 32) in LDS;
+// the next slice is loaded into registers while the current one is
+// multiplied.  A lane's A and B operands hold the same 8 (or 4) k values,
+// so the pairing inside the instruction is consistent.  The optional second
+// product (the linear bypass of the last layer) accumulates into the same
+// registers.  Epilogue: Z (FP32 pre-activation, skipped when null) and, when
+// act != 0, H = SiLU(Z) in FP16.  Requires M % 64 == 0, K % 16 == 0,
+// K2 % 16 == 0.
 __global__ void __launch_bounds__(256) gemm_rows_kernel(const _Float16 *__restrict__ A,
                                                         const _Float16 *__restrict__ W,
                                                         const float *__restrict__ bias, int K,
@@ -208,11 +212,12 @@ __global__ void __launch_bounds__(256) gemm_rows_kernel(const _Float16 *__restri
                                                         const _Float16 *__restrict__ W2, int K2,
                                                         float *__restrict__ Z, _Float16 *__restrict__ Hout, int act)
 {
-    __shared__ half4 sA[64 * 4];    // [row][k quad]
-    __shared__ half4 sB[256 * 4];   // [output][k quad]
+    __shared__ half8 sA[64 * 4];    // [row][k octet]
+    __shared__ half8 sB[256 * 4];   // [output][k octet]
+    half4 *sA4 = reinterpret_cast<half4 *>(sA), *sB4 = reinterpret_cast<half4 *>(sB);
     const int t = threadIdx.x, wave = t / 64, lane = t % 64;
     const long m0 = (long)blockIdx.x * 64;
-    const int r16 = lane % 16, kq = lane / 16;
+    const int r16 = lane % 16, g = lane / 16;
     float4v acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -220,29 +225,56 @@ __global__ void __launch_bounds__(256) gemm_rows_kernel(const _Float16 *__restri
         for (int c = 0; c < 4; ++c) acc[a][c] = float4v{0.f, 0.f, 0.f, 0.f};
 
     auto run = [&](const _Float16 *Ap, const _Float16 *Wp, int KK) {
-        // thread t stages quad t % 4 of A row t / 4 and all 4 quads of W row t
-        const _Float16 *ga = Ap + (m0 + t / 4) * KK + (t % 4) * 4;
+        const int K32 = KK & ~31;
+        // thread t stages octet t % 4 of A row t / 4 and all 4 octets of W row t
+        const _Float16 *ga = Ap + (m0 + t / 4) * KK + (t % 4) * 8;
         const _Float16 *gw = Wp + (long)t * KK;
-        half4 ra = *(const half4 *)ga;
-        half4 rw[4];
+        if (K32 > 0) {
+            half8 ra = *(const half8 *)ga;
+            half8 rw[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) rw[q] = *(const half4 *)(gw + 4 * q);
-        for (int k = 0; k < KK; k += 16) {
-            __syncthreads();   // the previous slice has been read
-            sA[t] = ra;
+            for (int q = 0; q < 4; ++q) rw[q] = *(const half8 *)(gw + 8 * q);
+            for (int k = 0; k < K32; k += 32) {
+                __syncthreads();   // the previous slice has been read
+                sA[t] = ra;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) sB[t * 4 + q] = rw[q];
-            __syncthreads();
-            if (k + 16 < KK) {
-                ra = *(const half4 *)(ga + k + 16);
+                for (int q = 0; q < 4; ++q) sB[t * 4 + q] = rw[q];
+                __syncthreads();
+                if (k + 32 < K32) {
+                    ra = *(const half8 *)(ga + k + 32);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) rw[q] = *(const half4 *)(gw + k + 16 + 4 * q);
+                    for (int q = 0; q < 4; ++q) rw[q] = *(const half8 *)(gw + k + 32 + 8 * q);
+                }
+                half8 av[4], bv[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) av[a] = sA[(16 * a + r16) * 4 + g];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) bv[c] = sB[(64 * wave + 16 * c + r16) * 4 + g];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[a], bv[c], acc[a][c], 0, 0, 0);
             }
+        }
+        if (KK > K32) {
+            // 16-wide remainder: quads instead of octets
+            const _Float16 *ga4 = Ap + (m0 + t / 4) * KK + K32 + (t % 4) * 4;
+            const _Float16 *gw4 = Wp + (long)t * KK + K32;
+            const half4 ra = *(const half4 *)ga4;
+            half4 rw[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) rw[q] = *(const half4 *)(gw4 + 4 * q);
+            __syncthreads();
+            sA4[t] = ra;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sB4[t * 4 + q] = rw[q];
+            __syncthreads();
             half4 av[4], bv[4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) av[a] = sA[(16 * a + r16) * 4 + kq];
+            for (int a = 0; a < 4; ++a) av[a] = sA4[(16 * a + r16) * 4 + g];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) bv[c] = sB[(64 * wave + 16 * c + r16) * 4 + kq];
+            for (int c = 0; c < 4; ++c) bv[c] = sB4[(64 * wave + 16 * c + r16) * 4 + g];
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -260,7 +292,7 @@ __global__ void __launch_bounds__(256) gemm_rows_kernel(const _Float16 *__restri
         for (int c = 0; c < 4; ++c)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const long row = m0 + 16 * a + 4 * kq + i;
+                const long row = m0 + 16 * a + 4 * g + i;
                 const int col = 64 * wave + 16 * c + r16;
                 const float z = acc[a][c][i] + bias[col];
                 if (Z) Z[row * 256 + col] = z;
