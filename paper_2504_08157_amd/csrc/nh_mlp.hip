@@ -52,21 +52,22 @@ __device__ __forceinline__ double dim_factor(const MlpColParams &p, int f, int k
     return sqrt(p.gamma * L[2] / L[0]);
 }
 
-// 64 columns per workgroup of 256 threads: lane = column (every load reads
-// 64 consecutive columns of one level, coalesced), the 4 waves split the
+// 64 columns per workgroup of 512 threads: lane = column (every load reads
+// 64 consecutive columns of one level, coalesced), the 8 waves split the
 // levels of the scale sum and the canonical levels of the resampling; the
 // features of the 64 columns are assembled in LDS and written out as whole
 // rows.  The interpolation intervals of the canonical levels and the
 // inverse dimension factors of every level are tabulated in LDS first
 // (dynamic LDS: 3 n_z doubles).
-__global__ void __launch_bounds__(256) mlp_features_kernel(MlpColParams p, const double *__restrict__ b,
+__global__ void __launch_bounds__(512) mlp_features_kernel(MlpColParams p, const double *__restrict__ b,
                                                            const double *__restrict__ lb,
                                                            const double *__restrict__ x, long col0,
                                                            long ncol, _Float16 *__restrict__ feat,
                                                            double *__restrict__ scale, float *__restrict__ tgt)
 {
+    constexpr int NWV = 8;   // waves
     __shared__ _Float16 sf[64][kMlpIn];
-    __shared__ double spart[4][64];
+    __shared__ double spart[NWV][64];
     __shared__ int sk0[kMlpNC];
     __shared__ double st[kMlpNC];
     extern __shared__ double sdinv[];   // [3][n_z]
@@ -76,8 +77,9 @@ __global__ void __launch_bounds__(256) mlp_features_kernel(MlpColParams p, const
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int fld[3] = {0, 3, 4};
     const double H = p.z[nz - 1] - p.z[0];
-    for (int i = threadIdx.x; i < 3 * nz; i += 256) sdinv[i] = 1.0 / dim_factor(p, i / nz, i % nz);
-    for (int c = threadIdx.x; c < kMlpNC; c += 256) canon_interp(p.z, nz, p.z[0] + H * p.zc[c], &sk0[c], &st[c]);
+    for (int i = threadIdx.x; i < 3 * nz; i += 64 * NWV) sdinv[i] = 1.0 / dim_factor(p, i / nz, i % nz);
+    for (int c = threadIdx.x; c < kMlpNC; c += 64 * NWV)
+        canon_interp(p.z, nz, p.z[0] + H * p.zc[c], &sk0[c], &st[c]);
     __syncthreads();
     const long r0 = (long)blockIdx.x * 64;
     const long r = r0 + lane;
@@ -86,8 +88,9 @@ __global__ void __launch_bounds__(256) mlp_features_kernel(MlpColParams p, const
     // s = RMS over the column of the dimensionless b and alpha L_v b
     double a = 0.0;
 #pragma unroll 4
-    for (int k = q; k < nz; k += 4) {
+    for (int k = q; k < nz; k += NWV) {
         const long I = col + (long)k * nxy;
+#pragma unroll
         for (int f = 0; f < 3; ++f) {
             const double d = sdinv[f * nz + k];
             const double v = b[fld[f] * U + I] * d;
@@ -97,10 +100,15 @@ __global__ void __launch_bounds__(256) mlp_features_kernel(MlpColParams p, const
     }
     spart[q][lane] = a;
     __syncthreads();
-    const double s = sqrt((spart[0][lane] + spart[1][lane] + spart[2][lane] + spart[3][lane]) / (3.0 * nz)) + 1e-300;
-    for (int c = q; c < kMlpNC; c += 4) {
+    double ssum = 0.0;
+#pragma unroll
+    for (int w = 0; w < NWV; ++w) ssum += spart[w][lane];
+    const double s = sqrt(ssum / (3.0 * nz)) + 1e-300;
+#pragma unroll 3
+    for (int c = q; c < kMlpNC; c += NWV) {
         const int k0 = sk0[c];
         const double t = st[c];
+#pragma unroll
         for (int f = 0; f < 3; ++f) {
             const long I0 = fld[f] * U + col + (long)k0 * nxy, I1 = I0 + nxy;
             const double d0 = sdinv[f * nz + k0], d1 = sdinv[f * nz + k0 + 1];
@@ -122,24 +130,24 @@ __global__ void __launch_bounds__(256) mlp_features_kernel(MlpColParams p, const
         for (int i = 2 * kMlpNF + 4; i < kMlpIn; ++i) sf[lane][i] = (_Float16)0.0f;
         if (ok) scale[r] = s;
     } else if (tgt && ok) {
-        for (int i = kMlpNF + q - 1; i < kMlpOut; i += 3) tgt[r * kMlpOut + i] = 0.0f;
+        for (int i = kMlpNF + q - 1; i < kMlpOut; i += NWV - 1) tgt[r * kMlpOut + i] = 0.0f;
     }
     __syncthreads();
     // rows of 400 halves = 200 words; threads write consecutive words
     const long nrow = ncol - r0 < 64 ? ncol - r0 : 64;
     const uint32_t *src = reinterpret_cast<const uint32_t *>(&sf[0][0]);
     uint32_t *dst = reinterpret_cast<uint32_t *>(feat + r0 * kMlpIn);
-    for (long i = threadIdx.x; i < nrow * (kMlpIn / 2); i += 256) dst[i] = src[i];
+    for (long i = threadIdx.x; i < nrow * (kMlpIn / 2); i += 64 * NWV) dst[i] = src[i];
 }
 
 // x0 = b + D s (y resampled from the canonical to the lattice levels); the
 // w correction is zero on the bottom and top levels, and a non-finite
-// prediction falls back to x0 = b.  64 columns per workgroup of 256
+// prediction falls back to x0 = b.  64 columns per workgroup of 512
 // threads: the used outputs of the 64 rows of y are staged in LDS, lane =
-// column (b reads and x0 writes coalesced), the 4 waves split the levels.
+// column (b reads and x0 writes coalesced), the 8 waves split the levels.
 // Per-level tables (dynamic LDS: 4 n_z doubles and n_z ints): the canonical
 // interval and weight of each lattice level and its dimension factors.
-__global__ void __launch_bounds__(256) mlp_guess_kernel(MlpColParams p, const double *__restrict__ b, long col0,
+__global__ void __launch_bounds__(512) mlp_guess_kernel(MlpColParams p, const double *__restrict__ b, long col0,
                                                         long ncol, const float *__restrict__ y,
                                                         const double *__restrict__ scale, double *__restrict__ x0)
 {
@@ -153,7 +161,7 @@ __global__ void __launch_bounds__(256) mlp_guess_kernel(MlpColParams p, const do
     const long U = nxy * nz;
     const int fld[3] = {0, 3, 4};
     const double H = p.z[nz - 1] - p.z[0];
-    for (int k = threadIdx.x; k < nz; k += 256) {
+    for (int k = threadIdx.x; k < nz; k += 512) {
         const double zh = (p.z[k] - p.z[0]) / H;
         int lo = 0, hi = kMlpNC - 1;
         while (hi - lo > 1) {
@@ -169,7 +177,7 @@ __global__ void __launch_bounds__(256) mlp_guess_kernel(MlpColParams p, const do
     }
     const long r0 = (long)blockIdx.x * 64;
     const long nrow = ncol - r0 < 64 ? ncol - r0 : 64;
-    for (long i = threadIdx.x; i < nrow * kMlpNF; i += 256) {
+    for (long i = threadIdx.x; i < nrow * kMlpNF; i += 512) {
         const long rr = i / kMlpNF;
         const int c = (int)(i - rr * kMlpNF);
         sy[rr][c] = y[(r0 + rr) * kMlpOut + c];
@@ -179,10 +187,12 @@ __global__ void __launch_bounds__(256) mlp_guess_kernel(MlpColParams p, const do
     if (lane >= nrow) return;
     const long r = r0 + lane;
     const double s = scale[r];
-    for (int k = q; k < nz; k += 4) {
+#pragma unroll 2
+    for (int k = q; k < nz; k += 8) {
         const long I = col0 + r + (long)k * nxy;
         const int lo = lg[k];
         const double t = tg[k];
+#pragma unroll
         for (int f = 0; f < 3; ++f) {
             const float *yr = &sy[lane][f * kMlpNC];
             double d = (1.0 - t) * yr[lo] + t * yr[lo + 1];
@@ -456,7 +466,7 @@ hipError_t launch_mlp_features(const MlpColParams &p, const double *b, const dou
 {
     const int grid = (int)((ncol + 63) / 64);
     const size_t lds = sizeof(double) * 3 * (size_t)p.nz;
-    hipLaunchKernelGGL(mlp_features_kernel, dim3(grid), dim3(256), lds, s, p, b, lb, x, col0, ncol,
+    hipLaunchKernelGGL(mlp_features_kernel, dim3(grid), dim3(512), lds, s, p, b, lb, x, col0, ncol,
                        (_Float16 *)feat, scale, tgt);
     return hipGetLastError();
 }
@@ -466,7 +476,7 @@ hipError_t launch_mlp_guess(const MlpColParams &p, const double *b, long col0, l
 {
     const int grid = (int)((ncol + 63) / 64);
     const size_t lds = (sizeof(double) * 4 + sizeof(int)) * (size_t)p.nz;
-    hipLaunchKernelGGL(mlp_guess_kernel, dim3(grid), dim3(256), lds, s, p, b, col0, ncol, y, scale, x0);
+    hipLaunchKernelGGL(mlp_guess_kernel, dim3(grid), dim3(512), lds, s, p, b, col0, ncol, y, scale, x0);
     return hipGetLastError();
 }
 
