@@ -301,6 +301,17 @@ nh_status nh_mlp_samples(nh_mlp *m, nh_ctx *ctx, double alpha, const double *dev
                          int64_t col0, int64_t ncol, void *dev_feat, double *dev_scale, float *dev_tgt,
                          double *dev_tmp);
 
+/* The initial guess x0 of (I - alpha L_v) x = b in every column of ctx, as
+   used by nh_hevi_step: features of b and alpha L_v b, the network, and
+   x0 = b + D s (output resampled to the lattice levels), the w correction
+   zero on the walls and a non-finite prediction replaced by x0 = b.
+   dev_b device [5][U] (fields rho', w, theta' are used), dev_tmp device
+   [5][U] scratch (receives L_v b in fields 0, 3, 4), dev_x0 device [3][U]
+   (rho', w, theta').  Asynchronous on the context's stream.  NH_EINVAL for
+   null arguments, alpha < 0 or non-finite, or a context without reference
+   state. */
+nh_status nh_mlp_guess(nh_mlp *m, nh_ctx *ctx, double alpha, const double *dev_b, double *dev_tmp,
+                       double *dev_x0);
 nh_status nh_mlp_last_error(const nh_mlp *m, char *buf, size_t n);
 nh_status nh_mlp_destroy(nh_mlp *m);
 

@@ -34,10 +34,11 @@ namespace nh {
 // keeping the (2N+1)-level window of the two stencil inputs (rho0 w and
 // p'_L) in registers, so every value of x is read once and every value of y
 // written once, coalesced along x.  Level data and stencil rows are
-// wave-uniform.  Taps outside the column see zero inputs.
+// wave-uniform.  Taps outside the column see zero inputs.  With uv false
+// the (zero) u and v rows are not written.
 template <int N>
 __global__ void __launch_bounds__(256) lv_apply_kernel(HeviParams h, const double *__restrict__ x,
-                                                       double *__restrict__ y)
+                                                       double *__restrict__ y, bool uv)
 {
     constexpr int NC = 2 * N + 1;
     const long nxy = (long)h.nx * h.ny;
@@ -75,8 +76,10 @@ __global__ void __launch_bounds__(256) lv_apply_kernel(HeviParams h, const doubl
         }
         const long I = col + (long)k * nxy;
         y[I] = -d_rw;
-        y[U + I] = 0.0;
-        y[2 * U + I] = 0.0;
+        if (uv) {
+            y[U + I] = 0.0;
+            y[2 * U + I] = 0.0;
+        }
         y[3 * U + I] = (k == 0 || k == nz - 1) ? 0.0 : -d_pl * L[7] - h.g * rr[0] * L[7];
         y[4 * U + I] = -ww[0] * L[3];
 #pragma unroll
@@ -679,17 +682,17 @@ size_t gmres_lds_bytes(int nz, int N, int restart)
     return n * sizeof(double);
 }
 
-hipError_t launch_lv_apply(const HeviParams &h, const double *x, double *y, hipStream_t s)
+hipError_t launch_lv_apply(const HeviParams &h, const double *x, double *y, hipStream_t s, bool uv)
 {
     const long nxy = (long)h.nx * h.ny;
     const dim3 grid((unsigned)((nxy + 255) / 256)), blk(256);
     switch (h.N) {
-    case 1: hipLaunchKernelGGL(lv_apply_kernel<1>, grid, blk, 0, s, h, x, y); break;
-    case 2: hipLaunchKernelGGL(lv_apply_kernel<2>, grid, blk, 0, s, h, x, y); break;
-    case 3: hipLaunchKernelGGL(lv_apply_kernel<3>, grid, blk, 0, s, h, x, y); break;
-    case 4: hipLaunchKernelGGL(lv_apply_kernel<4>, grid, blk, 0, s, h, x, y); break;
-    case 5: hipLaunchKernelGGL(lv_apply_kernel<5>, grid, blk, 0, s, h, x, y); break;
-    case 6: hipLaunchKernelGGL(lv_apply_kernel<6>, grid, blk, 0, s, h, x, y); break;
+    case 1: hipLaunchKernelGGL(lv_apply_kernel<1>, grid, blk, 0, s, h, x, y, uv); break;
+    case 2: hipLaunchKernelGGL(lv_apply_kernel<2>, grid, blk, 0, s, h, x, y, uv); break;
+    case 3: hipLaunchKernelGGL(lv_apply_kernel<3>, grid, blk, 0, s, h, x, y, uv); break;
+    case 4: hipLaunchKernelGGL(lv_apply_kernel<4>, grid, blk, 0, s, h, x, y, uv); break;
+    case 5: hipLaunchKernelGGL(lv_apply_kernel<5>, grid, blk, 0, s, h, x, y, uv); break;
+    case 6: hipLaunchKernelGGL(lv_apply_kernel<6>, grid, blk, 0, s, h, x, y, uv); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -82,7 +82,8 @@ struct LinComb {
 };
 
 size_t gmres_lds_bytes(int nz, int N, int restart);
-hipError_t launch_lv_apply(const HeviParams &h, const double *x, double *y, hipStream_t s);
+// y = L_v x on [5][U]; with uv false the u and v rows of y are left untouched
+hipError_t launch_lv_apply(const HeviParams &h, const double *x, double *y, hipStream_t s, bool uv = true);
 hipError_t launch_axpy_multi(long n, const double *base, int nsrc, const LinComb &lc, double *out,
                              hipStream_t s);
 hipError_t launch_gmres(const HeviParams &h, const GmresArgs &g, hipStream_t s);
@@ -120,6 +121,15 @@ struct MlpNet {
     double *scale;                 // [max_batch] column scales
 };
 
+// FP16 weights and FP32 biases of the network, by value for kernels
+struct MlpWeights {
+    const _Float16 *W[4];   // W1 [256][400], W2 [256][256], W3 [256][256], bypass S [256][400]
+    const float *bias[3];
+};
+
+// x0 of columns col0 .. col0 + ncol - 1 from b and L_v b in one kernel
+hipError_t launch_mlp_infer(const MlpColParams &p, const MlpNet &net, const double *b, const double *lb, long col0,
+                            long ncol, double *x0, hipStream_t s);
 hipError_t launch_mlp_features(const MlpColParams &p, const double *b, const double *lb, const double *x,
                                long col0, long ncol, void *feat, double *scale, float *tgt, hipStream_t s);
 hipError_t launch_mlp_guess(const MlpColParams &p, const double *b, long col0, long ncol, const float *y,

@@ -202,19 +202,34 @@ __global__ void __launch_bounds__(512) mlp_guess_kernel(MlpColParams p, const do
     }
 }
 
+// acc += A B^T over one 32-wide k slice held as 8 halves per lane, as two
+// v_mfma_f32_16x16x16_f16 (halves 0-3, then 4-7 of both operands: the same
+// k values pair up).  The single-instruction v_mfma_f32_16x16x32_f16 form
+// gave run-to-run different results in the fused inference kernel (whose K
+// loop reloads the operand registers from LDS right behind the MFMAs), so
+// it is not used.
+__device__ __forceinline__ float4v mfma_k32(const half8 &a, const half8 &b, float4v c)
+{
+    const half4 al = {a[0], a[1], a[2], a[3]}, ah = {a[4], a[5], a[6], a[7]};
+    const half4 bl = {b[0], b[1], b[2], b[3]}, bh = {b[4], b[5], b[6], b[7]};
+    c = __builtin_amdgcn_mfma_f32_16x16x16f16(al, bl, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bh, c, 0, 0, 0);
+}
+
 // ---------------------------------------------------------------- forward GEMM (MFMA)
 // C[M x 256] = A[M x K] W[256 x K]^T (+ A2[M x K2] W2[256 x K2]^T) + bias,
-// FP16 operands, FP32 accumulation on v_mfma_f32_16x16x32_f16 (a 16-wide
-// K remainder on v_mfma_f32_16x16x16_f16).  Workgroup: 64 rows and all 256
+// FP16 operands, FP32 accumulation on v_mfma_f32_16x16x16_f16 (two per
+// 32-wide K slice, one for a 16-wide remainder).  Workgroup: 64 rows and all 256
 // outputs, 4 waves (wave w: outputs 64 w .. 64 w + 63, 4 x 4 MFMA tiles).
-// The K loop stages 32-wide slices of A (64 x 32) and W (256 x 32) in LDS;
-// the next slice is loaded into registers while the current one is
-// multiplied.  A lane's A and B operands hold the same 8 (or 4) k values,
-// so the pairing inside the instruction is consistent.  The optional second
-// product (the linear bypass of the last layer) accumulates into the same
-// registers.  Epilogue: Z (FP32 pre-activation, skipped when null) and, when
-// act != 0, H = SiLU(Z) in FP16.  Requires M % 64 == 0, K % 16 == 0,
-// K2 % 16 == 0.
+// The K loop stages 32-wide slices of A (64 x 32, shared by the 4 waves) in
+// LDS; each wave loads its own W fragments straight from memory (W is a
+// few hundred KB and stays in L2).  The next slice of both is loaded into
+// registers while the current one is multiplied.  A lane's A and B operands
+// hold the same 8 (or 4) k values, so the pairing inside the instruction is
+// consistent.  The optional second product (the linear bypass of the last
+// layer) accumulates into the same registers.  Epilogue: Z (FP32
+// pre-activation, skipped when null) and, when act != 0, H = SiLU(Z) in
+// FP16.  Requires M % 64 == 0, K % 16 == 0, K2 % 16 == 0.
 __global__ void __launch_bounds__(256) gemm_rows_kernel(const _Float16 *__restrict__ A,
                                                         const _Float16 *__restrict__ W,
                                                         const float *__restrict__ bias, int K,
@@ -223,8 +238,7 @@ __global__ void __launch_bounds__(256) gemm_rows_kernel(const _Float16 *__restri
                                                         float *__restrict__ Z, _Float16 *__restrict__ Hout, int act)
 {
     __shared__ half8 sA[64 * 4];    // [row][k octet]
-    __shared__ half8 sB[256 * 4];   // [output][k octet]
-    half4 *sA4 = reinterpret_cast<half4 *>(sA), *sB4 = reinterpret_cast<half4 *>(sB);
+    half4 *sA4 = reinterpret_cast<half4 *>(sA);
     const int t = threadIdx.x, wave = t / 64, lane = t % 64;
     const long m0 = (long)blockIdx.x * 64;
     const int r16 = lane % 16, g = lane / 16;
@@ -236,55 +250,51 @@ __global__ void __launch_bounds__(256) gemm_rows_kernel(const _Float16 *__restri
 
     auto run = [&](const _Float16 *Ap, const _Float16 *Wp, int KK) {
         const int K32 = KK & ~31;
-        // thread t stages octet t % 4 of A row t / 4 and all 4 octets of W row t
+        // thread t stages octet t % 4 of A row t / 4; lane (r16, g) of wave w
+        // reads k octet g of W rows 64 w + 16 c + r16
         const _Float16 *ga = Ap + (m0 + t / 4) * KK + (t % 4) * 8;
-        const _Float16 *gw = Wp + (long)t * KK;
+        const _Float16 *gw = Wp + (long)(64 * wave + r16) * KK + 8 * g;
         if (K32 > 0) {
             half8 ra = *(const half8 *)ga;
-            half8 rw[4];
+            half8 bv[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) rw[q] = *(const half8 *)(gw + 8 * q);
+            for (int c = 0; c < 4; ++c) bv[c] = *(const half8 *)(gw + (long)16 * c * KK);
             for (int k = 0; k < K32; k += 32) {
                 __syncthreads();   // the previous slice has been read
                 sA[t] = ra;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) sB[t * 4 + q] = rw[q];
                 __syncthreads();
+                half8 bn[4];
                 if (k + 32 < K32) {
                     ra = *(const half8 *)(ga + k + 32);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) rw[q] = *(const half8 *)(gw + k + 32 + 8 * q);
+                    for (int c = 0; c < 4; ++c) bn[c] = *(const half8 *)(gw + (long)16 * c * KK + k + 32);
                 }
-                half8 av[4], bv[4];
+                half8 av[4];
 #pragma unroll
                 for (int a = 0; a < 4; ++a) av[a] = sA[(16 * a + r16) * 4 + g];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) bv[c] = sB[(64 * wave + 16 * c + r16) * 4 + g];
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
                     for (int c = 0; c < 4; ++c)
-                        acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[a], bv[c], acc[a][c], 0, 0, 0);
+                        acc[a][c] = mfma_k32(av[a], bv[c], acc[a][c]);
+                if (k + 32 < K32)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) bv[c] = bn[c];
             }
         }
         if (KK > K32) {
             // 16-wide remainder: quads instead of octets
-            const _Float16 *ga4 = Ap + (m0 + t / 4) * KK + K32 + (t % 4) * 4;
-            const _Float16 *gw4 = Wp + (long)t * KK + K32;
-            const half4 ra = *(const half4 *)ga4;
-            half4 rw[4];
+            const half4 ra = *(const half4 *)(Ap + (m0 + t / 4) * KK + K32 + (t % 4) * 4);
+            const _Float16 *gw4 = Wp + (long)(64 * wave + r16) * KK + K32 + 4 * g;
+            half4 bv[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) rw[q] = *(const half4 *)(gw4 + 4 * q);
+            for (int c = 0; c < 4; ++c) bv[c] = *(const half4 *)(gw4 + (long)16 * c * KK);
             __syncthreads();
             sA4[t] = ra;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) sB4[t * 4 + q] = rw[q];
             __syncthreads();
-            half4 av[4], bv[4];
+            half4 av[4];
 #pragma unroll
             for (int a = 0; a < 4; ++a) av[a] = sA4[(16 * a + r16) * 4 + g];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) bv[c] = sB4[(64 * wave + 16 * c + r16) * 4 + g];
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -308,6 +318,220 @@ __global__ void __launch_bounds__(256) gemm_rows_kernel(const _Float16 *__restri
                 if (Z) Z[row * 256 + col] = z;
                 if (act) Hout[row * 256 + col] = (_Float16)(z / (1.0f + expf(-z)));
             }
+}
+
+// ---------------------------------------------------------------- fused inference
+// The guess x0 of 64 columns per workgroup of 512 threads (8 waves) with
+// everything between the right-hand side and x0 kept in LDS: the features
+// of the 64 columns (computed as in mlp_features_kernel), the three layers
+// on v_mfma_f32_16x16x16_f16 with the A operands read from LDS (wave w:
+// outputs 32 w .. 32 w + 31 of the 64 rows; W fragments from memory, where
+// they stay L2 resident), the hidden activations in LDS, and the
+// resampling of the output to the lattice levels (as in mlp_guess_kernel).
+// The MFMA operands and the order of accumulation are those of
+// gemm_rows_kernel, so the guess equals that of the separate kernels.
+constexpr int kLdF = kMlpIn + 8;    // LDS row of the features (halves), padded
+constexpr int kLdH = kMlpHid + 8;   // LDS row of the activations (halves), padded
+static_assert(64 * (kMlpNF + 1) * 4 <= 64 * kLdF * 2, "output rows fit in the feature rows");
+
+__global__ void __launch_bounds__(512) mlp_infer_kernel(MlpColParams p, MlpWeights wt,
+                                                        const double *__restrict__ b,
+                                                        const double *__restrict__ lb, long col0, long ncol,
+                                                        double *__restrict__ x0)
+{
+    constexpr int NWV = 8;
+    __shared__ __align__(16) _Float16 sf[64 * kLdF];
+    __shared__ __align__(16) _Float16 sh[64 * kLdH];
+    __shared__ double spart[NWV][64];
+    __shared__ double sscale[64];
+    __shared__ int sk0[kMlpNC];
+    __shared__ double st[kMlpNC];
+    extern __shared__ double stab[];
+    const int nz = p.nz;
+    double *sdinv = stab;              // [3][n_z] inverse dimension factors
+    double *dg = stab + 3 * nz;        // [3][n_z] dimension factors
+    double *tg = stab + 6 * nz;        // [n_z] canonical weight of each lattice level
+    int *lg = (int *)(stab + 7 * nz);  // [n_z] canonical interval of each lattice level
+    float *sy = reinterpret_cast<float *>(sf);   // [64][kMlpNF + 1] outputs, after the last layer
+
+    const long nxy = (long)p.nx * p.ny;
+    const long U = nxy * nz;
+    const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
+    const int fld[3] = {0, 3, 4};
+    const double H = p.z[nz - 1] - p.z[0];
+
+    // ---- tables
+    for (int i = tid; i < 3 * nz; i += 64 * NWV) {
+        sdinv[i] = 1.0 / dim_factor(p, i / nz, i % nz);
+        dg[i] = dim_factor(p, i / nz, i % nz);
+    }
+    for (int c = tid; c < kMlpNC; c += 64 * NWV) canon_interp(p.z, nz, p.z[0] + H * p.zc[c], &sk0[c], &st[c]);
+    for (int k = tid; k < nz; k += 64 * NWV) {
+        const double zh = (p.z[k] - p.z[0]) / H;
+        int lo = 0, hi = kMlpNC - 1;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (p.zc[mid] <= zh) lo = mid; else hi = mid;
+        }
+        double t = (zh - p.zc[lo]) / (p.zc[lo + 1] - p.zc[lo]);
+        if (t < 0.0) t = 0.0;
+        if (t > 1.0) t = 1.0;
+        lg[k] = lo;
+        tg[k] = t;
+    }
+    __syncthreads();
+
+    // ---- features (lane = column, the waves split the levels)
+    const long r0 = (long)blockIdx.x * 64;
+    const long nrow = ncol - r0 < 64 ? ncol - r0 : 64;
+    const long r = r0 + lane;
+    const long col = col0 + (lane < nrow ? r : r0);
+    {
+        double a = 0.0;
+#pragma unroll 4
+        for (int k = q; k < nz; k += NWV) {
+            const long I = col + (long)k * nxy;
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                const double d = sdinv[f * nz + k];
+                const double v = b[fld[f] * U + I] * d;
+                const double l = p.alpha * lb[fld[f] * U + I] * d;
+                a += v * v + l * l;
+            }
+        }
+        spart[q][lane] = a;
+    }
+    __syncthreads();
+    double ssum = 0.0;
+#pragma unroll
+    for (int w = 0; w < NWV; ++w) ssum += spart[w][lane];
+    const double s = sqrt(ssum / (3.0 * nz)) + 1e-300;
+    _Float16 *fr = sf + lane * kLdF;
+#pragma unroll 3
+    for (int c = q; c < kMlpNC; c += NWV) {
+        const int k0 = sk0[c];
+        const double t = st[c];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const long I0 = fld[f] * U + col + (long)k0 * nxy, I1 = I0 + nxy;
+            const double d0 = sdinv[f * nz + k0], d1 = sdinv[f * nz + k0 + 1];
+            const double vb = (1.0 - t) * (b[I0] * d0) + t * (b[I1] * d1);
+            const double vl = (1.0 - t) * (p.alpha * lb[I0] * d0) + t * (p.alpha * lb[I1] * d1);
+            fr[f * kMlpNC + c] = (_Float16)(vb / s);
+            fr[kMlpNF + f * kMlpNC + c] = (_Float16)(vl / s);
+        }
+    }
+    if (q == 0) {
+        fr[2 * kMlpNF] = (_Float16)(log10(s) / 10.0);
+        fr[2 * kMlpNF + 1] = (_Float16)(p.alpha / 10.0);
+        fr[2 * kMlpNF + 2] = (_Float16)(100.0 * p.alpha * dim_factor(p, 1, 0) / H);
+        fr[2 * kMlpNF + 3] = (_Float16)(log10(H) / 5.0);
+        for (int i = 2 * kMlpNF + 4; i < kMlpIn; ++i) fr[i] = (_Float16)0.0f;
+        sscale[lane] = s;
+    }
+    __syncthreads();
+
+    // ---- layers
+    const int wave = q, r16 = lane % 16, g = lane / 16;
+    float4v acc[4][2];
+    auto zero = [&]() {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) acc[a][c] = float4v{0.f, 0.f, 0.f, 0.f};
+    };
+    // acc += S[64 x KK] (LDS, row stride ld) Wp[32 w .. 32 w + 31][KK]^T
+    auto mma = [&](const _Float16 *S, int ld, const _Float16 *Wp, int KK) {
+        const int K32 = KK & ~31;
+        const _Float16 *gw = Wp + (long)(32 * wave + r16) * KK + 8 * g;
+        if (K32 > 0) {
+            half8 bv[2], bn[2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) bv[c] = *(const half8 *)(gw + (long)16 * c * KK);
+            for (int k = 0; k < K32; k += 32) {
+                if (k + 32 < K32)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) bn[c] = *(const half8 *)(gw + (long)16 * c * KK + k + 32);
+                half8 av[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) av[a] = *(const half8 *)(S + (16 * a + r16) * ld + k + 8 * g);
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+                        acc[a][c] = mfma_k32(av[a], bv[c], acc[a][c]);
+                if (k + 32 < K32)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) bv[c] = bn[c];
+            }
+        }
+        if (KK > K32) {
+            const _Float16 *gw4 = Wp + (long)(32 * wave + r16) * KK + K32 + 4 * g;
+            half4 bv[2], av[4];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) bv[c] = *(const half4 *)(gw4 + (long)16 * c * KK);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] = *(const half4 *)(S + (16 * a + r16) * ld + K32 + 4 * g);
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x16f16(av[a], bv[c], acc[a][c], 0, 0, 0);
+        }
+    };
+    // H = SiLU(acc + bias) into the activation rows (lane: rows 4 g + i, column r16 of each tile)
+    auto store_h = [&](const float *bias) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = 16 * a + 4 * g + i, cl = 32 * wave + 16 * c + r16;
+                    const float z = acc[a][c][i] + bias[cl];
+                    sh[row * kLdH + cl] = (_Float16)(z / (1.0f + expf(-z)));
+                }
+    };
+    zero();
+    mma(sf, kLdF, wt.W[0], kMlpIn);
+    store_h(wt.bias[0]);
+    __syncthreads();
+    zero();
+    mma(sh, kLdH, wt.W[1], kMlpHid);
+    __syncthreads();   // every wave has read H1
+    store_h(wt.bias[1]);
+    __syncthreads();
+    zero();
+    mma(sh, kLdH, wt.W[2], kMlpHid);
+    mma(sf, kLdF, wt.W[3], kMlpIn);
+    __syncthreads();   // every wave has read the features and H2
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * a + 4 * g + i, cl = 32 * wave + 16 * c + r16;
+                if (cl < kMlpNF) sy[row * (kMlpNF + 1) + cl] = acc[a][c][i] + wt.bias[2][cl];
+            }
+    __syncthreads();
+
+    // ---- resampling to the lattice levels (lane = column, the waves split the levels)
+    if (lane >= nrow) return;
+    const double sc = sscale[lane];
+#pragma unroll 2
+    for (int k = q; k < nz; k += NWV) {
+        const long I = col0 + r + (long)k * nxy;
+        const int lo = lg[k];
+        const double t = tg[k];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const float *yr = sy + lane * (kMlpNF + 1) + f * kMlpNC;
+            double d = (1.0 - t) * yr[lo] + t * yr[lo + 1];
+            if (!isfinite(d) || (f == 1 && (k == 0 || k == nz - 1))) d = 0.0;
+            x0[f * U + I] = b[fld[f] * U + I] + dg[f * nz + k] * sc * d;
+        }
+    }
 }
 
 // ---------------------------------------------------------------- backward (FP32)
@@ -477,6 +701,18 @@ hipError_t launch_mlp_guess(const MlpColParams &p, const double *b, long col0, l
     const int grid = (int)((ncol + 63) / 64);
     const size_t lds = (sizeof(double) * 4 + sizeof(int)) * (size_t)p.nz;
     hipLaunchKernelGGL(mlp_guess_kernel, dim3(grid), dim3(512), lds, s, p, b, col0, ncol, y, scale, x0);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_infer(const MlpColParams &p, const MlpNet &net, const double *b, const double *lb, long col0,
+                            long ncol, double *x0, hipStream_t s)
+{
+    MlpWeights wt;
+    for (int i = 0; i < 4; ++i) wt.W[i] = (const _Float16 *)net.wh[i];
+    for (int i = 0; i < 3; ++i) wt.bias[i] = net.b[i];
+    const int grid = (int)((ncol + 63) / 64);
+    const size_t lds = (sizeof(double) * 7 + sizeof(int)) * (size_t)p.nz;
+    hipLaunchKernelGGL(mlp_infer_kernel, dim3(grid), dim3(512), lds, s, p, wt, b, lb, col0, ncol, x0);
     return hipGetLastError();
 }
 

@@ -1022,17 +1022,10 @@ MlpColParams mlp_col_params(const nh_ctx *c, double alpha)
 nh_status mlp_guess(nh_mlp *m, nh_ctx *c, double alpha, const double *b, double *lb, double *x0)
 {
     if (m->sticky) return fail(c, NH_ESTATE, "MLP in error state");
-    HIPCHK(c, launch_lv_apply(hevi_params(c), b, lb, c->stream));
+    HIPCHK(c, launch_lv_apply(hevi_params(c), b, lb, c->stream, false));
     const MlpColParams cp = mlp_col_params(c, alpha);
     const long ncol = (long)c->n[0] * c->n[1];
-    for (long c0 = 0; c0 < ncol; c0 += m->max_batch) {
-        const long nb = std::min<long>(m->max_batch, ncol - c0);
-        const int M = (int)((nb + 63) / 64 * 64);
-        if (M > nb) HIPCHK(c, hipMemsetAsync(m->net.feat, 0, sizeof(uint16_t) * kMlpIn * M, c->stream));
-        HIPCHK(c, launch_mlp_features(cp, b, lb, nullptr, c0, nb, m->net.feat, m->net.scale, nullptr, c->stream));
-        HIPCHK(c, mlp_forward(m->net, M, m->net.feat, c->stream, false));
-        HIPCHK(c, launch_mlp_guess(cp, b, c0, nb, m->net.Y, m->net.scale, x0, c->stream));
-    }
+    HIPCHK(c, launch_mlp_infer(cp, m->net, b, lb, 0, ncol, x0, c->stream));
     return NH_OK;
 }
 
@@ -1183,10 +1176,21 @@ nh_status nh_mlp_samples(nh_mlp *m, nh_ctx *c, double alpha, const double *dev_b
     const long nc = (long)c->n[0] * c->n[1];
     if (col0 < 0 || ncol <= 0 || col0 + ncol > nc) return fail(c, NH_EINVAL, "column range outside the lattice");
     if (!c->have_ref) return fail(c, NH_EINVAL, "reference state not set");
-    HIPCHK(c, launch_lv_apply(hevi_params(c), dev_b, dev_tmp, c->stream));
+    HIPCHK(c, launch_lv_apply(hevi_params(c), dev_b, dev_tmp, c->stream, false));
     const MlpColParams cp = mlp_col_params(c, alpha);
     HIPCHK(c, launch_mlp_features(cp, dev_b, dev_tmp, dev_x, col0, ncol, dev_feat, dev_scale, dev_tgt, c->stream));
     return NH_OK;
+}
+
+nh_status nh_mlp_guess(nh_mlp *m, nh_ctx *c, double alpha, const double *dev_b, double *dev_tmp, double *dev_x0)
+{
+    nh_status st = guard(c);
+    if (st) return st;
+    if (!m) return fail(c, NH_EINVAL, "null MLP");
+    if (!dev_b || !dev_tmp || !dev_x0) return fail(c, NH_EINVAL, "null arrays");
+    if (!c->have_ref) return fail(c, NH_EINVAL, "reference state not set");
+    if (!(alpha >= 0.0 && alpha < 1e300)) return fail(c, NH_EINVAL, "alpha must be finite and >= 0");
+    return mlp_guess(m, c, alpha, dev_b, dev_tmp, dev_x0);
 }
 
 nh_status nh_mlp_last_error(const nh_mlp *m, char *buf, size_t n)

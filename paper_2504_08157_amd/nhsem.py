@@ -111,6 +111,7 @@ _SIGS = {
     "nh_mlp_set_params": (ctypes.c_int32, [_vp, _vp]),
     "nh_mlp_samples": (ctypes.c_int32, [_vp, _vp, ctypes.c_double, _vp, _vp, ctypes.c_int64, ctypes.c_int64,
                                         _vp, _vp, _vp, _vp]),
+    "nh_mlp_guess": (ctypes.c_int32, [_vp, _vp, ctypes.c_double, _vp, _vp, _vp]),
     "nh_mlp_last_error": (ctypes.c_int32, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     "nh_mlp_destroy": (ctypes.c_int32, [_vp]),
     "nh_last_error": (ctypes.c_int32, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
@@ -474,6 +475,16 @@ class ColumnMLP:
                                        _tptr(tgt) if tgt is not None else None, _tptr(tmp))
         _check(ctx.h, code)
         return feat, scale, tgt
+
+    def nh_mlp_guess(self, ctx, alpha, b, out=None, tmp=None):
+        """Initial guess [3][U] (rho', w, theta') of the column solves for b [5][U]."""
+        import torch
+        if out is None:
+            out = torch.empty(3 * ctx.U, dtype=torch.float64, device=self.device)
+        if tmp is None:
+            tmp = torch.empty(5 * ctx.U, dtype=torch.float64, device=self.device)
+        _check(ctx.h, self.lib.nh_mlp_guess(self.h, ctx.h, float(alpha), _tptr(b), _tptr(tmp), _tptr(out)))
+        return out
 
 
 class Batch:

@@ -97,6 +97,41 @@ def test_features_match_oracle(oracle_mod):
     assert _rel(tgt.cpu().numpy(), to) <= 1e-6
 
 
+def test_fused_guess_matches_separate_kernels(oracle_mod):
+    """The one-kernel inference of nh_mlp_guess (features, network and
+    resampling in LDS) against the separate feature and forward kernels
+    followed by the oracle's resampling, on a ragged column count (117)."""
+    import torch
+    from paper_2504_08157_amd import nhsem
+    ph = W.Physics()
+    mesh = W.MeshSpec((3, 2, 4), 4, W.uniform_edges(0, 30e3, 3), W.uniform_edges(0, 20e3, 2),
+                      W.stretched_edges(0, 15e3, 4, seed=8), (True, True))
+    ctx = nhsem.Context(mesh, ph)
+    orc = oracle_mod.Oracle(mesh, ph)
+    g = ctx.nh_lattice_coords(); o = orc.lattice_coords()
+    ctx.nh_set_reference(*W.constant_n_reference(g[2]))
+    orc.set_reference(*W.constant_n_reference(o[2]))
+    bq = W.smooth_random_state(*o, *W.constant_n_reference(o[2]), seed=4, walls=(False, False))
+    ncol = ctx.nx * ctx.ny
+    m = nhsem.ColumnMLP(max_batch=128)
+    rng = np.random.default_rng(12)
+    m.nh_mlp_set_params(torch.from_numpy(rng.normal(scale=0.03, size=m.nparam).astype(np.float32)).cuda())
+    alpha = 0.9
+    bd = torch.from_numpy(bq).cuda()
+    x0 = m.nh_mlp_guess(ctx, alpha, bd).cpu().numpy().reshape(3, orc.nz, ncol)
+    feat, scale, _ = m.nh_mlp_samples(ctx, alpha, bd)
+    fpad = torch.zeros((128, MO.IN), dtype=torch.float16, device="cuda")
+    fpad[:ncol] = feat
+    y = m.nh_mlp_forward(fpad).cpu().numpy()[:ncol].astype(np.float64)
+    sel = lambda a: np.stack([a[0], a[3], a[4]]).reshape(3, orc.nz, -1)
+    rho0, th0 = W.constant_n_reference(o[2])
+    D = MO.dimension_factors(rho0, orc.reference_pressure(), th0, ph.cp / ph.cv)
+    ref = MO.column_guess(sel(bq), y, o[2], D, scale.cpu().numpy())
+    corr, corr_ref = x0 - sel(bq), ref - sel(bq)
+    assert np.linalg.norm(corr_ref) > 1e-3 * np.linalg.norm(sel(bq))   # the network changes the guess
+    assert _rel(corr, corr_ref) <= 1e-12, _rel(corr, corr_ref)
+
+
 def test_untrained_guess_equals_default(oracle_mod):
     import torch
     from paper_2504_08157_amd import nhsem
