@@ -227,7 +227,7 @@ __device__ __forceinline__ float4v mfma_k32(const half8 &a, const half8 &b, floa
 // registers while the current one is multiplied.  A lane's A and B operands
 // hold the same 8 (or 4) k values, so the pairing inside the instruction is
 // consistent.  The optional second product (the linear bypass of the last
-// layer) accumulates into the same registers.  Epilogue: Z (FP32
+// layer) is accumulated first, into the same registers.  Epilogue: Z (FP32
 // pre-activation, skipped when null) and, when act != 0, H = SiLU(Z) in
 // FP16.  Requires M % 64 == 0, K % 16 == 0, K2 % 16 == 0.
 __global__ void __launch_bounds__(256) gemm_rows_kernel(const _Float16 *__restrict__ A,
@@ -302,8 +302,10 @@ __global__ void __launch_bounds__(256) gemm_rows_kernel(const _Float16 *__restri
                     acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x16f16(av[a], bv[c], acc[a][c], 0, 0, 0);
         }
     };
-    run(A, W, K);
+    // the bypass product first (the fused inference kernel accumulates in
+    // the same order)
     if (A2) run(A2, W2, K2);
+    run(A, W, K);
 
     // output layout: lane holds rows 4 (lane / 16) + i, column lane % 16 of each 16 x 16 tile
 #pragma unroll
@@ -326,22 +328,27 @@ __global__ void __launch_bounds__(256) gemm_rows_kernel(const _Float16 *__restri
 // of the 64 columns (computed as in mlp_features_kernel), the three layers
 // on v_mfma_f32_16x16x16_f16 with the A operands read from LDS (wave w:
 // outputs 32 w .. 32 w + 31 of the 64 rows; W fragments from memory, where
-// they stay L2 resident), the hidden activations in LDS, and the
-// resampling of the output to the lattice levels (as in mlp_guess_kernel).
-// The MFMA operands and the order of accumulation are those of
-// gemm_rows_kernel, so the guess equals that of the separate kernels.
+// they stay L2 resident), and the resampling of the output to the lattice
+// levels (as in mlp_guess_kernel).  Layer 1 and the linear bypass share one
+// pass over the features, after which one LDS region holds in turn the
+// features, H1, H2 and the output rows (about 58 KB per workgroup, two
+// workgroups per CU).  The MFMA operands and the order of accumulation are
+// those of gemm_rows_kernel, so the guess equals that of the separate
+// kernels.
 constexpr int kLdF = kMlpIn + 8;    // LDS row of the features (halves), padded
 constexpr int kLdH = kMlpHid + 8;   // LDS row of the activations (halves), padded
-static_assert(64 * (kMlpNF + 1) * 4 <= 64 * kLdF * 2, "output rows fit in the feature rows");
+constexpr int kRegBytes = 64 * kLdF * 2;   // the shared region: features, then H1, H2, output rows
+static_assert(64 * (kMlpNF + 1) * 4 <= kRegBytes && 64 * kLdH * 2 <= kRegBytes, "region sizes");
 
-__global__ void __launch_bounds__(512) mlp_infer_kernel(MlpColParams p, MlpWeights wt,
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) mlp_infer_kernel(MlpColParams p, MlpWeights wt,
                                                         const double *__restrict__ b,
                                                         const double *__restrict__ lb, long col0, long ncol,
                                                         double *__restrict__ x0)
 {
     constexpr int NWV = 8;
-    __shared__ __align__(16) _Float16 sf[64 * kLdF];
-    __shared__ __align__(16) _Float16 sh[64 * kLdH];
+    __shared__ __align__(16) unsigned char sreg[kRegBytes];
+    _Float16 *sf = reinterpret_cast<_Float16 *>(sreg);   // features [64][kLdF]
+    _Float16 *sh = reinterpret_cast<_Float16 *>(sreg);   // H1, then H2 [64][kLdH]
     __shared__ double spart[NWV][64];
     __shared__ double sscale[64];
     __shared__ int sk0[kMlpNC];
@@ -352,7 +359,7 @@ __global__ void __launch_bounds__(512) mlp_infer_kernel(MlpColParams p, MlpWeigh
     double *dg = stab + 3 * nz;        // [3][n_z] dimension factors
     double *tg = stab + 6 * nz;        // [n_z] canonical weight of each lattice level
     int *lg = (int *)(stab + 7 * nz);  // [n_z] canonical interval of each lattice level
-    float *sy = reinterpret_cast<float *>(sf);   // [64][kMlpNF + 1] outputs, after the last layer
+    float *sy = reinterpret_cast<float *>(sreg);   // [64][kMlpNF + 1] outputs, after the last layer
 
     const long nxy = (long)p.nx * p.ny;
     const long U = nxy * nz;
@@ -433,78 +440,98 @@ __global__ void __launch_bounds__(512) mlp_infer_kernel(MlpColParams p, MlpWeigh
 
     // ---- layers
     const int wave = q, r16 = lane % 16, g = lane / 16;
-    float4v acc[4][2];
-    auto zero = [&]() {
+    float4v acc[4][2], acc3[4][2];   // current layer; last layer (bypass first)
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int c = 0; c < 2; ++c) acc[a][c] = float4v{0.f, 0.f, 0.f, 0.f};
-    };
-    // acc += S[64 x KK] (LDS, row stride ld) Wp[32 w .. 32 w + 31][KK]^T
-    auto mma = [&](const _Float16 *S, int ld, const _Float16 *Wp, int KK) {
+        for (int c = 0; c < 2; ++c) {
+            acc[a][c] = float4v{0.f, 0.f, 0.f, 0.f};
+            acc3[a][c] = float4v{0.f, 0.f, 0.f, 0.f};
+        }
+    // C += S[64 x KK] (LDS, row stride ld) Wp[32 w .. 32 w + 31][KK]^T for
+    // up to two (W, C) pairs sharing the A fragments
+    auto mma = [&](const _Float16 *S, int ld, int KK, const _Float16 *Wa, float4v (&Ca)[4][2],
+                   const _Float16 *Wb, float4v (&Cb)[4][2]) __attribute__((always_inline)) {
         const int K32 = KK & ~31;
-        const _Float16 *gw = Wp + (long)(32 * wave + r16) * KK + 8 * g;
+        const long wrow = (long)(32 * wave + r16) * KK;
         if (K32 > 0) {
-            half8 bv[2], bn[2];
+            half8 ba[2], bb[2];
 #pragma unroll
-            for (int c = 0; c < 2; ++c) bv[c] = *(const half8 *)(gw + (long)16 * c * KK);
+            for (int c = 0; c < 2; ++c) {
+                ba[c] = *(const half8 *)(Wa + wrow + (long)16 * c * KK + 8 * g);
+                if (Wb) bb[c] = *(const half8 *)(Wb + wrow + (long)16 * c * KK + 8 * g);
+            }
             for (int k = 0; k < K32; k += 32) {
+                half8 na[2], nb[2];
                 if (k + 32 < K32)
 #pragma unroll
-                    for (int c = 0; c < 2; ++c) bn[c] = *(const half8 *)(gw + (long)16 * c * KK + k + 32);
+                    for (int c = 0; c < 2; ++c) {
+                        na[c] = *(const half8 *)(Wa + wrow + (long)16 * c * KK + k + 32 + 8 * g);
+                        if (Wb) nb[c] = *(const half8 *)(Wb + wrow + (long)16 * c * KK + k + 32 + 8 * g);
+                    }
                 half8 av[4];
 #pragma unroll
                 for (int a = 0; a < 4; ++a) av[a] = *(const half8 *)(S + (16 * a + r16) * ld + k + 8 * g);
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
-                    for (int c = 0; c < 2; ++c)
-                        acc[a][c] = mfma_k32(av[a], bv[c], acc[a][c]);
+                    for (int c = 0; c < 2; ++c) {
+                        Ca[a][c] = mfma_k32(av[a], ba[c], Ca[a][c]);
+                        if (Wb) Cb[a][c] = mfma_k32(av[a], bb[c], Cb[a][c]);
+                    }
                 if (k + 32 < K32)
 #pragma unroll
-                    for (int c = 0; c < 2; ++c) bv[c] = bn[c];
+                    for (int c = 0; c < 2; ++c) {
+                        ba[c] = na[c];
+                        if (Wb) bb[c] = nb[c];
+                    }
             }
         }
         if (KK > K32) {
-            const _Float16 *gw4 = Wp + (long)(32 * wave + r16) * KK + K32 + 4 * g;
-            half4 bv[2], av[4];
+            half4 ba[2], bb[2], av[4];
 #pragma unroll
-            for (int c = 0; c < 2; ++c) bv[c] = *(const half4 *)(gw4 + (long)16 * c * KK);
+            for (int c = 0; c < 2; ++c) {
+                ba[c] = *(const half4 *)(Wa + wrow + (long)16 * c * KK + K32 + 4 * g);
+                if (Wb) bb[c] = *(const half4 *)(Wb + wrow + (long)16 * c * KK + K32 + 4 * g);
+            }
 #pragma unroll
             for (int a = 0; a < 4; ++a) av[a] = *(const half4 *)(S + (16 * a + r16) * ld + K32 + 4 * g);
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int c = 0; c < 2; ++c)
-                    acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x16f16(av[a], bv[c], acc[a][c], 0, 0, 0);
+                for (int c = 0; c < 2; ++c) {
+                    Ca[a][c] = __builtin_amdgcn_mfma_f32_16x16x16f16(av[a], ba[c], Ca[a][c], 0, 0, 0);
+                    if (Wb) Cb[a][c] = __builtin_amdgcn_mfma_f32_16x16x16f16(av[a], bb[c], Cb[a][c], 0, 0, 0);
+                }
         }
     };
-    // H = SiLU(acc + bias) into the activation rows (lane: rows 4 g + i, column r16 of each tile)
-    auto store_h = [&](const float *bias) {
+    // H = SiLU(acc + bias) into the activation rows (lane: rows 4 g + i,
+    // column r16 of each tile); acc is cleared for the next layer
+    auto store_h = [&](const float *bias) __attribute__((always_inline)) {
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int c = 0; c < 2; ++c)
+            for (int c = 0; c < 2; ++c) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int row = 16 * a + 4 * g + i, cl = 32 * wave + 16 * c + r16;
                     const float z = acc[a][c][i] + bias[cl];
                     sh[row * kLdH + cl] = (_Float16)(z / (1.0f + expf(-z)));
                 }
+                acc[a][c] = float4v{0.f, 0.f, 0.f, 0.f};
+            }
     };
-    zero();
-    mma(sf, kLdF, wt.W[0], kMlpIn);
+    // layer 1 and the bypass of the last layer: one pass over the features
+    mma(sf, kLdF, kMlpIn, wt.W[3], acc3, wt.W[0], acc);
+    __syncthreads();   // every wave has read the features
     store_h(wt.bias[0]);
     __syncthreads();
-    zero();
-    mma(sh, kLdH, wt.W[1], kMlpHid);
+    mma(sh, kLdH, kMlpHid, wt.W[1], acc, nullptr, acc);
     __syncthreads();   // every wave has read H1
     store_h(wt.bias[1]);
     __syncthreads();
-    zero();
-    mma(sh, kLdH, wt.W[2], kMlpHid);
-    mma(sf, kLdF, wt.W[3], kMlpIn);
-    __syncthreads();   // every wave has read the features and H2
+    mma(sh, kLdH, kMlpHid, wt.W[2], acc3, nullptr, acc3);
+    __syncthreads();   // every wave has read H2
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -512,7 +539,7 @@ __global__ void __launch_bounds__(512) mlp_infer_kernel(MlpColParams p, MlpWeigh
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int row = 16 * a + 4 * g + i, cl = 32 * wave + 16 * c + r16;
-                if (cl < kMlpNF) sy[row * (kMlpNF + 1) + cl] = acc[a][c][i] + wt.bias[2][cl];
+                if (cl < kMlpNF) sy[row * (kMlpNF + 1) + cl] = acc3[a][c][i] + wt.bias[2][cl];
             }
     __syncthreads();
 
