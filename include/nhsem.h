@@ -204,7 +204,8 @@ nh_status nh_hevi_attach(nh_ctx *ctx, void *dev_ws, size_t bytes);
 nh_status nh_lv_apply(nh_ctx *ctx, const double *dev_x, double *dev_y);
 
 /* Solve (I - alpha L_v) x = b in every column by restarted matrix-free
-   GMRES (one wavefront per column, Krylov basis in LDS).  dev_b, dev_x:
+   GMRES (one wavefront per column; with restart 10 and 3 n_z <= 256 the
+   Krylov basis is held in registers, otherwise in LDS).  dev_b, dev_x:
    [5][U]; the u, v fields of x are copied from b.  dev_x0: initial guess of
    (rho', w, theta') as [3][U], or NULL for x0 = b.  dev_iters: optional
    device int32 [n_x n_y] receiving the Arnoldi steps per column (negative:
