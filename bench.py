@@ -66,7 +66,9 @@ def parse():
                          "copy: a plain device-to-device copy of known size, the calibration run for the "
                          "HBM byte counters; precision: FP32-mixed vs FP64 after --err-steps steps")
     ap.add_argument("--members", type=int, default=48)
-    ap.add_argument("--mlp-epochs", type=int, default=40, help="training epochs of the column MLP (hevi mode)")
+    ap.add_argument("--mlp-epochs", type=int, default=160, help="training epochs of the column MLP (hevi mode)")
+    ap.add_argument("--mlp-random-batches", type=int, default=32,
+                    help="batches of random column right-hand sides in the MLP training data (hevi mode)")
     ap.add_argument("--gmres-restart", type=int, default=10, help="Krylov vectors per GMRES cycle (hevi mode)")
     return ap.parse_args()
 
@@ -119,7 +121,7 @@ def bench_hevi(args):
     wr.mesh = W._tc_mesh(32, 32, w.mesh.nel[2])   # same column grid, 16384 columns per random batch
     tr = LG.fit(mlp, w, w.dt, warm, [(W.cfg_tc_small(), 2, w.dt), (W.cfg_bubble(), 2, 0.5)],
                 epochs=args.mlp_epochs, batch=1024, lr=1e-3, max_per_step=24576, random_grid=wr,
-                random_batches=16)
+                random_batches=args.mlp_random_batches)
     res = LG.compare(mlp, w, warm=warm, held=args.steps, dt=w.dt, restart=args.gmres_restart)
     ctx = nhsem.Context(w.mesh, w.phys)
     U = ctx.U
