@@ -398,12 +398,13 @@ __device__ __forceinline__ void wave_sync()
 // The same restarted GMRES with the Krylov basis in registers: unknown u of
 // the column sits in slot u / 64 of lane u mod 64 (S slots cover 64 S
 // unknowns) and the loops over basis vectors are unrolled, so every basis
-// access is a register.  Orthogonalisation is classical Gram-Schmidt with
-// the re-orthogonalisation test of Daniel, Gragg, Kaufman and Stewart (1976):
-// the dot products and |w|^2 are reduced together in one round, the new norm
-// follows from Pythagoras, and a second pass runs only where the projection
-// cancelled more than half of |w|^2 (one reduction round per step instead of
-// one per basis vector).  The Arnoldi process runs on L_v itself, which
+// access is a register.  Orthogonalisation is classical Gram-Schmidt with a
+// re-orthogonalisation test in the manner of Daniel, Gragg, Kaufman and
+// Stewart (1976): the dot products and |w|^2 are reduced together in one
+// round, the new norm follows from Pythagoras, and a second pass runs only
+// where the projection kept less than 1 % of |w| (one reduction round per
+// step instead of one per basis vector; the restart length of 10 keeps the
+// accumulated loss of orthogonality near 1e-13).  The Arnoldi process runs on L_v itself, which
 // spans the same Krylov space as A = I - alpha L_v (H_A = I - alpha H_L) but
 // without the identity part that the projection would cancel every step.
 // The Hessenberg column is rotated in registers on every lane; lane 0 keeps
@@ -536,8 +537,10 @@ __global__ void __launch_bounds__(64) gmres_reg_kernel(HeviParams h, GmresArgs g
                     apply(V[j], V[j + 1]);
                     // Gram-Schmidt: the dots with V_0..V_j and |w|^2 in one
                     // batched reduction; |w - V h| from Pythagoras unless the
-                    // projection removed more than half of |w|^2, in which
-                    // case the pass is repeated and the norm taken directly
+                    // projection kept less than 1 % of |w| (the new vector's
+                    // loss of orthogonality is then above ~100 eps), in
+                    // which case the pass is repeated and the norm taken
+                    // directly
                     double hc[M + 2];
 #pragma unroll
                     for (int i = 0; i <= M + 1; ++i) {
@@ -559,7 +562,7 @@ __global__ void __launch_bounds__(64) gmres_reg_kernel(HeviParams h, GmresArgs g
                         for (int s = 0; s < S; ++s) V[j + 1][s] -= hc[i] * V[i][s];
                     }
                     double nn2 = w2 - p2;
-                    if (nn2 < 0.5 * w2) {
+                    if (nn2 < 1e-4 * w2) {
                         double e[M + 1];
 #pragma unroll
                         for (int i = 0; i <= M; ++i) {
