@@ -110,6 +110,7 @@ def bench_hevi(args):
     `warmup` default steps of this case (the held-out steps that are timed
     come after them), and random column right-hand sides solved by the
     library's column GMRES on this vertical grid."""
+    import numpy as np
     import torch
     from paper_2504_08157_amd import learned_guess as LG
     from paper_2504_08157_amd import nhsem
@@ -123,6 +124,11 @@ def bench_hevi(args):
                 epochs=args.mlp_epochs, batch=1024, lr=1e-3, max_per_step=24576, random_grid=wr,
                 random_batches=args.mlp_random_batches)
     res = LG.compare(mlp, w, warm=warm, held=args.steps, dt=w.dt, restart=args.gmres_restart)
+    # the same steps with the column systems solved through their Schur
+    # complement in w (restart 10 only)
+    res_s = None
+    if args.gmres_restart == 10:
+        res_s = LG.compare(mlp, w, warm=warm, held=args.steps, dt=w.dt, restart=10, schur=True)
     ctx = nhsem.Context(w.mesh, w.phys)
     U = ctx.U
     ctx.close()
@@ -141,6 +147,16 @@ def bench_hevi(args):
                  "state_rel_diff_stacked": res["state_rel_diff_stacked"],
                  "training": tr},
     }
+    if res_s is not None:
+        ds, ms = res_s["default"], res_s["mlp"]
+        out["hevi"]["schur_form"] = {
+            "default": ds, "mlp": ms, "speedup_step": ds["ms_per_step"] / ms["ms_per_step"],
+            "iteration_ratio": ms["iters_per_solve"] / ds["iters_per_solve"],
+            "state_rel_diff_stacked": res_s["state_rel_diff_stacked"],
+            "speedup_vs_full_form_default": d["ms_per_step"] / ds["ms_per_step"],
+            "state_rel_diff_vs_full_form": float(
+                np.linalg.norm(res_s["final_default"] - res["final_default"]) / np.linalg.norm(res["final_default"])),
+        }
     print(json.dumps(out), flush=True)
 
 

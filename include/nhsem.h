@@ -184,6 +184,12 @@ typedef struct {
     int32_t restart;          /* Krylov vectors per cycle, 1..40 (paper: < 20) */
     int32_t max_restarts;     /* restarts before NH_ENOCONV */
     double rtol;              /* stop when ||b - A x||_2 <= rtol ||b||_2 */
+    int32_t schur;            /* 0: GMRES on the column system in (rho', w, theta');
+                                 1: GMRES on its Schur complement in the interior w
+                                 values (rho', theta' eliminated per column, then
+                                 reconstructed); same stopping test on the full
+                                 system; restart 10 and n_z <= 130 only
+                                 (NH_EUNSUPPORTED otherwise) */
 } nh_gmres_opts;
 typedef struct {
     int64_t columns;          /* columns per solve */

@@ -669,6 +669,304 @@ __global__ void __launch_bounds__(64) gmres_reg_kernel(HeviParams h, GmresArgs g
     }
 }
 
+// ---------------------------------------------------------------- GMRES, Schur form
+// The same column system solved through its Schur complement in w.  With
+// (I - alpha L_v) x = b written per field, the rho' and theta' rows give
+// rho' = b_rho + alpha L_rw w and theta' = b_th + alpha L_tw w
+// (L_rw w = -d/dz (rho0 w), L_tw w = -w d theta0/dz), so the interior w rows
+// become (I - alpha^2 M) w = b_w + alpha L_w(b_rho + alpha L_rw w_wall,
+// b_th + alpha L_tw w_wall) with M w = L_w(L_rw w, L_tw w) and L_w the w row
+// of L_v acting on (rho', theta'); the wall values of w are b_w (their rows
+// of L_v are zero).  GMRES runs on the n_z - 2 interior w values (Arnoldi on
+// M, H = I - alpha^2 H_M), one register slot per 64 of them.  The full-system
+// residual of the reconstructed (rho', w, theta') is the Schur residual on
+// the interior w rows and zero elsewhere, so the stopping test
+// ||b - A x|| <= rtol ||b|| is the same as for the full form (||b|| over
+// all 3 n_z unknowns).
+template <int M, int S>
+__global__ void __launch_bounds__(64) gmres_schur_kernel(HeviParams h, GmresArgs g)
+{
+    extern __shared__ double smem[];
+    const int nz = h.nz, N = h.N, NC = 2 * N + 1, lane = threadIdx.x;
+    const int NP = nz + 2 * N;
+    double *slc = smem;                   // nz x 5: rho0, p0, d theta0/dz, 1/rho0, 1/theta0
+    double *sgz = slc + nz * 5;           // nz x NC
+    double *ww = sgz + nz * NC;           // nz: w at every level
+    double *tp = ww + nz;                 // 2 NP: rho0 w and p'_L, N zeros on both ends
+    double *rt = tp + 2 * NP;             // nz: rho' component
+    double *tt = rt + nz;                 // nz: theta' component
+    double *br = tt + nz;                 // nz: b_rho
+    double *bt = br + nz;                 // nz: b_theta
+    double *bw = bt + nz;                 // nz: b_w
+    double *sb = bw + nz;                 // 64 S: reduced right-hand side
+    double *sx = sb + 64 * S;             // 64 S: iterate
+    double *R = sx + 64 * S;              // M x M triangular factor
+    double *cs = R + M * M;
+    double *sn = cs + M;
+    double *gv = sn + M;
+
+    for (int k = lane; k < nz; k += 64) {
+        const double *L = h.lev + k * kLevW;
+        slc[k * 5 + 0] = L[0];
+        slc[k * 5 + 1] = L[2];
+        slc[k * 5 + 2] = L[3];
+        slc[k * 5 + 3] = L[7];
+        slc[k * 5 + 4] = L[8];
+    }
+    for (int i = lane; i < nz * NC; i += 64) sgz[i] = h.gz[i];
+    for (int i = lane; i < 2 * NP; i += 64) tp[i] = 0.0;
+    __syncthreads();
+
+    // slot s of this lane holds interior level sk (1 .. nz-2), or nothing (0)
+    int sk[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int k = 1 + lane + 64 * s;
+        sk[s] = k <= nz - 2 ? k : 0;
+    }
+    const double beta = g.alpha * g.alpha;
+
+    // From ww (w at every level): rt = rb + c L_rw ww, tt = tb + c L_tw ww at
+    // every level (rb, tb may be null), and, if y is given, y[s] = L_w(rt, tt)
+    // at the lane's interior levels.
+    auto chain = [&](double c, const double *rb, const double *tb, double (*y)[S]) __attribute__((always_inline)) {
+        for (int k = lane; k < nz; k += 64) tp[N + k] = slc[k * 5] * ww[k];
+        wave_sync();
+        for (int k = lane; k < nz; k += 64) {
+            const double *L = slc + k * 5;
+            const double *G = sgz + k * NC;
+            const double *T = tp + k;
+            double d = 0.0;
+            for (int o = 0; o < NC; ++o) d += G[o] * T[o];
+            const double r = (rb ? rb[k] : 0.0) - c * d;
+            const double th = (tb ? tb[k] : 0.0) - c * ww[k] * L[2];
+            rt[k] = r;
+            tt[k] = th;
+            tp[NP + N + k] = h.gamma * L[1] * (r * L[3] + th * L[4]);
+        }
+        wave_sync();
+        if (y) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int k = sk[s];
+                double v = 0.0;
+                if (k > 0) {
+                    const double *G = sgz + k * NC;
+                    const double *T = tp + NP + k;
+                    double d = 0.0;
+                    for (int o = 0; o < NC; ++o) d += G[o] * T[o];
+                    v = -d * slc[k * 5 + 3] - h.g * rt[k] * slc[k * 5 + 3];
+                }
+                (*y)[s] = v;
+            }
+        }
+        // the exchange arrays are rewritten by the next call
+        wave_sync();
+    };
+    // y = M x for interior vectors x in registers (walls zero)
+    auto apply = [&](const double (&x)[S], double (&y)[S]) __attribute__((always_inline)) {
+        for (int k = lane; k < nz; k += 64)
+            if (k == 0 || k == nz - 1) ww[k] = 0.0;
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+            if (sk[s] > 0) ww[sk[s]] = x[s];
+        wave_sync();
+        chain(1.0, nullptr, nullptr, &y);
+    };
+
+    const long nxy = (long)h.nx * h.ny;
+    const long U = nxy * nz;
+    for (long col = blockIdx.x; col < nxy; col += gridDim.x) {
+        double bn2 = 0.0;
+        for (int k = lane; k < nz; k += 64) {
+            const long I = col + (long)k * nxy;
+            const double a = g.b[I], w = g.b[3 * U + I], t = g.b[4 * U + I];
+            br[k] = a;
+            bw[k] = w;
+            bt[k] = t;
+            bn2 += a * a + w * w + t * t;
+        }
+        const double bn = sqrt(wave_sum1(bn2));
+        const double tol = g.rtol * bn;
+        // reduced right-hand side: b_w + alpha L_w(b_rho + alpha L_rw w_wall, b_th + alpha L_tw w_wall)
+        for (int k = lane; k < nz; k += 64) ww[k] = (k == 0 || k == nz - 1) ? bw[k] : 0.0;
+        wave_sync();
+        {
+            double y[S];
+            chain(g.alpha, br, bt, &y);
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                if (sk[s] > 0) {
+                    sb[lane + 64 * s] = bw[sk[s]] + g.alpha * y[s];
+                    sx[lane + 64 * s] = g.x0 ? g.x0[U + col + (long)sk[s] * nxy] : bw[sk[s]];
+                }
+        }
+        int iters = 0;
+        bool conv = bn == 0.0;
+        if (conv)
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                if (sk[s] > 0) sx[lane + 64 * s] = 0.0;
+        for (int rs = 0; rs <= g.max_restarts && !conv; ++rs) {
+            double V[M + 1][S];
+            {
+                double t[S];
+#pragma unroll
+                for (int s = 0; s < S; ++s) t[s] = sk[s] > 0 ? sx[lane + 64 * s] : 0.0;
+                apply(t, V[0]);
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+                    V[0][s] = sk[s] > 0 ? sb[lane + 64 * s] - (t[s] - beta * V[0][s]) : 0.0;
+            }
+            double rn2 = 0.0;
+#pragma unroll
+            for (int s = 0; s < S; ++s) rn2 += V[0][s] * V[0][s];
+            const double rn = sqrt(wave_sum1(rn2));
+            if (rn <= tol) { conv = true; break; }
+            {
+                const double inv = 1.0 / rn;
+#pragma unroll
+                for (int s = 0; s < S; ++s) V[0][s] *= inv;
+            }
+            double gj = rn, res = rn;
+            int jn = 0;
+            bool done = false;
+            static_for<M>([&](auto jc) __attribute__((always_inline)) {
+                constexpr int j = decltype(jc)::value;
+                if (!done) {
+                    apply(V[j], V[j + 1]);
+                    double hc[M + 2];
+#pragma unroll
+                    for (int i = 0; i <= M + 1; ++i) {
+                        hc[i] = 0.0;
+                        if (i <= j)
+#pragma unroll
+                            for (int s = 0; s < S; ++s) hc[i] += V[j + 1][s] * V[i][s];
+                        if (i == j + 1)
+#pragma unroll
+                            for (int s = 0; s < S; ++s) hc[i] += V[j + 1][s] * V[j + 1][s];
+                    }
+                    wave_sum_t<j + 2>(hc);
+                    const double w2 = hc[j + 1];
+                    double p2 = 0.0;
+#pragma unroll
+                    for (int i = 0; i <= j; ++i) {
+                        p2 += hc[i] * hc[i];
+#pragma unroll
+                        for (int s = 0; s < S; ++s) V[j + 1][s] -= hc[i] * V[i][s];
+                    }
+                    double nn2 = w2 - p2;
+                    if (nn2 < 1e-4 * w2) {
+                        double e[M + 1];
+#pragma unroll
+                        for (int i = 0; i <= M; ++i) {
+                            e[i] = 0.0;
+                            if (i <= j)
+#pragma unroll
+                                for (int s = 0; s < S; ++s) e[i] += V[j + 1][s] * V[i][s];
+                        }
+                        wave_sum_t<j + 1>(e);
+#pragma unroll
+                        for (int i = 0; i <= j; ++i) {
+#pragma unroll
+                            for (int s = 0; s < S; ++s) V[j + 1][s] -= e[i] * V[i][s];
+                            hc[i] += e[i];
+                        }
+                        double t2 = 0.0;
+#pragma unroll
+                        for (int s = 0; s < S; ++s) t2 += V[j + 1][s] * V[j + 1][s];
+                        nn2 = wave_sum1(t2);
+                    }
+                    const double nn = sqrt(nn2 > 0.0 ? nn2 : 0.0);
+                    if (nn > 0.0) {
+                        const double inv = 1.0 / nn;
+#pragma unroll
+                        for (int s = 0; s < S; ++s) V[j + 1][s] *= inv;
+                    }
+#pragma unroll
+                    for (int i = 0; i <= j; ++i) hc[i] = (i == j ? 1.0 : 0.0) - beta * hc[i];
+                    const double sub = -beta * nn;
+#pragma unroll
+                    for (int i = 0; i < j; ++i) {
+                        const double c = cs[i], sg = sn[i], a = hc[i], bb = hc[i + 1];
+                        hc[i] = c * a + sg * bb;
+                        hc[i + 1] = -sg * a + c * bb;
+                    }
+                    const double a = hc[j];
+                    const double r = sqrt(a * a + sub * sub);
+                    const double c = r > 0.0 ? a / r : 1.0, sg = r > 0.0 ? sub / r : 0.0;
+                    if (lane == 0) {
+#pragma unroll
+                        for (int i = 0; i < j; ++i) R[i * M + j] = hc[i];
+                        R[j * M + j] = r;
+                        cs[j] = c;
+                        sn[j] = sg;
+                        gv[j] = c * gj;
+                    }
+                    wave_sync();
+                    gj = -sg * gj;
+                    res = fabs(gj);
+                    ++iters;
+                    jn = j + 1;
+                    done = res <= tol || nn == 0.0;
+                }
+            });
+            double y[M];
+#pragma unroll
+            for (int i = M - 1; i >= 0; --i) {
+                y[i] = 0.0;
+                if (i < jn) {
+                    double acc = gv[i];
+#pragma unroll
+                    for (int l = i + 1; l < M; ++l)
+                        if (l < jn) acc -= R[i * M + l] * y[l];
+                    y[i] = acc / R[i * M + i];
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                if (sk[s] > 0) {
+                    double acc = sx[lane + 64 * s];
+#pragma unroll
+                    for (int i = 0; i < M; ++i) acc += y[i] * V[i][s];
+                    sx[lane + 64 * s] = acc;
+                }
+            }
+            if (res <= tol) {
+                double t[S], w[S];
+#pragma unroll
+                for (int s = 0; s < S; ++s) t[s] = sk[s] > 0 ? sx[lane + 64 * s] : 0.0;
+                apply(t, w);
+                double tn2 = 0.0;
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    const double d = sk[s] > 0 ? sb[lane + 64 * s] - (t[s] - beta * w[s]) : 0.0;
+                    tn2 += d * d;
+                }
+                conv = sqrt(wave_sum1(tn2)) <= tol;
+            }
+        }
+        // reconstruct rho' and theta' from the full w column
+        for (int k = lane; k < nz; k += 64)
+            if (k == 0 || k == nz - 1) ww[k] = bw[k];
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+            if (sk[s] > 0) ww[sk[s]] = sx[lane + 64 * s];
+        wave_sync();
+        chain(g.alpha, br, bt, nullptr);
+        for (int k = lane; k < nz; k += 64) {
+            const long I = col + (long)k * nxy;
+            g.x[I] = rt[k];
+            g.x[3 * U + I] = ww[k];
+            g.x[4 * U + I] = tt[k];
+            g.x[U + I] = g.b[U + I];
+            g.x[2 * U + I] = g.b[2 * U + I];
+        }
+        if (lane == 0 && g.iters) g.iters[col] = conv ? iters : -iters - 1;
+        wave_sync();
+    }
+}
+
 static int grid_for(long n, int block)
 {
     long gsz = (n + block - 1) / block;
@@ -711,6 +1009,18 @@ hipError_t launch_axpy_multi(long n, const double *base, int nsrc, const LinComb
 hipError_t launch_gmres(const HeviParams &h, const GmresArgs &g, hipStream_t s)
 {
     const long ncol = (long)h.nx * h.ny;
+    if (g.schur) {
+        if (g.restart != kGmresRegM || h.nz - 2 > 64 * kGmresSchurSlots) return hipErrorInvalidValue;
+        const size_t lds = sizeof(double) * ((size_t)h.nz * 5 + (size_t)h.nz * (2 * h.N + 1) + 6 * (size_t)h.nz +
+                                             2 * (h.nz + 2 * h.N) + 2 * 64 * kGmresSchurSlots +
+                                             kGmresRegM * kGmresRegM + 3 * kGmresRegM);
+        const int grid = (int)(ncol < 32768 ? ncol : 32768);
+        if (h.nz - 2 <= 64)
+            hipLaunchKernelGGL((gmres_schur_kernel<kGmresRegM, 1>), dim3(grid), dim3(64), lds, s, h, g);
+        else
+            hipLaunchKernelGGL((gmres_schur_kernel<kGmresRegM, kGmresSchurSlots>), dim3(grid), dim3(64), lds, s, h, g);
+        return hipGetLastError();
+    }
     if (g.restart == kGmresRegM && 3 * h.nz <= 64 * kGmresRegSlots) {
         // register basis: LDS for the level tables, the exchange vector and
         // the Hessenberg data only

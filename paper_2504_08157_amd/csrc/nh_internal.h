@@ -73,6 +73,7 @@ struct GmresArgs {
     double rtol;
     int restart, max_restarts;
     int *iters;          // [n_x n_y] Arnoldi steps per column (negative: not converged), or null
+    int schur;           // 1: solve the Schur complement in w (restart kGmresRegM only)
 };
 
 constexpr int kMaxComb = 6;
@@ -88,9 +89,11 @@ hipError_t launch_axpy_multi(long n, const double *base, int nsrc, const LinComb
                              hipStream_t s);
 hipError_t launch_gmres(const HeviParams &h, const GmresArgs &g, hipStream_t s);
 
+constexpr int kGmresRegM = 10;        // restart length of the register-basis GMRES
+constexpr int kGmresRegSlots = 4;     // unknowns per lane it supports (3 n_z <= 256)
+constexpr int kGmresSchurSlots = 2;   // Schur form: interior w levels up to 128
+
 // ---- column MLP
-constexpr int kGmresRegM = 10;      // restart length of the register-basis GMRES
-constexpr int kGmresRegSlots = 4;   // unknowns per lane it supports (3 n_z <= 256)
 constexpr int kMlpIn = 400;    // 394 features padded to a multiple of 16
 constexpr int kMlpHid = 256;
 constexpr int kMlpOut = 256;   // 3 fields x 65 canonical levels, padded to a multiple of 64

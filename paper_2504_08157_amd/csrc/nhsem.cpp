@@ -737,6 +737,13 @@ nh_status check_gmres_opts(nh_ctx *c, const nh_gmres_opts *o)
     if (o->restart < 1 || o->restart > 40) return fail(c, NH_EINVAL, "restart must be in 1..40");
     if (o->max_restarts < 0 || o->max_restarts > 1000) return fail(c, NH_EINVAL, "max_restarts out of range");
     if (!(o->rtol > 0.0) || !(o->rtol < 1.0)) return fail(c, NH_EINVAL, "rtol must be in (0, 1)");
+    if (o->schur != 0 && o->schur != 1) return fail(c, NH_EINVAL, "schur must be 0 or 1");
+    if (o->schur) {
+        if (o->restart != kGmresRegM) return fail(c, NH_EUNSUPPORTED, "the Schur form runs with restart %d", kGmresRegM);
+        if (c->n[2] - 2 > 64 * kGmresSchurSlots)
+            return fail(c, NH_EUNSUPPORTED, "the Schur form supports up to %d interior levels", 64 * kGmresSchurSlots);
+        return NH_OK;
+    }
     if (gmres_lds_bytes(c->n[2], c->N, o->restart) > 160 * 1024)
         return fail(c, NH_EUNSUPPORTED, "column too tall for an LDS-resident Krylov basis of this restart length");
     return NH_OK;
@@ -747,7 +754,7 @@ hipError_t run_gmres(nh_ctx *c, double alpha, const double *b, const double *x0,
 {
     GmresArgs g{};
     g.b = b; g.x0 = x0; g.x = x; g.alpha = alpha; g.rtol = o->rtol;
-    g.restart = o->restart; g.max_restarts = o->max_restarts; g.iters = iters;
+    g.restart = o->restart; g.max_restarts = o->max_restarts; g.iters = iters; g.schur = o->schur;
     return launch_gmres(hevi_params(c), g, c->stream);
 }
 

@@ -151,14 +151,15 @@ def fit(mlp, w_eval, dt, warm, sources, epochs, batch=1024, lr=1e-3, max_per_ste
             "batch": batch}
 
 
-def compare(mlp, w, warm, held, dt, rtol=1e-10, restart=20):
+def compare(mlp, w, warm, held, dt, rtol=1e-10, restart=20, schur=False):
     """From the state after `warm` default steps, run `held` steps twice --
     default guess and MLP guess -- and report GMRES iterations, step times
-    and the difference of the final states."""
+    and the difference of the final states (schur: solve the Schur
+    complement in w)."""
     import torch
     ctx = hevi_context(w)
     for s in range(warm):
-        ctx.nh_hevi_step(s * dt, dt, rtol=rtol, max_restarts=30, restart=restart)
+        ctx.nh_hevi_step(s * dt, dt, rtol=rtol, max_restarts=30, restart=restart, schur=schur)
     q0 = ctx.nh_get_state().clone()
     out = {}
     finals = {}
@@ -170,7 +171,8 @@ def compare(mlp, w, warm, held, dt, rtol=1e-10, restart=20):
         for s in range(held):
             e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
-            st = ctx.nh_hevi_step((warm + s) * dt, dt, rtol=rtol, max_restarts=60, restart=restart, guess=g)
+            st = ctx.nh_hevi_step((warm + s) * dt, dt, rtol=rtol, max_restarts=60, restart=restart, guess=g,
+                                  schur=schur)
             e1.record()
             torch.cuda.synchronize()
             ms += e0.elapsed_time(e1)
@@ -185,5 +187,6 @@ def compare(mlp, w, warm, held, dt, rtol=1e-10, restart=20):
     # in the norm the solver's tolerance is stated in (all fields stacked)
     out["state_rel_diff_stacked"] = float(np.linalg.norm(d) / np.linalg.norm(finals["default"]))
     out["columns"] = ctx.nx * ctx.ny
+    out["final_default"] = finals["default"]   # for comparisons between solver forms
     ctx.close()
     return out

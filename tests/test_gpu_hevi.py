@@ -39,10 +39,14 @@ def test_lv_apply_parity(oracle_mod):
     assert np.all(y[1] == 0) and np.all(y[2] == 0)
 
 
-# restart 10 runs the register-basis kernel, 20 the LDS-basis one
-@pytest.mark.parametrize("restart", [20, 10])
+# restart 10 runs the register-basis kernel, 20 the LDS-basis one; schur
+# solves the Schur complement in w
+FORMS = [(20, False), (10, False), (10, True)]
+
+
+@pytest.mark.parametrize("restart,schur", FORMS)
 @pytest.mark.parametrize("alpha", [0.3, 2.0])
-def test_column_gmres_vs_direct(oracle_mod, alpha, restart):
+def test_column_gmres_vs_direct(oracle_mod, alpha, restart, schur):
     ctx, orc, g, o, torch = _pair(oracle_mod)
     Lm = oracle_mod.column_matrix(orc)
     b = _state(o, 5)
@@ -52,7 +56,8 @@ def test_column_gmres_vs_direct(oracle_mod, alpha, restart):
     X = np.linalg.solve(A, B)
     bd = torch.from_numpy(_state(g, 5)).cuda()
     iters = torch.zeros(ctx.nx * ctx.ny, dtype=torch.int32, device="cuda")
-    x, st = ctx.nh_column_solve(alpha, bd, restart=restart, max_restarts=30, rtol=1e-12, iters=iters)
+    x, st = ctx.nh_column_solve(alpha, bd, restart=restart, max_restarts=30, rtol=1e-12, iters=iters,
+                                schur=schur)
     x = x.cpu().numpy()
     for f, blk in ((0, X[:nz]), (3, X[nz:2 * nz]), (4, X[2 * nz:])):
         ref = blk.reshape(x[f].shape)
@@ -61,11 +66,28 @@ def test_column_gmres_vs_direct(oracle_mod, alpha, restart):
     np.testing.assert_array_equal(x[1], bg[1]); np.testing.assert_array_equal(x[2], bg[2])
     it = iters.cpu().numpy()
     assert st.not_converged == 0 and (it > 0).all() and st.iters_total == it.sum()
-    print("alpha", alpha, "restart", restart, "iters mean", it.mean(), "max", it.max())
+    print("alpha", alpha, "restart", restart, "schur", schur, "iters mean", it.mean(), "max", it.max())
     # starting from the exact solution needs no Arnoldi step
     x0 = torch.from_numpy(np.stack([x[0], x[3], x[4]])).cuda()
-    _, st0 = ctx.nh_column_solve(alpha, bd, x0=x0, restart=restart, rtol=1e-9, iters=iters)
+    _, st0 = ctx.nh_column_solve(alpha, bd, x0=x0, restart=restart, rtol=1e-9, iters=iters, schur=schur)
     assert st0.iters_total == 0
+
+
+@pytest.mark.parametrize("restart,schur", FORMS)
+def test_gmres_degenerate_cases(oracle_mod, restart, schur):
+    """b = 0 gives x = 0 with no Arnoldi step; alpha = 0 (A = I) gives x = b
+    in at most one step."""
+    ctx, orc, g, o, torch = _pair(oracle_mod)
+    iters = torch.zeros(ctx.nx * ctx.ny, dtype=torch.int32, device="cuda")
+    b0 = torch.zeros(5 * ctx.U, dtype=torch.float64, device="cuda")
+    x, st = ctx.nh_column_solve(1.0, b0, restart=restart, iters=iters, schur=schur)
+    assert torch.count_nonzero(x).item() == 0 and st.iters_total == 0 and st.not_converged == 0
+    bd = torch.from_numpy(_state(g, 7)).cuda()
+    x, st = ctx.nh_column_solve(0.0, bd, restart=restart, rtol=1e-12, iters=iters, schur=schur)
+    xs, bs = x.cpu().numpy(), bd.cpu().numpy()
+    assert st.not_converged == 0 and st.iters_max <= 1
+    for f in range(5):
+        assert np.linalg.norm(xs[f] - bs[f]) <= 1e-14 * np.linalg.norm(bs[f]), f
 
 
 def test_gmres_reports_non_convergence(oracle_mod):
@@ -77,17 +99,20 @@ def test_gmres_reports_non_convergence(oracle_mod):
     with pytest.raises(nhsem.NHError) as e:
         ctx.nh_column_solve(2.0, bd, restart=2, max_restarts=0, rtol=1e-12)
     assert e.value.code == nhsem.NH_ENOCONV
+    with pytest.raises(nhsem.NHError) as e:
+        ctx.nh_column_solve(2.0, bd, restart=20, schur=True)
+    assert e.value.code == nhsem.NH_EUNSUPPORTED
 
 
-@pytest.mark.parametrize("restart", [20, 10])
-def test_hevi_step_parity(oracle_mod, restart):
+@pytest.mark.parametrize("restart,schur", FORMS)
+def test_hevi_step_parity(oracle_mod, restart, schur):
     ctx, orc, g, o, torch = _pair(oracle_mod)
     Lm = oracle_mod.column_matrix(orc)
     q = _state(o, 9, amp=0.3)
     ctx.nh_set_state(torch.from_numpy(_state(g, 9, amp=0.3)).cuda())
     dt = 4.0
     for n in range(2):
-        st = ctx.nh_hevi_step(n * dt, dt, restart=restart, rtol=1e-13, max_restarts=40)
+        st = ctx.nh_hevi_step(n * dt, dt, restart=restart, rtol=1e-13, max_restarts=40, schur=schur)
         q = oracle_mod.ark2_step(orc, Lm, n * dt, dt, q)
         assert st.not_converged == 0 and st.solves == 2
     got = ctx.nh_get_state().cpu().numpy()
