@@ -42,7 +42,8 @@ def collect(mlp, w, steps, dt, t0=0.0, rtol=1e-10, max_per_step=None, seed=8):
     rng = np.random.default_rng(seed)
     a_dt = None
     for s in range(steps):
-        ctx.nh_hevi_step(t0 + s * dt, dt, rtol=rtol, max_restarts=30)
+        # the Schur form: the same solutions to the tolerance, in half the steps
+        ctx.nh_hevi_step(t0 + s * dt, dt, rtol=rtol, max_restarts=30, restart=10, schur=True)
         a_dt, solves = ctx.nh_hevi_last_solves()
         for (R, X) in solves:
             f, _, t = mlp.nh_mlp_samples(ctx, a_dt * dt, R, X)
@@ -75,7 +76,7 @@ def collect_random(mlp, w, batches, alpha, seed=11, rtol=1e-12):
     for k in range(batches):
         q = W.random_column_rhs(z, D, ncol, seed + k).reshape(5, -1)
         b = torch.from_numpy(np.ascontiguousarray(q)).cuda()
-        xs, st = ctx.nh_column_solve(alpha, b, rtol=rtol, max_restarts=60)
+        xs, st = ctx.nh_column_solve(alpha, b, rtol=rtol, max_restarts=60, restart=10, schur=True)
         f, _, t = mlp.nh_mlp_samples(ctx, alpha, b, xs)
         feats.append(f)
         tgts.append(t)
