@@ -173,6 +173,35 @@ nh_status nh_diagnostics(nh_ctx *ctx, double out[8]);
 nh_status nh_check_finite(nh_ctx *ctx);
 
 /* ------------------------------------------------------------------
+ * Tensor hyper-diffusion (section on tensor-based hyper-diffusion):
+ * H_q = -(div tau grad)^2 q (order alpha = 2) on all five fields, with
+ * tau = (J E) diag(nu_i lambda_i^-1) (J E)^T from the eigendecomposition of
+ * the metric tensor G = J^-1 J^-T and nu_i = c_i^(1/2) dx_i^2 / dt^(1/2),
+ * dx_i the element extent along principal axis i (repeated eigenvalues:
+ * axes in x, y, z order).  The Laplacian is the continuous-Galerkin weak
+ * form with the LGL quadrature, direct stiffness summation and the inverse
+ * diagonal mass (no boundary term).  On the lattice's box elements it is
+ * applied as one assembled (2N+1)-tap operator per direction.
+ * ------------------------------------------------------------------ */
+
+/* Device workspace nh_set_hyperdiffusion needs (a state-sized array and the
+   operator rows). */
+nh_status nh_hyperdiffusion_workspace_bytes(const nh_ctx *ctx, size_t *bytes);
+
+/* Enable H_q with coefficients c[3] (dimensionless, >= 0, for the principal
+   axes in ascending order of the metric eigenvalues, i.e. descending element
+   extent) and time step dt: computes the operator rows into dev_ws (borrowed,
+   256-byte aligned, at least nh_hyperdiffusion_workspace_bytes) and adds
+   H_q(q^s) to the tendency in nh_rhs, nh_rk_step and the explicit part of
+   nh_hevi_step.  c == NULL disables it.  NH_EUNSUPPORTED if the order of the
+   element extents (x, y, z) changes across the mesh. */
+nh_status nh_set_hyperdiffusion(nh_ctx *ctx, const double *c, double dt, void *dev_ws, size_t bytes);
+
+/* dev_H = H_q(dev_q) on device [5][U] arrays (distinct); needs
+   nh_set_hyperdiffusion.  Asynchronous on the context's stream. */
+nh_status nh_hyperdiffusion(nh_ctx *ctx, const double *dev_q, double *dev_H);
+
+/* ------------------------------------------------------------------
  * 1D-IMEX (HEVI) step (Sec. 2.3: IMEX split S = (S - L) + L with the fast
  * waves implicit, ARK2 "ARK(2,3,2)b", matrix-free GMRES).  Here L = L_v, the
  * linearisation of S about the resting reference restricted to vertical

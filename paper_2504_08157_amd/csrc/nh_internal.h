@@ -89,6 +89,15 @@ hipError_t launch_axpy_multi(long n, const double *base, int nsrc, const LinComb
                              hipStream_t s);
 hipError_t launch_gmres(const HeviParams &h, const GmresArgs &g, hipStream_t s);
 
+// ---- tensor hyper-diffusion (box elements: one assembled 1D operator per direction)
+struct HyperParams {
+    int nx, ny, nz, N, perx, pery;
+    const double *sx, *sy, *sz;   // [n_d][2N+1] operator rows per lattice position of each direction
+};
+// out = scale * (div tau grad) q on [5][U] (out += ... with accumulate)
+hipError_t launch_hd_laplace(const HyperParams &h, const double *q, double *out, double scale, bool accumulate,
+                             hipStream_t s);
+
 constexpr int kGmresRegM = 10;        // restart length of the register-basis GMRES
 constexpr int kGmresRegSlots = 4;     // unknowns per lane it supports (3 n_z <= 256)
 constexpr int kGmresSchurSlots = 2;   // Schur form: interior w levels up to 128

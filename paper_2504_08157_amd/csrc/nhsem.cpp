@@ -43,6 +43,9 @@ struct nh_ctx {
     size_t hws_bytes;
     int *hiters;
     float *gxf, *gyf;
+    // tensor hyper-diffusion (caller-provided workspace, see nh_set_hyperdiffusion)
+    bool hd_on;
+    double *hd_tmp, *hd_s[3];
     // forcing
     int nsnap[kNF];
     std::vector<double> tsnap[kNF];
@@ -308,11 +311,60 @@ StageParams stage_params(const nh_ctx *c, double t, const double *qs, const doub
 
 // One fused stage launch, then the forcing of fields 0..3 (used by
 // manufactured solutions; the heating of field 4 is fused in the kernel).
+HyperParams hyper_params(const nh_ctx *c)
+{
+    HyperParams h{};
+    h.nx = c->n[0]; h.ny = c->n[1]; h.nz = c->n[2]; h.N = c->N;
+    h.perx = c->per[0]; h.pery = c->per[1];
+    h.sx = c->hd_s[0]; h.sy = c->hd_s[1]; h.sz = c->hd_s[2];
+    return h;
+}
+
+size_t hyper_bytes(const nh_ctx *c)
+{
+    const size_t nc = 2 * (size_t)c->N + 1;
+    return align_up(sizeof(double) * kNF * (size_t)c->U) +
+           align_up(sizeof(double) * nc * ((size_t)c->n[0] + c->n[1] + c->n[2]));
+}
+
+// Rows of -m^-1 K along one direction: K = sum_e (tau_e / a_e) D^T W D and
+// m = sum_e a_e W assembled over the elements of the line (a_e the half
+// length of element e), periodic lines wrapped; row p holds the taps of the
+// nodes p - N .. p + N.
+void hyper_rows(const nh_ctx *c, int nel, const double *edges, int periodic, const std::vector<double> &tau,
+                std::vector<double> &rows)
+{
+    const int N = c->N, n1 = N + 1, nc = 2 * N + 1;
+    const int n = nel * N + (periodic ? 0 : 1);
+    rows.assign((size_t)n * nc, 0.0);
+    std::vector<double> m(n, 0.0);
+    for (int e = 0; e < nel; ++e) {
+        const double a = 0.5 * (edges[e + 1] - edges[e]);
+        for (int i = 0; i < n1; ++i) {
+            const int P = (e * N + i) % n;
+            m[P] += a * c->w[i];
+            for (int j = 0; j < n1; ++j) {
+                double k = 0.0;
+                for (int q = 0; q < n1; ++q) k += c->D[q * n1 + i] * c->w[q] * c->D[q * n1 + j];
+                rows[(size_t)P * nc + (j - i + N)] += tau[e] / a * k;
+            }
+        }
+    }
+    for (int P = 0; P < n; ++P)
+        for (int o = 0; o < nc; ++o) rows[(size_t)P * nc + o] = -rows[(size_t)P * nc + o] / m[P];
+}
+
 hipError_t run_stage(nh_ctx *c, double t, const double *qs, const double *qn, double *out, double a,
                      double b, double cc)
 {
     const StageParams p = stage_params(c, t, qs, qn, out, a, b, cc);
     hipError_t e = launch_stage(c->N, c->precision, c->tile, p, c->stream);
+    if (e == hipSuccess && c->hd_on) {
+        // out += cc H(qs), H = -(div tau grad)^2 qs
+        const HyperParams hp = hyper_params(c);
+        e = launch_hd_laplace(hp, qs, c->hd_tmp, 1.0, false, c->stream);
+        if (e == hipSuccess) e = launch_hd_laplace(hp, c->hd_tmp, out, -cc, true, c->stream);
+    }
     for (int f = 0; f < 4 && e == hipSuccess; ++f) {
         if (c->nsnap[f] == 0) continue;
         const double *f0, *f1;
@@ -782,6 +834,93 @@ nh_status gather_stats(nh_ctx *c, const int *dev_iters, int nsolves, nh_solve_st
 }  // namespace
 
 extern "C" {
+
+nh_status nh_hyperdiffusion_workspace_bytes(const nh_ctx *c, size_t *bytes)
+{
+    if (!c) return fail(nullptr, NH_EINVAL, "null context");
+    if (!bytes) return fail(nullptr, NH_EINVAL, "null output");
+    *bytes = hyper_bytes(c);
+    return NH_OK;
+}
+
+nh_status nh_set_hyperdiffusion(nh_ctx *c, const double *coef, double dt, void *dev_ws, size_t bytes)
+{
+    nh_status st = guard(c);
+    if (st) return st;
+    if (!coef) {
+        c->hd_on = false;
+        return NH_OK;
+    }
+    for (int i = 0; i < 3; ++i)
+        if (!(coef[i] >= 0.0) || !isfinite(coef[i])) return fail(c, NH_EINVAL, "coefficients must be finite and >= 0");
+    if (!(dt > 0.0) || !isfinite(dt)) return fail(c, NH_EINVAL, "dt must be finite and > 0");
+    if (!dev_ws) return fail(c, NH_EINVAL, "null hyper-diffusion workspace");
+    if (((uintptr_t)dev_ws & 255) != 0) return fail(c, NH_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < hyper_bytes(c)) return fail(c, NH_ESPACE, "hyper-diffusion workspace %zu < %zu bytes", bytes,
+                                            hyper_bytes(c));
+    // principal-axis rank of each direction in every element: the metric
+    // tensor of a box is diag(4 / h^2); ascending eigenvalues = descending
+    // extents, values equal to 1e-10 (relative) taken in x, y, z order
+    const std::vector<double> *edges[3] = {&c->xe, &c->ye, &c->ze};
+    int rank[3] = {-1, -1, -1};
+    for (int ez = 0; ez < c->nel[2]; ++ez)
+        for (int ey = 0; ey < c->nel[1]; ++ey)
+            for (int ex = 0; ex < c->nel[0]; ++ex) {
+                const int el[3] = {ex, ey, ez};
+                double g[3], gmax = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    const double h = (*edges[d])[el[d] + 1] - (*edges[d])[el[d]];
+                    g[d] = 4.0 / (h * h);
+                    gmax = std::max(gmax, g[d]);
+                }
+                const double tol = 1e-10 * gmax;
+                for (int d = 0; d < 3; ++d) {
+                    int r = 0;
+                    for (int o = 0; o < 3; ++o) {
+                        if (o == d) continue;
+                        const bool before = g[o] < g[d] - tol || (std::fabs(g[o] - g[d]) <= tol && o < d);
+                        r += before ? 1 : 0;
+                    }
+                    if (rank[d] < 0) rank[d] = r;
+                    else if (rank[d] != r)
+                        return fail(c, NH_EUNSUPPORTED,
+                                    "the order of element extents changes across the mesh (tau not separable)");
+                }
+            }
+    // tau of direction d in element e: nu_rank = c_rank^(1/2) h^2 / dt^(1/2)
+    char *w = (char *)dev_ws;
+    c->hd_tmp = (double *)w;
+    double *tab = (double *)(w + align_up(sizeof(double) * kNF * (size_t)c->U));
+    std::vector<double> all;
+    for (int d = 0; d < 3; ++d) {
+        const int nel = c->nel[d];
+        std::vector<double> tau(nel), rows;
+        for (int e = 0; e < nel; ++e) {
+            const double h = (*edges[d])[e + 1] - (*edges[d])[e];
+            tau[e] = std::sqrt(coef[rank[d]]) * h * h / std::sqrt(dt);
+        }
+        hyper_rows(c, nel, edges[d]->data(), d < 2 ? c->per[d] : 0, tau, rows);
+        c->hd_s[d] = tab + all.size();
+        all.insert(all.end(), rows.begin(), rows.end());
+    }
+    HIPCHK(c, hipMemcpyAsync(tab, all.data(), sizeof(double) * all.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->hd_on = true;
+    return NH_OK;
+}
+
+nh_status nh_hyperdiffusion(nh_ctx *c, const double *dev_q, double *dev_H)
+{
+    nh_status st = guard(c);
+    if (st) return st;
+    if (!c->hd_on) return fail(c, NH_EINVAL, "hyper-diffusion not set");
+    if (!dev_q || !dev_H) return fail(c, NH_EINVAL, "null arrays");
+    if (dev_q == dev_H) return fail(c, NH_EINVAL, "dev_q and dev_H must differ");
+    const HyperParams hp = hyper_params(c);
+    HIPCHK(c, launch_hd_laplace(hp, dev_q, c->hd_tmp, 1.0, false, c->stream));
+    HIPCHK(c, launch_hd_laplace(hp, c->hd_tmp, dev_H, -1.0, false, c->stream));
+    return NH_OK;
+}
 
 nh_status nh_hevi_workspace_bytes(const nh_ctx *c, size_t *bytes)
 {

@@ -113,6 +113,9 @@ _SIGS = {
     "nh_mlp_samples": (ctypes.c_int32, [_vp, _vp, ctypes.c_double, _vp, _vp, ctypes.c_int64, ctypes.c_int64,
                                         _vp, _vp, _vp, _vp]),
     "nh_mlp_guess": (ctypes.c_int32, [_vp, _vp, ctypes.c_double, _vp, _vp, _vp]),
+    "nh_hyperdiffusion_workspace_bytes": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "nh_set_hyperdiffusion": (ctypes.c_int32, [_vp, _vp, ctypes.c_double, _vp, ctypes.c_size_t]),
+    "nh_hyperdiffusion": (ctypes.c_int32, [_vp, _vp, _vp]),
     "nh_mlp_last_error": (ctypes.c_int32, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     "nh_mlp_destroy": (ctypes.c_int32, [_vp]),
     "nh_last_error": (ctypes.c_int32, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
@@ -353,6 +356,26 @@ class Context:
         self._c(self.lib.nh_hevi_workspace_bytes(self.h, ctypes.byref(n)))
         self.hws = torch.empty(n.value, dtype=torch.uint8, device=self.device)
         self._c(self.lib.nh_hevi_attach(self.h, _tptr(self.hws), n.value))
+
+    def nh_set_hyperdiffusion(self, c, dt):
+        """Enable the tensor hyper-diffusion term with coefficients c (3) and
+        time step dt (c = None disables it)."""
+        import torch
+        if c is None:
+            self._c(self.lib.nh_set_hyperdiffusion(self.h, None, 0.0, None, 0))
+            return
+        n = ctypes.c_size_t(0)
+        self._c(self.lib.nh_hyperdiffusion_workspace_bytes(self.h, ctypes.byref(n)))
+        self.hdws = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        cc = (ctypes.c_double * 3)(*[float(v) for v in c])
+        self._c(self.lib.nh_set_hyperdiffusion(self.h, cc, float(dt), _tptr(self.hdws), n.value))
+
+    def nh_hyperdiffusion(self, q, out=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(q)
+        self._c(self.lib.nh_hyperdiffusion(self.h, _tptr(q), _tptr(out)))
+        return out
 
     def nh_lv_apply(self, x, out=None):
         import torch
