@@ -60,11 +60,12 @@ def parse():
     ap.add_argument("--tile", type=int, default=-1, help="stage-kernel tile variant; -1 = tune by timing")
     ap.add_argument("--copy-mib", type=int, default=1024, help="buffer size of the copy calibration")
     ap.add_argument("--err-steps", type=int, default=600, help="steps of the FP32-vs-FP64 comparison (precision mode)")
-    ap.add_argument("--mode", choices=["rk", "hevi", "batched", "copy", "precision"], default="rk",
+    ap.add_argument("--mode", choices=["rk", "hevi", "batched", "copy", "precision", "hyper"], default="rk",
                     help="rk: SSP-RK3 on the per-GPU TC share (headline); hevi: HEVI ARK2 step with and "
                          "without the learned GMRES guess; batched: 48 uneven instances in graph launches; "
                          "copy: a plain device-to-device copy of known size, the calibration run for the "
-                         "HBM byte counters; precision: FP32-mixed vs FP64 after --err-steps steps")
+                         "HBM byte counters; precision: FP32-mixed vs FP64 after --err-steps steps; "
+                         "hyper: the tensor hyper-diffusion term alone and the SSP-RK3 step with it")
     ap.add_argument("--members", type=int, default=48)
     ap.add_argument("--mlp-epochs", type=int, default=160, help="training epochs of the column MLP (hevi mode)")
     ap.add_argument("--mlp-random-batches", type=int, default=32,
@@ -293,6 +294,65 @@ def bench_precision(args):
     }), flush=True)
 
 
+def bench_hyper(args):
+    """Tensor hyper-diffusion on the per-GPU TC share: H_q alone (two
+    launches of the directional weak-Laplacian kernel) and the SSP-RK3 step
+    with H_q in every stage's tendency (per stage: the stage kernel, then
+    one plain and one accumulating Laplacian launch), against the step
+    without it.  Coefficients c = (1e-6, 1e-6, 2e-6): explicit-stable at
+    dt = 0.25 s on these elements."""
+    import torch
+    from paper_2504_08157_amd import nhsem
+    from paper_2504_08157_amd import workloads as W
+    w = W.cfg_tc_large() if args.workload == "tc_large" else W.cfg_tc_small()
+    ctx, q0 = _tc_context(w, nhsem.NH_FP64)
+    ctx.nh_set_tile(0 if args.tile < 0 else args.tile)
+    c = (1e-6, 1e-6, 2e-6)
+    ctx.nh_set_hyperdiffusion(c, w.dt)
+    U = ctx.U
+    H = ctx.nh_hyperdiffusion(q0)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    s = torch.cuda.current_stream()
+
+    def timed(fn, n):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        a.record(s)
+        for _ in range(n):
+            fn()
+        b.record(s)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / n
+
+    ms_hq = timed(lambda: ctx.nh_hyperdiffusion(q0, out=H), args.steps)
+    ctx.nh_set_state(q0)
+    ms_with = timed(lambda: ctx.nh_rk_step(0.0, w.dt, 1), args.steps)
+    if ctx.nh_check_finite() != 0:
+        raise RuntimeError("non-finite state after the steps with hyper-diffusion")
+    ctx.nh_set_hyperdiffusion(None, 0.0)
+    ctx.nh_set_state(q0)
+    ms_without = timed(lambda: ctx.nh_rk_step(0.0, w.dt, 1), args.steps)
+    # H_q: per unique node, each launch reads 5 and writes 5 doubles
+    bytes_hq = 2 * 2 * 5 * 8 * U
+    achieved = bytes_hq / (ms_hq / 1e3) / 1e9
+    print(json.dumps({
+        "metric": "DOF-stage updates/s (FP32/batched vs FP64 plain) at stated L2 error; % HBM peak",
+        "value": 5 * U * 3 / (ms_with / 1e3), "unit": "DOF-stage updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_with, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "mode": "hyper", "dt": w.dt, "coefficients": list(c)},
+        "hyperdiffusion": {"ms_hq": ms_hq, "ms_step_with": ms_with, "ms_step_without": ms_without,
+                           "step_cost_ratio": ms_with / ms_without},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": bytes_hq / 2,
+                     "kernel": "hd_laplace_tile_kernel (plain form, two launches per H_q)",
+                     "avg_launch_ms": ms_hq / 2},
+    }), flush=True)
+
+
 def bench_copy(args):
     """A plain device copy of args.copy_mib MiB, timed; under the FETCH_SIZE /
     WRITE_SIZE counters it gives the counter-to-byte factor of this GPU."""
@@ -330,6 +390,8 @@ def main():
         return bench_copy(args)
     if args.mode == "precision":
         return bench_precision(args)
+    if args.mode == "hyper":
+        return bench_hyper(args)
     import numpy as np
     import torch
     from paper_2504_08157_amd import nhsem

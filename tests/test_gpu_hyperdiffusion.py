@@ -17,6 +17,10 @@ CASES = {
     "periodic_N4": ((3, 4, 2), 4, (True, True), False),
     "mixed_N3": ((5, 2, 3), 3, (True, False), True),
     "periodic_x1_N5": ((1, 3, 2), 5, (True, True), True),
+    # 68 x 21 lattice columns: two 64 x 16 tiles each way, ragged in both
+    "multi_tile_N4": ((17, 5, 2), 4, (True, False), True),
+    "walls_N2": ((9, 7, 3), 2, (False, False), False),
+    "periodic_y_N6": ((3, 2, 2), 6, (False, True), True),
 }
 
 
