@@ -60,12 +60,13 @@ def parse():
     ap.add_argument("--tile", type=int, default=-1, help="stage-kernel tile variant; -1 = tune by timing")
     ap.add_argument("--copy-mib", type=int, default=1024, help="buffer size of the copy calibration")
     ap.add_argument("--err-steps", type=int, default=600, help="steps of the FP32-vs-FP64 comparison (precision mode)")
-    ap.add_argument("--mode", choices=["rk", "hevi", "batched", "copy", "precision", "hyper"], default="rk",
+    ap.add_argument("--mode", choices=["rk", "hevi", "batched", "copy", "precision", "hyper", "ri"], default="rk",
                     help="rk: SSP-RK3 on the per-GPU TC share (headline); hevi: HEVI ARK2 step with and "
                          "without the learned GMRES guess; batched: 48 uneven instances in graph launches; "
                          "copy: a plain device-to-device copy of known size, the calibration run for the "
                          "HBM byte counters; precision: FP32-mixed vs FP64 after --err-steps steps; "
-                         "hyper: the tensor hyper-diffusion term alone and the SSP-RK3 step with it")
+                         "hyper: the tensor hyper-diffusion term alone and the SSP-RK3 step with it; "
+                         "ri: the RI-velocity diagnostic (centroids, 50-strip azimuthal means, u_RI)")
     ap.add_argument("--members", type=int, default=48)
     ap.add_argument("--mlp-epochs", type=int, default=160, help="training epochs of the column MLP (hevi mode)")
     ap.add_argument("--mlp-random-batches", type=int, default=32,
@@ -353,6 +354,61 @@ def bench_hyper(args):
     }), flush=True)
 
 
+def bench_ri(args):
+    """RI-velocity diagnostic on the per-GPU TC share (the balanced vortex
+    after --warmup SSP-RK3 steps): per-level centroids, 50-strip azimuthal
+    means of the tangential speed, u_RI.  Algorithmic bytes per node: u, v, w
+    read by the centroid pass and u, v by the strip pass (40 B).  The oracle
+    computes the same diagnostic on the host for the cpu_baseline figure."""
+    import numpy as np
+    import torch
+    from paper_2504_08157_amd import nhsem
+    from paper_2504_08157_amd import workloads as W
+    w = W.cfg_tc_large() if args.workload == "tc_large" else W.cfg_tc_small()
+    ctx, q0 = _tc_context(w, nhsem.NH_FP64)
+    ctx.nh_set_tile(0 if args.tile < 0 else args.tile)
+    ctx.nh_rk_step(0.0, w.dt, args.warmup)
+    q = ctx.nh_get_state()
+    U = ctx.U
+    out = ctx.nh_ri_velocity(q, nstrips=50)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    for _ in range(args.steps):
+        out = ctx.nh_ri_velocity(q, nstrips=50)
+    b.record(s)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / args.steps
+    res = out["result"].cpu().numpy().tolist()
+    bytes_call = 40 * U
+    achieved = bytes_call / (ms / 1e3) / 1e9
+    line = {
+        "metric": "DOF-stage updates/s (FP32/batched vs FP64 plain) at stated L2 error; % HBM peak",
+        "value": U / (ms / 1e3), "unit": "nodes/s (RI diagnostic)", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "mode": "ri", "nstrips": 50, "rk_steps_before": args.warmup},
+        "ri": {"u_ri": res[0], "r_ri": res[1], "z_ri": res[2], "u_max": res[3]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_call": bytes_call,
+                     "kernel": "RI diagnostic (centroid and strip passes with their final reductions)"},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle import ri_velocity as RI
+        oracle.build(force=False)
+        orc = oracle.Oracle(w.mesh, w.phys)
+        qh = q.cpu().numpy()
+        t0 = time.perf_counter()
+        want = RI.ri_velocity(orc, qh, nstrips=50)
+        sec = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": U / sec, "unit": "nodes/s (RI diagnostic)", "cores": 1, "kind": "oracle",
+                                "sample": "the full diagnostic of the same state, NumPy on one host thread",
+                                "u_ri_oracle": want["u_ri"]}
+    print(json.dumps(line), flush=True)
+
+
 def bench_copy(args):
     """A plain device copy of args.copy_mib MiB, timed; under the FETCH_SIZE /
     WRITE_SIZE counters it gives the counter-to-byte factor of this GPU."""
@@ -392,6 +448,8 @@ def main():
         return bench_precision(args)
     if args.mode == "hyper":
         return bench_hyper(args)
+    if args.mode == "ri":
+        return bench_ri(args)
     import numpy as np
     import torch
     from paper_2504_08157_amd import nhsem

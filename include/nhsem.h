@@ -202,6 +202,40 @@ nh_status nh_set_hyperdiffusion(nh_ctx *ctx, const double *c, double dt, void *d
 nh_status nh_hyperdiffusion(nh_ctx *ctx, const double *dev_q, double *dev_H);
 
 /* ------------------------------------------------------------------
+ * RI-velocity diagnostic (section on the RI velocity): u_RI is the maximum
+ * over radius and height of the azimuthal mean of the tangential speed
+ * u_theta = |(I - e_r e_r^T - e_z e_z^T) u| about the centre of each level,
+ * the centre being the speed-weighted mean position of the level (LGL
+ * quadrature; a level at rest takes the domain midpoint), and the azimuthal
+ * mean the arithmetic mean over the lattice nodes of an open annulus
+ * j eps < r < (j+1) eps, eps = rmax / nstrips (the paper uses 50 strips).
+ * Strip membership is decided in FP64 on squared radii (dx*dx + dy*dy
+ * against (j*eps)*(j*eps), no fused multiply-add); nodes on a strip edge and
+ * the centre itself belong to no strip.
+ * ------------------------------------------------------------------ */
+
+/* Device workspace nh_ri_velocity needs for nstrips strips (1..4096). */
+nh_status nh_ri_workspace_bytes(const nh_ctx *ctx, int32_t nstrips, size_t *bytes);
+
+/* Diagnostic of the device state dev_q [5][U], asynchronous on the
+   context's stream.  Device outputs (caller-allocated):
+     dev_center [2][n_z]  x_c then y_c per level; an input instead when
+                          center_given != 0;
+     dev_ubar [n_z][nstrips]   strip means of u_theta (0 for an empty strip);
+     dev_count [n_z][nstrips]  nodes per strip;
+     dev_result [4]  u_RI (the largest mean of a populated strip, the first in
+                     (level, strip) order on ties), the radius of its strip
+                     centre ((j + 1/2) eps), the height of its level (both -1
+                     if no strip is populated), and the maximum horizontal
+                     speed max sqrt(u^2 + v^2).
+   dev_ws: borrowed, 256-byte aligned, nh_ri_workspace_bytes.  Strip sums
+   are accumulated in an unordered way, so means may differ in the last bits
+   between calls. */
+nh_status nh_ri_velocity(nh_ctx *ctx, const double *dev_q, int32_t nstrips, double rmax, int32_t center_given,
+                         double *dev_center, double *dev_ubar, int32_t *dev_count, double *dev_result,
+                         void *dev_ws, size_t bytes);
+
+/* ------------------------------------------------------------------
  * 1D-IMEX (HEVI) step (Sec. 2.3: IMEX split S = (S - L) + L with the fast
  * waves implicit, ARK2 "ARK(2,3,2)b", matrix-free GMRES).  Here L = L_v, the
  * linearisation of S about the resting reference restricted to vertical

@@ -98,6 +98,25 @@ struct HyperParams {
 hipError_t launch_hd_laplace(const HyperParams &h, const double *q, double *out, double scale, bool accumulate,
                              hipStream_t s);
 
+// ---- RI-velocity diagnostic
+constexpr int kRiMaxStrips = 4096;
+struct RiParams {
+    int nx, ny, nz, nstrips, nb;   // nb: chunks (workgroups) per level
+    long U;
+    const double *x, *y;           // lattice coordinates [n_x], [n_y]
+    const double *mx, *my;         // assembled 1D masses
+    double eps, xmid, ymid;        // strip width; centre of a level at rest
+};
+struct RiWork {
+    double *cpart;   // [n_z][nb][3] centroid partial sums
+    double *ssum;    // [n_z][nb][n_strips] strip partial sums
+    int *scnt;       // [n_z][nb][n_strips] strip partial counts
+    double *umax;    // [n_z][nb] partial maxima of the horizontal speed
+};
+size_t ri_lds_bytes(int nstrips);
+hipError_t launch_ri(const RiParams &p, const double *q, bool center_given, double *center, double *ubar,
+                     int *count, double *result, const double *z, const RiWork &w, hipStream_t s);
+
 constexpr int kGmresRegM = 10;        // restart length of the register-basis GMRES
 constexpr int kGmresRegSlots = 4;     // unknowns per lane it supports (3 n_z <= 256)
 constexpr int kGmresSchurSlots = 2;   // Schur form: interior w levels up to 128

@@ -37,7 +37,7 @@ struct nh_ctx {
     char *ws;
     size_t ws_bytes;
     double *q[3];
-    double *gx, *gy, *gz, *zl, *lev, *hz2, *mx, *my, *mz, *hx, *hy, *hz, *wl, *cst, *diag_part, *diag_out;
+    double *gx, *gy, *gz, *xl, *yl, *zl, *lev, *hz2, *mx, *my, *mz, *hx, *hy, *hz, *wl, *cst, *diag_part, *diag_out;
     // HEVI workspace (caller-provided, see nh_hevi_attach)
     char *hws;
     size_t hws_bytes;
@@ -187,7 +187,7 @@ void line_tables(int N, int nel, int periodic, const double *edges, const std::v
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t q[3], gx, gy, gz, zl, gxf, gyf, lev, hz2, mx, my, mz, hx, hy, hz, wl, cst, dpart, dout, total;
+    size_t q[3], gx, gy, gz, xl, yl, zl, gxf, gyf, lev, hz2, mx, my, mz, hx, hy, hz, wl, cst, dpart, dout, total;
 };
 
 bool valid_desc(const nh_mesh_desc *m, std::string *why)
@@ -233,6 +233,8 @@ Layout layout_for(const nh_mesh_desc *m)
     L.gx = take(sizeof(double) * nx * nc);
     L.gy = take(sizeof(double) * ny * nc);
     L.gz = take(sizeof(double) * nz * nc);
+    L.xl = take(sizeof(double) * nx);
+    L.yl = take(sizeof(double) * ny);
     L.zl = take(sizeof(double) * nz);
     L.gxf = take(sizeof(float) * nx * nc);
     L.gyf = take(sizeof(float) * ny * nc);
@@ -431,6 +433,8 @@ nh_status nh_init_mesh(const nh_mesh_desc *mesh, const nh_physics *phys, void *d
     for (int f = 0; f < kNF; ++f) { c->nsnap[f] = 0; c->snap[f] = nullptr; }
     for (int i = 0; i < 3; ++i) c->q[i] = (double *)(c->ws + L.q[i]);
     c->gx = (double *)(c->ws + L.gx); c->gy = (double *)(c->ws + L.gy); c->gz = (double *)(c->ws + L.gz);
+    c->xl = (double *)(c->ws + L.xl);
+    c->yl = (double *)(c->ws + L.yl);
     c->zl = (double *)(c->ws + L.zl);
     c->hws = nullptr; c->hws_bytes = 0; c->hiters = nullptr;
     c->gxf = (float *)(c->ws + L.gxf); c->gyf = (float *)(c->ws + L.gyf);
@@ -472,6 +476,8 @@ nh_status nh_init_mesh(const nh_mesh_desc *mesh, const nh_physics *phys, void *d
     if (e == hipSuccess) e = up(c->gx, c->G[0].data(), sizeof(double) * c->G[0].size());
     if (e == hipSuccess) e = up(c->gy, c->G[1].data(), sizeof(double) * c->G[1].size());
     if (e == hipSuccess) e = up(c->gz, c->G[2].data(), sizeof(double) * c->G[2].size());
+    if (e == hipSuccess) e = up(c->xl, c->lx.data(), sizeof(double) * c->lx.size());
+    if (e == hipSuccess) e = up(c->yl, c->ly.data(), sizeof(double) * c->ly.size());
     if (e == hipSuccess) e = up(c->zl, c->lz.data(), sizeof(double) * c->lz.size());
     if (e == hipSuccess) e = up(c->gxf, gxf.data(), sizeof(float) * gxf.size());
     if (e == hipSuccess) e = up(c->gyf, gyf.data(), sizeof(float) * gyf.size());
@@ -919,6 +925,64 @@ nh_status nh_hyperdiffusion(nh_ctx *c, const double *dev_q, double *dev_H)
     const HyperParams hp = hyper_params(c);
     HIPCHK(c, launch_hd_laplace(hp, dev_q, c->hd_tmp, 1.0, false, c->stream));
     HIPCHK(c, launch_hd_laplace(hp, c->hd_tmp, dev_H, -1.0, false, c->stream));
+    return NH_OK;
+}
+
+// ---- RI-velocity diagnostic: workspace carve (per-workgroup partials); nb
+// workgroups per level of ~4096 columns each
+static int ri_chunks(const nh_ctx *c)
+{
+    const int64_t nxy = (int64_t)c->n[0] * c->n[1];
+    return (int)std::min<int64_t>(256, std::max<int64_t>(1, (nxy + 4095) / 4096));
+}
+
+static size_t ri_bytes(const nh_ctx *c, int ns, RiWork *w, char *base)
+{
+    const size_t nb = ri_chunks(c), nz = c->n[2];
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return base ? base + o : nullptr; };
+    double *cpart = (double *)take(sizeof(double) * nz * nb * 3);
+    double *ssum = (double *)take(sizeof(double) * nz * nb * ns);
+    int *scnt = (int *)take(sizeof(int) * nz * nb * ns);
+    double *umax = (double *)take(sizeof(double) * nz * nb);
+    if (w) *w = RiWork{cpart, ssum, scnt, umax};
+    return off;
+}
+
+nh_status nh_ri_workspace_bytes(const nh_ctx *c, int32_t nstrips, size_t *bytes)
+{
+    if (!c || !bytes) return fail(nullptr, NH_EINVAL, "null argument");
+    if (nstrips < 1 || nstrips > kRiMaxStrips) return fail(nullptr, NH_EINVAL, "nstrips must be in [1, %d]", kRiMaxStrips);
+    *bytes = ri_bytes(c, nstrips, nullptr, nullptr);
+    return NH_OK;
+}
+
+nh_status nh_ri_velocity(nh_ctx *c, const double *dev_q, int32_t nstrips, double rmax, int32_t center_given,
+                         double *dev_center, double *dev_ubar, int32_t *dev_count, double *dev_result, void *dev_ws,
+                         size_t bytes)
+{
+    nh_status st = guard(c);
+    if (st) return st;
+    if (nstrips < 1 || nstrips > kRiMaxStrips) return fail(c, NH_EINVAL, "nstrips must be in [1, %d]", kRiMaxStrips);
+    if (!(rmax > 0.0) || !isfinite(rmax)) return fail(c, NH_EINVAL, "rmax must be finite and > 0");
+    if (!dev_q || !dev_center || !dev_ubar || !dev_count || !dev_result || !dev_ws)
+        return fail(c, NH_EINVAL, "null arrays");
+    if (((uintptr_t)dev_ws & 255) != 0) return fail(c, NH_EINVAL, "RI workspace must be 256-byte aligned");
+    const size_t need = ri_bytes(c, nstrips, nullptr, nullptr);
+    if (bytes < need) return fail(c, NH_ESPACE, "RI workspace %zu < %zu bytes", bytes, need);
+    RiWork w;
+    ri_bytes(c, nstrips, &w, (char *)dev_ws);
+    RiParams p{};
+    p.nx = c->n[0]; p.ny = c->n[1]; p.nz = c->n[2];
+    p.nstrips = nstrips;
+    p.nb = ri_chunks(c);
+    p.U = c->U;
+    p.x = c->xl; p.y = c->yl; p.mx = c->mx; p.my = c->my;
+    p.eps = rmax / nstrips;
+    p.xmid = 0.5 * (c->xe.front() + c->xe.back());
+    p.ymid = 0.5 * (c->ye.front() + c->ye.back());
+    HIPCHK(c, launch_ri(p, dev_q, center_given != 0, dev_center, dev_ubar, dev_count, dev_result, c->zl, w,
+                        c->stream));
     return NH_OK;
 }
 

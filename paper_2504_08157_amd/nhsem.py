@@ -116,6 +116,9 @@ _SIGS = {
     "nh_hyperdiffusion_workspace_bytes": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
     "nh_set_hyperdiffusion": (ctypes.c_int32, [_vp, _vp, ctypes.c_double, _vp, ctypes.c_size_t]),
     "nh_hyperdiffusion": (ctypes.c_int32, [_vp, _vp, _vp]),
+    "nh_ri_workspace_bytes": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "nh_ri_velocity": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp,
+                                        _vp, _vp, ctypes.c_size_t]),
     "nh_mlp_last_error": (ctypes.c_int32, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     "nh_mlp_destroy": (ctypes.c_int32, [_vp]),
     "nh_last_error": (ctypes.c_int32, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
@@ -376,6 +379,35 @@ class Context:
             out = torch.empty_like(q)
         self._c(self.lib.nh_hyperdiffusion(self.h, _tptr(q), _tptr(out)))
         return out
+
+    def nh_ri_velocity(self, q, nstrips=50, rmax=None, center=None):
+        """RI-velocity diagnostic of device state q: dict of device tensors
+        center [2][n_z], ubar [n_z][nstrips], count [n_z][nstrips] and result
+        [4] = (u_RI, its strip radius, its level height, max horizontal
+        speed).  rmax defaults to half the smaller horizontal extent; center
+        (a [2][n_z] device tensor) replaces the computed centroid."""
+        import torch
+        m = self.mesh
+        if rmax is None:
+            rmax = 0.5 * min(float(m.xe[-1]) - float(m.xe[0]), float(m.ye[-1]) - float(m.ye[0]))
+        n = ctypes.c_size_t()
+        self._c(self.lib.nh_ri_workspace_bytes(self.h, int(nstrips), ctypes.byref(n)))
+        if getattr(self, "riws", None) is None or self.riws.numel() < n.value:
+            self.riws = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        nz = self.nz
+        given = center is not None
+        if given:
+            if center.dtype != torch.float64 or not center.is_cuda or tuple(center.shape) != (2, nz):
+                raise ValueError("center must be a float64 device tensor of shape (2, n_z)")
+            cen = center.contiguous()
+        else:
+            cen = torch.empty((2, nz), dtype=torch.float64, device="cuda")
+        ubar = torch.empty((nz, nstrips), dtype=torch.float64, device="cuda")
+        count = torch.empty((nz, nstrips), dtype=torch.int32, device="cuda")
+        res = torch.empty(4, dtype=torch.float64, device="cuda")
+        self._c(self.lib.nh_ri_velocity(self.h, _tptr(q), int(nstrips), float(rmax), 1 if given else 0, _tptr(cen),
+                                        _tptr(ubar), _tptr(count), _tptr(res), _tptr(self.riws), n.value))
+        return {"center": cen, "ubar": ubar, "count": count, "result": res}
 
     def nh_lv_apply(self, x, out=None):
         import torch
