@@ -6,5 +6,6 @@ package never imports the GPU library.
 """
 from .oracle import (  # noqa: F401
     Oracle, build, lgl, load, hevi_coefficients, ark2_step, ark2_generic, column_matrix, num_threads,
+    l3_matrix, imex3d_step,
 )
 from . import mlp_oracle  # noqa: F401,E402

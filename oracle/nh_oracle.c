@@ -668,5 +668,81 @@ void or_lv_apply(void *p, const double *x, double *y)
     }
 }
 
+/*
+ * Linear operator of the 3D-IMEX split (Sec. 2.3): the linearisation of S
+ * about the resting reference in all three directions (acoustic and gravity
+ * terms), with p'_L = gamma p0 (rho'/rho0 + theta'/theta0), plus the
+ * implicit upper absorbing layer of the w equation (damping -tau(z) w, the
+ * Klemp form; the Rayleigh damping of u, v and theta' stays explicit):
+ *   (L)_rho'   = - d/dx (rho0 u) - d/dy (rho0 v) - d/dz (rho0 w)
+ *   (L)_u      = - (1/rho0) dp'_L/dx
+ *   (L)_v      = - (1/rho0) dp'_L/dy
+ *   (L)_w      = - (1/rho0) dp'_L/dz - g rho'/rho0 - tau w
+ *   (L)_theta' = - w dtheta0/dz.
+ * Discretised like S (element-local contractions weighted by w_i w_j w_k J,
+ * DSS, divided by M) with the wall conditions of S.
+ */
+void or_l3_apply(void *p, const double *x, double *y)
+{
+    or_ctx *c = (or_ctx *)p;
+    const int n1 = c->n1, np = c->np;
+    const int64_t U = c->U, L = c->L;
+    const double gam = c->cp / c->cv;
+    const int nxy = c->n[0] * c->n[1];
+    if (!c->work) c->work = (double *)malloc(sizeof(double) * NF * c->L);
+    double *r = c->work;
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < c->E; ++e) {
+        double F[5][MAXNP];  /* rho0 u, rho0 v, rho0 w, p'_L, theta0 */
+        int ex = (int)(e % c->nel[0]), ey = (int)((e / c->nel[0]) % c->nel[1]);
+        int ez = (int)(e / ((int64_t)c->nel[0] * c->nel[1]));
+        double hx = c->xe[ex + 1] - c->xe[ex], hy = c->ye[ey + 1] - c->ye[ey], hz = c->ze[ez + 1] - c->ze[ez];
+        double J = hx * hy * hz / 8.0;
+        for (int m = 0; m < np; ++m) {
+            int64_t I = c->intma[e * np + m];
+            int lev = (int)(I / nxy);
+            F[0][m] = c->rho0[lev] * x[1 * U + I];
+            F[1][m] = c->rho0[lev] * x[2 * U + I];
+            F[2][m] = c->rho0[lev] * x[3 * U + I];
+            F[3][m] = gam * c->p0[lev] * (x[0 * U + I] / c->rho0[lev] + x[4 * U + I] / c->theta0[lev]);
+            F[4][m] = c->theta0[lev];
+        }
+        for (int k = 0; k < n1; ++k)
+            for (int j = 0; j < n1; ++j)
+                for (int i = 0; i < n1; ++i) {
+                    int m = i + n1 * (j + n1 * k);
+                    double dx0 = 0.0, dy1 = 0.0, dz2 = 0.0, dxp = 0.0, dyp = 0.0, dzp = 0.0, dzt = 0.0;
+                    for (int l = 0; l < n1; ++l) {
+                        int mx = l + n1 * (j + n1 * k), my = i + n1 * (l + n1 * k), mz = i + n1 * (j + n1 * l);
+                        dx0 += c->D[i * n1 + l] * F[0][mx];
+                        dxp += c->D[i * n1 + l] * F[3][mx];
+                        dy1 += c->D[j * n1 + l] * F[1][my];
+                        dyp += c->D[j * n1 + l] * F[3][my];
+                        dz2 += c->D[k * n1 + l] * F[2][mz];
+                        dzp += c->D[k * n1 + l] * F[3][mz];
+                        dzt += c->D[k * n1 + l] * F[4][mz];
+                    }
+                    double ax = 2.0 / hx, ay = 2.0 / hy, az = 2.0 / hz;
+                    int64_t I = c->intma[e * np + m];
+                    int lev = (int)(I / nxy);
+                    double S[5];
+                    S[0] = -(ax * dx0 + ay * dy1 + az * dz2);
+                    S[1] = -ax * dxp / c->rho0[lev];
+                    S[2] = -ay * dyp / c->rho0[lev];
+                    S[3] = -az * dzp / c->rho0[lev] - c->g * x[0 * U + I] / c->rho0[lev] - c->tau[lev] * x[3 * U + I];
+                    S[4] = -x[3 * U + I] * az * dzt;
+                    double wJ = c->w[i] * c->w[j] * c->w[k] * J;
+                    for (int f = 0; f < 5; ++f) r[f * L + e * np + m] = wJ * S[f];
+                }
+    }
+    for (int f = 0; f < NF; ++f) {
+        double *o = y + f * U;
+        for (int64_t I = 0; I < U; ++I) o[I] = 0.0;
+        for (int64_t m = 0; m < L; ++m) o[c->intma[m]] += r[f * L + m];
+        for (int64_t I = 0; I < U; ++I) o[I] /= c->M[I];
+    }
+    apply_walls(c, y);
+}
+
 /* Threads an OpenMP loop of the oracle uses. */
 int or_num_threads(void) { return omp_get_max_threads(); }

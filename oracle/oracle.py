@@ -63,6 +63,7 @@ def load():
     lib.or_dss.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _dp, _dp]
     lib.or_scatter.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp]
     lib.or_lv_apply.argtypes = [ctypes.c_void_p, _dp, _dp]
+    lib.or_l3_apply.argtypes = [ctypes.c_void_p, _dp, _dp]
     lib.or_num_threads.restype = ctypes.c_int
     lib.or_rhs_sample.restype = ctypes.c_int
     lib.or_rhs_sample.argtypes = [ctypes.c_void_p, ctypes.c_double, _dp, ctypes.c_int64, _lp, _dp]
@@ -222,6 +223,14 @@ class Oracle:
         self.lib.or_lv_apply(self.h, _p(x), _p(y))
         return y.reshape((5,) + self.shape)
 
+    def l3_apply(self, x):
+        """The 3D-IMEX linear operator (acoustic and gravity terms in all
+        directions, implicit damping of w in the absorbing layer)."""
+        x = _c(x).reshape(5, self.U)
+        y = np.zeros((5, self.U))
+        self.lib.or_l3_apply(self.h, _p(x), _p(y))
+        return y.reshape((5,) + self.shape)
+
 
 # ---------------------------------------------------------------- HEVI / ARK2
 def hevi_coefficients():
@@ -292,6 +301,34 @@ def ark2_generic(S, L, solve, t, dt, q):
     for j in range(3):
         out = out + dt * b[j] * Sv[j]
     return out
+
+
+def l3_matrix(orc: Oracle):
+    """Dense matrix of the oracle's 3D linear operator over all 5U unknowns
+    (field-major lattice order), by applying it to unit vectors: for small
+    meshes, where the implicit systems of the 3D-IMEX step are then solved
+    directly."""
+    n = 5 * orc.U
+    Lm = np.zeros((n, n))
+    e = np.zeros(n)
+    for a in range(n):
+        e[a] = 1.0
+        Lm[:, a] = orc.l3_apply(e).reshape(-1)
+        e[a] = 0.0
+    return Lm
+
+
+def imex3d_step(orc: Oracle, Lm, t, dt, q):
+    """One 3D-IMEX ARK2 step (Sec. 2.3): explicit part S - L, implicit L over
+    the whole mesh, every stage system (I - dt At_ii L) Q = rhs solved
+    directly with the dense matrix Lm of l3_matrix.  Returns q^{n+1}."""
+    q = np.asarray(q, dtype=np.float64).reshape((5,) + orc.shape)
+    n = Lm.shape[0]
+
+    def solve(a, rhs):
+        return np.linalg.solve(np.eye(n) - a * Lm, rhs.reshape(-1)).reshape(rhs.shape)
+
+    return ark2_generic(orc.rhs, orc.l3_apply, solve, t, dt, q)
 
 
 def ark2_step(orc: Oracle, Lm, t, dt, q):
