@@ -300,6 +300,47 @@ nh_status nh_hevi_last_solves(nh_ctx *ctx, const double **R2, const double **X2,
                               const double **X3, double *alpha_per_dt, double *reserved);
 
 /* ------------------------------------------------------------------
+ * 3D-IMEX step (Sec. 2.3 with the linear operator over all directions):
+ * L is the linearisation of S about the resting reference in x, y and z
+ * (acoustic and gravity terms, p'_L = gamma p0 (rho'/rho0 + theta'/theta0)),
+ *   L_rho' = -d/dx(rho0 u) - d/dy(rho0 v) - d/dz(rho0 w),
+ *   L_u = -(1/rho0) dp'_L/dx,  L_v = -(1/rho0) dp'_L/dy,
+ *   L_w = -(1/rho0) dp'_L/dz - g rho'/rho0 - tau(z) w,
+ *   L_theta' = -w dtheta0/dz,
+ * discretised like S (DSS'd derivative stencils, the walls of S); the
+ * damping of w in the absorbing layer is implicit, that of u, v and theta'
+ * stays in the explicit part.  Each implicit stage solves one global system
+ * (I - dt At_ii L) Q = R in 5U unknowns by restarted matrix-free GMRES
+ * (classical Gram-Schmidt with a second pass when needed, fixed-order
+ * device reductions).  nh_gmres_opts: restart 1..32, schur must be 0
+ * (NH_EUNSUPPORTED), stop when ||R - A Q||_2 <= rtol ||R||_2 (global).
+ * ------------------------------------------------------------------ */
+
+/* Device workspace of nh_global_solve and nh_imex3d_step for a restart
+   length (restart + 1 Krylov vectors, one scratch vector and, for the step,
+   eight state-sized arrays; 5U doubles each). */
+nh_status nh_imex3d_workspace_bytes(const nh_ctx *ctx, int32_t restart, size_t *bytes);
+
+/* dev_y = L dev_x on device [5][U] arrays (distinct). */
+nh_status nh_l3_apply(nh_ctx *ctx, const double *dev_x, double *dev_y);
+
+/* Solve (I - alpha L) dev_x = dev_b (alpha >= 0) from dev_x0 (NULL: dev_b);
+   dev_b and dev_x distinct.  Synchronises the stream once per Arnoldi step
+   (the small Hessenberg problem is solved on the host).  stats (optional):
+   columns = 1, solves = 1, iters = Arnoldi steps.  NH_ENOCONV when the
+   residual test fails after max_restarts restarts (dev_x holds the last
+   iterate). */
+nh_status nh_global_solve(nh_ctx *ctx, double alpha, const double *dev_b, const double *dev_x0, double *dev_x,
+                          const nh_gmres_opts *opts, void *dev_ws, size_t bytes, nh_solve_stats *stats);
+
+/* One 3D-IMEX ARK2 step of the context state from t to t + dt: the same
+   tableau and stage structure as nh_hevi_step with L in place of L_v (two
+   global solves per step).  stats as for nh_global_solve, summed over the
+   two solves; NH_ENOCONV if either missed rtol (the step is completed). */
+nh_status nh_imex3d_step(nh_ctx *ctx, double t, double dt, const nh_gmres_opts *opts, void *dev_ws, size_t bytes,
+                         nh_solve_stats *stats);
+
+/* ------------------------------------------------------------------
  * Batched instances: many contexts (uneven meshes, orders 2..6, one
  * precision) advanced by SSP-RK3 together.  Per stage, one grouped launch
  * per order covers every instance of that order, its workgroups taking

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnhsem.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["nh_kernels.hip", "nh_hevi.hip", "nh_mlp.hip", "nh_hyper.hip", "nh_ri.hip", "nhsem.cpp"]
+SOURCES = ["nh_kernels.hip", "nh_hevi.hip", "nh_mlp.hip", "nh_hyper.hip", "nh_ri.hip", "nh_imex3d.hip", "nhsem.cpp"]
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # packed FP32 (v_pk_*_f32) is kept off for every kernel

@@ -98,6 +98,28 @@ struct HyperParams {
 hipError_t launch_hd_laplace(const HyperParams &h, const double *q, double *out, double scale, bool accumulate,
                              hipStream_t s);
 
+// ---- 3D-IMEX: linear operator over all directions and the global GMRES
+constexpr int kG3MaxRestart = 32;
+struct L3Params {
+    int nx, ny, nz, N, perx, pery;
+    const double *gx, *gy;   // DSS'd x/y first-derivative stencils [n][2N+1]
+    const double *lev;       // level table [n_z][kLevW]
+    double gamma;
+    HeviParams hv;           // the vertical part (L_v)
+};
+struct G3Work {
+    double *V;      // (restart + 1) Krylov vectors of 5U
+    double *t;      // one 5U vector
+    double *part;   // [1024][35] block partial sums
+    double *red;    // [35] reduced sums
+};
+// out = a x + c L x on [5][U] (out may not alias x)
+hipError_t launch_l3(const L3Params &h, const double *x, double *out, double a, double c, hipStream_t s);
+// (I - alpha L) x = b by restarted GMRES(m); iters = Arnoldi steps, relres =
+// final ||b - A x|| / ||b||
+hipError_t gmres3d(const L3Params &h, const G3Work &w, double alpha, const double *b, const double *x0, double *x,
+                   int m, int max_restarts, double rtol, hipStream_t s, int *iters, double *relres);
+
 // ---- RI-velocity diagnostic
 constexpr int kRiMaxStrips = 4096;
 struct RiParams {

@@ -1092,6 +1092,160 @@ nh_status nh_hevi_step(nh_ctx *c, double t, double dt, const nh_gmres_opts *opts
     return gather_stats(c, c->hiters, 2, stats);
 }
 
+// ---- 3D-IMEX (linear operator over all directions, global GMRES)
+static L3Params l3_params(const nh_ctx *c)
+{
+    L3Params h{};
+    h.nx = c->n[0]; h.ny = c->n[1]; h.nz = c->n[2]; h.N = c->N;
+    h.perx = c->per[0]; h.pery = c->per[1];
+    h.gx = c->gx; h.gy = c->gy; h.lev = c->lev;
+    h.gamma = c->phys.cp / c->phys.cv;
+    h.hv = hevi_params(c);
+    return h;
+}
+
+// workspace: restart + 1 Krylov vectors, one scratch vector, partial sums,
+// then (step only) the ARK2 arrays S_0..2, L_0..1, Q_1..2, R
+static size_t g3_bytes(const nh_ctx *c, int restart, bool step, G3Work *w, double **ark, char *base)
+{
+    const size_t nv = align_up(sizeof(double) * kNF * (size_t)c->U);
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return base ? base + o : nullptr; };
+    G3Work g{};
+    g.V = (double *)take(nv * (restart + 1));
+    g.t = (double *)take(nv);
+    g.part = (double *)take(sizeof(double) * 1024 * 35);
+    g.red = (double *)take(sizeof(double) * 35);
+    if (step)
+        for (int i = 0; i < 8; ++i) {
+            double *a = (double *)take(nv);
+            if (ark) ark[i] = a;
+        }
+    if (w) *w = g;
+    return off;
+}
+
+static nh_status check_g3_opts(nh_ctx *c, const nh_gmres_opts *o)
+{
+    if (!o) return fail(c, NH_EINVAL, "null GMRES options");
+    if (o->restart < 1 || o->restart > kG3MaxRestart)
+        return fail(c, NH_EINVAL, "restart must be in [1, %d]", kG3MaxRestart);
+    if (o->max_restarts < 0) return fail(c, NH_EINVAL, "max_restarts must be >= 0");
+    if (!(o->rtol > 0.0) || !(o->rtol < 1.0)) return fail(c, NH_EINVAL, "rtol must be in (0, 1)");
+    if (o->schur) return fail(c, NH_EUNSUPPORTED, "no Schur form of the global solve");
+    return NH_OK;
+}
+
+static nh_status check_g3_ws(nh_ctx *c, const nh_gmres_opts *o, bool step, void *ws, size_t bytes)
+{
+    if (!ws) return fail(c, NH_EINVAL, "null 3D-IMEX workspace");
+    if (((uintptr_t)ws & 255) != 0) return fail(c, NH_EINVAL, "3D-IMEX workspace must be 256-byte aligned");
+    const size_t need = g3_bytes(c, o->restart, step, nullptr, nullptr, nullptr);
+    if (bytes < need) return fail(c, NH_ESPACE, "3D-IMEX workspace %zu < %zu bytes", bytes, need);
+    return NH_OK;
+}
+
+static void g3_count(nh_solve_stats *st, int it, double relres, double rtol)
+{
+    if (!st) return;
+    st->columns = 1;
+    st->solves += 1;
+    st->iters_total += it;
+    st->iters_max = std::max<int64_t>(st->iters_max, it);
+    if (!(relres <= rtol)) st->not_converged += 1;
+}
+
+nh_status nh_l3_apply(nh_ctx *c, const double *dev_x, double *dev_y)
+{
+    nh_status st = guard(c);
+    if (st) return st;
+    if (!c->have_ref) return fail(c, NH_EINVAL, "reference state not set");
+    if (!dev_x || !dev_y) return fail(c, NH_EINVAL, "null arrays");
+    if (dev_x == dev_y) return fail(c, NH_EINVAL, "dev_x and dev_y must differ");
+    HIPCHK(c, launch_l3(l3_params(c), dev_x, dev_y, 0.0, 1.0, c->stream));
+    return NH_OK;
+}
+
+nh_status nh_imex3d_workspace_bytes(const nh_ctx *c, int32_t restart, size_t *bytes)
+{
+    if (!c || !bytes) return fail(nullptr, NH_EINVAL, "null argument");
+    if (restart < 1 || restart > kG3MaxRestart) return fail(nullptr, NH_EINVAL, "restart must be in [1, %d]", kG3MaxRestart);
+    *bytes = g3_bytes(c, restart, true, nullptr, nullptr, nullptr);
+    return NH_OK;
+}
+
+nh_status nh_global_solve(nh_ctx *c, double alpha, const double *dev_b, const double *dev_x0, double *dev_x,
+                          const nh_gmres_opts *opts, void *dev_ws, size_t bytes, nh_solve_stats *stats)
+{
+    nh_status st = guard(c);
+    if (st) return st;
+    if (!c->have_ref) return fail(c, NH_EINVAL, "reference state not set");
+    if (!dev_b || !dev_x) return fail(c, NH_EINVAL, "null arrays");
+    if (dev_b == dev_x) return fail(c, NH_EINVAL, "dev_b and dev_x must differ");
+    if (!isfinite(alpha) || alpha < 0.0) return fail(c, NH_EINVAL, "alpha must be finite and >= 0");
+    if ((st = check_g3_opts(c, opts))) return st;
+    if ((st = check_g3_ws(c, opts, false, dev_ws, bytes))) return st;
+    G3Work w;
+    g3_bytes(c, opts->restart, false, &w, nullptr, (char *)dev_ws);
+    if (stats) *stats = nh_solve_stats{};
+    int it = 0;
+    double rr = 0.0;
+    HIPCHK(c, gmres3d(l3_params(c), w, alpha, dev_b, dev_x0, dev_x, opts->restart, opts->max_restarts, opts->rtol,
+                      c->stream, &it, &rr));
+    g3_count(stats, it, rr, opts->rtol);
+    if (!(rr <= opts->rtol)) return fail(c, NH_ENOCONV, "global GMRES: relative residual %.3e > %.3e", rr, opts->rtol);
+    return NH_OK;
+}
+
+nh_status nh_imex3d_step(nh_ctx *c, double t, double dt, const nh_gmres_opts *opts, void *dev_ws, size_t bytes,
+                         nh_solve_stats *stats)
+{
+    nh_status st = guard(c);
+    if (st) return st;
+    if (!c->have_ref) return fail(c, NH_EINVAL, "reference state not set");
+    if (!isfinite(t) || !(dt > 0.0) || !isfinite(dt)) return fail(c, NH_EINVAL, "bad time step");
+    if ((st = check_g3_opts(c, opts))) return st;
+    if ((st = check_g3_ws(c, opts, true, dev_ws, bytes))) return st;
+    G3Work w;
+    double *a[8];
+    g3_bytes(c, opts->restart, true, &w, a, (char *)dev_ws);
+    if (stats) *stats = nh_solve_stats{};
+    static const Ark2 ark;
+    const long n = kNF * (long)c->U;
+    const L3Params h = l3_params(c);
+    double *Q1 = c->q[0];
+    double *S[3] = {a[0], a[1], a[2]};
+    double *Lx[2] = {a[3], a[4]};
+    double *Q[3] = {Q1, a[5], a[6]};
+    double *R = a[7];
+    bool missed = false;
+    for (int i = 0; i < 3; ++i) {
+        if (i > 0) {
+            // R = q^n + dt sum_{j<i} [A_ij S_j + (At_ij - A_ij) L_j]
+            LinComb lc{};
+            int ns = 0;
+            for (int j = 0; j < i; ++j) {
+                lc.src[ns] = S[j]; lc.c[ns++] = dt * ark.A[i][j];
+                lc.src[ns] = Lx[j]; lc.c[ns++] = dt * (ark.At[i][j] - ark.A[i][j]);
+            }
+            HIPCHK(c, launch_axpy_multi(n, Q1, ns, lc, R, c->stream));
+            int it = 0;
+            double rr = 0.0;
+            HIPCHK(c, gmres3d(h, w, dt * ark.At[i][i], R, R, Q[i], opts->restart, opts->max_restarts, opts->rtol,
+                              c->stream, &it, &rr));
+            g3_count(stats, it, rr, opts->rtol);
+            missed = missed || !(rr <= opts->rtol);
+        }
+        HIPCHK(c, run_stage(c, t + ark.c[i] * dt, Q[i], nullptr, S[i], 0.0, 0.0, 1.0));
+        if (i < 2) HIPCHK(c, launch_l3(h, Q[i], Lx[i], 0.0, 1.0, c->stream));
+    }
+    LinComb lc{};
+    for (int j = 0; j < 3; ++j) { lc.src[j] = S[j]; lc.c[j] = dt * ark.b[j]; }
+    HIPCHK(c, launch_axpy_multi(n, Q1, 3, lc, Q1, c->stream));
+    if (missed) return fail(c, NH_ENOCONV, "3D-IMEX step: a stage solve missed rtol");
+    return NH_OK;
+}
+
 }  // extern "C"
 
 extern "C" {

@@ -116,6 +116,12 @@ _SIGS = {
     "nh_hyperdiffusion_workspace_bytes": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
     "nh_set_hyperdiffusion": (ctypes.c_int32, [_vp, _vp, ctypes.c_double, _vp, ctypes.c_size_t]),
     "nh_hyperdiffusion": (ctypes.c_int32, [_vp, _vp, _vp]),
+    "nh_imex3d_workspace_bytes": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "nh_l3_apply": (ctypes.c_int32, [_vp, _vp, _vp]),
+    "nh_global_solve": (ctypes.c_int32, [_vp, ctypes.c_double, _vp, _vp, _vp, ctypes.POINTER(nh_gmres_opts), _vp,
+                                         ctypes.c_size_t, ctypes.POINTER(nh_solve_stats)]),
+    "nh_imex3d_step": (ctypes.c_int32, [_vp, ctypes.c_double, ctypes.c_double, ctypes.POINTER(nh_gmres_opts), _vp,
+                                        ctypes.c_size_t, ctypes.POINTER(nh_solve_stats)]),
     "nh_ri_workspace_bytes": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     "nh_ri_velocity": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp,
                                         _vp, _vp, ctypes.c_size_t]),
@@ -435,6 +441,46 @@ class Context:
         st = nh_solve_stats()
         code = self.lib.nh_hevi_step(self.h, float(t), float(dt), ctypes.byref(opts),
                                      guess.h if guess is not None else None, ctypes.byref(st))
+        if check:
+            self._c(code)
+        return st
+
+    def _g3ws(self, restart):
+        import torch
+        n = ctypes.c_size_t()
+        self._c(self.lib.nh_imex3d_workspace_bytes(self.h, int(restart), ctypes.byref(n)))
+        if getattr(self, "g3ws", None) is None or self.g3ws.numel() < n.value:
+            self.g3ws = None
+            self.g3ws = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        return self.g3ws
+
+    def nh_l3_apply(self, x, out=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(x)
+        self._c(self.lib.nh_l3_apply(self.h, _tptr(x), _tptr(out)))
+        return out
+
+    def nh_global_solve(self, alpha, b, x0=None, out=None, restart=20, max_restarts=50, rtol=1e-10, check=True):
+        """(I - alpha L) x = b over the whole mesh (3D linear operator)."""
+        import torch
+        if out is None:
+            out = torch.empty_like(b)
+        ws = self._g3ws(restart)
+        opts = nh_gmres_opts(restart, max_restarts, rtol, 0)
+        st = nh_solve_stats()
+        code = self.lib.nh_global_solve(self.h, float(alpha), _tptr(b), _tptr(x0) if x0 is not None else None,
+                                        _tptr(out), ctypes.byref(opts), _tptr(ws), ws.numel(), ctypes.byref(st))
+        if check:
+            self._c(code)
+        return out, st
+
+    def nh_imex3d_step(self, t, dt, restart=20, max_restarts=50, rtol=1e-10, check=True):
+        ws = self._g3ws(restart)
+        opts = nh_gmres_opts(restart, max_restarts, rtol, 0)
+        st = nh_solve_stats()
+        code = self.lib.nh_imex3d_step(self.h, float(t), float(dt), ctypes.byref(opts), _tptr(ws), ws.numel(),
+                                       ctypes.byref(st))
         if check:
             self._c(code)
         return st

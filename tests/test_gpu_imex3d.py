@@ -1,0 +1,106 @@
+"""GPU 3D-IMEX pieces against the oracle (Sec. 2.3 with the linear operator
+over all three directions): the operator itself, the global GMRES solve and
+the ARK2 step, plus degenerate cases and argument errors."""
+import numpy as np
+import pytest
+
+from paper_2504_08157_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+MESHES = {
+    "periodic_N3": ((3, 3, 2), 3, (True, True), False, 0.0),
+    "walls_stretched_N4_sponge": ((3, 2, 3), 4, (False, False), True, 0.05),
+    "mixed_N5": ((2, 3, 2), 5, (True, False), True, 0.0),
+    "periodic_x1_N3": ((1, 4, 3), 3, (True, True), False, 0.02),
+}
+
+
+def _pair(oracle_mod, nel, N, per, stretched, tau):
+    from paper_2504_08157_amd import nhsem
+    ph = W.Physics(sponge_z0=3e3 if tau else 0.0, sponge_tau=tau)
+    ze = W.stretched_edges(0, 6e3, nel[2], seed=2) if stretched else W.uniform_edges(0, 6e3, nel[2])
+    mesh = W.MeshSpec(nel, N, W.uniform_edges(0, 30e3, nel[0]), W.uniform_edges(0, 24e3, nel[1]), ze, per)
+    ctx, orc = nhsem.Context(mesh, ph), oracle_mod.Oracle(mesh, ph)
+    g, o = ctx.nh_lattice_coords(), orc.lattice_coords()
+    ctx.nh_set_reference(*W.constant_n_reference(g[2]))
+    orc.set_reference(*W.constant_n_reference(o[2]))
+    q = W.smooth_random_state(*o, *W.constant_n_reference(o[2]), seed=7, walls=(not per[0], not per[1]))
+    return ctx, orc, q
+
+
+def _rel(a, b):
+    return max(np.linalg.norm(a[f] - b[f]) / max(np.linalg.norm(b[f]), 1e-300) for f in range(5))
+
+
+@pytest.mark.parametrize("case", list(MESHES))
+def test_l3_apply_parity(oracle_mod, case):
+    import torch
+    ctx, orc, q = _pair(oracle_mod, *MESHES[case])
+    got = ctx.nh_l3_apply(torch.from_numpy(q).cuda()).cpu().numpy()
+    want = orc.l3_apply(q)
+    for f in range(5):
+        n = np.linalg.norm(want[f])
+        if n == 0:
+            assert np.abs(got[f]).max() == 0.0
+        else:
+            assert np.linalg.norm(got[f] - want[f]) <= 1e-12 * n, (case, f)
+
+
+@pytest.mark.parametrize("case", ["periodic_N3", "walls_stretched_N4_sponge"])
+def test_global_solve_against_direct(oracle_mod, case):
+    """GMRES to rtol 1e-12: the residual measured with the oracle's operator
+    is at rtol, and the solution matches the oracle's direct solve to the
+    accuracy that residual allows."""
+    import torch
+    ctx, orc, q = _pair(oracle_mod, *MESHES[case])
+    Lm = oracle_mod.l3_matrix(orc)
+    alpha = 2.0
+    xg, st = ctx.nh_global_solve(alpha, torch.from_numpy(q).cuda(), restart=30, max_restarts=40, rtol=1e-12)
+    x = xg.cpu().numpy()
+    r = q - (x - alpha * orc.l3_apply(x))
+    assert np.linalg.norm(r) <= 2e-12 * np.linalg.norm(q)
+    xd = np.linalg.solve(np.eye(Lm.shape[0]) - alpha * Lm, q.reshape(-1)).reshape(q.shape)
+    assert _rel(x, xd) <= 1e-9
+    assert st.solves == 1 and st.iters_total > 0 and st.not_converged == 0
+
+
+def test_imex3d_step_against_oracle(oracle_mod):
+    """Two 3D-IMEX ARK2 steps (acoustic Courant number ~3) against the
+    oracle's step with direct stage solves."""
+    import torch
+    ctx, orc, q = _pair(oracle_mod, *MESHES["walls_stretched_N4_sponge"])
+    q = 0.3 * q
+    Lm = oracle_mod.l3_matrix(orc)
+    x = orc.lattice_coords()[0]
+    dt = 3 * np.diff(x).min() / 350.0
+    ctx.nh_set_state(torch.from_numpy(q).cuda())
+    want = q.copy()
+    its = 0
+    for k in range(2):
+        st = ctx.nh_imex3d_step(k * dt, dt, restart=30, max_restarts=40, rtol=1e-13)
+        its += st.iters_total
+        assert st.solves == 2 and st.not_converged == 0
+        want = oracle_mod.imex3d_step(orc, Lm, k * dt, dt, want)
+    got = ctx.nh_get_state().cpu().numpy().reshape(q.shape)
+    assert _rel(got, want) <= 1e-10
+    assert its > 0
+
+
+def test_degenerate_and_errors(oracle_mod):
+    import torch
+    from paper_2504_08157_amd import nhsem
+    ctx, orc, q = _pair(oracle_mod, *MESHES["periodic_N3"])
+    b = torch.from_numpy(q).cuda()
+    x, st = ctx.nh_global_solve(0.0, b, restart=5)
+    assert torch.equal(x, b) and st.iters_total == 0
+    z, st = ctx.nh_global_solve(1.0, torch.zeros_like(b), restart=5)
+    assert (z == 0).all() and st.iters_total == 0
+    for kw, code in ((dict(restart=0), nhsem.NH_EINVAL), (dict(restart=33), nhsem.NH_EINVAL),
+                     (dict(rtol=0.0), nhsem.NH_EINVAL)):
+        with pytest.raises(nhsem.NHError) as e:
+            ctx.nh_global_solve(1.0, b, **kw)
+        assert e.value.code == code
+    # a solve that cannot meet rtol in the allowed cycles reports NH_ENOCONV
+    _, st = ctx.nh_global_solve(50.0, b, restart=1, max_restarts=0, rtol=1e-14, check=False)
+    assert st.not_converged == 1
