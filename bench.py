@@ -60,14 +60,17 @@ def parse():
     ap.add_argument("--tile", type=int, default=-1, help="stage-kernel tile variant; -1 = tune by timing")
     ap.add_argument("--copy-mib", type=int, default=1024, help="buffer size of the copy calibration")
     ap.add_argument("--err-steps", type=int, default=600, help="steps of the FP32-vs-FP64 comparison (precision mode)")
-    ap.add_argument("--mode", choices=["rk", "hevi", "batched", "copy", "precision", "hyper", "ri"], default="rk",
+    ap.add_argument("--mode", choices=["rk", "hevi", "batched", "copy", "precision", "hyper", "ri", "imex3d"],
+                    default="rk",
                     help="rk: SSP-RK3 on the per-GPU TC share (headline); hevi: HEVI ARK2 step with and "
                          "without the learned GMRES guess; batched: 48 uneven instances in graph launches; "
                          "copy: a plain device-to-device copy of known size, the calibration run for the "
                          "HBM byte counters; precision: FP32-mixed vs FP64 after --err-steps steps; "
                          "hyper: the tensor hyper-diffusion term alone and the SSP-RK3 step with it; "
-                         "ri: the RI-velocity diagnostic (centroids, 50-strip azimuthal means, u_RI)")
+                         "ri: the RI-velocity diagnostic (centroids, 50-strip azimuthal means, u_RI); "
+                         "imex3d: 3D-IMEX ARK2 steps (global GMRES) against HEVI and explicit RK3")
     ap.add_argument("--members", type=int, default=48)
+    ap.add_argument("--imex-time", type=float, default=8.0, help="simulated seconds of the imex3d comparison")
     ap.add_argument("--mlp-epochs", type=int, default=160, help="training epochs of the column MLP (hevi mode)")
     ap.add_argument("--mlp-random-batches", type=int, default=32,
                     help="batches of random column right-hand sides in the MLP training data (hevi mode)")
@@ -409,6 +412,69 @@ def bench_ri(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_imex3d(args):
+    """3D-IMEX ARK2 (global GMRES(20) to rtol 1e-8 per stage) on the
+    96 x 96 x 16, N = 4 HEVI case against HEVI ARK2 (column GMRES(10), Schur
+    form, rtol 1e-10) and explicit SSP-RK3, each from the same state over the
+    same --imex-time simulated seconds: ms per step, ms per simulated second,
+    Krylov steps per solve, and the state error against an RK3 reference at
+    dt = 0.125 s."""
+    import numpy as np
+    import torch
+    from paper_2504_08157_amd import nhsem
+    from paper_2504_08157_amd import workloads as W
+    w = W.cfg_hevi()
+    ctx, q0 = _tc_context(w, nhsem.NH_FP64)
+    ctx.nh_set_tile(0 if args.tile < 0 else args.tile)
+    T = args.imex_time
+    U = ctx.U
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def run(kind, dt):
+        ctx.nh_set_state(q0)
+        n = int(round(T / dt))
+        its = solves = missed = 0
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        a.record()
+        for k in range(n):
+            if kind == "rk3":
+                ctx.nh_rk_step(k * dt, dt, 1)
+            elif kind == "hevi":
+                st = ctx.nh_hevi_step(k * dt, dt, restart=10, max_restarts=20, rtol=1e-10, schur=True)
+                its += st.iters_total; solves += st.solves * st.columns   # column solves
+            else:
+                st = ctx.nh_imex3d_step(k * dt, dt, restart=20, max_restarts=40, rtol=1e-8, check=False)
+                its += st.iters_total; solves += st.solves; missed += st.not_converged
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        out = {"dt": dt, "steps": n, "ms_per_step": ms / n, "ms_per_simulated_s": ms / T}
+        if solves:
+            out["krylov_steps_per_solve"] = its / solves
+            out["solves_missing_rtol"] = missed
+        return out, ctx.nh_get_state().cpu().numpy().reshape(5, -1)
+
+    ctx.nh_hevi_attach()
+    ref_info, ref = run("rk3", 0.125)
+    res = {}
+    for kind, dt in (("rk3", 0.25), ("hevi", 2.0), ("imex3d", 2.0), ("imex3d", 4.0), ("imex3d", 8.0)):
+        info, qf = run(kind, dt)
+        info["state_rel_err_vs_reference"] = [float(np.linalg.norm(qf[f] - ref[f]) / np.linalg.norm(ref[f]))
+                                              for f in range(5)]
+        res[f"{kind}_dt{dt:g}"] = info
+    best = res["imex3d_dt8"]
+    print(json.dumps({
+        "metric": "DOF-stage updates/s (FP32/batched vs FP64 plain) at stated L2 error; % HBM peak",
+        "value": 5 * U * 3 / (best["ms_per_step"] / 1e3), "unit": "DOF-stage updates/s", "n_gpus": 1,
+        "steps": best["steps"], "warmup": 0, "ms_per_step": best["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "mode": "imex3d", "simulated_s": T,
+                   "gmres": "global GMRES(20), rtol 1e-8 per stage; HEVI: column GMRES(10) Schur form, rtol 1e-10"},
+        "imex3d": res, "reference": {"kind": "rk3", **ref_info},
+    }), flush=True)
+
+
 def bench_copy(args):
     """A plain device copy of args.copy_mib MiB, timed; under the FETCH_SIZE /
     WRITE_SIZE counters it gives the counter-to-byte factor of this GPU."""
@@ -450,6 +516,8 @@ def main():
         return bench_hyper(args)
     if args.mode == "ri":
         return bench_ri(args)
+    if args.mode == "imex3d":
+        return bench_imex3d(args)
     import numpy as np
     import torch
     from paper_2504_08157_amd import nhsem

@@ -256,7 +256,7 @@ typedef struct {
 } nh_gmres_opts;
 typedef struct {
     int64_t columns;          /* columns per solve */
-    int64_t solves;           /* column solves counted (columns x solves per call) */
+    int64_t solves;           /* solves of the call, each over `columns` columns */
     int64_t iters_total;      /* Arnoldi steps summed over all column solves */
     int64_t iters_max;        /* most Arnoldi steps of one column solve */
     int64_t not_converged;    /* column solves that missed rtol */
