@@ -432,7 +432,7 @@ def bench_imex3d(args):
 
     def run(kind, dt):
         ctx.nh_set_state(q0)
-        n = int(round(T / dt))
+        n = max(1, int(round(T / dt)))
         its = solves = missed = 0
         torch.cuda.synchronize()
         a, b = ev(), ev()
@@ -449,7 +449,7 @@ def bench_imex3d(args):
         b.record()
         torch.cuda.synchronize()
         ms = a.elapsed_time(b)
-        out = {"dt": dt, "steps": n, "ms_per_step": ms / n, "ms_per_simulated_s": ms / T}
+        out = {"dt": dt, "steps": n, "ms_per_step": ms / n, "ms_per_simulated_s": ms / (n * dt)}
         if solves:
             out["krylov_steps_per_solve"] = its / solves
             out["solves_missing_rtol"] = missed
@@ -458,12 +458,13 @@ def bench_imex3d(args):
     ctx.nh_hevi_attach()
     ref_info, ref = run("rk3", 0.125)
     res = {}
-    for kind, dt in (("rk3", 0.25), ("hevi", 2.0), ("imex3d", 2.0), ("imex3d", 4.0), ("imex3d", 8.0)):
+    runs = [("rk3", 0.25), ("hevi", 2.0)] + [("imex3d", d) for d in (2.0, 4.0, 8.0) if d <= T + 1e-9]
+    for kind, dt in runs:
         info, qf = run(kind, dt)
         info["state_rel_err_vs_reference"] = [float(np.linalg.norm(qf[f] - ref[f]) / np.linalg.norm(ref[f]))
                                               for f in range(5)]
         res[f"{kind}_dt{dt:g}"] = info
-    best = res["imex3d_dt8"]
+    best = res[f"imex3d_dt{runs[-1][1]:g}"]
     print(json.dumps({
         "metric": "DOF-stage updates/s (FP32/batched vs FP64 plain) at stated L2 error; % HBM peak",
         "value": 5 * U * 3 / (best["ms_per_step"] / 1e3), "unit": "DOF-stage updates/s", "n_gpus": 1,

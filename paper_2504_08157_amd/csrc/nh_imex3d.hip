@@ -132,15 +132,22 @@ __global__ void __launch_bounds__(kKryThreads) kry_dots_kernel(const double *__r
     }
 }
 
-// out[j] = sum over blocks of part[b][j], j <= nv
-__global__ void __launch_bounds__(kKryThreads) kry_final_kernel(const double *__restrict__ part, int nb, int nv,
+// out[j] = sum over blocks of part[b][j]: workgroup j sums quantity j, each
+// thread a fixed strided subset of the blocks, then a fixed tree
+__global__ void __launch_bounds__(kKryThreads) kry_final_kernel(const double *__restrict__ part, int nb,
                                                                 double *__restrict__ out)
 {
-    for (int j = threadIdx.x; j <= nv; j += kKryThreads) {
-        double s = 0.0;
-        for (int b = 0; b < nb; ++b) s += part[(long)b * (kKryMaxV + 1) + j];
-        out[j] = s;
+    __shared__ double red[kKryThreads];
+    const int j = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kKryThreads) s += part[(long)b * (kKryMaxV + 1) + j];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = kKryThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) out[j] = red[0];
 }
 
 struct KryCoef {
@@ -184,7 +191,7 @@ struct Kry {
     // host copies of nv + 1 reduced quantities
     hipError_t fetch(int nv, double *host)
     {
-        hipLaunchKernelGGL(kry_final_kernel, dim3(1), dim3(kKryThreads), 0, s, w.part, kKryBlocks, nv, w.red);
+        hipLaunchKernelGGL(kry_final_kernel, dim3(nv + 1), dim3(kKryThreads), 0, s, w.part, kKryBlocks, w.red);
         hipError_t e = hipMemcpyAsync(host, w.red, sizeof(double) * (nv + 1), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         return e;
