@@ -413,9 +413,10 @@ def bench_ri(args):
 
 
 def bench_imex3d(args):
-    """3D-IMEX ARK2 (global GMRES(20) to rtol 1e-8 per stage) on the
-    96 x 96 x 16, N = 4 HEVI case against HEVI ARK2 (column GMRES(10), Schur
-    form, rtol 1e-10) and explicit SSP-RK3, each from the same state over the
+    """3D-IMEX ARK2 (global GMRES(20) to rtol 1e-8 per stage, plain and
+    right-preconditioned by the column solves) on the 96 x 96 x 16, N = 4
+    HEVI case against HEVI ARK2 (column GMRES(10), Schur form, rtol 1e-10)
+    and explicit SSP-RK3, each from the same state over the
     same --imex-time simulated seconds: ms per step, ms per simulated second,
     Krylov steps per solve, and the state error against an RK3 reference at
     dt = 0.125 s."""
@@ -444,7 +445,8 @@ def bench_imex3d(args):
                 st = ctx.nh_hevi_step(k * dt, dt, restart=10, max_restarts=20, rtol=1e-10, schur=True)
                 its += st.iters_total; solves += st.solves * st.columns   # column solves
             else:
-                st = ctx.nh_imex3d_step(k * dt, dt, restart=20, max_restarts=40, rtol=1e-8, check=False)
+                st = ctx.nh_imex3d_step(k * dt, dt, restart=20, max_restarts=40, rtol=1e-8, check=False,
+                                        precondition=kind == "imex3d_pc")
                 its += st.iters_total; solves += st.solves; missed += st.not_converged
         b.record()
         torch.cuda.synchronize()
@@ -458,20 +460,22 @@ def bench_imex3d(args):
     ctx.nh_hevi_attach()
     ref_info, ref = run("rk3", 0.125)
     res = {}
-    runs = [("rk3", 0.25), ("hevi", 2.0)] + [("imex3d", d) for d in (2.0, 4.0, 8.0) if d <= T + 1e-9]
+    runs = [("rk3", 0.25), ("hevi", 2.0)] + [(k, d) for k in ("imex3d", "imex3d_pc") for d in (2.0, 4.0, 8.0)
+                                            if d <= T + 1e-9]
     for kind, dt in runs:
         info, qf = run(kind, dt)
         info["state_rel_err_vs_reference"] = [float(np.linalg.norm(qf[f] - ref[f]) / np.linalg.norm(ref[f]))
                                               for f in range(5)]
         res[f"{kind}_dt{dt:g}"] = info
-    best = res[f"imex3d_dt{runs[-1][1]:g}"]
+    best = res[f"imex3d_pc_dt{runs[-1][1]:g}"]
     print(json.dumps({
         "metric": "DOF-stage updates/s (FP32/batched vs FP64 plain) at stated L2 error; % HBM peak",
         "value": 5 * U * 3 / (best["ms_per_step"] / 1e3), "unit": "DOF-stage updates/s", "n_gpus": 1,
         "steps": best["steps"], "warmup": 0, "ms_per_step": best["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": w.name, "mode": "imex3d", "simulated_s": T,
-                   "gmres": "global GMRES(20), rtol 1e-8 per stage; HEVI: column GMRES(10) Schur form, rtol 1e-10"},
+                   "gmres": "global GMRES(20), rtol 1e-8 per stage (imex3d_pc: flexible, column solves as right "
+                            "preconditioner); HEVI: column GMRES(10) Schur form, rtol 1e-10"},
         "imex3d": res, "reference": {"kind": "rk3", **ref_info},
     }), flush=True)
 

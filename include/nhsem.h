@@ -253,6 +253,11 @@ typedef struct {
                                  reconstructed); same stopping test on the full
                                  system; restart 10 and n_z <= 130 only
                                  (NH_EUNSUPPORTED otherwise) */
+    int32_t precondition;     /* global (3D-IMEX) solves only, ignored by the
+                                 column solves: 1 = right-precondition with the
+                                 column systems (I - alpha L_v), solved by the
+                                 column GMRES(10) to rtol 1e-6 (flexible GMRES:
+                                 the preconditioned vectors are kept) */
 } nh_gmres_opts;
 typedef struct {
     int64_t columns;          /* columns per solve */
@@ -317,8 +322,9 @@ nh_status nh_hevi_last_solves(nh_ctx *ctx, const double **R2, const double **X2,
  * ------------------------------------------------------------------ */
 
 /* Device workspace of nh_global_solve and nh_imex3d_step for a restart
-   length (restart + 1 Krylov vectors, one scratch vector and, for the step,
-   eight state-sized arrays; 5U doubles each). */
+   length (restart + 1 Krylov vectors, restart preconditioned vectors, one
+   scratch vector and, for the step, eight state-sized arrays; 5U doubles
+   each). */
 nh_status nh_imex3d_workspace_bytes(const nh_ctx *ctx, int32_t restart, size_t *bytes);
 
 /* dev_y = L dev_x on device [5][U] arrays (distinct). */

@@ -13,7 +13,8 @@
 // solved by restarted GMRES with classical Gram-Schmidt (a second pass when
 // the kept norm falls below 1e-2 of the vector's), its dot products reduced
 // in a fixed order on the device and its small Hessenberg problem on the
-// host.
+// host; optionally right-preconditioned by the column systems of the 1D
+// split (flexible GMRES, since those are solved iteratively).
 #include "nh_internal.h"
 
 #include <cmath>
@@ -219,8 +220,19 @@ struct Kry {
 
 }  // namespace
 
+// z = (I - alpha L_v)^-1 v column by column (column GMRES(10) to rtol 1e-6;
+// the Schur form where the column is short enough); u, v rows are copied
+static hipError_t column_precond(const L3Params &h, double alpha, const double *v, double *z, hipStream_t s)
+{
+    GmresArgs g{};
+    g.b = v; g.x0 = nullptr; g.x = z; g.alpha = alpha; g.rtol = 1e-6;
+    g.restart = kGmresRegM; g.max_restarts = 10; g.iters = nullptr;
+    g.schur = h.nz - 2 <= 64 * kGmresSchurSlots ? 1 : 0;
+    return launch_gmres(h.hv, g, s);
+}
+
 hipError_t gmres3d(const L3Params &h, const G3Work &w, double alpha, const double *b, const double *x0, double *x,
-                   int m, int max_restarts, double rtol, hipStream_t s, int *iters, double *relres)
+                   int m, int max_restarts, double rtol, bool precond, hipStream_t s, int *iters, double *relres)
 {
     const long n = (long)kNF * h.nx * h.ny * h.nz;
     Kry k{h, w, s, n};
@@ -257,7 +269,14 @@ hipError_t gmres3d(const L3Params &h, const G3Work &w, double alpha, const doubl
         bool conv = false;
         for (; j < m; ++j) {
             double *vj = V + (long)j * n, *vn = V + (long)(j + 1) * n;
-            if ((e = launch_l3(h, vj, vn, 1.0, -alpha, s)) != hipSuccess) return e;
+            // flexible GMRES: z_j = M^-1 v_j kept, the new direction is A z_j
+            const double *zj = vj;
+            if (precond) {
+                double *zz = w.Z + (long)j * n;
+                if ((e = column_precond(h, alpha, vj, zz, s)) != hipSuccess) return e;
+                zj = zz;
+            }
+            if ((e = launch_l3(h, zj, vn, 1.0, -alpha, s)) != hipSuccess) return e;
             // classical Gram-Schmidt, a second pass when the kept norm is small
             double hc[kKryMaxV + 1], h2[kKryMaxV + 1];
             if ((e = k.dots(V, j + 1, vn, hc)) != hipSuccess) return e;
@@ -306,7 +325,7 @@ hipError_t gmres3d(const L3Params &h, const G3Work &w, double alpha, const doubl
         }
         std::vector<double> ny(j);
         for (int i = 0; i < j; ++i) ny[i] = -y[i];
-        if ((e = k.axpy(V, j, ny.data(), x, x, 1.0, false, nullptr)) != hipSuccess) return e;
+        if ((e = k.axpy(precond ? w.Z : V, j, ny.data(), x, x, 1.0, false, nullptr)) != hipSuccess) return e;
         (void)conv;
     }
     // final residual after the last cycle

@@ -109,6 +109,7 @@ struct L3Params {
 };
 struct G3Work {
     double *V;      // (restart + 1) Krylov vectors of 5U
+    double *Z;      // restart preconditioned vectors (flexible GMRES)
     double *t;      // one 5U vector
     double *part;   // [1024][35] block partial sums
     double *red;    // [35] reduced sums
@@ -117,8 +118,9 @@ struct G3Work {
 hipError_t launch_l3(const L3Params &h, const double *x, double *out, double a, double c, hipStream_t s);
 // (I - alpha L) x = b by restarted GMRES(m); iters = Arnoldi steps, relres =
 // final ||b - A x|| / ||b||
+// precond: right-precondition with the column systems (I - alpha L_v)
 hipError_t gmres3d(const L3Params &h, const G3Work &w, double alpha, const double *b, const double *x0, double *x,
-                   int m, int max_restarts, double rtol, hipStream_t s, int *iters, double *relres);
+                   int m, int max_restarts, double rtol, bool precond, hipStream_t s, int *iters, double *relres);
 
 // ---- RI-velocity diagnostic
 constexpr int kRiMaxStrips = 4096;

@@ -1104,8 +1104,9 @@ static L3Params l3_params(const nh_ctx *c)
     return h;
 }
 
-// workspace: restart + 1 Krylov vectors, one scratch vector, partial sums,
-// then (step only) the ARK2 arrays S_0..2, L_0..1, Q_1..2, R
+// workspace: restart + 1 Krylov vectors, restart preconditioned vectors, one
+// scratch vector, partial sums, then (step only) the ARK2 arrays S_0..2,
+// L_0..1, Q_1..2, R
 static size_t g3_bytes(const nh_ctx *c, int restart, bool step, G3Work *w, double **ark, char *base)
 {
     const size_t nv = align_up(sizeof(double) * kNF * (size_t)c->U);
@@ -1113,6 +1114,7 @@ static size_t g3_bytes(const nh_ctx *c, int restart, bool step, G3Work *w, doubl
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return base ? base + o : nullptr; };
     G3Work g{};
     g.V = (double *)take(nv * (restart + 1));
+    g.Z = (double *)take(nv * restart);
     g.t = (double *)take(nv);
     g.part = (double *)take(sizeof(double) * 1024 * 35);
     g.red = (double *)take(sizeof(double) * 35);
@@ -1133,6 +1135,9 @@ static nh_status check_g3_opts(nh_ctx *c, const nh_gmres_opts *o)
     if (o->max_restarts < 0) return fail(c, NH_EINVAL, "max_restarts must be >= 0");
     if (!(o->rtol > 0.0) || !(o->rtol < 1.0)) return fail(c, NH_EINVAL, "rtol must be in (0, 1)");
     if (o->schur) return fail(c, NH_EUNSUPPORTED, "no Schur form of the global solve");
+    if (o->precondition != 0 && o->precondition != 1) return fail(c, NH_EINVAL, "precondition must be 0 or 1");
+    if (o->precondition && 3 * c->n[2] > 256 && c->n[2] - 2 > 64 * kGmresSchurSlots)
+        return fail(c, NH_EUNSUPPORTED, "column preconditioner needs n_z <= 130");
     return NH_OK;
 }
 
@@ -1191,7 +1196,7 @@ nh_status nh_global_solve(nh_ctx *c, double alpha, const double *dev_b, const do
     int it = 0;
     double rr = 0.0;
     HIPCHK(c, gmres3d(l3_params(c), w, alpha, dev_b, dev_x0, dev_x, opts->restart, opts->max_restarts, opts->rtol,
-                      c->stream, &it, &rr));
+                      opts->precondition != 0, c->stream, &it, &rr));
     g3_count(stats, it, rr, opts->rtol);
     if (!(rr <= opts->rtol)) return fail(c, NH_ENOCONV, "global GMRES: relative residual %.3e > %.3e", rr, opts->rtol);
     return NH_OK;
@@ -1232,7 +1237,7 @@ nh_status nh_imex3d_step(nh_ctx *c, double t, double dt, const nh_gmres_opts *op
             int it = 0;
             double rr = 0.0;
             HIPCHK(c, gmres3d(h, w, dt * ark.At[i][i], R, R, Q[i], opts->restart, opts->max_restarts, opts->rtol,
-                              c->stream, &it, &rr));
+                              opts->precondition != 0, c->stream, &it, &rr));
             g3_count(stats, it, rr, opts->rtol);
             missed = missed || !(rr <= opts->rtol);
         }

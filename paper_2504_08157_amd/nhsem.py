@@ -52,7 +52,7 @@ class nh_physics(ctypes.Structure):
 
 class nh_gmres_opts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("max_restarts", ctypes.c_int32), ("rtol", ctypes.c_double),
-                ("schur", ctypes.c_int32)]
+                ("schur", ctypes.c_int32), ("precondition", ctypes.c_int32)]
 
 
 class nh_solve_stats(ctypes.Structure):
@@ -461,13 +461,14 @@ class Context:
         self._c(self.lib.nh_l3_apply(self.h, _tptr(x), _tptr(out)))
         return out
 
-    def nh_global_solve(self, alpha, b, x0=None, out=None, restart=20, max_restarts=50, rtol=1e-10, check=True):
+    def nh_global_solve(self, alpha, b, x0=None, out=None, restart=20, max_restarts=50, rtol=1e-10, check=True,
+                        precondition=False):
         """(I - alpha L) x = b over the whole mesh (3D linear operator)."""
         import torch
         if out is None:
             out = torch.empty_like(b)
         ws = self._g3ws(restart)
-        opts = nh_gmres_opts(restart, max_restarts, rtol, 0)
+        opts = nh_gmres_opts(restart, max_restarts, rtol, 0, int(bool(precondition)))
         st = nh_solve_stats()
         code = self.lib.nh_global_solve(self.h, float(alpha), _tptr(b), _tptr(x0) if x0 is not None else None,
                                         _tptr(out), ctypes.byref(opts), _tptr(ws), ws.numel(), ctypes.byref(st))
@@ -475,9 +476,9 @@ class Context:
             self._c(code)
         return out, st
 
-    def nh_imex3d_step(self, t, dt, restart=20, max_restarts=50, rtol=1e-10, check=True):
+    def nh_imex3d_step(self, t, dt, restart=20, max_restarts=50, rtol=1e-10, check=True, precondition=False):
         ws = self._g3ws(restart)
-        opts = nh_gmres_opts(restart, max_restarts, rtol, 0)
+        opts = nh_gmres_opts(restart, max_restarts, rtol, 0, int(bool(precondition)))
         st = nh_solve_stats()
         code = self.lib.nh_imex3d_step(self.h, float(t), float(dt), ctypes.byref(opts), _tptr(ws), ws.numel(),
                                        ctypes.byref(st))

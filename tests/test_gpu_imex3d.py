@@ -47,16 +47,19 @@ def test_l3_apply_parity(oracle_mod, case):
             assert np.linalg.norm(got[f] - want[f]) <= 1e-12 * n, (case, f)
 
 
+@pytest.mark.parametrize("pc", [False, True], ids=["plain", "column_preconditioned"])
 @pytest.mark.parametrize("case", ["periodic_N3", "walls_stretched_N4_sponge"])
-def test_global_solve_against_direct(oracle_mod, case):
-    """GMRES to rtol 1e-12: the residual measured with the oracle's operator
-    is at rtol, and the solution matches the oracle's direct solve to the
-    accuracy that residual allows."""
+def test_global_solve_against_direct(oracle_mod, case, pc):
+    """GMRES to rtol 1e-12 (plain, or right-preconditioned by the column
+    solves): the residual measured with the oracle's operator is at rtol,
+    and the solution matches the oracle's direct solve to the accuracy that
+    residual allows."""
     import torch
     ctx, orc, q = _pair(oracle_mod, *MESHES[case])
     Lm = oracle_mod.l3_matrix(orc)
     alpha = 2.0
-    xg, st = ctx.nh_global_solve(alpha, torch.from_numpy(q).cuda(), restart=30, max_restarts=40, rtol=1e-12)
+    xg, st = ctx.nh_global_solve(alpha, torch.from_numpy(q).cuda(), restart=30, max_restarts=40, rtol=1e-12,
+                                 precondition=pc)
     x = xg.cpu().numpy()
     r = q - (x - alpha * orc.l3_apply(x))
     assert np.linalg.norm(r) <= 2e-12 * np.linalg.norm(q)
@@ -65,7 +68,8 @@ def test_global_solve_against_direct(oracle_mod, case):
     assert st.solves == 1 and st.iters_total > 0 and st.not_converged == 0
 
 
-def test_imex3d_step_against_oracle(oracle_mod):
+@pytest.mark.parametrize("pc", [False, True], ids=["plain", "column_preconditioned"])
+def test_imex3d_step_against_oracle(oracle_mod, pc):
     """Two 3D-IMEX ARK2 steps (acoustic Courant number ~3) against the
     oracle's step with direct stage solves."""
     import torch
@@ -78,7 +82,7 @@ def test_imex3d_step_against_oracle(oracle_mod):
     want = q.copy()
     its = 0
     for k in range(2):
-        st = ctx.nh_imex3d_step(k * dt, dt, restart=30, max_restarts=40, rtol=1e-13)
+        st = ctx.nh_imex3d_step(k * dt, dt, restart=30, max_restarts=40, rtol=1e-13, precondition=pc)
         its += st.iters_total
         assert st.solves == 2 and st.not_converged == 0
         want = oracle_mod.imex3d_step(orc, Lm, k * dt, dt, want)
@@ -130,8 +134,9 @@ def test_full_size_hevi_case(oracle_mod):
         n = np.linalg.norm(want[f])
         assert np.linalg.norm(got[f] - want[f]) <= 1e-12 * max(n, 1e-300), f
     alpha = 0.29 * 2.0
-    x, st = ctx.nh_global_solve(alpha, qd, restart=20, max_restarts=20, rtol=1e-10)
-    xh = x.cpu().numpy()
-    r = q - (xh - alpha * orc.l3_apply(xh))
-    assert np.linalg.norm(r) <= 1.5e-10 * np.linalg.norm(q)
-    assert st.not_converged == 0
+    for pc in (False, True):
+        x, st = ctx.nh_global_solve(alpha, qd, restart=20, max_restarts=20, rtol=1e-10, precondition=pc)
+        xh = x.cpu().numpy()
+        r = q - (xh - alpha * orc.l3_apply(xh))
+        assert np.linalg.norm(r) <= 1.5e-10 * np.linalg.norm(q), pc
+        assert st.not_converged == 0
