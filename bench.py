@@ -28,19 +28,23 @@ COUNTERS = os.path.join(ROOT, "profiles", "stage_kernel_tc_128x128x20_N4_fp64_hb
 KERNEL_SRC = os.path.join(ROOT, "paper_2504_08157_amd", "csrc", "nh_kernels.hip")
 
 
-def measured_traffic(tile):
-    """HBM bytes per stage launch from the committed FETCH_SIZE / WRITE_SIZE
-    summary (copy-calibrated), or None when the stage kernel source or the
-    tile differs from the profiled one."""
+HD_COUNTERS = os.path.join(ROOT, "profiles", "hd_laplace_tc_128x128x20_N4_hbm_counters.txt")
+HD_SRC = os.path.join(ROOT, "paper_2504_08157_amd", "csrc", "nh_hyper.hip")
+
+
+def measured_traffic(tile, counters=COUNTERS, src=KERNEL_SRC):
+    """HBM bytes per launch from a committed FETCH_SIZE / WRITE_SIZE summary
+    (copy-calibrated), or None when the kernel source (or the stage tile)
+    differs from the profiled one."""
     import hashlib
     try:
         kv = {}
-        for line in open(COUNTERS):
+        for line in open(counters):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.split()[0]
-        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-        if kv.get("source_sha256") != sha or int(kv.get("tile_variant", -1)) != tile:
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if kv.get("source_sha256") != sha or (tile is not None and int(kv.get("tile_variant", -1)) != tile):
             return None
         return float(kv["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -350,7 +354,9 @@ def bench_hyper(args):
         "hyperdiffusion": {"ms_hq": ms_hq, "ms_step_with": ms_with, "ms_step_without": ms_without,
                            "step_cost_ratio": ms_with / ms_without},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(None, HD_COUNTERS, HD_SRC) if w.name == "tc_128x128x20_N4" else None,
+                     "traffic_unit": "HBM bytes per plain launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "algorithmic_bytes_per_launch": bytes_hq / 2,
                      "kernel": "hd_laplace_tile_kernel (plain form, two launches per H_q)",
                      "avg_launch_ms": ms_hq / 2},
