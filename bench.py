@@ -513,7 +513,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
-              f"described in DESIGN.md", file=sys.stderr)
+              f"a design, not built", file=sys.stderr)
         sys.exit(2)
     if args.mode == "hevi":
         return bench_hevi(args)
