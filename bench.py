@@ -474,6 +474,23 @@ def bench_imex3d(args):
                                               for f in range(5)]
         res[f"{kind}_dt{dt:g}"] = info
     best = res[f"imex3d_pc_dt{runs[-1][1]:g}"]
+    # roofline of one application of the 3D operator (L_v kernel + horizontal
+    # pass): per node the L_v kernel reads 3 fields and writes 5 rows, the
+    # horizontal pass reads 5 fields and 3 L_v rows and writes 5 (168 B)
+    xq = ctx.nh_get_state()
+    yq = torch.empty_like(xq)
+    for _ in range(3):
+        ctx.nh_l3_apply(xq, yq)
+    torch.cuda.synchronize()
+    a, b = ev(), ev()
+    a.record()
+    for _ in range(20):
+        ctx.nh_l3_apply(xq, yq)
+    b.record()
+    torch.cuda.synchronize()
+    l3_ms = a.elapsed_time(b) / 20
+    l3_bytes = 168 * U
+    l3_gbs = l3_bytes / (l3_ms / 1e3) / 1e9
     print(json.dumps({
         "metric": "DOF-stage updates/s (FP32/batched vs FP64 plain) at stated L2 error; % HBM peak",
         "value": 5 * U * 3 / (best["ms_per_step"] / 1e3), "unit": "DOF-stage updates/s", "n_gpus": 1,
@@ -483,6 +500,10 @@ def bench_imex3d(args):
                    "gmres": "global GMRES(20), rtol 1e-8 per stage (imex3d_pc: flexible, column solves as right "
                             "preconditioner); HEVI: column GMRES(10) Schur form, rtol 1e-10"},
         "imex3d": res, "reference": {"kind": "rk3", **ref_info},
+        "roofline": {"bound": "hbm", "achieved": l3_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": l3_gbs / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_call": l3_bytes,
+                     "kernel": "application of the 3D operator (lv_apply_kernel + l3_combine_kernel)",
+                     "avg_call_ms": l3_ms},
     }), flush=True)
 
 
