@@ -502,7 +502,7 @@ def bench_imex3d(args):
         "imex3d": res, "reference": {"kind": "rk3", **ref_info},
         "roofline": {"bound": "hbm", "achieved": l3_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": l3_gbs / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_call": l3_bytes,
-                     "kernel": "application of the 3D operator (lv_apply_kernel + l3_combine_kernel)",
+                     "kernel": "application of the 3D operator (lv_apply_kernel + l3_tile_kernel)",
                      "avg_call_ms": l3_ms},
     }), flush=True)
 

@@ -7,7 +7,8 @@
 //   (L)_w      = - (1/rho0) dp'_L/dz - g rho'/rho0 - tau(z) w
 //   (L)_theta' = - w dtheta0/dz,        p'_L = gamma p0 (rho'/rho0 + theta'/theta0),
 // the vertical terms from the column-walking L_v kernel, the horizontal ones
-// from the DSS'd x/y derivative stencils of the explicit path, the damping
+// from the DSS'd x/y derivative stencils of the explicit path (a tiled pass
+// with the x/y planes staged in LDS), the damping
 // of w in the absorbing layer implicit (the Klemp form of an upper sponge).
 // Each stage system (I - a L) x = b is one global system in 5U unknowns,
 // solved by restarted GMRES with classical Gram-Schmidt (a second pass when
@@ -23,55 +24,143 @@
 namespace nh {
 
 // out[f] = a x[f] + c (lv[f] + horizontal and damping terms of L x) at every
-// node; lv holds L_v x (u, v rows zero).  Walls: u rows zero at x walls, v
-// rows at y walls, w rows at the bottom and top.  lv may alias out.
-__global__ void __launch_bounds__(256) l3_combine_kernel(L3Params h, const double *__restrict__ x, const double *lv,
-                                                         double *out, double a, double c)
+// node, lv holding L_v x (u, v rows zero; lv may alias out, x may not).
+// Walls: u rows zero at x walls, v rows at y walls, w rows at the bottom and
+// top.  A workgroup of 64 x 8 lattice columns walks a chunk of kL3KZ levels, staging per level the planes of u, v and p'_L of
+// its tile plus an N-wide x/y halo in LDS (two buffers, one barrier per
+// level); the x and y taps come from LDS, the node's own rho', w, theta' and
+// L_v rows from coalesced loads.  All loads of a level are issued two levels
+// ahead into register slots indexed at compile time.  Chunks of levels give
+// enough workgroups on meshes of few columns.
+constexpr int kL3TX = 64, kL3TY = 8, kL3KZ = 8, kL3P = 2;
+
+__device__ __forceinline__ int l3_xcd_block(int b, int n)
 {
-    const long nxy = (long)h.nx * h.ny, U = nxy * h.nz;
-    const int NC = 2 * h.N + 1;
-    for (long I = blockIdx.x * (long)blockDim.x + threadIdx.x; I < U; I += (long)gridDim.x * blockDim.x) {
-        const int ix = (int)(I % h.nx), iy = (int)((I / h.nx) % h.ny), iz = (int)(I / nxy);
-        const double *Lv = h.lev + (long)iz * kLevW;
-        const double rho0 = Lv[0], p0 = Lv[2], tau = Lv[4], irho0 = Lv[7], ith0 = Lv[8];
-        const double gp = h.gamma * p0;
-        double dux = 0.0, dpx = 0.0, dvy = 0.0, dpy = 0.0;
-        for (int o = 0; o < NC; ++o) {
-            const double cf = h.gx[(long)ix * NC + o];
-            if (cf == 0.0) continue;
-            int j = ix + o - h.N;
-            if (j < 0 || j >= h.nx) {
-                if (!h.perx) continue;
-                j += j < 0 ? h.nx : -h.nx;
-            }
-            const long J = I + (j - ix);
-            dux += cf * x[U + J];
-            dpx += cf * (gp * (x[J] * irho0 + x[4 * U + J] * ith0));
+    const int q = n >> 3, r = n & 7, x = b & 7, j = b >> 3;
+    return x * q + (x < r ? x : r) + j;
+}
+
+template <int I, int E, class F>
+__device__ __forceinline__ void l3_unrolled(F &&f)
+{
+    if constexpr (I < E) {
+        f(std::integral_constant<int, I>{});
+        l3_unrolled<I + 1, E>(f);
+    }
+}
+
+template <int N>
+__global__ void __launch_bounds__(kL3TX * kL3TY) l3_tile_kernel(L3Params h, const double *__restrict__ x,
+                                                                const double *lv, double *out, double a, double c,
+                                                                const double *__restrict__ lev)
+{
+    constexpr int NC = 2 * N + 1, PX = kL3TX + 2 * N, PY = kL3TY + 2 * N, PS = PX * PY;
+    constexpr int NT = kL3TX * kL3TY, NS = (PS + NT - 1) / NT, P = kL3P;
+    __shared__ double tile[2][3][PS];   // u, v, p'_L
+    const long nxy = (long)h.nx * h.ny;
+    const int nz = h.nz;
+    const long U = nxy * nz;
+    const int ntx = (h.nx + kL3TX - 1) / kL3TX, nty = (h.ny + kL3TY - 1) / kL3TY;
+    const int t = l3_xcd_block(blockIdx.x, gridDim.x);
+    const int tt = t % (ntx * nty), kc = t / (ntx * nty);
+    const int kb = kc * kL3KZ, ke = kb + kL3KZ < nz ? kb + kL3KZ : nz;
+    const int tx = threadIdx.x % kL3TX, ty = threadIdx.x / kL3TX;
+    const int x0 = (tt % ntx) * kL3TX, y0 = (tt / ntx) * kL3TY;
+    const int ix = x0 + tx, iy = y0 + ty;
+    const bool own = ix < h.nx && iy < h.ny;
+    const long col = own ? ix + (long)iy * h.nx : 0;
+    double cx[NC], cy[NC];
+#pragma unroll
+    for (int o = 0; o < NC; ++o) {
+        cx[o] = own ? h.gx[(long)ix * NC + o] : 0.0;
+        cy[o] = own ? h.gy[(long)iy * NC + o] : 0.0;
+    }
+    long sc[NS];
+    bool sv[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        const int s = threadIdx.x + i * NT;
+        int jx = x0 - N + s % PX, jy = y0 - N + s / PX;
+        bool ok = s < PS;
+        if (jx < 0 || jx >= h.nx) {
+            ok = ok && h.perx;
+            jx = ((jx % h.nx) + h.nx) % h.nx;
         }
-        for (int o = 0; o < NC; ++o) {
-            const double cf = h.gy[(long)iy * NC + o];
-            if (cf == 0.0) continue;
-            int j = iy + o - h.N;
-            if (j < 0 || j >= h.ny) {
-                if (!h.pery) continue;
-                j += j < 0 ? h.ny : -h.ny;
-            }
-            const long J = I + (long)(j - iy) * h.nx;
-            dvy += cf * x[2 * U + J];
-            dpy += cf * (gp * (x[J] * irho0 + x[4 * U + J] * ith0));
+        if (jy < 0 || jy >= h.ny) {
+            ok = ok && h.pery;
+            jy = ((jy % h.ny) + h.ny) % h.ny;
         }
-        double Lr = lv[I] - rho0 * (dux + dvy);
-        double Lu = -irho0 * dpx, Lvv = -irho0 * dpy;
-        double Lw = lv[3 * U + I] - tau * x[3 * U + I];
-        const double Lt = lv[4 * U + I];
-        if (!h.perx && (ix == 0 || ix == h.nx - 1)) Lu = 0.0;
-        if (!h.pery && (iy == 0 || iy == h.ny - 1)) Lvv = 0.0;
-        if (iz == 0 || iz == h.nz - 1) Lw = 0.0;
-        out[I] = a * x[I] + c * Lr;
-        out[U + I] = a * x[U + I] + c * Lu;
-        out[2 * U + I] = a * x[2 * U + I] + c * Lvv;
-        out[3 * U + I] = a * x[3 * U + I] + c * Lw;
-        out[4 * U + I] = a * x[4 * U + I] + c * Lt;
+        sv[i] = ok;
+        sc[i] = ok ? jx + (long)jy * h.nx : 0;
+    }
+    auto level = [&](int k) -> long { return (long)(k < ke ? k : ke - 1) * nxy; };
+    // slot contents: staged rho', u, v, theta' of NS nodes; own rho', w,
+    // theta' of x and of L_v x
+    double sr[P][NS], su[P][NS], sv2[P][NS], st[P][NS], ox[P][3], ol[P][3];
+    auto load = [&](int p, int k) {
+        const long L = level(k);
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+            sr[p][i] = x[sc[i] + L];
+            su[p][i] = x[U + sc[i] + L];
+            sv2[p][i] = x[2 * U + sc[i] + L];
+            st[p][i] = x[4 * U + sc[i] + L];
+        }
+        ox[p][0] = x[col + L];
+        ox[p][1] = x[3 * U + col + L];
+        ox[p][2] = x[4 * U + col + L];
+        ol[p][0] = lv[col + L];
+        ol[p][1] = lv[3 * U + col + L];
+        ol[p][2] = lv[4 * U + col + L];
+    };
+    l3_unrolled<0, P>([&](auto J) { load(decltype(J)::value, kb + decltype(J)::value); });
+    for (int k0 = kb; k0 < ke; k0 += P) {
+        l3_unrolled<0, P>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            const int k = k0 + j;
+            const double *Lv = lev + level(k) / nxy * kLevW;
+            const double rho0 = Lv[0], p0 = Lv[2], tau = Lv[4], irho0 = Lv[7], ith0 = Lv[8];
+            const double gp = h.gamma * p0;
+            double(*T)[PS] = tile[(k - kb) & 1];
+#pragma unroll
+            for (int i = 0; i < NS; ++i) {
+                const int sidx = threadIdx.x + i * NT;
+                if (sidx < PS) {
+                    T[0][sidx] = sv[i] ? su[j][i] : 0.0;
+                    T[1][sidx] = sv[i] ? sv2[j][i] : 0.0;
+                    T[2][sidx] = sv[i] ? gp * (sr[j][i] * irho0 + st[j][i] * ith0) : 0.0;
+                }
+            }
+            const double xr = ox[j][0], xw = ox[j][1], xt = ox[j][2];
+            const double lr = ol[j][0], lw = ol[j][1], lt = ol[j][2];
+            load(j, k + P);
+            __syncthreads();
+            double dux = 0.0, dpx = 0.0, dvy = 0.0, dpy = 0.0;
+#pragma unroll
+            for (int o = 0; o < NC; ++o) {
+                const int jx = (ty + N) * PX + tx + o, jy = (ty + o) * PX + tx + N;
+                dux += cx[o] * T[0][jx];
+                dpx += cx[o] * T[2][jx];
+                dvy += cy[o] * T[1][jy];
+                dpy += cy[o] * T[2][jy];
+            }
+            const int jo = (ty + N) * PX + tx + N;
+            const double xu = T[0][jo], xv = T[1][jo];
+            double Lr = lr - rho0 * (dux + dvy);
+            double Lu = -irho0 * dpx, Lvv = -irho0 * dpy;
+            double Lw = lw - tau * xw;
+            if (!h.perx && (ix == 0 || ix == h.nx - 1)) Lu = 0.0;
+            if (!h.pery && (iy == 0 || iy == h.ny - 1)) Lvv = 0.0;
+            if (k == 0 || k == nz - 1) Lw = 0.0;
+            if (own && k < ke) {
+                const long I = col + (long)k * nxy;
+                out[I] = a * xr + c * Lr;
+                out[U + I] = a * xu + c * Lu;
+                out[2 * U + I] = a * xv + c * Lvv;
+                out[3 * U + I] = a * xw + c * Lw;
+                out[4 * U + I] = a * xt + c * lt;
+            }
+        });
     }
 }
 
@@ -79,11 +168,17 @@ hipError_t launch_l3(const L3Params &h, const double *x, double *out, double a, 
 {
     hipError_t e = launch_lv_apply(h.hv, x, out, s, true);
     if (e != hipSuccess) return e;
-    const long U = (long)h.nx * h.ny * h.nz;
-    long blocks = (U + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(l3_combine_kernel, dim3((unsigned)blocks), dim3(256), 0, s, h, x, (const double *)out, out,
-                       a, c);
+    const int ntx = (h.nx + kL3TX - 1) / kL3TX, nty = (h.ny + kL3TY - 1) / kL3TY;
+    const int nkc = (h.nz + kL3KZ - 1) / kL3KZ;
+    const dim3 grid((unsigned)(ntx * nty * nkc)), blk(kL3TX * kL3TY);
+    switch (h.N) {
+    case 2: hipLaunchKernelGGL(l3_tile_kernel<2>, grid, blk, 0, s, h, x, (const double *)out, out, a, c, h.lev); break;
+    case 3: hipLaunchKernelGGL(l3_tile_kernel<3>, grid, blk, 0, s, h, x, (const double *)out, out, a, c, h.lev); break;
+    case 4: hipLaunchKernelGGL(l3_tile_kernel<4>, grid, blk, 0, s, h, x, (const double *)out, out, a, c, h.lev); break;
+    case 5: hipLaunchKernelGGL(l3_tile_kernel<5>, grid, blk, 0, s, h, x, (const double *)out, out, a, c, h.lev); break;
+    case 6: hipLaunchKernelGGL(l3_tile_kernel<6>, grid, blk, 0, s, h, x, (const double *)out, out, a, c, h.lev); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
