@@ -13,6 +13,10 @@ MESHES = {
     "walls_stretched_N4_sponge": ((3, 2, 3), 4, (False, False), True, 0.05),
     "mixed_N5": ((2, 3, 2), 5, (True, False), True, 0.0),
     "periodic_x1_N3": ((1, 4, 3), 3, (True, True), False, 0.02),
+    "walls_N2": ((7, 5, 4), 2, (False, False), False, 0.0),
+    "periodic_stretched_N6": ((3, 2, 2), 6, (True, True), True, 0.03),
+    # 69 x 40 columns, 17 levels: several 64 x 8 tiles and 8-level chunks, ragged
+    "multi_tile_N4": ((17, 10, 4), 4, (False, True), True, 0.0),
 }
 
 
