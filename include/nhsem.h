@@ -354,7 +354,8 @@ nh_status nh_imex3d_step(nh_ctx *ctx, double t, double dt, const nh_gmres_opts *
  * captured once into a hipGraph and replayed (the per-stage descriptors of
  * the next K steps are uploaded with one copy before each replay).  Each
  * instance computes bitwise the same as nh_rk_step on its own.
- * Restrictions: reference set on every context, forcing only on theta'.
+ * Restrictions: reference set on every context, forcing only on theta',
+ * hyper-diffusion off (NH_EUNSUPPORTED at create and step otherwise).
  * The batch owns no context; contexts must outlive it.
  * ------------------------------------------------------------------ */
 typedef struct nh_batch nh_batch;

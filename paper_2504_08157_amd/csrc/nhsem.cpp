@@ -1671,6 +1671,7 @@ nh_status nh_batch_create(nh_ctx *const *ctxs, int32_t n, int32_t steps_per_grap
         if (c->sticky) return fail(nullptr, NH_ESTATE, "context %d is in an error state", i);
         if (!c->have_ref) return fail(nullptr, NH_EINVAL, "context %d has no reference state", i);
         if (c->precision != prec) return fail(nullptr, NH_EINVAL, "all instances must share one precision");
+        if (c->hd_on) return fail(nullptr, NH_EUNSUPPORTED, "batched stages do not add the hyper-diffusion term");
         for (int f = 0; f < 4; ++f)
             if (c->nsnap[f]) return fail(nullptr, NH_EUNSUPPORTED, "batched stages fuse only the theta' forcing");
         for (int j = 0; j < i; ++j)
@@ -1735,8 +1736,11 @@ nh_status nh_batch_step(nh_batch *b, double t, double dt, int32_t nsteps)
         return bfail(b, NH_EINVAL, "nsteps must be a multiple of the %d steps per graph", b->K);
     if (!isfinite(t) || !isfinite(dt)) return bfail(b, NH_EINVAL, "bad time arguments");
     const int n = (int)b->ctx.size();
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < n; ++i) {
         if (b->ctx[i]->sticky) return bfail(b, NH_ESTATE, "context %d in an error state", i);
+        if (b->ctx[i]->hd_on)
+            return bfail(b, NH_EUNSUPPORTED, "context %d has hyper-diffusion on: batched stages do not add it", i);
+    }
     const double ca[3] = {0.0, 0.75, 1.0 / 3.0}, cb[3] = {1.0, 0.25, 2.0 / 3.0}, cc[3] = {1.0, 0.25, 2.0 / 3.0};
     const double ct[3] = {0.0, 1.0, 0.5};
     for (int r = 0; r < nsteps / b->K; ++r) {

@@ -67,3 +67,13 @@ def test_batch_rejects_bad_arguments():
     b = nhsem.Batch([ctx], steps_per_graph=3)
     with pytest.raises(nhsem.NHError):
         b.nh_batch_step(0.0, 1.0, 4)
+    # hyper-diffusion is not part of the batched stages: refused at step and create
+    ctx.nh_set_hyperdiffusion((1e-6, 1e-6, 1e-6), 1.0)
+    with pytest.raises(nhsem.NHError) as e:
+        b.nh_batch_step(0.0, 1.0, 3)
+    assert e.value.code == nhsem.NH_EUNSUPPORTED
+    with pytest.raises(nhsem.NHError) as e:
+        nhsem.Batch([ctx])
+    assert e.value.code == nhsem.NH_EUNSUPPORTED
+    ctx.nh_set_hyperdiffusion(None, 0.0)
+    nhsem.Batch([ctx]).nh_batch_step(0.0, 1.0, 1)
