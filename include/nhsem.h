@@ -230,7 +230,9 @@ nh_status nh_ri_workspace_bytes(const nh_ctx *ctx, int32_t nstrips, size_t *byte
                      speed max sqrt(u^2 + v^2).
    dev_ws: borrowed, 256-byte aligned, nh_ri_workspace_bytes.  Strip sums
    are accumulated in an unordered way, so means may differ in the last bits
-   between calls. */
+   between calls.  Errors: NH_EINVAL (nstrips outside 1..4096, rmax not
+   finite and > 0, a null array, a misaligned workspace), NH_ESPACE (workspace
+   too small); nothing is launched then. */
 nh_status nh_ri_velocity(nh_ctx *ctx, const double *dev_q, int32_t nstrips, double rmax, int32_t center_given,
                          double *dev_center, double *dev_ubar, int32_t *dev_count, double *dev_result,
                          void *dev_ws, size_t bytes);
@@ -327,7 +329,8 @@ nh_status nh_hevi_last_solves(nh_ctx *ctx, const double **R2, const double **X2,
    each). */
 nh_status nh_imex3d_workspace_bytes(const nh_ctx *ctx, int32_t restart, size_t *bytes);
 
-/* dev_y = L dev_x on device [5][U] arrays (distinct). */
+/* dev_y = L dev_x on device [5][U] arrays (distinct; NH_EINVAL otherwise or
+   without a reference state). */
 nh_status nh_l3_apply(nh_ctx *ctx, const double *dev_x, double *dev_y);
 
 /* Solve (I - alpha L) dev_x = dev_b (alpha >= 0) from dev_x0 (NULL: dev_b);
@@ -335,7 +338,10 @@ nh_status nh_l3_apply(nh_ctx *ctx, const double *dev_x, double *dev_y);
    (the small Hessenberg problem is solved on the host).  stats (optional):
    columns = 1, solves = 1, iters = Arnoldi steps.  NH_ENOCONV when the
    residual test fails after max_restarts restarts (dev_x holds the last
-   iterate). */
+   iterate); NH_EINVAL for bad options (restart outside 1..32, rtol outside
+   (0, 1), negative max_restarts or alpha, aliased arrays), NH_EUNSUPPORTED
+   for schur != 0 or a column preconditioner on n_z > 130, NH_ESPACE for a
+   small workspace. */
 nh_status nh_global_solve(nh_ctx *ctx, double alpha, const double *dev_b, const double *dev_x0, double *dev_x,
                           const nh_gmres_opts *opts, void *dev_ws, size_t bytes, nh_solve_stats *stats);
 
