@@ -194,7 +194,10 @@ nh_status nh_hyperdiffusion_workspace_bytes(const nh_ctx *ctx, size_t *bytes);
    256-byte aligned, at least nh_hyperdiffusion_workspace_bytes) and adds
    H_q(q^s) to the tendency in nh_rhs, nh_rk_step and the explicit part of
    nh_hevi_step.  c == NULL disables it.  NH_EUNSUPPORTED if the order of the
-   element extents (x, y, z) changes across the mesh. */
+   element extents (x, y, z) changes across the mesh; NH_EINVAL for c_i < 0
+   or not finite, dt not finite and > 0, a null or misaligned workspace;
+   NH_ESPACE for a small one.  The workspace must stay valid while the term
+   is on. */
 nh_status nh_set_hyperdiffusion(nh_ctx *ctx, const double *c, double dt, void *dev_ws, size_t bytes);
 
 /* dev_H = H_q(dev_q) on device [5][U] arrays (distinct); needs
