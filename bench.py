@@ -32,10 +32,18 @@ HD_COUNTERS = os.path.join(ROOT, "profiles", "hd_laplace_tc_128x128x20_N4_hbm_co
 HD_SRC = os.path.join(ROOT, "paper_2504_08157_amd", "csrc", "nh_hyper.hip")
 
 
-def measured_traffic(tile, counters=COUNTERS, src=KERNEL_SRC):
-    """HBM bytes per launch from a committed FETCH_SIZE / WRITE_SIZE summary
-    (copy-calibrated), or None when the kernel source (or the stage tile)
-    differs from the profiled one."""
+RI_COUNTERS = os.path.join(ROOT, "profiles", "ri_velocity_tc_128x128x20_N4_hbm_counters.txt")
+RI_SRC = os.path.join(ROOT, "paper_2504_08157_amd", "csrc", "nh_ri.hip")
+L3_COUNTERS = os.path.join(ROOT, "profiles", "l3_apply_tc_hevi_96x96x16_N4_hbm_counters.txt")
+L3_SRC = (os.path.join(ROOT, "paper_2504_08157_amd", "csrc", "nh_imex3d.hip"),
+          os.path.join(ROOT, "paper_2504_08157_amd", "csrc", "nh_hevi.hip"))
+
+
+def measured_traffic(tile, counters=COUNTERS, src=KERNEL_SRC, key="traffic_bytes_per_launch"):
+    """HBM bytes per launch (or call) from a committed FETCH_SIZE / WRITE_SIZE
+    summary (copy-calibrated), or None when the kernel source (the sources
+    hashed in order, for a tuple) or the stage tile differs from the profiled
+    one."""
     import hashlib
     try:
         kv = {}
@@ -43,10 +51,12 @@ def measured_traffic(tile, counters=COUNTERS, src=KERNEL_SRC):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.split()[0]
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if kv.get("source_sha256") != sha or (tile is not None and int(kv.get("tile_variant", -1)) != tile):
+        h = hashlib.sha256()
+        for path in (src if isinstance(src, tuple) else (src,)):
+            h.update(open(path, "rb").read())
+        if kv.get("source_sha256") != h.hexdigest() or (tile is not None and int(kv.get("tile_variant", -1)) != tile):
             return None
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv[key])
     except (OSError, KeyError, ValueError):
         return None
 
@@ -400,7 +410,11 @@ def bench_ri(args):
         "config": {"workload": w.name, "mode": "ri", "nstrips": 50, "rk_steps_before": args.warmup},
         "ri": {"u_ri": res[0], "r_ri": res[1], "z_ri": res[2], "u_max": res[3]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_call": bytes_call,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(None, RI_COUNTERS, RI_SRC, "traffic_bytes_per_call")
+                     if w.name == "tc_128x128x20_N4" else None,
+                     "traffic_unit": "HBM bytes per call (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_bytes_per_call": bytes_call,
                      "kernel": "RI diagnostic (centroid and strip passes with their final reductions)"},
     }
     if not args.no_cpu_baseline:
@@ -501,7 +515,10 @@ def bench_imex3d(args):
                             "preconditioner); HEVI: column GMRES(10) Schur form, rtol 1e-10"},
         "imex3d": res, "reference": {"kind": "rk3", **ref_info},
         "roofline": {"bound": "hbm", "achieved": l3_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": l3_gbs / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_call": l3_bytes,
+                     "frac": l3_gbs / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(None, L3_COUNTERS, L3_SRC, "traffic_bytes_per_call"),
+                     "traffic_unit": "HBM bytes per call (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_bytes_per_call": l3_bytes,
                      "kernel": "application of the 3D operator (lv_apply_kernel + l3_tile_kernel)",
                      "avg_call_ms": l3_ms},
     }), flush=True)
