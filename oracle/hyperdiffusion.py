@@ -24,7 +24,11 @@ Readings (the paper does not fix them):
     r_a = - sum_n w_n |J_n| grad psi_a(x_n) . tau_n grad q(x_n), then direct
     stiffness summation and the inverse of the assembled diagonal mass;
     no boundary term (natural condition on walls; periodic directions wrap);
-  * H_q is applied to all five prognostic fields.
+  * H_q is applied to all five prognostic fields;
+  * the no-flux walls are imposed strongly on the whole tendency, H_q
+    included: after H_q is formed, the wall-normal velocity rows (u on the
+    x walls, v on the y walls, w at the bottom and the top) are set to zero,
+    as the right-hand side does after its DSS (hyperdiffusion_tendency).
 
 Everything is evaluated element by element from the node coordinates; no
 assumption on the element shape is made.
@@ -148,3 +152,26 @@ def hyperdiffusion(geo, q, c, dt, alpha=2):
     for _ in range(alpha):
         r = weak_laplacian(geo, r, c, dt, alpha)
     return (-1) ** (alpha + 1) * r
+
+
+def wall_mask(orc, F):
+    """Zero the wall-normal velocity rows of a tendency F [5][U]: u where the
+    lattice x index is 0 or n_x - 1 on a non-periodic x, v likewise in y, w
+    at the bottom and top levels (the no-flux condition imposed strongly)."""
+    F = np.array(F, dtype=np.float64).reshape((5,) + orc.shape)
+    per = [bool(v) for v in orc.mesh.periodic]
+    if not per[0]:
+        F[1][:, :, 0] = 0.0
+        F[1][:, :, -1] = 0.0
+    if not per[1]:
+        F[2][:, 0, :] = 0.0
+        F[2][:, -1, :] = 0.0
+    F[3][0] = 0.0
+    F[3][-1] = 0.0
+    return F.reshape(5, -1)
+
+
+def hyperdiffusion_tendency(geo, q, c, dt, alpha=2):
+    """The contribution of H_q to dq/dt: H_q of all five fields with the
+    wall-normal velocity rows zeroed."""
+    return wall_mask(geo.orc, hyperdiffusion(geo, q, c, dt, alpha))

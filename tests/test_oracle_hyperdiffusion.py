@@ -110,3 +110,69 @@ def test_fourier_mode_convergence(oracle_mod):
         L = HD.weak_laplacian(geo, q, c, dt)
         err.append(np.linalg.norm(L + tau * k ** 2 * q) / np.linalg.norm(tau * k ** 2 * q))
     assert err[0] <= 1e-4 and err[1] <= err[0] / 12, err
+
+
+def _walled_state(orc, seed):
+    x, y, z = orc.lattice_coords()
+    q = W.smooth_random_state(x, y, z, *W.constant_n_reference(z), seed=seed, walls=(True, True))
+    # wall-normal velocities exactly zero (sin(pi) is not)
+    q[1][:, :, [0, -1]] = 0.0
+    q[2][:, [0, -1], :] = 0.0
+    q[3][[0, -1]] = 0.0
+    return q.reshape(5, -1)
+
+
+def test_wall_mask_matches_rhs_walls(oracle_mod):
+    """The mask zeroes exactly the rows the C oracle's right-hand side zeroes
+    after its DSS (an independent implementation of the no-flux walls):
+    masking its output changes nothing, and the mask of a tendency of ones
+    removes 2 n_y n_z u rows, 2 n_x n_z v rows and 2 n_x n_y w rows."""
+    geo, orc = _geo(oracle_mod, (3, 2, 2), (False, False), N=3)
+    orc.set_reference(*W.constant_n_reference(orc.lattice_coords()[2]))
+    q = _walled_state(orc, 11)
+    R = orc.rhs(0.0, q).reshape(5, -1)
+    assert np.array_equal(HD.wall_mask(orc, R), R)
+    ones = HD.wall_mask(orc, np.ones((5, orc.U)))
+    nz, ny, nx = orc.shape
+    assert (ones == 0).sum(axis=1).tolist() == [0, 2 * ny * nz, 2 * nx * nz, 2 * nx * ny, 0]
+    # periodic x and y: only w keeps its rows at bottom and top
+    _, orp = _geo(oracle_mod, (3, 2, 2), (True, True), N=3)
+    onesp = HD.wall_mask(orp, np.ones((5, orp.U)))
+    assert (onesp == 0).sum(axis=1).tolist() == [0, 0, 0, 2 * orp.nx * orp.ny, 0]
+
+
+def test_masked_tendency_keeps_walls_and_mass(oracle_mod):
+    """Three SSP-RK3 steps of dq/dt = S + H_q with the wall rows of H_q
+    zeroed keep u, v on the side walls and w at the bottom and top exactly
+    zero and the mass-weighted sum of rho' constant to 1e-13 of its size.
+    Adding H_q unmasked instead puts velocity on the walls, and the mass then
+    drifts by far more (the divergence's sum is the boundary flux)."""
+    geo, orc = _geo(oracle_mod, (3, 2, 2), (False, False), N=3)
+    orc.set_physics(W.Physics(f=5e-5))
+    orc.set_reference(*W.constant_n_reference(orc.lattice_coords()[2]))
+    c, hdt, dt = (1e-6, 2e-6, 5e-6), 1.0, 0.5
+    M = orc.mass().reshape(-1)
+    q0 = _walled_state(orc, 12)
+
+    def run(masked):
+        def F(t, y):
+            H = HD.hyperdiffusion(geo, y, c, hdt)
+            H = HD.wall_mask(orc, H) if masked else H
+            return orc.rhs(t, y).reshape(5, -1) + H
+        y = q0.copy()
+        for s in range(3):
+            t = s * dt
+            y1 = y + dt * F(t, y)
+            y2 = 0.75 * y + 0.25 * (y1 + dt * F(t + dt, y1))
+            y = y / 3.0 + 2.0 / 3.0 * (y2 + dt * F(t + 0.5 * dt, y2))
+        return y.reshape((5,) + orc.shape)
+
+    m0 = (M * q0[0]).sum()
+    scale = (M * np.abs(q0[0])).sum()
+    y = run(True)
+    assert np.all(y[1][:, :, [0, -1]] == 0.0) and np.all(y[2][:, [0, -1], :] == 0.0)
+    assert np.all(y[3][[0, -1]] == 0.0)
+    assert abs((M * y[0].reshape(-1)).sum() - m0) <= 1e-13 * scale
+    yu = run(False)
+    assert np.abs(yu[1][:, :, [0, -1]]).max() > 1e-6
+    assert abs((M * yu[0].reshape(-1)).sum() - m0) > 1e-9 * scale
