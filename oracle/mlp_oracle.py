@@ -79,6 +79,11 @@ def mse(y, t):
     return ((y - t) ** 2).mean()
 
 
+def mse_grad(y, t):
+    """Gradient of mse(y, t) with respect to y."""
+    return 2.0 * (y - t) / y.size
+
+
 def adam(w, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
     m = b1 * m + (1 - b1) * g
     v = b2 * v + (1 - b2) * g * g

@@ -122,3 +122,74 @@ def test_column_features_bounded_when_a_field_vanishes():
     np.testing.assert_allclose(feat[0, k] / feat[0, 2 * 65 + k],
                                np.interp(MO.canonical_levels()[k] * 1000.0, z, b[0, :, 0] / D[0]) /
                                np.interp(MO.canonical_levels()[k] * 1000.0, z, b[2, :, 0] / D[2]), rtol=1e-12)
+
+
+def test_forward_closed_form():
+    """A network with a handful of nonzero weights, evaluated by hand with
+    sigmoid(ln 3) = 3/4, so silu(ln 3) = (3/4) ln 3 and silu(-ln 3) =
+    -(1/4) ln 3.  Hidden unit 3 reads input 7 (W1[3, 7]: row = unit, column
+    = input), unit 5 of layer 2 reads unit 3 (W2[5, 3]) with a bias that
+    brings it back to ln 3, output 9 reads unit 5 of layer 2 (W3[9, 5]) and,
+    through the bypass, input 7 (S[9, 7]); output 10 is a bias only, output
+    11 a negative pre-activation.  A transposed operand, a dropped bias or
+    bypass moves or changes these values."""
+    ln3 = np.log(3.0)
+    W1, b1, W2, b2, W3, b3, S = [np.zeros(s) for s in MO.SHAPES]
+    W1[3, 7] = 1.0
+    W1[4, 7] = -1.0
+    W2[5, 3] = 1.0
+    b2[5] = 0.25 * ln3                      # (3/4) ln 3 + (1/4) ln 3 = ln 3
+    W3[9, 5] = 2.0
+    b3[9] = 0.1
+    S[9, 7] = -1.0
+    b3[10] = 0.7
+    W2[6, 4] = 4.0                          # 4 silu(-ln 3) = -ln 3
+    W3[11, 6] = 1.0
+    w = MO.flatten([W1, b1, W2, b2, W3, b3, S])
+    x = np.zeros((2, MO.IN))
+    x[0, 7] = ln3
+    x[1, 2] = 5.0                           # reaches nothing
+    y, (xc, z1, h1, z2, h2) = MO.forward(w, x)
+    np.testing.assert_allclose(h1[0, 3], 0.75 * ln3, rtol=1e-15)
+    np.testing.assert_allclose(h1[0, 4], -0.25 * ln3, rtol=1e-15)
+    want = np.zeros(MO.OUT)
+    want[9] = 2.0 * 0.75 * ln3 + 0.1 - ln3
+    want[10] = 0.7
+    want[11] = -0.25 * ln3                  # silu(-ln 3)
+    np.testing.assert_allclose(y[0], want, rtol=1e-14, atol=1e-15)
+    # row 1: every layer-1 unit is silu(0) = 0, so unit 5 of layer 2 sees
+    # only its bias, silu((1/4) ln 3), and unit 6 is silu(0) = 0
+    want1 = np.zeros(MO.OUT)
+    zb = 0.25 * ln3
+    want1[9] = 2.0 * zb / (1.0 + np.exp(-zb)) + 0.1
+    want1[10] = 0.7
+    np.testing.assert_allclose(y[1], want1, rtol=1e-14, atol=1e-15)
+
+
+def test_mse_gradient_central_differences():
+    rng = np.random.default_rng(2)
+    y = rng.normal(size=(4, 7))
+    t = rng.normal(size=(4, 7))
+    g = MO.mse_grad(y, t)
+    h = 1e-6
+    for i in np.ndindex(y.shape):
+        yp = y.copy(); yp[i] += h
+        ym = y.copy(); ym[i] -= h
+        fd = (MO.mse(yp, t) - MO.mse(ym, t)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-9, (i, fd, g[i])
+
+
+def test_adam_second_step_closed_forms():
+    """Constant gradient: the bias-corrected moments equal g and g^2 at every
+    step, so each step moves by lr sign(g).  Gradient g then -g: the second
+    step's corrected moments are -(1 - b1)/(1 + b1) g and g^2, a move of
+    +lr (1 - b1)/(1 + b1) sign(g)."""
+    rng = np.random.default_rng(3)
+    w = rng.normal(size=40); g = rng.normal(size=40)
+    lr, b1, b2 = 1e-2, 0.9, 0.999
+    m = v = np.zeros(40)
+    w1, m1, v1 = MO.adam(w, g, m, v, 1, lr, b1, b2, eps=0.0)
+    w2, _, _ = MO.adam(w1, g, m1, v1, 2, lr, b1, b2, eps=0.0)
+    np.testing.assert_allclose(w2, w - 2 * lr * np.sign(g), rtol=0, atol=1e-14)
+    w2b, _, _ = MO.adam(w1, -g, m1, v1, 2, lr, b1, b2, eps=0.0)
+    np.testing.assert_allclose(w2b, w1 + lr * (1 - b1) / (1 + b1) * np.sign(g), rtol=0, atol=1e-14)
