@@ -193,14 +193,17 @@ nh_status nh_hyperdiffusion_workspace_bytes(const nh_ctx *ctx, size_t *bytes);
    extent) and time step dt: computes the operator rows into dev_ws (borrowed,
    256-byte aligned, at least nh_hyperdiffusion_workspace_bytes) and adds
    H_q(q^s) to the tendency in nh_rhs, nh_rk_step and the explicit part of
-   nh_hevi_step.  c == NULL disables it.  NH_EUNSUPPORTED if the order of the
+   nh_hevi_step, with its wall-normal velocity rows zeroed (u on x walls, v
+   on y walls, w at the bottom and top: the no-flux walls are imposed on the
+   whole tendency).  c == NULL disables it.  NH_EUNSUPPORTED if the order of the
    element extents (x, y, z) changes across the mesh; NH_EINVAL for c_i < 0
    or not finite, dt not finite and > 0, a null or misaligned workspace;
    NH_ESPACE for a small one.  The workspace must stay valid while the term
    is on. */
 nh_status nh_set_hyperdiffusion(nh_ctx *ctx, const double *c, double dt, void *dev_ws, size_t bytes);
 
-/* dev_H = H_q(dev_q) on device [5][U] arrays (distinct); needs
+/* dev_H = H_q(dev_q) on device [5][U] arrays (distinct), the term as it
+   enters the tendency: wall-normal velocity rows zero.  Needs
    nh_set_hyperdiffusion.  Asynchronous on the context's stream. */
 nh_status nh_hyperdiffusion(nh_ctx *ctx, const double *dev_q, double *dev_H);
 
@@ -371,11 +374,16 @@ typedef struct nh_batch nh_batch;
 nh_status nh_batch_workspace_bytes(nh_ctx *const *ctxs, int32_t n, int32_t steps_per_graph, size_t *bytes);
 
 /* tile_variant: optional [7] array indexed by order (tuner's choice per
-   order); hip_stream must be a non-default stream (graph capture). */
+   order), kept by the batch (the contexts' own tile settings are neither
+   used nor changed); hip_stream must be a non-default stream (graph
+   capture). */
 nh_status nh_batch_create(nh_ctx *const *ctxs, int32_t n, int32_t steps_per_graph, const int32_t *tile_variant,
                           void *dev_ws, size_t bytes, void *hip_stream, nh_batch **out);
 
-/* Advance every instance nsteps (a multiple of steps_per_graph) from t. */
+/* Advance every instance nsteps (a multiple of steps_per_graph) from t.
+   Re-checks every context first: NH_EUNSUPPORTED if one has since turned on
+   hyper-diffusion or forcing of fields 0..3, NH_EINVAL if its precision
+   changed, NH_ESTATE if it is in an error state; nothing is launched then. */
 nh_status nh_batch_step(nh_batch *b, double t, double dt, int32_t nsteps);
 nh_status nh_batch_last_error(const nh_batch *b, char *buf, size_t n);
 nh_status nh_batch_destroy(nh_batch *b);
@@ -411,6 +419,13 @@ nh_status nh_mlp_backward(nh_mlp *m, int64_t batch, const void *dev_x_f16, const
    Adam (Kingma & Ba, bias-corrected).  dev_loss (device float, optional). */
 nh_status nh_mlp_train_step(nh_mlp *m, int64_t batch, const void *dev_x_f16, const float *dev_t, float lr,
                             float b1, float b2, float eps, float *dev_loss);
+
+/* One Adam step (Kingma & Ba, bias-corrected with the step count kept since
+   creation or nh_mlp_set_params) on the FP32 masters with the gradients of
+   the last nh_mlp_backward, then the FP16 copies refreshed: the update that
+   nh_mlp_train_step applies.  NH_EINVAL for lr <= 0, b1 or b2 outside
+   [0, 1), eps <= 0. */
+nh_status nh_mlp_adam_step(nh_mlp *m, float lr, float b1, float b2, float eps);
 
 /* Copy FP32 master parameters and/or gradients to device arrays; *n = count. */
 nh_status nh_mlp_params(nh_mlp *m, float *dev_master, float *dev_grad, int64_t *n);

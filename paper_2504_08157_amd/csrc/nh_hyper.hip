@@ -55,10 +55,13 @@ __device__ __forceinline__ void hd_static_for(F &&f)
 template <int N>
 constexpr int hd_prefetch() { return N >= 6 ? 2 : 4; }
 
+// With wallmask set, the wall-normal velocity rows are left out (zero, or
+// unchanged when accumulating): u on the x walls, v on the y walls, w at the
+// bottom and top levels, the no-flux condition imposed on the whole tendency.
 template <int N, bool ACC, int P = hd_prefetch<N>()>
 __global__ void __launch_bounds__(kHdTX * kHdTY) hd_laplace_tile_kernel(HyperParams h, const double *__restrict__ q,
                                                                         double *__restrict__ out, double scale,
-                                                                        const double *__restrict__ sz)
+                                                                        const double *__restrict__ sz, int wallmask)
 {
     constexpr int NC = 2 * N + 1, PX = kHdTX + 2 * N, PY = kHdTY + 2 * N;
     constexpr int NT = kHdTX * kHdTY, NS = (PX * PY + NT - 1) / NT;
@@ -74,6 +77,11 @@ __global__ void __launch_bounds__(kHdTX * kHdTY) hd_laplace_tile_kernel(HyperPar
     const int ix = x0 + tx, iy = y0 + ty;
     const bool own = ix < h.nx && iy < h.ny;
     const long col = own ? ix + (long)iy * h.nx : 0;
+    // this column's wall-normal rows: every level (u, v on a wall column) or
+    // the bottom and top levels (w)
+    const bool colwall = wallmask && ((f == 1 && !h.perx && (ix == 0 || ix == h.nx - 1)) ||
+                                      (f == 2 && !h.pery && (iy == 0 || iy == h.ny - 1)));
+    const bool zwall = wallmask && f == 3;
     const double *qf = q + (long)f * U;
     double *of = out + (long)f * U;
     double cx[NC], cy[NC];
@@ -143,6 +151,7 @@ __global__ void __launch_bounds__(kHdTX * kHdTY) hd_laplace_tile_kernel(HyperPar
                 ay += cy[o] * tl[(ty + o) * PX + tx + N];
             }
             double v = scale * (ax + ay + az);
+            if (colwall || (zwall && (k == 0 || k == nz - 1))) v = 0.0;
             if constexpr (ACC) v = apre[j] + v;
             if (own && k < nz) of[col + (long)k * nxy] = v;
 #pragma unroll
@@ -156,26 +165,28 @@ __global__ void __launch_bounds__(kHdTX * kHdTY) hd_laplace_tile_kernel(HyperPar
 
 template <int N>
 static void hd_launch(const HyperParams &h, const double *q, double *out, double scale, bool accumulate,
-                      hipStream_t s)
+                      bool wallmask, hipStream_t s)
 {
     const int ntx = (h.nx + kHdTX - 1) / kHdTX, nty = (h.ny + kHdTY - 1) / kHdTY;
     const dim3 grid((unsigned)(ntx * nty * kNF)), blk(kHdTX * kHdTY);
     if (accumulate)
-        hipLaunchKernelGGL((hd_laplace_tile_kernel<N, true>), grid, blk, 0, s, h, q, out, scale, h.sz);
+        hipLaunchKernelGGL((hd_laplace_tile_kernel<N, true>), grid, blk, 0, s, h, q, out, scale, h.sz,
+                           wallmask ? 1 : 0);
     else
-        hipLaunchKernelGGL((hd_laplace_tile_kernel<N, false>), grid, blk, 0, s, h, q, out, scale, h.sz);
+        hipLaunchKernelGGL((hd_laplace_tile_kernel<N, false>), grid, blk, 0, s, h, q, out, scale, h.sz,
+                           wallmask ? 1 : 0);
 }
 
 hipError_t launch_hd_laplace(const HyperParams &h, const double *q, double *out, double scale, bool accumulate,
-                             hipStream_t s)
+                             bool wallmask, hipStream_t s)
 {
     switch (h.N) {
-    case 1: hd_launch<1>(h, q, out, scale, accumulate, s); break;
-    case 2: hd_launch<2>(h, q, out, scale, accumulate, s); break;
-    case 3: hd_launch<3>(h, q, out, scale, accumulate, s); break;
-    case 4: hd_launch<4>(h, q, out, scale, accumulate, s); break;
-    case 5: hd_launch<5>(h, q, out, scale, accumulate, s); break;
-    case 6: hd_launch<6>(h, q, out, scale, accumulate, s); break;
+    case 1: hd_launch<1>(h, q, out, scale, accumulate, wallmask, s); break;
+    case 2: hd_launch<2>(h, q, out, scale, accumulate, wallmask, s); break;
+    case 3: hd_launch<3>(h, q, out, scale, accumulate, wallmask, s); break;
+    case 4: hd_launch<4>(h, q, out, scale, accumulate, wallmask, s); break;
+    case 5: hd_launch<5>(h, q, out, scale, accumulate, wallmask, s); break;
+    case 6: hd_launch<6>(h, q, out, scale, accumulate, wallmask, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

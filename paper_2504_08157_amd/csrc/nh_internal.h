@@ -94,9 +94,10 @@ struct HyperParams {
     int nx, ny, nz, N, perx, pery;
     const double *sx, *sy, *sz;   // [n_d][2N+1] operator rows per lattice position of each direction
 };
-// out = scale * (div tau grad) q on [5][U] (out += ... with accumulate)
+// out = scale * (div tau grad) q on [5][U] (out += ... with accumulate); with
+// wallmask the wall-normal velocity rows get no contribution
 hipError_t launch_hd_laplace(const HyperParams &h, const double *q, double *out, double scale, bool accumulate,
-                             hipStream_t s);
+                             bool wallmask, hipStream_t s);
 
 // ---- 3D-IMEX: linear operator over all directions and the global GMRES
 constexpr int kG3MaxRestart = 32;

@@ -292,8 +292,10 @@ void forcing_at(const nh_ctx *c, int f, double t, const double **a, const double
     *lam = (t - ts[k]) / (ts[k + 1] - ts[k]);
 }
 
+// Stage parameters of context c; the tile counts follow tile variant
+// `variant` (the context's own unless a batch launches it with another).
 StageParams stage_params(const nh_ctx *c, double t, const double *qs, const double *qn, double *out,
-                         double a, double b, double cc)
+                         double a, double b, double cc, int variant = -1)
 {
     StageParams p{};
     p.qs = qs; p.qn = qn; p.out = out;
@@ -304,7 +306,7 @@ StageParams stage_params(const nh_ctx *c, double t, const double *qs, const doub
     p.nx = c->n[0]; p.ny = c->n[1]; p.nz = c->n[2]; p.nelz = c->nel[2];
     p.perx = c->per[0]; p.pery = c->per[1];
     int tx, ty;
-    stage_tile(c->N, c->tile, &tx, &ty);
+    stage_tile(c->N, variant < 0 ? c->tile : variant, &tx, &ty);
     p.ntx = (c->n[0] + tx - 1) / tx;
     p.nty = (c->n[1] + ty - 1) / ty;
     p.fcor = c->phys.f; p.g = c->phys.g; p.gamma = c->phys.cp / c->phys.cv;
@@ -364,8 +366,8 @@ hipError_t run_stage(nh_ctx *c, double t, const double *qs, const double *qn, do
     if (e == hipSuccess && c->hd_on) {
         // out += cc H(qs), H = -(div tau grad)^2 qs
         const HyperParams hp = hyper_params(c);
-        e = launch_hd_laplace(hp, qs, c->hd_tmp, 1.0, false, c->stream);
-        if (e == hipSuccess) e = launch_hd_laplace(hp, c->hd_tmp, out, -cc, true, c->stream);
+        e = launch_hd_laplace(hp, qs, c->hd_tmp, 1.0, false, false, c->stream);
+        if (e == hipSuccess) e = launch_hd_laplace(hp, c->hd_tmp, out, -cc, true, true, c->stream);
     }
     for (int f = 0; f < 4 && e == hipSuccess; ++f) {
         if (c->nsnap[f] == 0) continue;
@@ -923,8 +925,8 @@ nh_status nh_hyperdiffusion(nh_ctx *c, const double *dev_q, double *dev_H)
     if (!dev_q || !dev_H) return fail(c, NH_EINVAL, "null arrays");
     if (dev_q == dev_H) return fail(c, NH_EINVAL, "dev_q and dev_H must differ");
     const HyperParams hp = hyper_params(c);
-    HIPCHK(c, launch_hd_laplace(hp, dev_q, c->hd_tmp, 1.0, false, c->stream));
-    HIPCHK(c, launch_hd_laplace(hp, c->hd_tmp, dev_H, -1.0, false, c->stream));
+    HIPCHK(c, launch_hd_laplace(hp, dev_q, c->hd_tmp, 1.0, false, false, c->stream));
+    HIPCHK(c, launch_hd_laplace(hp, c->hd_tmp, dev_H, -1.0, false, true, c->stream));
     return NH_OK;
 }
 
@@ -1506,6 +1508,17 @@ nh_status nh_mlp_train_step(nh_mlp *m, int64_t batch, const void *dev_x_f16, con
     return NH_OK;
 }
 
+nh_status nh_mlp_adam_step(nh_mlp *m, float lr, float b1, float b2, float eps)
+{
+    if (!m) return fail(nullptr, NH_EINVAL, "null MLP");
+    if (m->sticky) return NH_ESTATE;
+    if (!(lr > 0) || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1) || !(eps > 0))
+        return mfail(m, NH_EINVAL, "bad Adam hyper-parameters");
+    ++m->step;
+    MLPCHK(m, mlp_adam(m->net, lr, b1, b2, eps, m->step, m->stream));
+    return NH_OK;
+}
+
 nh_status nh_mlp_params(nh_mlp *m, float *dev_master, float *dev_grad, int64_t *n)
 {
     if (!m) return fail(nullptr, NH_EINVAL, "null MLP");
@@ -1594,6 +1607,7 @@ struct nh_batch {
         int2 *work;  // device
     };
     std::vector<Group> groups;
+    std::vector<int> variant;  // tile variant of each instance (its order group's)
     StageParams *table;  // device [K][3][n]
     std::vector<StageParams> host;
     hipStream_t stream;
@@ -1712,9 +1726,11 @@ nh_status nh_batch_create(nh_ctx *const *ctxs, int32_t n, int32_t steps_per_grap
         for (auto &it : items) all.push_back(it.second);
         tiles_total += items.size();
         b->groups.push_back(g);
-        for (int i = 0; i < n; ++i)
-            if (ctxs[i]->N == N) b->ctx[i]->tile = var;
     }
+    b->variant.assign(n, 0);
+    for (int i = 0; i < n; ++i)
+        for (const auto &g : b->groups)
+            if (g.N == ctxs[i]->N) b->variant[i] = g.variant;
     // descriptor tables sit after the work lists (sized for the larger tile variant)
     b->table = (StageParams *)(w + (need - align_up(sizeof(StageParams) * (size_t)steps_per_graph * 3 * n)));
     b->host.resize((size_t)steps_per_graph * 3 * n);
@@ -1740,6 +1756,12 @@ nh_status nh_batch_step(nh_batch *b, double t, double dt, int32_t nsteps)
         if (b->ctx[i]->sticky) return bfail(b, NH_ESTATE, "context %d in an error state", i);
         if (b->ctx[i]->hd_on)
             return bfail(b, NH_EUNSUPPORTED, "context %d has hyper-diffusion on: batched stages do not add it", i);
+        for (int f = 0; f < 4; ++f)
+            if (b->ctx[i]->nsnap[f])
+                return bfail(b, NH_EUNSUPPORTED, "context %d has forcing on field %d: batched stages fuse only the "
+                                                 "theta' forcing", i, f);
+        if (b->ctx[i]->precision != b->precision)
+            return bfail(b, NH_EINVAL, "context %d changed precision after the batch was created", i);
     }
     const double ca[3] = {0.0, 0.75, 1.0 / 3.0}, cb[3] = {1.0, 0.25, 2.0 / 3.0}, cc[3] = {1.0, 0.25, 2.0 / 3.0};
     const double ct[3] = {0.0, 1.0, 0.5};
@@ -1752,7 +1774,8 @@ nh_status nh_batch_step(nh_batch *b, double t, double dt, int32_t nsteps)
                     const double *qs = s == 0 ? c->q[0] : (s == 1 ? c->q[1] : c->q[2]);
                     double *o = s == 0 ? c->q[1] : (s == 1 ? c->q[2] : c->q[0]);
                     b->host[((size_t)k * 3 + s) * n + i] =
-                        stage_params(c, ts + ct[s] * dt, qs, s == 0 ? nullptr : c->q[0], o, ca[s], cb[s], cc[s] * dt);
+                        stage_params(c, ts + ct[s] * dt, qs, s == 0 ? nullptr : c->q[0], o, ca[s], cb[s], cc[s] * dt,
+                                     b->variant[i]);
                 }
         }
         BCHK(b, hipMemcpyAsync(b->table, b->host.data(), sizeof(StageParams) * b->host.size(),

@@ -108,6 +108,7 @@ _SIGS = {
     "nh_mlp_backward": (ctypes.c_int32, [_vp, ctypes.c_int64, _vp, _vp]),
     "nh_mlp_train_step": (ctypes.c_int32, [_vp, ctypes.c_int64, _vp, _vp, ctypes.c_float, ctypes.c_float,
                                            ctypes.c_float, ctypes.c_float, _vp]),
+    "nh_mlp_adam_step": (ctypes.c_int32, [_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
     "nh_mlp_params": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
     "nh_mlp_set_params": (ctypes.c_int32, [_vp, _vp]),
     "nh_mlp_samples": (ctypes.c_int32, [_vp, _vp, ctypes.c_double, _vp, _vp, ctypes.c_int64, ctypes.c_int64,
@@ -553,6 +554,9 @@ class ColumnMLP:
     def nh_mlp_train_step(self, x_f16, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, loss=None):
         self._c(self.lib.nh_mlp_train_step(self.h, x_f16.shape[0], _tptr(x_f16), _tptr(t), lr, b1, b2, eps,
                                            _tptr(loss) if loss is not None else None))
+
+    def nh_mlp_adam_step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self._c(self.lib.nh_mlp_adam_step(self.h, lr, b1, b2, eps))
 
     def nh_mlp_params(self):
         import torch

@@ -77,3 +77,71 @@ def test_batch_rejects_bad_arguments():
     assert e.value.code == nhsem.NH_EUNSUPPORTED
     ctx.nh_set_hyperdiffusion(None, 0.0)
     nhsem.Batch([ctx]).nh_batch_step(0.0, 1.0, 1)
+
+
+def test_batch_rechecks_contexts_at_step():
+    """Forcing of fields 0..3 and a precision change made after the batch was
+    created are refused at step, before anything is launched; a context's
+    later tile setting does not change what the batch computes (the batch
+    keeps its own tile variant per order)."""
+    import torch
+    from paper_2504_08157_amd import nhsem
+    ctx, q0 = _instance(1, (3, 2, 2), 4)
+    with torch.cuda.stream(torch.cuda.Stream()):
+        b = nhsem.Batch([ctx], steps_per_graph=1, tile_variant={4: 1})
+        f1 = torch.zeros((1,) + ctx.shape, dtype=torch.float64, device="cuda").reshape(1, -1)
+        ctx.nh_set_forcing(1, np.array([0.0]), f1)
+        with pytest.raises(nhsem.NHError) as e:
+            b.nh_batch_step(0.0, 1.0, 1)
+        assert e.value.code == nhsem.NH_EUNSUPPORTED
+        ctx.nh_set_forcing(1, None, None)
+        ctx.nh_set_precision(nhsem.NH_FP32_MIXED)
+        with pytest.raises(nhsem.NHError) as e:
+            b.nh_batch_step(0.0, 1.0, 1)
+        assert e.value.code == nhsem.NH_EINVAL
+        ctx.nh_set_precision(nhsem.NH_FP64)
+        # the context's own tile changes; the batch still covers every tile
+        ctx.nh_set_tile(0)
+        ctx.nh_set_state(q0)
+        b.nh_batch_step(0.0, 1.0, 2)
+        torch.cuda.synchronize()
+    got = ctx.nh_get_state().cpu().numpy()
+    b.close()
+    ctx.nh_set_state(q0)
+    ctx.nh_rk_step(0.0, 1.0, 2)
+    np.testing.assert_array_equal(got, ctx.nh_get_state().cpu().numpy())
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32_mixed"])
+def test_ensemble48_batched_equals_single(precision):
+    """The 48-member uneven ensemble (8 x 8 x 8 ... 40 x 40 x 16 elements,
+    N in 3..5, 23.5 M unique nodes) in FP64 and FP32-mixed: two steps in
+    batched graph launches equal, bit for bit, two steps of each member on
+    its own."""
+    import torch
+    from paper_2504_08157_amd import nhsem
+    ctxs, q0s = [], []
+    for i in range(48):
+        w = W.cfg_ensemble_member(i)
+        c = nhsem.Context(w.mesh, w.phys, precision=precision)
+        x, y, z = c.nh_lattice_coords()
+        c.nh_set_reference(*W.reference_profiles(w, z))
+        t, Q = W.heating(w, x, y, z)
+        c._heat = torch.from_numpy(Q.reshape(len(t), -1)).cuda()
+        c.nh_set_forcing(4, t, c._heat)
+        q0 = torch.from_numpy(W.initial_state(w, x, y, z)).cuda()
+        c.nh_set_state(q0)
+        ctxs.append(c); q0s.append(q0)
+    assert sum(c.U for c in ctxs) == 23522986
+    dt = 0.25
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b = nhsem.Batch(ctxs, steps_per_graph=2, tile_variant={3: 1, 4: 0, 5: 1}, stream=s)
+        b.nh_batch_step(0.0, dt, 2)
+    torch.cuda.synchronize()
+    got = [c.nh_get_state() for c in ctxs]
+    b.close()
+    for i, (c, q0) in enumerate(zip(ctxs, q0s)):
+        c.nh_set_state(q0)
+        c.nh_rk_step(0.0, dt, 2)
+        assert torch.equal(got[i], c.nh_get_state()), i

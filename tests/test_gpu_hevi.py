@@ -119,3 +119,54 @@ def test_hevi_step_parity(oracle_mod, restart, schur):
     for f in range(5):
         err = np.linalg.norm(got[f] - q[f]) / np.linalg.norm(q[f])
         assert err <= 1e-10, (f, err)
+
+
+# Columns of the benchmarked height and taller: 16 elements of order 4 give
+# n_z = 65 (195 unknowns over all four register slots of the full form, field
+# boundaries at unknowns 65 and 130 inside slots 1 and 2; 63 interior w values
+# in the Schur form's one slot), 17 elements give n_z = 69 (207 unknowns; 67
+# interior w values: the Schur form's two-slot instance).
+TALL = {"nz65": (2, 2, 16), "nz69": (2, 2, 17)}
+
+
+@pytest.mark.parametrize("restart,schur", FORMS)
+@pytest.mark.parametrize("tall", list(TALL))
+def test_column_gmres_tall_columns(oracle_mod, tall, restart, schur):
+    ctx, orc, g, o, torch = _pair(oracle_mod, nel=TALL[tall], H=20e3)
+    Lm = oracle_mod.column_matrix(orc)
+    nz = orc.nz
+    for alpha, seed in ((0.3, 21), (2.0, 22)):
+        b = _state(o, seed)
+        A = np.eye(3 * nz) - alpha * Lm
+        B = np.concatenate([b[0].reshape(nz, -1), b[3].reshape(nz, -1), b[4].reshape(nz, -1)])
+        X = np.linalg.solve(A, B)
+        bd = torch.from_numpy(_state(g, seed)).cuda()
+        iters = torch.zeros(ctx.nx * ctx.ny, dtype=torch.int32, device="cuda")
+        x, st = ctx.nh_column_solve(alpha, bd, restart=restart, max_restarts=60, rtol=1e-12, iters=iters,
+                                    schur=schur)
+        x = x.cpu().numpy()
+        assert st.not_converged == 0
+        for f, blk in ((0, X[:nz]), (3, X[nz:2 * nz]), (4, X[2 * nz:])):
+            ref = blk.reshape(x[f].shape)
+            err = np.linalg.norm(x[f] - ref) / np.linalg.norm(ref)
+            assert err <= 1e-9, (tall, alpha, f, err)
+        print(tall, "alpha", alpha, "restart", restart, "schur", schur, "iters mean", iters.float().mean().item())
+
+
+@pytest.mark.parametrize("restart,schur", FORMS)
+def test_hevi_step_parity_nz65(oracle_mod, restart, schur):
+    """Two ARK2 steps with columns of the benchmarked height (n_z = 65)
+    against the oracle's step with direct column solves."""
+    ctx, orc, g, o, torch = _pair(oracle_mod, nel=TALL["nz65"], H=20e3)
+    Lm = oracle_mod.column_matrix(orc)
+    q = _state(o, 23, amp=0.3)
+    ctx.nh_set_state(torch.from_numpy(_state(g, 23, amp=0.3)).cuda())
+    dt = 2.0
+    for n in range(2):
+        st = ctx.nh_hevi_step(n * dt, dt, restart=restart, rtol=1e-13, max_restarts=60, schur=schur)
+        q = oracle_mod.ark2_step(orc, Lm, n * dt, dt, q)
+        assert st.not_converged == 0 and st.solves == 2
+    got = ctx.nh_get_state().cpu().numpy()
+    for f in range(5):
+        err = np.linalg.norm(got[f] - q[f]) / np.linalg.norm(q[f])
+        assert err <= 1e-10, (f, err)

@@ -170,3 +170,57 @@ def test_learned_guess_reduces_iterations():
     print(res)
     assert res["mlp"]["iters_per_solve"] < res["default"]["iters_per_solve"], res
     assert res["state_rel_diff_stacked"] < 1e-8, res
+
+
+def test_train_step_matches_oracle():
+    """One nh_mlp_train_step against the oracle's forward, MSE gradient and
+    backward on the same FP16-rounded weights and inputs (loss and every
+    gradient tensor to 5e-3, the FP16 forward's accuracy), and its Adam
+    update against the oracle's Adam applied to the step's own gradient
+    (FP32 arithmetic: 1e-5 of the update)."""
+    m, torch, w, wo, x = _mlp_with_random_params(seed=11)
+    rng = np.random.default_rng(12)
+    t = rng.normal(scale=0.5, size=(x.shape[0], MO.OUT)).astype(np.float32)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    m.nh_mlp_train_step(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(), lr=lr, b1=b1, b2=b2, eps=eps,
+                        loss=loss)
+    w1, g = m.nh_mlp_params()
+    w1, g = w1.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64)
+    yo, cache = MO.forward(wo, x.astype(np.float64))
+    to = t.astype(np.float64)
+    lo = MO.mse(yo, to)
+    assert abs(loss.item() - lo) <= 5e-3 * lo, (loss.item(), lo)
+    go = MO.backward(wo, cache, MO.mse_grad(yo, to))
+    for i, (a, b) in enumerate(zip(MO.unflatten(g), MO.unflatten(go))):
+        assert _rel(a, b) <= 5e-3, (i, _rel(a, b))
+    w0 = w.astype(np.float64)
+    z = np.zeros_like(w0)
+    wa, _, _ = MO.adam(w0, g, z, z, 1, lr, b1, b2, eps)
+    assert np.linalg.norm(w1 - wa) <= 1e-5 * np.linalg.norm(wa - w0)
+
+
+def test_adam_step_matches_oracle():
+    """nh_mlp_adam_step three times on the gradient of one backward pass
+    against the oracle's Adam over the same three steps (FP32 moments)."""
+    m, torch, w, wo, x = _mlp_with_random_params(seed=13)
+    rng = np.random.default_rng(14)
+    dy = rng.normal(size=(x.shape[0], MO.OUT)).astype(np.float32)
+    xd = torch.from_numpy(x).cuda()
+    m.nh_mlp_forward(xd)
+    m.nh_mlp_backward(xd, torch.from_numpy(dy).cuda())
+    lr, b1, b2, eps = 2e-3, 0.8, 0.99, 1e-6
+    wa = w.astype(np.float64)
+    _, g = m.nh_mlp_params()
+    g = g.cpu().numpy().astype(np.float64)
+    mo = vo = np.zeros_like(wa)
+    for step in range(1, 4):
+        m.nh_mlp_adam_step(lr, b1, b2, eps)
+        wa, mo, vo = MO.adam(wa, g, mo, vo, step, lr, b1, b2, eps)
+    w3, _ = m.nh_mlp_params()
+    w3 = w3.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(w3 - wa) <= 1e-5 * np.linalg.norm(wa - w.astype(np.float64))
+    # bad hyper-parameters are refused
+    from paper_2504_08157_amd import nhsem
+    with pytest.raises(nhsem.NHError):
+        m.nh_mlp_adam_step(lr=-1.0)
