@@ -243,6 +243,24 @@ nh_status nh_ri_velocity(nh_ctx *ctx, const double *dev_q, int32_t nstrips, doub
                          double *dev_center, double *dev_ubar, int32_t *dev_count, double *dev_result,
                          void *dev_ws, size_t bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the same
+   diagnostic, arguments and outputs as nh_ri_velocity, with its partial sums
+   in a fixed 8 MiB scratch array that the library holds in device memory,
+   one copy per GPU, until the process ends (no workspace argument; no
+   hipMalloc, hipFree or allocating library call).  The scratch address of
+   the context's device is resolved in nh_init_mesh.  Every call on one GPU
+   shares that GPU's scratch: calls that overlap on one GPU (other streams,
+   other threads, other contexts on the same device) race and must be
+   ordered by the caller.  NH_ESPACE, with nothing launched, when the
+   partial sums would exceed the scratch (n_z * nb * (32 + 12 nstrips) bytes
+   in 256-byte aligned blocks, nb = ceil(n_x n_y / 4096) chunks per level, at
+   most 256: on a 512 x 512 x 81 lattice up to about 130 strips); other
+   errors as nh_ri_velocity. */
+nh_status nh_ri_velocity_noalloc(nh_ctx *ctx, const double *dev_q, int32_t nstrips, double rmax,
+                                 int32_t center_given, double *dev_center, double *dev_ubar, int32_t *dev_count,
+                                 double *dev_result);
+
 /* ------------------------------------------------------------------
  * 1D-IMEX (HEVI) step (Sec. 2.3: IMEX split S = (S - L) + L with the fast
  * waves implicit, ARK2 "ARK(2,3,2)b", matrix-free GMRES).  Here L = L_v, the

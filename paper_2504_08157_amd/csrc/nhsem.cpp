@@ -17,6 +17,7 @@
 
 #include <string>
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 using namespace nh;
@@ -50,14 +51,50 @@ struct nh_ctx {
     int nsnap[kNF];
     std::vector<double> tsnap[kNF];
     const double *snap[kNF];
+    // device of the context and the address of that device's copy of the
+    // allocation-free scratch array (see nh_ri_velocity_noalloc)
+    int device;
+    void *scratch_dev;
     // error state
     bool sticky;
     std::string err;
 };
 
+// Scratch of the allocation-free entry point nh_ri_velocity_noalloc: a fixed
+// array in device memory, one copy per GPU, held until the process ends.  On
+// the host `scratch` is only a stand-in symbol, never a device address: the
+// address of each GPU's copy is resolved once per device, with that device
+// current, by resolve_scratch() (called from nh_init_mesh), and only that
+// resolved address is handed to kernels.
+constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
 namespace {
 
 thread_local std::string g_last_global_error;
+
+// Per-device address of `scratch`, resolved on first use of each device.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices];
+
+// Address of the current device's copy of `scratch` (null on error).
+hipError_t resolve_scratch(int *device, void **addr)
+{
+    *addr = nullptr;
+    hipError_t e = hipGetDevice(device);
+    if (e != hipSuccess) return e;
+    if (*device < 0 || *device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[*device]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[*device] = ptr;
+    }
+    *addr = g_scratch_addr[*device];
+    return hipSuccess;
+}
 
 nh_status fail(nh_ctx *c, nh_status code, const char *fmt, ...)
 {
@@ -411,7 +448,15 @@ nh_status nh_init_mesh(const nh_mesh_desc *mesh, const nh_physics *phys, void *d
     if (((uintptr_t)dev_ws & 255) != 0) return fail(nullptr, NH_EINVAL, "workspace must be 256-byte aligned");
     if (ws_bytes < L.total) return fail(nullptr, NH_ESPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
 
+    int device = -1;
+    void *scratch_dev = nullptr;
+    {
+        const hipError_t e = resolve_scratch(&device, &scratch_dev);
+        if (e != hipSuccess) return fail(nullptr, NH_EHIP, "scratch address: %s", hipGetErrorString(e));
+    }
     nh_ctx *c = new nh_ctx();
+    c->device = device;
+    c->scratch_dev = scratch_dev;
     c->N = mesh->order;
     for (int d = 0; d < 3; ++d) c->nel[d] = mesh->nel[d];
     c->per[0] = mesh->periodic[0];
@@ -959,19 +1004,53 @@ nh_status nh_ri_workspace_bytes(const nh_ctx *c, int32_t nstrips, size_t *bytes)
     return NH_OK;
 }
 
-nh_status nh_ri_velocity(nh_ctx *c, const double *dev_q, int32_t nstrips, double rmax, int32_t center_given,
-                         double *dev_center, double *dev_ubar, int32_t *dev_count, double *dev_result, void *dev_ws,
-                         size_t bytes)
+static nh_status ri_check(nh_ctx *c, const double *dev_q, int32_t nstrips, double rmax, double *dev_center,
+                          double *dev_ubar, int32_t *dev_count, double *dev_result)
 {
     nh_status st = guard(c);
     if (st) return st;
     if (nstrips < 1 || nstrips > kRiMaxStrips) return fail(c, NH_EINVAL, "nstrips must be in [1, %d]", kRiMaxStrips);
     if (!(rmax > 0.0) || !isfinite(rmax)) return fail(c, NH_EINVAL, "rmax must be finite and > 0");
-    if (!dev_q || !dev_center || !dev_ubar || !dev_count || !dev_result || !dev_ws)
-        return fail(c, NH_EINVAL, "null arrays");
+    if (!dev_q || !dev_center || !dev_ubar || !dev_count || !dev_result) return fail(c, NH_EINVAL, "null arrays");
+    return NH_OK;
+}
+
+static nh_status ri_run(nh_ctx *c, const double *dev_q, int32_t nstrips, double rmax, int32_t center_given,
+                        double *dev_center, double *dev_ubar, int32_t *dev_count, double *dev_result, void *dev_ws);
+
+nh_status nh_ri_velocity(nh_ctx *c, const double *dev_q, int32_t nstrips, double rmax, int32_t center_given,
+                         double *dev_center, double *dev_ubar, int32_t *dev_count, double *dev_result, void *dev_ws,
+                         size_t bytes)
+{
+    nh_status st = ri_check(c, dev_q, nstrips, rmax, dev_center, dev_ubar, dev_count, dev_result);
+    if (st) return st;
+    if (!dev_ws) return fail(c, NH_EINVAL, "null arrays");
     if (((uintptr_t)dev_ws & 255) != 0) return fail(c, NH_EINVAL, "RI workspace must be 256-byte aligned");
     const size_t need = ri_bytes(c, nstrips, nullptr, nullptr);
     if (bytes < need) return fail(c, NH_ESPACE, "RI workspace %zu < %zu bytes", bytes, need);
+    return ri_run(c, dev_q, nstrips, rmax, center_given, dev_center, dev_ubar, dev_count, dev_result, dev_ws);
+}
+
+nh_status nh_ri_velocity_noalloc(nh_ctx *c, const double *dev_q, int32_t nstrips, double rmax, int32_t center_given,
+                                 double *dev_center, double *dev_ubar, int32_t *dev_count, double *dev_result)
+{
+    nh_status st = ri_check(c, dev_q, nstrips, rmax, dev_center, dev_ubar, dev_count, dev_result);
+    if (st) return st;
+    const size_t need = ri_bytes(c, nstrips, nullptr, nullptr);
+    if (need > kNoAllocScratchBytes)
+        return fail(c, NH_ESPACE,
+                    "the diagnostic needs %zu bytes of partial sums here; the allocation-free form holds at most %zu "
+                    "(fewer strips, or nh_ri_velocity with a workspace)", need, kNoAllocScratchBytes);
+    if (!c->scratch_dev) return fail(c, NH_ESTATE, "scratch address of the context's device not resolved");
+    // every partial the kernels read is written first in the same call: the
+    // scratch needs no clearing
+    return ri_run(c, dev_q, nstrips, rmax, center_given, dev_center, dev_ubar, dev_count, dev_result,
+                  c->scratch_dev);
+}
+
+static nh_status ri_run(nh_ctx *c, const double *dev_q, int32_t nstrips, double rmax, int32_t center_given,
+                        double *dev_center, double *dev_ubar, int32_t *dev_count, double *dev_result, void *dev_ws)
+{
     RiWork w;
     ri_bytes(c, nstrips, &w, (char *)dev_ws);
     RiParams p{};

@@ -126,6 +126,8 @@ _SIGS = {
     "nh_ri_workspace_bytes": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     "nh_ri_velocity": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp,
                                         _vp, _vp, ctypes.c_size_t]),
+    "nh_ri_velocity_noalloc": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _vp,
+                                                _vp, _vp, _vp]),
     "nh_mlp_last_error": (ctypes.c_int32, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     "nh_mlp_destroy": (ctypes.c_int32, [_vp]),
     "nh_last_error": (ctypes.c_int32, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
@@ -415,6 +417,30 @@ class Context:
         self._c(self.lib.nh_ri_velocity(self.h, _tptr(q), int(nstrips), float(rmax), 1 if given else 0, _tptr(cen),
                                         _tptr(ubar), _tptr(count), _tptr(res), _tptr(self.riws), n.value))
         return {"center": cen, "ubar": ubar, "count": count, "result": res}
+
+    def nh_ri_velocity_noalloc(self, q, nstrips=50, rmax=None, center=None, out=None):
+        """nh_ri_velocity through the allocation-free entry point (partial sums
+        in the library's fixed scratch).  out: optional dict of preallocated
+        output tensors (center, ubar, count, result) as nh_ri_velocity returns."""
+        import torch
+        m = self.mesh
+        if rmax is None:
+            rmax = 0.5 * min(float(m.xe[-1]) - float(m.xe[0]), float(m.ye[-1]) - float(m.ye[0]))
+        nz = self.nz
+        given = center is not None
+        if out is None:
+            out = {"center": torch.empty((2, nz), dtype=torch.float64, device="cuda"),
+                   "ubar": torch.empty((nz, nstrips), dtype=torch.float64, device="cuda"),
+                   "count": torch.empty((nz, nstrips), dtype=torch.int32, device="cuda"),
+                   "result": torch.empty(4, dtype=torch.float64, device="cuda")}
+        if given:
+            if center.dtype != torch.float64 or not center.is_cuda or tuple(center.shape) != (2, nz):
+                raise ValueError("center must be a float64 device tensor of shape (2, n_z)")
+            out["center"].copy_(center)
+        self._c(self.lib.nh_ri_velocity_noalloc(self.h, _tptr(q), int(nstrips), float(rmax), 1 if given else 0,
+                                                _tptr(out["center"]), _tptr(out["ubar"]), _tptr(out["count"]),
+                                                _tptr(out["result"])))
+        return out
 
     def nh_lv_apply(self, x, out=None):
         import torch
