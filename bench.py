@@ -219,7 +219,7 @@ def bench_batched(args):
     best = {}
     s = torch.cuda.Stream()
     tune = {}
-    for v in (0, 1):
+    for v in (0, 1, 2):
         with torch.cuda.stream(s):
             b = nhsem.Batch(ctxs, steps_per_graph=K, tile_variant={n: v for n in range(7)}, stream=s)
             b.nh_batch_step(0.0, dt, K)
@@ -590,7 +590,7 @@ def main():
     tune = {}
     if tile < 0:
         # tile autotuning: time each variant over a few steps, keep the fastest
-        for v in (0, 1):
+        for v in (0, 1, 2):
             ctx.nh_set_tile(v)
             ctx.nh_rk_step(0.0, dt, 2)
             e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)

@@ -102,10 +102,13 @@ nh_status nh_set_precision(nh_ctx *ctx, int32_t precision);
 
 /* Workgroup tile of the stage kernel (columns per workgroup from
    nh_tile_shape): variant 0 (default) rows of ~32 lattice columns, a few
-   element rows deep; variant 1 a squarer ~16 x 16 tile.  Both variants compute
-   every node with the same arithmetic in the same order, so results are
-   bitwise identical.  Chosen by the caller's tuner from measured times.
-   NH_EINVAL for any other value. */
+   element rows deep; variant 1 a squarer ~16 x 16 tile.  Variants 0 and 1
+   compute every node with the same arithmetic in the same order, so results
+   are bitwise identical.  Variant 2 (order 4 only; other orders run variant
+   0) is variant 0's tile with the nodes assigned to threads by node class and
+   the x/y derivatives written per element (a different order of the same
+   sums: equal to variants 0 and 1 to rounding).  Chosen by the caller's tuner
+   from measured times.  NH_EINVAL for any other value. */
 nh_status nh_set_tile(nh_ctx *ctx, int32_t variant);
 
 /* Columns per tile (tx x ty) of a variant for order N (no context needed). */

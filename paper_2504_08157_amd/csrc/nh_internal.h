@@ -26,6 +26,10 @@ struct StageParams {
     const double *gy;      // [n_y][2N+1]
     const float *gxf;      // FP32 copies for the mixed-precision path
     const float *gyf;
+    const double *cfx;     // [n_x][2] the x average written per element: weight of the
+                           // element the node ends (local index N), of the one it starts or
+                           // lies inside
+    const double *cfy;     // [n_y][2]
     const double *lev;     // [n_z][kLevW]
     const double *hz2;     // [nel_z] 2 / h_z of each element layer
     const double *cst;     // [kCst]: D (row-major, (N+1)^2) then the EOS series
@@ -206,6 +210,6 @@ hipError_t launch_mass(const GeomParams &g, double *M, hipStream_t s);
 hipError_t launch_diag(const GeomParams &g, const double *q, double *partials, double *out8,
                        hipStream_t s);
 void stage_tile(int N, int variant, int *tx, int *ty);
-constexpr int kTileVariants = 2;
+constexpr int kTileVariants = 3;
 
 }  // namespace nh

@@ -465,6 +465,493 @@ stage_kernel_batched(const StageParams *__restrict__ P, const int2 *__restrict__
     stage_body<N, AX, AY, T>(P[it.x], it.y);
 }
 
+// ---------------------------------------------------------------- stage, node-class form
+// The same fused stage as stage_body, with nodes assigned to threads by
+// node class: wave (i, j) of the workgroup takes every node whose local x
+// index is i and local y index is j, over all AX x AY elements of the tile
+// and all N levels of the slab (lane = element + AX AY level).  Within a
+// wave the x and y derivative rules are then uniform: a node inside its
+// element (i != 0) uses the element-local (N+1)-tap contraction with the
+// LGL derivative row D[i] and one per-node factor 2/h; a node on an element
+// face (i = 0) uses the left element's row D[N] and the right element's row
+// D[0], each with its factor of the mass-weighted average -- the same
+// discrete operator as the (2N+1)-tap stencil of stage_body, with about a
+// third fewer taps and the tap weights wave-uniform (scalar registers)
+// instead of per-lane LDS reads.
+//
+// LDS: the N+1 levels of the current element in five plane slots (fields
+// p', u, v, w, theta', rho'); slots 0 and 4 alternate as the element's
+// bottom and top level (the top of one element is the bottom of the next,
+// so no level is copied or staged twice) and slots 1..N-1 hold the local
+// levels between.  Plane address of (px, py): py RP + (py / N) PADY + px,
+// the skew PADY per element row and the slot bases chosen (residues 0, 1,
+// 0, 1, 0 mod 4 doubles) so that the 32 lanes of a half-wave -- 8 elements
+// along x, 2 element rows, 2 levels -- read 64 distinct banks.  The lower
+// element's weighted z-derivative at the shared level (the carry) is
+// computed for every column and field by all threads at the end of each
+// element, double-buffered in LDS.
+template <int N, int AX, int AY>
+struct ClsShape {
+    static_assert(N == 4 && AX == 8 && AY == 2, "bank layout worked out for 8 x 2 elements of order 4");
+    static constexpr int N1 = N + 1, NE = AX * AY;
+    static constexpr int TX = AX * N, TY = AY * N, NCOL = TX * TY;
+    static constexpr int NT = N * N * 64;
+    static constexpr int PX = TX + N + 1, PY = TY + N + 1;
+    static constexpr int RP = PX, PADY = 2;
+    static constexpr int PSZ = (PY - 1) * RP + ((PY - 1) / N) * PADY + PX;
+    static constexpr int FS = PSZ, SLOT = 6 * PSZ;
+    static constexpr int NSP = NCOL + (TX + TY) * N1;
+    static constexpr int up4(int v, int r) { return v + (((r - v % 4) % 4) + 4) % 4; }
+    static constexpr int B0 = 0;
+    static constexpr int B1 = up4(B0 + SLOT, 1);
+    static constexpr int B2 = up4(B1 + SLOT, 0);
+    static constexpr int B3 = up4(B2 + SLOT, 1);
+    static constexpr int B4 = up4(B3 + SLOT, 0);
+    static constexpr int TOTAL = B4 + SLOT;
+    static __host__ __device__ constexpr int addr(int px, int py) { return py * RP + (py / N) * PADY + px; }
+};
+
+__device__ __forceinline__ double wave_uniform(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float wave_uniform(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+
+// One LDS read that the compiler may not merge with a neighbouring one:
+// merged pairs (ds_read2_b64 with adjacent or row-strided offsets) took eight
+// bank-conflict cycles each in the node-class layout, where single reads of
+// the same addresses take none (measured on gfx950).
+template <typename T>
+__device__ __forceinline__ T lds_one(const T *p)
+{
+    typedef __attribute__((address_space(3))) const volatile T lds_t;
+    return *(lds_t *)p;
+}
+
+template <int N, int AX, int AY, typename T>
+__device__ __forceinline__ void stage_body_cls(const StageParams &p, const int tile)
+{
+    using S = ClsShape<N, AX, AY>;
+    constexpr int N1 = S::N1, NE = S::NE, TX = S::TX, TY = S::TY, NCOL = S::NCOL, NT = S::NT;
+    constexpr int PX = S::PX, RP = S::RP, PADY = S::PADY, FS = S::FS, NSP = S::NSP;
+    constexpr bool kF64 = sizeof(T) == 8;
+
+    __shared__ T planes[S::TOTAL + N * RP];
+    __shared__ T sD[N1 * N1];
+    __shared__ double sE[kEosTerms];
+    __shared__ uint32_t smap[NSP];
+    __shared__ uint16_t sidx[NSP];
+    __shared__ double slev[N1 * 5];
+    __shared__ double stlev[N1 * 3];
+    __shared__ T scarry[2][6 * NCOL];
+    // per tile column / row: the two factors of the x (y) average (cfx, cfy)
+    __shared__ T scx[2 * TX], scy[2 * TY];
+
+    const int tid = threadIdx.x;
+    const int bx = tile % p.ntx, by = tile / p.ntx;
+    const int x0 = bx * TX, y0 = by * TY;
+    const uint32_t nx = p.nx, ny = p.ny;
+    const uint32_t plane_bytes = nx * ny * 8u;
+    const uint64_t field_bytes = (uint64_t)plane_bytes * (uint32_t)p.nz;
+
+    for (int i = tid; i < N1 * N1; i += NT) sD[i] = T(p.cst[kCstD + i]);
+    for (int i = tid; i < kEosTerms; i += NT) sE[i] = p.cst[kCstEos + i];
+    for (int i = tid; i < S::TOTAL + N * RP; i += NT) planes[i] = T(0);
+    for (int i = tid; i < 6 * NCOL; i += NT) scarry[0][i] = T(0);   // no element below the bottom
+    for (int i = tid; i < 2 * TX; i += NT) {
+        const int xg = x0 + i / 2;
+        scx[i] = T(p.cfx[2 * (xg < p.nx ? xg : p.nx - 1) + i % 2]);
+    }
+    for (int i = tid; i < 2 * TY; i += NT) {
+        const int yg = y0 + i / 2;
+        scy[i] = T(p.cfy[2 * (yg < p.ny ? yg : p.ny - 1) + i % 2]);
+    }
+    for (int sn = tid; sn < NSP; sn += NT) {
+        int px, py;
+        if (sn < NCOL) {
+            px = N + sn % TX;
+            py = N + sn / TX;
+        } else if (sn < NCOL + TY * N1) {
+            const int s1 = sn - NCOL, c = s1 % N1;
+            px = (c < N) ? c : N + TX;
+            py = N + s1 / N1;
+        } else {
+            const int s2 = sn - NCOL - TY * N1, r = s2 / TX;
+            px = N + s2 % TX;
+            py = (r < N) ? r : N + TY;
+        }
+        int xg = x0 + px - N, yg = y0 + py - N;
+        bool ok = true;
+        if (xg < 0 || xg >= p.nx) {
+            if (p.perx) {
+                xg += (xg < 0) ? p.nx : -p.nx;
+                ok = xg < p.nx;
+            } else {
+                ok = false;
+            }
+        }
+        if (yg < 0 || yg >= p.ny) {
+            if (p.pery) {
+                yg += (yg < 0) ? p.ny : -p.ny;
+                ok = ok && yg < p.ny;
+            } else {
+                ok = false;
+            }
+        }
+        smap[sn] = ok ? ((uint32_t)xg + nx * (uint32_t)yg) * 8u : 0xffffffffu;
+        sidx[sn] = (uint16_t)S::addr(px, py);
+    }
+    for (int i = tid; i < N1 * 3; i += NT) {
+        const int c = i % 3;
+        stlev[i] = p.lev[(long)(i / 3) * kLevW + (c == 0 ? 7 : c == 1 ? 8 : 2)];
+    }
+    __syncthreads();
+
+    auto fill_stlev = [&](int k0) {
+        for (int i = tid; i < N1 * 3; i += NT) {
+            const int c = i % 3;
+            stlev[i] = p.lev[(long)(k0 + i / 3) * kLevW + (c == 0 ? 7 : c == 1 ? 8 : 2)];
+        }
+    };
+    // Stage node s of level k (EOS level data in stlev slot j) into the
+    // plane slot starting at `base`.  The loads are unconditional (a node
+    // outside the lattice reads column 0 and is zeroed after): a load under a
+    // branch makes the compiler wait for it where the branch joins.
+    auto stage = [&](int k, int j, int s, int base) {
+        const uint32_t off = smap[s];
+        const bool in = off != 0xffffffffu;
+        const double *L = stlev + j * 3;
+        const char *b = (const char *)p.qs + ((in ? off : 0u) + plane_bytes * (uint32_t)k);
+        double v0 = *(const double *)(b);
+        double v1 = *(const double *)(b + field_bytes);
+        double v2 = *(const double *)(b + 2 * field_bytes);
+        double v3 = *(const double *)(b + 3 * field_bytes);
+        double v4 = *(const double *)(b + 4 * field_bytes);
+        v0 = in ? v0 : 0.0; v1 = in ? v1 : 0.0; v2 = in ? v2 : 0.0; v3 = in ? v3 : 0.0; v4 = in ? v4 : 0.0;
+        const double pp = pert_pressure(v0, v4, L[0], L[1], L[2], p.gamma, sE);
+        T *P = planes + base + sidx[s];
+        P[0] = T(pp);
+        P[FS] = T(v1);
+        P[2 * FS] = T(v2);
+        P[3 * FS] = T(v3);
+        P[4 * FS] = T(v4);
+        P[5 * FS] = T(v0);
+    };
+
+    // this thread's node class and node.  Waves w, w + 4, w + 8, w + 12 share
+    // a SIMD: class (k, (k + w) mod 4) for wave w + 4k gives every SIMD one
+    // face class in x and one in y (the face rules take 2N+2 taps, the
+    // interior ones N+1), so the SIMDs finish together.
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int ci = wv / N, cj = (wv / N + wv % N) % N;
+    const int lane = tid & 63;
+    const int el = lane % NE;
+    const int ex = el % AX, ey = el / AX;
+    // per-lane values, laundered at every element (below) so that the
+    // compiler does not hoist address arithmetic derived from them out of
+    // the element loop (it would hold it in registers it does not have)
+    int l = lane / NE;
+    int tx = ex * N + ci, ty = ey * N + cj, col = ty * TX + tx;
+    int gx0 = x0 + tx, gy0 = y0 + ty;
+    int noff = S::addr(N + ex * N, N + ey * N) + cj * RP + ci;
+    // wave-uniform derivative rows D[i], D[j] (scalar registers) and this
+    // lane's row D[l] for the z contraction
+    T dxr[N1], dyr[N1];
+#pragma unroll
+    for (int m = 0; m < N1; ++m) {
+        dxr[m] = wave_uniform(sD[ci * N1 + m]);
+        dyr[m] = wave_uniform(sD[cj * N1 + m]);
+    }
+    // plane slot of local level 1..N-1 (level 0 and N: the bottom and top
+    // slots, which alternate between elements)
+    auto mid_slot = [](int m) { return m == 1 ? S::B1 : (m == 2 ? S::B2 : S::B3); };
+
+// NH_FENCE: a compiler memory barrier (no loads moved or merged across it at
+// the IR level) plus a scheduling barrier: it keeps the loads of one field's
+// taps from being hoisted together with every other field's, which would need
+// more registers than a 1024-thread workgroup has.
+#define NH_FENCE()                        \
+    do {                                  \
+        asm volatile("" ::: "memory");    \
+        __builtin_amdgcn_sched_barrier(0); \
+    } while (0)
+#define NH_PIN(a) \
+    asm volatile("" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]))
+
+    struct NodeIn {
+        uint32_t o;
+        bool valid;
+        double qn[5], h0, h1;
+    };
+    // (unconditional loads, as in `stage`; q^n and the heating snapshots are
+    // read from q^s when absent and weighted by zero)
+    auto prefetch = [&](int k, NodeIn &nd) {
+        nd.valid = gx0 < p.nx && gy0 < p.ny;
+        const int gx = nd.valid ? gx0 : 0, gy = nd.valid ? gy0 : 0;
+        nd.o = ((uint32_t)gx + nx * (uint32_t)gy) * 8u + plane_bytes * (uint32_t)k;
+        const char *qnb = (const char *)(p.a != 0.0 ? p.qn : p.qs);
+        const char *h0b = (const char *)(p.hq0 ? p.hq0 : p.qs), *h1b = (const char *)(p.hq0 ? p.hq1 : p.qs);
+#pragma unroll
+        for (int f = 0; f < 5; ++f) nd.qn[f] = *(const double *)(qnb + nd.o + f * field_bytes);
+        nd.h0 = *(const double *)(h0b + nd.o);
+        nd.h1 = *(const double *)(h1b + nd.o);
+    };
+
+    // Derivatives of the staged fields along x or y at the node `nd` of
+    // class c, in the element-average form: S_R = sum_k D[c][k] f(P + R(k))
+    // over the element starting at P = node - c (the node itself on a face)
+    // and, on a face, the mirrored left element S_L = sum_k D[0][k]
+    // f(node - L(k)); with D[N][N-k] = -D[0][k] the average is c1 S_R - c0 S_L
+    // (x: R(k) = L(k) = k; y: R(k) = k RP + PADY at k = N, L(k) = k RP +
+    // PADY for k >= 1).  Field by field, all taps of a field loaded before its
+    // multiply-adds; the momentum component (u along x, v along y) and the
+    // mass flux (rho0 + rho') u share one pass.  Each derivative is folded
+    // into the tendency XY as it is formed: with a the advecting velocity
+    // component (u or v), XY[0] -= d(mass flux), XY[f] -= a d f (f = u, v, w,
+    // theta'), and the pressure gradient -d p' / rho into XY[1] (x) or
+    // XY[2] (y).
+    auto deriv = [&](auto ydir_c, const T *nd, int c, const T (&cr)[N1], T c0, T c1, T r0, T a, T inv, T (&XY)[5]) {
+        constexpr bool ydir = decltype(ydir_c)::value;
+        const T *P = nd - c * (ydir ? RP : 1);
+        const bool face = c == 0;
+        auto offR = [&](int k) { return ydir ? k * RP + (k == N ? PADY : 0) : k; };
+        auto offL = [&](int k) { return ydir ? -(k * RP + (k >= 1 ? PADY : 0)) : -k; };
+        constexpr int FM = ydir ? 2 : 1;
+        T dm, dfl;
+        {
+            T m[N1], v[N1], sr = T(0), sf = T(0);
+#pragma unroll
+            for (int k = 0; k < N1; ++k) m[k] = lds_one(P + FM * FS + offR(k));
+#pragma unroll
+            for (int k = 0; k < N1; ++k) v[k] = lds_one(P + 5 * FS + offR(k));
+#pragma unroll
+            for (int k = 0; k < N1; ++k) {
+                sr += cr[k] * m[k];
+                sf += cr[k] * ((r0 + v[k]) * m[k]);
+            }
+            dm = c1 * sr;
+            dfl = c1 * sf;
+        }
+        if (face) {
+            NH_FENCE();
+            T m[N1], v[N1], sl = T(0), sf = T(0);
+#pragma unroll
+            for (int k = 0; k < N1; ++k) m[k] = lds_one(nd + FM * FS + offL(k));
+#pragma unroll
+            for (int k = 0; k < N1; ++k) v[k] = lds_one(nd + 5 * FS + offL(k));
+#pragma unroll
+            for (int k = 0; k < N1; ++k) {
+                sl += cr[k] * m[k];
+                sf += cr[k] * ((r0 + v[k]) * m[k]);
+            }
+            dm -= c0 * sl;
+            dfl -= c0 * sf;
+        }
+        XY[0] -= dfl;
+        XY[FM] -= a * dm;
+        constexpr int rest[4] = {0, 3 - FM, 3, 4};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            NH_FENCE();
+            const int fo = rest[q] * FS;
+            T v[N1], sr = T(0), sl = T(0);
+#pragma unroll
+            for (int k = 0; k < N1; ++k) v[k] = lds_one(P + fo + offR(k));
+#pragma unroll
+            for (int k = 0; k < N1; ++k) sr += cr[k] * v[k];
+            T dd = c1 * sr;
+            if (face) {
+#pragma unroll
+                for (int k = 0; k < N1; ++k) v[k] = lds_one(nd + fo + offL(k));
+#pragma unroll
+                for (int k = 0; k < N1; ++k) sl += cr[k] * v[k];
+                dd -= c0 * sl;
+            }
+            if (q == 0) XY[FM] -= dd * inv;   // pressure gradient
+            else XY[rest[q]] -= a * dd;
+        }
+    };
+
+    // Complete the tendency at level k (level-data row li of slev) and write
+    // a q^n + b q^s + c R: R holds the x, y and z derivative terms, the
+    // pointwise terms (Coriolis, sponge, buoyancy, heating) are added here.
+    auto finish = [&](int k, int li, const NodeIn &nd, const T *own, const T (&R)[5], const T inv) {
+        NH_FENCE();
+        const bool valid = nd.valid;
+        const int gx = valid ? gx0 : 0, gy = valid ? gy0 : 0;
+        const double *L = slev + li * 5;
+        const uint32_t o = nd.o;
+        const T u = own[FS], v = own[2 * FS], w = own[3 * FS], th = own[4 * FS], rp = own[5 * FS];
+        const T tau = T(L[2]);
+        double qs[5];
+        if constexpr (kF64) {
+            qs[0] = rp; qs[1] = u; qs[2] = v; qs[3] = w; qs[4] = th;
+        } else {
+            const char *qb = (const char *)p.qs + o;
+#pragma unroll
+            for (int f = 0; f < 5; ++f) qs[f] = *(const double *)(qb + f * field_bytes);
+        }
+        double Rd[5];
+        Rd[0] = double(R[0]);
+        Rd[1] = double(R[1] + T(p.fcor) * v - tau * u);
+        Rd[2] = double(R[2] - T(p.fcor) * u - tau * v);
+        Rd[3] = double(R[3] - T(p.g) * rp * inv - tau * w);
+        Rd[4] = double(R[4] - w * T(L[1]) - tau * th);
+        if (p.hq0) Rd[4] += (1.0 - p.hlam) * nd.h0 + p.hlam * nd.h1;
+        if (!p.perx && (gx == 0 || gx == p.nx - 1)) Rd[1] = 0.0;
+        if (!p.pery && (gy == 0 || gy == p.ny - 1)) Rd[2] = 0.0;
+        if (k == 0 || k == p.nz - 1) Rd[3] = 0.0;
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+            const double r = (p.a != 0.0 ? p.a * nd.qn[f] : 0.0) + p.b * qs[f] + p.c * Rd[f];
+            if (valid) *(double *)((char *)p.out + o + f * field_bytes) = r;
+        }
+    };
+
+    // x and y part of the tendency at `own` (reference density r0 of its
+    // level) into R, and 1/rho
+    auto horizontal = [&](const T *own, T r0, T (&R)[5], T &inv) {
+        NH_FENCE();
+        inv = T(1) / (r0 + own[5 * FS]);
+#pragma unroll
+        for (int f = 0; f < 5; ++f) R[f] = T(0);
+        deriv(std::integral_constant<bool, false>{}, own, ci, dxr, ci == 0 ? scx[2 * tx] : T(0), scx[2 * tx + 1], r0,
+              own[FS], inv, R);
+        NH_FENCE();
+        deriv(std::integral_constant<bool, true>{}, own, cj, dyr, cj == 0 ? scy[2 * ty] : T(0), scy[2 * ty + 1], r0,
+              own[2 * FS], inv, R);
+    };
+
+    for (int s = tid; s < NSP; s += NT) stage(0, 0, s, S::B0);
+    for (int ez = 0; ez < p.nelz; ++ez) {
+        asm volatile("" : "+v"(l), "+v"(tx), "+v"(ty), "+v"(col), "+v"(gx0), "+v"(gy0), "+v"(noff));
+        const int sbot = (ez & 1) ? S::B4 : S::B0, stop = (ez & 1) ? S::B0 : S::B4;
+        for (int i = tid; i < N * NSP; i += NT) {
+            const int lv = 1 + i / NSP;
+            stage(ez * N + lv, lv, i % NSP, lv < N ? mid_slot(lv) : stop);
+        }
+        for (int i = tid; i < N1 * 5; i += NT) {
+            const int c = i % 5;
+            slev[i] = p.lev[(long)(ez * N + i / 5) * kLevW + (c == 0 ? 0 : c + 2)];
+        }
+        __syncthreads();
+        const T h2 = T(p.hz2[ez]);
+        {
+            const int k = ez * N + l;
+            const int myslot = (l == 0) ? sbot : mid_slot(l);
+            const T *own = planes + myslot + noff;
+            const T r0 = T(slev[l * 5]);
+            T R[5], inv;
+            horizontal(own, r0, R, inv);
+            NH_FENCE();
+            NodeIn nd;
+            prefetch(k, nd);
+            // z: element-local contraction with this lane's row D[l], tap by
+            // tap (the six accumulators pinned after each tap, so the
+            // scheduler cannot hoist every tap's loads at once); on level 0
+            // the lower element's weighted contribution (the carry) is added.
+            // Folded into R.
+            {
+                NH_FENCE();
+                T dz[6];
+#pragma unroll
+                for (int f = 0; f < 6; ++f) dz[f] = T(0);
+#pragma unroll
+                for (int m = 0; m < N1; ++m) {
+                    const int sm = (m == 0) ? sbot : (m == N ? stop : mid_slot(m));
+                    const T *q = planes + sm + noff;
+                    const T d = sD[l * N1 + m];
+                    const T w = lds_one(q + 3 * FS);
+                    const T r0m = T(slev[m * 5]);
+                    dz[0] += d * lds_one(q);
+                    dz[1] += d * lds_one(q + FS);
+                    dz[2] += d * lds_one(q + 2 * FS);
+                    dz[3] += d * w;
+                    dz[4] += d * lds_one(q + 4 * FS);
+                    dz[5] += d * ((r0m + lds_one(q + 5 * FS)) * w);
+                    NH_PIN(dz);
+                }
+                const bool bot = l == 0;
+                const T sc = bot ? h2 * T(slev[4]) : h2;
+                const T *cry = scarry[ez & 1] + col;
+#pragma unroll
+                for (int f = 0; f < 6; ++f) dz[f] = sc * dz[f] + (bot ? cry[f * NCOL] : T(0));
+                const T w = own[3 * FS];
+                R[0] -= dz[5];
+                R[1] -= w * dz[1];
+                R[2] -= w * dz[2];
+                R[3] -= w * dz[3] + dz[0] * inv;
+                R[4] -= w * dz[4];
+            }
+            finish(k, l, nd, own, R, inv);
+        }
+        // carry for the element above (or the top level): the weighted
+        // one-sided z derivative of this element at its top level (row D[N]),
+        // per column and field
+        NH_FENCE();
+        {
+            const T wlo = T(slev[N * 5 + 3]);
+            for (int t = tid; t < 6 * NCOL; t += NT) {
+                const int c = t % NCOL, f = t / NCOL;
+                const int off = S::addr(N + c % TX, N + c / TX);
+                T v[N1], acc = T(0);
+#pragma unroll
+                for (int m = 0; m < N1; ++m) {
+                    const int sm = (m == 0) ? sbot : (m == N ? stop : mid_slot(m));
+                    v[m] = (f == 5) ? (T(slev[m * 5]) + planes[sm + off + 5 * FS]) * planes[sm + off + 3 * FS]
+                                    : planes[sm + off + f * FS];
+                }
+#pragma unroll
+                for (int m = 0; m < N1; ++m) acc += sD[N * N1 + m] * v[m];
+                scarry[(ez + 1) & 1][t] = wlo * (h2 * acc);
+            }
+        }
+        if (ez + 1 < p.nelz) fill_stlev((ez + 1) * N);
+        __syncthreads();
+    }
+    // top level: only the contribution of the element below (lanes of level
+    // 0 take it; level data of the last element's top row)
+    if (l == 0) {
+        const int ktop = p.nz - 1;
+        const int stop = (p.nelz & 1) ? S::B4 : S::B0;
+        NodeIn nd;
+        prefetch(ktop, nd);
+        const T *own = planes + stop + noff;
+        T R[5], inv;
+        horizontal(own, T(slev[N * 5]), R, inv);
+        const T *cry = scarry[p.nelz & 1] + col;
+        const T w = own[3 * FS];
+        R[0] -= cry[5 * NCOL];
+        R[1] -= w * cry[NCOL];
+        R[2] -= w * cry[2 * NCOL];
+        R[3] -= w * cry[3 * NCOL] + cry[0] * inv;
+        R[4] -= w * cry[4 * NCOL];
+        finish(ktop, N, nd, own, R, inv);
+    }
+#undef NH_FENCE
+#undef NH_PIN
+}
+
+template <int N, int AX, int AY, typename T>
+__global__ void __launch_bounds__((ClsShape<N, AX, AY>::NT)) stage_kernel_cls(const StageParams p)
+{
+    stage_body_cls<N, AX, AY, T>(p, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+template <int N, int AX, int AY, typename T>
+__global__ void __launch_bounds__((ClsShape<N, AX, AY>::NT))
+stage_kernel_cls_batched(const StageParams *__restrict__ P, const int2 *__restrict__ work)
+{
+    const int2 it = work[blockIdx.x];
+    stage_body_cls<N, AX, AY, T>(P[it.x], it.y);
+}
+
 // Tile shapes per order (AX x AY elements).  Variant 0 uses rows of 32 (or
 // 30) lattice columns so that each half-wave's stencil reads cover one
 // contiguous 256-byte LDS row (bank-conflict free); variant 1 is a squarer
@@ -481,13 +968,33 @@ void stage_tile(int N, int variant, int *tx, int *ty)
     switch (N) {
 #define NH_TILE(NN, AX0, AY0, AX1, AY1)                 \
     case NN:                                            \
-        *tx = (variant ? AX1 : AX0) * NN;               \
-        *ty = (variant ? AY1 : AY0) * NN;               \
+        *tx = (variant == 1 ? AX1 : AX0) * NN;          \
+        *ty = (variant == 1 ? AY1 : AY0) * NN;          \
         return;
         NH_TILE_CASES(NH_TILE)
 #undef NH_TILE
     default: *tx = *ty = 0;
     }
+}
+
+template <int N, int AX, int AY>
+static void launch_cls(int precision, const StageParams &p, hipStream_t s)
+{
+    const dim3 grid(p.ntx * p.nty), block(ClsShape<N, AX, AY>::NT);
+    if (precision == 0)
+        hipLaunchKernelGGL((stage_kernel_cls<N, AX, AY, double>), grid, block, 0, s, p);
+    else
+        hipLaunchKernelGGL((stage_kernel_cls<N, AX, AY, float>), grid, block, 0, s, p);
+}
+
+template <int N, int AX, int AY>
+static void launch_cls_batched(int precision, const StageParams *P, const int2 *work, int nitems, hipStream_t s)
+{
+    const dim3 grid(nitems), block(ClsShape<N, AX, AY>::NT);
+    if (precision == 0)
+        hipLaunchKernelGGL((stage_kernel_cls_batched<N, AX, AY, double>), grid, block, 0, s, P, work);
+    else
+        hipLaunchKernelGGL((stage_kernel_cls_batched<N, AX, AY, float>), grid, block, 0, s, P, work);
 }
 
 template <int N, int AX, int AY>
@@ -514,10 +1021,11 @@ hipError_t launch_stage_batched(int N, int precision, int variant, const StagePa
                                 int nitems, hipStream_t s)
 {
     switch (N) {
-#define NH_LAUNCHB(NN, AX0, AY0, AX1, AY1)                                           \
-    case NN:                                                                         \
-        if (variant) launch_batched_one<NN, AX1, AY1>(precision, P, work, nitems, s); \
-        else launch_batched_one<NN, AX0, AY0>(precision, P, work, nitems, s);         \
+#define NH_LAUNCHB(NN, AX0, AY0, AX1, AY1)                                                \
+    case NN:                                                                              \
+        if (variant == 1) launch_batched_one<NN, AX1, AY1>(precision, P, work, nitems, s); \
+        else if (variant == 2 && NN == 4) launch_cls_batched<4, 8, 2>(precision, P, work, nitems, s); \
+        else launch_batched_one<NN, AX0, AY0>(precision, P, work, nitems, s);              \
         break;
         NH_TILE_CASES(NH_LAUNCHB)
 #undef NH_LAUNCHB
@@ -532,7 +1040,8 @@ hipError_t launch_stage(int N, int precision, int variant, const StageParams &p,
     switch (N) {
 #define NH_LAUNCH(NN, AX0, AY0, AX1, AY1)                              \
     case NN:                                                           \
-        if (variant) launch_one<NN, AX1, AY1>(precision, p, s);        \
+        if (variant == 1) launch_one<NN, AX1, AY1>(precision, p, s);   \
+        else if (variant == 2 && NN == 4) launch_cls<4, 8, 2>(precision, p, s); \
         else launch_one<NN, AX0, AY0>(precision, p, s);                \
         break;
         NH_TILE_CASES(NH_LAUNCH)

@@ -30,6 +30,7 @@ struct nh_ctx {
     std::vector<double> lx, ly, lz;     // lattice coordinates
     std::vector<double> m1[3];          // assembled 1D masses
     std::vector<double> G[3];           // [n][2N+1] DSS'd derivative stencils
+    std::vector<double> CF[3];          // [n][2] per-element factors of the same average
     std::vector<double> levtab;         // [n_z][kLevW]
     nh_physics phys;
     bool have_ref;
@@ -39,6 +40,7 @@ struct nh_ctx {
     size_t ws_bytes;
     double *q[3];
     double *gx, *gy, *gz, *xl, *yl, *zl, *lev, *hz2, *mx, *my, *mz, *hx, *hy, *hz, *wl, *cst, *diag_part, *diag_out;
+    double *cfx, *cfy;
     // HEVI workspace (caller-provided, see nh_hevi_attach)
     char *hws;
     size_t hws_bytes;
@@ -181,22 +183,33 @@ void lgl_basis(int N, std::vector<double> &xi, std::vector<double> &w, std::vect
         }
         D[i * n1 + i] = -s;
     }
+    // exact antisymmetry under the reflection of the nodes,
+    // D[N-i][N-j] = -D[i][j] (the first half of the rows is kept)
+    for (int i = 0; i < n1; ++i)
+        for (int j = 0; j < n1; ++j)
+            if (i > N - i || (i == N - i && j > N - j)) D[i * n1 + j] = -D[(N - i) * n1 + (N - j)];
+    if (N % 2 == 0) D[(N / 2) * n1 + N / 2] = 0.0;
 }
 
 // Per-direction tables along one lattice line: coordinates, assembled 1D
-// mass m(I) = sum_{e ∋ I} w_i h_e / 2, and the DSS'd first-derivative
-// stencil G[I][N + o] (offset o in -N..N): the m-weighted average of the
-// one-sided element derivatives (2/h_e) sum_l D_il f(e, l) of the elements
-// sharing I.
+// mass m(I) = sum_{e ∋ I} w_i h_e / 2, the DSS'd first-derivative stencil
+// G[I][N + o] (offset o in -N..N): the m-weighted average of the one-sided
+// element derivatives (2/h_e) sum_l D_il f(e, l) of the elements sharing I,
+// and the two factors of the same average written per element, CF [n][2]:
+// CF[I][0] weights the one-sided derivative of the element in which I is the
+// last node (local index N; 0 if there is none), CF[I][1] that of the
+// element in which I has local index 0..N-1 (0 if there is none), each
+// (w_i h/2) / m(I) * 2/h.
 void line_tables(int N, int nel, int periodic, const double *edges, const std::vector<double> &xi,
                  const std::vector<double> &w, const std::vector<double> &D, std::vector<double> &coord,
-                 std::vector<double> &m1, std::vector<double> &G)
+                 std::vector<double> &m1, std::vector<double> &G, std::vector<double> &CF)
 {
     const int n = nel * N + (periodic ? 0 : 1);
     const int nc = 2 * N + 1, n1 = N + 1;
     coord.assign(n, 0.0);
     m1.assign(n, 0.0);
     G.assign((size_t)n * nc, 0.0);
+    CF.assign((size_t)n * 2, 0.0);
     for (int e = 0; e < nel; ++e) {
         const double h = edges[e + 1] - edges[e];
         for (int i = 0; i < n1; ++i) {
@@ -213,6 +226,7 @@ void line_tables(int N, int nel, int periodic, const double *edges, const std::v
             int I = e * N + i;
             if (periodic) I %= n;
             const double wt = (w[i] * h / 2) / m1[I];
+            CF[(size_t)I * 2 + (i == N ? 0 : 1)] += wt * (2.0 / h);
             for (int l = 0; l < n1; ++l) {
                 const int off = l - i;  // lattice offset of node l relative to node i
                 G[(size_t)I * nc + N + off] += wt * (2.0 / h) * D[i * n1 + l];
@@ -224,7 +238,8 @@ void line_tables(int N, int nel, int periodic, const double *edges, const std::v
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t q[3], gx, gy, gz, xl, yl, zl, gxf, gyf, lev, hz2, mx, my, mz, hx, hy, hz, wl, cst, dpart, dout, total;
+    size_t q[3], gx, gy, gz, xl, yl, zl, gxf, gyf, lev, hz2, mx, my, mz, hx, hy, hz, wl, cst, dpart, dout, cfx, cfy,
+        total;
 };
 
 bool valid_desc(const nh_mesh_desc *m, std::string *why)
@@ -287,6 +302,8 @@ Layout layout_for(const nh_mesh_desc *m)
     L.cst = take(sizeof(double) * kCst);
     L.dpart = take(sizeof(double) * kDiagBlocks * 8);
     L.dout = take(sizeof(double) * 8);
+    L.cfx = take(sizeof(double) * nx * 2);
+    L.cfy = take(sizeof(double) * ny * 2);
     L.total = off;
     return L;
 }
@@ -338,6 +355,7 @@ StageParams stage_params(const nh_ctx *c, double t, const double *qs, const doub
     p.qs = qs; p.qn = qn; p.out = out;
     p.a = a; p.b = b; p.c = cc;
     p.gx = c->gx; p.gy = c->gy; p.gxf = c->gxf; p.gyf = c->gyf;
+    p.cfx = c->cfx; p.cfy = c->cfy;
     p.lev = c->lev; p.hz2 = c->hz2; p.cst = c->cst;
     forcing_at(c, 4, t, &p.hq0, &p.hq1, &p.hlam);
     p.nx = c->n[0]; p.ny = c->n[1]; p.nz = c->n[2]; p.nelz = c->nel[2];
@@ -492,11 +510,13 @@ nh_status nh_init_mesh(const nh_mesh_desc *mesh, const nh_physics *phys, void *d
     c->cst = (double *)(c->ws + L.cst);
     c->diag_part = (double *)(c->ws + L.dpart);
     c->diag_out = (double *)(c->ws + L.dout);
+    c->cfx = (double *)(c->ws + L.cfx);
+    c->cfy = (double *)(c->ws + L.cfy);
 
     lgl_basis(c->N, c->xi, c->w, c->D);
-    line_tables(c->N, c->nel[0], c->per[0], c->xe.data(), c->xi, c->w, c->D, c->lx, c->m1[0], c->G[0]);
-    line_tables(c->N, c->nel[1], c->per[1], c->ye.data(), c->xi, c->w, c->D, c->ly, c->m1[1], c->G[1]);
-    line_tables(c->N, c->nel[2], 0, c->ze.data(), c->xi, c->w, c->D, c->lz, c->m1[2], c->G[2]);
+    line_tables(c->N, c->nel[0], c->per[0], c->xe.data(), c->xi, c->w, c->D, c->lx, c->m1[0], c->G[0], c->CF[0]);
+    line_tables(c->N, c->nel[1], c->per[1], c->ye.data(), c->xi, c->w, c->D, c->ly, c->m1[1], c->G[1], c->CF[1]);
+    line_tables(c->N, c->nel[2], 0, c->ze.data(), c->xi, c->w, c->D, c->lz, c->m1[2], c->G[2], c->CF[2]);
 
     std::vector<float> gxf(c->G[0].begin(), c->G[0].end()), gyf(c->G[1].begin(), c->G[1].end());
     std::vector<double> hz2(c->nel[2]), hx(c->nel[0]), hy(c->nel[1]), hz(c->nel[2]);
@@ -522,6 +542,8 @@ nh_status nh_init_mesh(const nh_mesh_desc *mesh, const nh_physics *phys, void *d
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = up(c->gx, c->G[0].data(), sizeof(double) * c->G[0].size());
     if (e == hipSuccess) e = up(c->gy, c->G[1].data(), sizeof(double) * c->G[1].size());
+    if (e == hipSuccess) e = up(c->cfx, c->CF[0].data(), sizeof(double) * c->CF[0].size());
+    if (e == hipSuccess) e = up(c->cfy, c->CF[1].data(), sizeof(double) * c->CF[1].size());
     if (e == hipSuccess) e = up(c->gz, c->G[2].data(), sizeof(double) * c->G[2].size());
     if (e == hipSuccess) e = up(c->xl, c->lx.data(), sizeof(double) * c->lx.size());
     if (e == hipSuccess) e = up(c->yl, c->ly.data(), sizeof(double) * c->ly.size());
@@ -570,7 +592,7 @@ nh_status nh_set_tile(nh_ctx *c, int32_t variant)
 {
     nh_status st = guard(c);
     if (st) return st;
-    if (variant < 0 || variant >= kTileVariants) return fail(c, NH_EINVAL, "tile variant must be 0 or 1");
+    if (variant < 0 || variant >= kTileVariants) return fail(c, NH_EINVAL, "tile variant must be 0, 1 or 2");
     c->tile = variant;
     return NH_OK;
 }

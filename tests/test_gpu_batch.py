@@ -112,8 +112,9 @@ def test_batch_rechecks_contexts_at_step():
     np.testing.assert_array_equal(got, ctx.nh_get_state().cpu().numpy())
 
 
-@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32_mixed"])
-def test_ensemble48_batched_equals_single(precision):
+@pytest.mark.parametrize("precision,tv", [(0, {3: 1, 4: 0, 5: 1}), (0, {3: 0, 4: 2, 5: 1}),
+                                          (1, {3: 1, 4: 2, 5: 0})], ids=["fp64", "fp64_class", "fp32_mixed_class"])
+def test_ensemble48_batched_equals_single(precision, tv):
     """The 48-member uneven ensemble (8 x 8 x 8 ... 40 x 40 x 16 elements,
     N in 3..5, 23.5 M unique nodes) in FP64 and FP32-mixed: two steps in
     batched graph launches equal, bit for bit, two steps of each member on
@@ -136,12 +137,13 @@ def test_ensemble48_batched_equals_single(precision):
     dt = 0.25
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
-        b = nhsem.Batch(ctxs, steps_per_graph=2, tile_variant={3: 1, 4: 0, 5: 1}, stream=s)
+        b = nhsem.Batch(ctxs, steps_per_graph=2, tile_variant=tv, stream=s)
         b.nh_batch_step(0.0, dt, 2)
     torch.cuda.synchronize()
     got = [c.nh_get_state() for c in ctxs]
     b.close()
     for i, (c, q0) in enumerate(zip(ctxs, q0s)):
+        c.nh_set_tile(tv[c.mesh.order])
         c.nh_set_state(q0)
         c.nh_rk_step(0.0, dt, 2)
         assert torch.equal(got[i], c.nh_get_state()), i

@@ -68,6 +68,53 @@ def test_rhs_parity(oracle_mod, name, nel, N, per, stretch):
     assert (err <= TOL64).all(), err
 
 
+# the node-class form of the stage kernel (tile variant 2, order 4): every
+# order-4 case above plus a mesh of several tiles with ragged edges in x and
+# y and an odd number of element layers (the bottom/top plane slots swap
+# roles every layer)
+CLS_CASES = [c for c in RHS_CASES if c[2] == 4] + [
+    ("multi_tile_ragged_N4", (11, 5, 3), 4, (True, False), True),
+    ("walls_tall_N4", (3, 2, 7), 4, (False, False), True),
+]
+
+
+@pytest.mark.parametrize("name,nel,N,per,stretch", CLS_CASES, ids=[c[0] for c in CLS_CASES])
+def test_rhs_parity_class_kernel(oracle_mod, name, nel, N, per, stretch):
+    ph = W.Physics(f=1e-3, sponge_z0=600.0, sponge_tau=0.05)
+    ctx, orc, g, o, prof, torch = _pair(oracle_mod, _mesh(nel, N, per, stretch=stretch), ph)
+    ctx.nh_set_tile(2)
+    walls = (not per[0], not per[1])
+    qg = W.smooth_random_state(*g, *prof(g[2]), seed=7, walls=walls)
+    qo = W.smooth_random_state(*o, *prof(o[2]), seed=7, walls=walls)
+    dq = ctx.nh_rhs(0.0, torch.from_numpy(qg).cuda()).cpu().numpy()
+    ref = orc.rhs(0.0, qo)
+    err = _rel(dq, ref)
+    print(name, err)
+    assert (err <= TOL64).all(), err
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32_mixed"])
+def test_rk3_class_kernel_tc_with_heating(oracle_mod, precision):
+    """Ten SSP-RK3 steps of the heated vortex through the node-class stage
+    kernel, FP64 to 1e-12 and FP32-mixed to the FP32 tolerances."""
+    w = W.cfg_tc_small()
+    w.mesh = W._tc_mesh(9, 5, 3)
+    ctx, orc, g, o, prof, torch = _pair(oracle_mod, w.mesh, w.phys, reference="constant_n", precision=precision)
+    ctx.nh_set_tile(2)
+    tg, Qg = W.heating(w, *g)
+    to, Qo = W.heating(w, *o)
+    Qdev = torch.from_numpy(Qg.reshape(len(tg), -1)).cuda()
+    ctx.nh_set_forcing(4, tg - 1500.0, Qdev)
+    orc.set_forcing(4, to - 1500.0, Qo)
+    ctx.nh_set_state(torch.from_numpy(W.initial_state(w, *g)).cuda())
+    ctx.nh_rk_step(0.0, 2.0, 10)
+    got = ctx.nh_get_state().cpu().numpy()
+    ref = orc.rk3(0.0, 2.0, 10, W.initial_state(w, *o))
+    err = _rel(got, ref)
+    print("class kernel", precision, err)
+    assert (err <= (TOL64 if precision == 0 else TOL32_RK)).all(), err
+
+
 def test_rest_state_exactly_zero(oracle_mod):
     ph = W.Physics(f=5e-5, sponge_z0=500.0, sponge_tau=0.02)
     ctx, orc, g, o, prof, torch = _pair(oracle_mod, _mesh((5, 4, 3), 4, (True, False), stretch=True), ph,
@@ -262,7 +309,7 @@ def test_tile_variants_bitwise_equal(oracle_mod, N):
         outs.append(ctx.nh_rhs(0.0, q).cpu().numpy())
     np.testing.assert_array_equal(outs[0], outs[1])
     with pytest.raises(nhsem.NHError):
-        ctx.nh_set_tile(2)
+        ctx.nh_set_tile(3)
 
 
 def test_full_size_sampled_rhs_parity(oracle_mod):
@@ -302,7 +349,7 @@ def test_full_size_sampled_rhs_parity(oracle_mod):
 
     qr = W.smooth_random_state(*o, *prof(o[2]), seed=8, walls=(False, False))
     ref = orc.rhs_sample(t, qr, nodes)
-    for v in (0, 1):
+    for v in (0, 1, 2):
         err = _rel(gpu(qr, v), ref)
         print("random, tile", v, err)
         assert (err <= TOL64).all(), (v, err)
@@ -331,7 +378,7 @@ def test_full_size_sampled_rhs_parity(oracle_mod):
     wind = np.abs(qv[1].reshape(-1)[nodes]) + np.abs(qv[2].reshape(-1)[nodes])
     summands = th0[iz] * (2.0 / hx) * np.abs(Dm).sum(axis=1).max() * wind
     scale[4] = max(scale[4], 1e-3 * np.linalg.norm(summands))
-    for v in (0, 1):
+    for v in (0, 1, 2):
         err = np.linalg.norm(gpu(qv, v) - ref, axis=1) / scale
         print("vortex, tile", v, err, "scales", scale)
         assert (err <= TOL64).all(), (v, err)
