@@ -401,6 +401,19 @@ nh_status nh_batch_workspace_bytes(nh_ctx *const *ctxs, int32_t n, int32_t steps
 nh_status nh_batch_create(nh_ctx *const *ctxs, int32_t n, int32_t steps_per_graph, const int32_t *tile_variant,
                           void *dev_ws, size_t bytes, void *hip_stream, nh_batch **out);
 
+/* Launch form of the next graph capture (the current graph, if any, is
+   dropped).  persistent = 1: per (order group, stage) one launch of at most
+   one workgroup per compute unit, whose workgroups take (instance, tile)
+   items from the cost-sorted list through a device counter in the batch
+   workspace, zeroed by a fill kernel at the start of each graph replay
+   (persistent = 0: one workgroup per item).  concurrent_groups = 1: each
+   order group's chain of stage launches is captured on a stream of its own
+   (forked from and joined back to the batch stream), so the groups'
+   launches may overlap; otherwise they run in step, stage, group order.
+   Results do not depend on the form.  Default 0, 0.  NH_EINVAL for flags
+   other than 0 or 1. */
+nh_status nh_batch_set_mode(nh_batch *b, int32_t persistent, int32_t concurrent_groups);
+
 /* Advance every instance nsteps (a multiple of steps_per_graph) from t.
    Re-checks every context first: NH_EUNSUPPORTED if one has since turned on
    hyper-diffusion or forcing of fields 0..3, NH_EINVAL if its precision

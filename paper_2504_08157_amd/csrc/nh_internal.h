@@ -55,8 +55,12 @@ struct GeomParams {
 };
 
 hipError_t launch_stage(int N, int precision, int variant, const StageParams &p, hipStream_t s);
+// Grouped stage launch over `nitems` (instance, tile) items; with a device
+// counter (zeroed beforehand) the persistent form with at most persist_grid
+// workgroups, else one workgroup per item.
 hipError_t launch_stage_batched(int N, int precision, int variant, const StageParams *P, const int2 *work,
-                                int nitems, hipStream_t s);
+                                int nitems, int *counter, int persist_grid, hipStream_t s);
+hipError_t launch_zero_ints(int *p, int n, hipStream_t s);
 struct WallParams {
     int nx, ny, nz, perx, pery;
 };

@@ -93,7 +93,7 @@ struct StageShape {
 // contribution at the shared bottom level is carried in registers by the
 // threads that own the bottom level (same threads for every element).
 template <int N, int AX, int AY, typename T>
-__device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
+__device__ __forceinline__ void stage_body(const StageParams &p, const int tile, const int tid)
 {
     using S = StageShape<N, AX, AY>;
     constexpr int N1 = S::N1, TX = S::TX, TY = S::TY, NCOL = S::NCOL, NOWN = S::NOWN;
@@ -121,7 +121,6 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile)
     __shared__ double stlev[N1 * 3];
     __shared__ T scarry[6 * NCOL];
 
-    const int tid = threadIdx.x;
     const int bx = tile % p.ntx, by = tile / p.ntx;
     const int x0 = bx * TX, y0 = by * TY;
     const uint32_t nx = p.nx, ny = p.ny;
@@ -451,7 +450,7 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
 template <int N, int AX, int AY, typename T>
 __global__ void __launch_bounds__((StageShape<N, AX, AY>::NT)) stage_kernel(const StageParams p)
 {
-    stage_body<N, AX, AY, T>(p, xcd_tile(blockIdx.x, gridDim.x));
+    stage_body<N, AX, AY, T>(p, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x);
 }
 
 // Batched form: workgroup b takes work item work[b] = (instance, tile) from a
@@ -462,7 +461,7 @@ __global__ void __launch_bounds__((StageShape<N, AX, AY>::NT))
 stage_kernel_batched(const StageParams *__restrict__ P, const int2 *__restrict__ work)
 {
     const int2 it = work[blockIdx.x];
-    stage_body<N, AX, AY, T>(P[it.x], it.y);
+    stage_body<N, AX, AY, T>(P[it.x], it.y, threadIdx.x);
 }
 
 // ---------------------------------------------------------------- stage, node-class form
@@ -535,7 +534,7 @@ __device__ __forceinline__ T lds_one(const T *p)
 }
 
 template <int N, int AX, int AY, typename T>
-__device__ __forceinline__ void stage_body_cls(const StageParams &p, const int tile)
+__device__ __forceinline__ void stage_body_cls(const StageParams &p, const int tile, const int tid)
 {
     using S = ClsShape<N, AX, AY>;
     constexpr int N1 = S::N1, NE = S::NE, TX = S::TX, TY = S::TY, NCOL = S::NCOL, NT = S::NT;
@@ -553,7 +552,6 @@ __device__ __forceinline__ void stage_body_cls(const StageParams &p, const int t
     // per tile column / row: the two factors of the x (y) average (cfx, cfy)
     __shared__ T scx[2 * TX], scy[2 * TY];
 
-    const int tid = threadIdx.x;
     const int bx = tile % p.ntx, by = tile / p.ntx;
     const int x0 = bx * TX, y0 = by * TY;
     const uint32_t nx = p.nx, ny = p.ny;
@@ -941,7 +939,7 @@ __device__ __forceinline__ void stage_body_cls(const StageParams &p, const int t
 template <int N, int AX, int AY, typename T>
 __global__ void __launch_bounds__((ClsShape<N, AX, AY>::NT)) stage_kernel_cls(const StageParams p)
 {
-    stage_body_cls<N, AX, AY, T>(p, xcd_tile(blockIdx.x, gridDim.x));
+    stage_body_cls<N, AX, AY, T>(p, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x);
 }
 
 template <int N, int AX, int AY, typename T>
@@ -949,27 +947,89 @@ __global__ void __launch_bounds__((ClsShape<N, AX, AY>::NT))
 stage_kernel_cls_batched(const StageParams *__restrict__ P, const int2 *__restrict__ work)
 {
     const int2 it = work[blockIdx.x];
-    stage_body_cls<N, AX, AY, T>(P[it.x], it.y);
+    stage_body_cls<N, AX, AY, T>(P[it.x], it.y, threadIdx.x);
 }
 
-// Tile shapes per order (AX x AY elements).  Variant 0 uses rows of 32 (or
-// 30) lattice columns so that each half-wave's stencil reads cover one
-// contiguous 256-byte LDS row (bank-conflict free); variant 1 is a squarer
-// ~16 x 16 tile with a smaller halo.
-#define NH_TILE_CASES(X) \
-    X(2, 16, 4, 8, 8)    \
-    X(3, 10, 3, 5, 5)    \
-    X(4, 8, 2, 4, 4)     \
-    X(5, 6, 1, 3, 2)     \
-    X(6, 4, 1, 2, 2)
+// Persistent batched forms: a grid of at most one workgroup per CU, each
+// workgroup taking (instance, tile) items from the cost-sorted list in order
+// through a device counter (one vector atomic per item, by thread 0) until
+// the list is exhausted -- every workgroup reaches the exit.  The counter is
+// zeroed by a fill kernel before the launch (inside the captured graph).
+template <int N, int AX, int AY, typename T>
+__global__ void __launch_bounds__((StageShape<N, AX, AY>::NT))
+stage_kernel_persist(const StageParams *__restrict__ P, const int2 *__restrict__ work, int nitems, int *counter)
+{
+    __shared__ int item;
+    for (;;) {
+        if (threadIdx.x == 0) item = __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        // uniform across the workgroup: readfirstlane lets the compiler keep
+        // the item's descriptor in scalar registers
+        const int it = __builtin_amdgcn_readfirstlane(item);
+        __syncthreads();
+        if (it >= nitems) break;
+        // the thread index is passed laundered, so that per-thread arithmetic
+        // of the body is not hoisted out of the item loop (and held in
+        // registers across items)
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const int2 w = work[it];
+        stage_body<N, AX, AY, T>(P[w.x], w.y, tid);
+        __syncthreads();
+    }
+}
+
+template <int N, int AX, int AY, typename T>
+__global__ void __launch_bounds__((ClsShape<N, AX, AY>::NT))
+stage_kernel_cls_persist(const StageParams *__restrict__ P, const int2 *__restrict__ work, int nitems, int *counter)
+{
+    __shared__ int item;
+    for (;;) {
+        if (threadIdx.x == 0) item = __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        // uniform across the workgroup: readfirstlane lets the compiler keep
+        // the item's descriptor in scalar registers
+        const int it = __builtin_amdgcn_readfirstlane(item);
+        __syncthreads();
+        if (it >= nitems) break;
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const int2 w = work[it];
+        stage_body_cls<N, AX, AY, T>(P[w.x], w.y, tid);
+        __syncthreads();
+    }
+}
+
+__global__ void zero_ints_kernel(int *p, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+hipError_t launch_zero_ints(int *p, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_ints_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+// Tile shapes per order (AX x AY elements), three per order.  Variant 0 uses
+// rows of 32 (or 30) lattice columns so that each half-wave's stencil reads
+// cover one contiguous 256-byte LDS row (bank-conflict free); variant 1 is a
+// squarer ~16 x 16 tile with a smaller halo; variant 2 a third shape (order 4:
+// variant 0's tile in the node-class form).
+#define NH_TILE_CASES(X)    \
+    X(2, 16, 4, 8, 8, 16, 8) \
+    X(3, 10, 3, 5, 5, 8, 4)  \
+    X(4, 8, 2, 4, 4, 8, 2)   \
+    X(5, 6, 1, 3, 2, 4, 2)   \
+    X(6, 4, 1, 2, 2, 3, 1)
 
 void stage_tile(int N, int variant, int *tx, int *ty)
 {
     switch (N) {
-#define NH_TILE(NN, AX0, AY0, AX1, AY1)                 \
-    case NN:                                            \
-        *tx = (variant == 1 ? AX1 : AX0) * NN;          \
-        *ty = (variant == 1 ? AY1 : AY0) * NN;          \
+#define NH_TILE(NN, AX0, AY0, AX1, AY1, AX2, AY2)                          \
+    case NN:                                                               \
+        *tx = (variant == 1 ? AX1 : (variant == 2 ? AX2 : AX0)) * NN;      \
+        *ty = (variant == 1 ? AY1 : (variant == 2 ? AY2 : AY0)) * NN;      \
         return;
         NH_TILE_CASES(NH_TILE)
 #undef NH_TILE
@@ -1008,24 +1068,55 @@ static void launch_one(int precision, const StageParams &p, hipStream_t s)
 }
 
 template <int N, int AX, int AY>
-static void launch_batched_one(int precision, const StageParams *P, const int2 *work, int nitems, hipStream_t s)
+static void launch_batched_one(int precision, const StageParams *P, const int2 *work, int nitems, int *counter,
+                               int persist_grid, hipStream_t s)
 {
-    const dim3 grid(nitems), block(StageShape<N, AX, AY>::NT);
+    const dim3 block(StageShape<N, AX, AY>::NT);
+    if (counter) {
+        const dim3 grid(nitems < persist_grid ? nitems : persist_grid);
+        if (precision == 0)
+            hipLaunchKernelGGL((stage_kernel_persist<N, AX, AY, double>), grid, block, 0, s, P, work, nitems, counter);
+        else
+            hipLaunchKernelGGL((stage_kernel_persist<N, AX, AY, float>), grid, block, 0, s, P, work, nitems, counter);
+        return;
+    }
+    const dim3 grid(nitems);
     if (precision == 0)
         hipLaunchKernelGGL((stage_kernel_batched<N, AX, AY, double>), grid, block, 0, s, P, work);
     else
         hipLaunchKernelGGL((stage_kernel_batched<N, AX, AY, float>), grid, block, 0, s, P, work);
 }
 
+template <int N, int AX, int AY>
+static void launch_cls_batched_any(int precision, const StageParams *P, const int2 *work, int nitems, int *counter,
+                                   int persist_grid, hipStream_t s)
+{
+    const dim3 block(ClsShape<N, AX, AY>::NT);
+    if (counter) {
+        const dim3 grid(nitems < persist_grid ? nitems : persist_grid);
+        if (precision == 0)
+            hipLaunchKernelGGL((stage_kernel_cls_persist<N, AX, AY, double>), grid, block, 0, s, P, work, nitems,
+                               counter);
+        else
+            hipLaunchKernelGGL((stage_kernel_cls_persist<N, AX, AY, float>), grid, block, 0, s, P, work, nitems,
+                               counter);
+        return;
+    }
+    launch_cls_batched<N, AX, AY>(precision, P, work, nitems, s);
+}
+
 hipError_t launch_stage_batched(int N, int precision, int variant, const StageParams *P, const int2 *work,
-                                int nitems, hipStream_t s)
+                                int nitems, int *counter, int persist_grid, hipStream_t s)
 {
     switch (N) {
-#define NH_LAUNCHB(NN, AX0, AY0, AX1, AY1)                                                \
-    case NN:                                                                              \
-        if (variant == 1) launch_batched_one<NN, AX1, AY1>(precision, P, work, nitems, s); \
-        else if (variant == 2 && NN == 4) launch_cls_batched<4, 8, 2>(precision, P, work, nitems, s); \
-        else launch_batched_one<NN, AX0, AY0>(precision, P, work, nitems, s);              \
+#define NH_LAUNCHB(NN, AX0, AY0, AX1, AY1, AX2, AY2)                                                          \
+    case NN:                                                                                                  \
+        if (variant == 1) launch_batched_one<NN, AX1, AY1>(precision, P, work, nitems, counter, persist_grid, s); \
+        else if (variant == 2 && NN == 4)                                                                     \
+            launch_cls_batched_any<4, 8, 2>(precision, P, work, nitems, counter, persist_grid, s);            \
+        else if (variant == 2)                                                                                \
+            launch_batched_one<NN, AX2, AY2>(precision, P, work, nitems, counter, persist_grid, s);           \
+        else launch_batched_one<NN, AX0, AY0>(precision, P, work, nitems, counter, persist_grid, s);          \
         break;
         NH_TILE_CASES(NH_LAUNCHB)
 #undef NH_LAUNCHB
@@ -1038,10 +1129,11 @@ hipError_t launch_stage_batched(int N, int precision, int variant, const StagePa
 hipError_t launch_stage(int N, int precision, int variant, const StageParams &p, hipStream_t s)
 {
     switch (N) {
-#define NH_LAUNCH(NN, AX0, AY0, AX1, AY1)                              \
+#define NH_LAUNCH(NN, AX0, AY0, AX1, AY1, AX2, AY2)                    \
     case NN:                                                           \
         if (variant == 1) launch_one<NN, AX1, AY1>(precision, p, s);   \
         else if (variant == 2 && NN == 4) launch_cls<4, 8, 2>(precision, p, s); \
+        else if (variant == 2) launch_one<NN, AX2, AY2>(precision, p, s); \
         else launch_one<NN, AX0, AY0>(precision, p, s);                \
         break;
         NH_TILE_CASES(NH_LAUNCH)

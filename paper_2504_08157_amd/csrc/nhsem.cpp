@@ -1703,6 +1703,12 @@ nh_status nh_mlp_destroy(nh_mlp *m)
 struct nh_batch {
     std::vector<nh_ctx *> ctx;
     int K, precision;
+    // persistent: one persistent launch per (order group, stage) fed by a
+    // device counter; concurrent: each order group's chain of launches on a
+    // stream of its own inside the graph (the groups' launches overlap)
+    bool persistent, concurrent;
+    int *counters;        // device [K][3][groups]
+    int persist_grid;     // workgroups of a persistent launch (one per CU)
     struct Group {
         int N, variant, nitems;
         int2 *work;  // device
@@ -1720,18 +1726,25 @@ struct nh_batch {
 
 namespace {
 
+// Workspace of a batch: the work lists (sized for the tile variant with the
+// most tiles), the per-stage descriptor tables of K steps and the counters of
+// the persistent launches (K steps x 3 stages x at most kMaxN - 1 order groups).
+size_t batch_tables_bytes(int n, int K) { return align_up(sizeof(StageParams) * (size_t)K * 3 * n); }
+size_t batch_counter_bytes(int K) { return align_up(sizeof(int) * (size_t)K * 3 * (kMaxN - 1)); }
+
 size_t batch_bytes(nh_ctx *const *ctxs, int n, int K)
 {
     size_t tiles = 0;
     for (int i = 0; i < n; ++i) {
-        int tx, ty, tx1, ty1;
-        stage_tile(ctxs[i]->N, 0, &tx, &ty);
-        stage_tile(ctxs[i]->N, 1, &tx1, &ty1);
-        const size_t t0 = (size_t)((ctxs[i]->n[0] + tx - 1) / tx) * ((ctxs[i]->n[1] + ty - 1) / ty);
-        const size_t t1 = (size_t)((ctxs[i]->n[0] + tx1 - 1) / tx1) * ((ctxs[i]->n[1] + ty1 - 1) / ty1);
-        tiles += std::max(t0, t1);
+        size_t most = 0;
+        for (int v = 0; v < kTileVariants; ++v) {
+            int tx, ty;
+            stage_tile(ctxs[i]->N, v, &tx, &ty);
+            most = std::max(most, (size_t)((ctxs[i]->n[0] + tx - 1) / tx) * ((ctxs[i]->n[1] + ty - 1) / ty));
+        }
+        tiles += most;
     }
-    return align_up(sizeof(int2) * tiles) + align_up(sizeof(StageParams) * (size_t)K * 3 * n);
+    return align_up(sizeof(int2) * tiles) + batch_tables_bytes(n, K) + batch_counter_bytes(K);
 }
 
 nh_status bfail(nh_batch *b, nh_status code, const char *fmt, ...)
@@ -1801,6 +1814,15 @@ nh_status nh_batch_create(nh_ctx *const *ctxs, int32_t n, int32_t steps_per_grap
     b->sticky = false;
     b->graph = nullptr;
     b->exec = nullptr;
+    b->persistent = false;
+    b->concurrent = false;
+    b->persist_grid = 256;
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            b->persist_grid = cus;
+    }
     char *w = (char *)dev_ws;
     int2 *work = (int2 *)w;
     size_t tiles_total = 0;
@@ -1832,8 +1854,11 @@ nh_status nh_batch_create(nh_ctx *const *ctxs, int32_t n, int32_t steps_per_grap
     for (int i = 0; i < n; ++i)
         for (const auto &g : b->groups)
             if (g.N == ctxs[i]->N) b->variant[i] = g.variant;
-    // descriptor tables sit after the work lists (sized for the larger tile variant)
-    b->table = (StageParams *)(w + (need - align_up(sizeof(StageParams) * (size_t)steps_per_graph * 3 * n)));
+    // descriptor tables and counters sit after the work lists (sized for the
+    // tile variant with the most tiles)
+    b->table = (StageParams *)(w + (need - batch_counter_bytes(steps_per_graph) -
+                                    batch_tables_bytes(n, steps_per_graph)));
+    b->counters = (int *)(w + (need - batch_counter_bytes(steps_per_graph)));
     b->host.resize((size_t)steps_per_graph * 3 * n);
     hipError_t e = hipMemcpyAsync(work, all.data(), sizeof(int2) * all.size(), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -1882,18 +1907,69 @@ nh_status nh_batch_step(nh_batch *b, double t, double dt, int32_t nsteps)
         BCHK(b, hipMemcpyAsync(b->table, b->host.data(), sizeof(StageParams) * b->host.size(),
                                hipMemcpyHostToDevice, b->stream));
         if (!b->captured) {
-            BCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+            const int ng = (int)b->groups.size();
+            // fork/join streams and events of the concurrent form (default
+            // priority), released once the capture has ended
+            std::vector<hipStream_t> gs;
+            std::vector<hipEvent_t> ev;
             hipError_t e = hipSuccess;
-            for (int k = 0; k < b->K && e == hipSuccess; ++k)
-                for (int s = 0; s < 3 && e == hipSuccess; ++s)
-                    for (const auto &g : b->groups) {
-                        e = launch_stage_batched(g.N, b->precision, g.variant, b->table + ((size_t)k * 3 + s) * n,
-                                                 g.work, g.nitems, b->stream);
-                        if (e != hipSuccess) break;
-                    }
+            if (b->concurrent) {
+                for (int g = 0; g < ng && e == hipSuccess; ++g) {
+                    hipStream_t st = nullptr;
+                    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+                    if (e == hipSuccess) gs.push_back(st);
+                }
+                for (int g = 0; g <= ng && e == hipSuccess; ++g) {
+                    hipEvent_t x = nullptr;
+                    e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
+                    if (e == hipSuccess) ev.push_back(x);
+                }
+            }
+            auto release = [&]() {
+                for (auto st : gs) (void)hipStreamDestroy(st);
+                for (auto x : ev) (void)hipEventDestroy(x);
+            };
+            if (e != hipSuccess) {
+                release();
+                return bfail(b, NH_EHIP, "streams for the concurrent form: %s", hipGetErrorString(e));
+            }
+            e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) {
+                release();
+                return bfail(b, NH_EHIP, "begin capture: %s", hipGetErrorString(e));
+            }
+            // counters are cleared by a fill kernel (not a memset node)
+            if (b->persistent) e = launch_zero_ints(b->counters, b->K * 3 * (kMaxN - 1), b->stream);
+            if (b->concurrent && e == hipSuccess) {
+                e = hipEventRecord(ev[ng], b->stream);
+                for (int g = 0; g < ng && e == hipSuccess; ++g) e = hipStreamWaitEvent(gs[g], ev[ng], 0);
+            }
+            auto launch = [&](int k, int s, int g) {
+                const auto &G = b->groups[g];
+                int *ctr = b->persistent ? b->counters + ((size_t)k * 3 + s) * (kMaxN - 1) + g : nullptr;
+                return launch_stage_batched(G.N, b->precision, G.variant, b->table + ((size_t)k * 3 + s) * n, G.work,
+                                            G.nitems, ctr, b->persist_grid, b->concurrent ? gs[g] : b->stream);
+            };
+            if (b->concurrent) {
+                for (int g = 0; g < ng && e == hipSuccess; ++g)
+                    for (int k = 0; k < b->K && e == hipSuccess; ++k)
+                        for (int s = 0; s < 3 && e == hipSuccess; ++s) e = launch(k, s, g);
+                for (int g = 0; g < ng && e == hipSuccess; ++g) {
+                    e = hipEventRecord(ev[g], gs[g]);
+                    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, ev[g], 0);
+                }
+            } else {
+                for (int k = 0; k < b->K && e == hipSuccess; ++k)
+                    for (int s = 0; s < 3 && e == hipSuccess; ++s)
+                        for (int g = 0; g < ng && e == hipSuccess; ++g) e = launch(k, s, g);
+            }
             hipGraph_t graph = nullptr;
             hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
-            if (e != hipSuccess) return bfail(b, NH_EHIP, "capture: %s", hipGetErrorString(e));
+            release();
+            if (e != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return bfail(b, NH_EHIP, "capture: %s", hipGetErrorString(e));
+            }
             if (e2 != hipSuccess) return bfail(b, NH_EHIP, "end capture: %s", hipGetErrorString(e2));
             b->graph = graph;
             BCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
@@ -1901,6 +1977,23 @@ nh_status nh_batch_step(nh_batch *b, double t, double dt, int32_t nsteps)
         }
         BCHK(b, hipGraphLaunch(b->exec, b->stream));
     }
+    return NH_OK;
+}
+
+nh_status nh_batch_set_mode(nh_batch *b, int32_t persistent, int32_t concurrent_groups)
+{
+    if (!b) return fail(nullptr, NH_EINVAL, "null batch");
+    if (b->sticky) return NH_ESTATE;
+    if ((persistent != 0 && persistent != 1) || (concurrent_groups != 0 && concurrent_groups != 1))
+        return bfail(b, NH_EINVAL, "mode flags must be 0 or 1");
+    b->persistent = persistent != 0;
+    b->concurrent = concurrent_groups != 0;
+    // the next step captures the graph again
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->captured = false;
     return NH_OK;
 }
 

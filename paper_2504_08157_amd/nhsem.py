@@ -99,6 +99,7 @@ _SIGS = {
     "nh_batch_create": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, ctypes.c_size_t, _vp,
                                          ctypes.POINTER(_vp)]),
     "nh_batch_step": (ctypes.c_int32, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32]),
+    "nh_batch_set_mode": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int32]),
     "nh_batch_last_error": (ctypes.c_int32, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     "nh_batch_destroy": (ctypes.c_int32, [_vp]),
     "nh_mlp_workspace_bytes": (ctypes.c_int32, [ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
@@ -623,7 +624,8 @@ class ColumnMLP:
 class Batch:
     """Batched SSP-RK3 over several Contexts, one graph per K steps."""
 
-    def __init__(self, contexts, steps_per_graph=1, tile_variant=None, stream=None):
+    def __init__(self, contexts, steps_per_graph=1, tile_variant=None, stream=None, persistent=False,
+                 concurrent=False):
         import torch
         self.lib = load()
         self.contexts = list(contexts)
@@ -641,6 +643,15 @@ class Batch:
                                               n.value, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
         self.h = h
         self.K = steps_per_graph
+        if persistent or concurrent:
+            self.nh_batch_set_mode(persistent, concurrent)
+
+    def nh_batch_set_mode(self, persistent, concurrent):
+        code = self.lib.nh_batch_set_mode(self.h, 1 if persistent else 0, 1 if concurrent else 0)
+        if code != NH_OK:
+            buf = ctypes.create_string_buffer(512)
+            self.lib.nh_batch_last_error(self.h, buf, 512)
+            raise NHError(code, buf.value.decode(errors="replace"))
 
     def nh_batch_step(self, t, dt, nsteps):
         code = self.lib.nh_batch_step(self.h, float(t), float(dt), int(nsteps))

@@ -28,19 +28,25 @@ def _instance(i, nel, N, device="cuda"):
 SPECS = [((5, 4, 3), 4), ((3, 6, 2), 3), ((4, 3, 2), 5), ((7, 5, 4), 4), ((2, 2, 3), 2)]
 
 
-def test_batched_equals_single_instances(oracle_mod):
+# launch forms of the batch: (persistent, concurrent order groups)
+MODES = [(False, False), (True, False), (False, True), (True, True)]
+
+
+@pytest.mark.parametrize("persistent,concurrent", MODES, ids=["graph", "persistent", "concurrent", "persist_conc"])
+def test_batched_equals_single_instances(oracle_mod, persistent, concurrent):
     import torch
     from paper_2504_08157_amd import nhsem
     ctxs, q0s = zip(*[_instance(i, nel, N) for i, (nel, N) in enumerate(SPECS)])
     dt, steps = 1.0, 4
+    tv = {2: 2, 3: 2, 4: 1, 5: 2}
     with torch.cuda.stream(torch.cuda.Stream()):
-        b = nhsem.Batch(ctxs, steps_per_graph=2, tile_variant={4: 1})
+        b = nhsem.Batch(ctxs, steps_per_graph=2, tile_variant=tv, persistent=persistent, concurrent=concurrent)
         b.nh_batch_step(0.0, dt, steps)
         torch.cuda.synchronize()
     got = [c.nh_get_state().cpu().numpy() for c in ctxs]
     b.close()
     for c, q0, gb in zip(ctxs, q0s, got):
-        c.nh_set_tile(0)
+        c.nh_set_tile(tv.get(c.mesh.order, 0))
         c.nh_set_state(q0)
         c.nh_rk_step(0.0, dt, steps)
         ref = c.nh_get_state().cpu().numpy()
@@ -112,13 +118,16 @@ def test_batch_rechecks_contexts_at_step():
     np.testing.assert_array_equal(got, ctx.nh_get_state().cpu().numpy())
 
 
-@pytest.mark.parametrize("precision,tv", [(0, {3: 1, 4: 0, 5: 1}), (0, {3: 0, 4: 2, 5: 1}),
-                                          (1, {3: 1, 4: 2, 5: 0})], ids=["fp64", "fp64_class", "fp32_mixed_class"])
-def test_ensemble48_batched_equals_single(precision, tv):
+@pytest.mark.parametrize("precision,tv,mode", [(0, {3: 1, 4: 0, 5: 1}, (False, False)),
+                                               (0, {3: 2, 4: 2, 5: 1}, (True, True)),
+                                               (1, {3: 1, 4: 2, 5: 2}, (True, False))],
+                         ids=["fp64", "fp64_persist_conc", "fp32_mixed_persist"])
+def test_ensemble48_batched_equals_single(precision, tv, mode):
     """The 48-member uneven ensemble (8 x 8 x 8 ... 40 x 40 x 16 elements,
     N in 3..5, 23.5 M unique nodes) in FP64 and FP32-mixed: two steps in
-    batched graph launches equal, bit for bit, two steps of each member on
-    its own."""
+    batched graph launches (one workgroup per item, or persistent, with the
+    order groups in step or concurrent) equal, bit for bit, two steps of each
+    member on its own."""
     import torch
     from paper_2504_08157_amd import nhsem
     ctxs, q0s = [], []
@@ -137,7 +146,7 @@ def test_ensemble48_batched_equals_single(precision, tv):
     dt = 0.25
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
-        b = nhsem.Batch(ctxs, steps_per_graph=2, tile_variant=tv, stream=s)
+        b = nhsem.Batch(ctxs, steps_per_graph=2, tile_variant=tv, stream=s, persistent=mode[0], concurrent=mode[1])
         b.nh_batch_step(0.0, dt, 2)
     torch.cuda.synchronize()
     got = [c.nh_get_state() for c in ctxs]
