@@ -24,7 +24,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_STAGE = {1: 40 + 16 + 40, 2: 40 + 40 + 16 + 40, 3: 40 + 40 + 16 + 40}
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "stage_kernel_tc_128x128x20_N4_fp64_hbm_counters.txt")
+COUNTERS = os.path.join(ROOT, "profiles", "stage_kernel_tc_128x128x20_N4_fp64_counters.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2504_08157_amd", "csrc", "nh_kernels.hip")
 
 
@@ -310,14 +310,27 @@ def bench_precision(args):
     states = {}
     for name, prec in (("fp64", nhsem.NH_FP64), ("fp32", nhsem.NH_FP32_MIXED)):
         ctx, q0 = _tc_context(w, prec)
-        ctx.nh_set_tile(0 if args.tile < 0 else args.tile)
+        tune = {}
+        if args.tile < 0:
+            # tile tuner for this precision: a few steps per variant
+            for v in (0, 1, 2):
+                ctx.nh_set_tile(v)
+                ctx.nh_rk_step(0.0, w.dt, 2)
+                a0 = torch.cuda.Event(enable_timing=True); a1 = torch.cuda.Event(enable_timing=True)
+                a0.record(); ctx.nh_rk_step(0.0, w.dt, 10); a1.record()
+                torch.cuda.synchronize()
+                tune[v] = a0.elapsed_time(a1) / 10
+            ctx.nh_set_state(q0)
+        tile = min(tune, key=tune.get) if tune else args.tile
+        ctx.nh_set_tile(tile)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
         ctx.nh_rk_step(0.0, w.dt, args.err_steps)
         e1.record()
         torch.cuda.synchronize()
-        out[name] = {"ms_per_step": e0.elapsed_time(e1) / args.err_steps}
+        out[name] = {"ms_per_step": e0.elapsed_time(e1) / args.err_steps, "tile_variant": tile,
+                     "tile_ms_per_step": {str(k): v for k, v in tune.items()}}
         states[name] = ctx.nh_get_state().cpu().numpy()
         ctx.close()
         del ctx, q0

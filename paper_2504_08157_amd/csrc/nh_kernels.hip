@@ -120,6 +120,10 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile,
     // slot 0 the bottom level, slots 1..N the element's new levels.
     __shared__ double stlev[N1 * 3];
     __shared__ T scarry[6 * NCOL];
+    // FP32 form: the tile's own nodes in FP64 (ring of N+1 levels, as the
+    // planes), kept at staging for the RK combination a q^n + b q^s + c R,
+    // which stays FP64
+    __shared__ double qown[kF64 ? 1 : N1 * 5 * NCOL];
 
     const int bx = tile % p.ntx, by = tile / p.ntx;
     const int x0 = bx * TX, y0 = by * TY;
@@ -222,6 +226,12 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile,
         }
         T(*P)[PS] = pl[k % N1];
         const int idx = sidx[s];
+        if constexpr (!kF64) {
+            if (s < NCOL) {
+                double *Q = qown + (k % N1) * 5 * NCOL + s;
+                Q[0] = v0; Q[NCOL] = v1; Q[2 * NCOL] = v2; Q[3 * NCOL] = v3; Q[4 * NCOL] = v4;
+            }
+        }
         P[0][idx] = T(pp);
         P[1][idx] = T(v1);
         P[2][idx] = T(v2);
@@ -352,9 +362,9 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile,
         if constexpr (kF64) {
             qs[0] = own[5]; qs[1] = own[1]; qs[2] = own[2]; qs[3] = own[3]; qs[4] = own[4];
         } else {
-            const char *qb = (const char *)p.qs + o;
+            const double *Q = qown + (k % N1) * 5 * NCOL + (ty * TX + tx);
 #pragma unroll
-            for (int f = 0; f < 5; ++f) qs[f] = *(const double *)(qb + f * field_bytes);
+            for (int f = 0; f < 5; ++f) qs[f] = Q[f * NCOL];
         }
         T R[5];
         R[0] = XY[0] - dz[5];
