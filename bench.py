@@ -162,6 +162,9 @@ def bench_hevi(args):
                    "columns": res["columns"]},
         "hevi": {"default": d, "mlp": m, "speedup_step": d["ms_per_step"] / m["ms_per_step"],
                  "iteration_ratio": m["iters_per_solve"] / d["iters_per_solve"],
+                 "mlp_pick": res["mlp_pick"], "speedup_step_pick": d["ms_per_step"] / res["mlp_pick"]["ms_per_step"],
+                 "iteration_ratio_pick": res["mlp_pick"]["iters_per_solve"] / d["iters_per_solve"],
+                 "state_rel_diff_stacked_pick": res["state_rel_diff_stacked_pick"],
                  "state_rel_diff_mlp_vs_default": res["state_rel_diff"],
                  "state_rel_diff_stacked": res["state_rel_diff_stacked"],
                  "training": tr},
@@ -171,6 +174,8 @@ def bench_hevi(args):
         out["hevi"]["schur_form"] = {
             "default": ds, "mlp": ms, "speedup_step": ds["ms_per_step"] / ms["ms_per_step"],
             "iteration_ratio": ms["iters_per_solve"] / ds["iters_per_solve"],
+            "mlp_pick": res_s["mlp_pick"], "speedup_step_pick": ds["ms_per_step"] / res_s["mlp_pick"]["ms_per_step"],
+            "iteration_ratio_pick": res_s["mlp_pick"]["iters_per_solve"] / ds["iters_per_solve"],
             "state_rel_diff_stacked": res_s["state_rel_diff_stacked"],
             "speedup_vs_full_form_default": d["ms_per_step"] / ds["ms_per_step"],
             "state_rel_diff_vs_full_form": float(

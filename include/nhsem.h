@@ -287,6 +287,12 @@ typedef struct {
                                  column systems (I - alpha L_v), solved by the
                                  column GMRES(10) to rtol 1e-6 (flexible GMRES:
                                  the preconditioned vectors are kept) */
+    int32_t guess_pick;       /* column solves started from a given guess (dev_x0,
+                                 or the MLP guess of nh_hevi_step), restart 10 forms:
+                                 1 = per column, compare the residual of the guess
+                                 with that of the default start x0 = b and start
+                                 from the smaller (one more operator application
+                                 per column, not counted as an Arnoldi step) */
 } nh_gmres_opts;
 typedef struct {
     int64_t columns;          /* columns per solve */

@@ -505,6 +505,23 @@ __global__ void __launch_bounds__(64) gmres_reg_kernel(HeviParams h, GmresArgs g
 #pragma unroll
             for (int s = 0; s < S; ++s)
                 if (sf[s] < 3) sx[lane + 64 * s] = 0.0;
+        // guess choice: the residual norm of the default start x = b, to be
+        // compared with that of the given guess at the first restart
+        bool choose = g.pick && g.x0 && !conv;
+        double rdef = 0.0;
+        if (choose) {
+            double t[S], y[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) t[s] = sf[s] < 3 ? sb[lane + 64 * s] : 0.0;
+            apply(t, y);
+            double r2 = 0.0;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const double r = sf[s] < 3 ? sb[lane + 64 * s] - (t[s] - g.alpha * y[s]) : 0.0;
+                r2 += r * r;
+            }
+            rdef = sqrt(wave_sum1(r2));
+        }
         for (int rs = 0; rs <= g.max_restarts && !conv; ++rs) {
             double V[M + 1][S];
             {
@@ -520,6 +537,18 @@ __global__ void __launch_bounds__(64) gmres_reg_kernel(HeviParams h, GmresArgs g
 #pragma unroll
             for (int s = 0; s < S; ++s) rn2 += V[0][s] * V[0][s];
             const double rn = sqrt(wave_sum1(rn2));
+            if (choose) {
+                // keep the guess with the smaller residual: start again
+                // from x = b if the given one is worse
+                choose = false;
+                if (rdef < rn) {
+#pragma unroll
+                    for (int s = 0; s < S; ++s)
+                        if (sf[s] < 3) sx[lane + 64 * s] = sb[lane + 64 * s];
+                    --rs;
+                    continue;
+                }
+            }
             if (rn <= tol) { conv = true; break; }
             {
                 const double inv = 1.0 / rn;
@@ -807,6 +836,23 @@ __global__ void __launch_bounds__(64) gmres_schur_kernel(HeviParams h, GmresArgs
 #pragma unroll
             for (int s = 0; s < S; ++s)
                 if (sk[s] > 0) sx[lane + 64 * s] = 0.0;
+        // guess choice (as in the full form), on the reduced system: the
+        // residual of the default start w = b_w
+        bool choose = g.pick && g.x0 && !conv;
+        double rdef = 0.0;
+        if (choose) {
+            double t[S], y[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) t[s] = sk[s] > 0 ? bw[sk[s]] : 0.0;
+            apply(t, y);
+            double r2 = 0.0;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const double r = sk[s] > 0 ? sb[lane + 64 * s] - (t[s] - beta * y[s]) : 0.0;
+                r2 += r * r;
+            }
+            rdef = sqrt(wave_sum1(r2));
+        }
         for (int rs = 0; rs <= g.max_restarts && !conv; ++rs) {
             double V[M + 1][S];
             {
@@ -822,6 +868,16 @@ __global__ void __launch_bounds__(64) gmres_schur_kernel(HeviParams h, GmresArgs
 #pragma unroll
             for (int s = 0; s < S; ++s) rn2 += V[0][s] * V[0][s];
             const double rn = sqrt(wave_sum1(rn2));
+            if (choose) {
+                choose = false;
+                if (rdef < rn) {
+#pragma unroll
+                    for (int s = 0; s < S; ++s)
+                        if (sk[s] > 0) sx[lane + 64 * s] = bw[sk[s]];
+                    --rs;
+                    continue;
+                }
+            }
             if (rn <= tol) { conv = true; break; }
             {
                 const double inv = 1.0 / rn;

@@ -82,6 +82,7 @@ struct GmresArgs {
     int restart, max_restarts;
     int *iters;          // [n_x n_y] Arnoldi steps per column (negative: not converged), or null
     int schur;           // 1: solve the Schur complement in w (restart kGmresRegM only)
+    int pick;            // with x0: per column, start from x0 or from b, whichever has the smaller residual
 };
 
 constexpr int kMaxComb = 6;

@@ -882,6 +882,7 @@ hipError_t run_gmres(nh_ctx *c, double alpha, const double *b, const double *x0,
     GmresArgs g{};
     g.b = b; g.x0 = x0; g.x = x; g.alpha = alpha; g.rtol = o->rtol;
     g.restart = o->restart; g.max_restarts = o->max_restarts; g.iters = iters; g.schur = o->schur;
+    g.pick = o->guess_pick;
     return launch_gmres(hevi_params(c), g, c->stream);
 }
 

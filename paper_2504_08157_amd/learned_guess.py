@@ -153,10 +153,11 @@ def fit(mlp, w_eval, dt, warm, sources, epochs, batch=1024, lr=1e-3, max_per_ste
 
 
 def compare(mlp, w, warm, held, dt, rtol=1e-10, restart=20, schur=False):
-    """From the state after `warm` default steps, run `held` steps twice --
-    default guess and MLP guess -- and report GMRES iterations, step times
-    and the difference of the final states (schur: solve the Schur
-    complement in w)."""
+    """From the state after `warm` default steps, run `held` steps three
+    times -- default guess, MLP guess, and the MLP guess with the per-column
+    choice against the default start (the smaller initial residual) -- and
+    report GMRES iterations, step times and the difference of the final
+    states (schur: solve the Schur complement in w)."""
     import torch
     ctx = hevi_context(w)
     for s in range(warm):
@@ -164,7 +165,7 @@ def compare(mlp, w, warm, held, dt, rtol=1e-10, restart=20, schur=False):
     q0 = ctx.nh_get_state().clone()
     out = {}
     finals = {}
-    for name, g in (("default", None), ("mlp", mlp)):
+    for name, g, pick in (("default", None, False), ("mlp", mlp, False), ("mlp_pick", mlp, True)):
         ctx.nh_set_state(q0)
         torch.cuda.synchronize()
         it, ms = 0, 0.0
@@ -173,7 +174,7 @@ def compare(mlp, w, warm, held, dt, rtol=1e-10, restart=20, schur=False):
             e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
             st = ctx.nh_hevi_step((warm + s) * dt, dt, rtol=rtol, max_restarts=60, restart=restart, guess=g,
-                                  schur=schur)
+                                  schur=schur, pick=pick)
             e1.record()
             torch.cuda.synchronize()
             ms += e0.elapsed_time(e1)
@@ -182,6 +183,8 @@ def compare(mlp, w, warm, held, dt, rtol=1e-10, restart=20, schur=False):
         solves = held * 2 * ctx.nx * ctx.ny
         out[name] = {"iters_per_solve": it / solves, "iters_max": mx, "ms_per_step": ms / held}
         finals[name] = ctx.nh_get_state().cpu().numpy()
+    dp = finals["mlp_pick"] - finals["default"]
+    out["state_rel_diff_stacked_pick"] = float(np.linalg.norm(dp) / np.linalg.norm(finals["default"]))
     d = finals["mlp"] - finals["default"]
     out["state_rel_diff"] = [float(np.linalg.norm(d[f]) / max(np.linalg.norm(finals["default"][f]), 1e-300))
                              for f in range(5)]

@@ -52,7 +52,7 @@ class nh_physics(ctypes.Structure):
 
 class nh_gmres_opts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("max_restarts", ctypes.c_int32), ("rtol", ctypes.c_double),
-                ("schur", ctypes.c_int32), ("precondition", ctypes.c_int32)]
+                ("schur", ctypes.c_int32), ("precondition", ctypes.c_int32), ("guess_pick", ctypes.c_int32)]
 
 
 class nh_solve_stats(ctypes.Structure):
@@ -451,11 +451,11 @@ class Context:
         return out
 
     def nh_column_solve(self, alpha, b, x0=None, out=None, restart=20, max_restarts=10, rtol=1e-10,
-                        iters=None, check=True, schur=False):
+                        iters=None, check=True, schur=False, pick=False):
         import torch
         if out is None:
             out = torch.empty_like(b)
-        opts = nh_gmres_opts(restart, max_restarts, rtol, int(bool(schur)))
+        opts = nh_gmres_opts(restart, max_restarts, rtol, int(bool(schur)), 0, int(bool(pick)))
         st = nh_solve_stats()
         code = self.lib.nh_column_solve(self.h, float(alpha), _tptr(b), _tptr(x0) if x0 is not None else None,
                                         _tptr(out), ctypes.byref(opts), ctypes.byref(st),
@@ -464,8 +464,9 @@ class Context:
             self._c(code)
         return out, st
 
-    def nh_hevi_step(self, t, dt, restart=20, max_restarts=10, rtol=1e-10, guess=None, check=True, schur=False):
-        opts = nh_gmres_opts(restart, max_restarts, rtol, int(bool(schur)))
+    def nh_hevi_step(self, t, dt, restart=20, max_restarts=10, rtol=1e-10, guess=None, check=True, schur=False,
+                     pick=False):
+        opts = nh_gmres_opts(restart, max_restarts, rtol, int(bool(schur)), 0, int(bool(pick)))
         st = nh_solve_stats()
         code = self.lib.nh_hevi_step(self.h, float(t), float(dt), ctypes.byref(opts),
                                      guess.h if guess is not None else None, ctypes.byref(st))

@@ -170,3 +170,38 @@ def test_hevi_step_parity_nz65(oracle_mod, restart, schur):
     for f in range(5):
         err = np.linalg.norm(got[f] - q[f]) / np.linalg.norm(q[f])
         assert err <= 1e-10, (f, err)
+
+
+@pytest.mark.parametrize("schur", [False, True], ids=["full", "schur"])
+def test_guess_pick(oracle_mod, schur):
+    """With the per-column guess choice, a poor guess (the exact solution
+    times 3 plus noise) is replaced by the default start where that has the
+    smaller residual, and the solve still reaches the direct solution; the
+    exact solution as guess is kept (no Arnoldi step)."""
+    ctx, orc, g, o, torch = _pair(oracle_mod, nel=TALL["nz65"], H=20e3)
+    Lm = oracle_mod.column_matrix(orc)
+    nz = orc.nz
+    alpha = 0.3
+    b = _state(o, 31)
+    A = np.eye(3 * nz) - alpha * Lm
+    B = np.concatenate([b[0].reshape(nz, -1), b[3].reshape(nz, -1), b[4].reshape(nz, -1)])
+    X = np.linalg.solve(A, B)
+    bd = torch.from_numpy(_state(g, 31)).cuda()
+    iters = torch.zeros(ctx.nx * ctx.ny, dtype=torch.int32, device="cuda")
+    xd, st_def = ctx.nh_column_solve(alpha, bd, restart=10, max_restarts=60, rtol=1e-12, iters=iters, schur=schur)
+    rng = np.random.default_rng(3)
+    Xs = X.reshape(3, nz, -1)
+    bad = torch.from_numpy((3.0 * Xs + rng.normal(size=Xs.shape) * np.abs(Xs).max(axis=(1, 2), keepdims=True))
+                           .reshape(3, -1)).cuda()
+    x, st = ctx.nh_column_solve(alpha, bd, x0=bad, restart=10, max_restarts=60, rtol=1e-12, iters=iters,
+                                schur=schur, pick=True)
+    x = x.cpu().numpy()
+    assert st.not_converged == 0
+    # the poor guess is dropped: the same Arnoldi work as the default start
+    assert st.iters_total == st_def.iters_total, (st.iters_total, st_def.iters_total)
+    for f, blk in ((0, X[:nz]), (3, X[nz:2 * nz]), (4, X[2 * nz:])):
+        ref = blk.reshape(x[f].shape)
+        assert np.linalg.norm(x[f] - ref) <= 1e-9 * np.linalg.norm(ref)
+    good = torch.from_numpy(np.ascontiguousarray(Xs.reshape(3, -1))).cuda()
+    _, st0 = ctx.nh_column_solve(alpha, bd, x0=good, restart=10, rtol=1e-9, iters=iters, schur=schur, pick=True)
+    assert st0.iters_total == 0
