@@ -358,8 +358,8 @@ nh_status nh_hevi_last_solves(nh_ctx *ctx, const double **R2, const double **X2,
 
 /* Device workspace of nh_global_solve and nh_imex3d_step for a restart
    length (restart + 1 Krylov vectors, restart preconditioned vectors, one
-   scratch vector and, for the step, eight state-sized arrays; 5U doubles
-   each). */
+   scratch vector and, for the step, eight state-sized arrays, 5U doubles
+   each; plus the block partial sums and the solver's device state). */
 nh_status nh_imex3d_workspace_bytes(const nh_ctx *ctx, int32_t restart, size_t *bytes);
 
 /* dev_y = L dev_x on device [5][U] arrays (distinct; NH_EINVAL otherwise or
@@ -367,8 +367,12 @@ nh_status nh_imex3d_workspace_bytes(const nh_ctx *ctx, int32_t restart, size_t *
 nh_status nh_l3_apply(nh_ctx *ctx, const double *dev_x, double *dev_y);
 
 /* Solve (I - alpha L) dev_x = dev_b (alpha >= 0) from dev_x0 (NULL: dev_b);
-   dev_b and dev_x distinct.  Synchronises the stream once per Arnoldi step
-   (the small Hessenberg problem is solved on the host).  stats (optional):
+   dev_b and dev_x distinct.  The Hessenberg problem and the convergence
+   test run on the device; the host queues each Arnoldi step while the one
+   before runs, waits on an event of the stream every step and synchronises
+   the stream once per solve (the call returns with the solve complete).  The
+   first 3D-IMEX call on a context creates a small host-mapped status block
+   and two events, released by nh_destroy.  stats (optional):
    columns = 1, solves = 1, iters = Arnoldi steps.  NH_ENOCONV when the
    residual test fails after max_restarts restarts (dev_x holds the last
    iterate); NH_EINVAL for bad options (restart outside 1..32, rtol outside
@@ -500,7 +504,8 @@ nh_status nh_mlp_destroy(nh_mlp *m);
 /* Text of the last error (always NUL-terminated when n > 0). */
 nh_status nh_last_error(const nh_ctx *ctx, char *buf, size_t n);
 
-/* Destroy the context (host memory only; the workspace stays the caller's). */
+/* Destroy the context (host memory, and the 3D-IMEX status block and events
+   if a global solve made them; the workspace stays the caller's). */
 nh_status nh_destroy(nh_ctx *ctx);
 
 #ifdef __cplusplus

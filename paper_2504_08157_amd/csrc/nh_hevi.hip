@@ -38,8 +38,9 @@ namespace nh {
 // the (zero) u and v rows are not written.
 template <int N>
 __global__ void __launch_bounds__(256) lv_apply_kernel(HeviParams h, const double *__restrict__ x,
-                                                       double *__restrict__ y, bool uv)
+                                                       double *__restrict__ y, bool uv, const int *gate)
 {
+    if (gate && *gate == 0) return;
     constexpr int NC = 2 * N + 1;
     const long nxy = (long)h.nx * h.ny;
     const long col = blockIdx.x * 256L + threadIdx.x;
@@ -143,6 +144,7 @@ __device__ void column_apply(const HeviParams &h, double alpha, const double *x,
 
 __global__ void __launch_bounds__(64) gmres_column_kernel(HeviParams h, GmresArgs g)
 {
+    if (g.gate && *g.gate == 0) return;
     extern __shared__ double smem[];
     const int nz = h.nz, NU = 3 * nz, m = g.restart, lane = threadIdx.x;
     const int NC = 2 * h.N + 1;
@@ -413,6 +415,7 @@ __device__ __forceinline__ void wave_sync()
 template <int M, int S>
 __global__ void __launch_bounds__(64) gmres_reg_kernel(HeviParams h, GmresArgs g)
 {
+    if (g.gate && *g.gate == 0) return;
     extern __shared__ double smem[];
     const int nz = h.nz, NU = 3 * nz, N = h.N, NC = 2 * N + 1, lane = threadIdx.x;
     const int NP = nz + 2 * N;            // padded length of the L_v intermediates
@@ -715,6 +718,7 @@ __global__ void __launch_bounds__(64) gmres_reg_kernel(HeviParams h, GmresArgs g
 template <int M, int S>
 __global__ void __launch_bounds__(64) gmres_schur_kernel(HeviParams h, GmresArgs g)
 {
+    if (g.gate && *g.gate == 0) return;
     extern __shared__ double smem[];
     const int nz = h.nz, N = h.N, NC = 2 * N + 1, lane = threadIdx.x;
     const int NP = nz + 2 * N;
@@ -1039,17 +1043,18 @@ size_t gmres_lds_bytes(int nz, int N, int restart)
     return n * sizeof(double);
 }
 
-hipError_t launch_lv_apply(const HeviParams &h, const double *x, double *y, hipStream_t s, bool uv)
+hipError_t launch_lv_apply(const HeviParams &h, const double *x, double *y, hipStream_t s, bool uv,
+                           const int *gate)
 {
     const long nxy = (long)h.nx * h.ny;
     const dim3 grid((unsigned)((nxy + 255) / 256)), blk(256);
     switch (h.N) {
-    case 1: hipLaunchKernelGGL(lv_apply_kernel<1>, grid, blk, 0, s, h, x, y, uv); break;
-    case 2: hipLaunchKernelGGL(lv_apply_kernel<2>, grid, blk, 0, s, h, x, y, uv); break;
-    case 3: hipLaunchKernelGGL(lv_apply_kernel<3>, grid, blk, 0, s, h, x, y, uv); break;
-    case 4: hipLaunchKernelGGL(lv_apply_kernel<4>, grid, blk, 0, s, h, x, y, uv); break;
-    case 5: hipLaunchKernelGGL(lv_apply_kernel<5>, grid, blk, 0, s, h, x, y, uv); break;
-    case 6: hipLaunchKernelGGL(lv_apply_kernel<6>, grid, blk, 0, s, h, x, y, uv); break;
+    case 1: hipLaunchKernelGGL(lv_apply_kernel<1>, grid, blk, 0, s, h, x, y, uv, gate); break;
+    case 2: hipLaunchKernelGGL(lv_apply_kernel<2>, grid, blk, 0, s, h, x, y, uv, gate); break;
+    case 3: hipLaunchKernelGGL(lv_apply_kernel<3>, grid, blk, 0, s, h, x, y, uv, gate); break;
+    case 4: hipLaunchKernelGGL(lv_apply_kernel<4>, grid, blk, 0, s, h, x, y, uv, gate); break;
+    case 5: hipLaunchKernelGGL(lv_apply_kernel<5>, grid, blk, 0, s, h, x, y, uv, gate); break;
+    case 6: hipLaunchKernelGGL(lv_apply_kernel<6>, grid, blk, 0, s, h, x, y, uv, gate); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -13,9 +13,9 @@
 // Each stage system (I - a L) x = b is one global system in 5U unknowns,
 // solved by restarted GMRES with classical Gram-Schmidt (a second pass when
 // the kept norm falls below 1e-2 of the vector's), its dot products reduced
-// in a fixed order on the device and its small Hessenberg problem on the
-// host; optionally right-preconditioned by the column systems of the 1D
-// split (flexible GMRES, since those are solved iteratively).
+// in a fixed order and its small Hessenberg problem solved on the device;
+// optionally right-preconditioned by the column systems of the 1D split
+// (flexible GMRES, since those are solved iteratively).
 #include "nh_internal.h"
 
 #include <cmath>
@@ -54,8 +54,9 @@ __device__ __forceinline__ void l3_unrolled(F &&f)
 template <int N>
 __global__ void __launch_bounds__(kL3TX * kL3TY) l3_tile_kernel(L3Params h, const double *__restrict__ x,
                                                                 const double *lv, double *out, double a, double c,
-                                                                const double *__restrict__ lev)
+                                                                const double *__restrict__ lev, const int *gate)
 {
+    if (gate && *gate == 0) return;
     constexpr int NC = 2 * N + 1, PX = kL3TX + 2 * N, PY = kL3TY + 2 * N, PS = PX * PY;
     constexpr int NT = kL3TX * kL3TY, NS = (PS + NT - 1) / NT, P = kL3P;
     __shared__ double tile[2][3][PS];   // u, v, p'_L
@@ -166,28 +167,33 @@ __global__ void __launch_bounds__(kL3TX * kL3TY) l3_tile_kernel(L3Params h, cons
     }
 }
 
-hipError_t launch_l3(const L3Params &h, const double *x, double *out, double a, double c, hipStream_t s)
+hipError_t launch_l3(const L3Params &h, const double *x, double *out, double a, double c, hipStream_t s,
+                     const int *gate)
 {
-    hipError_t e = launch_lv_apply(h.hv, x, out, s, true);
+    hipError_t e = launch_lv_apply(h.hv, x, out, s, true, gate);
     if (e != hipSuccess) return e;
     const int ntx = (h.nx + kL3TX - 1) / kL3TX, nty = (h.ny + kL3TY - 1) / kL3TY;
     const int nkc = (h.nz + kL3KZ - 1) / kL3KZ;
     const dim3 grid((unsigned)(ntx * nty * nkc)), blk(kL3TX * kL3TY);
     switch (h.N) {
-    case 2: hipLaunchKernelGGL(l3_tile_kernel<2>, grid, blk, 0, s, h, x, (const double *)out, out, a, c, h.lev); break;
-    case 3: hipLaunchKernelGGL(l3_tile_kernel<3>, grid, blk, 0, s, h, x, (const double *)out, out, a, c, h.lev); break;
-    case 4: hipLaunchKernelGGL(l3_tile_kernel<4>, grid, blk, 0, s, h, x, (const double *)out, out, a, c, h.lev); break;
-    case 5: hipLaunchKernelGGL(l3_tile_kernel<5>, grid, blk, 0, s, h, x, (const double *)out, out, a, c, h.lev); break;
-    case 6: hipLaunchKernelGGL(l3_tile_kernel<6>, grid, blk, 0, s, h, x, (const double *)out, out, a, c, h.lev); break;
+    case 2: hipLaunchKernelGGL(l3_tile_kernel<2>, grid, blk, 0, s, h, x, (const double *)out, out, a, c, h.lev, gate); break;
+    case 3: hipLaunchKernelGGL(l3_tile_kernel<3>, grid, blk, 0, s, h, x, (const double *)out, out, a, c, h.lev, gate); break;
+    case 4: hipLaunchKernelGGL(l3_tile_kernel<4>, grid, blk, 0, s, h, x, (const double *)out, out, a, c, h.lev, gate); break;
+    case 5: hipLaunchKernelGGL(l3_tile_kernel<5>, grid, blk, 0, s, h, x, (const double *)out, out, a, c, h.lev, gate); break;
+    case 6: hipLaunchKernelGGL(l3_tile_kernel<6>, grid, blk, 0, s, h, x, (const double *)out, out, a, c, h.lev, gate); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-// ---- Krylov kernels on n-vectors.  Partial sums per block, then one block
-// sums the partials of each quantity in block order: the same result on
-// every call.
-constexpr int kKryBlocks = 1024, kKryThreads = 256, kKryMaxV = 34;
+
+// ---- Krylov kernels on n-vectors.  Dot products are summed per block into
+// quantity-major partials, then by one workgroup in a fixed order: the same
+// result on every call.  The Hessenberg problem, the rotations and the
+// convergence test live on the device (G3State), so the host queues the
+// launches of a cycle ahead of their results; launches past the end of the
+// process see their gate flag at 0 and return at once.
+constexpr int kKryBlocks = 1024, kKryThreads = 256, kKryMaxV = 34, kKryCtl = 1024;
 
 __device__ __forceinline__ double kry_wave_sum(double v)
 {
@@ -196,74 +202,89 @@ __device__ __forceinline__ double kry_wave_sum(double v)
     return v;
 }
 
-// part[b][j] = sum over block b's elements of V_j . w (j < nv), and
-// part[b][nv] = w . w
-__global__ void __launch_bounds__(kKryThreads) kry_dots_kernel(const double *__restrict__ V, long stride, int nv,
+// part[j][b] = sum over block b's elements of V_j . w (j < NV), and
+// part[NV][b] = w . w.  All loads of an iteration are unconditional (the
+// index of a lane past the end is clamped and its weight zeroed after the
+// loads), so they are in flight together; for short bases each lane takes
+// UF elements a grid stride apart, so that every CU still has enough bytes
+// in flight to run at memory speed.
+template <int NV>
+__global__ void __launch_bounds__(kKryThreads) kry_dots_kernel(const double *__restrict__ V, long stride,
                                                                const double *__restrict__ w, long n,
-                                                               double *__restrict__ part)
+                                                               double *__restrict__ part, const int *gate)
 {
-    __shared__ double red[kKryThreads / 64][kKryMaxV + 1];
-    double acc[kKryMaxV + 1];
+    constexpr int UF = NV <= 1 ? 4 : NV <= 3 ? 2 : 1;
+    if (gate && *gate == 0) return;
+    __shared__ double red[kKryThreads / 64][NV + 1];
+    double acc[NV + 1];
 #pragma unroll
-    for (int j = 0; j <= kKryMaxV; ++j) acc[j] = 0.0;
-    for (long i = blockIdx.x * (long)kKryThreads + threadIdx.x; i < n; i += (long)gridDim.x * kKryThreads) {
-        const double wi = w[i];
+    for (int j = 0; j <= NV; ++j) acc[j] = 0.0;
+    const long S = (long)gridDim.x * kKryThreads;
+    for (long i0 = blockIdx.x * (long)kKryThreads + threadIdx.x; i0 < n; i0 += S * UF) {
+        long ii[UF];
+        double wi[UF], vv[NV > 0 ? NV : 1][UF];
 #pragma unroll
-        for (int j = 0; j < kKryMaxV; ++j)
-            if (j < nv) acc[j] += V[j * stride + i] * wi;
-        acc[kKryMaxV] += wi * wi;
+        for (int u = 0; u < UF; ++u) ii[u] = i0 + u * S < n ? i0 + u * S : n - 1;
+#pragma unroll
+        for (int u = 0; u < UF; ++u) wi[u] = w[ii[u]];
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+#pragma unroll
+            for (int u = 0; u < UF; ++u) vv[j][u] = V[j * stride + ii[u]];
+#pragma unroll
+        for (int u = 1; u < UF; ++u)
+            if (i0 + u * S >= n) wi[u] = 0.0;
+#pragma unroll
+        for (int u = 0; u < UF; ++u) {
+            acc[NV] += wi[u] * wi[u];
+#pragma unroll
+            for (int j = 0; j < NV; ++j) acc[j] += vv[j][u] * wi[u];
+        }
     }
     const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
 #pragma unroll
-    for (int j = 0; j <= kKryMaxV; ++j) {
-        if (j < nv || j == kKryMaxV) {
-            const double s = kry_wave_sum(acc[j]);
-            if (lane == 0) red[wv][j] = s;
-        }
+    for (int j = 0; j <= NV; ++j) {
+        const double s = kry_wave_sum(acc[j]);
+        if (lane == 0) red[wv][j] = s;
     }
     __syncthreads();
-    for (int j = threadIdx.x; j <= nv; j += kKryThreads) {
-        const int jj = j < nv ? j : kKryMaxV;
+    for (int j = threadIdx.x; j <= NV; j += kKryThreads) {
         double s = 0.0;
-        for (int q = 0; q < kKryThreads / 64; ++q) s += red[q][jj];
-        part[(long)blockIdx.x * (kKryMaxV + 1) + j] = s;
+        for (int q = 0; q < kKryThreads / 64; ++q) s += red[q][j];
+        part[(long)j * kKryBlocks + blockIdx.x] = s;
     }
 }
 
-// out[j] = sum over blocks of part[b][j]: workgroup j sums quantity j, each
-// thread a fixed strided subset of the blocks, then a fixed tree
-__global__ void __launch_bounds__(kKryThreads) kry_final_kernel(const double *__restrict__ part, int nb,
-                                                                double *__restrict__ out)
+template <int NV>
+static void launch_dots(int nv, const double *V, long n, const double *x, double *part, const int *gate,
+                        hipStream_t s)
 {
-    __shared__ double red[kKryThreads];
-    const int j = blockIdx.x;
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += kKryThreads) s += part[(long)b * (kKryMaxV + 1) + j];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int h = kKryThreads / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-        __syncthreads();
+    if constexpr (NV <= kG3MaxRestart) {
+        if (nv == NV)
+            hipLaunchKernelGGL(kry_dots_kernel<NV>, dim3(kKryBlocks), dim3(kKryThreads), 0, s, V, n, x, n, part,
+                               gate);
+        else
+            launch_dots<NV + 1>(nv, V, n, x, part, gate, s);
     }
-    if (threadIdx.x == 0) out[j] = red[0];
 }
 
-struct KryCoef {
-    double c[kKryMaxV];
-};
-
-// y = s (w - sum_j c_j V_j) (j < nv); with norm != 0 also part[b][0] =
-// block sums of the result squared (before the scale s)
+// y = s (w - sum_j c_j V_j) for j < nv, nv = *nvp when given, s = *sc when
+// given (else 1), coefficients c in device memory; with norm also part[0][b]
+// = block sums of (w - sum_j c_j V_j)^2.  y may alias w.
 __global__ void __launch_bounds__(kKryThreads) kry_axpy_kernel(const double *__restrict__ V, long stride, int nv,
-                                                               KryCoef cf, const double *w, double *y, long n,
-                                                               double s, int norm, double *__restrict__ part)
+                                                               const int *nvp, const double *cf, const double *w,
+                                                               double *y, long n, const double *sc, int norm,
+                                                               double *__restrict__ part, const int *gate)
 {
+    if (gate && *gate == 0) return;
     __shared__ double red[kKryThreads / 64];
+    const int nvv = nvp ? *nvp : nv;
+    const double s = sc ? *sc : 1.0;
     double acc = 0.0;
     for (long i = blockIdx.x * (long)kKryThreads + threadIdx.x; i < n; i += (long)gridDim.x * kKryThreads) {
         double v = w[i];
 #pragma unroll 4
-        for (int j = 0; j < nv; ++j) v -= cf.c[j] * V[j * stride + i];
+        for (int j = 0; j < nvv; ++j) v -= cf[j] * V[j * stride + i];
         acc += v * v;
         y[i] = s * v;
     }
@@ -274,44 +295,180 @@ __global__ void __launch_bounds__(kKryThreads) kry_axpy_kernel(const double *__r
     if (threadIdx.x == 0) {
         double r = 0.0;
         for (int q = 0; q < kKryThreads / 64; ++q) r += red[q];
-        part[(long)blockIdx.x * (kKryMaxV + 1)] = r;
+        part[blockIdx.x] = r;
     }
+}
+
+// The nq quantities of the block partials summed into out (LDS): wave v
+// sums quantities v, v + 16, ..., each lane a fixed strided subset of the
+// blocks, then a fixed butterfly.  Ends with a barrier.
+__device__ void kry_reduce(const double *__restrict__ part, int nq, double *out)
+{
+    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+    for (int q = wv; q < nq; q += kKryCtl / 64) {
+        double s = 0.0;
+#pragma unroll
+        for (int b = 0; b < kKryBlocks / 64; ++b) s += part[(long)q * kKryBlocks + b * 64 + lane];
+        s = kry_wave_sum(s);
+        if (lane == 0) out[q] = s;
+    }
+    __syncthreads();
+}
+
+__device__ void g3_publish(const G3State *st, G3Status *hs)
+{
+    volatile G3Status *v = hs;
+    v->go = st->go;
+    v->open = st->open;
+    v->iters = st->iters;
+    v->relres = st->relres;
+    __threadfence_system();
+}
+
+// Start of a solve: ||b|| from the partials of b . b
+__global__ void __launch_bounds__(kKryCtl) g3_begin_kernel(G3State *st, const double *__restrict__ part,
+                                                           G3Status *hs)
+{
+    __shared__ double red[1];
+    kry_reduce(part, 1, red);
+    if (threadIdx.x != 0) return;
+    const double bn = sqrt(red[0]);
+    st->bn = bn;
+    st->bzero = bn == 0.0;
+    st->open = bn > 0.0;
+    st->go = 0;
+    st->pass2 = 0;
+    st->ncols = 0;
+    st->iters = 0;
+    st->relres = 0.0;
+    st->one = 1.0;
+    st->zero = 0.0;
+    g3_publish(st, hs);
+}
+
+// Start of a cycle: beta = ||r|| from the partials of the residual; the solve
+// ends when beta <= rtol ||b||, else (unless this is the final check) the
+// Arnoldi process starts from V_0 = r / beta.
+__global__ void __launch_bounds__(kKryCtl) g3_cycle_kernel(G3State *st, const double *__restrict__ part,
+                                                           double rtol, int final, G3Status *hs)
+{
+    if (st->open == 0) return;
+    __shared__ double red[1];
+    kry_reduce(part, 1, red);
+    if (threadIdx.x != 0) return;
+    const double beta = sqrt(red[0]), bn = st->bn;
+    st->relres = beta / bn;
+    st->ncols = 0;
+    st->pass2 = 0;
+    if (beta <= rtol * bn) {
+        st->open = 0;
+        st->go = 0;
+    } else {
+        st->go = final ? 0 : 1;
+        st->scale = 1.0 / beta;
+        st->gv[0] = beta;
+        for (int i = 1; i <= kG3MaxRestart; ++i) st->gv[i] = 0.0;
+    }
+    g3_publish(st, hs);
+}
+
+// Column j of the Hessenberg matrix from the partials of V_i . w (i <= j) and
+// w . w (pass 1) or of the second pass.  The norm of the kept part is
+// ||w||^2 - sum h_i^2 when that keeps at least 1e-4 of ||w||^2 (the vector
+// is then written normalised by the combination that orthogonalises it);
+// otherwise a second pass orthogonalises the kept part again and its norm
+// comes from that pass.  Then the earlier rotations, a new one, the rotated
+// residual and the convergence test.
+__global__ void __launch_bounds__(kKryCtl) g3_column_kernel(G3State *st, const double *__restrict__ part, int j,
+                                                            int m, double rtol, int pass, G3Status *hs)
+{
+    if (pass == 1 ? st->go == 0 : st->pass2 == 0) return;
+    __shared__ double red[kKryMaxV + 1];
+    kry_reduce(part, j + 2, red);
+    if (threadIdx.x != 0) return;
+    double h2 = 0.0;
+    for (int i = 0; i <= j; ++i) h2 += red[i] * red[i];
+    const double w2 = red[j + 1];
+    double k2 = w2 - h2;
+    if (pass == 1) {
+        for (int i = 0; i <= j; ++i) st->coef[i] = red[i];
+        if (!(k2 >= 1e-4 * w2)) {   // second pass
+            for (int i = 0; i <= j; ++i) st->hc[i] = red[i];
+            st->pass2 = 1;
+            st->scale = 1.0;
+            return;
+        }
+        for (int i = 0; i <= j; ++i) st->hc[i] = red[i];
+        st->pass2 = 0;
+    } else {
+        for (int i = 0; i <= j; ++i) {
+            st->coef[i] = red[i];
+            st->hc[i] += red[i];
+        }
+    }
+    const double hn = k2 > 0.0 ? sqrt(k2) : 0.0;
+    st->scale = hn > 0.0 ? 1.0 / hn : 0.0;
+    double *H = st->H;
+    constexpr int R = kG3MaxRestart;
+    for (int i = 0; i <= j; ++i) H[i * R + j] = st->hc[i];
+    H[(j + 1) * R + j] = hn;
+    for (int i = 0; i < j; ++i) {
+        const double a0 = H[i * R + j], a1 = H[(i + 1) * R + j];
+        H[i * R + j] = st->cs[i] * a0 + st->sn[i] * a1;
+        H[(i + 1) * R + j] = -st->sn[i] * a0 + st->cs[i] * a1;
+    }
+    const double a0 = H[j * R + j], a1 = H[(j + 1) * R + j];
+    const double rr = hypot(a0, a1);
+    st->cs[j] = rr > 0.0 ? a0 / rr : 1.0;
+    st->sn[j] = rr > 0.0 ? a1 / rr : 0.0;
+    H[j * R + j] = rr;
+    H[(j + 1) * R + j] = 0.0;
+    st->gv[j + 1] = -st->sn[j] * st->gv[j];
+    st->gv[j] = st->cs[j] * st->gv[j];
+    st->iters += 1;
+    st->ncols = j + 1;
+    // estimate met (the next cycle checks the true residual), breakdown or
+    // the restart length reached
+    if (fabs(st->gv[j + 1]) <= rtol * st->bn || hn == 0.0 || j + 1 == m) {
+        st->go = 0;
+        st->pass2 = 0;
+    }
+    g3_publish(st, hs);
+}
+
+// End of a cycle: H y = g over the cycle's columns (upper triangular), and
+// the coefficients -y of the update x += Z y (Z = V unpreconditioned)
+__global__ void __launch_bounds__(64) g3_end_kernel(G3State *st)
+{
+    const int nc = st->ncols;
+    if (nc == 0 || threadIdx.x != 0) return;
+    constexpr int R = kG3MaxRestart;
+    double y[kG3MaxRestart];
+    for (int i = nc - 1; i >= 0; --i) {
+        double v = st->gv[i];
+        for (int l = i + 1; l < nc; ++l) v -= st->H[i * R + l] * y[l];
+        y[i] = v / st->H[i * R + i];
+    }
+    for (int i = 0; i < nc; ++i) st->coef[i] = -y[i];
 }
 
 namespace {
 
 struct Kry {
-    const L3Params &h;
     const G3Work &w;
     hipStream_t s;
     long n;
 
-    // host copies of nv + 1 reduced quantities
-    hipError_t fetch(int nv, double *host)
+    void dots(const double *V, int nv, const double *x, const int *gate)
     {
-        hipLaunchKernelGGL(kry_final_kernel, dim3(nv + 1), dim3(kKryThreads), 0, s, w.part, kKryBlocks, w.red);
-        hipError_t e = hipMemcpyAsync(host, w.red, sizeof(double) * (nv + 1), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        return e;
+        launch_dots<0>(nv, V, n, x, w.part, gate, s);
     }
-    hipError_t dots(const double *V, int nv, const double *x, double *host)
+    // y = sc (x - sum_j cf_j V_j)
+    void axpy(const double *V, int nv, const int *nvp, const double *cf, const double *x, double *y,
+              const double *sc, bool norm, const int *gate)
     {
-        hipLaunchKernelGGL(kry_dots_kernel, dim3(kKryBlocks), dim3(kKryThreads), 0, s, V, n, nv, x, n, w.part);
-        return fetch(nv, host);
-    }
-    // y = sc (x - sum c_j V_j); returns ||x - sum c_j V_j||^2 when norm
-    hipError_t axpy(const double *V, int nv, const double *c, const double *x, double *y, double sc, bool norm,
-                    double *n2)
-    {
-        KryCoef k{};
-        for (int j = 0; j < nv; ++j) k.c[j] = c[j];
-        hipLaunchKernelGGL(kry_axpy_kernel, dim3(kKryBlocks), dim3(kKryThreads), 0, s, V, n, nv, k, x, y, n, sc,
-                           norm ? 1 : 0, w.part);
-        if (!norm) return hipGetLastError();
-        double h2[2];
-        hipError_t e = fetch(0, h2);
-        *n2 = h2[0];
-        return e;
+        hipLaunchKernelGGL(kry_axpy_kernel, dim3(kKryBlocks), dim3(kKryThreads), 0, s, V, n, nv, nvp, cf, x, y, n, sc,
+                           norm ? 1 : 0, w.part, gate);
     }
 };
 
@@ -319,115 +476,88 @@ struct Kry {
 
 // z = (I - alpha L_v)^-1 v column by column (column GMRES(10) to rtol 1e-6;
 // the Schur form where the column is short enough); u, v rows are copied
-static hipError_t column_precond(const L3Params &h, double alpha, const double *v, double *z, hipStream_t s)
+static hipError_t column_precond(const L3Params &h, double alpha, const double *v, double *z, const int *gate,
+                                 hipStream_t s)
 {
     GmresArgs g{};
     g.b = v; g.x0 = nullptr; g.x = z; g.alpha = alpha; g.rtol = 1e-6;
     g.restart = kGmresRegM; g.max_restarts = 10; g.iters = nullptr;
     g.schur = h.nz - 2 <= 64 * kGmresSchurSlots ? 1 : 0;
+    g.gate = gate;
     return launch_gmres(h.hv, g, s);
 }
 
+// The host queues one Arnoldi step while the previous one runs: before it
+// queues step j it waits for the event after step j - 2 (the cycle start for
+// j = 1) and reads the status the kernels wrote, so at most one step is
+// queued past the end of the process, and that one does nothing.  One
+// stream synchronisation per solve reads the result.
 hipError_t gmres3d(const L3Params &h, const G3Work &w, double alpha, const double *b, const double *x0, double *x,
                    int m, int max_restarts, double rtol, bool precond, hipStream_t s, int *iters, double *relres)
 {
     const long n = (long)kNF * h.nx * h.ny * h.nz;
-    Kry k{h, w, s, n};
+    Kry k{w, s, n};
     hipError_t e;
+    G3State *st = w.state;
     double *V = w.V;   // (m + 1) vectors of n
-    double tmp[kKryMaxV + 1];
-    // ||b||
-    if ((e = k.dots(V, 0, b, tmp)) != hipSuccess) return e;
-    const double bn = std::sqrt(tmp[0]);
     *iters = 0;
     *relres = 0.0;
-    if (x0 != x) {
-        e = hipMemcpyAsync(x, x0 ? x0 : b, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) return e;
-    }
-    if (bn == 0.0) {
-        const double z = 0.0;
-        return k.axpy(V, 0, &z, x, x, 0.0, false, nullptr);   // x = 0
-    }
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
-    for (int cyc = 0; cyc <= max_restarts; ++cyc) {
-        // r = b - (x - alpha L x) into V_0
-        if ((e = launch_l3(h, x, w.t, 1.0, -alpha, s)) != hipSuccess) return e;
-        const double one = 1.0;
-        double r2 = 0.0;
-        if ((e = k.axpy(w.t, 1, &one, b, V, 1.0, true, &r2)) != hipSuccess) return e;
-        const double beta = std::sqrt(r2);
-        *relres = beta / bn;
-        if (beta <= rtol * bn) return hipSuccess;
-        if ((e = k.axpy(V, 0, &one, V, V, 1.0 / beta, false, nullptr)) != hipSuccess) return e;
-        std::fill(g.begin(), g.end(), 0.0);
-        g[0] = beta;
-        int j = 0;
-        for (; j < m; ++j) {
+    // ||b||, x = x0 (or b); x = 0 when b = 0
+    k.dots(V, 0, b, nullptr);
+    hipLaunchKernelGGL(g3_begin_kernel, dim3(1), dim3(kKryCtl), 0, s, st, (const double *)w.part, w.status_dev);
+    if (x0 != x) k.axpy(V, 0, nullptr, nullptr, x0 ? x0 : b, x, nullptr, false, nullptr);
+    k.axpy(V, 0, nullptr, nullptr, x, x, &st->zero, false, &st->bzero);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    auto mark = [&](int i) { return hipEventRecord(w.ev[i & 1], s); };
+    for (int cyc = 0; cyc <= max_restarts + 1; ++cyc) {
+        const bool final = cyc == max_restarts + 1;
+        // r = b - (x - alpha L x) into V_0, ||r||, then V_0 = r / ||r||
+        if ((e = launch_l3(h, x, w.t, 1.0, -alpha, s, &st->open)) != hipSuccess) return e;
+        k.axpy(w.t, 1, nullptr, &st->one, b, V, nullptr, true, &st->open);
+        hipLaunchKernelGGL(g3_cycle_kernel, dim3(1), dim3(kKryCtl), 0, s, st, (const double *)w.part, rtol,
+                           final ? 1 : 0, w.status_dev);
+        if (final) break;
+        k.axpy(V, 0, nullptr, nullptr, V, V, &st->scale, false, &st->go);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = mark(0)) != hipSuccess) return e;
+        bool waited = false;
+        for (int j = 0; j < m; ++j) {
+            if (j >= 1) {
+                if ((e = hipEventSynchronize(w.ev[(j - 1) & 1])) != hipSuccess) return e;
+                waited = true;
+                if (w.status->go == 0) break;
+            }
             double *vj = V + (long)j * n, *vn = V + (long)(j + 1) * n;
             // flexible GMRES: z_j = M^-1 v_j kept, the new direction is A z_j
             const double *zj = vj;
             if (precond) {
                 double *zz = w.Z + (long)j * n;
-                if ((e = column_precond(h, alpha, vj, zz, s)) != hipSuccess) return e;
+                if ((e = column_precond(h, alpha, vj, zz, &st->go, s)) != hipSuccess) return e;
                 zj = zz;
             }
-            if ((e = launch_l3(h, zj, vn, 1.0, -alpha, s)) != hipSuccess) return e;
-            // classical Gram-Schmidt, a second pass when the kept norm is small
-            double hc[kKryMaxV + 1], h2[kKryMaxV + 1];
-            if ((e = k.dots(V, j + 1, vn, hc)) != hipSuccess) return e;
-            const double w2 = hc[j + 1];
-            double k2 = 0.0;
-            if ((e = k.axpy(V, j + 1, hc, vn, vn, 1.0, true, &k2)) != hipSuccess) return e;
-            if (k2 < 1e-4 * w2) {
-                if ((e = k.dots(V, j + 1, vn, h2)) != hipSuccess) return e;
-                for (int i = 0; i <= j; ++i) hc[i] += h2[i];
-                if ((e = k.axpy(V, j + 1, h2, vn, vn, 1.0, true, &k2)) != hipSuccess) return e;
-            }
-            const double hn = std::sqrt(k2);
-            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hc[i];
-            H[(size_t)(j + 1) * m + j] = hn;
-            if (hn > 0.0) {
-                const double sc = 1.0 / hn;
-                const double z = 0.0;
-                if ((e = k.axpy(V, 0, &z, vn, vn, sc, false, nullptr)) != hipSuccess) return e;
-            }
-            // Givens rotations
-            for (int i = 0; i < j; ++i) {
-                const double a0 = H[(size_t)i * m + j], a1 = H[(size_t)(i + 1) * m + j];
-                H[(size_t)i * m + j] = cs[i] * a0 + sn[i] * a1;
-                H[(size_t)(i + 1) * m + j] = -sn[i] * a0 + cs[i] * a1;
-            }
-            const double a0 = H[(size_t)j * m + j], a1 = H[(size_t)(j + 1) * m + j];
-            const double rr = std::hypot(a0, a1);
-            cs[j] = rr > 0.0 ? a0 / rr : 1.0;
-            sn[j] = rr > 0.0 ? a1 / rr : 0.0;
-            H[(size_t)j * m + j] = rr;
-            H[(size_t)(j + 1) * m + j] = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
-            ++*iters;
-            if (std::fabs(g[j + 1]) <= rtol * bn || hn == 0.0) {   // estimate met (the next cycle checks the true residual)
-                ++j;
-                break;
-            }
+            if ((e = launch_l3(h, zj, vn, 1.0, -alpha, s, &st->go)) != hipSuccess) return e;
+            // classical Gram-Schmidt, the second pass gated on the first's verdict
+            k.dots(V, j + 1, vn, &st->go);
+            hipLaunchKernelGGL(g3_column_kernel, dim3(1), dim3(kKryCtl), 0, s, st, (const double *)w.part, j, m, rtol,
+                               1, w.status_dev);
+            k.axpy(V, j + 1, nullptr, st->coef, vn, vn, &st->scale, false, &st->go);
+            k.dots(V, j + 1, vn, &st->pass2);
+            hipLaunchKernelGGL(g3_column_kernel, dim3(1), dim3(kKryCtl), 0, s, st, (const double *)w.part, j, m, rtol,
+                               2, w.status_dev);
+            k.axpy(V, j + 1, nullptr, st->coef, vn, vn, &st->scale, false, &st->pass2);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if ((e = mark(j + 1)) != hipSuccess) return e;
         }
-        // x += V y, H y = g (upper triangular, j columns)
-        for (int i = j - 1; i >= 0; --i) {
-            double v = g[i];
-            for (int l = i + 1; l < j; ++l) v -= H[(size_t)i * m + l] * y[l];
-            y[i] = v / H[(size_t)i * m + i];
-        }
-        std::vector<double> ny(j);
-        for (int i = 0; i < j; ++i) ny[i] = -y[i];
-        if ((e = k.axpy(precond ? w.Z : V, j, ny.data(), x, x, 1.0, false, nullptr)) != hipSuccess) return e;
+        if (!waited && (e = hipEventSynchronize(w.ev[0])) != hipSuccess) return e;
+        // x += Z y over the cycle's columns
+        hipLaunchKernelGGL(g3_end_kernel, dim3(1), dim3(64), 0, s, st);
+        k.axpy(precond ? w.Z : V, 0, &st->ncols, st->coef, x, x, nullptr, false, &st->ncols);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (w.status->open == 0) break;
     }
-    // final residual after the last cycle
-    if ((e = launch_l3(h, x, w.t, 1.0, -alpha, s)) != hipSuccess) return e;
-    const double one = 1.0;
-    double r2 = 0.0;
-    if ((e = k.axpy(w.t, 1, &one, b, V, 1.0, true, &r2)) != hipSuccess) return e;
-    *relres = std::sqrt(r2) / bn;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    *iters = w.status->iters;
+    *relres = w.status->relres;
     return hipSuccess;
 }
 

@@ -83,6 +83,7 @@ struct GmresArgs {
     int *iters;          // [n_x n_y] Arnoldi steps per column (negative: not converged), or null
     int schur;           // 1: solve the Schur complement in w (restart kGmresRegM only)
     int pick;            // with x0: per column, start from x0 or from b, whichever has the smaller residual
+    const int *gate;     // device flag: the launch does nothing while it is 0 (null: always runs)
 };
 
 constexpr int kMaxComb = 6;
@@ -92,8 +93,10 @@ struct LinComb {
 };
 
 size_t gmres_lds_bytes(int nz, int N, int restart);
-// y = L_v x on [5][U]; with uv false the u and v rows of y are left untouched
-hipError_t launch_lv_apply(const HeviParams &h, const double *x, double *y, hipStream_t s, bool uv = true);
+// y = L_v x on [5][U]; with uv false the u and v rows of y are left untouched;
+// with a gate (device flag) nothing is done while it is 0
+hipError_t launch_lv_apply(const HeviParams &h, const double *x, double *y, hipStream_t s, bool uv = true,
+                           const int *gate = nullptr);
 hipError_t launch_axpy_multi(long n, const double *base, int nsrc, const LinComb &lc, double *out,
                              hipStream_t s);
 hipError_t launch_gmres(const HeviParams &h, const GmresArgs &g, hipStream_t s);
@@ -117,15 +120,42 @@ struct L3Params {
     double gamma;
     HeviParams hv;           // the vertical part (L_v)
 };
+// Device-resident state of one global GMRES solve: the Hessenberg problem,
+// the coefficients of the next vector combination and the control flags
+// that gate the launches queued ahead of them.
+struct G3State {
+    double H[(kG3MaxRestart + 1) * kG3MaxRestart];   // rotated Hessenberg, H[i kG3MaxRestart + j]
+    double cs[kG3MaxRestart], sn[kG3MaxRestart], gv[kG3MaxRestart + 1];
+    double hc[kG3MaxRestart + 1];     // current column after the first Gram-Schmidt pass
+    double coef[kG3MaxRestart + 1];   // coefficients of the next combination
+    double scale, one, zero, bn, relres;
+    int go;      // the current cycle's Arnoldi process continues
+    int pass2;   // the current column takes a second Gram-Schmidt pass
+    int open;    // rtol not met yet
+    int bzero;   // b = 0
+    int ncols;   // columns of the current cycle
+    int iters;   // Arnoldi steps so far
+};
+// What the host reads of the solve: written by the kernels into host-mapped
+// memory, read once an event recorded after them has completed.
+struct G3Status {
+    int go, open, iters, pad;
+    double relres;
+};
 struct G3Work {
     double *V;      // (restart + 1) Krylov vectors of 5U
     double *Z;      // restart preconditioned vectors (flexible GMRES)
     double *t;      // one 5U vector
-    double *part;   // [1024][35] block partial sums
-    double *red;    // [35] reduced sums
+    double *part;   // [35][1024] block partial sums, quantity-major
+    G3State *state;                 // device
+    G3Status *status_dev;           // host-mapped status, device address
+    const volatile G3Status *status;  // the same, host address
+    hipEvent_t ev[2];               // marks of the host's look-ahead
 };
-// out = a x + c L x on [5][U] (out may not alias x)
-hipError_t launch_l3(const L3Params &h, const double *x, double *out, double a, double c, hipStream_t s);
+// out = a x + c L x on [5][U] (out may not alias x); with a gate (device
+// flag) nothing is done while it is 0
+hipError_t launch_l3(const L3Params &h, const double *x, double *out, double a, double c, hipStream_t s,
+                     const int *gate = nullptr);
 // (I - alpha L) x = b by restarted GMRES(m); iters = Arnoldi steps, relres =
 // final ||b - A x|| / ||b||
 // precond: right-precondition with the column systems (I - alpha L_v)

@@ -57,6 +57,10 @@ struct nh_ctx {
     // allocation-free scratch array (see nh_ri_velocity_noalloc)
     int device;
     void *scratch_dev;
+    // host-mapped status and look-ahead events of the global GMRES (made by
+    // the first 3D-IMEX solve, released by nh_destroy)
+    G3Status *g3s_host, *g3s_dev;
+    hipEvent_t g3ev[2];
     // error state
     bool sticky;
     std::string err;
@@ -1221,7 +1225,7 @@ static size_t g3_bytes(const nh_ctx *c, int restart, bool step, G3Work *w, doubl
     g.Z = (double *)take(nv * restart);
     g.t = (double *)take(nv);
     g.part = (double *)take(sizeof(double) * 1024 * 35);
-    g.red = (double *)take(sizeof(double) * 35);
+    g.state = (G3State *)take(sizeof(G3State));
     if (step)
         for (int i = 0; i < 8; ++i) {
             double *a = (double *)take(nv);
@@ -1229,6 +1233,34 @@ static size_t g3_bytes(const nh_ctx *c, int restart, bool step, G3Work *w, doubl
         }
     if (w) *w = g;
     return off;
+}
+
+// The context's host-mapped status block and events, made on first use
+static nh_status g3_host(nh_ctx *c, G3Work *w)
+{
+    if (!c->g3s_host) {
+        void *p = nullptr;
+        HIPCHK(c, hipHostMalloc(&p, sizeof(G3Status), hipHostMallocMapped | hipHostMallocCoherent));
+        void *d = nullptr;
+        hipError_t e = hipHostGetDevicePointer(&d, p, 0);
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+        if (e != hipSuccess) {
+            for (hipEvent_t x : ev)
+                if (x) (void)hipEventDestroy(x);
+            (void)hipHostFree(p);
+            HIPCHK(c, e);
+        }
+        c->g3s_host = (G3Status *)p;
+        c->g3s_dev = (G3Status *)d;
+        c->g3ev[0] = ev[0];
+        c->g3ev[1] = ev[1];
+    }
+    w->status = c->g3s_host;
+    w->status_dev = c->g3s_dev;
+    w->ev[0] = c->g3ev[0];
+    w->ev[1] = c->g3ev[1];
+    return NH_OK;
 }
 
 static nh_status check_g3_opts(nh_ctx *c, const nh_gmres_opts *o)
@@ -1296,6 +1328,7 @@ nh_status nh_global_solve(nh_ctx *c, double alpha, const double *dev_b, const do
     if ((st = check_g3_ws(c, opts, false, dev_ws, bytes))) return st;
     G3Work w;
     g3_bytes(c, opts->restart, false, &w, nullptr, (char *)dev_ws);
+    if ((st = g3_host(c, &w))) return st;
     if (stats) *stats = nh_solve_stats{};
     int it = 0;
     double rr = 0.0;
@@ -1318,6 +1351,7 @@ nh_status nh_imex3d_step(nh_ctx *c, double t, double dt, const nh_gmres_opts *op
     G3Work w;
     double *a[8];
     g3_bytes(c, opts->restart, true, &w, a, (char *)dev_ws);
+    if ((st = g3_host(c, &w))) return st;
     if (stats) *stats = nh_solve_stats{};
     static const Ark2 ark;
     const long n = kNF * (long)c->U;
@@ -1369,6 +1403,10 @@ nh_status nh_last_error(const nh_ctx *c, char *buf, size_t n)
 nh_status nh_destroy(nh_ctx *c)
 {
     if (!c) return NH_EINVAL;
+    if (c->g3s_host) {
+        (void)hipHostFree(c->g3s_host);
+        for (hipEvent_t e : c->g3ev) (void)hipEventDestroy(e);
+    }
     delete c;
     return NH_OK;
 }
