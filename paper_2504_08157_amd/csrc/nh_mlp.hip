@@ -205,8 +205,9 @@ __global__ void __launch_bounds__(512) mlp_guess_kernel(MlpColParams p, const do
 // acc += A B^T over one 32-wide k slice held as 8 halves per lane, as two
 // v_mfma_f32_16x16x16_f16 (halves 0-3, then 4-7 of both operands: the same
 // k values pair up).  The single-instruction v_mfma_f32_16x16x32_f16 form
-// gave run-to-run different results in the fused inference kernel (whose K
-// loop reloads the operand registers from LDS right behind the MFMAs), so
+// gave run-to-run different results in the fused inference kernel although
+// its LDS accesses are race-free between barriers; that build spills MFMA
+// operands and rewrites their registers right behind the instruction, so
 // it is not used.
 __device__ __forceinline__ float4v mfma_k32(const half8 &a, const half8 &b, float4v c)
 {

@@ -132,6 +132,32 @@ def test_fused_guess_matches_separate_kernels(oracle_mod):
     assert _rel(corr, corr_ref) <= 1e-12, _rel(corr, corr_ref)
 
 
+def test_fused_guess_and_forward_repeatable():
+    """The same input three times: the fused guess (16,384 columns, 256
+    workgroups of the inference kernel) and the forward GEMMs return the
+    same bits every time."""
+    import torch
+    from paper_2504_08157_amd import nhsem
+    w = W.cfg_hevi()
+    w.mesh = W._tc_mesh(32, 32, 6)
+    ctx = nhsem.Context(w.mesh, w.phys)
+    g = ctx.nh_lattice_coords()
+    ctx.nh_set_reference(*W.reference_profiles(w, g[2]))
+    assert ctx.nx * ctx.ny == 16384
+    m = nhsem.ColumnMLP(max_batch=16384)
+    rng = np.random.default_rng(21)
+    m.nh_mlp_set_params(torch.from_numpy(rng.normal(scale=0.05, size=m.nparam).astype(np.float32)).cuda())
+    b = torch.from_numpy(W.smooth_random_state(*g, *W.reference_profiles(w, g[2]), seed=5,
+                                               walls=(False, False))).cuda()
+    x = torch.from_numpy(rng.normal(size=(16384, MO.IN)).astype(np.float16)).cuda()
+    ref_g = m.nh_mlp_guess(ctx, 0.7, b).clone()
+    ref_y = m.nh_mlp_forward(x).clone()
+    assert torch.isfinite(ref_g).all() and torch.isfinite(ref_y).all()
+    for _ in range(2):
+        assert torch.equal(m.nh_mlp_guess(ctx, 0.7, b), ref_g)
+        assert torch.equal(m.nh_mlp_forward(x), ref_y)
+
+
 def test_untrained_guess_equals_default(oracle_mod):
     import torch
     from paper_2504_08157_amd import nhsem
