@@ -61,6 +61,102 @@ def measured_traffic(tile, counters=COUNTERS, src=KERNEL_SRC, key="traffic_bytes
         return None
 
 
+GMRES_COUNTERS = os.path.join(ROOT, "profiles", "gmres_column_hevi_96x96x16_N4_counters.txt")
+GMRES_SRC = os.path.join(ROOT, "paper_2504_08157_amd", "csrc", "nh_hevi.hip")
+# MI355X vector FP64: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz; a
+# wave64 VALU instruction occupies its SIMD for 4 cycles
+FP64_VALU_PEAK_TFLOPS = 78.6
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+
+
+def gmres_counters(form):
+    """Per column and Arnoldi step of the column GMRES kernel of `form`
+    ("full" or "schur"): VALU wave instructions and executed FP64 flops from
+    the committed SQ counter summary, or None when nh_hevi.hip differs from
+    the profiled source."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(GMRES_COUNTERS):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.split()[0]
+        if kv.get("source_sha256") != hashlib.sha256(open(GMRES_SRC, "rb").read()).hexdigest():
+            return None
+        return float(kv[f"{form}_valu_insts_per_column_step"]), float(kv[f"{form}_fp64_flops_per_column_step"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def time_column_solves(ctx, w, reps, rtol=1e-10):
+    """The two implicit solves of the last HEVI step of ctx, solved again by
+    nh_column_solve in the full and the Schur form (default guess, GMRES(10),
+    rtol): live time per solve (HIP events on the library's stream), Arnoldi
+    steps, and the kernel's place under the FP64 VALU roof from the counter
+    summary."""
+    import torch
+    a_dt, solves = ctx.nh_hevi_last_solves()
+    out = {}
+    xs = torch.empty(5 * ctx.U, dtype=torch.float64, device="cuda")
+    for form, schur in (("full", False), ("schur", True)):
+        ms, steps, n = 0.0, 0, 0
+        for (R, _) in solves:
+            ctx.nh_column_solve(a_dt * w.dt, R, out=xs, restart=10, max_restarts=30, rtol=rtol, schur=schur)
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                _, st = ctx.nh_column_solve(a_dt * w.dt, R, out=xs, restart=10, max_restarts=30, rtol=rtol,
+                                            schur=schur)
+                e1.record()
+                torch.cuda.synchronize()
+                ms += e0.elapsed_time(e1)
+                steps += st.iters_total
+                n += 1
+        ncol = ctx.nx * ctx.ny
+        rate = steps / (ms / 1e3)   # column Arnoldi steps per second
+        r = {"ms_per_solve": ms / n, "arnoldi_steps_per_column": steps / n / ncol, "column_steps_per_s": rate,
+             "column_steps_per_solve": steps / n}
+        c = gmres_counters(form)
+        if c is not None:
+            insts, flops = c
+            r["roofline"] = {"bound": "alu", "achieved": flops * rate / 1e12, "peak": FP64_VALU_PEAK_TFLOPS,
+                             "unit": "TFLOP/s", "frac": flops * rate / 1e12 / FP64_VALU_PEAK_TFLOPS,
+                             "valu_issue_frac": insts * rate / VALU_ISSUE_PEAK,
+                             "valu_insts_per_column_step": insts, "fp64_flops_per_column_step": flops,
+                             "note": "executed FP64 flops and VALU instructions per column step from the "
+                                     "committed SQ counter summary; time and steps live"}
+        else:
+            r["roofline"] = None
+        out[form] = r
+    return out
+
+
+def bench_gmres(args):
+    """Column GMRES alone on the 96 x 96 x 16, N = 4 HEVI case: `warmup`
+    default HEVI steps, then the two implicit solves of the last one solved
+    again `steps` times each, in the full and the Schur form."""
+    from paper_2504_08157_amd import learned_guess as LG
+    from paper_2504_08157_amd import workloads as W
+    w = W.cfg_hevi()
+    ctx = LG.hevi_context(w)
+    for s in range(max(args.warmup, 1)):
+        ctx.nh_hevi_step(s * w.dt, w.dt, rtol=1e-10, max_restarts=30, restart=10, schur=True)
+    res = time_column_solves(ctx, w, max(args.steps, 1))
+    ncol = ctx.nx * ctx.ny
+    U = ctx.U
+    ctx.close()
+    f = res["schur"]
+    line = {
+        "metric": "column Arnoldi steps/s (column GMRES, FP64)", "value": f["column_steps_per_s"],
+        "unit": "column Arnoldi steps/s", "n_gpus": 1, "steps": args.steps, "warmup": max(args.warmup, 1),
+        "ms_per_step": f["ms_per_solve"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "mode": "gmres", "columns": ncol, "U": U,
+                   "gmres": "GMRES(10), rtol 1e-10, default guess, the last HEVI step's two solves"},
+        "roofline": f["roofline"], "gmres": res}
+    print(json.dumps(line), flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,7 +170,8 @@ def parse():
     ap.add_argument("--tile", type=int, default=-1, help="stage-kernel tile variant; -1 = tune by timing")
     ap.add_argument("--copy-mib", type=int, default=1024, help="buffer size of the copy calibration")
     ap.add_argument("--err-steps", type=int, default=600, help="steps of the FP32-vs-FP64 comparison (precision mode)")
-    ap.add_argument("--mode", choices=["rk", "hevi", "batched", "copy", "precision", "hyper", "ri", "imex3d"],
+    ap.add_argument("--mode", choices=["rk", "hevi", "batched", "copy", "precision", "hyper", "ri", "imex3d",
+                                       "gmres"],
                     default="rk",
                     help="rk: SSP-RK3 on the per-GPU TC share (headline); hevi: HEVI ARK2 step with and "
                          "without the learned GMRES guess; batched: 48 uneven instances in graph launches; "
@@ -82,7 +179,8 @@ def parse():
                          "HBM byte counters; precision: FP32-mixed vs FP64 after --err-steps steps; "
                          "hyper: the tensor hyper-diffusion term alone and the SSP-RK3 step with it; "
                          "ri: the RI-velocity diagnostic (centroids, 50-strip azimuthal means, u_RI); "
-                         "imex3d: 3D-IMEX ARK2 steps (global GMRES) against HEVI and explicit RK3")
+                         "imex3d: 3D-IMEX ARK2 steps (global GMRES) against HEVI and explicit RK3; "
+                         "gmres: the column GMRES alone (full and Schur form) with its FP64 VALU roofline")
     ap.add_argument("--members", type=int, default=48)
     ap.add_argument("--imex-time", type=float, default=8.0, help="simulated seconds of the imex3d comparison")
     ap.add_argument("--mlp-epochs", type=int, default=160, help="training epochs of the column MLP (hevi mode)")
@@ -116,10 +214,51 @@ def cpu_baseline(w, nel, min_seconds):
         q = orc.rk3(steps * w.dt, w.dt, 1, q)
         sec += time.perf_counter() - t0
         steps += 1
-    return {"value": 5 * orc.U * 3 * steps / sec, "unit": "DOF-stage updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{steps} SSP-RK3 steps (3 RHS each) of a {nel}x{nel}x{mesh.nel[2]} element N={mesh.order} "
-                      f"box of the same workload (U={orc.U}), {sec:.2f} s"}
+    out = {"value": 5 * orc.U * 3 * steps / sec, "unit": "DOF-stage updates/s", "cores": oracle.num_threads(),
+           "kind": "oracle",
+           "sample": f"{steps} SSP-RK3 steps (3 RHS each) of a {nel}x{nel}x{mesh.nel[2]} element N={mesh.order} "
+                     f"box of the same workload (U={orc.U}), {sec:.2f} s",
+           "cpu_model": cpu_model()}
+    del orc, q, Q
+    # the same oracle on one host thread, on a smaller box of the same
+    # workload (a whole step of the full box takes about half a minute there)
+    n1 = max(8, nel // 4)
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        mesh1 = W._tc_mesh(n1, n1, w.mesh.nel[2], w.mesh.order, half=600.0e3 * n1 / w.mesh.nel[0])
+        sub1 = W.Workload(w.name, mesh1, w.phys, w.dt, 1, w.reference, w.ic, vmax=w.vmax, heating_T=w.heating_T)
+        orc = oracle.Oracle(mesh1, w.phys)
+        x, y, z = orc.lattice_coords()
+        orc.set_reference(*W.reference_profiles(sub1, z))
+        t, Q = W.heating(sub1, x, y, z)
+        orc.set_forcing(4, t, Q)
+        q = W.initial_state(sub1, x, y, z)
+        steps1, sec1 = 0, 0.0
+        while sec1 < min_seconds / 2 and steps1 < 1000:
+            t0 = time.perf_counter()
+            q = orc.rk3(steps1 * w.dt, w.dt, 1, q)
+            sec1 += time.perf_counter() - t0
+            steps1 += 1
+    finally:
+        oracle.set_num_threads(threads)
+    out["value_1thread"] = 5 * orc.U * 3 * steps1 / sec1
+    out["sample_1thread"] = (f"{steps1} SSP-RK3 steps of a {n1}x{n1}x{mesh1.nel[2]} element N={mesh1.order} box "
+                             f"(U={orc.U}) on 1 thread, {sec1:.2f} s")
+    return out
+
+
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or the platform's."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
 
 
 def bench_hevi(args):
@@ -148,7 +287,10 @@ def bench_hevi(args):
     res_s = None
     if args.gmres_restart == 10:
         res_s = LG.compare(mlp, w, warm=warm, held=args.steps, dt=w.dt, restart=10, schur=True)
-    ctx = nhsem.Context(w.mesh, w.phys)
+    ctx = LG.hevi_context(w)
+    for s in range(warm):
+        ctx.nh_hevi_step(s * w.dt, w.dt, rtol=1e-10, max_restarts=30, restart=10, schur=True)
+    gm = time_column_solves(ctx, w, 3)
     U = ctx.U
     ctx.close()
     d, m = res["default"], res["mlp"]
@@ -168,6 +310,7 @@ def bench_hevi(args):
                  "state_rel_diff_mlp_vs_default": res["state_rel_diff"],
                  "state_rel_diff_stacked": res["state_rel_diff_stacked"],
                  "training": tr},
+        "gmres": gm,
     }
     if res_s is not None:
         ds, ms = res_s["default"], res_s["mlp"]
@@ -611,6 +754,8 @@ def main():
         return bench_ri(args)
     if args.mode == "imex3d":
         return bench_imex3d(args)
+    if args.mode == "gmres":
+        return bench_gmres(args)
     import numpy as np
     import torch
     from paper_2504_08157_amd import nhsem

@@ -746,3 +746,6 @@ void or_l3_apply(void *p, const double *x, double *y)
 
 /* Threads an OpenMP loop of the oracle uses. */
 int or_num_threads(void) { return omp_get_max_threads(); }
+
+/* Sets the threads of the oracle's later parallel loops (n >= 1). */
+void or_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }

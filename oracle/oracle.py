@@ -65,6 +65,7 @@ def load():
     lib.or_lv_apply.argtypes = [ctypes.c_void_p, _dp, _dp]
     lib.or_l3_apply.argtypes = [ctypes.c_void_p, _dp, _dp]
     lib.or_num_threads.restype = ctypes.c_int
+    lib.or_set_num_threads.argtypes = [ctypes.c_int]
     lib.or_rhs_sample.restype = ctypes.c_int
     lib.or_rhs_sample.argtypes = [ctypes.c_void_p, ctypes.c_double, _dp, ctypes.c_int64, _lp, _dp]
     _lib = lib
@@ -91,6 +92,11 @@ def lgl(N):
 def num_threads():
     """OpenMP threads the oracle's parallel loops use."""
     return int(load().or_num_threads())
+
+
+def set_num_threads(n):
+    """Threads of the oracle's later parallel loops."""
+    load().or_set_num_threads(int(n))
 
 
 class Oracle:
