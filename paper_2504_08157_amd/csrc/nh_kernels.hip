@@ -68,6 +68,18 @@ __device__ __forceinline__ double pert_pressure(double rp, double tp, double inv
 // Workgroup shape of the stage kernel: tile of TX x TY lattice columns
 // (AX x AY elements), one thread per owned node of a z-element slab
 // (N levels x TX x TY, at most 1024).
+// Two values of the stage kernel's arithmetic type in one LDS element.
+template <typename T>
+struct Pair;
+template <>
+struct Pair<double> {
+    using type = double2;
+};
+template <>
+struct Pair<float> {
+    using type = float2;
+};
+
 template <int N, int AX, int AY>
 struct StageShape {
     static constexpr int N1 = N + 1;
@@ -99,12 +111,15 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile,
     constexpr int N1 = S::N1, TX = S::TX, TY = S::TY, NCOL = S::NCOL, NOWN = S::NOWN;
     constexpr int NT = S::NT, PX = S::PX, PS = S::PS, NSP = S::NSP, NC = S::NC;
     constexpr bool kF64 = sizeof(T) == 8;
+    using T2 = typename Pair<T>::type;
 
-    // Plane slots, plus N rows of padding: stencil taps past the last row of
-    // a plane read finite padding or the next plane (always with a zero
-    // coefficient), so tap addresses need no clamping.
-    __shared__ T plbuf[N1 * 6 * PS + N * PX];
-    T(*pl)[6][PS] = reinterpret_cast<T(*)[6][PS]>(plbuf);
+    // Plane slots of field pairs (p', u), (v, w), (theta', rho'), one 16-byte
+    // (FP32: 8-byte) LDS element per pair, so that a stencil tap reads the six
+    // fields with three loads; plus N rows of padding: stencil taps past the
+    // last row of a plane read finite padding or the next plane (always with
+    // a zero coefficient), so tap addresses need no clamping.
+    __shared__ T2 plbuf[N1 * 3 * PS + N * PX];
+    T2(*pl)[3][PS] = reinterpret_cast<T2(*)[3][PS]>(plbuf);
     __shared__ T cx[TX * NC];
     __shared__ T cy[TY * NC];
     __shared__ T sD[N1 * N1];
@@ -148,7 +163,7 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile,
     for (int i = tid; i < N1 * N1; i += NT) sD[i] = T(p.cst[kCstD + i]);
     for (int i = tid; i < kEosTerms; i += NT) sE[i] = p.cst[kCstEos + i];
     // slots that are never staged (plane corners, padding) stay zero
-    for (int i = tid; i < N1 * 6 * PS + N * PX; i += NT) plbuf[i] = T(0);
+    for (int i = tid; i < N1 * 3 * PS + N * PX; i += NT) plbuf[i] = T2{T(0), T(0)};
     __syncthreads();
 
     // Staging map, the same for every level: staged node s (0 <= s < NSP)
@@ -224,7 +239,7 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile,
             v4 = *(const double *)(b + 4 * field_bytes);
             pp = pert_pressure(v0, v4, L[0], L[1], L[2], p.gamma, sE);
         }
-        T(*P)[PS] = pl[k % N1];
+        T2(*P)[PS] = pl[k % N1];
         const int idx = sidx[s];
         if constexpr (!kF64) {
             if (s < NCOL) {
@@ -232,12 +247,9 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile,
                 Q[0] = v0; Q[NCOL] = v1; Q[2 * NCOL] = v2; Q[3 * NCOL] = v3; Q[4 * NCOL] = v4;
             }
         }
-        P[0][idx] = T(pp);
-        P[1][idx] = T(v1);
-        P[2][idx] = T(v2);
-        P[3][idx] = T(v3);
-        P[4][idx] = T(v4);
-        P[5][idx] = T(v0);
+        P[0][idx] = T2{T(pp), T(v1)};
+        P[1][idx] = T2{T(v2), T(v3)};
+        P[2][idx] = T2{T(v4), T(v0)};
     };
 
     // x/y part of the tendency at (tx, ty) of plane slot `sl` (reference
@@ -252,7 +264,7 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile,
     asm volatile("" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]))
     auto horizontal = [&](int sl, T r0, int tx, int ty, T *XY, T &inv) {
         NH_FENCE();
-        const T(*P)[PS] = pl[sl];
+        const T2(*P)[PS] = pl[sl];
         T dx[6], dy[6];
 #pragma unroll
         for (int f = 0; f < 6; ++f) { dx[f] = T(0); dy[f] = T(0); }
@@ -261,12 +273,13 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile,
         for (int m = 0; m < NC; ++m) {
             const T c = cx[tx * NC + m];
             const int j = rowx + tx + m;
-            dx[0] += c * P[0][j];
-            dx[1] += c * P[1][j];
-            dx[2] += c * P[2][j];
-            dx[3] += c * P[3][j];
-            dx[4] += c * P[4][j];
-            dx[5] += c * ((r0 + P[5][j]) * P[1][j]);
+            const T2 a = P[0][j], b = P[1][j], e = P[2][j];
+            dx[0] += c * a.x;
+            dx[1] += c * a.y;
+            dx[2] += c * b.x;
+            dx[3] += c * b.y;
+            dx[4] += c * e.x;
+            dx[5] += c * ((r0 + e.y) * a.y);
             NH_PIN(dx);
         }
         NH_FENCE();
@@ -274,18 +287,19 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile,
         for (int m = 0; m < NC; ++m) {
             const T c = cy[ty * NC + m];
             const int j = (ty + m) * PX + N + tx;
-            dy[0] += c * P[0][j];
-            dy[1] += c * P[1][j];
-            dy[2] += c * P[2][j];
-            dy[3] += c * P[3][j];
-            dy[4] += c * P[4][j];
-            dy[5] += c * ((r0 + P[5][j]) * P[2][j]);
+            const T2 a = P[0][j], b = P[1][j], e = P[2][j];
+            dy[0] += c * a.x;
+            dy[1] += c * a.y;
+            dy[2] += c * b.x;
+            dy[3] += c * b.y;
+            dy[4] += c * e.x;
+            dy[5] += c * ((r0 + e.y) * b.x);
             NH_PIN(dy);
         }
         NH_FENCE();
         const int jo = rowx + N + tx;
-        const T u = P[1][jo], v = P[2][jo];
-        inv = T(1) / (r0 + P[5][jo]);
+        const T u = P[0][jo].y, v = P[1][jo].x;
+        inv = T(1) / (r0 + P[2][jo].y);
         XY[0] = -(dx[5] + dy[5]);
         XY[1] = -(u * dx[1] + v * dy[1]) - dx[0] * inv;
         XY[2] = -(u * dx[2] + v * dy[2]) - dy[0] * inv;
@@ -301,16 +315,17 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile,
         for (int f = 0; f < 6; ++f) dz[f] = T(0);
 #pragma unroll
         for (int m = 0; m < N1; ++m) {
-            const T(*P)[PS] = pl[(ez * N + m) % N1];
+            const T2(*P)[PS] = pl[(ez * N + m) % N1];
             const T d = sD[r * N1 + m];
-            const T w = P[3][jo];
+            const T2 a = P[0][jo], b = P[1][jo], e = P[2][jo];
+            const T w = b.y;
             const T r0 = T(slev[m * 5]);
-            dz[0] += d * P[0][jo];
-            dz[1] += d * P[1][jo];
-            dz[2] += d * P[2][jo];
+            dz[0] += d * a.x;
+            dz[1] += d * a.y;
+            dz[2] += d * b.x;
             dz[3] += d * w;
-            dz[4] += d * P[4][jo];
-            dz[5] += d * ((r0 + P[5][jo]) * w);
+            dz[4] += d * e.x;
+            dz[5] += d * ((r0 + e.y) * w);
             NH_PIN(dz);
         }
 #pragma unroll
@@ -346,10 +361,14 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile,
         // registers through the contractions
         T own[6];
         {
-            const T(*P)[PS] = pl[k % N1];
+            const T2(*P)[PS] = pl[k % N1];
             const int jo = (N + ty) * PX + N + tx;
-#pragma unroll
-            for (int f = 1; f < 6; ++f) own[f] = P[f][jo];
+            const T2 a = P[0][jo], b = P[1][jo], e = P[2][jo];
+            own[1] = a.y;
+            own[2] = b.x;
+            own[3] = b.y;
+            own[4] = e.x;
+            own[5] = e.y;
         }
         const bool valid = nd.valid;
         const int gx = valid ? gx0 : 0, gy = valid ? gy0 : 0;
