@@ -157,6 +157,69 @@ def bench_gmres(args):
     print(json.dumps(line), flush=True)
 
 
+# GEMM flops per sample of the column MLP (400 -> 256 -> 256 -> 256 with the
+# 400 -> 256 bypass): forward W1, W2, W3, S; backward dH2, dH1 and the four
+# weight gradients
+MLP_FWD_FLOPS = 2 * (400 * 256 + 256 * 256 + 256 * 256 + 400 * 256)
+MLP_BWD_FLOPS = 2 * (256 * 256 * 2 + 400 * 256 * 2 + 256 * 256 * 2)
+MFMA_F16_PEAK_TFLOPS = 2500.0
+MFMA_F32_PEAK_TFLOPS = 157.3
+
+
+def bench_mlp(args):
+    """The column MLP's training kernels alone on seeded synthetic features
+    and targets (batch 1024 and 4096): forward GEMMs (FP16 MFMA), backward
+    (FP32 MFMA GEMMs, bias sums, SiLU derivative) and whole training steps
+    (forward, MSE gradient, backward, Adam), timed with HIP events."""
+    import numpy as np
+    import torch
+    from paper_2504_08157_amd import nhsem
+    rng = np.random.default_rng(17)
+    res = {}
+    for B in (1024, 4096):
+        m = nhsem.ColumnMLP(max_batch=B, seed=7)
+        x = torch.from_numpy(rng.normal(size=(B, nhsem.MLP_IN)).astype(np.float16)).cuda()
+        t = torch.from_numpy(rng.normal(scale=0.1, size=(B, nhsem.MLP_OUT)).astype(np.float32)).cuda()
+        dy = torch.from_numpy(rng.normal(scale=1e-4, size=(B, nhsem.MLP_OUT)).astype(np.float32)).cuda()
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+
+        def timed(fn, n):
+            for _ in range(max(args.warmup, 1)):
+                fn()
+            e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(n):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / n
+
+        n = max(args.steps, 10)
+        fwd = timed(lambda: m.nh_mlp_forward(x), n)
+        bwd = timed(lambda: m.nh_mlp_backward(x, dy), n)
+        stp = timed(lambda: m.nh_mlp_train_step(x, t, lr=1e-4, loss=loss), n)
+        af = MLP_FWD_FLOPS * B / (fwd / 1e3) / 1e12
+        ab = MLP_BWD_FLOPS * B / (bwd / 1e3) / 1e12
+        res[str(B)] = {"forward_ms": fwd, "backward_ms": bwd, "train_step_ms": stp,
+                       "samples_per_s": B / (stp / 1e3),
+                       "forward_tflops": af, "forward_frac_of_f16_mfma_peak": af / MFMA_F16_PEAK_TFLOPS,
+                       "backward_tflops": ab, "backward_frac_of_f32_mfma_peak": ab / MFMA_F32_PEAK_TFLOPS}
+        del m
+    r = res["4096"]
+    line = {"metric": "MLP training samples/s (column guess network)", "value": r["samples_per_s"],
+            "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": r["train_step_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f16+f32", "data": "synthetic",
+            "config": {"workload": "column MLP 400-256-256-256 with bypass", "mode": "mlp", "batch": 4096},
+            "roofline": {"bound": "mfma", "achieved": r["backward_tflops"], "peak": MFMA_F32_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": r["backward_frac_of_f32_mfma_peak"],
+                         "kernel": "backward (FP32 MFMA GEMMs with their bias sums and SiLU derivative)",
+                         "flops_per_sample": MLP_BWD_FLOPS},
+            "mlp": res}
+    print(json.dumps(line), flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,7 +234,7 @@ def parse():
     ap.add_argument("--copy-mib", type=int, default=1024, help="buffer size of the copy calibration")
     ap.add_argument("--err-steps", type=int, default=600, help="steps of the FP32-vs-FP64 comparison (precision mode)")
     ap.add_argument("--mode", choices=["rk", "hevi", "batched", "copy", "precision", "hyper", "ri", "imex3d",
-                                       "gmres"],
+                                       "gmres", "mlp"],
                     default="rk",
                     help="rk: SSP-RK3 on the per-GPU TC share (headline); hevi: HEVI ARK2 step with and "
                          "without the learned GMRES guess; batched: 48 uneven instances in graph launches; "
@@ -180,7 +243,8 @@ def parse():
                          "hyper: the tensor hyper-diffusion term alone and the SSP-RK3 step with it; "
                          "ri: the RI-velocity diagnostic (centroids, 50-strip azimuthal means, u_RI); "
                          "imex3d: 3D-IMEX ARK2 steps (global GMRES) against HEVI and explicit RK3; "
-                         "gmres: the column GMRES alone (full and Schur form) with its FP64 VALU roofline")
+                         "gmres: the column GMRES alone (full and Schur form) with its FP64 VALU roofline; "
+                         "mlp: the column MLP's forward, backward and training step alone")
     ap.add_argument("--members", type=int, default=48)
     ap.add_argument("--imex-time", type=float, default=8.0, help="simulated seconds of the imex3d comparison")
     ap.add_argument("--mlp-epochs", type=int, default=160, help="training epochs of the column MLP (hevi mode)")
@@ -310,6 +374,8 @@ def bench_hevi(args):
                  "state_rel_diff_mlp_vs_default": res["state_rel_diff"],
                  "state_rel_diff_stacked": res["state_rel_diff_stacked"],
                  "training": tr},
+        # the dominant kernel of the timed steps: the full-form column GMRES
+        "roofline": gm["full"]["roofline"],
         "gmres": gm,
     }
     if res_s is not None:
@@ -756,6 +822,8 @@ def main():
         return bench_imex3d(args)
     if args.mode == "gmres":
         return bench_gmres(args)
+    if args.mode == "mlp":
+        return bench_mlp(args)
     import numpy as np
     import torch
     from paper_2504_08157_amd import nhsem

@@ -93,10 +93,8 @@ struct LinComb {
 };
 
 size_t gmres_lds_bytes(int nz, int N, int restart);
-// y = L_v x on [5][U]; with uv false the u and v rows of y are left untouched;
-// with a gate (device flag) nothing is done while it is 0
-hipError_t launch_lv_apply(const HeviParams &h, const double *x, double *y, hipStream_t s, bool uv = true,
-                           const int *gate = nullptr);
+// y = L_v x on [5][U]; with uv false the u and v rows of y are left untouched
+hipError_t launch_lv_apply(const HeviParams &h, const double *x, double *y, hipStream_t s, bool uv = true);
 hipError_t launch_axpy_multi(long n, const double *base, int nsrc, const LinComb &lc, double *out,
                              hipStream_t s);
 hipError_t launch_gmres(const HeviParams &h, const GmresArgs &g, hipStream_t s);
@@ -193,6 +191,7 @@ constexpr int kMlpSlices = 16;  // batch slices of the weight-gradient GEMMs
 constexpr int kMlpNC = 65;     // canonical levels: LGL nodes of 16 order-4 elements
 constexpr int kMlpNF = 3 * kMlpNC;
 constexpr int kMlpLossBlocks = 256;
+constexpr int kMlpColRows = 64;    // rows per partial of the bias-gradient column sums
 
 struct MlpColParams {
     int nx, ny, nz;

@@ -562,51 +562,91 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) m
     }
 }
 
-// ---------------------------------------------------------------- backward (FP32)
-// C[M x N] = sum_k A(m, k) B(k, n) with element strides; A, B of type TA, TB
-// (FP16 or FP32), FP32 accumulation, 64 x 64 tiles staged through LDS in
-// K-chunks of 16.  Split K: workgroup z sums k in [z kslice, (z+1) kslice)
-// into C + z M N (partials reduced by sum_slices_kernel).
-template <typename TA, typename TB>
-__global__ void __launch_bounds__(256) gemm_f32_kernel(const TA *__restrict__ A, long sam, long sak,
-                                                       const TB *__restrict__ B, long sbk, long sbn, int M,
-                                                       int N, int K, float *__restrict__ C, int kslice)
+// ---------------------------------------------------------------- backward (FP32 MFMA)
+// C[Mo x No] = sum_k A(mo, k) B(k, no) over k in [z kslice, (z + 1) kslice),
+// into C + z Mo No (split K; the slices are summed by sum_slices_kernel).
+// A is FP32 with element strides (sam, sak), B FP16 or FP32 with strides
+// (sbk, sbn).  FP32 products and accumulation on v_mfma_f32_16x16x4_f32
+// (lane l: A row l % 16 and B column l % 16 at k = l / 16; result rows
+// 4 (l / 16) + i, column l % 16).  Workgroup: a 64 x 64 tile, 4 waves of
+// 2 x 2 MFMA tiles (wave w: rows 32 (w / 2) .., columns 32 (w % 2) ..); K
+// staged through LDS in chunks of 32 as FP32, rows of kBkLd floats so that
+// the four k rows a wave reads at once fall in distinct banks.  Staging
+// walks whichever operand index has unit stride fastest (coalesced loads).
+constexpr int kBkK = 32, kBkLd = 80, kBkPer = kBkK * 64 / 256;
+
+template <typename TB>
+__global__ void __launch_bounds__(256) gemm_mfma32_kernel(const float *__restrict__ A, long sam, long sak,
+                                                          const TB *__restrict__ B, long sbk, long sbn, int Mo,
+                                                          int No, int K, float *__restrict__ C, int kslice)
 {
-    __shared__ float As[16][64 + 1];
-    __shared__ float Bs[16][64 + 1];
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    __shared__ float As[kBkK][kBkLd];
+    __shared__ float Bs[kBkK][kBkLd];
+    const int t = threadIdx.x, wave = t / 64, lane = t % 64;
     const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
     const int kb = blockIdx.z * kslice, ke = min(K, kb + kslice);
-    C += (long)blockIdx.z * M * N;
-    float acc[4][4] = {};
-    for (int k0 = kb; k0 < ke; k0 += 16) {
-        for (int i = threadIdx.x; i < 16 * 64; i += 256) {
-            const int kk = i / 64, mm = i % 64;
-            const int gm = m0 + mm, gk = k0 + kk;
-            As[kk][mm] = (gm < M && gk < ke) ? (float)A[gm * sam + gk * sak] : 0.f;
-            const int gn = n0 + mm;
-            Bs[kk][mm] = (gn < N && gk < ke) ? (float)B[gk * sbk + gn * sbn] : 0.f;
+    C += (long)blockIdx.z * Mo * No;
+    const int wm = 32 * (wave / 2), wn = 32 * (wave % 2);
+    const int r16 = lane % 16, kq = lane / 16;
+    // staging slots of this thread: (k, m) of A and (k, n) of B for each of
+    // kBkPer values, the unit-stride index running fastest
+    int ka[kBkPer], ma[kBkPer], kbs[kBkPer], nb[kBkPer];
+#pragma unroll
+    for (int r = 0; r < kBkPer; ++r) {
+        const int i = t + r * 256;
+        ka[r] = sak == 1 ? i % kBkK : i / 64;
+        ma[r] = sak == 1 ? i / kBkK : i % 64;
+        kbs[r] = sbk == 1 ? i % kBkK : i / 64;
+        nb[r] = sbk == 1 ? i / kBkK : i % 64;
+    }
+    float ra[kBkPer], rb[kBkPer];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < kBkPer; ++r) {
+            const int gm = m0 + ma[r], gka = k0 + ka[r];
+            ra[r] = (gm < Mo && gka < ke) ? A[gm * sam + gka * sak] : 0.f;
+            const int gn = n0 + nb[r], gkb = k0 + kbs[r];
+            rb[r] = (gn < No && gkb < ke) ? (float)B[gkb * sbk + gn * sbn] : 0.f;
+        }
+    };
+    float4v acc[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = float4v{0.f, 0.f, 0.f, 0.f};
+    load(kb);
+    for (int k0 = kb; k0 < ke; k0 += kBkK) {
+        __syncthreads();   // the previous chunk has been read
+#pragma unroll
+        for (int r = 0; r < kBkPer; ++r) {
+            As[ka[r]][ma[r]] = ra[r];
+            Bs[kbs[r]][nb[r]] = rb[r];
         }
         __syncthreads();
+        if (k0 + kBkK < ke) load(k0 + kBkK);   // next chunk in flight during the products
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            float a[4], bb[4];
+        for (int kk = 0; kk < kBkK; kk += 4) {
+            float a[2], b[2];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) { a[i] = As[kk][ty * 4 + i]; bb[i] = Bs[kk][tx * 4 + i]; }
+            for (int x = 0; x < 2; ++x) {
+                a[x] = As[kk + kq][wm + 16 * x + r16];
+                b[x] = Bs[kk + kq][wn + 16 * x + r16];
+            }
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int x = 0; x < 2; ++x)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * bb[j];
+                for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x], b[y], acc[x][y], 0, 0, 0);
         }
-        __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int gm = m0 + ty * 4 + i, gn = n0 + tx * 4 + j;
-            if (gm < M && gn < N) C[(long)gm * N + gn] = acc[i][j];
-        }
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = m0 + wm + 16 * x + 4 * kq + i, col = n0 + wn + 16 * y + r16;
+                if (row < Mo && col < No) C[(long)row * No + col] = acc[x][y][i];
+            }
 }
 
 // out[i] = sum_z P[z][i], z = 0 .. slices-1 in order (deterministic)
@@ -619,26 +659,24 @@ __global__ void sum_slices_kernel(const float *__restrict__ P, int slices, long 
     }
 }
 
-// column sums: out[n] = sum_m X[m][n].  Workgroup of 256 threads = 16
-// columns x 16 row phases (coalesced 64-byte row segments); the 16 partial
-// sums of a column are added in a fixed order, so the result is
-// deterministic.
-__global__ void __launch_bounds__(256) colsum_kernel(const float *__restrict__ X, int M, int N,
-                                                     float *__restrict__ out)
+// column sums of X [M][N] over row chunks of kMlpColRows: part[c][n] = sum over
+// rows m of chunk c of X[m][n].  Workgroup of 256 threads = 64 columns x 4
+// row phases (coalesced 256-byte row segments); the 4 phase sums of a column
+// are added in a fixed order, and sum_slices_kernel adds the chunks in
+// order, so the result is deterministic.
+__global__ void __launch_bounds__(256) colsum_part_kernel(const float *__restrict__ X, int M, int N,
+                                                          float *__restrict__ part)
 {
-    __shared__ float part[16][17];
-    const int c = threadIdx.x % 16, r = threadIdx.x / 16;
-    const int n = blockIdx.x * 16 + c;
+    __shared__ float ph[4][64];
+    const int c = threadIdx.x % 64, r = threadIdx.x / 64;
+    const int n = blockIdx.x * 64 + c;
+    const int m0 = blockIdx.y * kMlpColRows, m1 = min(M, m0 + kMlpColRows);
     float s = 0.f;
     if (n < N)
-        for (int m = r; m < M; m += 16) s += X[(long)m * N + n];
-    part[r][c] = s;
+        for (int m = m0 + r; m < m1; m += 4) s += X[(long)m * N + n];
+    ph[r][c] = s;
     __syncthreads();
-    if (r == 0 && n < N) {
-        float t = 0.f;
-        for (int i = 0; i < 16; ++i) t += part[i][c];
-        out[n] = t;
-    }
+    if (r == 0 && n < N) part[(long)blockIdx.y * N + n] = ((ph[0][c] + ph[1][c]) + ph[2][c]) + ph[3][c];
 }
 
 // dY = 2 (Y - T) / (M N), loss partials per block
@@ -661,13 +699,16 @@ __global__ void mse_grad_kernel(const float *__restrict__ Y, const float *__rest
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-__global__ void sum_kernel(const float *__restrict__ part, int n, float scale, float *__restrict__ out)
+// *out = scale * sum of part[0 .. n): one wave, lane l the entries l, l + 64,
+// ... in order, then a fixed butterfly
+__global__ void __launch_bounds__(64) sum_kernel(const float *__restrict__ part, int n, float scale,
+                                                 float *__restrict__ out)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        float s = 0.f;
-        for (int i = 0; i < n; ++i) s += part[i];
-        *out = s * scale;
-    }
+    float s = 0.f;
+    for (int i = threadIdx.x; i < n; i += 64) s += part[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (threadIdx.x == 0) *out = s * scale;
 }
 
 // dZ = dH * SiLU'(Z),  SiLU'(z) = sig(z) (1 + z (1 - sig(z)))
@@ -770,10 +811,19 @@ static void weight_grad(const float *A, long lda, const TB *B, long ldb, int Mo,
     if (slices > kMlpSlices) slices = kMlpSlices;
     if (slices < 1) slices = 1;
     const int kslice = (K + slices - 1) / slices;
-    hipLaunchKernelGGL((gemm_f32_kernel<float, TB>), dim3((No + 63) / 64, (Mo + 63) / 64, slices), dim3(256), 0, s,
+    hipLaunchKernelGGL((gemm_mfma32_kernel<TB>), dim3((No + 63) / 64, (Mo + 63) / 64, slices), dim3(256), 0, s,
                        A, 1L, lda, B, ldb, 1L, Mo, No, K, part, kslice);
     const long n = (long)Mo * No;
     hipLaunchKernelGGL(sum_slices_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, part, slices, n, G);
+}
+
+// out[n] = sum over the M rows of X[m][n], through row-chunk partials in part
+static void column_sums(const float *X, int M, int N, float *out, float *part, hipStream_t s)
+{
+    const int chunks = (M + kMlpColRows - 1) / kMlpColRows;
+    hipLaunchKernelGGL(colsum_part_kernel, dim3((N + 63) / 64, chunks), dim3(256), 0, s, X, M, N, part);
+    const long n = N;
+    hipLaunchKernelGGL(sum_slices_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, part, chunks, n, out);
 }
 
 hipError_t mlp_backward(const MlpNet &net, int M, const void *X, const float *dY, hipStream_t s)
@@ -785,21 +835,21 @@ hipError_t mlp_backward(const MlpNet &net, int M, const void *X, const float *dY
     weight_grad(dY, (long)kMlpOut, Xh, (long)kMlpIn, kMlpOut, kMlpIn, M, net.gw[3], net.part_k, s);
     // layer 3: dW3 = dY^T H2 [256 x 256], db3 = sum dY, dH2 = dY W3 [M x 256]
     weight_grad(dY, (long)kMlpOut, H2, (long)kMlpHid, kMlpOut, kMlpHid, M, net.gw[2], net.part_k, s);
-    hipLaunchKernelGGL(colsum_kernel, dim3((kMlpOut + 15) / 16), blk, 0, s, dY, M, kMlpOut, net.gb[2]);
-    hipLaunchKernelGGL((gemm_f32_kernel<float, _Float16>), dim3(kMlpHid / 64, M / 64, 1), blk, 0, s, dY,
+    column_sums(dY, M, kMlpOut, net.gb[2], net.part_k, s);
+    hipLaunchKernelGGL((gemm_mfma32_kernel<_Float16>), dim3(kMlpHid / 64, M / 64, 1), blk, 0, s, dY,
                        (long)kMlpOut, 1L, W3, (long)kMlpHid, 1L, M, kMlpHid, kMlpOut, net.dH, kMlpOut);
     hipLaunchKernelGGL(silu_back_kernel, dim3(grid_for((long)M * kMlpHid, 256)), blk, 0, s, net.dH, net.Z2,
                        (long)M * kMlpHid, net.dZ);
     // layer 2
     weight_grad(net.dZ, (long)kMlpHid, H1, (long)kMlpHid, kMlpHid, kMlpHid, M, net.gw[1], net.part_k, s);
-    hipLaunchKernelGGL(colsum_kernel, dim3((kMlpHid + 15) / 16), blk, 0, s, net.dZ, M, kMlpHid, net.gb[1]);
-    hipLaunchKernelGGL((gemm_f32_kernel<float, _Float16>), dim3(kMlpHid / 64, M / 64, 1), blk, 0, s, net.dZ,
+    column_sums(net.dZ, M, kMlpHid, net.gb[1], net.part_k, s);
+    hipLaunchKernelGGL((gemm_mfma32_kernel<_Float16>), dim3(kMlpHid / 64, M / 64, 1), blk, 0, s, net.dZ,
                        (long)kMlpHid, 1L, W2, (long)kMlpHid, 1L, M, kMlpHid, kMlpHid, net.dH, kMlpHid);
     hipLaunchKernelGGL(silu_back_kernel, dim3(grid_for((long)M * kMlpHid, 256)), blk, 0, s, net.dH, net.Z1,
                        (long)M * kMlpHid, net.dZ);
     // layer 1: dW1 = dZ1^T X [256 x K0]
     weight_grad(net.dZ, (long)kMlpHid, Xh, (long)kMlpIn, kMlpHid, kMlpIn, M, net.gw[0], net.part_k, s);
-    hipLaunchKernelGGL(colsum_kernel, dim3((kMlpHid + 15) / 16), blk, 0, s, net.dZ, M, kMlpHid, net.gb[0]);
+    column_sums(net.dZ, M, kMlpHid, net.gb[0], net.part_k, s);
     return hipGetLastError();
 }
 

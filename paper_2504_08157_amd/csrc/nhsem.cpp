@@ -1453,7 +1453,10 @@ MlpLayout mlp_layout(long B)
     L.acts[7] = take(sizeof(float) * 4);               // loss
     L.acts[8] = take(sizeof(uint16_t) * B * kMlpHid);  // H1
     L.acts[9] = take(sizeof(uint16_t) * B * kMlpHid);  // H2
-    L.acts[10] = take(sizeof(float) * kMlpSlices * kMlpOut * kMlpIn);  // split-K partials
+    // split-K partials of the weight gradients, and the row-chunk partials
+    // of the bias gradients
+    const size_t colsum_part = (size_t)((B + kMlpColRows - 1) / kMlpColRows) * kMlpOut;
+    L.acts[10] = take(sizeof(float) * std::max<size_t>((size_t)kMlpSlices * kMlpOut * kMlpIn, colsum_part));
     L.feat = take(sizeof(uint16_t) * B * kMlpIn);
     L.scale = take(sizeof(double) * B);
     L.total = off;
