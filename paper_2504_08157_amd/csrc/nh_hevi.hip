@@ -38,9 +38,8 @@ namespace nh {
 // the (zero) u and v rows are not written.
 template <int N>
 __global__ void __launch_bounds__(256) lv_apply_kernel(HeviParams h, const double *__restrict__ x,
-                                                       double *__restrict__ y, bool uv, const int *gate)
+                                                       double *__restrict__ y, bool uv)
 {
-    if (gate && *gate == 0) return;
     constexpr int NC = 2 * N + 1;
     const long nxy = (long)h.nx * h.ny;
     const long col = blockIdx.x * 256L + threadIdx.x;
@@ -1043,18 +1042,17 @@ size_t gmres_lds_bytes(int nz, int N, int restart)
     return n * sizeof(double);
 }
 
-hipError_t launch_lv_apply(const HeviParams &h, const double *x, double *y, hipStream_t s, bool uv,
-                           const int *gate)
+hipError_t launch_lv_apply(const HeviParams &h, const double *x, double *y, hipStream_t s, bool uv)
 {
     const long nxy = (long)h.nx * h.ny;
     const dim3 grid((unsigned)((nxy + 255) / 256)), blk(256);
     switch (h.N) {
-    case 1: hipLaunchKernelGGL(lv_apply_kernel<1>, grid, blk, 0, s, h, x, y, uv, gate); break;
-    case 2: hipLaunchKernelGGL(lv_apply_kernel<2>, grid, blk, 0, s, h, x, y, uv, gate); break;
-    case 3: hipLaunchKernelGGL(lv_apply_kernel<3>, grid, blk, 0, s, h, x, y, uv, gate); break;
-    case 4: hipLaunchKernelGGL(lv_apply_kernel<4>, grid, blk, 0, s, h, x, y, uv, gate); break;
-    case 5: hipLaunchKernelGGL(lv_apply_kernel<5>, grid, blk, 0, s, h, x, y, uv, gate); break;
-    case 6: hipLaunchKernelGGL(lv_apply_kernel<6>, grid, blk, 0, s, h, x, y, uv, gate); break;
+    case 1: hipLaunchKernelGGL(lv_apply_kernel<1>, grid, blk, 0, s, h, x, y, uv); break;
+    case 2: hipLaunchKernelGGL(lv_apply_kernel<2>, grid, blk, 0, s, h, x, y, uv); break;
+    case 3: hipLaunchKernelGGL(lv_apply_kernel<3>, grid, blk, 0, s, h, x, y, uv); break;
+    case 4: hipLaunchKernelGGL(lv_apply_kernel<4>, grid, blk, 0, s, h, x, y, uv); break;
+    case 5: hipLaunchKernelGGL(lv_apply_kernel<5>, grid, blk, 0, s, h, x, y, uv); break;
+    case 6: hipLaunchKernelGGL(lv_apply_kernel<6>, grid, blk, 0, s, h, x, y, uv); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -23,16 +23,20 @@
 
 namespace nh {
 
-// out[f] = a x[f] + c (lv[f] + horizontal and damping terms of L x) at every
-// node, lv holding L_v x (u, v rows zero; lv may alias out, x may not).
-// Walls: u rows zero at x walls, v rows at y walls, w rows at the bottom and
-// top.  A workgroup of 64 x 8 lattice columns walks a chunk of kL3KZ levels, staging per level the planes of u, v and p'_L of
-// its tile plus an N-wide x/y halo in LDS (two buffers, one barrier per
-// level); the x and y taps come from LDS, the node's own rho', w, theta' and
-// L_v rows from coalesced loads.  All loads of a level are issued two levels
-// ahead into register slots indexed at compile time.  Chunks of levels give
-// enough workgroups on meshes of few columns.
-constexpr int kL3TX = 64, kL3TY = 8, kL3KZ = 8, kL3P = 2;
+// out[f] = a x[f] + c (L x)[f] at every node, all of L in one walk (out may
+// not alias x).  Walls: u rows zero at x walls, v rows at y walls, w rows at
+// the bottom and top.  A workgroup of 64 x 8 lattice columns walks a chunk
+// of kL3KZ levels.  Per level it stages the planes of u, v and p'_L of its
+// tile plus an N-wide x/y halo in LDS (two buffers, one barrier per level)
+// for the x and y taps; the vertical part (L_v) comes from a (2N+1)-level
+// window of rho0 w and p'_L of the thread's own column in registers, filled
+// with the N levels below the chunk and the N levels above each level as
+// the walk goes (taps outside the column see zero inputs), as in the
+// column-walking L_v kernel.  All loads of a level, the window's lead level
+// included, are issued two levels ahead into register slots indexed at
+// compile time.  Chunks of levels give enough workgroups on meshes of few
+// columns.
+constexpr int kL3TX = 64, kL3TY = 8, kL3KZ = 16, kL3P = 2;
 
 __device__ __forceinline__ int l3_xcd_block(int b, int n)
 {
@@ -49,12 +53,13 @@ __device__ __forceinline__ void l3_unrolled(F &&f)
     }
 }
 
-// (lev is h.lev passed again as a restrict pointer so that its per-level
-// values are read with scalar loads)
+// (lev and gz are h.lev and h.hv.gz passed again as restrict pointers so
+// that their per-level values are read with scalar loads)
 template <int N>
 __global__ void __launch_bounds__(kL3TX * kL3TY) l3_tile_kernel(L3Params h, const double *__restrict__ x,
-                                                                const double *lv, double *out, double a, double c,
-                                                                const double *__restrict__ lev, const int *gate)
+                                                                double *out, double a, double c,
+                                                                const double *__restrict__ lev,
+                                                                const double *__restrict__ gz, const int *gate)
 {
     if (gate && *gate == 0) return;
     constexpr int NC = 2 * N + 1, PX = kL3TX + 2 * N, PY = kL3TY + 2 * N, PS = PX * PY;
@@ -72,6 +77,7 @@ __global__ void __launch_bounds__(kL3TX * kL3TY) l3_tile_kernel(L3Params h, cons
     const int ix = x0 + tx, iy = y0 + ty;
     const bool own = ix < h.nx && iy < h.ny;
     const long col = own ? ix + (long)iy * h.nx : 0;
+    const double gamma = h.gamma, grav = h.hv.g;
     double cx[NC], cy[NC];
 #pragma unroll
     for (int o = 0; o < NC; ++o) {
@@ -97,9 +103,24 @@ __global__ void __launch_bounds__(kL3TX * kL3TY) l3_tile_kernel(L3Params h, cons
         sc[i] = ok ? jx + (long)jy * h.nx : 0;
     }
     auto level = [&](int k) -> long { return (long)(k < ke ? k : ke - 1) * nxy; };
+    // rho0 w and p'_L of the own column at level kk (zero outside the column)
+    auto vert = [&](int kk, double r, double w, double th, double &va, double &vb) {
+        const double *L = lev + (long)(kk < 0 ? 0 : kk < nz ? kk : nz - 1) * kLevW;
+        const bool in = kk >= 0 && kk < nz;
+        va = in ? L[0] * w : 0.0;
+        vb = in ? gamma * L[2] * (r * L[7] + th * L[8]) : 0.0;
+    };
+    // the vertical window: slots o = 0 .. 2N hold levels k - N + o
+    double ta[NC], tb[NC];
+#pragma unroll
+    for (int o = 0; o < 2 * N; ++o) {
+        const int kk = kb - N + o;
+        const long L = (long)(kk < 0 ? 0 : kk < nz ? kk : nz - 1) * nxy;
+        vert(kk, x[col + L], x[3 * U + col + L], x[4 * U + col + L], ta[o], tb[o]);
+    }
     // slot contents: staged rho', u, v, theta' of NS nodes; own rho', w,
-    // theta' of x and of L_v x
-    double sr[P][NS], su[P][NS], sv2[P][NS], st[P][NS], ox[P][3], ol[P][3];
+    // theta' of x at the level and at the window's lead level (level + N)
+    double sr[P][NS], su[P][NS], sv2[P][NS], st[P][NS], ox[P][3], oz[P][3];
     auto load = [&](int p, int k) {
         const long L = level(k);
 #pragma unroll
@@ -112,9 +133,11 @@ __global__ void __launch_bounds__(kL3TX * kL3TY) l3_tile_kernel(L3Params h, cons
         ox[p][0] = x[col + L];
         ox[p][1] = x[3 * U + col + L];
         ox[p][2] = x[4 * U + col + L];
-        ol[p][0] = lv[col + L];
-        ol[p][1] = lv[3 * U + col + L];
-        ol[p][2] = lv[4 * U + col + L];
+        const int kz = k + N;
+        const long Z = (long)(kz < nz ? kz : nz - 1) * nxy;
+        oz[p][0] = x[col + Z];
+        oz[p][1] = x[3 * U + col + Z];
+        oz[p][2] = x[4 * U + col + Z];
     };
     l3_unrolled<0, P>([&](auto J) { load(decltype(J)::value, kb + decltype(J)::value); });
     for (int k0 = kb; k0 < ke; k0 += P) {
@@ -122,8 +145,8 @@ __global__ void __launch_bounds__(kL3TX * kL3TY) l3_tile_kernel(L3Params h, cons
             constexpr int j = decltype(J)::value;
             const int k = k0 + j;
             const double *Lv = lev + level(k) / nxy * kLevW;
-            const double rho0 = Lv[0], p0 = Lv[2], tau = Lv[4], irho0 = Lv[7], ith0 = Lv[8];
-            const double gp = h.gamma * p0;
+            const double rho0 = Lv[0], p0 = Lv[2], dth0 = Lv[3], tau = Lv[4], irho0 = Lv[7], ith0 = Lv[8];
+            const double gp = gamma * p0;
             double(*T)[PS] = tile[(k - kb) & 1];
 #pragma unroll
             for (int i = 0; i < NS; ++i) {
@@ -135,8 +158,21 @@ __global__ void __launch_bounds__(kL3TX * kL3TY) l3_tile_kernel(L3Params h, cons
                 }
             }
             const double xr = ox[j][0], xw = ox[j][1], xt = ox[j][2];
-            const double lr = ol[j][0], lw = ol[j][1], lt = ol[j][2];
+            vert(k + N, oz[j][0], oz[j][1], oz[j][2], ta[2 * N], tb[2 * N]);
             load(j, k + P);
+            // vertical part at level k
+            const double *G = gz + (long)(k < ke ? k : ke - 1) * NC;
+            double d_rw = 0.0, d_pl = 0.0;
+#pragma unroll
+            for (int o = 0; o < NC; ++o) {
+                d_rw += G[o] * ta[o];
+                d_pl += G[o] * tb[o];
+            }
+#pragma unroll
+            for (int o = 0; o < 2 * N; ++o) {
+                ta[o] = ta[o + 1];
+                tb[o] = tb[o + 1];
+            }
             __syncthreads();
             double dux = 0.0, dpx = 0.0, dvy = 0.0, dpy = 0.0;
 #pragma unroll
@@ -149,9 +185,10 @@ __global__ void __launch_bounds__(kL3TX * kL3TY) l3_tile_kernel(L3Params h, cons
             }
             const int jo = (ty + N) * PX + tx + N;
             const double xu = T[0][jo], xv = T[1][jo];
-            double Lr = lr - rho0 * (dux + dvy);
+            double Lr = -d_rw - rho0 * (dux + dvy);
             double Lu = -irho0 * dpx, Lvv = -irho0 * dpy;
-            double Lw = lw - tau * xw;
+            double Lw = -d_pl * irho0 - grav * xr * irho0 - tau * xw;
+            const double Lt = -xw * dth0;
             if (!h.perx && (ix == 0 || ix == h.nx - 1)) Lu = 0.0;
             if (!h.pery && (iy == 0 || iy == h.ny - 1)) Lvv = 0.0;
             if (k == 0 || k == nz - 1) Lw = 0.0;
@@ -161,7 +198,7 @@ __global__ void __launch_bounds__(kL3TX * kL3TY) l3_tile_kernel(L3Params h, cons
                 out[U + I] = a * xu + c * Lu;
                 out[2 * U + I] = a * xv + c * Lvv;
                 out[3 * U + I] = a * xw + c * Lw;
-                out[4 * U + I] = a * xt + c * lt;
+                out[4 * U + I] = a * xt + c * Lt;
             }
         });
     }
@@ -170,22 +207,19 @@ __global__ void __launch_bounds__(kL3TX * kL3TY) l3_tile_kernel(L3Params h, cons
 hipError_t launch_l3(const L3Params &h, const double *x, double *out, double a, double c, hipStream_t s,
                      const int *gate)
 {
-    hipError_t e = launch_lv_apply(h.hv, x, out, s, true, gate);
-    if (e != hipSuccess) return e;
     const int ntx = (h.nx + kL3TX - 1) / kL3TX, nty = (h.ny + kL3TY - 1) / kL3TY;
     const int nkc = (h.nz + kL3KZ - 1) / kL3KZ;
     const dim3 grid((unsigned)(ntx * nty * nkc)), blk(kL3TX * kL3TY);
     switch (h.N) {
-    case 2: hipLaunchKernelGGL(l3_tile_kernel<2>, grid, blk, 0, s, h, x, (const double *)out, out, a, c, h.lev, gate); break;
-    case 3: hipLaunchKernelGGL(l3_tile_kernel<3>, grid, blk, 0, s, h, x, (const double *)out, out, a, c, h.lev, gate); break;
-    case 4: hipLaunchKernelGGL(l3_tile_kernel<4>, grid, blk, 0, s, h, x, (const double *)out, out, a, c, h.lev, gate); break;
-    case 5: hipLaunchKernelGGL(l3_tile_kernel<5>, grid, blk, 0, s, h, x, (const double *)out, out, a, c, h.lev, gate); break;
-    case 6: hipLaunchKernelGGL(l3_tile_kernel<6>, grid, blk, 0, s, h, x, (const double *)out, out, a, c, h.lev, gate); break;
+    case 2: hipLaunchKernelGGL(l3_tile_kernel<2>, grid, blk, 0, s, h, x, out, a, c, h.lev, h.hv.gz, gate); break;
+    case 3: hipLaunchKernelGGL(l3_tile_kernel<3>, grid, blk, 0, s, h, x, out, a, c, h.lev, h.hv.gz, gate); break;
+    case 4: hipLaunchKernelGGL(l3_tile_kernel<4>, grid, blk, 0, s, h, x, out, a, c, h.lev, h.hv.gz, gate); break;
+    case 5: hipLaunchKernelGGL(l3_tile_kernel<5>, grid, blk, 0, s, h, x, out, a, c, h.lev, h.hv.gz, gate); break;
+    case 6: hipLaunchKernelGGL(l3_tile_kernel<6>, grid, blk, 0, s, h, x, out, a, c, h.lev, h.hv.gz, gate); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
-
 
 // ---- Krylov kernels on n-vectors.  Dot products are summed per block into
 // quantity-major partials, then by one workgroup in a fixed order: the same
