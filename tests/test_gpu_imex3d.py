@@ -114,6 +114,20 @@ def test_degenerate_and_errors(oracle_mod):
     assert st.not_converged == 1
 
 
+@pytest.mark.parametrize("pc", [False, True], ids=["plain", "column_preconditioned"])
+def test_global_solve_breakdown_and_second_pass(oracle_mod, pc):
+    """alpha = 0 from a zero start: A = I, so the first new direction lies in
+    the span of V_0 -- the first Gram-Schmidt pass keeps nothing, the second
+    pass runs, the kept norm is (numerically) zero and the process stops
+    after one Arnoldi step with x = b to rounding."""
+    import torch
+    ctx, orc, q = _pair(oracle_mod, *MESHES["periodic_N3"])
+    b = torch.from_numpy(q).cuda()
+    x, st = ctx.nh_global_solve(0.0, b, x0=torch.zeros_like(b), restart=5, rtol=1e-12, precondition=pc)
+    assert st.iters_total == 1 and st.not_converged == 0
+    assert _rel(x.cpu().numpy(), q) <= 1e-14
+
+
 def test_full_size_hevi_case(oracle_mod):
     """The 96 x 96 x 16 element (N = 4) case the 3D-IMEX benchmark runs: the
     operator against the oracle's on the whole lattice (a smooth random
