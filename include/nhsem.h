@@ -480,7 +480,8 @@ nh_status nh_mlp_set_params(nh_mlp *m, const float *dev_master);
 /* Training samples / features for columns [col0, col0 + ncol) of ctx: the
    right-hand side b of (I - alpha L_v) x = b and, if dev_x is given, the
    solution x.  dev_feat FP16 [ncol][400], dev_scale double [ncol] (the
-   column scale), dev_tgt float [ncol][256] (the scaled dimensionless
+   column scale: RMS of the dimensionless alpha L_v b), dev_tgt float
+   [ncol][256] (the scaled dimensionless
    correction x - b on the 65 canonical levels per field, zero past 195;
    needs dev_x), dev_tmp device [5][U] scratch. */
 nh_status nh_mlp_samples(nh_mlp *m, nh_ctx *ctx, double alpha, const double *dev_b, const double *dev_x,
@@ -488,8 +489,9 @@ nh_status nh_mlp_samples(nh_mlp *m, nh_ctx *ctx, double alpha, const double *dev
                          double *dev_tmp);
 
 /* The initial guess x0 of (I - alpha L_v) x = b in every column of ctx, as
-   used by nh_hevi_step: features of b and alpha L_v b, the network, and
-   x0 = b + D s (output resampled to the lattice levels), the w correction
+   used by nh_hevi_step: features of the default start's residual
+   alpha L_v b (dimensionless, divided by its column RMS s), the network,
+   and x0 = b + D s (output resampled to the lattice levels), the w correction
    zero on the walls and a non-finite prediction replaced by x0 = b.
    dev_b device [5][U] (fields rho', w, theta' are used), dev_tmp device
    [5][U] scratch (receives L_v b in fields 0, 3, 4), dev_x0 device [3][U]

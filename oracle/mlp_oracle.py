@@ -10,8 +10,12 @@ library (the learned-guess design is this project's own; the paper has no
 learned part):
   * fields (rho', w, theta') are made dimensionless level by level with the
     reference state: rho'/rho0, w/c0 (c0 = sqrt(gamma p0 / rho0)), theta'/theta0;
-  * one scale per column, s = RMS over the column's 3 n_z values of the
-    dimensionless b and alpha L_v b together;
+  * the default start x0 = b leaves the residual r = b - (I - alpha L_v) b
+    = alpha L_v b, and the exact correction is x - b = (I - alpha L_v)^-1 r:
+    a linear function of r alone.  The features are r (dimensionless)
+    divided by one scale per column, s = RMS of the dimensionless r over the
+    column's 3 n_z values, so that the correction is predicted relative to
+    its own size and not to the size of b;
   * the canonical column is the 65 LGL nodes of 16 equal order-4 elements
     on the normalised height (z - z_0) / H; lattice data are resampled to it
     linearly in z, and the predicted correction back to the lattice levels
@@ -113,18 +117,19 @@ def dimension_factors(rho0, p0, theta0, gamma):
 def column_features(b, lb, z, alpha, D):
     """b, lb: arrays [3][n_z][ncol] of (rho', w, theta') of the right-hand
     side and of L_v b; z: lattice levels; D: dimension factors [3][n_z].
-    Returns features [ncol][400] and the column scales s [ncol]."""
+    Returns features [ncol][400] and the column scales s [ncol]: the
+    dimensionless residual alpha L_v b / (D s) of the default start on the
+    canonical levels (entries 0 .. 194), zeros (195 .. 389), then the scalars
+    log10 s / 10, alpha / 10, 100 alpha c0(z_0) / H, log10 H / 5."""
     nz, ncol = b.shape[1], b.shape[2]
-    bh = b / D[:, :, None]
     lh = alpha * lb / D[:, :, None]
-    s = np.sqrt(((bh ** 2).sum(axis=(0, 1)) + (lh ** 2).sum(axis=(0, 1))) / (3 * nz)) + 1e-300
+    s = np.sqrt((lh ** 2).sum(axis=(0, 1)) / (3 * nz)) + 1e-300
     H = z[-1] - z[0]
     zc = z[0] + H * canonical_levels()
     feat = np.zeros((ncol, IN))
     for f in range(3):
         for c in range(ncol):
-            feat[c, f * NC:(f + 1) * NC] = np.interp(zc, z, bh[f, :, c]) / s[c]
-            feat[c, NF + f * NC:NF + (f + 1) * NC] = np.interp(zc, z, lh[f, :, c]) / s[c]
+            feat[c, f * NC:(f + 1) * NC] = np.interp(zc, z, lh[f, :, c]) / s[c]
     feat[:, 2 * NF] = np.log10(s) / 10.0
     feat[:, 2 * NF + 1] = alpha / 10.0
     feat[:, 2 * NF + 2] = 100.0 * alpha * D[1, 0] / H

@@ -8,13 +8,16 @@
 // correction is linear for a fixed column grid and alpha ((I - alpha L_v)^-1
 // - I), the hidden layers carry its dependence on those.
 // Features of a column with right-hand side b (fields rho', w, theta' on the
-// n_z lattice levels): the fields are made dimensionless level by level
+// n_z lattice levels): the default start x0 = b leaves the residual
+// r = alpha L_v b, and the exact correction x - b = (I - alpha L_v)^-1 r is a
+// linear function of r alone.  r is made dimensionless level by level
 // (rho'/rho0, w/c0 with c0 = sqrt(gamma p0 / rho0), theta'/theta0), divided
-// by one column scale s (RMS of the dimensionless b and alpha L_v b over the
-// column's 3 n_z values) and resampled linearly in z to the 65 canonical
-// levels (LGL nodes of 16 equal order-4 elements of the column), for b and
-// for alpha L_v b (the first Neumann term of (I - alpha L_v)^-1); then 4
-// scalars (log10 s / 10, alpha / 10, 100 alpha c0(z_0) / H, log10 H / 5).
+// by one column scale s (RMS of the dimensionless r over the column's 3 n_z
+// values) and resampled linearly in z to the 65 canonical levels (LGL nodes
+// of 16 equal order-4 elements of the column): features 0 .. 194; 195 .. 389
+// are zero; then 4 scalars (log10 s / 10, alpha / 10, 100 alpha c0(z_0) / H,
+// log10 H / 5).  The correction is thus predicted relative to its own size,
+// not to the size of b.
 // Output: the dimensionless correction on the canonical levels,
 // x0 = b + D s resample^-1(y), with the w correction zero on the walls.
 #include "nh_internal.h"
@@ -85,17 +88,15 @@ __global__ void __launch_bounds__(512) mlp_features_kernel(MlpColParams p, const
     const long r = r0 + lane;
     const bool ok = r < ncol;
     const long col = col0 + (ok ? r : 0);
-    // s = RMS over the column of the dimensionless b and alpha L_v b
+    // s = RMS over the column of the dimensionless residual alpha L_v b
     double a = 0.0;
 #pragma unroll 4
     for (int k = q; k < nz; k += NWV) {
         const long I = col + (long)k * nxy;
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
-            const double d = sdinv[f * nz + k];
-            const double v = b[fld[f] * U + I] * d;
-            const double l = p.alpha * lb[fld[f] * U + I] * d;
-            a += v * v + l * l;
+            const double l = p.alpha * lb[fld[f] * U + I] * sdinv[f * nz + k];
+            a += l * l;
         }
     }
     spart[q][lane] = a;
@@ -112,10 +113,9 @@ __global__ void __launch_bounds__(512) mlp_features_kernel(MlpColParams p, const
         for (int f = 0; f < 3; ++f) {
             const long I0 = fld[f] * U + col + (long)k0 * nxy, I1 = I0 + nxy;
             const double d0 = sdinv[f * nz + k0], d1 = sdinv[f * nz + k0 + 1];
-            const double vb = (1.0 - t) * (b[I0] * d0) + t * (b[I1] * d1);
             const double vl = (1.0 - t) * (p.alpha * lb[I0] * d0) + t * (p.alpha * lb[I1] * d1);
-            sf[lane][f * kMlpNC + c] = (_Float16)(vb / s);
-            sf[lane][kMlpNF + f * kMlpNC + c] = (_Float16)(vl / s);
+            sf[lane][f * kMlpNC + c] = (_Float16)(vl / s);
+            sf[lane][kMlpNF + f * kMlpNC + c] = (_Float16)0.0f;
             if (tgt && ok) {
                 const double vx = (1.0 - t) * ((x[I0] - b[I0]) * d0) + t * ((x[I1] - b[I1]) * d1);
                 tgt[r * kMlpOut + f * kMlpNC + c] = (float)(vx / s);
@@ -401,10 +401,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) m
             const long I = col + (long)k * nxy;
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
-                const double d = sdinv[f * nz + k];
-                const double v = b[fld[f] * U + I] * d;
-                const double l = p.alpha * lb[fld[f] * U + I] * d;
-                a += v * v + l * l;
+                const double l = p.alpha * lb[fld[f] * U + I] * sdinv[f * nz + k];
+                a += l * l;
             }
         }
         spart[q][lane] = a;
@@ -423,10 +421,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) m
         for (int f = 0; f < 3; ++f) {
             const long I0 = fld[f] * U + col + (long)k0 * nxy, I1 = I0 + nxy;
             const double d0 = sdinv[f * nz + k0], d1 = sdinv[f * nz + k0 + 1];
-            const double vb = (1.0 - t) * (b[I0] * d0) + t * (b[I1] * d1);
             const double vl = (1.0 - t) * (p.alpha * lb[I0] * d0) + t * (p.alpha * lb[I1] * d1);
-            fr[f * kMlpNC + c] = (_Float16)(vb / s);
-            fr[kMlpNF + f * kMlpNC + c] = (_Float16)(vl / s);
+            fr[f * kMlpNC + c] = (_Float16)(vl / s);
+            fr[kMlpNF + f * kMlpNC + c] = (_Float16)0.0f;
         }
     }
     if (q == 0) {

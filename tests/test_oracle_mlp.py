@@ -57,8 +57,9 @@ def _dims(nz, rho=1.2, c=340.0, th=300.0, gamma=1.4):
 
 
 def test_column_features_on_linear_profiles():
-    """Linear profiles survive the linear resampling exactly; the common
-    scale is the RMS of the dimensionless b and alpha L_v b together."""
+    """Linear profiles survive the linear resampling exactly; the scale is
+    the RMS of the dimensionless alpha L_v b (the default start's residual)
+    alone, b itself enters only the targets."""
     z = np.linspace(0, 1000.0, 17)
     ncol = 3
     D = _dims(17)
@@ -66,24 +67,26 @@ def test_column_features_on_linear_profiles():
     b = np.zeros((3, 17, ncol)); lb = np.zeros_like(b)
     for f in range(3):
         for c in range(ncol):
-            b[f, :, c] = D[f] * (f + 1) * (c + 1) * (1.0 + z / 1000.0)
-            lb[f, :, c] = -b[f, :, c]
+            b[f, :, c] = 1e3 * D[f] * (f + 1) * (c + 1) * (1.0 + z / 1000.0)
+            lb[f, :, c] = -1e-3 * b[f, :, c]
     feat, s = MO.column_features(b, lb, z, alpha=2.0, D=D)
     zc = MO.canonical_levels()
     prof = 1.0 + z / 1000.0
     for c in range(ncol):
-        # sum over fields of ((f+1)(c+1))^2 (1 + 4) mean(prof^2), over 3 n_z values
-        s_ref = np.sqrt(5.0 * (c + 1) ** 2 * (1 + 4 + 9) * (prof ** 2).mean() / 3.0)
+        # alpha L_v b / D = -2 (f+1)(c+1) prof: sum over fields of
+        # 4 ((f+1)(c+1))^2 mean(prof^2), over 3 n_z values
+        s_ref = np.sqrt(4.0 * (c + 1) ** 2 * (1 + 4 + 9) * (prof ** 2).mean() / 3.0)
         np.testing.assert_allclose(s[c], s_ref, rtol=1e-14)
         for f in range(3):
-            np.testing.assert_allclose(feat[c, f * 65:(f + 1) * 65], (f + 1) * (c + 1) * (1 + zc) / s_ref, rtol=1e-13)
-            np.testing.assert_allclose(feat[c, 195 + f * 65:195 + (f + 1) * 65],
-                                       -2.0 * (f + 1) * (c + 1) * (1 + zc) / s_ref, rtol=1e-13)
+            np.testing.assert_allclose(feat[c, f * 65:(f + 1) * 65], -2.0 * (f + 1) * (c + 1) * (1 + zc) / s_ref,
+                                       rtol=1e-13)
         np.testing.assert_allclose(feat[c, 390], np.log10(s_ref) / 10.0, rtol=1e-14)
+    assert np.all(feat[:, 195:390] == 0)
     assert np.all(feat[:, 394:] == 0) and np.allclose(feat[:, 391], 0.2)
     np.testing.assert_allclose(feat[:, 392], 100.0 * 2.0 * 340.0 / 1000.0, rtol=1e-14)
-    t = MO.column_targets(b, 2 * b, z, D, s)
-    np.testing.assert_allclose(t[:, :195], feat[:, :195], rtol=1e-13)
+    # x = b + 1e-3 b: the correction is 1e-3 b = -lb, i.e. -feat / alpha on the canonical levels
+    t = MO.column_targets(b, b - lb, z, D, s)
+    np.testing.assert_allclose(t[:, :195], -feat[:, :195] / 2.0, rtol=1e-13)
     assert np.all(t[:, 195:] == 0)
 
 
@@ -106,22 +109,60 @@ def test_column_guess_inverts_targets_on_the_canonical_grid():
 
 
 def test_column_features_bounded_when_a_field_vanishes():
-    """w = 0 in b (a state at rest in the vertical) while L_v b has a w
-    component: one common scale keeps every feature O(1) and the ratios
-    between the fields intact."""
+    """A residual with no w component and a tiny rho' one: one common scale
+    keeps every feature O(1) and the ratios between the fields intact; a
+    zero residual (b already the solution) gives zero features."""
     z = np.linspace(0, 1000.0, 17)
     D = _dims(17)
-    b = np.zeros((3, 17, 1)); lb = np.zeros_like(b)
-    b[0, :, 0] = 1e-3 * np.cos(z / 300.0)
-    b[2, :, 0] = 0.5 * np.sin(z / 200.0)
-    lb[1, :, 0] = 2e-3 * np.sin(z / 250.0)
+    b = np.zeros((3, 17, 2)); lb = np.zeros_like(b)
+    b[1, :, 0] = 3.0
+    lb[0, :, 0] = 1e-3 * np.cos(z / 300.0)
+    lb[2, :, 0] = 0.5 * np.sin(z / 200.0)
     feat, s = MO.column_features(b, lb, z, alpha=3.0, D=D)
     assert np.all(np.abs(feat[:, :390]) <= np.sqrt(3 * 17.0) + 1e-12)
-    # the dimensionless rho' and theta' blocks keep their true ratio
     k = 30
     np.testing.assert_allclose(feat[0, k] / feat[0, 2 * 65 + k],
-                               np.interp(MO.canonical_levels()[k] * 1000.0, z, b[0, :, 0] / D[0]) /
-                               np.interp(MO.canonical_levels()[k] * 1000.0, z, b[2, :, 0] / D[2]), rtol=1e-12)
+                               np.interp(MO.canonical_levels()[k] * 1000.0, z, lb[0, :, 0] / D[0]) /
+                               np.interp(MO.canonical_levels()[k] * 1000.0, z, lb[2, :, 0] / D[2]), rtol=1e-12)
+    assert np.all(feat[0, 65:130] == 0)
+    assert np.all(feat[1, :390] == 0) and np.all(np.isfinite(feat))
+
+
+def test_exact_targets_are_one_linear_map_of_the_features(oracle_mod):
+    """On a column grid equal to the canonical one (16 equal order-4
+    elements, so the resampling is the identity) the exact target of every
+    column is the same matrix applied to its features: the dimensionless
+    (I - alpha L_v)^-1, from the oracle's own L_v and LAPACK solves, for
+    right-hand sides of very different sizes and shapes."""
+    from paper_2504_08157_amd import workloads as W
+    ph = W.Physics(g=W.G)
+    mesh = W.MeshSpec((1, 1, 16), 4, W.uniform_edges(0, 40e3, 1), W.uniform_edges(0, 40e3, 1),
+                      W.uniform_edges(0, 20e3, 16), (True, True))
+    o = oracle_mod.Oracle(mesh, ph)
+    x, y, z = o.lattice_coords()
+    rho0, th0 = W.constant_n_reference(z)
+    o.set_reference(rho0, th0)
+    Lm = oracle_mod.column_matrix(o)
+    nz = o.nz
+    assert nz == 65
+    alpha = 2.0 * 0.29289321881345254
+    A = np.eye(3 * nz) - alpha * Lm
+    rng = np.random.default_rng(3)
+    ncol = 6
+    B = rng.normal(size=(3 * nz, ncol)) * np.logspace(-6, 3, ncol)[None, :]
+    B[nz] = B[2 * nz - 1] = 0.0          # w right-hand side zero on the walls
+    X = np.linalg.solve(A, B)
+    LB = Lm @ B
+    col = lambda M: M.reshape(3, nz, ncol)
+    # dimension factors: any positive per-level factors serve the identity
+    D = np.stack([rho0, np.full(nz, 340.0) * (1 + z / 4e4), th0])
+    feat, s = MO.column_features(col(B), col(LB), z, alpha, D)
+    T = MO.column_targets(col(B), col(X), z, D, s)
+    Dv = D.reshape(-1)
+    M = (np.linalg.inv(A) @ np.diag(Dv)) / Dv[:, None]     # D^-1 (I - alpha L)^-1 D
+    for c in range(ncol):
+        np.testing.assert_allclose(T[c, :195], M @ feat[c, :195], rtol=0,
+                                   atol=1e-10 * np.abs(T[c, :195]).max())
 
 
 def test_forward_closed_form():
