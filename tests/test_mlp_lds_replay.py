@@ -28,8 +28,8 @@ def test_source_holds_the_replayed_expressions():
               "constexpr int kRegBytes = 64 * kLdF * 2;",
               "_Float16 *fr = sf + lane * kLdF;",
               "for (int c = q; c < kMlpNC; c += NWV) {",
-              "fr[f * kMlpNC + c] = (_Float16)(vb / s);",
-              "fr[kMlpNF + f * kMlpNC + c] = (_Float16)(vl / s);",
+              "fr[f * kMlpNC + c] = (_Float16)(vl / s);",
+              "fr[kMlpNF + f * kMlpNC + c] = (_Float16)0.0f;",
               "for (int i = 2 * kMlpNF + 4; i < kMlpIn; ++i) fr[i] = (_Float16)0.0f;",
               "av[a] = *(const half8 *)(S + (16 * a + r16) * ld + k + 8 * g);",
               "av[a] = *(const half4 *)(S + (16 * a + r16) * ld + K32 + 4 * g);",
