@@ -370,6 +370,10 @@ def bench_hevi(args):
                  "mlp_pick": res["mlp_pick"], "speedup_step_pick": d["ms_per_step"] / res["mlp_pick"]["ms_per_step"],
                  "iteration_ratio_pick": res["mlp_pick"]["iters_per_solve"] / d["iters_per_solve"],
                  "state_rel_diff_stacked_pick": res["state_rel_diff_stacked_pick"],
+                 "mlp_2pass": res["mlp_2pass"],
+                 "speedup_step_2pass": d["ms_per_step"] / res["mlp_2pass"]["ms_per_step"],
+                 "iteration_ratio_2pass": res["mlp_2pass"]["iters_per_solve"] / d["iters_per_solve"],
+                 "state_rel_diff_stacked_2pass": res["state_rel_diff_stacked_2pass"],
                  "state_rel_diff_mlp_vs_default": res["state_rel_diff"],
                  "state_rel_diff_stacked": res["state_rel_diff_stacked"],
                  "training": tr},
@@ -384,6 +388,10 @@ def bench_hevi(args):
             "iteration_ratio": ms["iters_per_solve"] / ds["iters_per_solve"],
             "mlp_pick": res_s["mlp_pick"], "speedup_step_pick": ds["ms_per_step"] / res_s["mlp_pick"]["ms_per_step"],
             "iteration_ratio_pick": res_s["mlp_pick"]["iters_per_solve"] / ds["iters_per_solve"],
+            "mlp_2pass": res_s["mlp_2pass"],
+            "speedup_step_2pass": ds["ms_per_step"] / res_s["mlp_2pass"]["ms_per_step"],
+            "iteration_ratio_2pass": res_s["mlp_2pass"]["iters_per_solve"] / ds["iters_per_solve"],
+            "state_rel_diff_stacked_2pass": res_s["state_rel_diff_stacked_2pass"],
             "state_rel_diff_stacked": res_s["state_rel_diff_stacked"],
             "speedup_vs_full_form_default": d["ms_per_step"] / ds["ms_per_step"],
             "state_rel_diff_vs_full_form": float(

@@ -488,13 +488,24 @@ nh_status nh_mlp_samples(nh_mlp *m, nh_ctx *ctx, double alpha, const double *dev
                          int64_t col0, int64_t ncol, void *dev_feat, double *dev_scale, float *dev_tgt,
                          double *dev_tmp);
 
+/* Network applications per initial guess (default 1): pass 1 predicts the
+   correction of the default start b from its residual alpha L_v b; each
+   further pass applies the same network to the residual
+   r = b - (I - alpha L_v) x0 of the guess so far (whose exact correction
+   (I - alpha L_v)^-1 r is the same linear map) and adds its prediction.
+   Used by nh_mlp_guess and by nh_hevi_step with this network.  NH_EINVAL
+   for passes outside 1 .. 4. */
+nh_status nh_mlp_set_passes(nh_mlp *m, int32_t passes);
+
 /* The initial guess x0 of (I - alpha L_v) x = b in every column of ctx, as
    used by nh_hevi_step: features of the default start's residual
    alpha L_v b (dimensionless, divided by its column RMS s), the network,
    and x0 = b + D s (output resampled to the lattice levels), the w correction
-   zero on the walls and a non-finite prediction replaced by x0 = b.
+   zero on the walls and a non-finite prediction replaced by x0 = b; then
+   the refinement passes set by nh_mlp_set_passes (alpha > 0 only).
    dev_b device [5][U] (fields rho', w, theta' are used), dev_tmp device
-   [5][U] scratch (receives L_v b in fields 0, 3, 4), dev_x0 device [3][U]
+   [5][U] scratch (receives L_v b, or the residual of the last refinement
+   pass, in fields 0, 3, 4), dev_x0 device [3][U]
    (rho', w, theta').  Asynchronous on the context's stream.  NH_EINVAL for
    null arguments, alpha < 0 or non-finite, or a context without reference
    state. */

@@ -119,8 +119,10 @@ def column_features(b, lb, z, alpha, D):
     side and of L_v b; z: lattice levels; D: dimension factors [3][n_z].
     Returns features [ncol][400] and the column scales s [ncol]: the
     dimensionless residual alpha L_v b / (D s) of the default start on the
-    canonical levels (entries 0 .. 194), zeros (195 .. 389), then the scalars
-    log10 s / 10, alpha / 10, 100 alpha c0(z_0) / H, log10 H / 5."""
+    canonical levels (entries 0 .. 194), zeros (195 .. 390: the correction is
+    homogeneous of degree one in r, so once r is divided by s the map does
+    not depend on s, and s is not a feature), then the scalars alpha / 10,
+    100 alpha c0(z_0) / H, log10 H / 5."""
     nz, ncol = b.shape[1], b.shape[2]
     lh = alpha * lb / D[:, :, None]
     s = np.sqrt((lh ** 2).sum(axis=(0, 1)) / (3 * nz)) + 1e-300
@@ -130,7 +132,6 @@ def column_features(b, lb, z, alpha, D):
     for f in range(3):
         for c in range(ncol):
             feat[c, f * NC:(f + 1) * NC] = np.interp(zc, z, lh[f, :, c]) / s[c]
-    feat[:, 2 * NF] = np.log10(s) / 10.0
     feat[:, 2 * NF + 1] = alpha / 10.0
     feat[:, 2 * NF + 2] = 100.0 * alpha * D[1, 0] / H
     feat[:, 2 * NF + 3] = np.log10(H) / 5.0

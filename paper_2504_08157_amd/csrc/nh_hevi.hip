@@ -36,9 +36,13 @@ namespace nh {
 // written once, coalesced along x.  Level data and stencil rows are
 // wave-uniform.  Taps outside the column see zero inputs.  With uv false
 // the (zero) u and v rows are not written.
-template <int N>
+// Residual form (RESID): x holds (rho', w, theta') as [3][U] and the
+// kernel writes the residual of (I - alpha L_v) x = b,
+// y = b - x + alpha L_v x, in fields 0, 3, 4 of [5][U] (b also [5][U]).
+template <int N, bool RESID>
 __global__ void __launch_bounds__(256) lv_apply_kernel(HeviParams h, const double *__restrict__ x,
-                                                       double *__restrict__ y, bool uv)
+                                                       double *__restrict__ y, bool uv, double alpha,
+                                                       const double *__restrict__ b)
 {
     constexpr int NC = 2 * N + 1;
     const long nxy = (long)h.nx * h.ny;
@@ -46,26 +50,28 @@ __global__ void __launch_bounds__(256) lv_apply_kernel(HeviParams h, const doubl
     if (col >= nxy) return;
     const int nz = h.nz;
     const long U = nxy * nz;
-    double ta[NC], tb[NC], rr[N + 1], ww[N + 1];
+    const long xw = RESID ? U : 3 * U, xt = RESID ? 2 * U : 4 * U;   // offsets of w and theta' in x
+    double ta[NC], tb[NC], rr[N + 1], ww[N + 1], th[N + 1];
     // level kk into the window's last slot (zeros above the top)
-    auto load = [&](int kk, double &a, double &bb, double &r, double &w) {
-        a = bb = r = w = 0.0;
+    auto load = [&](int kk, double &a, double &bb, double &r, double &w, double &t) {
+        a = bb = r = w = t = 0.0;
         if (kk < nz) {
             const double *L = h.lev + (long)kk * kLevW;
             const long J = col + (long)kk * nxy;
             r = x[J];
-            w = x[3 * U + J];
+            w = x[xw + J];
+            t = x[xt + J];
             a = L[0] * w;
-            bb = h.gamma * L[2] * (r * L[7] + x[4 * U + J] * L[8]);
+            bb = h.gamma * L[2] * (r * L[7] + t * L[8]);
         }
     };
 #pragma unroll
     for (int o = 0; o < N; ++o) { ta[o] = 0.0; tb[o] = 0.0; }
     // levels 0 .. N-1 into window slots N .. 2N-1 (rr/ww slots 0 .. N-1)
 #pragma unroll
-    for (int j = 0; j < N; ++j) load(j, ta[N + j], tb[N + j], rr[j], ww[j]);
+    for (int j = 0; j < N; ++j) load(j, ta[N + j], tb[N + j], rr[j], ww[j], th[j]);
     for (int k = 0; k < nz; ++k) {
-        load(k + N, ta[2 * N], tb[2 * N], rr[N], ww[N]);
+        load(k + N, ta[2 * N], tb[2 * N], rr[N], ww[N], th[N]);
         const double *L = h.lev + (long)k * kLevW;
         const double *G = h.gz + (long)k * NC;
         double d_rw = 0.0, d_pl = 0.0;
@@ -75,17 +81,26 @@ __global__ void __launch_bounds__(256) lv_apply_kernel(HeviParams h, const doubl
             d_pl += G[o] * tb[o];
         }
         const long I = col + (long)k * nxy;
-        y[I] = -d_rw;
-        if (uv) {
-            y[U + I] = 0.0;
-            y[2 * U + I] = 0.0;
+        const double l0 = -d_rw;
+        const double l3 = (k == 0 || k == nz - 1) ? 0.0 : -d_pl * L[7] - h.g * rr[0] * L[7];
+        const double l4 = -ww[0] * L[3];
+        if constexpr (RESID) {
+            y[I] = b[I] - rr[0] + alpha * l0;
+            y[3 * U + I] = b[3 * U + I] - ww[0] + alpha * l3;
+            y[4 * U + I] = b[4 * U + I] - th[0] + alpha * l4;
+        } else {
+            y[I] = l0;
+            if (uv) {
+                y[U + I] = 0.0;
+                y[2 * U + I] = 0.0;
+            }
+            y[3 * U + I] = l3;
+            y[4 * U + I] = l4;
         }
-        y[3 * U + I] = (k == 0 || k == nz - 1) ? 0.0 : -d_pl * L[7] - h.g * rr[0] * L[7];
-        y[4 * U + I] = -ww[0] * L[3];
 #pragma unroll
         for (int o = 0; o < 2 * N; ++o) { ta[o] = ta[o + 1]; tb[o] = tb[o + 1]; }
 #pragma unroll
-        for (int j = 0; j < N; ++j) { rr[j] = rr[j + 1]; ww[j] = ww[j + 1]; }
+        for (int j = 0; j < N; ++j) { rr[j] = rr[j + 1]; ww[j] = ww[j + 1]; th[j] = th[j + 1]; }
     }
 }
 
@@ -1042,20 +1057,33 @@ size_t gmres_lds_bytes(int nz, int N, int restart)
     return n * sizeof(double);
 }
 
-hipError_t launch_lv_apply(const HeviParams &h, const double *x, double *y, hipStream_t s, bool uv)
+template <bool RESID>
+static hipError_t launch_lv(const HeviParams &h, const double *x, double *y, hipStream_t s, bool uv, double alpha,
+                            const double *b)
 {
     const long nxy = (long)h.nx * h.ny;
     const dim3 grid((unsigned)((nxy + 255) / 256)), blk(256);
     switch (h.N) {
-    case 1: hipLaunchKernelGGL(lv_apply_kernel<1>, grid, blk, 0, s, h, x, y, uv); break;
-    case 2: hipLaunchKernelGGL(lv_apply_kernel<2>, grid, blk, 0, s, h, x, y, uv); break;
-    case 3: hipLaunchKernelGGL(lv_apply_kernel<3>, grid, blk, 0, s, h, x, y, uv); break;
-    case 4: hipLaunchKernelGGL(lv_apply_kernel<4>, grid, blk, 0, s, h, x, y, uv); break;
-    case 5: hipLaunchKernelGGL(lv_apply_kernel<5>, grid, blk, 0, s, h, x, y, uv); break;
-    case 6: hipLaunchKernelGGL(lv_apply_kernel<6>, grid, blk, 0, s, h, x, y, uv); break;
+    case 1: hipLaunchKernelGGL((lv_apply_kernel<1, RESID>), grid, blk, 0, s, h, x, y, uv, alpha, b); break;
+    case 2: hipLaunchKernelGGL((lv_apply_kernel<2, RESID>), grid, blk, 0, s, h, x, y, uv, alpha, b); break;
+    case 3: hipLaunchKernelGGL((lv_apply_kernel<3, RESID>), grid, blk, 0, s, h, x, y, uv, alpha, b); break;
+    case 4: hipLaunchKernelGGL((lv_apply_kernel<4, RESID>), grid, blk, 0, s, h, x, y, uv, alpha, b); break;
+    case 5: hipLaunchKernelGGL((lv_apply_kernel<5, RESID>), grid, blk, 0, s, h, x, y, uv, alpha, b); break;
+    case 6: hipLaunchKernelGGL((lv_apply_kernel<6, RESID>), grid, blk, 0, s, h, x, y, uv, alpha, b); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_lv_apply(const HeviParams &h, const double *x, double *y, hipStream_t s, bool uv)
+{
+    return launch_lv<false>(h, x, y, s, uv, 0.0, nullptr);
+}
+
+hipError_t launch_lv_resid(const HeviParams &h, double alpha, const double *b, const double *x3, double *y,
+                           hipStream_t s)
+{
+    return launch_lv<true>(h, x3, y, s, false, alpha, b);
 }
 
 hipError_t launch_axpy_multi(long n, const double *base, int nsrc, const LinComb &lc, double *out,

@@ -95,6 +95,10 @@ struct LinComb {
 size_t gmres_lds_bytes(int nz, int N, int restart);
 // y = L_v x on [5][U]; with uv false the u and v rows of y are left untouched
 hipError_t launch_lv_apply(const HeviParams &h, const double *x, double *y, hipStream_t s, bool uv = true);
+// y (fields 0, 3, 4 of [5][U]) = b - x3 + alpha L_v x3: the residual of
+// (I - alpha L_v) x = b at x3 = (rho', w, theta') as [3][U].
+hipError_t launch_lv_resid(const HeviParams &h, double alpha, const double *b, const double *x3, double *y,
+                           hipStream_t s);
 hipError_t launch_axpy_multi(long n, const double *base, int nsrc, const LinComb &lc, double *out,
                              hipStream_t s);
 hipError_t launch_gmres(const HeviParams &h, const GmresArgs &g, hipStream_t s);
@@ -187,6 +191,7 @@ constexpr int kGmresSchurSlots = 2;   // Schur form: interior w levels up to 128
 constexpr int kMlpIn = 400;    // 394 features padded to a multiple of 16
 constexpr int kMlpHid = 256;
 constexpr int kMlpOut = 256;   // 3 fields x 65 canonical levels, padded to a multiple of 64
+constexpr int kMlpMaxPasses = 4;   // network applications per initial guess, at most
 constexpr int kMlpSlices = 16;  // batch slices of the weight-gradient GEMMs
 constexpr int kMlpNC = 65;     // canonical levels: LGL nodes of 16 order-4 elements
 constexpr int kMlpNF = 3 * kMlpNC;
@@ -221,9 +226,13 @@ struct MlpWeights {
     const float *bias[3];
 };
 
-// x0 of columns col0 .. col0 + ncol - 1 from b and L_v b in one kernel
-hipError_t launch_mlp_infer(const MlpColParams &p, const MlpNet &net, const double *b, const double *lb, long col0,
-                            long ncol, double *x0, hipStream_t s);
+// x0 = base + the network's correction for the residual rscale * res of
+// columns col0 .. col0 + ncol - 1 in one kernel: base = b ([5][U]) with
+// res = L_v b, rscale = alpha (first pass), or base = the previous guess
+// ([3][U], base3) with res its residual, rscale = 1 (refinement; x0 may be
+// base)
+hipError_t launch_mlp_infer(const MlpColParams &p, const MlpNet &net, const double *base, bool base3,
+                            const double *lb, double rscale, long col0, long ncol, double *x0, hipStream_t s);
 hipError_t launch_mlp_features(const MlpColParams &p, const double *b, const double *lb, const double *x,
                                long col0, long ncol, void *feat, double *scale, float *tgt, hipStream_t s);
 hipError_t launch_mlp_guess(const MlpColParams &p, const double *b, long col0, long ncol, const float *y,

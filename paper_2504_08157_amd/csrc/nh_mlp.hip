@@ -14,10 +14,11 @@
 // (rho'/rho0, w/c0 with c0 = sqrt(gamma p0 / rho0), theta'/theta0), divided
 // by one column scale s (RMS of the dimensionless r over the column's 3 n_z
 // values) and resampled linearly in z to the 65 canonical levels (LGL nodes
-// of 16 equal order-4 elements of the column): features 0 .. 194; 195 .. 389
-// are zero; then 4 scalars (log10 s / 10, alpha / 10, 100 alpha c0(z_0) / H,
-// log10 H / 5).  The correction is thus predicted relative to its own size,
-// not to the size of b.
+// of 16 equal order-4 elements of the column): features 0 .. 194; 195 .. 390
+// are zero (the correction is homogeneous of degree one in r, so the map
+// from r / s does not depend on s); then 3 scalars (alpha / 10,
+// 100 alpha c0(z_0) / H, log10 H / 5).  The correction is thus predicted
+// relative to its own size, not to the size of b.
 // Output: the dimensionless correction on the canonical levels,
 // x0 = b + D s resample^-1(y), with the w correction zero on the walls.
 #include "nh_internal.h"
@@ -123,7 +124,7 @@ __global__ void __launch_bounds__(512) mlp_features_kernel(MlpColParams p, const
         }
     }
     if (q == 0) {
-        sf[lane][2 * kMlpNF] = (_Float16)(log10(s) / 10.0);
+        sf[lane][2 * kMlpNF] = (_Float16)0.0f;
         sf[lane][2 * kMlpNF + 1] = (_Float16)(p.alpha / 10.0);
         sf[lane][2 * kMlpNF + 2] = (_Float16)(100.0 * p.alpha * dim_factor(p, 1, 0) / H);
         sf[lane][2 * kMlpNF + 3] = (_Float16)(log10(H) / 5.0);
@@ -341,10 +342,16 @@ constexpr int kLdH = kMlpHid + 8;   // LDS row of the activations (halves), padd
 constexpr int kRegBytes = 64 * kLdF * 2;   // the shared region: features, then H1, H2, output rows
 static_assert(64 * (kMlpNF + 1) * 4 <= kRegBytes && 64 * kLdH * 2 <= kRegBytes, "region sizes");
 
+// x0 = base + D s (network of the residual res, dimensionless) per column:
+// base is b ([5][U], fields 0, 3, 4) with res = alpha L_v b for the first
+// pass, or the previous guess ([3][U], base3) with res = its residual
+// b - (I - alpha L_v) x0 for a refinement pass; rscale multiplies res
+// (alpha, or 1).  x0 may be base (each element is read before it is
+// written, by the same thread).
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) mlp_infer_kernel(MlpColParams p, MlpWeights wt,
-                                                        const double *__restrict__ b,
-                                                        const double *__restrict__ lb, long col0, long ncol,
-                                                        double *__restrict__ x0)
+                                                        const double *base, bool base3,
+                                                        const double *__restrict__ lb, double rscale, long col0,
+                                                        long ncol, double *x0)
 {
     constexpr int NWV = 8;
     __shared__ __align__(16) unsigned char sreg[kRegBytes];
@@ -401,7 +408,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) m
             const long I = col + (long)k * nxy;
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
-                const double l = p.alpha * lb[fld[f] * U + I] * sdinv[f * nz + k];
+                const double l = rscale * lb[fld[f] * U + I] * sdinv[f * nz + k];
                 a += l * l;
             }
         }
@@ -421,13 +428,13 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) m
         for (int f = 0; f < 3; ++f) {
             const long I0 = fld[f] * U + col + (long)k0 * nxy, I1 = I0 + nxy;
             const double d0 = sdinv[f * nz + k0], d1 = sdinv[f * nz + k0 + 1];
-            const double vl = (1.0 - t) * (p.alpha * lb[I0] * d0) + t * (p.alpha * lb[I1] * d1);
+            const double vl = (1.0 - t) * (rscale * lb[I0] * d0) + t * (rscale * lb[I1] * d1);
             fr[f * kMlpNC + c] = (_Float16)(vl / s);
             fr[kMlpNF + f * kMlpNC + c] = (_Float16)0.0f;
         }
     }
     if (q == 0) {
-        fr[2 * kMlpNF] = (_Float16)(log10(s) / 10.0);
+        fr[2 * kMlpNF] = (_Float16)0.0f;
         fr[2 * kMlpNF + 1] = (_Float16)(p.alpha / 10.0);
         fr[2 * kMlpNF + 2] = (_Float16)(100.0 * p.alpha * dim_factor(p, 1, 0) / H);
         fr[2 * kMlpNF + 3] = (_Float16)(log10(H) / 5.0);
@@ -554,7 +561,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) m
             const float *yr = sy + lane * (kMlpNF + 1) + f * kMlpNC;
             double d = (1.0 - t) * yr[lo] + t * yr[lo + 1];
             if (!isfinite(d) || (f == 1 && (k == 0 || k == nz - 1))) d = 0.0;
-            x0[f * U + I] = b[fld[f] * U + I] + dg[f * nz + k] * sc * d;
+            x0[f * U + I] = base[(base3 ? f : fld[f]) * U + I] + dg[f * nz + k] * sc * d;
         }
     }
 }
@@ -770,15 +777,16 @@ hipError_t launch_mlp_guess(const MlpColParams &p, const double *b, long col0, l
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_infer(const MlpColParams &p, const MlpNet &net, const double *b, const double *lb, long col0,
-                            long ncol, double *x0, hipStream_t s)
+hipError_t launch_mlp_infer(const MlpColParams &p, const MlpNet &net, const double *base, bool base3,
+                            const double *lb, double rscale, long col0, long ncol, double *x0, hipStream_t s)
 {
     MlpWeights wt;
     for (int i = 0; i < 4; ++i) wt.W[i] = (const _Float16 *)net.wh[i];
     for (int i = 0; i < 3; ++i) wt.bias[i] = net.b[i];
     const int grid = (int)((ncol + 63) / 64);
     const size_t lds = (sizeof(double) * 7 + sizeof(int)) * (size_t)p.nz;
-    hipLaunchKernelGGL(mlp_infer_kernel, dim3(grid), dim3(512), lds, s, p, wt, b, lb, col0, ncol, x0);
+    hipLaunchKernelGGL(mlp_infer_kernel, dim3(grid), dim3(512), lds, s, p, wt, base, base3, lb, rscale, col0, ncol,
+                       x0);
     return hipGetLastError();
 }
 

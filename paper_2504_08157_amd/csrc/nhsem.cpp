@@ -1418,6 +1418,7 @@ struct nh_mlp {
     MlpNet net;
     long max_batch;
     int step;
+    int passes;   // network applications per initial guess (nh_mlp_set_passes)
     hipStream_t stream;
     bool sticky;
     std::string err;
@@ -1533,13 +1534,22 @@ MlpColParams mlp_col_params(const nh_ctx *c, double alpha)
 
 }  // namespace
 
+// First pass: x0 = b + N(alpha L_v b); each further pass applies the
+// network to the residual its guess leaves, r = b - (I - alpha L_v) x0 (the
+// exact correction of x0 is (I - alpha L_v)^-1 r, the same map as for the
+// first pass), and adds the predicted correction in place.
 nh_status mlp_guess(nh_mlp *m, nh_ctx *c, double alpha, const double *b, double *lb, double *x0)
 {
     if (m->sticky) return fail(c, NH_ESTATE, "MLP in error state");
-    HIPCHK(c, launch_lv_apply(hevi_params(c), b, lb, c->stream, false));
+    const HeviParams hp = hevi_params(c);
+    HIPCHK(c, launch_lv_apply(hp, b, lb, c->stream, false));
     const MlpColParams cp = mlp_col_params(c, alpha);
     const long ncol = (long)c->n[0] * c->n[1];
-    HIPCHK(c, launch_mlp_infer(cp, m->net, b, lb, 0, ncol, x0, c->stream));
+    HIPCHK(c, launch_mlp_infer(cp, m->net, b, false, lb, alpha, 0, ncol, x0, c->stream));
+    for (int k = 1; k < m->passes && alpha > 0.0; ++k) {
+        HIPCHK(c, launch_lv_resid(hp, alpha, b, x0, lb, c->stream));
+        HIPCHK(c, launch_mlp_infer(cp, m->net, x0, true, lb, 1.0, 0, ncol, x0, c->stream));
+    }
     return NH_OK;
 }
 
@@ -1594,6 +1604,7 @@ nh_status nh_mlp_create(int64_t max_batch, uint64_t seed, void *dev_ws, size_t b
     n.feat = w + L.feat; n.scale = (double *)(w + L.scale);
     m->max_batch = max_batch;
     m->step = 0;
+    m->passes = 1;
     m->stream = (hipStream_t)hip_stream;
     m->sticky = false;
     std::vector<float> h;
@@ -1704,6 +1715,14 @@ nh_status nh_mlp_samples(nh_mlp *m, nh_ctx *c, double alpha, const double *dev_b
     HIPCHK(c, launch_lv_apply(hevi_params(c), dev_b, dev_tmp, c->stream, false));
     const MlpColParams cp = mlp_col_params(c, alpha);
     HIPCHK(c, launch_mlp_features(cp, dev_b, dev_tmp, dev_x, col0, ncol, dev_feat, dev_scale, dev_tgt, c->stream));
+    return NH_OK;
+}
+
+nh_status nh_mlp_set_passes(nh_mlp *m, int32_t passes)
+{
+    if (!m) return fail(nullptr, NH_EINVAL, "null MLP");
+    if (passes < 1 || passes > kMlpMaxPasses) return mfail(m, NH_EINVAL, "passes must be 1 .. 4");
+    m->passes = passes;
     return NH_OK;
 }
 

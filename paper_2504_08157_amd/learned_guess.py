@@ -153,11 +153,12 @@ def fit(mlp, w_eval, dt, warm, sources, epochs, batch=1024, lr=1e-3, max_per_ste
 
 
 def compare(mlp, w, warm, held, dt, rtol=1e-10, restart=20, schur=False):
-    """From the state after `warm` default steps, run `held` steps three
-    times -- default guess, MLP guess, and the MLP guess with the per-column
-    choice against the default start (the smaller initial residual) -- and
-    report GMRES iterations, step times and the difference of the final
-    states (schur: solve the Schur complement in w)."""
+    """From the state after `warm` default steps, run `held` steps four
+    times -- default guess, MLP guess, the MLP guess with the per-column
+    choice against the default start (the smaller initial residual), and
+    the MLP guess refined by a second pass of the network on its own
+    residual -- and report GMRES iterations, step times and the difference
+    of the final states (schur: solve the Schur complement in w)."""
     import torch
     ctx = hevi_context(w)
     for s in range(warm):
@@ -165,7 +166,9 @@ def compare(mlp, w, warm, held, dt, rtol=1e-10, restart=20, schur=False):
     q0 = ctx.nh_get_state().clone()
     out = {}
     finals = {}
-    for name, g, pick in (("default", None, False), ("mlp", mlp, False), ("mlp_pick", mlp, True)):
+    for name, g, pick, passes in (("default", None, False, 1), ("mlp", mlp, False, 1), ("mlp_pick", mlp, True, 1),
+                                  ("mlp_2pass", mlp, False, 2)):
+        mlp.nh_mlp_set_passes(passes)
         ctx.nh_set_state(q0)
         torch.cuda.synchronize()
         it, ms = 0, 0.0
@@ -183,7 +186,10 @@ def compare(mlp, w, warm, held, dt, rtol=1e-10, restart=20, schur=False):
         solves = held * 2 * ctx.nx * ctx.ny
         out[name] = {"iters_per_solve": it / solves, "iters_max": mx, "ms_per_step": ms / held}
         finals[name] = ctx.nh_get_state().cpu().numpy()
+    mlp.nh_mlp_set_passes(1)
     dp = finals["mlp_pick"] - finals["default"]
+    d2 = finals["mlp_2pass"] - finals["default"]
+    out["state_rel_diff_stacked_2pass"] = float(np.linalg.norm(d2) / np.linalg.norm(finals["default"]))
     out["state_rel_diff_stacked_pick"] = float(np.linalg.norm(dp) / np.linalg.norm(finals["default"]))
     d = finals["mlp"] - finals["default"]
     out["state_rel_diff"] = [float(np.linalg.norm(d[f]) / max(np.linalg.norm(finals["default"][f]), 1e-300))

@@ -250,3 +250,100 @@ def test_adam_step_matches_oracle():
     from paper_2504_08157_amd import nhsem
     with pytest.raises(nhsem.NHError):
         m.nh_mlp_adam_step(lr=-1.0)
+
+
+def _canonical_column_case(oracle_mod, nel=(2, 2, 16)):
+    """A context and oracle whose column grid is the canonical one (16 equal
+    order-4 elements), so feature resampling is the identity."""
+    from paper_2504_08157_amd import nhsem
+    w = W.cfg_hevi()
+    mesh = W.MeshSpec(nel, 4, W.uniform_edges(0, 40e3, nel[0]), W.uniform_edges(0, 40e3, nel[1]),
+                      W.uniform_edges(0, 20e3, nel[2]), (True, True))
+    ctx = nhsem.Context(mesh, w.phys)
+    orc = oracle_mod.Oracle(mesh, w.phys)
+    g = ctx.nh_lattice_coords(); o = orc.lattice_coords()
+    ctx.nh_set_reference(*W.constant_n_reference(g[2]))
+    orc.set_reference(*W.constant_n_reference(o[2]))
+    ctx.nh_hevi_attach()
+    return ctx, orc, o, w.phys
+
+
+def _exact_map_params(m, orc, o, ph, alpha, oracle_mod):
+    """Network parameters whose hidden path is zero and whose bypass is the
+    dimensionless (I - alpha L_v)^-1 of the oracle on features 0 .. 194: the
+    exact correction map in FP16."""
+    Lm = oracle_mod.column_matrix(orc)
+    nz = orc.nz
+    rho0, th0 = W.constant_n_reference(o[2])
+    D = MO.dimension_factors(rho0, orc.reference_pressure(), th0, ph.cp / ph.cv).reshape(-1)
+    M = (np.linalg.inv(np.eye(3 * nz) - alpha * Lm) * D[None, :]) / D[:, None]
+    parts = [np.zeros(s) for s in MO.SHAPES]
+    parts[6][:3 * nz, :3 * nz] = M
+    return MO.flatten(parts).astype(np.float32)
+
+
+def test_refinement_pass_matches_oracle(oracle_mod):
+    """Second pass of nh_mlp_guess (the network on the residual of its first
+    guess) against the oracle: the residual from the oracle's L_v, features,
+    the GPU forward on them, the oracle's resampling; random parameters,
+    the pass-2 correction to FP16 rounding of the features."""
+    import torch
+    from paper_2504_08157_amd import nhsem
+    ctx, orc, o, ph = _canonical_column_case(oracle_mod, nel=(3, 2, 16))
+    m = nhsem.ColumnMLP(max_batch=128)
+    rng = np.random.default_rng(21)
+    m.nh_mlp_set_params(torch.from_numpy(rng.normal(scale=0.03, size=m.nparam).astype(np.float32)).cuda())
+    bq = W.smooth_random_state(*o, *W.constant_n_reference(o[2]), seed=6, walls=(False, False))
+    bd = torch.from_numpy(bq).cuda()
+    alpha = 0.6
+    ncol = ctx.nx * ctx.ny
+    sel = lambda a: np.stack([a[0], a[3], a[4]]).reshape(3, orc.nz, -1)
+    x1 = m.nh_mlp_guess(ctx, alpha, bd).cpu().numpy().reshape(3, orc.nz, ncol)
+    m.nh_mlp_set_passes(2)
+    x2 = m.nh_mlp_guess(ctx, alpha, bd).cpu().numpy().reshape(3, orc.nz, ncol)
+    # the oracle's residual of x1 and the features of the second pass
+    full = np.zeros_like(bq)
+    full[0], full[3], full[4] = (x1[f].reshape(bq[0].shape) for f in range(3))
+    r1 = sel(bq) - x1 + alpha * sel(orc.lv_apply(full))
+    rho0, th0 = W.constant_n_reference(o[2])
+    D = MO.dimension_factors(rho0, orc.reference_pressure(), th0, ph.cp / ph.cv)
+    fo, so = MO.column_features(x1, r1 / alpha, o[2], alpha, D)
+    fpad = torch.zeros((128, MO.IN), dtype=torch.float16, device="cuda")
+    fpad[:ncol] = torch.from_numpy(fo.astype(np.float16)).cuda()
+    y = m.nh_mlp_forward(fpad).cpu().numpy()[:ncol].astype(np.float64)
+    ref = MO.column_guess(x1, y, o[2], D, so)
+    assert np.linalg.norm(ref - x1) > 1e-3 * np.linalg.norm(x1 - sel(bq))   # pass 2 changes the guess
+    assert _rel(x2 - x1, ref - x1) <= 5e-3, _rel(x2 - x1, ref - x1)
+    with pytest.raises(RuntimeError):
+        m.nh_mlp_set_passes(0)
+    with pytest.raises(RuntimeError):
+        m.nh_mlp_set_passes(5)
+
+
+def test_refinement_pass_with_the_exact_map(oracle_mod):
+    """With the exact correction map as the network (bypass = the
+    dimensionless (I - alpha L_v)^-1 in FP16), one pass leaves the FP16
+    rounding of the map, a residual about 1e-3 of the default start's, and
+    each refinement pass multiplies it by about that factor again."""
+    import torch
+    from paper_2504_08157_amd import nhsem
+    ctx, orc, o, ph = _canonical_column_case(oracle_mod)
+    alpha = 0.6
+    m = nhsem.ColumnMLP(max_batch=64)
+    m.nh_mlp_set_params(torch.from_numpy(_exact_map_params(m, orc, o, ph, alpha, oracle_mod)).cuda())
+    bq = W.smooth_random_state(*o, *W.constant_n_reference(o[2]), seed=8, walls=(False, False))
+    bd = torch.from_numpy(bq).cuda()
+    ncol = ctx.nx * ctx.ny
+    sel = lambda a: np.stack([a[0], a[3], a[4]]).reshape(3, orc.nz, -1)
+
+    def resid(x):
+        full = np.zeros_like(bq)
+        full[0], full[3], full[4] = (x[f].reshape(bq[0].shape) for f in range(3))
+        return np.linalg.norm(sel(bq) - x + alpha * sel(orc.lv_apply(full)))
+
+    r = [resid(sel(bq))]
+    for passes in (1, 2, 3):
+        m.nh_mlp_set_passes(passes)
+        r.append(resid(m.nh_mlp_guess(ctx, alpha, bd).cpu().numpy().reshape(3, orc.nz, ncol)))
+    print("residuals", r)
+    assert r[1] < 1e-2 * r[0] and r[2] < 1e-2 * r[1] and r[3] < r[2], r

@@ -80,8 +80,7 @@ def test_column_features_on_linear_profiles():
         for f in range(3):
             np.testing.assert_allclose(feat[c, f * 65:(f + 1) * 65], -2.0 * (f + 1) * (c + 1) * (1 + zc) / s_ref,
                                        rtol=1e-13)
-        np.testing.assert_allclose(feat[c, 390], np.log10(s_ref) / 10.0, rtol=1e-14)
-    assert np.all(feat[:, 195:390] == 0)
+    assert np.all(feat[:, 195:391] == 0)
     assert np.all(feat[:, 394:] == 0) and np.allclose(feat[:, 391], 0.2)
     np.testing.assert_allclose(feat[:, 392], 100.0 * 2.0 * 340.0 / 1000.0, rtol=1e-14)
     # x = b + 1e-3 b: the correction is 1e-3 b = -lb, i.e. -feat / alpha on the canonical levels
