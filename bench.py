@@ -156,11 +156,11 @@ def bench_gmres(args):
     print(json.dumps(line), flush=True)
 
 
-# GEMM flops per sample of the column MLP (400 -> 256 -> 256 -> 256 with the
-# 400 -> 256 bypass): forward W1, W2, W3, S; backward dH2, dH1 and the four
+# GEMM flops per sample of the column MLP (208 -> 256 -> 256 -> 256 with the
+# 208 -> 256 bypass): forward W1, W2, W3, S; backward dH2, dH1 and the four
 # weight gradients
-MLP_FWD_FLOPS = 2 * (400 * 256 + 256 * 256 + 256 * 256 + 400 * 256)
-MLP_BWD_FLOPS = 2 * (256 * 256 * 2 + 400 * 256 * 2 + 256 * 256 * 2)
+MLP_FWD_FLOPS = 2 * (208 * 256 + 256 * 256 + 256 * 256 + 208 * 256)
+MLP_BWD_FLOPS = 2 * (256 * 256 * 2 + 208 * 256 * 2 + 256 * 256 * 2)
 MFMA_F16_PEAK_TFLOPS = 2500.0
 MFMA_F32_PEAK_TFLOPS = 157.3
 
@@ -210,7 +210,7 @@ def bench_mlp(args):
             "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": r["train_step_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f16+f32", "data": "synthetic",
-            "config": {"workload": "column MLP 400-256-256-256 with bypass", "mode": "mlp", "batch": 4096},
+            "config": {"workload": "column MLP 208-256-256-256 with bypass", "mode": "mlp", "batch": 4096},
             "roofline": {"bound": "mfma", "achieved": r["backward_tflops"], "peak": MFMA_F32_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": r["backward_frac_of_f32_mfma_peak"],
                          "kernel": "backward (FP32 MFMA GEMMs with their bias sums and SiLU derivative)",
@@ -246,9 +246,11 @@ def parse():
                          "mlp: the column MLP's forward, backward and training step alone")
     ap.add_argument("--members", type=int, default=48)
     ap.add_argument("--imex-time", type=float, default=8.0, help="simulated seconds of the imex3d comparison")
-    ap.add_argument("--mlp-epochs", type=int, default=160, help="training epochs of the column MLP (hevi mode)")
-    ap.add_argument("--mlp-random-batches", type=int, default=32,
+    ap.add_argument("--mlp-epochs", type=int, default=100, help="training epochs of the column MLP (hevi mode)")
+    ap.add_argument("--mlp-random-batches", type=int, default=96,
                     help="batches of random column right-hand sides in the MLP training data (hevi mode)")
+    ap.add_argument("--mlp-finetune-epochs", type=int, default=120,
+                    help="further epochs on the evaluated column grid's samples alone, batch 8192 (hevi mode)")
     ap.add_argument("--gmres-restart", type=int, default=10, help="Krylov vectors per GMRES cycle (hevi mode)")
     return ap.parse_args()
 
@@ -343,7 +345,7 @@ def bench_hevi(args):
     wr.mesh = W._tc_mesh(32, 32, w.mesh.nel[2])   # same column grid, 16384 columns per random batch
     tr = LG.fit(mlp, w, w.dt, warm, [(W.cfg_tc_small(), 2, w.dt), (W.cfg_bubble(), 2, 0.5)],
                 epochs=args.mlp_epochs, batch=1024, lr=1e-3, max_per_step=24576, random_grid=wr,
-                random_batches=args.mlp_random_batches)
+                random_batches=args.mlp_random_batches, finetune_epochs=args.mlp_finetune_epochs)
     res = LG.compare(mlp, w, warm=warm, held=args.steps, dt=w.dt, restart=args.gmres_restart)
     # the same steps with the column systems solved through their Schur
     # complement in w (restart 10 only)
@@ -356,11 +358,12 @@ def bench_hevi(args):
     gm = time_column_solves(ctx, w, 3)
     U = ctx.U
     ctx.close()
-    d, m = res["default"], res["mlp"]
+    d, m, m2 = res["default"], res["mlp"], res["mlp_2pass"]
     out = {
         "metric": "DOF-stage updates/s (FP32/batched vs FP64 plain) at stated L2 error; % HBM peak",
-        "value": 5 * U * 3 / (m["ms_per_step"] / 1e3), "unit": "DOF-stage updates/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": warm, "ms_per_step": m["ms_per_step"],
+        # the learned guess with two network passes (the form the speed-up is quoted for)
+        "value": 5 * U * 3 / (m2["ms_per_step"] / 1e3), "unit": "DOF-stage updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": warm, "ms_per_step": m2["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f16", "data": "synthetic",
         "config": {"workload": w.name, "mode": "hevi", "dt": w.dt,
                    "gmres": f"GMRES({args.gmres_restart}), rtol 1e-10",

@@ -435,12 +435,12 @@ nh_status nh_batch_destroy(nh_batch *b);
 /* ------------------------------------------------------------------
  * Column MLP for the initial guess of the HEVI column solves (trained on
  * solves the method itself produces; the Krylov solve still runs to the
- * same tolerance).  Network 400 -> 256 -> 256 -> 256 with SiLU and a
+ * same tolerance).  Network 208 -> 256 -> 256 -> 256 with SiLU and a
  * linear bypass, y = W3 h2 + b3 + S x; FP16 weights and activations on MFMA
  * with FP32 accumulation in the forward pass, FP32 backward, Adam on FP32
- * master weights.  Parameters, in order: W1 [256][400], b1 [256],
- * W2 [256][256], b2 [256], W3 [256][256], b3 [256], S [256][400].
- * Inputs x: FP16 [batch][400] (features of nh_mlp_samples); outputs y: FP32
+ * master weights.  Parameters, in order: W1 [256][208], b1 [256],
+ * W2 [256][256], b2 [256], W3 [256][256], b3 [256], S [256][208].
+ * Inputs x: FP16 [batch][208] (features of nh_mlp_samples); outputs y: FP32
  * [batch][256] (the first 3 x 65 are used).  batch: multiple of 64, at most the capacity given at
  * creation.
  * ------------------------------------------------------------------ */
@@ -479,7 +479,7 @@ nh_status nh_mlp_set_params(nh_mlp *m, const float *dev_master);
 
 /* Training samples / features for columns [col0, col0 + ncol) of ctx: the
    right-hand side b of (I - alpha L_v) x = b and, if dev_x is given, the
-   solution x.  dev_feat FP16 [ncol][400], dev_scale double [ncol] (the
+   solution x.  dev_feat FP16 [ncol][208], dev_scale double [ncol] (the
    column scale: RMS of the dimensionless alpha L_v b), dev_tgt float
    [ncol][256] (the scaled dimensionless
    correction x - b on the 65 canonical levels per field, zero past 195;

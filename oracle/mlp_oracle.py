@@ -2,7 +2,7 @@
 
 Network y = W3 s(W2 s(W1 x + b1) + b2) + b3 + S x with SiLU
 s(z) = z / (1 + e^-z) and a linear bypass S, parameters flattened in the
-order W1 [256][400], b1, W2 [256][256], b2, W3 [256][256], b3, S [256][400];
+order W1 [256][208], b1, W2 [256][256], b2, W3 [256][256], b3, S [256][208];
 mean-squared-error loss; Adam (Kingma & Ba 2015) with bias correction.
 
 Column features, targets and the guess follow the definition used by the
@@ -25,7 +25,7 @@ from __future__ import annotations
 
 import numpy as np
 
-IN, HID, OUT = 400, 256, 256
+IN, HID, OUT = 208, 256, 256
 NC = 65          # canonical levels
 NF = 3 * NC      # used outputs (rho', w, theta' on the canonical levels)
 SHAPES = [(HID, IN), (HID,), (HID, HID), (HID,), (OUT, HID), (OUT,), (OUT, IN)]
@@ -117,12 +117,12 @@ def dimension_factors(rho0, p0, theta0, gamma):
 def column_features(b, lb, z, alpha, D):
     """b, lb: arrays [3][n_z][ncol] of (rho', w, theta') of the right-hand
     side and of L_v b; z: lattice levels; D: dimension factors [3][n_z].
-    Returns features [ncol][400] and the column scales s [ncol]: the
+    Returns features [ncol][208] and the column scales s [ncol]: the
     dimensionless residual alpha L_v b / (D s) of the default start on the
-    canonical levels (entries 0 .. 194), zeros (195 .. 390: the correction is
-    homogeneous of degree one in r, so once r is divided by s the map does
-    not depend on s, and s is not a feature), then the scalars alpha / 10,
-    100 alpha c0(z_0) / H, log10 H / 5."""
+    canonical levels (entries 0 .. 194), the scalars alpha / 10,
+    100 alpha c0(z_0) / H, log10 H / 5 (195 .. 197), zeros to 207.  s is not
+    a feature: the correction is homogeneous of degree one in r, so once r
+    is divided by s the map does not depend on s."""
     nz, ncol = b.shape[1], b.shape[2]
     lh = alpha * lb / D[:, :, None]
     s = np.sqrt((lh ** 2).sum(axis=(0, 1)) / (3 * nz)) + 1e-300
@@ -132,9 +132,9 @@ def column_features(b, lb, z, alpha, D):
     for f in range(3):
         for c in range(ncol):
             feat[c, f * NC:(f + 1) * NC] = np.interp(zc, z, lh[f, :, c]) / s[c]
-    feat[:, 2 * NF + 1] = alpha / 10.0
-    feat[:, 2 * NF + 2] = 100.0 * alpha * D[1, 0] / H
-    feat[:, 2 * NF + 3] = np.log10(H) / 5.0
+    feat[:, NF] = alpha / 10.0
+    feat[:, NF + 1] = 100.0 * alpha * D[1, 0] / H
+    feat[:, NF + 2] = np.log10(H) / 5.0
     return feat, s
 
 

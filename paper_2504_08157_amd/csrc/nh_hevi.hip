@@ -31,11 +31,10 @@ namespace nh {
 
 // ---------------------------------------------------------------- L_v on a state
 // y = L_v x on [5][U].  One thread per lattice column walks up the levels
-// keeping the (2N+1)-level window of the two stencil inputs (rho0 w and
-// p'_L) in registers, so every value of x is read once and every value of y
+// (lv_walk: the (2N+1)-level window of the two stencil inputs rho0 w and
+// p'_L in registers), so every value of x is read once and every value of y
 // written once, coalesced along x.  Level data and stencil rows are
-// wave-uniform.  Taps outside the column see zero inputs.  With uv false
-// the (zero) u and v rows are not written.
+// wave-uniform.  With uv false the (zero) u and v rows are not written.
 // Residual form (RESID): x holds (rho', w, theta') as [3][U] and the
 // kernel writes the residual of (I - alpha L_v) x = b,
 // y = b - x + alpha L_v x, in fields 0, 3, 4 of [5][U] (b also [5][U]).
@@ -44,64 +43,27 @@ __global__ void __launch_bounds__(256) lv_apply_kernel(HeviParams h, const doubl
                                                        double *__restrict__ y, bool uv, double alpha,
                                                        const double *__restrict__ b)
 {
-    constexpr int NC = 2 * N + 1;
     const long nxy = (long)h.nx * h.ny;
     const long col = blockIdx.x * 256L + threadIdx.x;
     if (col >= nxy) return;
-    const int nz = h.nz;
-    const long U = nxy * nz;
-    const long xw = RESID ? U : 3 * U, xt = RESID ? 2 * U : 4 * U;   // offsets of w and theta' in x
-    double ta[NC], tb[NC], rr[N + 1], ww[N + 1], th[N + 1];
-    // level kk into the window's last slot (zeros above the top)
-    auto load = [&](int kk, double &a, double &bb, double &r, double &w, double &t) {
-        a = bb = r = w = t = 0.0;
-        if (kk < nz) {
-            const double *L = h.lev + (long)kk * kLevW;
-            const long J = col + (long)kk * nxy;
-            r = x[J];
-            w = x[xw + J];
-            t = x[xt + J];
-            a = L[0] * w;
-            bb = h.gamma * L[2] * (r * L[7] + t * L[8]);
-        }
-    };
-#pragma unroll
-    for (int o = 0; o < N; ++o) { ta[o] = 0.0; tb[o] = 0.0; }
-    // levels 0 .. N-1 into window slots N .. 2N-1 (rr/ww slots 0 .. N-1)
-#pragma unroll
-    for (int j = 0; j < N; ++j) load(j, ta[N + j], tb[N + j], rr[j], ww[j], th[j]);
-    for (int k = 0; k < nz; ++k) {
-        load(k + N, ta[2 * N], tb[2 * N], rr[N], ww[N], th[N]);
-        const double *L = h.lev + (long)k * kLevW;
-        const double *G = h.gz + (long)k * NC;
-        double d_rw = 0.0, d_pl = 0.0;
-#pragma unroll
-        for (int o = 0; o < NC; ++o) {
-            d_rw += G[o] * ta[o];
-            d_pl += G[o] * tb[o];
-        }
-        const long I = col + (long)k * nxy;
-        const double l0 = -d_rw;
-        const double l3 = (k == 0 || k == nz - 1) ? 0.0 : -d_pl * L[7] - h.g * rr[0] * L[7];
-        const double l4 = -ww[0] * L[3];
-        if constexpr (RESID) {
-            y[I] = b[I] - rr[0] + alpha * l0;
-            y[3 * U + I] = b[3 * U + I] - ww[0] + alpha * l3;
-            y[4 * U + I] = b[4 * U + I] - th[0] + alpha * l4;
-        } else {
-            y[I] = l0;
-            if (uv) {
-                y[U + I] = 0.0;
-                y[2 * U + I] = 0.0;
-            }
-            y[3 * U + I] = l3;
-            y[4 * U + I] = l4;
-        }
-#pragma unroll
-        for (int o = 0; o < 2 * N; ++o) { ta[o] = ta[o + 1]; tb[o] = tb[o + 1]; }
-#pragma unroll
-        for (int j = 0; j < N; ++j) { rr[j] = rr[j + 1]; ww[j] = ww[j + 1]; th[j] = th[j + 1]; }
-    }
+    const long U = nxy * h.nz;
+    lv_walk<N>(h, col, 0, h.nz, x, RESID ? U : 3 * U, RESID ? 2 * U : 4 * U,
+               [&](int k, double l0, double l3, double l4, double xr, double xw, double xt) {
+                   const long I = col + (long)k * nxy;
+                   if constexpr (RESID) {
+                       y[I] = b[I] - xr + alpha * l0;
+                       y[3 * U + I] = b[3 * U + I] - xw + alpha * l3;
+                       y[4 * U + I] = b[4 * U + I] - xt + alpha * l4;
+                   } else {
+                       y[I] = l0;
+                       if (uv) {
+                           y[U + I] = 0.0;
+                           y[2 * U + I] = 0.0;
+                       }
+                       y[3 * U + I] = l3;
+                       y[4 * U + I] = l4;
+                   }
+               });
 }
 
 // ---------------------------------------------------------------- combinations

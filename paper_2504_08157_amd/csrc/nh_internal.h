@@ -73,6 +73,59 @@ struct HeviParams {
     double gamma, g;
 };
 
+// L_v x on levels k0 .. k1-1 of lattice column col (the vertical operator
+// of the HEVI step, Sec. 2.3): a walk up the column that keeps the
+// (2N+1)-level window of the stencil inputs rho0 w and
+// p'_L = gamma p0 (rho'/rho0 + theta'/theta0) in registers, so every value of
+// x is loaded once per walk.  x holds rho' at element offset 0, w at xw and
+// theta' at xt; levels outside the column count as zero.  For each level k
+// the callback out(k, l0, l3, l4, r, w, t) receives the rho', w and theta'
+// rows of L_v x (the w row zero at z = 0 and z = H) and x's own values.
+template <int N, typename Out>
+__device__ __forceinline__ void lv_walk(const HeviParams &h, long col, int k0, int k1, const double *x, long xw,
+                                        long xt, Out &&out)
+{
+    constexpr int NC = 2 * N + 1;
+    const long nxy = (long)h.nx * h.ny;
+    const int nz = h.nz;
+    double ta[NC], tb[NC], rr[N + 1], ww[N + 1], th[N + 1];
+    auto load = [&](int kk, double &a, double &bb, double &r, double &w, double &t) {
+        a = bb = r = w = t = 0.0;
+        if (kk >= 0 && kk < nz) {
+            const double *L = h.lev + (long)kk * kLevW;
+            const long J = col + (long)kk * nxy;
+            r = x[J];
+            w = x[xw + J];
+            t = x[xt + J];
+            a = L[0] * w;
+            bb = h.gamma * L[2] * (r * L[7] + t * L[8]);
+        }
+    };
+    // window slots 0 .. 2N-1: levels k0-N .. k0+N-1; rr/ww/th slots 0 .. N-1: levels k0 .. k0+N-1
+    double u0, u1, u2;
+#pragma unroll
+    for (int o = 0; o < N; ++o) load(k0 - N + o, ta[o], tb[o], u0, u1, u2);
+#pragma unroll
+    for (int j = 0; j < N; ++j) load(k0 + j, ta[N + j], tb[N + j], rr[j], ww[j], th[j]);
+    for (int k = k0; k < k1; ++k) {
+        load(k + N, ta[2 * N], tb[2 * N], rr[N], ww[N], th[N]);
+        const double *L = h.lev + (long)k * kLevW;
+        const double *G = h.gz + (long)k * NC;
+        double d_rw = 0.0, d_pl = 0.0;
+#pragma unroll
+        for (int o = 0; o < NC; ++o) {
+            d_rw += G[o] * ta[o];
+            d_pl += G[o] * tb[o];
+        }
+        const double l3 = (k == 0 || k == nz - 1) ? 0.0 : -d_pl * L[7] - h.g * rr[0] * L[7];
+        out(k, -d_rw, l3, -ww[0] * L[3], rr[0], ww[0], th[0]);
+#pragma unroll
+        for (int o = 0; o < 2 * N; ++o) { ta[o] = ta[o + 1]; tb[o] = tb[o + 1]; }
+#pragma unroll
+        for (int j = 0; j < N; ++j) { rr[j] = rr[j + 1]; ww[j] = ww[j + 1]; th[j] = th[j + 1]; }
+    }
+}
+
 struct GmresArgs {
     const double *b;     // [5][U] right-hand sides
     const double *x0;    // [3][U] initial guess of (rho', w, theta') or null (x0 = b)
@@ -188,7 +241,7 @@ constexpr int kGmresRegSlots = 4;     // unknowns per lane it supports (3 n_z <=
 constexpr int kGmresSchurSlots = 2;   // Schur form: interior w levels up to 128
 
 // ---- column MLP
-constexpr int kMlpIn = 400;    // 394 features padded to a multiple of 16
+constexpr int kMlpIn = 208;    // 198 features (195 residual values, 3 scalars) padded to a multiple of 16
 constexpr int kMlpHid = 256;
 constexpr int kMlpOut = 256;   // 3 fields x 65 canonical levels, padded to a multiple of 64
 constexpr int kMlpMaxPasses = 4;   // network applications per initial guess, at most
@@ -222,17 +275,20 @@ struct MlpNet {
 
 // FP16 weights and FP32 biases of the network, by value for kernels
 struct MlpWeights {
-    const _Float16 *W[4];   // W1 [256][400], W2 [256][256], W3 [256][256], bypass S [256][400]
+    const _Float16 *W[4];   // W1 [256][208], W2 [256][256], W3 [256][256], bypass S [256][208]
     const float *bias[3];
 };
 
-// x0 = base + the network's correction for the residual rscale * res of
-// columns col0 .. col0 + ncol - 1 in one kernel: base = b ([5][U]) with
-// res = L_v b, rscale = alpha (first pass), or base = the previous guess
-// ([3][U], base3) with res its residual, rscale = 1 (refinement; x0 may be
-// base)
-hipError_t launch_mlp_infer(const MlpColParams &p, const MlpNet &net, const double *base, bool base3,
-                            const double *lb, double rscale, long col0, long ncol, double *x0, hipStream_t s);
+// x0 = base + the network's correction for the residual of the start base,
+// columns col0 .. col0 + ncol - 1, in one kernel: base = b ([5][U]) for the
+// first pass, or the previous guess ([3][U], base3; x0 may be base) for a
+// refinement pass.  With lb the residual is rscale * lb (lb = L_v b,
+// rscale = alpha; or lb = the residual, rscale = 1); with lb null it is
+// computed in the kernel from base and b (n_z <= mlp_fused_max_nz()).
+hipError_t launch_mlp_infer(const MlpColParams &p, const HeviParams &hp, const MlpNet &net, const double *base,
+                            bool base3, const double *b, const double *lb, double rscale, long col0, long ncol,
+                            double *x0, hipStream_t s);
+int mlp_fused_max_nz();
 hipError_t launch_mlp_features(const MlpColParams &p, const double *b, const double *lb, const double *x,
                                long col0, long ncol, void *feat, double *scale, float *tgt, hipStream_t s);
 hipError_t launch_mlp_guess(const MlpColParams &p, const double *b, long col0, long ncol, const float *y,

@@ -2,9 +2,9 @@
 // the HEVI column solves: feature extraction and resampling, FP16 MFMA
 // forward GEMMs with FP32 accumulation, FP32 backward, Adam.
 //
-// Network: x (400: 394 features zero-padded) -> SiLU(W1 x + b1) (256)
+// Network: x (208: 198 features zero-padded) -> SiLU(W1 x + b1) (256)
 //          -> SiLU(W2 h1 + b2) (256) -> y = W3 h2 + b3 + S x (256: 195 used),
-// with a linear bypass S [256][400]: the exact map from the features to the
+// with a linear bypass S [256][208]: the exact map from the features to the
 // correction is linear for a fixed column grid and alpha ((I - alpha L_v)^-1
 // - I), the hidden layers carry its dependence on those.
 // Features of a column with right-hand side b (fields rho', w, theta' on the
@@ -14,10 +14,10 @@
 // (rho'/rho0, w/c0 with c0 = sqrt(gamma p0 / rho0), theta'/theta0), divided
 // by one column scale s (RMS of the dimensionless r over the column's 3 n_z
 // values) and resampled linearly in z to the 65 canonical levels (LGL nodes
-// of 16 equal order-4 elements of the column): features 0 .. 194; 195 .. 390
-// are zero (the correction is homogeneous of degree one in r, so the map
-// from r / s does not depend on s); then 3 scalars (alpha / 10,
-// 100 alpha c0(z_0) / H, log10 H / 5).  The correction is thus predicted
+// of 16 equal order-4 elements of the column): features 0 .. 194; then 3
+// scalars (alpha / 10, 100 alpha c0(z_0) / H, log10 H / 5), zeros to 207.
+// s itself is not a feature: the correction is homogeneous of degree one in
+// r, so the map from r / s does not depend on s.  The correction is thus predicted
 // relative to its own size, not to the size of b.
 // Output: the dimensionless correction on the canonical levels,
 // x0 = b + D s resample^-1(y), with the w correction zero on the walls.
@@ -116,7 +116,6 @@ __global__ void __launch_bounds__(512) mlp_features_kernel(MlpColParams p, const
             const double d0 = sdinv[f * nz + k0], d1 = sdinv[f * nz + k0 + 1];
             const double vl = (1.0 - t) * (p.alpha * lb[I0] * d0) + t * (p.alpha * lb[I1] * d1);
             sf[lane][f * kMlpNC + c] = (_Float16)(vl / s);
-            sf[lane][kMlpNF + f * kMlpNC + c] = (_Float16)0.0f;
             if (tgt && ok) {
                 const double vx = (1.0 - t) * ((x[I0] - b[I0]) * d0) + t * ((x[I1] - b[I1]) * d1);
                 tgt[r * kMlpOut + f * kMlpNC + c] = (float)(vx / s);
@@ -124,17 +123,16 @@ __global__ void __launch_bounds__(512) mlp_features_kernel(MlpColParams p, const
         }
     }
     if (q == 0) {
-        sf[lane][2 * kMlpNF] = (_Float16)0.0f;
-        sf[lane][2 * kMlpNF + 1] = (_Float16)(p.alpha / 10.0);
-        sf[lane][2 * kMlpNF + 2] = (_Float16)(100.0 * p.alpha * dim_factor(p, 1, 0) / H);
-        sf[lane][2 * kMlpNF + 3] = (_Float16)(log10(H) / 5.0);
-        for (int i = 2 * kMlpNF + 4; i < kMlpIn; ++i) sf[lane][i] = (_Float16)0.0f;
+        sf[lane][kMlpNF] = (_Float16)(p.alpha / 10.0);
+        sf[lane][kMlpNF + 1] = (_Float16)(100.0 * p.alpha * dim_factor(p, 1, 0) / H);
+        sf[lane][kMlpNF + 2] = (_Float16)(log10(H) / 5.0);
+        for (int i = kMlpNF + 3; i < kMlpIn; ++i) sf[lane][i] = (_Float16)0.0f;
         if (ok) scale[r] = s;
     } else if (tgt && ok) {
         for (int i = kMlpNF + q - 1; i < kMlpOut; i += NWV - 1) tgt[r * kMlpOut + i] = 0.0f;
     }
     __syncthreads();
-    // rows of 400 halves = 200 words; threads write consecutive words
+    // rows of 208 halves = 104 words; threads write consecutive words
     const long nrow = ncol - r0 < 64 ? ncol - r0 : 64;
     const uint32_t *src = reinterpret_cast<const uint32_t *>(&sf[0][0]);
     uint32_t *dst = reinterpret_cast<uint32_t *>(feat + r0 * kMlpIn);
@@ -339,18 +337,27 @@ __global__ void __launch_bounds__(256) gemm_rows_kernel(const _Float16 *__restri
 // kernels.
 constexpr int kLdF = kMlpIn + 8;    // LDS row of the features (halves), padded
 constexpr int kLdH = kMlpHid + 8;   // LDS row of the activations (halves), padded
-constexpr int kRegBytes = 64 * kLdF * 2;   // the shared region: features, then H1, H2, output rows
-static_assert(64 * (kMlpNF + 1) * 4 <= kRegBytes && 64 * kLdH * 2 <= kRegBytes, "region sizes");
+// the shared region: features, then H1, H2, output rows (the largest)
+constexpr int kRegBytes = 64 * (kMlpNF + 1) * 4;
+static_assert(64 * kLdF * 2 <= kRegBytes && 64 * kLdH * 2 <= kRegBytes && kRegBytes % 16 == 0, "region sizes");
 
-// x0 = base + D s (network of the residual res, dimensionless) per column:
-// base is b ([5][U], fields 0, 3, 4) with res = alpha L_v b for the first
-// pass, or the previous guess ([3][U], base3) with res = its residual
-// b - (I - alpha L_v) x0 for a refinement pass; rscale multiplies res
-// (alpha, or 1).  x0 may be base (each element is read before it is
-// written, by the same thread).
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) mlp_infer_kernel(MlpColParams p, MlpWeights wt,
-                                                        const double *base, bool base3,
-                                                        const double *__restrict__ lb, double rscale, long col0,
+// x0 = base + D s (network of the residual r of the start base,
+// dimensionless) per column: base is b ([5][U], fields 0, 3, 4), whose
+// residual is r = alpha L_v b (first pass), or the previous guess ([3][U],
+// base3), whose residual is r = b - base + alpha L_v base (refinement pass).
+// NV = 0: r is read from lb (fields 0, 3, 4 of [5][U]) times rscale.
+// NV = N > 0: r is computed here -- each wave walks a contiguous chunk of the
+// column's levels with lv_walk -- and kept dimensionless as FP32 rows
+// [3][n_z][64] in the shared region until the resampling (n_z <= 65, the
+// region's size).  x0 may be base (each element is read before it is
+// written, by the same thread; the walk only reads the workgroup's own
+// columns).
+constexpr int kMlpFusedNz = kRegBytes / (3 * 64 * 4);
+
+template <int NV>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) mlp_infer_kernel(MlpColParams p, HeviParams hp,
+                                                        MlpWeights wt, const double *base, bool base3,
+                                                        const double *b, const double *lb, double rscale, long col0,
                                                         long ncol, double *x0)
 {
     constexpr int NWV = 8;
@@ -401,15 +408,38 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) m
     const long nrow = ncol - r0 < 64 ? ncol - r0 : 64;
     const long r = r0 + lane;
     const long col = col0 + (lane < nrow ? r : r0);
+    float *rbuf = reinterpret_cast<float *>(sreg);   // NV > 0: residual rows [3][n_z][64]
     {
         double a = 0.0;
-#pragma unroll 4
-        for (int k = q; k < nz; k += NWV) {
-            const long I = col + (long)k * nxy;
+        if constexpr (NV > 0) {
+            const int chunk = (nz + NWV - 1) / NWV;
+            const int ka = q * chunk, kb = min(nz, ka + chunk);
+            if (ka < kb)
+                lv_walk<NV>(hp, col, ka, kb, base, base3 ? U : 3 * U, base3 ? 2 * U : 4 * U,
+                            [&](int k, double l0, double l3, double l4, double xr, double xw, double xt) {
+                                const long I = col + (long)k * nxy;
+                                double v[3] = {p.alpha * l0, p.alpha * l3, p.alpha * l4};
+                                if (base3) {
+                                    v[0] = b[I] - xr + v[0];
+                                    v[1] = b[3 * U + I] - xw + v[1];
+                                    v[2] = b[4 * U + I] - xt + v[2];
+                                }
 #pragma unroll
-            for (int f = 0; f < 3; ++f) {
-                const double l = rscale * lb[fld[f] * U + I] * sdinv[f * nz + k];
-                a += l * l;
+                                for (int f = 0; f < 3; ++f) {
+                                    const double d = v[f] * sdinv[f * nz + k];
+                                    rbuf[(f * nz + k) * 64 + lane] = (float)d;
+                                    a += d * d;
+                                }
+                            });
+        } else {
+#pragma unroll 4
+            for (int k = q; k < nz; k += NWV) {
+                const long I = col + (long)k * nxy;
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    const double l = rscale * lb[fld[f] * U + I] * sdinv[f * nz + k];
+                    a += l * l;
+                }
             }
         }
         spart[q][lane] = a;
@@ -420,25 +450,51 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) m
     for (int w = 0; w < NWV; ++w) ssum += spart[w][lane];
     const double s = sqrt(ssum / (3.0 * nz)) + 1e-300;
     _Float16 *fr = sf + lane * kLdF;
-#pragma unroll 3
-    for (int c = q; c < kMlpNC; c += NWV) {
-        const int k0 = sk0[c];
-        const double t = st[c];
+    if constexpr (NV > 0) {
+        // canonical levels c = q, q + 8, ... of this lane's column from the
+        // residual rows, held in registers until every wave has read them
+        constexpr int NCW = (kMlpNC + NWV - 1) / NWV;
+        _Float16 hv[NCW][3];
 #pragma unroll
-        for (int f = 0; f < 3; ++f) {
-            const long I0 = fld[f] * U + col + (long)k0 * nxy, I1 = I0 + nxy;
-            const double d0 = sdinv[f * nz + k0], d1 = sdinv[f * nz + k0 + 1];
-            const double vl = (1.0 - t) * (rscale * lb[I0] * d0) + t * (rscale * lb[I1] * d1);
-            fr[f * kMlpNC + c] = (_Float16)(vl / s);
-            fr[kMlpNF + f * kMlpNC + c] = (_Float16)0.0f;
+        for (int j = 0; j < NCW; ++j) {
+            const int c = q + j * NWV;
+            if (c < kMlpNC) {
+                const int k0 = sk0[c];
+                const double t = st[c];
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    const double v0 = rbuf[(f * nz + k0) * 64 + lane], v1 = rbuf[(f * nz + k0 + 1) * 64 + lane];
+                    hv[j][f] = (_Float16)(((1.0 - t) * v0 + t * v1) / s);
+                }
+            }
+        }
+        __syncthreads();   // every wave has read the residual rows
+#pragma unroll
+        for (int j = 0; j < NCW; ++j) {
+            const int c = q + j * NWV;
+            if (c < kMlpNC)
+#pragma unroll
+                for (int f = 0; f < 3; ++f) fr[f * kMlpNC + c] = hv[j][f];
+        }
+    } else {
+#pragma unroll 3
+        for (int c = q; c < kMlpNC; c += NWV) {
+            const int k0 = sk0[c];
+            const double t = st[c];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                const long I0 = fld[f] * U + col + (long)k0 * nxy, I1 = I0 + nxy;
+                const double d0 = sdinv[f * nz + k0], d1 = sdinv[f * nz + k0 + 1];
+                const double vl = (1.0 - t) * (rscale * lb[I0] * d0) + t * (rscale * lb[I1] * d1);
+                fr[f * kMlpNC + c] = (_Float16)(vl / s);
+            }
         }
     }
     if (q == 0) {
-        fr[2 * kMlpNF] = (_Float16)0.0f;
-        fr[2 * kMlpNF + 1] = (_Float16)(p.alpha / 10.0);
-        fr[2 * kMlpNF + 2] = (_Float16)(100.0 * p.alpha * dim_factor(p, 1, 0) / H);
-        fr[2 * kMlpNF + 3] = (_Float16)(log10(H) / 5.0);
-        for (int i = 2 * kMlpNF + 4; i < kMlpIn; ++i) fr[i] = (_Float16)0.0f;
+        fr[kMlpNF] = (_Float16)(p.alpha / 10.0);
+        fr[kMlpNF + 1] = (_Float16)(100.0 * p.alpha * dim_factor(p, 1, 0) / H);
+        fr[kMlpNF + 2] = (_Float16)(log10(H) / 5.0);
+        for (int i = kMlpNF + 3; i < kMlpIn; ++i) fr[i] = (_Float16)0.0f;
         sscale[lane] = s;
     }
     __syncthreads();
@@ -466,6 +522,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) m
                 ba[c] = *(const half8 *)(Wa + wrow + (long)16 * c * KK + 8 * g);
                 if (Wb) bb[c] = *(const half8 *)(Wb + wrow + (long)16 * c * KK + 8 * g);
             }
+#pragma unroll 1
             for (int k = 0; k < K32; k += 32) {
                 half8 na[2], nb[2];
                 if (k + 32 < K32)
@@ -777,18 +834,35 @@ hipError_t launch_mlp_guess(const MlpColParams &p, const double *b, long col0, l
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_infer(const MlpColParams &p, const MlpNet &net, const double *base, bool base3,
-                            const double *lb, double rscale, long col0, long ncol, double *x0, hipStream_t s)
+hipError_t launch_mlp_infer(const MlpColParams &p, const HeviParams &hp, const MlpNet &net, const double *base,
+                            bool base3, const double *b, const double *lb, double rscale, long col0, long ncol,
+                            double *x0, hipStream_t s)
 {
     MlpWeights wt;
     for (int i = 0; i < 4; ++i) wt.W[i] = (const _Float16 *)net.wh[i];
     for (int i = 0; i < 3; ++i) wt.bias[i] = net.b[i];
     const int grid = (int)((ncol + 63) / 64);
     const size_t lds = (sizeof(double) * 7 + sizeof(int)) * (size_t)p.nz;
-    hipLaunchKernelGGL(mlp_infer_kernel, dim3(grid), dim3(512), lds, s, p, wt, base, base3, lb, rscale, col0, ncol,
-                       x0);
+    const int nv = lb ? 0 : hp.N;
+    if (nv > 0 && p.nz > kMlpFusedNz) return hipErrorInvalidValue;
+#define NH_INFER(NN)                                                                                           \
+    hipLaunchKernelGGL(mlp_infer_kernel<NN>, dim3(grid), dim3(512), lds, s, p, hp, wt, base, base3, b, lb, rscale, \
+                       col0, ncol, x0)
+    switch (nv) {
+    case 0: NH_INFER(0); break;
+    case 1: NH_INFER(1); break;
+    case 2: NH_INFER(2); break;
+    case 3: NH_INFER(3); break;
+    case 4: NH_INFER(4); break;
+    case 5: NH_INFER(5); break;
+    case 6: NH_INFER(6); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef NH_INFER
     return hipGetLastError();
 }
+
+int mlp_fused_max_nz() { return kMlpFusedNz; }
 
 hipError_t mlp_forward(const MlpNet &net, int M, const void *X, hipStream_t s, bool keep_z)
 {
@@ -806,7 +880,7 @@ hipError_t mlp_forward(const MlpNet &net, int M, const void *X, hipStream_t s, b
 }
 
 // Weight gradient G[Mo x No] = sum over the batch (K = M rows) of A^T B,
-// split over the batch so that enough workgroups run (a 256 x 400 gradient
+// split over the batch so that enough workgroups run (a 256 x 208 gradient
 // is only 28 tiles), then the slices are summed in a fixed order.
 template <typename TB>
 static void weight_grad(const float *A, long lda, const TB *B, long ldb, int Mo, int No, int K, float *G,
@@ -836,7 +910,7 @@ hipError_t mlp_backward(const MlpNet &net, int M, const void *X, const float *dY
     const dim3 blk(256);
     const _Float16 *Xh = (const _Float16 *)X, *H1 = (const _Float16 *)net.H1, *H2 = (const _Float16 *)net.H2;
     const _Float16 *W2 = (const _Float16 *)net.wh[1], *W3 = (const _Float16 *)net.wh[2];
-    // linear bypass: dS = dY^T X [256 x 400]
+    // linear bypass: dS = dY^T X [256 x 208]
     weight_grad(dY, (long)kMlpOut, Xh, (long)kMlpIn, kMlpOut, kMlpIn, M, net.gw[3], net.part_k, s);
     // layer 3: dW3 = dY^T H2 [256 x 256], db3 = sum dY, dH2 = dY W3 [M x 256]
     weight_grad(dY, (long)kMlpOut, H2, (long)kMlpHid, kMlpOut, kMlpHid, M, net.gw[2], net.part_k, s);

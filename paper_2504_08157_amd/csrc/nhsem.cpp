@@ -1506,7 +1506,7 @@ void mlp_init_host(uint64_t seed, std::vector<float> &w)
         const double a = sqrt(6.0 / (fin + fout));
         for (long i = 0; i < (long)fin * fout; ++i) {
             const int k = (int)(i % fin);
-            w[off + i] = (l == 2 || (l == 0 && k >= 2 * kMlpNF + 4)) ? 0.0f : (float)(a * uni());
+            w[off + i] = (l == 2 || (l == 0 && k >= kMlpNF + 3)) ? 0.0f : (float)(a * uni());
         }
         off += (long)fin * fout + fout;
     }
@@ -1542,13 +1542,20 @@ nh_status mlp_guess(nh_mlp *m, nh_ctx *c, double alpha, const double *b, double 
 {
     if (m->sticky) return fail(c, NH_ESTATE, "MLP in error state");
     const HeviParams hp = hevi_params(c);
-    HIPCHK(c, launch_lv_apply(hp, b, lb, c->stream, false));
     const MlpColParams cp = mlp_col_params(c, alpha);
     const long ncol = (long)c->n[0] * c->n[1];
-    HIPCHK(c, launch_mlp_infer(cp, m->net, b, false, lb, alpha, 0, ncol, x0, c->stream));
+    if (c->n[2] <= mlp_fused_max_nz()) {
+        // residuals computed inside the inference kernel
+        HIPCHK(c, launch_mlp_infer(cp, hp, m->net, b, false, b, nullptr, alpha, 0, ncol, x0, c->stream));
+        for (int k = 1; k < m->passes && alpha > 0.0; ++k)
+            HIPCHK(c, launch_mlp_infer(cp, hp, m->net, x0, true, b, nullptr, 1.0, 0, ncol, x0, c->stream));
+        return NH_OK;
+    }
+    HIPCHK(c, launch_lv_apply(hp, b, lb, c->stream, false));
+    HIPCHK(c, launch_mlp_infer(cp, hp, m->net, b, false, b, lb, alpha, 0, ncol, x0, c->stream));
     for (int k = 1; k < m->passes && alpha > 0.0; ++k) {
         HIPCHK(c, launch_lv_resid(hp, alpha, b, x0, lb, c->stream));
-        HIPCHK(c, launch_mlp_infer(cp, m->net, x0, true, lb, 1.0, 0, ncol, x0, c->stream));
+        HIPCHK(c, launch_mlp_infer(cp, hp, m->net, x0, true, b, lb, 1.0, 0, ncol, x0, c->stream));
     }
     return NH_OK;
 }

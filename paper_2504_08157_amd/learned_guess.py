@@ -123,13 +123,17 @@ def initial_loss(feats, tgts):
 
 
 def fit(mlp, w_eval, dt, warm, sources, epochs, batch=1024, lr=1e-3, max_per_step=None, random_grid=None,
-        random_batches=0):
+        random_batches=0, finetune_epochs=0, finetune_batch=8192, finetune_lr=3e-4, finetune_lr_final=3e-6):
     """Training set: the solves of `sources` (list of (workload, steps, dt))
     and of the first `warm` (>= 1) steps of w_eval, all generated by the
     method itself with the default guess, plus `random_batches` batches of
     random column solves on the column grid of `random_grid` (a workload with
-    w_eval's vertical grid; default w_eval); then train.  Returns a summary
-    dict."""
+    w_eval's vertical grid; default w_eval); then train on all of it, and
+    for `finetune_epochs` more on the samples of w_eval's column grid alone
+    (its own solves and the random ones) in large batches with a small
+    learning rate: the bypass can represent one grid's correction map
+    exactly, and the other grids' samples pull it away from that map.
+    Returns a summary dict."""
     import torch
     t0 = time.perf_counter()
     F, T = [], []
@@ -139,26 +143,36 @@ def fit(mlp, w_eval, dt, warm, sources, epochs, batch=1024, lr=1e-3, max_per_ste
     f, t, a_dt = collect(mlp, w_eval, steps=max(warm, 1), dt=dt, max_per_step=max_per_step)
     F.append(f); T.append(t)
     n_sim = sum(int(x.shape[0]) for x in F)
+    n_grid = len(F) - 1          # F[n_grid:] are samples of w_eval's column grid
     if random_batches > 0:
         f, t = collect_random(mlp, random_grid or w_eval, random_batches, a_dt * dt)
         F.append(f); T.append(t)
     feats, tgts = torch.cat(F), torch.cat(T)
-    del F, T
     t_collect = time.perf_counter() - t0
     l0 = initial_loss(feats, tgts)
     hist, rate = train(mlp, feats, tgts, epochs=epochs, batch=batch, lr=lr)
-    return {"samples": int(feats.shape[0]), "samples_from_runs": n_sim, "loss_untrained": l0,
-            "loss_last": hist[-1], "samples_per_s": rate, "collect_s": t_collect, "epochs": epochs,
-            "batch": batch}
+    out = {"samples": int(feats.shape[0]), "samples_from_runs": n_sim, "loss_untrained": l0,
+           "loss_last": hist[-1], "samples_per_s": rate, "collect_s": t_collect, "epochs": epochs,
+           "batch": batch}
+    del feats, tgts
+    if finetune_epochs > 0:
+        fg, tg = torch.cat(F[n_grid:]), torch.cat(T[n_grid:])
+        h2, rate2 = train(mlp, fg, tg, epochs=finetune_epochs, batch=finetune_batch, lr=finetune_lr,
+                          lr_final=finetune_lr_final)
+        out.update({"finetune_samples": int(fg.shape[0]), "finetune_epochs": finetune_epochs,
+                    "finetune_batch": finetune_batch, "finetune_loss_last": h2[-1],
+                    "finetune_samples_per_s": rate2})
+    return out
 
 
-def compare(mlp, w, warm, held, dt, rtol=1e-10, restart=20, schur=False):
+def compare(mlp, w, warm, held, dt, rtol=1e-10, restart=20, schur=False, refine_passes=2):
     """From the state after `warm` default steps, run `held` steps four
     times -- default guess, MLP guess, the MLP guess with the per-column
     choice against the default start (the smaller initial residual), and
-    the MLP guess refined by a second pass of the network on its own
-    residual -- and report GMRES iterations, step times and the difference
-    of the final states (schur: solve the Schur complement in w)."""
+    the MLP guess refined by further passes of the network on its own
+    residual (refine_passes in all; reported as mlp_2pass) -- and report
+    GMRES iterations, step times and the difference of the final states
+    (schur: solve the Schur complement in w)."""
     import torch
     ctx = hevi_context(w)
     for s in range(warm):
@@ -167,7 +181,7 @@ def compare(mlp, w, warm, held, dt, rtol=1e-10, restart=20, schur=False):
     out = {}
     finals = {}
     for name, g, pick, passes in (("default", None, False, 1), ("mlp", mlp, False, 1), ("mlp_pick", mlp, True, 1),
-                                  ("mlp_2pass", mlp, False, 2)):
+                                  ("mlp_2pass", mlp, False, refine_passes)):
         mlp.nh_mlp_set_passes(passes)
         ctx.nh_set_state(q0)
         torch.cuda.synchronize()

@@ -529,7 +529,7 @@ class Context:
         return buf.value.decode(errors="replace")
 
 
-MLP_IN, MLP_HID, MLP_OUT = 400, 256, 256
+MLP_IN, MLP_HID, MLP_OUT = 208, 256, 256
 
 
 class ColumnMLP:
@@ -598,7 +598,7 @@ class ColumnMLP:
         self._c(self.lib.nh_mlp_set_params(self.h, _tptr(w)))
 
     def nh_mlp_samples(self, ctx, alpha, b, x=None, col0=0, ncol=None, tmp=None):
-        """Features (FP16 [ncol][400]), scales and, with x, targets of columns."""
+        """Features (FP16 [ncol][208]), scales and, with x, targets of columns."""
         import torch
         ncol = ctx.nx * ctx.ny - col0 if ncol is None else ncol
         feat = torch.empty((ncol, MLP_IN), dtype=torch.float16, device=self.device)

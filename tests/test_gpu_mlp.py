@@ -97,15 +97,21 @@ def test_features_match_oracle(oracle_mod):
     assert _rel(tgt.cpu().numpy(), to) <= 1e-6
 
 
-def test_fused_guess_matches_separate_kernels(oracle_mod):
+@pytest.mark.parametrize("nelz,tol", [(4, 5e-3), (17, 1e-12)], ids=["residual_in_kernel", "residual_from_lv"])
+def test_fused_guess_matches_separate_kernels(oracle_mod, nelz, tol):
     """The one-kernel inference of nh_mlp_guess (features, network and
-    resampling in LDS) against the separate feature and forward kernels
-    followed by the oracle's resampling, on a ragged column count (117)."""
+    resampling in LDS) against the separate L_v, feature and forward kernels
+    followed by the oracle's resampling, on a ragged column count (117).
+    Columns of at most 65 levels (n_z = 17 here) compute their residual
+    inside the inference kernel and keep it as FP32 between the walk and
+    the resampling, so a feature can round to the neighbouring FP16 value:
+    the correction agrees to that rounding.  Taller columns (n_z = 69) read
+    L_v b from the separate kernel: the same arithmetic, to 1e-12."""
     import torch
     from paper_2504_08157_amd import nhsem
     ph = W.Physics()
-    mesh = W.MeshSpec((3, 2, 4), 4, W.uniform_edges(0, 30e3, 3), W.uniform_edges(0, 20e3, 2),
-                      W.stretched_edges(0, 15e3, 4, seed=8), (True, True))
+    mesh = W.MeshSpec((3, 2, nelz), 4, W.uniform_edges(0, 30e3, 3), W.uniform_edges(0, 20e3, 2),
+                      W.stretched_edges(0, 15e3, nelz, seed=8), (True, True))
     ctx = nhsem.Context(mesh, ph)
     orc = oracle_mod.Oracle(mesh, ph)
     g = ctx.nh_lattice_coords(); o = orc.lattice_coords()
@@ -129,7 +135,7 @@ def test_fused_guess_matches_separate_kernels(oracle_mod):
     ref = MO.column_guess(sel(bq), y, o[2], D, scale.cpu().numpy())
     corr, corr_ref = x0 - sel(bq), ref - sel(bq)
     assert np.linalg.norm(corr_ref) > 1e-3 * np.linalg.norm(sel(bq))   # the network changes the guess
-    assert _rel(corr, corr_ref) <= 1e-12, _rel(corr, corr_ref)
+    assert _rel(corr, corr_ref) <= tol, _rel(corr, corr_ref)
 
 
 def test_fused_guess_and_forward_repeatable():
@@ -253,8 +259,9 @@ def test_adam_step_matches_oracle():
 
 
 def _canonical_column_case(oracle_mod, nel=(2, 2, 16)):
-    """A context and oracle whose column grid is the canonical one (16 equal
-    order-4 elements), so feature resampling is the identity."""
+    """A context and oracle with nel[2] equal order-4 elements in z over
+    20 km; with 16 the column grid is the canonical one and feature
+    resampling is the identity."""
     from paper_2504_08157_amd import nhsem
     w = W.cfg_hevi()
     mesh = W.MeshSpec(nel, 4, W.uniform_edges(0, 40e3, nel[0]), W.uniform_edges(0, 40e3, nel[1]),
@@ -282,14 +289,17 @@ def _exact_map_params(m, orc, o, ph, alpha, oracle_mod):
     return MO.flatten(parts).astype(np.float32)
 
 
-def test_refinement_pass_matches_oracle(oracle_mod):
+@pytest.mark.parametrize("nelz", [16, 17], ids=["residual_in_kernel", "residual_walk_kernel"])
+def test_refinement_pass_matches_oracle(oracle_mod, nelz):
     """Second pass of nh_mlp_guess (the network on the residual of its first
     guess) against the oracle: the residual from the oracle's L_v, features,
     the GPU forward on them, the oracle's resampling; random parameters,
-    the pass-2 correction to FP16 rounding of the features."""
+    the pass-2 correction to FP16 rounding of the features.  n_z = 65: the
+    residual computed inside the inference kernel; n_z = 69: by the
+    residual form of the L_v walk, then the inference kernel."""
     import torch
     from paper_2504_08157_amd import nhsem
-    ctx, orc, o, ph = _canonical_column_case(oracle_mod, nel=(3, 2, 16))
+    ctx, orc, o, ph = _canonical_column_case(oracle_mod, nel=(3, 2, nelz))
     m = nhsem.ColumnMLP(max_batch=128)
     rng = np.random.default_rng(21)
     m.nh_mlp_set_params(torch.from_numpy(rng.normal(scale=0.03, size=m.nparam).astype(np.float32)).cuda())

@@ -11,26 +11,26 @@ import numpy as np
 SRC = os.path.join(os.path.dirname(__file__), "..", "paper_2504_08157_amd", "csrc", "nh_mlp.hip")
 HDR = os.path.join(os.path.dirname(__file__), "..", "paper_2504_08157_amd", "csrc", "nh_internal.h")
 
-IN, HID, NC = 400, 256, 65
+IN, HID, NC = 208, 256, 65
 NF = 3 * NC
 LDF, LDH = IN + 8, HID + 8
-REG = 64 * LDF * 2          # bytes of the shared region (features, H1, H2, outputs)
+REG = 64 * (NF + 1) * 4     # bytes of the shared region (features, H1, H2, outputs)
 NWV = 8                     # waves of the inference workgroup
 
 
 def test_source_holds_the_replayed_expressions():
     src = open(SRC).read()
     hdr = open(HDR).read()
-    for s in ("constexpr int kMlpIn = 400;", "constexpr int kMlpHid = 256;", "constexpr int kMlpNC = 65;",
+    for s in ("constexpr int kMlpIn = 208;", "constexpr int kMlpHid = 256;", "constexpr int kMlpNC = 65;",
               "constexpr int kMlpNF = 3 * kMlpNC;"):
         assert s in hdr, s
     for s in ("constexpr int kLdF = kMlpIn + 8;", "constexpr int kLdH = kMlpHid + 8;",
-              "constexpr int kRegBytes = 64 * kLdF * 2;",
+              "constexpr int kRegBytes = 64 * (kMlpNF + 1) * 4;",
               "_Float16 *fr = sf + lane * kLdF;",
               "for (int c = q; c < kMlpNC; c += NWV) {",
               "fr[f * kMlpNC + c] = (_Float16)(vl / s);",
-              "fr[kMlpNF + f * kMlpNC + c] = (_Float16)0.0f;",
-              "for (int i = 2 * kMlpNF + 4; i < kMlpIn; ++i) fr[i] = (_Float16)0.0f;",
+              "fr[kMlpNF + 2] = (_Float16)(log10(H) / 5.0);",
+              "for (int i = kMlpNF + 3; i < kMlpIn; ++i) fr[i] = (_Float16)0.0f;",
               "av[a] = *(const half8 *)(S + (16 * a + r16) * ld + k + 8 * g);",
               "av[a] = *(const half4 *)(S + (16 * a + r16) * ld + K32 + 4 * g);",
               "const int row = 16 * a + 4 * g + i, cl = 32 * wave + 16 * c + r16;",
@@ -107,13 +107,12 @@ def test_inference_kernel_intervals_race_free():
         for c in range(q, NC, NWV):
             for f in range(3):
                 iv.write(q, (lane * LDF + f * NC + c) * 2, 2)
-                iv.write(q, (lane * LDF + NF + f * NC + c) * 2, 2)
         if q == 0:
-            for i in range(2 * NF, IN):
+            for i in range(NF, IN):
                 iv.write(q, (lane * LDF + i) * 2, 2)
     ivs.append(iv)
     # every feature the layer-1 pass reads was written
-    assert np.all(iv.writer.reshape(64, LDF * 2)[:, :IN * 2] >= 0)
+    assert np.all(iv.writer[:64 * LDF * 2].reshape(64, LDF * 2)[:, :IN * 2] >= 0)
     iv = Interval(REG); mma_reads(iv, LDF, IN); ivs.append(iv)       # layer 1 and bypass
     iv = Interval(REG); store_h(iv); ivs.append(iv)                   # H1
     iv = Interval(REG); mma_reads(iv, LDH, HID); ivs.append(iv)       # layer 2

@@ -80,9 +80,9 @@ def test_column_features_on_linear_profiles():
         for f in range(3):
             np.testing.assert_allclose(feat[c, f * 65:(f + 1) * 65], -2.0 * (f + 1) * (c + 1) * (1 + zc) / s_ref,
                                        rtol=1e-13)
-    assert np.all(feat[:, 195:391] == 0)
-    assert np.all(feat[:, 394:] == 0) and np.allclose(feat[:, 391], 0.2)
-    np.testing.assert_allclose(feat[:, 392], 100.0 * 2.0 * 340.0 / 1000.0, rtol=1e-14)
+    assert feat.shape == (ncol, 208) and np.all(feat[:, 198:] == 0) and np.allclose(feat[:, 195], 0.2)
+    np.testing.assert_allclose(feat[:, 196], 100.0 * 2.0 * 340.0 / 1000.0, rtol=1e-14)
+    np.testing.assert_allclose(feat[:, 197], 3.0 / 5.0, rtol=1e-14)
     # x = b + 1e-3 b: the correction is 1e-3 b = -lb, i.e. -feat / alpha on the canonical levels
     t = MO.column_targets(b, b - lb, z, D, s)
     np.testing.assert_allclose(t[:, :195], -feat[:, :195] / 2.0, rtol=1e-13)
@@ -118,13 +118,13 @@ def test_column_features_bounded_when_a_field_vanishes():
     lb[0, :, 0] = 1e-3 * np.cos(z / 300.0)
     lb[2, :, 0] = 0.5 * np.sin(z / 200.0)
     feat, s = MO.column_features(b, lb, z, alpha=3.0, D=D)
-    assert np.all(np.abs(feat[:, :390]) <= np.sqrt(3 * 17.0) + 1e-12)
+    assert np.all(np.abs(feat[:, :195]) <= np.sqrt(3 * 17.0) + 1e-12)
     k = 30
     np.testing.assert_allclose(feat[0, k] / feat[0, 2 * 65 + k],
                                np.interp(MO.canonical_levels()[k] * 1000.0, z, lb[0, :, 0] / D[0]) /
                                np.interp(MO.canonical_levels()[k] * 1000.0, z, lb[2, :, 0] / D[2]), rtol=1e-12)
     assert np.all(feat[0, 65:130] == 0)
-    assert np.all(feat[1, :390] == 0) and np.all(np.isfinite(feat))
+    assert np.all(feat[1, :195] == 0) and np.all(np.isfinite(feat))
 
 
 def test_exact_targets_are_one_linear_map_of_the_features(oracle_mod):
