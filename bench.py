@@ -251,6 +251,8 @@ def parse():
                     help="batches of random column right-hand sides in the MLP training data (hevi mode)")
     ap.add_argument("--mlp-finetune-epochs", type=int, default=120,
                     help="further epochs on the evaluated column grid's samples alone, batch 8192 (hevi mode)")
+    ap.add_argument("--mlp-finetune-decay", type=float, default=3.0,
+                    help="decoupled weight decay of the hidden path during the fine-tune epochs (hevi mode)")
     ap.add_argument("--gmres-restart", type=int, default=10, help="Krylov vectors per GMRES cycle (hevi mode)")
     return ap.parse_args()
 
@@ -345,7 +347,8 @@ def bench_hevi(args):
     wr.mesh = W._tc_mesh(32, 32, w.mesh.nel[2])   # same column grid, 16384 columns per random batch
     tr = LG.fit(mlp, w, w.dt, warm, [(W.cfg_tc_small(), 2, w.dt), (W.cfg_bubble(), 2, 0.5)],
                 epochs=args.mlp_epochs, batch=1024, lr=1e-3, max_per_step=24576, random_grid=wr,
-                random_batches=args.mlp_random_batches, finetune_epochs=args.mlp_finetune_epochs)
+                random_batches=args.mlp_random_batches, finetune_epochs=args.mlp_finetune_epochs,
+                finetune_decay=args.mlp_finetune_decay)
     res = LG.compare(mlp, w, warm=warm, held=args.steps, dt=w.dt, restart=args.gmres_restart)
     # the same steps with the column systems solved through their Schur
     # complement in w (restart 10 only)

@@ -488,6 +488,13 @@ nh_status nh_mlp_samples(nh_mlp *m, nh_ctx *ctx, double alpha, const double *dev
                          int64_t col0, int64_t ncol, void *dev_feat, double *dev_scale, float *dev_tgt,
                          double *dev_tmp);
 
+/* Decoupled weight decay (Loshchilov & Hutter, AdamW) applied by every
+   later Adam step (nh_mlp_adam_step, nh_mlp_train_step) to the hidden
+   path's parameters W1, b1, W2, b2, W3, b3 -- not to the bypass S:
+   w -= lr (m_hat / (sqrt(v_hat) + eps) + wd w).  Default 0 (plain Adam).
+   NH_EINVAL for wd < 0 or non-finite. */
+nh_status nh_mlp_set_decay(nh_mlp *m, float wd);
+
 /* Network applications per initial guess (default 1): pass 1 predicts the
    correction of the default start b from its residual alpha L_v b; each
    further pass applies the same network to the residual

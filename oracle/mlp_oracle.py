@@ -88,12 +88,18 @@ def mse_grad(y, t):
     return 2.0 * (y - t) / y.size
 
 
-def adam(w, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
+def adam(w, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8, wd=0.0, ndecay=0):
+    """Adam with bias correction; the first ndecay parameters also take
+    decoupled weight decay wd (Loshchilov & Hutter 2019, AdamW):
+    w - lr (m_hat / (sqrt(v_hat) + eps) + wd w)."""
     m = b1 * m + (1 - b1) * g
     v = b2 * v + (1 - b2) * g * g
     mh = m / (1 - b1 ** step)
     vh = v / (1 - b2 ** step)
-    return w - lr * mh / (np.sqrt(vh) + eps), m, v
+    u = mh / (np.sqrt(vh) + eps)
+    d = np.zeros_like(w)
+    d[:ndecay] = wd * w[:ndecay]
+    return w - lr * (u + d), m, v
 
 
 def canonical_levels():

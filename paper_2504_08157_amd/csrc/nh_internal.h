@@ -55,11 +55,19 @@ struct GeomParams {
 };
 
 hipError_t launch_stage(int N, int precision, int variant, const StageParams &p, hipStream_t s);
-// Grouped stage launch over `nitems` (instance, tile) items; with a device
-// counter (zeroed beforehand) the persistent form with at most persist_grid
-// workgroups, else one workgroup per item.
+// Work items of one order group, split into one list per XCD: list x is
+// work[off[x] .. off[x + 1]), x = 0 .. kXcds - 1 (workgroup b of a launch
+// runs on XCD b mod kXcds).
+constexpr int kXcds = 8;
+struct XcdLists {
+    int off[kXcds + 1];
+};
+// Grouped stage launch over the (instance, tile) items of `xl`; with device
+// counters (kXcds, zeroed beforehand) the persistent form with at most
+// persist_grid workgroups, else one workgroup per item (kXcds * maxlen
+// workgroups, maxlen the longest list).
 hipError_t launch_stage_batched(int N, int precision, int variant, const StageParams *P, const int2 *work,
-                                int nitems, int *counter, int persist_grid, hipStream_t s);
+                                const XcdLists &xl, int maxlen, int *counter, int persist_grid, hipStream_t s);
 hipError_t launch_zero_ints(int *p, int n, hipStream_t s);
 struct WallParams {
     int nx, ny, nz, perx, pery;
@@ -296,7 +304,9 @@ hipError_t launch_mlp_guess(const MlpColParams &p, const double *b, long col0, l
 hipError_t mlp_forward(const MlpNet &net, int M, const void *X, hipStream_t s, bool keep_z = true);
 hipError_t mlp_backward(const MlpNet &net, int M, const void *X, const float *dY, hipStream_t s);
 hipError_t mlp_loss_grad(const MlpNet &net, int M, const float *T, float *loss, hipStream_t s);
-hipError_t mlp_adam(const MlpNet &net, float lr, float b1, float b2, float eps, int step, hipStream_t s);
+// Adam step; wd > 0 adds decoupled weight decay on the hidden path's
+// parameters (W1, b1, W2, b2, W3, b3), not on the bypass S
+hipError_t mlp_adam(const MlpNet &net, float lr, float b1, float b2, float eps, int step, float wd, hipStream_t s);
 hipError_t mlp_sync_half(const MlpNet &net, hipStream_t s);
 
 hipError_t launch_add_forcing(const WallParams &wp, int field, double c, const double *f0, const double *f1,

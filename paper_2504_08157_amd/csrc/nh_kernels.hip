@@ -482,15 +482,43 @@ __global__ void __launch_bounds__((StageShape<N, AX, AY>::NT)) stage_kernel(cons
     stage_body<N, AX, AY, T>(p, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x);
 }
 
-// Batched form: workgroup b takes work item work[b] = (instance, tile) from a
-// list sorted by cost (longest columns first) and reads that instance's
-// parameters from a device descriptor table.
+// Batched form: the (instance, tile) items of an order group sit in one list
+// per XCD, each a contiguous run of tiles of the cost-sorted sequence (so the
+// workgroups one XCD runs at a time are neighbours that share halos through
+// its L2); workgroup b runs on XCD x = b mod 8 and takes item b / 8 of list x
+// (none past its end), and reads the instance's parameters from a device
+// descriptor table.
+__device__ __forceinline__ int xcd_item(const XcdLists &xl, int b)
+{
+    const int x = b & (kXcds - 1), it = xl.off[x] + b / kXcds;
+    return it < xl.off[x + 1] ? it : -1;
+}
+
 template <int N, int AX, int AY, typename T>
 __global__ void __launch_bounds__((StageShape<N, AX, AY>::NT))
-stage_kernel_batched(const StageParams *__restrict__ P, const int2 *__restrict__ work)
+stage_kernel_batched(const StageParams *__restrict__ P, const int2 *__restrict__ work, const XcdLists xl)
 {
-    const int2 it = work[blockIdx.x];
+    const int i = xcd_item(xl, blockIdx.x);
+    if (i < 0) return;
+    const int2 it = work[i];
     stage_body<N, AX, AY, T>(P[it.x], it.y, threadIdx.x);
+}
+
+// Next item of a persistent workgroup whose home XCD list is `home`: from the
+// list of the first XCD (home, home + 1, ...) that is not exhausted, through
+// that list's device counter (one vector atomic per attempt, thread 0
+// only); `tried` counts the lists found exhausted and only grows, so every
+// workgroup reaches -1 (all lists exhausted) after at most one more attempt
+// per list.
+__device__ __forceinline__ int next_item(const XcdLists &xl, int *counter, int home, int &tried)
+{
+    while (tried < kXcds) {
+        const int x = (home + tried) & (kXcds - 1);
+        const int j = __hip_atomic_fetch_add(counter + x, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (xl.off[x] + j < xl.off[x + 1]) return xl.off[x] + j;
+        ++tried;
+    }
+    return -1;
 }
 
 // ---------------------------------------------------------------- stage, node-class form
@@ -973,30 +1001,35 @@ __global__ void __launch_bounds__((ClsShape<N, AX, AY>::NT)) stage_kernel_cls(co
 
 template <int N, int AX, int AY, typename T>
 __global__ void __launch_bounds__((ClsShape<N, AX, AY>::NT))
-stage_kernel_cls_batched(const StageParams *__restrict__ P, const int2 *__restrict__ work)
+stage_kernel_cls_batched(const StageParams *__restrict__ P, const int2 *__restrict__ work, const XcdLists xl)
 {
-    const int2 it = work[blockIdx.x];
+    const int i = xcd_item(xl, blockIdx.x);
+    if (i < 0) return;
+    const int2 it = work[i];
     stage_body_cls<N, AX, AY, T>(P[it.x], it.y, threadIdx.x);
 }
 
 // Persistent batched forms: a grid of at most one workgroup per CU, each
-// workgroup taking (instance, tile) items from the cost-sorted list in order
-// through a device counter (one vector atomic per item, by thread 0) until
-// the list is exhausted -- every workgroup reaches the exit.  The counter is
-// zeroed by a fill kernel before the launch (inside the captured graph).
+// workgroup taking (instance, tile) items in order from its own XCD's list,
+// then from the other lists once its own is exhausted (next_item), until
+// every list is exhausted -- every workgroup reaches the exit.  The counters
+// are zeroed by a fill kernel before the launch (inside the captured graph).
 template <int N, int AX, int AY, typename T>
 __global__ void __launch_bounds__((StageShape<N, AX, AY>::NT))
-stage_kernel_persist(const StageParams *__restrict__ P, const int2 *__restrict__ work, int nitems, int *counter)
+stage_kernel_persist(const StageParams *__restrict__ P, const int2 *__restrict__ work, const XcdLists xl,
+                     int *counter)
 {
     __shared__ int item;
+    int tried = 0;
+    const int home = blockIdx.x & (kXcds - 1);
     for (;;) {
-        if (threadIdx.x == 0) item = __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0) item = next_item(xl, counter, home, tried);
         __syncthreads();
         // uniform across the workgroup: readfirstlane lets the compiler keep
         // the item's descriptor in scalar registers
         const int it = __builtin_amdgcn_readfirstlane(item);
         __syncthreads();
-        if (it >= nitems) break;
+        if (it < 0) break;
         // the thread index is passed laundered, so that per-thread arithmetic
         // of the body is not hoisted out of the item loop (and held in
         // registers across items)
@@ -1010,17 +1043,20 @@ stage_kernel_persist(const StageParams *__restrict__ P, const int2 *__restrict__
 
 template <int N, int AX, int AY, typename T>
 __global__ void __launch_bounds__((ClsShape<N, AX, AY>::NT))
-stage_kernel_cls_persist(const StageParams *__restrict__ P, const int2 *__restrict__ work, int nitems, int *counter)
+stage_kernel_cls_persist(const StageParams *__restrict__ P, const int2 *__restrict__ work, const XcdLists xl,
+                         int *counter)
 {
     __shared__ int item;
+    int tried = 0;
+    const int home = blockIdx.x & (kXcds - 1);
     for (;;) {
-        if (threadIdx.x == 0) item = __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0) item = next_item(xl, counter, home, tried);
         __syncthreads();
         // uniform across the workgroup: readfirstlane lets the compiler keep
         // the item's descriptor in scalar registers
         const int it = __builtin_amdgcn_readfirstlane(item);
         __syncthreads();
-        if (it >= nitems) break;
+        if (it < 0) break;
         int tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
         const int2 w = work[it];
@@ -1077,13 +1113,14 @@ static void launch_cls(int precision, const StageParams &p, hipStream_t s)
 }
 
 template <int N, int AX, int AY>
-static void launch_cls_batched(int precision, const StageParams *P, const int2 *work, int nitems, hipStream_t s)
+static void launch_cls_batched(int precision, const StageParams *P, const int2 *work, const XcdLists &xl,
+                               int maxlen, hipStream_t s)
 {
-    const dim3 grid(nitems), block(ClsShape<N, AX, AY>::NT);
+    const dim3 grid(kXcds * maxlen), block(ClsShape<N, AX, AY>::NT);
     if (precision == 0)
-        hipLaunchKernelGGL((stage_kernel_cls_batched<N, AX, AY, double>), grid, block, 0, s, P, work);
+        hipLaunchKernelGGL((stage_kernel_cls_batched<N, AX, AY, double>), grid, block, 0, s, P, work, xl);
     else
-        hipLaunchKernelGGL((stage_kernel_cls_batched<N, AX, AY, float>), grid, block, 0, s, P, work);
+        hipLaunchKernelGGL((stage_kernel_cls_batched<N, AX, AY, float>), grid, block, 0, s, P, work, xl);
 }
 
 template <int N, int AX, int AY>
@@ -1097,55 +1134,59 @@ static void launch_one(int precision, const StageParams &p, hipStream_t s)
 }
 
 template <int N, int AX, int AY>
-static void launch_batched_one(int precision, const StageParams *P, const int2 *work, int nitems, int *counter,
-                               int persist_grid, hipStream_t s)
+static void launch_batched_one(int precision, const StageParams *P, const int2 *work, const XcdLists &xl, int maxlen,
+                               int *counter, int persist_grid, hipStream_t s)
 {
     const dim3 block(StageShape<N, AX, AY>::NT);
+    const int nitems = xl.off[kXcds];
     if (counter) {
         const dim3 grid(nitems < persist_grid ? nitems : persist_grid);
         if (precision == 0)
-            hipLaunchKernelGGL((stage_kernel_persist<N, AX, AY, double>), grid, block, 0, s, P, work, nitems, counter);
+            hipLaunchKernelGGL((stage_kernel_persist<N, AX, AY, double>), grid, block, 0, s, P, work, xl, counter);
         else
-            hipLaunchKernelGGL((stage_kernel_persist<N, AX, AY, float>), grid, block, 0, s, P, work, nitems, counter);
+            hipLaunchKernelGGL((stage_kernel_persist<N, AX, AY, float>), grid, block, 0, s, P, work, xl, counter);
         return;
     }
-    const dim3 grid(nitems);
+    const dim3 grid(kXcds * maxlen);
     if (precision == 0)
-        hipLaunchKernelGGL((stage_kernel_batched<N, AX, AY, double>), grid, block, 0, s, P, work);
+        hipLaunchKernelGGL((stage_kernel_batched<N, AX, AY, double>), grid, block, 0, s, P, work, xl);
     else
-        hipLaunchKernelGGL((stage_kernel_batched<N, AX, AY, float>), grid, block, 0, s, P, work);
+        hipLaunchKernelGGL((stage_kernel_batched<N, AX, AY, float>), grid, block, 0, s, P, work, xl);
 }
 
 template <int N, int AX, int AY>
-static void launch_cls_batched_any(int precision, const StageParams *P, const int2 *work, int nitems, int *counter,
-                                   int persist_grid, hipStream_t s)
+static void launch_cls_batched_any(int precision, const StageParams *P, const int2 *work, const XcdLists &xl,
+                                   int maxlen, int *counter, int persist_grid, hipStream_t s)
 {
     const dim3 block(ClsShape<N, AX, AY>::NT);
+    const int nitems = xl.off[kXcds];
     if (counter) {
         const dim3 grid(nitems < persist_grid ? nitems : persist_grid);
         if (precision == 0)
-            hipLaunchKernelGGL((stage_kernel_cls_persist<N, AX, AY, double>), grid, block, 0, s, P, work, nitems,
-                               counter);
+            hipLaunchKernelGGL((stage_kernel_cls_persist<N, AX, AY, double>), grid, block, 0, s, P, work, xl, counter);
         else
-            hipLaunchKernelGGL((stage_kernel_cls_persist<N, AX, AY, float>), grid, block, 0, s, P, work, nitems,
-                               counter);
+            hipLaunchKernelGGL((stage_kernel_cls_persist<N, AX, AY, float>), grid, block, 0, s, P, work, xl, counter);
         return;
     }
-    launch_cls_batched<N, AX, AY>(precision, P, work, nitems, s);
+    launch_cls_batched<N, AX, AY>(precision, P, work, xl, maxlen, s);
 }
 
 hipError_t launch_stage_batched(int N, int precision, int variant, const StageParams *P, const int2 *work,
-                                int nitems, int *counter, int persist_grid, hipStream_t s)
+                                const XcdLists &xl, int maxlen, int *counter, int persist_grid, hipStream_t s)
 {
+    if (xl.off[0] != 0 || maxlen < 1) return hipErrorInvalidValue;
+    for (int x = 0; x < kXcds; ++x)
+        if (xl.off[x + 1] < xl.off[x] || xl.off[x + 1] - xl.off[x] > maxlen) return hipErrorInvalidValue;
     switch (N) {
 #define NH_LAUNCHB(NN, AX0, AY0, AX1, AY1, AX2, AY2)                                                          \
     case NN:                                                                                                  \
-        if (variant == 1) launch_batched_one<NN, AX1, AY1>(precision, P, work, nitems, counter, persist_grid, s); \
+        if (variant == 1)                                                                                     \
+            launch_batched_one<NN, AX1, AY1>(precision, P, work, xl, maxlen, counter, persist_grid, s);       \
         else if (variant == 2 && NN == 4)                                                                     \
-            launch_cls_batched_any<4, 8, 2>(precision, P, work, nitems, counter, persist_grid, s);            \
+            launch_cls_batched_any<4, 8, 2>(precision, P, work, xl, maxlen, counter, persist_grid, s);        \
         else if (variant == 2)                                                                                \
-            launch_batched_one<NN, AX2, AY2>(precision, P, work, nitems, counter, persist_grid, s);           \
-        else launch_batched_one<NN, AX0, AY0>(precision, P, work, nitems, counter, persist_grid, s);          \
+            launch_batched_one<NN, AX2, AY2>(precision, P, work, xl, maxlen, counter, persist_grid, s);       \
+        else launch_batched_one<NN, AX0, AY0>(precision, P, work, xl, maxlen, counter, persist_grid, s);      \
         break;
         NH_TILE_CASES(NH_LAUNCHB)
 #undef NH_LAUNCHB

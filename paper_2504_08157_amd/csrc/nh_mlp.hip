@@ -783,10 +783,12 @@ __global__ void silu_back_kernel(const float *__restrict__ dH, const float *__re
     }
 }
 
-// Adam on FP32 masters (Kingma & Ba), then FP16 copies.
+// Adam on FP32 masters (Kingma & Ba), then FP16 copies.  The first ndecay
+// parameters also take decoupled weight decay wd (Loshchilov & Hutter):
+// w -= lr (m_hat / (sqrt(v_hat) + eps) + wd w).
 __global__ void adam_kernel(long n, const float *__restrict__ g, float *__restrict__ w, float *__restrict__ m,
                             float *__restrict__ v, _Float16 *__restrict__ wh, float lr, float b1, float b2,
-                            float eps, float c1, float c2)
+                            float eps, float c1, float c2, long ndecay, float wd)
 {
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         const float gi = g[i];
@@ -794,7 +796,9 @@ __global__ void adam_kernel(long n, const float *__restrict__ g, float *__restri
         const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
         m[i] = mi;
         v[i] = vi;
-        const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        float u = (mi / c1) / (sqrtf(vi / c2) + eps);
+        if (i < ndecay) u += wd * w[i];
+        const float wi = w[i] - lr * u;
         w[i] = wi;
         wh[i] = (_Float16)wi;
     }
@@ -941,11 +945,13 @@ hipError_t mlp_loss_grad(const MlpNet &net, int M, const float *T, float *loss, 
     return hipGetLastError();
 }
 
-hipError_t mlp_adam(const MlpNet &net, float lr, float b1, float b2, float eps, int step, hipStream_t s)
+hipError_t mlp_adam(const MlpNet &net, float lr, float b1, float b2, float eps, int step, float wd, hipStream_t s)
 {
     const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    // the hidden path (W1, b1, W2, b2, W3, b3) precedes the bypass S
+    const long ndecay = wd > 0.f ? net.nparam - (long)kMlpOut * kMlpIn : 0;
     hipLaunchKernelGGL(adam_kernel, dim3(grid_for(net.nparam, 256)), dim3(256), 0, s, net.nparam, net.grad,
-                       net.master, net.m, net.v, (_Float16 *)net.half, lr, b1, b2, eps, c1, c2);
+                       net.master, net.m, net.v, (_Float16 *)net.half, lr, b1, b2, eps, c1, c2, ndecay, wd);
     return hipGetLastError();
 }
 

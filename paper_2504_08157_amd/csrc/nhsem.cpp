@@ -1419,6 +1419,7 @@ struct nh_mlp {
     long max_batch;
     int step;
     int passes;   // network applications per initial guess (nh_mlp_set_passes)
+    float decay;  // decoupled weight decay of the hidden path (nh_mlp_set_decay)
     hipStream_t stream;
     bool sticky;
     std::string err;
@@ -1612,6 +1613,7 @@ nh_status nh_mlp_create(int64_t max_batch, uint64_t seed, void *dev_ws, size_t b
     m->max_batch = max_batch;
     m->step = 0;
     m->passes = 1;
+    m->decay = 0.0f;
     m->stream = (hipStream_t)hip_stream;
     m->sticky = false;
     std::vector<float> h;
@@ -1663,7 +1665,7 @@ nh_status nh_mlp_train_step(nh_mlp *m, int64_t batch, const void *dev_x_f16, con
     MLPCHK(m, mlp_loss_grad(m->net, M, dev_t, m->net.loss, m->stream));
     MLPCHK(m, mlp_backward(m->net, M, dev_x_f16, m->net.dY, m->stream));
     ++m->step;
-    MLPCHK(m, mlp_adam(m->net, lr, b1, b2, eps, m->step, m->stream));
+    MLPCHK(m, mlp_adam(m->net, lr, b1, b2, eps, m->step, m->decay, m->stream));
     if (dev_loss)
         MLPCHK(m, hipMemcpyAsync(dev_loss, m->net.loss, sizeof(float), hipMemcpyDeviceToDevice, m->stream));
     return NH_OK;
@@ -1676,7 +1678,7 @@ nh_status nh_mlp_adam_step(nh_mlp *m, float lr, float b1, float b2, float eps)
     if (!(lr > 0) || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1) || !(eps > 0))
         return mfail(m, NH_EINVAL, "bad Adam hyper-parameters");
     ++m->step;
-    MLPCHK(m, mlp_adam(m->net, lr, b1, b2, eps, m->step, m->stream));
+    MLPCHK(m, mlp_adam(m->net, lr, b1, b2, eps, m->step, m->decay, m->stream));
     return NH_OK;
 }
 
@@ -1722,6 +1724,14 @@ nh_status nh_mlp_samples(nh_mlp *m, nh_ctx *c, double alpha, const double *dev_b
     HIPCHK(c, launch_lv_apply(hevi_params(c), dev_b, dev_tmp, c->stream, false));
     const MlpColParams cp = mlp_col_params(c, alpha);
     HIPCHK(c, launch_mlp_features(cp, dev_b, dev_tmp, dev_x, col0, ncol, dev_feat, dev_scale, dev_tgt, c->stream));
+    return NH_OK;
+}
+
+nh_status nh_mlp_set_decay(nh_mlp *m, float wd)
+{
+    if (!m) return fail(nullptr, NH_EINVAL, "null MLP");
+    if (!(wd >= 0.0f && wd < 1e30f)) return mfail(m, NH_EINVAL, "weight decay must be finite and >= 0");
+    m->decay = wd;
     return NH_OK;
 }
 
@@ -1779,7 +1789,9 @@ struct nh_batch {
     int persist_grid;     // workgroups of a persistent launch (one per CU)
     struct Group {
         int N, variant, nitems;
-        int2 *work;  // device
+        int2 *work;   // device
+        XcdLists xl;  // the group's items as one contiguous list per XCD
+        int maxlen;   // longest of those lists
     };
     std::vector<Group> groups;
     std::vector<int> variant;  // tile variant of each instance (its order group's)
@@ -1798,7 +1810,8 @@ namespace {
 // most tiles), the per-stage descriptor tables of K steps and the counters of
 // the persistent launches (K steps x 3 stages x at most kMaxN - 1 order groups).
 size_t batch_tables_bytes(int n, int K) { return align_up(sizeof(StageParams) * (size_t)K * 3 * n); }
-size_t batch_counter_bytes(int K) { return align_up(sizeof(int) * (size_t)K * 3 * (kMaxN - 1)); }
+// one counter per XCD list of every (step, stage, order group) launch
+size_t batch_counter_bytes(int K) { return align_up(sizeof(int) * (size_t)K * 3 * (kMaxN - 1) * kXcds); }
 
 size_t batch_bytes(nh_ctx *const *ctxs, int n, int K)
 {
@@ -1913,7 +1926,24 @@ nh_status nh_batch_create(nh_ctx *const *ctxs, int32_t n, int32_t steps_per_grap
         if (items.empty()) continue;
         std::stable_sort(items.begin(), items.end(),
                          [](const std::pair<int, int2> &a, const std::pair<int, int2> &c) { return a.first > c.first; });
-        nh_batch::Group g{N, var, (int)items.size(), work + tiles_total};
+        // cut the sorted sequence (instances whole and in order, tiles
+        // row-major) into kXcds contiguous runs of about equal cost (column
+        // length): XCD x works through run x, so its concurrent workgroups
+        // are neighbouring tiles whose halos meet in its L2
+        nh_batch::Group g{N, var, (int)items.size(), work + tiles_total, XcdLists{}, 1};
+        {
+            double total = 0.0;
+            for (auto &it : items) total += it.first;
+            double acc = 0.0;
+            int x = 0;
+            g.xl.off[0] = 0;
+            for (int j = 0; j < (int)items.size(); ++j) {
+                acc += items[j].first;
+                while (x < kXcds - 1 && acc >= total * (x + 1) / kXcds) g.xl.off[++x] = j + 1;
+            }
+            while (x < kXcds) g.xl.off[++x] = (int)items.size();
+            for (int y = 0; y < kXcds; ++y) g.maxlen = std::max(g.maxlen, g.xl.off[y + 1] - g.xl.off[y]);
+        }
         for (auto &it : items) all.push_back(it.second);
         tiles_total += items.size();
         b->groups.push_back(g);
@@ -2007,16 +2037,17 @@ nh_status nh_batch_step(nh_batch *b, double t, double dt, int32_t nsteps)
                 return bfail(b, NH_EHIP, "begin capture: %s", hipGetErrorString(e));
             }
             // counters are cleared by a fill kernel (not a memset node)
-            if (b->persistent) e = launch_zero_ints(b->counters, b->K * 3 * (kMaxN - 1), b->stream);
+            if (b->persistent) e = launch_zero_ints(b->counters, b->K * 3 * (kMaxN - 1) * kXcds, b->stream);
             if (b->concurrent && e == hipSuccess) {
                 e = hipEventRecord(ev[ng], b->stream);
                 for (int g = 0; g < ng && e == hipSuccess; ++g) e = hipStreamWaitEvent(gs[g], ev[ng], 0);
             }
             auto launch = [&](int k, int s, int g) {
                 const auto &G = b->groups[g];
-                int *ctr = b->persistent ? b->counters + ((size_t)k * 3 + s) * (kMaxN - 1) + g : nullptr;
+                int *ctr = b->persistent ? b->counters + (((size_t)k * 3 + s) * (kMaxN - 1) + g) * kXcds : nullptr;
                 return launch_stage_batched(G.N, b->precision, G.variant, b->table + ((size_t)k * 3 + s) * n, G.work,
-                                            G.nitems, ctr, b->persist_grid, b->concurrent ? gs[g] : b->stream);
+                                            G.xl, G.maxlen, ctr, b->persist_grid,
+                                            b->concurrent ? gs[g] : b->stream);
             };
             if (b->concurrent) {
                 for (int g = 0; g < ng && e == hipSuccess; ++g)

@@ -85,10 +85,11 @@ def collect_random(mlp, w, batches, alpha, seed=11, rtol=1e-12):
     return torch.cat(feats), torch.cat(tgts)
 
 
-def train(mlp, feats, tgts, epochs=4, batch=4096, lr=1e-3, lr_final=None, seed=8, log=None):
+def train(mlp, feats, tgts, epochs=4, batch=4096, lr=1e-3, lr_final=None, seed=8, log=None, decay=0.0):
     """Adam over shuffled minibatches with a cosine learning-rate decay from
-    lr to lr_final (default lr / 20); returns the per-epoch loss history of
-    the last minibatch (host) and the training rate in samples/s."""
+    lr to lr_final (default lr / 20), with decoupled weight decay `decay` on
+    the hidden path (none on the bypass); returns the per-epoch loss history
+    of the last minibatch (host) and the training rate in samples/s."""
     import math
     import torch
     n = feats.shape[0] // 64 * 64
@@ -102,6 +103,7 @@ def train(mlp, feats, tgts, epochs=4, batch=4096, lr=1e-3, lr_final=None, seed=8
     t0 = time.perf_counter()
     nseen = 0
     step = 0
+    mlp.nh_mlp_set_decay(decay)
     for ep in range(epochs):
         perm = torch.from_numpy(rng.permutation(feats.shape[0])).to(feats.device)
         for b0 in range(0, n - batch + 1, batch):
@@ -114,6 +116,7 @@ def train(mlp, feats, tgts, epochs=4, batch=4096, lr=1e-3, lr_final=None, seed=8
         if log:
             log(f"epoch {ep} loss {hist[-1]:.4e}")
     torch.cuda.synchronize()
+    mlp.nh_mlp_set_decay(0.0)
     return hist, nseen / (time.perf_counter() - t0)
 
 
@@ -123,7 +126,8 @@ def initial_loss(feats, tgts):
 
 
 def fit(mlp, w_eval, dt, warm, sources, epochs, batch=1024, lr=1e-3, max_per_step=None, random_grid=None,
-        random_batches=0, finetune_epochs=0, finetune_batch=8192, finetune_lr=3e-4, finetune_lr_final=3e-6):
+        random_batches=0, finetune_epochs=0, finetune_batch=8192, finetune_lr=3e-4, finetune_lr_final=3e-6,
+        finetune_decay=0.0):
     """Training set: the solves of `sources` (list of (workload, steps, dt))
     and of the first `warm` (>= 1) steps of w_eval, all generated by the
     method itself with the default guess, plus `random_batches` batches of
@@ -131,8 +135,9 @@ def fit(mlp, w_eval, dt, warm, sources, epochs, batch=1024, lr=1e-3, max_per_ste
     w_eval's vertical grid; default w_eval); then train on all of it, and
     for `finetune_epochs` more on the samples of w_eval's column grid alone
     (its own solves and the random ones) in large batches with a small
-    learning rate: the bypass can represent one grid's correction map
-    exactly, and the other grids' samples pull it away from that map.
+    learning rate and decoupled weight decay `finetune_decay` on the hidden
+    path: the bypass can represent one grid's correction map exactly, and
+    the other grids' samples pull it away from that map.
     Returns a summary dict."""
     import torch
     t0 = time.perf_counter()
@@ -158,8 +163,9 @@ def fit(mlp, w_eval, dt, warm, sources, epochs, batch=1024, lr=1e-3, max_per_ste
     if finetune_epochs > 0:
         fg, tg = torch.cat(F[n_grid:]), torch.cat(T[n_grid:])
         h2, rate2 = train(mlp, fg, tg, epochs=finetune_epochs, batch=finetune_batch, lr=finetune_lr,
-                          lr_final=finetune_lr_final)
+                          lr_final=finetune_lr_final, decay=finetune_decay)
         out.update({"finetune_samples": int(fg.shape[0]), "finetune_epochs": finetune_epochs,
+                    "finetune_decay": finetune_decay,
                     "finetune_batch": finetune_batch, "finetune_loss_last": h2[-1],
                     "finetune_samples_per_s": rate2})
     return out

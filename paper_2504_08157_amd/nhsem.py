@@ -116,6 +116,7 @@ _SIGS = {
                                         _vp, _vp, _vp, _vp]),
     "nh_mlp_guess": (ctypes.c_int32, [_vp, _vp, ctypes.c_double, _vp, _vp, _vp]),
     "nh_mlp_set_passes": (ctypes.c_int32, [_vp, ctypes.c_int32]),
+    "nh_mlp_set_decay": (ctypes.c_int32, [_vp, ctypes.c_float]),
     "nh_hyperdiffusion_workspace_bytes": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
     "nh_set_hyperdiffusion": (ctypes.c_int32, [_vp, _vp, ctypes.c_double, _vp, ctypes.c_size_t]),
     "nh_hyperdiffusion": (ctypes.c_int32, [_vp, _vp, _vp]),
@@ -611,6 +612,9 @@ class ColumnMLP:
                                        _tptr(tgt) if tgt is not None else None, _tptr(tmp))
         _check(ctx.h, code)
         return feat, scale, tgt
+
+    def nh_mlp_set_decay(self, wd):
+        self._c(self.lib.nh_mlp_set_decay(self.h, float(wd)))
 
     def nh_mlp_set_passes(self, passes):
         self._c(self.lib.nh_mlp_set_passes(self.h, int(passes)))

@@ -258,6 +258,37 @@ def test_adam_step_matches_oracle():
         m.nh_mlp_adam_step(lr=-1.0)
 
 
+def test_adam_step_with_hidden_path_decay_matches_oracle():
+    """nh_mlp_set_decay: three Adam steps with decoupled weight decay on the
+    hidden path (every parameter before the bypass S) against the oracle's
+    AdamW on the same gradient; the bypass takes plain Adam."""
+    m, torch, w, wo, x = _mlp_with_random_params(seed=15)
+    rng = np.random.default_rng(16)
+    dy = rng.normal(size=(x.shape[0], MO.OUT)).astype(np.float32)
+    xd = torch.from_numpy(x).cuda()
+    m.nh_mlp_forward(xd)
+    m.nh_mlp_backward(xd, torch.from_numpy(dy).cuda())
+    lr, b1, b2, eps, wd = 2e-3, 0.8, 0.99, 1e-6, 0.5
+    m.nh_mlp_set_decay(wd)
+    nd = w.size - MO.OUT * MO.IN
+    wa = w.astype(np.float64)
+    _, g = m.nh_mlp_params()
+    g = g.cpu().numpy().astype(np.float64)
+    mo = vo = np.zeros_like(wa)
+    for step in range(1, 4):
+        m.nh_mlp_adam_step(lr, b1, b2, eps)
+        wa, mo, vo = MO.adam(wa, g, mo, vo, step, lr, b1, b2, eps, wd=wd, ndecay=nd)
+    w3, _ = m.nh_mlp_params()
+    w3 = w3.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(w3 - wa) <= 1e-5 * np.linalg.norm(wa - w.astype(np.float64))
+    # the decay reaches the hidden path and only it
+    wplain, _, _ = MO.adam(w.astype(np.float64), g, 0 * g, 0 * g, 1, lr, b1, b2, eps)
+    assert not np.allclose(wa[:nd], wplain[:nd])
+    from paper_2504_08157_amd import nhsem
+    with pytest.raises(nhsem.NHError):
+        m.nh_mlp_set_decay(-1.0)
+
+
 def _canonical_column_case(oracle_mod, nel=(2, 2, 16)):
     """A context and oracle with nel[2] equal order-4 elements in z over
     20 km; with 16 the column grid is the canonical one and feature

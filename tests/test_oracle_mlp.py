@@ -34,6 +34,18 @@ def test_adam_first_step_closed_form():
     np.testing.assert_allclose(w1, w - 1e-3 * np.sign(g), rtol=0, atol=1e-15)
 
 
+def test_adamw_first_step_closed_form():
+    """Decoupled weight decay on the first ndecay parameters: the first
+    bias-corrected step moves those by lr (sign(g) + wd w), the rest by
+    lr sign(g) (Loshchilov & Hutter 2019)."""
+    rng = np.random.default_rng(2)
+    w = rng.normal(size=40); g = rng.normal(size=40)
+    w1, m, v = MO.adam(w, g, np.zeros(40), np.zeros(40), 1, lr=1e-3, eps=0.0, wd=0.25, ndecay=25)
+    ref = w - 1e-3 * np.sign(g)
+    ref[:25] -= 1e-3 * 0.25 * w[:25]
+    np.testing.assert_allclose(w1, ref, rtol=0, atol=1e-15)
+
+
 def test_silu_derivative():
     z = np.linspace(-8, 8, 101)
     h = 1e-6
