@@ -479,14 +479,18 @@ nh_status nh_mlp_set_params(nh_mlp *m, const float *dev_master);
 
 /* Training samples / features for columns [col0, col0 + ncol) of ctx: the
    right-hand side b of (I - alpha L_v) x = b and, if dev_x is given, the
-   solution x.  dev_feat FP16 [ncol][208], dev_scale double [ncol] (the
-   column scale: RMS of the dimensionless alpha L_v b), dev_tgt float
-   [ncol][256] (the scaled dimensionless
-   correction x - b on the 65 canonical levels per field, zero past 195;
-   needs dev_x), dev_tmp device [5][U] scratch. */
+   solution x.  Without dev_x0 the samples are those of the default start
+   b: features of its residual alpha L_v b, targets x - b; with dev_x0
+   (device [3][U], rho', w, theta': a guess, e.g. the network's first pass)
+   those of the start x0: features of its residual b - (I - alpha L_v) x0,
+   targets x - x0 (the samples of a refinement pass).  dev_feat FP16
+   [ncol][208], dev_scale double [ncol] (the column scale: RMS of the
+   dimensionless residual), dev_tgt float [ncol][256] (the scaled
+   dimensionless correction on the 65 canonical levels per field, zero
+   past 195; needs dev_x), dev_tmp device [5][U] scratch. */
 nh_status nh_mlp_samples(nh_mlp *m, nh_ctx *ctx, double alpha, const double *dev_b, const double *dev_x,
                          int64_t col0, int64_t ncol, void *dev_feat, double *dev_scale, float *dev_tgt,
-                         double *dev_tmp);
+                         double *dev_tmp, const double *dev_x0);
 
 /* Decoupled weight decay (Loshchilov & Hutter, AdamW) applied by every
    later Adam step (nh_mlp_adam_step, nh_mlp_train_step) to the hidden

@@ -297,8 +297,12 @@ hipError_t launch_mlp_infer(const MlpColParams &p, const HeviParams &hp, const M
                             bool base3, const double *b, const double *lb, double rscale, long col0, long ncol,
                             double *x0, hipStream_t s);
 int mlp_fused_max_nz();
-hipError_t launch_mlp_features(const MlpColParams &p, const double *b, const double *lb, const double *x,
-                               long col0, long ncol, void *feat, double *scale, float *tgt, hipStream_t s);
+// features (and, with x, targets x - base) of the residual rscale * lb of
+// the start base: b ([5][U]) with lb = L_v b, rscale = alpha, or a previous
+// guess ([3][U], base3) with lb its residual, rscale = 1
+hipError_t launch_mlp_features(const MlpColParams &p, const double *base, bool base3, const double *lb,
+                               double rscale, const double *x, long col0, long ncol, void *feat, double *scale,
+                               float *tgt, hipStream_t s);
 hipError_t launch_mlp_guess(const MlpColParams &p, const double *b, long col0, long ncol, const float *y,
                             const double *scale, double *x0, hipStream_t s);
 hipError_t mlp_forward(const MlpNet &net, int M, const void *X, hipStream_t s, bool keep_z = true);

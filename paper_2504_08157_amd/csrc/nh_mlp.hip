@@ -62,10 +62,12 @@ __device__ __forceinline__ double dim_factor(const MlpColParams &p, int f, int k
 // features of the 64 columns are assembled in LDS and written out as whole
 // rows.  The interpolation intervals of the canonical levels and the
 // inverse dimension factors of every level are tabulated in LDS first
-// (dynamic LDS: 3 n_z doubles).
-__global__ void __launch_bounds__(512) mlp_features_kernel(MlpColParams p, const double *__restrict__ b,
-                                                           const double *__restrict__ lb,
-                                                           const double *__restrict__ x, long col0,
+// (dynamic LDS: 3 n_z doubles).  The residual of the start is rscale * lb
+// (fields 0, 3, 4 of [5][U]); the targets are the correction x - base of
+// that start, base = b ([5][U]) or a previous guess ([3][U], base3).
+__global__ void __launch_bounds__(512) mlp_features_kernel(MlpColParams p, const double *__restrict__ base,
+                                                           bool base3, const double *__restrict__ lb,
+                                                           double rscale, const double *__restrict__ x, long col0,
                                                            long ncol, _Float16 *__restrict__ feat,
                                                            double *__restrict__ scale, float *__restrict__ tgt)
 {
@@ -89,14 +91,14 @@ __global__ void __launch_bounds__(512) mlp_features_kernel(MlpColParams p, const
     const long r = r0 + lane;
     const bool ok = r < ncol;
     const long col = col0 + (ok ? r : 0);
-    // s = RMS over the column of the dimensionless residual alpha L_v b
+    // s = RMS over the column of the dimensionless residual
     double a = 0.0;
 #pragma unroll 4
     for (int k = q; k < nz; k += NWV) {
         const long I = col + (long)k * nxy;
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
-            const double l = p.alpha * lb[fld[f] * U + I] * sdinv[f * nz + k];
+            const double l = rscale * lb[fld[f] * U + I] * sdinv[f * nz + k];
             a += l * l;
         }
     }
@@ -114,10 +116,11 @@ __global__ void __launch_bounds__(512) mlp_features_kernel(MlpColParams p, const
         for (int f = 0; f < 3; ++f) {
             const long I0 = fld[f] * U + col + (long)k0 * nxy, I1 = I0 + nxy;
             const double d0 = sdinv[f * nz + k0], d1 = sdinv[f * nz + k0 + 1];
-            const double vl = (1.0 - t) * (p.alpha * lb[I0] * d0) + t * (p.alpha * lb[I1] * d1);
+            const double vl = (1.0 - t) * (rscale * lb[I0] * d0) + t * (rscale * lb[I1] * d1);
             sf[lane][f * kMlpNC + c] = (_Float16)(vl / s);
             if (tgt && ok) {
-                const double vx = (1.0 - t) * ((x[I0] - b[I0]) * d0) + t * ((x[I1] - b[I1]) * d1);
+                const long B0 = (base3 ? f : fld[f]) * U + col + (long)k0 * nxy, B1 = B0 + nxy;
+                const double vx = (1.0 - t) * ((x[I0] - base[B0]) * d0) + t * ((x[I1] - base[B1]) * d1);
                 tgt[r * kMlpOut + f * kMlpNC + c] = (float)(vx / s);
             }
         }
@@ -819,13 +822,14 @@ static int grid_for(long n, int block)
 }
 
 // ---------------------------------------------------------------- launchers
-hipError_t launch_mlp_features(const MlpColParams &p, const double *b, const double *lb, const double *x,
-                               long col0, long ncol, void *feat, double *scale, float *tgt, hipStream_t s)
+hipError_t launch_mlp_features(const MlpColParams &p, const double *base, bool base3, const double *lb,
+                               double rscale, const double *x, long col0, long ncol, void *feat, double *scale,
+                               float *tgt, hipStream_t s)
 {
     const int grid = (int)((ncol + 63) / 64);
     const size_t lds = sizeof(double) * 3 * (size_t)p.nz;
-    hipLaunchKernelGGL(mlp_features_kernel, dim3(grid), dim3(512), lds, s, p, b, lb, x, col0, ncol,
-                       (_Float16 *)feat, scale, tgt);
+    hipLaunchKernelGGL(mlp_features_kernel, dim3(grid), dim3(512), lds, s, p, base, base3, lb, rscale, x, col0,
+                       ncol, (_Float16 *)feat, scale, tgt);
     return hipGetLastError();
 }
 

@@ -1711,7 +1711,7 @@ nh_status nh_mlp_set_params(nh_mlp *m, const float *dev_master)
 
 nh_status nh_mlp_samples(nh_mlp *m, nh_ctx *c, double alpha, const double *dev_b, const double *dev_x,
                          int64_t col0, int64_t ncol, void *dev_feat, double *dev_scale, float *dev_tgt,
-                         double *dev_tmp)
+                         double *dev_tmp, const double *dev_x0)
 {
     nh_status st = guard(c);
     if (st) return st;
@@ -1721,9 +1721,17 @@ nh_status nh_mlp_samples(nh_mlp *m, nh_ctx *c, double alpha, const double *dev_b
     const long nc = (long)c->n[0] * c->n[1];
     if (col0 < 0 || ncol <= 0 || col0 + ncol > nc) return fail(c, NH_EINVAL, "column range outside the lattice");
     if (!c->have_ref) return fail(c, NH_EINVAL, "reference state not set");
-    HIPCHK(c, launch_lv_apply(hevi_params(c), dev_b, dev_tmp, c->stream, false));
     const MlpColParams cp = mlp_col_params(c, alpha);
-    HIPCHK(c, launch_mlp_features(cp, dev_b, dev_tmp, dev_x, col0, ncol, dev_feat, dev_scale, dev_tgt, c->stream));
+    if (dev_x0) {
+        // the residual of the start x0, and the correction x - x0
+        HIPCHK(c, launch_lv_resid(hevi_params(c), alpha, dev_b, dev_x0, dev_tmp, c->stream));
+        HIPCHK(c, launch_mlp_features(cp, dev_x0, true, dev_tmp, 1.0, dev_x, col0, ncol, dev_feat, dev_scale, dev_tgt,
+                                      c->stream));
+        return NH_OK;
+    }
+    HIPCHK(c, launch_lv_apply(hevi_params(c), dev_b, dev_tmp, c->stream, false));
+    HIPCHK(c, launch_mlp_features(cp, dev_b, false, dev_tmp, alpha, dev_x, col0, ncol, dev_feat, dev_scale, dev_tgt,
+                                  c->stream));
     return NH_OK;
 }
 

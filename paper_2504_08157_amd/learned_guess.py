@@ -31,10 +31,13 @@ def hevi_context(w, device="cuda"):
     return ctx
 
 
-def collect(mlp, w, steps, dt, t0=0.0, rtol=1e-10, max_per_step=None, seed=8):
+def collect(mlp, w, steps, dt, t0=0.0, rtol=1e-10, max_per_step=None, seed=8, refine=False):
     """Run `steps` HEVI steps of workload w; after each, turn both implicit
     solves into (features, targets).  Returns FP16 features, FP32 targets
-    (device tensors) and the implicit coefficient per dt of the solves."""
+    (device tensors) and the implicit coefficient per dt of the solves.
+    refine: samples of a refinement pass instead -- the start is the
+    network's own first-pass guess, the features its residual and the
+    targets the correction that remains."""
     import torch
     ctx = hevi_context(w)
     feats, tgts = [], []
@@ -46,7 +49,8 @@ def collect(mlp, w, steps, dt, t0=0.0, rtol=1e-10, max_per_step=None, seed=8):
         ctx.nh_hevi_step(t0 + s * dt, dt, rtol=rtol, max_restarts=30, restart=10, schur=True)
         a_dt, solves = ctx.nh_hevi_last_solves()
         for (R, X) in solves:
-            f, _, t = mlp.nh_mlp_samples(ctx, a_dt * dt, R, X)
+            x0 = mlp.nh_mlp_guess(ctx, a_dt * dt, R) if refine else None
+            f, _, t = mlp.nh_mlp_samples(ctx, a_dt * dt, R, X, x0=x0)
             if max_per_step and ncol > max_per_step:
                 idx = torch.from_numpy(rng.choice(ncol, max_per_step, replace=False)).cuda()
                 f, t = f[idx], t[idx]
@@ -57,11 +61,12 @@ def collect(mlp, w, steps, dt, t0=0.0, rtol=1e-10, max_per_step=None, seed=8):
     return torch.cat(feats), torch.cat(tgts), a_dt
 
 
-def collect_random(mlp, w, batches, alpha, seed=11, rtol=1e-12):
+def collect_random(mlp, w, batches, alpha, seed=11, rtol=1e-12, refine=False):
     """Solves of seeded random column right-hand sides on the column grid of
     workload w (the library's own batched GMRES, to rtol), turned into
     (features, targets): they span every direction of the column space,
-    which the few structures of one simulation do not."""
+    which the few structures of one simulation do not.  refine: samples of
+    a refinement pass (see collect)."""
     import torch
     ctx = nhsem.Context(w.mesh, w.phys)
     x, y, z = ctx.nh_lattice_coords()
@@ -77,7 +82,8 @@ def collect_random(mlp, w, batches, alpha, seed=11, rtol=1e-12):
         q = W.random_column_rhs(z, D, ncol, seed + k).reshape(5, -1)
         b = torch.from_numpy(np.ascontiguousarray(q)).cuda()
         xs, st = ctx.nh_column_solve(alpha, b, rtol=rtol, max_restarts=60, restart=10, schur=True)
-        f, _, t = mlp.nh_mlp_samples(ctx, alpha, b, xs)
+        x0 = mlp.nh_mlp_guess(ctx, alpha, b) if refine else None
+        f, _, t = mlp.nh_mlp_samples(ctx, alpha, b, xs, x0=x0)
         feats.append(f)
         tgts.append(t)
     torch.cuda.synchronize()
@@ -127,7 +133,7 @@ def initial_loss(feats, tgts):
 
 def fit(mlp, w_eval, dt, warm, sources, epochs, batch=1024, lr=1e-3, max_per_step=None, random_grid=None,
         random_batches=0, finetune_epochs=0, finetune_batch=8192, finetune_lr=3e-4, finetune_lr_final=3e-6,
-        finetune_decay=0.0):
+        finetune_decay=0.0, refine_random_batches=0, log=None):
     """Training set: the solves of `sources` (list of (workload, steps, dt))
     and of the first `warm` (>= 1) steps of w_eval, all generated by the
     method itself with the default guess, plus `random_batches` batches of
@@ -137,8 +143,12 @@ def fit(mlp, w_eval, dt, warm, sources, epochs, batch=1024, lr=1e-3, max_per_ste
     (its own solves and the random ones) in large batches with a small
     learning rate and decoupled weight decay `finetune_decay` on the hidden
     path: the bypass can represent one grid's correction map exactly, and
-    the other grids' samples pull it away from that map.
-    Returns a summary dict."""
+    the other grids' samples pull it away from that map.  With
+    refine_random_batches > 0 the fine-tune set also holds samples of a
+    refinement pass (the network's own first-pass guess as the start) from
+    the evaluated run's first steps and that many random batches, drawn
+    after the first training phase.  log: a callable that receives progress
+    lines.  Returns a summary dict."""
     import torch
     t0 = time.perf_counter()
     F, T = [], []
@@ -154,18 +164,29 @@ def fit(mlp, w_eval, dt, warm, sources, epochs, batch=1024, lr=1e-3, max_per_ste
         F.append(f); T.append(t)
     feats, tgts = torch.cat(F), torch.cat(T)
     t_collect = time.perf_counter() - t0
+    if log:
+        log(f"collected {int(feats.shape[0])} samples in {t_collect:.1f} s")
     l0 = initial_loss(feats, tgts)
-    hist, rate = train(mlp, feats, tgts, epochs=epochs, batch=batch, lr=lr)
+    hist, rate = train(mlp, feats, tgts, epochs=epochs, batch=batch, lr=lr, log=log)
     out = {"samples": int(feats.shape[0]), "samples_from_runs": n_sim, "loss_untrained": l0,
            "loss_last": hist[-1], "samples_per_s": rate, "collect_s": t_collect, "epochs": epochs,
            "batch": batch}
     del feats, tgts
     if finetune_epochs > 0:
+        if refine_random_batches > 0:
+            mlp.nh_mlp_set_passes(1)
+            f, t, _ = collect(mlp, w_eval, steps=max(warm, 1), dt=dt, max_per_step=max_per_step, refine=True)
+            F.append(f); T.append(t)
+            f, t = collect_random(mlp, random_grid or w_eval, refine_random_batches, a_dt * dt, seed=911,
+                                  refine=True)
+            F.append(f); T.append(t)
+            if log:
+                log("collected the refinement-pass samples")
         fg, tg = torch.cat(F[n_grid:]), torch.cat(T[n_grid:])
         h2, rate2 = train(mlp, fg, tg, epochs=finetune_epochs, batch=finetune_batch, lr=finetune_lr,
-                          lr_final=finetune_lr_final, decay=finetune_decay)
+                          lr_final=finetune_lr_final, decay=finetune_decay, log=log)
         out.update({"finetune_samples": int(fg.shape[0]), "finetune_epochs": finetune_epochs,
-                    "finetune_decay": finetune_decay,
+                    "finetune_decay": finetune_decay, "refine_random_batches": refine_random_batches,
                     "finetune_batch": finetune_batch, "finetune_loss_last": h2[-1],
                     "finetune_samples_per_s": rate2})
     return out

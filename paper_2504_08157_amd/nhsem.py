@@ -113,7 +113,7 @@ _SIGS = {
     "nh_mlp_params": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
     "nh_mlp_set_params": (ctypes.c_int32, [_vp, _vp]),
     "nh_mlp_samples": (ctypes.c_int32, [_vp, _vp, ctypes.c_double, _vp, _vp, ctypes.c_int64, ctypes.c_int64,
-                                        _vp, _vp, _vp, _vp]),
+                                        _vp, _vp, _vp, _vp, _vp]),
     "nh_mlp_guess": (ctypes.c_int32, [_vp, _vp, ctypes.c_double, _vp, _vp, _vp]),
     "nh_mlp_set_passes": (ctypes.c_int32, [_vp, ctypes.c_int32]),
     "nh_mlp_set_decay": (ctypes.c_int32, [_vp, ctypes.c_float]),
@@ -598,8 +598,9 @@ class ColumnMLP:
     def nh_mlp_set_params(self, w):
         self._c(self.lib.nh_mlp_set_params(self.h, _tptr(w)))
 
-    def nh_mlp_samples(self, ctx, alpha, b, x=None, col0=0, ncol=None, tmp=None):
-        """Features (FP16 [ncol][208]), scales and, with x, targets of columns."""
+    def nh_mlp_samples(self, ctx, alpha, b, x=None, col0=0, ncol=None, tmp=None, x0=None):
+        """Features (FP16 [ncol][208]), scales and, with x, targets of columns:
+        of the default start b, or of the start x0 ([3][U]) when given."""
         import torch
         ncol = ctx.nx * ctx.ny - col0 if ncol is None else ncol
         feat = torch.empty((ncol, MLP_IN), dtype=torch.float16, device=self.device)
@@ -609,7 +610,8 @@ class ColumnMLP:
             tmp = torch.empty(5 * ctx.U, dtype=torch.float64, device=self.device)
         code = self.lib.nh_mlp_samples(self.h, ctx.h, float(alpha), _tptr(b), _tptr(x) if x is not None else None,
                                        int(col0), int(ncol), _tptr(feat), _tptr(scale),
-                                       _tptr(tgt) if tgt is not None else None, _tptr(tmp))
+                                       _tptr(tgt) if tgt is not None else None, _tptr(tmp),
+                                       _tptr(x0) if x0 is not None else None)
         _check(ctx.h, code)
         return feat, scale, tgt
 

@@ -97,6 +97,42 @@ def test_features_match_oracle(oracle_mod):
     assert _rel(tgt.cpu().numpy(), to) <= 1e-6
 
 
+def test_samples_of_a_given_start_match_oracle(oracle_mod):
+    """nh_mlp_samples with a start x0 (the samples of a refinement pass):
+    features of the residual b - (I - alpha L_v) x0 and targets x - x0,
+    against the oracle's residual (its own L_v) and feature and target
+    definitions."""
+    import torch
+    from paper_2504_08157_amd import nhsem
+    ph = W.Physics()
+    mesh = W.MeshSpec((3, 2, 4), 4, W.uniform_edges(0, 30e3, 3), W.uniform_edges(0, 20e3, 2),
+                      W.stretched_edges(0, 15e3, 4, seed=8), (True, True))
+    ctx = nhsem.Context(mesh, ph)
+    orc = oracle_mod.Oracle(mesh, ph)
+    g = ctx.nh_lattice_coords(); o = orc.lattice_coords()
+    ctx.nh_set_reference(*W.constant_n_reference(g[2]))
+    orc.set_reference(*W.constant_n_reference(o[2]))
+    rho0, th0 = W.constant_n_reference(o[2])
+    bq = W.smooth_random_state(*o, *W.constant_n_reference(o[2]), seed=2, walls=(False, False))
+    xq = 1.3 * bq
+    sel = lambda a: np.stack([a[0], a[3], a[4]]).reshape(3, orc.nz, -1)
+    rng = np.random.default_rng(5)
+    x0 = sel(bq) * (1.0 + 0.01 * rng.normal(size=sel(bq).shape))
+    alpha = 0.7
+    m = nhsem.ColumnMLP(max_batch=64)
+    feat, scale, tgt = m.nh_mlp_samples(ctx, alpha, torch.from_numpy(bq).cuda(), torch.from_numpy(xq).cuda(),
+                                        x0=torch.from_numpy(np.ascontiguousarray(x0.reshape(-1))).cuda())
+    full = np.zeros_like(bq)
+    full[0], full[3], full[4] = (x0[f].reshape(bq[0].shape) for f in range(3))
+    r = sel(bq) - x0 + alpha * sel(orc.lv_apply(full))
+    D = MO.dimension_factors(rho0, orc.reference_pressure(), th0, ph.cp / ph.cv)
+    fo, so = MO.column_features(x0, r / alpha, o[2], alpha, D)
+    to = MO.column_targets(x0, sel(xq), o[2], D, so)
+    np.testing.assert_allclose(scale.cpu().numpy(), so, rtol=1e-10)
+    assert _rel(feat.cpu().numpy().astype(np.float64), fo) <= 2e-3
+    assert _rel(tgt.cpu().numpy(), to) <= 1e-6
+
+
 @pytest.mark.parametrize("nelz,tol", [(4, 5e-3), (17, 1e-12)], ids=["residual_in_kernel", "residual_from_lv"])
 def test_fused_guess_matches_separate_kernels(oracle_mod, nelz, tol):
     """The one-kernel inference of nh_mlp_guess (features, network and
