@@ -253,6 +253,10 @@ def parse():
                     help="further epochs on the evaluated column grid's samples alone, batch 8192 (hevi mode)")
     ap.add_argument("--mlp-finetune-decay", type=float, default=3.0,
                     help="decoupled weight decay of the hidden path during the fine-tune epochs (hevi mode)")
+    ap.add_argument("--mlp-refine-batches", type=int, default=32,
+                    help="random batches of refinement-pass samples in the fine-tune set (hevi mode)")
+    ap.add_argument("--mlp-passes", type=int, default=3,
+                    help="network passes of the refined learned guess (hevi mode)")
     ap.add_argument("--gmres-restart", type=int, default=10, help="Krylov vectors per GMRES cycle (hevi mode)")
     return ap.parse_args()
 
@@ -348,23 +352,28 @@ def bench_hevi(args):
     tr = LG.fit(mlp, w, w.dt, warm, [(W.cfg_tc_small(), 2, w.dt), (W.cfg_bubble(), 2, 0.5)],
                 epochs=args.mlp_epochs, batch=1024, lr=1e-3, max_per_step=24576, random_grid=wr,
                 random_batches=args.mlp_random_batches, finetune_epochs=args.mlp_finetune_epochs,
-                finetune_decay=args.mlp_finetune_decay)
-    res = LG.compare(mlp, w, warm=warm, held=args.steps, dt=w.dt, restart=args.gmres_restart)
+                finetune_decay=args.mlp_finetune_decay, refine_random_batches=args.mlp_refine_batches,
+                log=lambda m: print(m, file=sys.stderr, flush=True))
+    res = LG.compare(mlp, w, warm=warm, held=args.steps, dt=w.dt, restart=args.gmres_restart,
+                     refine_passes=args.mlp_passes)
+    print("compared the full form", file=sys.stderr, flush=True)
     # the same steps with the column systems solved through their Schur
     # complement in w (restart 10 only)
     res_s = None
     if args.gmres_restart == 10:
-        res_s = LG.compare(mlp, w, warm=warm, held=args.steps, dt=w.dt, restart=10, schur=True)
+        res_s = LG.compare(mlp, w, warm=warm, held=args.steps, dt=w.dt, restart=10, schur=True,
+                           refine_passes=args.mlp_passes)
+        print("compared the Schur form", file=sys.stderr, flush=True)
     ctx = LG.hevi_context(w)
     for s in range(warm):
         ctx.nh_hevi_step(s * w.dt, w.dt, rtol=1e-10, max_restarts=30, restart=10, schur=True)
     gm = time_column_solves(ctx, w, 3)
     U = ctx.U
     ctx.close()
-    d, m, m2 = res["default"], res["mlp"], res["mlp_2pass"]
+    d, m, m2 = res["default"], res["mlp"], res["mlp_refined"]
     out = {
         "metric": "DOF-stage updates/s (FP32/batched vs FP64 plain) at stated L2 error; % HBM peak",
-        # the learned guess with two network passes (the form the speed-up is quoted for)
+        # the learned guess refined by further network passes (the form the speed-up is quoted for)
         "value": 5 * U * 3 / (m2["ms_per_step"] / 1e3), "unit": "DOF-stage updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": warm, "ms_per_step": m2["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f16", "data": "synthetic",
@@ -376,10 +385,11 @@ def bench_hevi(args):
                  "mlp_pick": res["mlp_pick"], "speedup_step_pick": d["ms_per_step"] / res["mlp_pick"]["ms_per_step"],
                  "iteration_ratio_pick": res["mlp_pick"]["iters_per_solve"] / d["iters_per_solve"],
                  "state_rel_diff_stacked_pick": res["state_rel_diff_stacked_pick"],
-                 "mlp_2pass": res["mlp_2pass"],
-                 "speedup_step_2pass": d["ms_per_step"] / res["mlp_2pass"]["ms_per_step"],
-                 "iteration_ratio_2pass": res["mlp_2pass"]["iters_per_solve"] / d["iters_per_solve"],
-                 "state_rel_diff_stacked_2pass": res["state_rel_diff_stacked_2pass"],
+                 "refine_passes": args.mlp_passes,
+                 "mlp_refined": res["mlp_refined"],
+                 "speedup_step_refined": d["ms_per_step"] / res["mlp_refined"]["ms_per_step"],
+                 "iteration_ratio_refined": res["mlp_refined"]["iters_per_solve"] / d["iters_per_solve"],
+                 "state_rel_diff_stacked_refined": res["state_rel_diff_stacked_refined"],
                  "state_rel_diff_mlp_vs_default": res["state_rel_diff"],
                  "state_rel_diff_stacked": res["state_rel_diff_stacked"],
                  "training": tr},
@@ -394,10 +404,10 @@ def bench_hevi(args):
             "iteration_ratio": ms["iters_per_solve"] / ds["iters_per_solve"],
             "mlp_pick": res_s["mlp_pick"], "speedup_step_pick": ds["ms_per_step"] / res_s["mlp_pick"]["ms_per_step"],
             "iteration_ratio_pick": res_s["mlp_pick"]["iters_per_solve"] / ds["iters_per_solve"],
-            "mlp_2pass": res_s["mlp_2pass"],
-            "speedup_step_2pass": ds["ms_per_step"] / res_s["mlp_2pass"]["ms_per_step"],
-            "iteration_ratio_2pass": res_s["mlp_2pass"]["iters_per_solve"] / ds["iters_per_solve"],
-            "state_rel_diff_stacked_2pass": res_s["state_rel_diff_stacked_2pass"],
+            "mlp_refined": res_s["mlp_refined"],
+            "speedup_step_refined": ds["ms_per_step"] / res_s["mlp_refined"]["ms_per_step"],
+            "iteration_ratio_refined": res_s["mlp_refined"]["iters_per_solve"] / ds["iters_per_solve"],
+            "state_rel_diff_stacked_refined": res_s["state_rel_diff_stacked_refined"],
             "state_rel_diff_stacked": res_s["state_rel_diff_stacked"],
             "speedup_vs_full_form_default": d["ms_per_step"] / ds["ms_per_step"],
             "state_rel_diff_vs_full_form": float(

@@ -197,7 +197,7 @@ def compare(mlp, w, warm, held, dt, rtol=1e-10, restart=20, schur=False, refine_
     times -- default guess, MLP guess, the MLP guess with the per-column
     choice against the default start (the smaller initial residual), and
     the MLP guess refined by further passes of the network on its own
-    residual (refine_passes in all; reported as mlp_2pass) -- and report
+    residual (refine_passes in all; reported as mlp_refined) -- and report
     GMRES iterations, step times and the difference of the final states
     (schur: solve the Schur complement in w)."""
     import torch
@@ -208,7 +208,7 @@ def compare(mlp, w, warm, held, dt, rtol=1e-10, restart=20, schur=False, refine_
     out = {}
     finals = {}
     for name, g, pick, passes in (("default", None, False, 1), ("mlp", mlp, False, 1), ("mlp_pick", mlp, True, 1),
-                                  ("mlp_2pass", mlp, False, refine_passes)):
+                                  ("mlp_refined", mlp, False, refine_passes)):
         mlp.nh_mlp_set_passes(passes)
         ctx.nh_set_state(q0)
         torch.cuda.synchronize()
@@ -229,8 +229,8 @@ def compare(mlp, w, warm, held, dt, rtol=1e-10, restart=20, schur=False, refine_
         finals[name] = ctx.nh_get_state().cpu().numpy()
     mlp.nh_mlp_set_passes(1)
     dp = finals["mlp_pick"] - finals["default"]
-    d2 = finals["mlp_2pass"] - finals["default"]
-    out["state_rel_diff_stacked_2pass"] = float(np.linalg.norm(d2) / np.linalg.norm(finals["default"]))
+    d2 = finals["mlp_refined"] - finals["default"]
+    out["state_rel_diff_stacked_refined"] = float(np.linalg.norm(d2) / np.linalg.norm(finals["default"]))
     out["state_rel_diff_stacked_pick"] = float(np.linalg.norm(dp) / np.linalg.norm(finals["default"]))
     d = finals["mlp"] - finals["default"]
     out["state_rel_diff"] = [float(np.linalg.norm(d[f]) / max(np.linalg.norm(finals["default"][f]), 1e-300))
