@@ -415,25 +415,28 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) m
     {
         double a = 0.0;
         if constexpr (NV > 0) {
+            auto resid = [&](int k, double l0, double l3, double l4, double xr, double xw, double xt) {
+                const long I = col + (long)k * nxy;
+                double v[3] = {p.alpha * l0, p.alpha * l3, p.alpha * l4};
+                if (base3) {
+                    v[0] = b[I] - xr + v[0];
+                    v[1] = b[3 * U + I] - xw + v[1];
+                    v[2] = b[4 * U + I] - xt + v[2];
+                }
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    const double d = v[f] * sdinv[f * nz + k];
+                    rbuf[(f * nz + k) * 64 + lane] = (float)d;
+                    a += d * d;
+                }
+            };
+            // a contiguous chunk of levels per wave, walked with a window
+            // (computing each level from its own 2N+1 neighbours instead
+            // measured slower: 0.57 against 0.38 ms per pass)
+            const long xw = base3 ? U : 3 * U, xt = base3 ? 2 * U : 4 * U;
             const int chunk = (nz + NWV - 1) / NWV;
             const int ka = q * chunk, kb = min(nz, ka + chunk);
-            if (ka < kb)
-                lv_walk<NV>(hp, col, ka, kb, base, base3 ? U : 3 * U, base3 ? 2 * U : 4 * U,
-                            [&](int k, double l0, double l3, double l4, double xr, double xw, double xt) {
-                                const long I = col + (long)k * nxy;
-                                double v[3] = {p.alpha * l0, p.alpha * l3, p.alpha * l4};
-                                if (base3) {
-                                    v[0] = b[I] - xr + v[0];
-                                    v[1] = b[3 * U + I] - xw + v[1];
-                                    v[2] = b[4 * U + I] - xt + v[2];
-                                }
-#pragma unroll
-                                for (int f = 0; f < 3; ++f) {
-                                    const double d = v[f] * sdinv[f * nz + k];
-                                    rbuf[(f * nz + k) * 64 + lane] = (float)d;
-                                    a += d * d;
-                                }
-                            });
+            if (ka < kb) lv_walk<NV>(hp, col, ka, kb, base, xw, xt, resid);
         } else {
 #pragma unroll 4
             for (int k = q; k < nz; k += NWV) {
