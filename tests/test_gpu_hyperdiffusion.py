@@ -21,6 +21,10 @@ CASES = {
     "multi_tile_N4": ((17, 5, 2), 4, (True, False), True),
     "walls_N2": ((9, 7, 3), 2, (False, False), False),
     "periodic_y_N6": ((3, 2, 2), 6, (False, True), True),
+    # 71 x 20 columns, walls in x: two tiles each way for the one-walk form
+    "multi_tile_walls_N2": ((35, 10, 3), 2, (False, True), True),
+    # 70 x 19 columns, walls everywhere, ragged tiles
+    "multi_tile_walls_N3": ((23, 6, 2), 3, (False, False), True),
 }
 
 
