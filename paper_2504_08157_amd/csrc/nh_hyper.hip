@@ -118,13 +118,20 @@ __global__ void __launch_bounds__(kHdTX * kHdTY) hd_laplace_tile_kernel(HyperPar
     // k mod P holds the staged plane of level k (pre), the own column of q at
     // level k + N + 1 (wpre) and, accumulating, that of out at level k (apre).
     auto level = [&](int lv) -> long { return (long)(lv < nz ? lv : nz - 1) * nxy; };
+    // With h.stream the output column (read when accumulating, then
+    // written) bypasses the caches: touched once, it should not displace
+    // the staged planes' halos from L2.
+    auto ld_out = [&](const double *a) -> double {
+        if (h.stream) return __builtin_nontemporal_load(a);
+        return *a;
+    };
     double pre[P][NS], wpre[P], apre[ACC ? P : 1];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
 #pragma unroll
         for (int i = 0; i < NS; ++i) pre[p][i] = qf[sc[i] + level(p)];
         wpre[p] = qf[col + level(N + 1 + p)];
-        if constexpr (ACC) apre[p] = of[col + level(p)];
+        if constexpr (ACC) apre[p] = ld_out(of + col + level(p));
     }
     double win[NC];   // levels k - N .. k + N of the thread's column
 #pragma unroll
@@ -153,12 +160,15 @@ __global__ void __launch_bounds__(kHdTX * kHdTY) hd_laplace_tile_kernel(HyperPar
             double v = scale * (ax + ay + az);
             if (colwall || (zwall && (k == 0 || k == nz - 1))) v = 0.0;
             if constexpr (ACC) v = apre[j] + v;
-            if (own && k < nz) of[col + (long)k * nxy] = v;
+            if (own && k < nz) {
+                if (h.stream) __builtin_nontemporal_store(v, of + col + (long)k * nxy);
+                else of[col + (long)k * nxy] = v;
+            }
 #pragma unroll
             for (int o = 0; o < 2 * N; ++o) win[o] = win[o + 1];
             win[2 * N] = k + N + 1 < nz ? wpre[j] : 0.0;
             wpre[j] = qf[col + level(k + N + 1 + P)];
-            if constexpr (ACC) apre[j] = of[col + level(k + P)];
+            if constexpr (ACC) apre[j] = ld_out(of + col + level(k + P));
         });
     }
 }

@@ -40,7 +40,14 @@ struct StageParams {
     int perx, pery;
     int ntx, nty;
     double fcor, g, gamma;
+    int stream;            // stream q^n, the heating and the result past the caches
 };
+
+// States of at least this many bytes per array are streamed past the
+// caches by the stage and hyper-diffusion kernels (twice the 256 MB
+// last-level cache: below it the next launch re-reads what this one wrote
+// from that cache).
+constexpr size_t kStreamBytes = size_t(512) << 20;
 
 // Layout of the constant table StageParams::cst.
 constexpr int kCstD = 0;                          // D[i][j] = h_j'(xi_i), (N+1)^2 entries
@@ -167,6 +174,7 @@ hipError_t launch_gmres(const HeviParams &h, const GmresArgs &g, hipStream_t s);
 // ---- tensor hyper-diffusion (box elements: one assembled 1D operator per direction)
 struct HyperParams {
     int nx, ny, nz, N, perx, pery;
+    int stream;                   // stream the output column past the caches
     const double *sx, *sy, *sz;   // [n_d][2N+1] operator rows per lattice position of each direction
 };
 // out = scale * (div tau grad) q on [5][U] (out += ... with accumulate); with

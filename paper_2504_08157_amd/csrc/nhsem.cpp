@@ -369,6 +369,7 @@ StageParams stage_params(const nh_ctx *c, double t, const double *qs, const doub
     p.ntx = (c->n[0] + tx - 1) / tx;
     p.nty = (c->n[1] + ty - 1) / ty;
     p.fcor = c->phys.f; p.g = c->phys.g; p.gamma = c->phys.cp / c->phys.cv;
+    p.stream = sizeof(double) * kNF * (size_t)c->U >= kStreamBytes;
     return p;
 }
 
@@ -380,6 +381,7 @@ HyperParams hyper_params(const nh_ctx *c)
     h.nx = c->n[0]; h.ny = c->n[1]; h.nz = c->n[2]; h.N = c->N;
     h.perx = c->per[0]; h.pery = c->per[1];
     h.sx = c->hd_s[0]; h.sy = c->hd_s[1]; h.sz = c->hd_s[2];
+    h.stream = sizeof(double) * kNF * (size_t)c->U >= kStreamBytes;
     return h;
 }
 
