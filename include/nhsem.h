@@ -45,7 +45,7 @@ typedef int32_t nh_status;
 #define NH_EHIP (-3)          /* a HIP runtime call failed */
 #define NH_ENOCONV (-4)       /* an iterative solve did not converge */
 #define NH_ENONFINITE (-5)    /* NaN or Inf found in the state */
-#define NH_EUNSUPPORTED (-6)  /* valid request this build does not support */
+#define NH_EUNSUPPORTED (-6)  /* valid request the library does not support */
 #define NH_ESPACE (-7)        /* workspace too small */
 
 #define NH_FP64 0             /* all element arithmetic in FP64 */
