@@ -33,13 +33,14 @@ __device__ __forceinline__ int hd_xcd_block(int b, int n)
 // q [5][U].  Tiled column walk: a workgroup of 64 x 16 lattice columns of one
 // field walks up the levels; the plane of its tile plus an N-wide x/y halo
 // is staged in LDS per level (two planes, one barrier per level), and the z
-// taps come from the (2N+1)-level window each thread keeps of its own
-// column.  Halo nodes past a wall are staged as zeros (their coefficients
+// taps are accumulated per thread from the staged planes' own nodes (or, at
+// orders 5 and 6, taken from a register window of the thread's column).  Halo nodes past a wall are staged as zeros (their coefficients
 // are zero); periodic directions wrap.  Measured on a 512 x 512 x 81 lattice
 // (N = 4): 64 x 16 tiles beat 64 x 4, 64 x 8, 32 x 8 and 128 x 4 (fewer halo
 // re-reads per node), and staging beats reading the x and y taps through
 // the caches.
 constexpr int kHdTX = 64, kHdTY = 16;
+constexpr int kHdRunMaxN = 4;
 
 template <int I, int E, class F>
 __device__ __forceinline__ void hd_static_for(F &&f)
@@ -110,66 +111,146 @@ __global__ void __launch_bounds__(kHdTX * kHdTY) hd_laplace_tile_kernel(HyperPar
         sv[i] = ok;
         sc[i] = ok ? jx + (long)jy * h.nx : 0;
     }
-    // Every stream is loaded P levels ahead of its use into a ring of P
-    // register slots indexed at compile time (the level loop is unrolled by
-    // P, so no value is copied while its load is in flight), unconditionally
-    // (levels past the top are clamped) and masked only where it is consumed:
-    // every wait in the loop is then for loads issued P levels earlier.  Slot
-    // k mod P holds the staged plane of level k (pre), the own column of q at
-    // level k + N + 1 (wpre) and, accumulating, that of out at level k (apre).
-    auto level = [&](int lv) -> long { return (long)(lv < nz ? lv : nz - 1) * nxy; };
-    // With h.stream the output column (read when accumulating, then
-    // written) bypasses the caches: touched once, it should not displace
-    // the staged planes' halos from L2.
-    auto ld_out = [&](const double *a) -> double {
-        if (h.stream) return __builtin_nontemporal_load(a);
-        return *a;
-    };
-    double pre[P][NS], wpre[P], apre[ACC ? P : 1];
+    // Orders up to kHdRunMaxN accumulate the z taps as running sums fed from
+    // the staged planes (no second read of the thread's column; 3-5 % faster
+    // per H_q at N = 4); higher orders keep a register window of the column,
+    // which needs fewer registers there (the running sums spill at N = 5, 6).
+    if constexpr (N <= kHdRunMaxN) {
+        // Every stream is loaded P levels ahead of its use into a ring of P
+        // register slots indexed at compile time (the level loop is unrolled by
+        // P, so no value is copied while its load is in flight), unconditionally
+        // (levels outside the column are clamped) and masked only where it is
+        // consumed: every wait in the loop is then for loads issued P levels
+        // earlier.  Slot k mod P holds the staged plane of level k (pre) and,
+        // accumulating, the output column at level k - N (apre).
+        auto level = [&](int lv) -> long { return (long)(lv < 0 ? 0 : (lv < nz ? lv : nz - 1)) * nxy; };
+        // With h.stream the output column (read when accumulating, then
+        // written) bypasses the caches: touched once, it should not displace
+        // the staged planes' halos from L2.
+        auto ld_out = [&](const double *a) -> double {
+            if (h.stream) return __builtin_nontemporal_load(a);
+            return *a;
+        };
+        double pre[P][NS], apre[ACC ? P : 1];
 #pragma unroll
-    for (int p = 0; p < P; ++p) {
+        for (int p = 0; p < P; ++p) {
 #pragma unroll
-        for (int i = 0; i < NS; ++i) pre[p][i] = qf[sc[i] + level(p)];
-        wpre[p] = qf[col + level(N + 1 + p)];
-        if constexpr (ACC) apre[p] = ld_out(of + col + level(p));
-    }
-    double win[NC];   // levels k - N .. k + N of the thread's column
+            for (int i = 0; i < NS; ++i) pre[p][i] = qf[sc[i] + level(p)];
+            if constexpr (ACC) apre[p] = ld_out(of + col + level(p - N));
+        }
+        // Running sums of the thread's column: za[o] collects L q at level
+        // k - N + o.  The node of level k, read from the staged plane, adds its
+        // z tap to each of the 2N + 1 levels it reaches and its x/y part to its
+        // own level; level k - N is then complete and is written.  The z values
+        // come from the plane already in LDS instead of a second read of the
+        // column from memory.
+        double za[NC];
 #pragma unroll
-    for (int o = 0; o < N; ++o) win[o] = 0.0;
+        for (int o = 0; o < NC; ++o) za[o] = 0.0;
+        for (int k0 = 0; k0 < nz + N; k0 += P) {
+            hd_static_for<0, P>([&](auto J) {
+                constexpr int j = decltype(J)::value;
+                const int k = k0 + j;   // levels k >= nz add nothing; levels m >= nz are not written
+                double *tl = tile[k & 1];
 #pragma unroll
-    for (int o = 0; o <= N; ++o) win[N + o] = o < nz ? qf[col + level(o)] : 0.0;
-    for (int k0 = 0; k0 < nz; k0 += P) {
-        hd_static_for<0, P>([&](auto J) {
-            constexpr int j = decltype(J)::value;
-            const int k = k0 + j;   // levels k >= nz of the last pass compute nothing that is kept
-            double *tl = tile[k & 1];
+                for (int i = 0; i < NS; ++i)
+                    if (threadIdx.x + i * NT < PX * PY) tl[threadIdx.x + i * NT] = sv[i] ? pre[j][i] : 0.0;
 #pragma unroll
-            for (int i = 0; i < NS; ++i)
-                if (threadIdx.x + i * NT < PX * PY) tl[threadIdx.x + i * NT] = sv[i] ? pre[j][i] : 0.0;
+                for (int i = 0; i < NS; ++i) pre[j][i] = qf[sc[i] + level(k + P)];
+                __syncthreads();
+                if (k < nz) {
+                    double ax = 0.0, ay = 0.0;
 #pragma unroll
-            for (int i = 0; i < NS; ++i) pre[j][i] = qf[sc[i] + level(k + P)];
-            __syncthreads();
-            const double *Sk = sz + level(k) / nxy * NC;
-            double ax = 0.0, ay = 0.0, az = 0.0;
+                    for (int o = 0; o < NC; ++o) {
+                        ax += cx[o] * tl[(ty + N) * PX + tx + o];
+                        ay += cy[o] * tl[(ty + o) * PX + tx + N];
+                    }
+                    const double qk = tl[(ty + N) * PX + tx + N];
 #pragma unroll
-            for (int o = 0; o < NC; ++o) {
-                az += Sk[o] * win[o];
-                ax += cx[o] * tl[(ty + N) * PX + tx + o];
-                ay += cy[o] * tl[(ty + o) * PX + tx + N];
-            }
-            double v = scale * (ax + ay + az);
-            if (colwall || (zwall && (k == 0 || k == nz - 1))) v = 0.0;
-            if constexpr (ACC) v = apre[j] + v;
-            if (own && k < nz) {
-                if (h.stream) __builtin_nontemporal_store(v, of + col + (long)k * nxy);
-                else of[col + (long)k * nxy] = v;
-            }
+                    for (int o = 0; o < NC; ++o) {
+                        const int lv = k - N + o;   // level whose row takes q(k) with tap 2N - o
+                        if (lv >= 0 && lv < nz) za[o] += sz[(long)lv * NC + 2 * N - o] * qk;
+                    }
+                    za[N] += ax + ay;
+                }
+                const int m = k - N;
+                if (m >= 0 && m < nz) {
+                    double v = scale * za[0];
+                    if (colwall || (zwall && (m == 0 || m == nz - 1))) v = 0.0;
+                    if constexpr (ACC) v = apre[j] + v;
+                    if (own) {
+                        if (h.stream) __builtin_nontemporal_store(v, of + col + (long)m * nxy);
+                        else of[col + (long)m * nxy] = v;
+                    }
+                }
 #pragma unroll
-            for (int o = 0; o < 2 * N; ++o) win[o] = win[o + 1];
-            win[2 * N] = k + N + 1 < nz ? wpre[j] : 0.0;
-            wpre[j] = qf[col + level(k + N + 1 + P)];
-            if constexpr (ACC) apre[j] = ld_out(of + col + level(k + P));
-        });
+                for (int o = 0; o < 2 * N; ++o) za[o] = za[o + 1];
+                za[2 * N] = 0.0;
+                if constexpr (ACC) apre[j] = ld_out(of + col + level(k + P - N));
+            });
+        }
+    } else {
+        // Every stream is loaded P levels ahead of its use into a ring of P
+        // register slots indexed at compile time (the level loop is unrolled by
+        // P, so no value is copied while its load is in flight), unconditionally
+        // (levels past the top are clamped) and masked only where it is consumed:
+        // every wait in the loop is then for loads issued P levels earlier.  Slot
+        // k mod P holds the staged plane of level k (pre), the own column of q at
+        // level k + N + 1 (wpre) and, accumulating, that of out at level k (apre).
+        auto level = [&](int lv) -> long { return (long)(lv < nz ? lv : nz - 1) * nxy; };
+        // With h.stream the output column (read when accumulating, then
+        // written) bypasses the caches: touched once, it should not displace
+        // the staged planes' halos from L2.
+        auto ld_out = [&](const double *a) -> double {
+            if (h.stream) return __builtin_nontemporal_load(a);
+            return *a;
+        };
+        double pre[P][NS], wpre[P], apre[ACC ? P : 1];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+#pragma unroll
+            for (int i = 0; i < NS; ++i) pre[p][i] = qf[sc[i] + level(p)];
+            wpre[p] = qf[col + level(N + 1 + p)];
+            if constexpr (ACC) apre[p] = ld_out(of + col + level(p));
+        }
+        double win[NC];   // levels k - N .. k + N of the thread's column
+#pragma unroll
+        for (int o = 0; o < N; ++o) win[o] = 0.0;
+#pragma unroll
+        for (int o = 0; o <= N; ++o) win[N + o] = o < nz ? qf[col + level(o)] : 0.0;
+        for (int k0 = 0; k0 < nz; k0 += P) {
+            hd_static_for<0, P>([&](auto J) {
+                constexpr int j = decltype(J)::value;
+                const int k = k0 + j;   // levels k >= nz of the last pass compute nothing that is kept
+                double *tl = tile[k & 1];
+#pragma unroll
+                for (int i = 0; i < NS; ++i)
+                    if (threadIdx.x + i * NT < PX * PY) tl[threadIdx.x + i * NT] = sv[i] ? pre[j][i] : 0.0;
+#pragma unroll
+                for (int i = 0; i < NS; ++i) pre[j][i] = qf[sc[i] + level(k + P)];
+                __syncthreads();
+                const double *Sk = sz + level(k) / nxy * NC;
+                double ax = 0.0, ay = 0.0, az = 0.0;
+#pragma unroll
+                for (int o = 0; o < NC; ++o) {
+                    az += Sk[o] * win[o];
+                    ax += cx[o] * tl[(ty + N) * PX + tx + o];
+                    ay += cy[o] * tl[(ty + o) * PX + tx + N];
+                }
+                double v = scale * (ax + ay + az);
+                if (colwall || (zwall && (k == 0 || k == nz - 1))) v = 0.0;
+                if constexpr (ACC) v = apre[j] + v;
+                if (own && k < nz) {
+                    if (h.stream) __builtin_nontemporal_store(v, of + col + (long)k * nxy);
+                    else of[col + (long)k * nxy] = v;
+                }
+#pragma unroll
+                for (int o = 0; o < 2 * N; ++o) win[o] = win[o + 1];
+                win[2 * N] = k + N + 1 < nz ? wpre[j] : 0.0;
+                wpre[j] = qf[col + level(k + N + 1 + P)];
+                if constexpr (ACC) apre[j] = ld_out(of + col + level(k + P));
+            });
+        }
     }
 }
 
