@@ -57,13 +57,20 @@ def test_hyperdiffusion_parity(oracle_mod, case):
     assert np.array_equal(Hg[Ho == 0.0], Ho[Ho == 0.0]), case
 
 
-def test_rk3_with_hyperdiffusion(oracle_mod):
+# order 4 takes the running-sum form of the accumulating launch, order 6 the
+# register-window form
+RK_CASES = {"N4": ((4, 3, 3), 4), "N6": ((3, 2, 2), 6)}
+
+
+@pytest.mark.parametrize("case", list(RK_CASES))
+def test_rk3_with_hyperdiffusion(oracle_mod, case):
     """Two SSP-RK3 steps with H_q in the tendency against the oracle's
     right-hand side plus its H_q, stepped in the Shu-Osher form.  The
     coefficients are small enough for the explicit step (nu scales with the
     element extent, so the largest eigenvalue of H_q is ~ c (pi N)^4 / dt)."""
     import torch
-    ctx, orc, g, o = _pair(oracle_mod, (4, 3, 3), 4, (True, False), True)
+    nel, N = RK_CASES[case]
+    ctx, orc, g, o = _pair(oracle_mod, nel, N, (True, False), True)
     c_step = (1e-6, 2e-6, 5e-6)
     ctx.nh_set_hyperdiffusion(c_step, DT)
     q = W.smooth_random_state(*o, *W.constant_n_reference(o[2]), seed=6, walls=(False, True))
