@@ -333,17 +333,18 @@ __device__ __forceinline__ void stage_body(const StageParams &p, const int tile,
     };
 
     // Loads of the node's own global data (q^n, heating) issued before the
-    // contractions so their latency overlaps them.  With p.stream (set by
-    // the host for states well beyond the 256 MB last-level cache) these
-    // and the result stores are non-temporal: each is touched once per
-    // launch, and the caches are left to the staged q^s halos that
-    // neighbouring tiles re-read (0.3-2.6 % faster per launch on the
-    // 512 x 512 x 81 lattice; on states that fit the last-level cache the
-    // next stage re-reads the result from it, and streaming measured 6-11 %
-    // slower).  Every thread runs the
+    // contractions so their latency overlaps them.  Every thread runs the
     // arithmetic (coordinates clamped into the lattice) and only the stores
     // are predicated: a conditional use would let the compiler sink the
     // contractions into the branch and keep every loaded LDS value alive.
+    //
+    // With p.stream (set by the host for states of at least twice the
+    // 256 MB last-level cache) these loads and the result stores are
+    // non-temporal: each is touched once per launch, and the caches are
+    // left to the staged q^s halos that neighbouring tiles re-read
+    // (0.3-2.6 % faster per launch on the 512 x 512 x 81 lattice).  On
+    // states that fit the last-level cache the next stage re-reads the
+    // result from it, and streaming measured 6-11 % slower.
     struct NodeIn {
         uint32_t o;
         bool valid;
