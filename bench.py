@@ -29,6 +29,7 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2504_08157_amd", "csrc", "nh_kernels.hip"
 
 
 HD_COUNTERS = os.path.join(ROOT, "profiles", "hd_laplace_tc_128x128x20_N4_hbm_counters.txt")
+BAT_COUNTERS = os.path.join(ROOT, "profiles", "stage_kernel_batched_ensemble48_hbm_counters.txt")
 HD_SRC = os.path.join(ROOT, "paper_2504_08157_amd", "csrc", "nh_hyper.hip")
 
 
@@ -499,6 +500,19 @@ def bench_batched(args):
     # snapshots each stage (16 B): 96 + 136 + 136 = 368 B per node and step
     alg = 368.0 * Utot
     gbs = alg / (ms_batch * 1e-3) / 1e9
+    # HBM bytes per step from the committed counter summary, when this run's
+    # kernel source, precision, ensemble, tile table and (persistent) launch
+    # form are the profiled ones
+    traffic = None
+    if prec == nhsem.NH_FP64 and len(ctxs) == 48 and best.startswith("persistent"):
+        try:
+            with open(BAT_COUNTERS) as fh:
+                line = [l for l in fh if l.startswith("tile_table:")][0]
+            prof = {int(a): int(b) for a, b in (kv.split("=") for kv in line.split(":", 1)[1].strip().split(","))}
+            if prof == {int(k): int(v) for k, v in table.items()}:
+                traffic = measured_traffic(None, BAT_COUNTERS, KERNEL_SRC, key="traffic_bytes_per_step")
+        except (OSError, IndexError, ValueError):
+            traffic = None
     out = {
         "metric": "DOF-stage updates/s (FP32/batched vs FP64 plain) at stated L2 error; % HBM peak",
         "value": 5 * Utot * 3 / (ms_batch / 1e3), "unit": "DOF-stage updates/s", "n_gpus": 1,
@@ -509,7 +523,9 @@ def bench_batched(args):
                    "tile_ms_per_step_by_order": {str(N): {str(v): t for v, t in tune[N].items()} for N in orders},
                    "form": best, "ms_per_step_by_form": forms},
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
-                     "traffic": None, "algorithmic_bytes_per_step": alg,
+                     "traffic": traffic,
+                     "traffic_unit": "HBM bytes per step (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_bytes_per_step": alg,
                      "kernel": "all stage launches of one batched SSP-RK3 step (3 stages x order groups)"},
         "batched": {"ms_per_step_one_by_one": ms_single, "speedup_vs_one_by_one": ms_single / ms_batch,
                     "finite": ok},
