@@ -25,6 +25,7 @@ BYTES_STAGE = {1: 40 + 16 + 40, 2: 40 + 40 + 16 + 40, 3: 40 + 40 + 16 + 40}
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "stage_kernel_tc_128x128x20_N4_fp64_counters.txt")
+COUNTERS_FP32 = os.path.join(ROOT, "profiles", "stage_kernel_tc_128x128x20_N4_fp32_counters.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2504_08157_amd", "csrc", "nh_kernels.hip")
 
 
@@ -916,7 +917,8 @@ def main():
     value = 5 * U * 3 * args.steps / (ms / 1e3)
     bytes_step = U * sum(BYTES_STAGE.values())
     achieved = bytes_step * args.steps / (ms / 1e3) / 1e9
-    traffic = measured_traffic(tile) if prec == nhsem.NH_FP64 and w.name == "tc_128x128x20_N4" else None
+    traffic = (measured_traffic(tile, COUNTERS if prec == nhsem.NH_FP64 else COUNTERS_FP32)
+               if w.name == "tc_128x128x20_N4" else None)
     res = {
         "metric": "DOF-stage updates/s (FP32/batched vs FP64 plain) at stated L2 error; % HBM peak",
         "value": value,
